@@ -1,0 +1,153 @@
+/*
+ * bse.h -- C ABI of the MI355X (gfx950) solver for the Bethe-Salpeter
+ * eigenproblem of form I.
+ *
+ * Problem (Benner & Penke, Sec. 1 Eq. Hform1; Alg. 3 Require/Ensure):
+ *   H1 = [ A  B ; -B  -A ]  with  A = A^H, B = B^H  in C^{n x n}
+ *   and A + B, A - B positive definite (Lemma Qtransform, part 2).
+ * Output: the n positive eigenvalues lambda_1 <= ... <= lambda_n and
+ *   X in C^{2n x n} with H1 X = X diag(lambda) and X^H Sigma X = I_n,
+ *   Sigma = diag(I_n, -I_n) (Thm ProdEig, Eq. SigmaOrthEVecs; the
+ *   normalisation of Sec. 4).  Optionally also the mirrored negative half
+ *   -lambda_k with eigenvectors [0 I; I 0] x_k (Lemma ComputeNegEvecs, part 1).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are column-major (LAPACK convention); complex values are
+ *     interleaved (re, im) pairs of IEEE doubles (complex128).
+ *   - Every matrix and vector pointer is a DEVICE pointer owned by the
+ *     caller.  The library never allocates or frees device memory: the
+ *     caller passes a workspace of at least the size the matching
+ *     *_workspace_bytes query returns.  Nothing is retained after return.
+ *   - All device work is enqueued on `stream` (a hipStream_t; NULL = the
+ *     default stream).  The calls are synchronous: they wait on `stream`
+ *     to read the device status word (and, in the Jacobi phase, once per
+ *     sweep for the convergence count) before returning.
+ *   - Only the triangle selected by `uplo` ('L' or 'U') of A and B is read;
+ *     the imaginary parts of their diagonals are ignored.
+ *   - No C++ exception crosses the ABI.  Return codes:
+ *        0            success
+ *       -i            argument i (1-based) is invalid
+ *        1..n         leading minor i of A + B is not positive definite
+ *        n+1..2n      leading minor (i - n) of A - B is not positive definite
+ *        2n+1         Jacobi iteration did not converge within max_sweeps
+ *                     (outputs are written; info->max_off says how far off)
+ *        2n+2         mixed precision: refinement did not reach its tolerance
+ *                     (outputs are written)
+ *       <= -1000      HIP runtime error (-1000 - hipError_t)
+ */
+#ifndef BSE_H
+#define BSE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Route: Alg. 3 (CHOL+SVD: chol(A+B), chol(A-B), SVD of L2^H L1) or
+ * Alg. 2 (CHOL: chol(A-B), Hermitian eigenproblem of L^H (A+B) L). */
+enum { BSE_ROUTE_SVD = 0, BSE_ROUTE_EIG = 1 };
+/* Arithmetic: plain FP64 throughout, or complex64 bulk work on FP32 MFMA
+ * with FP64 diagonal Cholesky blocks and an FP64 residual-based refinement. */
+enum { BSE_PREC_FP64 = 0, BSE_PREC_MIXED = 1 };
+
+typedef struct {
+  int route;          /* BSE_ROUTE_*                                            */
+  int precision;      /* BSE_PREC_*                                             */
+  int max_sweeps;     /* Jacobi sweep limit; 0 = default (30 FP64, 20 mixed)    */
+  int refine_steps;   /* mixed only: refinement steps; 0 = default (1)          */
+  double jacobi_tol;  /* rotate a block pair while max |g_ij|/sqrt(g_ii g_jj)
+                         exceeds this; 0 = default n * eps of the bulk dtype    */
+  int want_negative;  /* nonzero: also write -lambda and [0 I; I 0] X           */
+  int uplo;           /* 'L' (default when 0) or 'U'                            */
+  int reserved[6];    /* must be zero                                           */
+} bse_opts_t;
+
+typedef struct {
+  int status;           /* same value as the return code                      */
+  int sweeps;           /* Jacobi sweeps run (the last one rotates nothing)   */
+  int fail_index;       /* non-HPD: 1-based leading minor, else 0             */
+  int rotations;        /* block-pair rotations over all sweeps               */
+  double max_off;       /* largest relative off-diagonal seen in the last sweep */
+  double refine_delta;  /* mixed: max |lambda change| / lambda of the last step */
+  double ms_phase[8];   /* phase times (ms): form, chol, W, jacobi, finalize,
+                           back-transform, refine, total; filled if requested  */
+  int timing;           /* in: 0 none; 1 fill ms_phase; 2 also time every
+                           Jacobi kernel launch with HIP events on `stream`   */
+  int pair_checks;      /* block pairs examined over all sweeps               */
+  double kernel_ms[3];  /* timing == 2: summed durations of the Jacobi Gram,
+                           inner-eigensolver and rotation kernels (ms)        */
+  int kernel_launches[3];
+  int reserved[3];
+} bse_info_t;
+
+/* Fill `opts` with the defaults (route SVD, FP64, lower triangles). */
+void bse_default_opts(bse_opts_t* opts);
+
+/* Workspace bytes bse_solve_h1 needs for order n under `opts` (NULL = defaults).
+ * Returns 0 for an invalid n or opts. */
+size_t bse_workspace_bytes(int n, const bse_opts_t* opts);
+
+/* All eigenpairs of H1 (Alg. 3 or Alg. 2; see the file header).
+ *   n        order of A and B (n >= 0; n = 0 returns 0 at once)
+ *   A, lda   n x n complex128, lda >= max(1, n); triangle `uplo` read
+ *   B, ldb   n x n complex128, ldb >= max(1, n)
+ *   lambda   n doubles (2n if want_negative: +lambda ascending, then -lambda)
+ *   X, ldx   2n x n complex128 (2n x 2n if want_negative), ldx >= max(1, 2n);
+ *            columns are Sigma-normalised eigenvectors in the order of lambda
+ *   work     device workspace of work_bytes >= bse_workspace_bytes(n, opts)
+ *   opts     NULL = defaults
+ *   info     optional (may be NULL) host struct with diagnostics
+ *   stream   hipStream_t
+ * A and B are not modified.  Outputs are undefined on a non-HPD status. */
+int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb,
+                 double* lambda, void* X, int ldx,
+                 void* work, size_t work_bytes,
+                 const bse_opts_t* opts, bse_info_t* info, void* stream);
+
+/* Workspace for bse_solve_batched over `batch` problems of orders n[0..batch). */
+size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* opts);
+
+/* `batch` independent problems in one call (same opts for all).
+ *   n, lda, ldb, ldx                 host arrays of length batch
+ *   A, B, lambda, X                  host arrays of device pointers
+ *   info                             optional host array of `batch` entries
+ * Returns 0 if every problem succeeded, else the status of the first problem
+ * (in index order) that failed, with every problem's own status in info[i].
+ * Problems are processed together: each phase is launched once for the
+ * whole batch with per-problem descriptors. */
+int bse_solve_batched(int batch, const int* n,
+                      const void* const* A, const int* lda,
+                      const void* const* B, const int* ldb,
+                      double* const* lambda, void* const* X, const int* ldx,
+                      void* work, size_t work_bytes,
+                      const bse_opts_t* opts, bse_info_t* info, void* stream);
+
+/* Workspace for bse_backward of order n. */
+size_t bse_backward_workspace_bytes(int n);
+
+/* Gradient of a real loss L(lambda) with respect to Hermitian A and B.
+ * With v_k = [a_k; b_k] the k-th column of X (X^H Sigma X = I) and
+ * w_k = dL/dlambda_k (derivatives with respect to the negative half folded in
+ * as -dL/d(-lambda_k)), first-order perturbation with the left eigenvector
+ * v_k^H Sigma (Thm EValSym, part 3) gives
+ *   G_A = sum_k w_k (a_k a_k^H + b_k b_k^H),
+ *   G_B = sum_k w_k (a_k b_k^H + b_k a_k^H),
+ * so that dL = Re tr(G_A^H dA) + Re tr(G_B^H dB) for Hermitian dA, dB.
+ *   X, ldx     2n x n complex128 (as written by bse_solve_h1)
+ *   w          n doubles (device)
+ *   gA, ldga   n x n complex128 output (full Hermitian matrix)
+ *   gB, ldgb   n x n complex128 output
+ * Return codes as above (0, -i, <= -1000). */
+int bse_backward(int n, const void* X, int ldx, const double* w,
+                 void* gA, int ldga, void* gB, int ldgb,
+                 void* work, size_t work_bytes, void* stream);
+
+/* Short text for a return code (static storage). */
+const char* bse_status_string(int status, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSE_H */

@@ -1,0 +1,327 @@
+"""Python binding of the HIP solver's C ABI (``include/bse.h``).
+
+Argument marshalling only: every step of the solve runs in ``libbse.so``.
+PyTorch provides device memory (inputs, outputs, workspace) and the current
+stream.  There is no CPU fallback; if the library is missing the calls raise.
+
+Layout: torch tensors are row-major, the ABI is column-major.  A row-major
+Hermitian ``A`` read as column-major is ``A^T = conj(A)``; the binding passes
+row-major inputs with ``uplo='U'`` (which selects the lower triangle of the
+row-major tensor), so the library solves the conjugated problem, whose
+eigenvalues are the same and whose eigenvectors are the conjugates.  The
+returned ``X`` is therefore a conjugated, transposed view of the library's
+column-major buffer (no copy).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbse.so")
+
+ROUTES = {"svd": 0, "eig": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
+class BSEOpts(ctypes.Structure):
+    _fields_ = [
+        ("route", ctypes.c_int),
+        ("precision", ctypes.c_int),
+        ("max_sweeps", ctypes.c_int),
+        ("refine_steps", ctypes.c_int),
+        ("jacobi_tol", ctypes.c_double),
+        ("want_negative", ctypes.c_int),
+        ("uplo", ctypes.c_int),
+        ("reserved", ctypes.c_int * 6),
+    ]
+
+
+class BSEInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("sweeps", ctypes.c_int),
+        ("fail_index", ctypes.c_int),
+        ("rotations", ctypes.c_int),
+        ("max_off", ctypes.c_double),
+        ("refine_delta", ctypes.c_double),
+        ("ms_phase", ctypes.c_double * 8),
+        ("timing", ctypes.c_int),
+        ("pair_checks", ctypes.c_int),
+        ("kernel_ms", ctypes.c_double * 3),
+        ("kernel_launches", ctypes.c_int * 3),
+        ("reserved", ctypes.c_int * 3),
+    ]
+
+    def as_dict(self):
+        return {
+            "status": self.status,
+            "sweeps": self.sweeps,
+            "fail_index": self.fail_index,
+            "rotations": self.rotations,
+            "max_off": self.max_off,
+            "refine_delta": self.refine_delta,
+            "ms_phase": list(self.ms_phase),
+            "pair_checks": self.pair_checks,
+            "kernel_ms": list(self.kernel_ms),
+            "kernel_launches": list(self.kernel_launches),
+        }
+
+
+PHASES = ["form", "chol", "W", "jacobi", "finalize", "back", "refine", "total"]
+
+EXPORTS = [
+    "bse_default_opts",
+    "bse_workspace_bytes",
+    "bse_solve_h1",
+    "bse_batched_workspace_bytes",
+    "bse_solve_batched",
+    "bse_backward_workspace_bytes",
+    "bse_backward",
+    "bse_status_string",
+]
+
+_lib = None
+
+
+def load_library(path: Optional[str] = None):
+    """Load ``libbse.so`` and declare the C signatures (raises if absent)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP solver library not built: {p} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(p)
+    vp = ctypes.c_void_p
+    ci = ctypes.c_int
+    lib.bse_default_opts.argtypes = [ctypes.POINTER(BSEOpts)]
+    lib.bse_default_opts.restype = None
+    lib.bse_workspace_bytes.argtypes = [ci, ctypes.POINTER(BSEOpts)]
+    lib.bse_workspace_bytes.restype = ctypes.c_size_t
+    lib.bse_solve_h1.argtypes = [ci, vp, ci, vp, ci, vp, vp, ci, vp, ctypes.c_size_t,
+                                 ctypes.POINTER(BSEOpts), ctypes.POINTER(BSEInfo), vp]
+    lib.bse_solve_h1.restype = ci
+    lib.bse_batched_workspace_bytes.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(BSEOpts)]
+    lib.bse_batched_workspace_bytes.restype = ctypes.c_size_t
+    lib.bse_solve_batched.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(vp), ctypes.POINTER(ci),
+                                      ctypes.POINTER(vp), ctypes.POINTER(ci), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(ci), vp, ctypes.c_size_t,
+                                      ctypes.POINTER(BSEOpts), ctypes.POINTER(BSEInfo), vp]
+    lib.bse_solve_batched.restype = ci
+    lib.bse_backward_workspace_bytes.argtypes = [ci]
+    lib.bse_backward_workspace_bytes.restype = ctypes.c_size_t
+    lib.bse_backward.argtypes = [ci, vp, ci, vp, vp, ci, vp, ci, vp, ctypes.c_size_t, vp]
+    lib.bse_backward.restype = ci
+    lib.bse_status_string.argtypes = [ci, ci]
+    lib.bse_status_string.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+class BSEError(RuntimeError):
+    def __init__(self, status: int, n: int, info=None):
+        lib = load_library()
+        msg = lib.bse_status_string(status, n).decode()
+        super().__init__(f"bse status {status}: {msg}")
+        self.status = status
+        self.info = info
+
+
+def make_opts(route="svd", precision="fp64", max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
+              want_negative=False, uplo="L") -> BSEOpts:
+    o = BSEOpts()
+    load_library().bse_default_opts(ctypes.byref(o))
+    o.route = ROUTES[route]
+    o.precision = PRECISIONS[precision]
+    o.max_sweeps = int(max_sweeps)
+    o.refine_steps = int(refine_steps)
+    o.jacobi_tol = float(jacobi_tol)
+    o.want_negative = 1 if want_negative else 0
+    o.uplo = ord(uplo)
+    return o
+
+
+def _stream_handle(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _matrix_arg(M: torch.Tensor, name: str):
+    """(pointer, ld, uplo) for a square complex128 CUDA tensor, without copying when possible."""
+    if M.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128")
+    if not M.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if M.dim() != 2 or M.shape[0] != M.shape[1]:
+        raise ValueError(f"{name} must be square")
+    if M.is_conj():
+        M = M.resolve_conj()
+    n = M.shape[0]
+    if n == 0:
+        return M, 0, 1, "L"
+    if M.stride(1) == 1 and M.stride(0) >= max(1, n):
+        # row-major: column-major view of A^T; its upper triangle is A's lower triangle
+        return M, M.data_ptr(), M.stride(0), "U"
+    if M.stride(0) == 1 and M.stride(1) >= max(1, n):
+        return M, M.data_ptr(), M.stride(1), "L"
+    M = M.contiguous()
+    return M, M.data_ptr(), n, "U"
+
+
+def workspace_bytes(n: int, **kw) -> int:
+    lib = load_library()
+    o = make_opts(**kw)
+    return int(lib.bse_workspace_bytes(n, ctypes.byref(o)))
+
+
+def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
+             want_negative=False, max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
+             timing=False, check=True, work: Optional[torch.Tensor] = None,
+             out=None):
+    """All eigenpairs of H1 = [[A, B], [-B, -A]] (lower triangles of A, B read).
+
+    Returns ``(lam, X, info)``: ``lam`` (n, ascending; 2n with ``want_negative``),
+    ``X`` (2n x n or 2n x 2n, complex128) with ``H1 X = X diag(lam)`` and
+    ``X^H Sigma X = I`` (``-I`` on the negative half), ``info`` a dict.
+    """
+    lib = load_library()
+    if A.shape != B.shape:
+        raise ValueError("A and B must have the same shape")
+    A_, pa, lda, ua = _matrix_arg(A, "A")
+    B_, pb, ldb, ub = _matrix_arg(B, "B")
+    if ua != ub:  # mixed layouts: bring B to A's
+        B_ = B_.contiguous() if ua == "U" else B_.mT.contiguous().mT
+        pb, ldb = B_.data_ptr(), (B_.stride(0) if ua == "U" else B_.stride(1))
+    n = A.shape[0]
+    dev = A.device
+    ncols = 2 * n if want_negative else n
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, ua)
+    if out is None:
+        lam = torch.empty(ncols, dtype=torch.float64, device=dev)
+        Xbuf = torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
+    else:
+        lam, Xbuf = out
+    need = int(lib.bse_workspace_bytes(n, ctypes.byref(o)))
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    info = BSEInfo()
+    info.timing = int(timing)
+    with torch.cuda.device(dev):
+        st = lib.bse_solve_h1(n, pa, lda, pb, ldb, lam.data_ptr(), Xbuf.data_ptr(), max(1, 2 * n),
+                              work.data_ptr(), work.numel(), ctypes.byref(o), ctypes.byref(info),
+                              _stream_handle(dev))
+    d = info.as_dict()
+    d["status"] = st
+    if check and st != 0:
+        raise BSEError(st, n, d)
+    X = Xbuf.mT
+    if ua == "U":
+        X = X.conj()
+    return lam, X, d
+
+
+def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
+                  max_sweeps=0, refine_steps=0, jacobi_tol=0.0, check=True):
+    """Independent problems ``(A_i, B_i)`` in one library call; returns lists of (lam, X) and infos."""
+    lib = load_library()
+    count = len(As)
+    if len(Bs) != count:
+        raise ValueError("As and Bs differ in length")
+    keep = []
+    ns, pas, ldas, pbs, ldbs, plams, pxs, ldxs, uplos = [], [], [], [], [], [], [], [], []
+    lams, Xbufs = [], []
+    dev = As[0].device if count else torch.device("cuda")
+    for A, B in zip(As, Bs):
+        A_, pa, lda, ua = _matrix_arg(A, "A")
+        B_, pb, ldb, ub = _matrix_arg(B, "B")
+        if ua != "U" or ub != "U":
+            A_ = A_.contiguous() if ua != "U" else A_
+            B_ = B_.contiguous() if ub != "U" else B_
+            pa, lda, pb, ldb = A_.data_ptr(), A_.stride(0), B_.data_ptr(), B_.stride(0)
+        keep += [A_, B_]
+        n = A.shape[0]
+        ncols = 2 * n if want_negative else n
+        lam = torch.empty(ncols, dtype=torch.float64, device=dev)
+        Xb = torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
+        lams.append(lam)
+        Xbufs.append(Xb)
+        ns.append(n); pas.append(pa); ldas.append(max(1, lda)); pbs.append(pb); ldbs.append(max(1, ldb))
+        plams.append(lam.data_ptr()); pxs.append(Xb.data_ptr()); ldxs.append(max(1, 2 * n))
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, "U")
+    IA = ctypes.c_int * max(count, 1)
+    PA = ctypes.c_void_p * max(count, 1)
+    c_n = IA(*ns)
+    need = int(lib.bse_batched_workspace_bytes(count, c_n, ctypes.byref(o)))
+    work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    infos = (BSEInfo * max(count, 1))()
+    with torch.cuda.device(dev):
+        st = lib.bse_solve_batched(count, c_n, PA(*pas), IA(*ldas), PA(*pbs), IA(*ldbs), PA(*plams),
+                                   PA(*pxs), IA(*ldxs), work.data_ptr(), work.numel(), ctypes.byref(o),
+                                   infos, _stream_handle(dev))
+    out_infos = [infos[i].as_dict() for i in range(count)]
+    if check and st != 0:
+        raise BSEError(st, ns[0] if ns else 0, out_infos)
+    results = [(lams[i], Xbufs[i].mT.conj()) for i in range(count)]
+    return results, out_infos, st
+
+
+def backward(X: torch.Tensor, w: torch.Tensor):
+    """``(G_A, G_B)`` for ``L = sum_k w_k lambda_k`` (see ``bse_backward`` in include/bse.h)."""
+    lib = load_library()
+    n2, n = X.shape
+    if n2 != 2 * n:
+        raise ValueError("X must be 2n x n")
+    if X.dtype != torch.complex128 or not X.is_cuda:
+        raise TypeError("X must be a complex128 CUDA tensor")
+    w = w.to(dtype=torch.float64, device=X.device).contiguous()
+    conj = X.is_conj()
+    Xr = X.conj() if conj else X            # buffer values (conj bit dropped, no copy)
+    Xr = Xr.resolve_conj()
+    if Xr.stride(0) != 1 or Xr.stride(1) < max(1, 2 * n):
+        Xr = Xr.mT.contiguous().mT
+    dev = X.device
+    gA = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    gB = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    work = torch.empty(max(1, int(lib.bse_backward_workspace_bytes(n))), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        st = lib.bse_backward(n, Xr.data_ptr(), Xr.stride(1), w.data_ptr(), gA.data_ptr(), n,
+                              gB.data_ptr(), n, work.data_ptr(), work.numel(), _stream_handle(dev))
+    if st != 0:
+        raise BSEError(st, n)
+    # gA, gB hold column-major G computed from the buffer values; the row-major
+    # reading of that memory is G^T, and conjugated inputs give conj(G).
+    GA = gA.mT
+    GB = gB.mT
+    if conj:
+        GA = GA.conj()
+        GB = GB.conj()
+    return GA, GB
+
+
+class BSEEig(torch.autograd.Function):
+    """``(lam, X) = BSEEig.apply(A, B)``; backward through ``lam`` only.
+
+    The gradient is the full Hermitian ``G`` with ``dL = Re tr(G^H dA)`` for
+    Hermitian perturbations; a nonzero gradient with respect to ``X`` raises.
+    """
+
+    @staticmethod
+    def forward(ctx, A, B, route="svd", precision="fp64"):
+        lam, X, _ = solve_h1(A.detach(), B.detach(), route=route, precision=precision)
+        ctx.save_for_backward(X)
+        ctx.mark_non_differentiable(X)
+        return lam, X
+
+    @staticmethod
+    def backward(ctx, g_lam, g_X):
+        (X,) = ctx.saved_tensors
+        if g_X is not None and bool(torch.any(g_X != 0)):
+            raise NotImplementedError("gradient with respect to eigenvectors is not supported")
+        if g_lam is None:
+            return None, None, None, None
+        GA, GB = backward(X, g_lam)
+        return GA, GB, None, None

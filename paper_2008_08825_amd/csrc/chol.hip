@@ -1,0 +1,202 @@
+// Forming M1 = A + B, M2 = A - B and their blocked Cholesky factorisations
+// (Alg. 3 steps 1-2; Thm ProdEig defines M1, M2; Lemma Qtransform part 2 says
+// both factorisations succeed exactly when the BSE Hamiltonian is definite).
+//
+// Right-looking blocked Cholesky with 64-column panels:
+//   1. one workgroup factors the 64 x 64 diagonal block in LDS (FP64) and
+//      also forms the inverse of that triangular block;
+//   2. the panel below is L21 = A21 L11^-H, a GEMM against the inverse;
+//   3. the trailing matrix takes the Hermitian rank-64 update
+//      A22 -= L21 L21^H on MFMA, lower tiles only.
+#include "common.hpp"
+#include "internal.hpp"
+
+#include <climits>
+
+namespace bse {
+namespace {
+
+constexpr int NB = 64;
+
+// One 64 x 64 tile of M1/M2 per workgroup.  Reading the upper triangle of a
+// column-major matrix means reading it transposed, so the tile goes through
+// LDS to keep global reads coalesced.
+__global__ __launch_bounds__(256) void k_form_m12(int n, int np, const double2* __restrict__ A,
+                                                  long lda, const double2* __restrict__ B, long ldb,
+                                                  int upper, double2* __restrict__ M1,
+                                                  double2* __restrict__ M2, long ldm) {
+  __shared__ double2 tile[64][65];
+  const int T = np / 64;
+  const int tm = blockIdx.x % T, tn = blockIdx.x / T;
+  const int m0 = tm * 64, n0 = tn * 64;
+  const int tid = threadIdx.x;
+  double2 va[16], vb[16];
+  if (tn <= tm) {
+    for (int pass = 0; pass < 2; ++pass) {
+      const double2* S = pass == 0 ? A : B;
+      const long lds = pass == 0 ? lda : ldb;
+      double2* v = pass == 0 ? va : vb;
+      if (upper) {
+        // element (i, j) of the lower triangle is conj(S[j + i * lds])
+        for (int q = 0; q < 16; ++q) {
+          int cc = tid & 63, rr = (tid >> 6) + 4 * q;  // cc runs along j (contiguous)
+          int i = m0 + rr, j = n0 + cc;
+          double2 x = make_double2(0.0, 0.0);
+          if (i < n && j < n && i >= j) x = S[j + (long)i * lds];
+          tile[rr][cc] = x;
+        }
+        __syncthreads();
+        for (int q = 0; q < 16; ++q) {
+          int r = tid & 63, c = (tid >> 6) + 4 * q;
+          double2 x = tile[r][c];
+          v[q] = make_double2(x.x, -x.y);
+        }
+        __syncthreads();
+      } else {
+        for (int q = 0; q < 16; ++q) {
+          int r = tid & 63, c = (tid >> 6) + 4 * q;
+          int i = m0 + r, j = n0 + c;
+          double2 x = make_double2(0.0, 0.0);
+          if (i < n && j < n && i >= j) x = S[i + (long)j * lds];
+          v[q] = x;
+        }
+      }
+    }
+  }
+  for (int q = 0; q < 16; ++q) {
+    int r = tid & 63, c = (tid >> 6) + 4 * q;
+    int i = m0 + r, j = n0 + c;
+    double2 o1, o2;
+    if (i >= n || j >= n) {
+      double d = (i == j) ? 1.0 : 0.0;
+      o1 = make_double2(d, 0.0); o2 = o1;
+    } else if (i < j) {
+      o1 = make_double2(0.0, 0.0); o2 = o1;
+    } else if (i == j) {
+      o1 = make_double2(va[q].x + vb[q].x, 0.0);
+      o2 = make_double2(va[q].x - vb[q].x, 0.0);
+    } else {
+      o1 = cadd(va[q], vb[q]);
+      o2 = csub(va[q], vb[q]);
+    }
+    M1[i + (long)j * ldm] = o1;
+    M2[i + (long)j * ldm] = o2;
+  }
+}
+
+// Unblocked Cholesky of the diagonal block M[j0:j0+64, j0:j0+64] (lower) and
+// the inverse of the resulting triangle, in one workgroup.  Writes L11 back
+// with a zero strict upper triangle and L11^-1 (64 x 64, ld 64) to `linv`.
+__global__ __launch_bounds__(256) void k_potf2_inv(double2* M, long ld, int j0,
+                                                   double2* __restrict__ linv, int* status,
+                                                   int base, int n_real) {
+  __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
+  __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
+  __shared__ int failed;
+  const int tid = threadIdx.x;
+  double2* D = M + j0 + (long)j0 * ld;
+  for (int q = 0; q < 16; ++q) {
+    int r = tid & 63, c = (tid >> 6) + 4 * q;
+    double2 v = (r >= c) ? D[r + (long)c * ld] : make_double2(0.0, 0.0);
+    Lr[r][c] = v.x; Li[r][c] = v.y;
+  }
+  if (tid == 0) failed = 0;
+  __syncthreads();
+  for (int j = 0; j < NB; ++j) {
+    if (tid == 0) {
+      double d = Lr[j][j];
+      if (!(d > 0.0)) {
+        failed = 1;
+        if (j0 + j < n_real) atomicMin(status, base + j0 + j + 1);
+      } else {
+        Lr[j][j] = sqrt(d);
+        Li[j][j] = 0.0;
+      }
+    }
+    __syncthreads();
+    if (failed) break;
+    const double inv = 1.0 / Lr[j][j];
+    if (tid > j && tid < NB) { Lr[tid][j] *= inv; Li[tid][j] *= inv; }
+    __syncthreads();
+    // trailing update of the block: L[i][k] -= L[i][j] conj(L[k][j]), j < k <= i
+    {
+      const int i = tid & 63;
+      if (i > j) {
+        const double lr = Lr[i][j], li = Li[i][j];
+        for (int k = j + 1 + (tid >> 6); k <= i; k += 4) {
+          const double kr = Lr[k][j], ki = Li[k][j];
+          Lr[i][k] -= lr * kr + li * ki;
+          Li[i][k] -= li * kr - lr * ki;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (failed) {
+    // leave the block as is; the caller stops after reading the status
+    return;
+  }
+  // Inverse of the lower triangle, one column per thread (forward substitution).
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < NB; ++i) { Xr[i][c] = 0.0; Xi[i][c] = 0.0; }
+    Xr[c][c] = 1.0 / Lr[c][c];
+    for (int i = c + 1; i < NB; ++i) {
+      double sr = 0.0, si = 0.0;
+      for (int k = c; k < i; ++k) {
+        const double ar = Lr[i][k], ai = Li[i][k], xr = Xr[k][c], xi = Xi[k][c];
+        sr += ar * xr - ai * xi;
+        si += ar * xi + ai * xr;
+      }
+      const double dinv = 1.0 / Lr[i][i];
+      Xr[i][c] = -sr * dinv;
+      Xi[i][c] = -si * dinv;
+    }
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    int r = tid & 63, c = (tid >> 6) + 4 * q;
+    double2 l = (r >= c) ? make_double2(Lr[r][c], Li[r][c]) : make_double2(0.0, 0.0);
+    D[r + (long)c * ld] = l;
+    linv[r + c * NB] = make_double2(Xr[r][c], Xi[r][c]);
+  }
+}
+
+}  // namespace
+
+hipError_t form_m12(int n, int np, const double2* A, long lda, const double2* B, long ldb,
+                    int upper, double2* M1, double2* M2, long ldm, hipStream_t s) {
+  const int T = np / 64;
+  k_form_m12<<<T * T, 256, 0, s>>>(n, np, A, lda, B, ldb, upper, M1, M2, ldm);
+  return hipGetLastError();
+}
+
+hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, int* status,
+                      int base, hipStream_t s) {
+  for (int j0 = 0; j0 < np; j0 += NB) {
+    k_potf2_inv<<<1, 256, 0, s>>>(M, ld, j0, linv, status, base, n_real);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int rows = np - j0 - NB;
+    if (rows <= 0) break;
+    double2* panel = M + (j0 + NB) + (long)j0 * ld;
+    GemmDesc t;  // L21 = A21 * L11^-H (in place: one workgroup per row tile)
+    t.M = rows; t.N = NB; t.K = NB;
+    t.A = panel; t.lda = ld; t.opA = 0;
+    t.B = linv; t.ldb = NB; t.opB = 1; t.triB = 1;
+    t.C = panel; t.ldc = ld;
+    e = gemm_z(t, s);
+    if (e != hipSuccess) return e;
+    GemmDesc h;  // A22 -= L21 L21^H, lower tiles
+    h.M = rows; h.N = rows; h.K = NB;
+    h.A = panel; h.lda = ld; h.opA = 0;
+    h.B = panel; h.ldb = ld; h.opB = 1;
+    h.C = M + (j0 + NB) + (long)(j0 + NB) * ld; h.ldc = ld;
+    h.alpha_re = -1.0; h.beta_re = 1.0; h.lowerC = 1;
+    e = gemm_z(h, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace bse

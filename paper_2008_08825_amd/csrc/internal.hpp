@@ -1,0 +1,83 @@
+// Internal launch interfaces of the HIP solver (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+namespace bse {
+
+// C[m, n] = alpha * sum_k opA(A)[m, k] * s[k] * opB(B)[k, n] * colscale[n] + beta * C[m, n]
+// opA = 0: A is M x K column-major; opA = 1: A is K x M and opA(A) = A^H.
+// opB = 0: B is K x N; opB = 1: B is N x K and opB(B) = B^H.
+// triA / triB: the stored A / B is lower triangular (its strict upper part is
+// zero), so the k-range of each output tile is cut to where both operands
+// can be nonzero.  lowerC: only tiles on or below the diagonal are computed.
+// mask > 0: outputs with m >= mask or n >= mask are written as zero.
+// batch > 1: blockIdx.y selects the problem; pointers advance by stride*.
+struct GemmDesc {
+  int M = 0, N = 0, K = 0;
+  const void* A = nullptr; long lda = 0; int opA = 0; int triA = 0;
+  const void* B = nullptr; long ldb = 0; int opB = 0; int triB = 0;
+  void* C = nullptr; long ldc = 0;
+  double alpha_re = 1.0, alpha_im = 0.0, beta_re = 0.0, beta_im = 0.0;
+  const void* kscale = nullptr;    // real, length K (same precision as data)
+  const void* colscale = nullptr;  // real, length N
+  int lowerC = 0;
+  int mask = 0;
+  int batch = 1;
+  long strideA = 0, strideB = 0, strideC = 0;
+};
+
+hipError_t gemm_z(const GemmDesc& d, hipStream_t s);  // complex128
+hipError_t gemm_c(const GemmDesc& d, hipStream_t s);  // complex64
+
+// Blocked Cholesky (lower) of an np x np Hermitian matrix held in its lower
+// triangle, in place; np % 64 == 0.  The strict upper triangle must be zero
+// on entry and stays zero.  First non-positive pivot (leading minor index,
+// 1-based, < n_real) is reported as atomicMin(status, base + index).
+hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv,
+                      int* status, int base, hipStream_t s);
+
+// M1 = A + B, M2 = A - B (lower triangles, zero strict upper part), padded to
+// np with identity; reads the `upper` or lower triangle of A, B.
+hipError_t form_m12(int n, int np, const double2* A, long lda, const double2* B,
+                    long ldb, int upper, double2* M1, double2* M2, long ldm,
+                    hipStream_t s);
+
+struct JacobiWork {
+  void* part = nullptr;    // partial Gram tiles
+  void* R = nullptr;       // rotations, pairs x 64 x 64
+  int* flags = nullptr;    // per pair
+  int* counter = nullptr;  // rotated pairs in the current sweep
+  double* maxoff = nullptr;
+};
+size_t jacobi_work_bytes(int np, int elem_bytes);
+void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w);
+
+struct JacobiResult {
+  int sweeps = 0;
+  int rotations = 0;
+  int pair_checks = 0;
+  double max_off = 0.0;
+  int converged = 0;
+  // per-kernel event timing (filled when time_kernels is set)
+  double kernel_ms[3] = {0.0, 0.0, 0.0};
+  int kernel_launches[3] = {0, 0, 0};
+};
+
+// One-sided block-Jacobi on the np columns of W (np % 64 == 0), in place:
+// on return the columns of W are mutually orthogonal (W_in Q = W_out, Q unitary).
+hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false);
+
+// Finalisation of the SVD route: sigma_j = ||W[:, j]||, ascending order of the
+// first n, lambda, inverse lambda and Ws[:, r] = W[:, perm r] sigma^-3/2.
+hipError_t finalize_sort_z(int n, int np, const double2* W, long ld, double* sigma,
+                           int* perm, double* lambda, int want_negative,
+                           double* invlam, double2* Ws, hipStream_t s);
+
+// X = [(V1 + V2)/2; (V2 - V1)/2] (and the mirrored negative half).
+hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv,
+                      double2* X, long ldx, int want_negative, hipStream_t s);
+
+}  // namespace bse

@@ -1,0 +1,478 @@
+// One-sided block-Jacobi SVD on MFMA (replaces the LAPACK SVD of Alg. 3 step 3).
+//
+// W (np x np, column-major) is split into N = np / 32 column blocks.  A sweep
+// runs N - 1 rounds of the round-robin ("circle") ordering; each round pairs
+// every block with one other, and the N / 2 pairs of a round are independent.
+// For a pair (p, q) with X = [W_p W_q] (np x 64):
+//   gram:   G = X^H X (64 x 64 Hermitian), split over row chunks on MFMA,
+//           only the ten 16 x 16 tiles on or below the diagonal;
+//   eig:    if max_{i != j} |G_ij| / sqrt(G_ii G_jj) > tol, the eigenvectors R
+//           of G by cyclic two-sided Jacobi in LDS (FP64), with inner
+//           rotations (|angle| <= pi/4) so R stays close to the identity as
+//           G approaches diagonal form;
+//   rotate: X <- X R on MFMA, in place.
+// A sweep in which no pair exceeds tol ends the iteration.  Afterwards the
+// columns of W are orthogonal: W_in Q = U Sigma with Q the product of the
+// rotations, so column norms are the singular values and the normalised
+// columns are the left singular vectors.
+#include "common.hpp"
+#include "internal.hpp"
+
+#include <vector>
+
+namespace bse {
+namespace {
+
+constexpr int JB = 32;      // columns per block
+constexpr int JP = 64;      // columns per pair
+constexpr int NTILE = 10;   // 16 x 16 tiles on or below the diagonal of a 64 x 64 Gram
+constexpr int LPAD = 1;
+
+__device__ __constant__ int kTileI[NTILE] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
+__device__ __constant__ int kTileJ[NTILE] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
+
+// Circle-method pairing: position 0 holds block 0, position i > 0 holds block
+// ((i - 1 + t) mod (N - 1)) + 1; pair k joins positions k and N - 1 - k.
+BSE_DEV void round_pair(int N, int t, int k, int& p, int& q) {
+  const int a = k, b = N - 1 - k;
+  p = (a == 0) ? 0 : ((a - 1 + t) % (N - 1)) + 1;
+  q = ((b - 1 + t) % (N - 1)) + 1;
+}
+
+BSE_DEV int pair_col(int p, int q, int c) { return c < JB ? p * JB + c : q * JB + (c - JB); }
+
+// ---------------------------------------------------------------- Gram tiles
+// Workgroup (pair k, chunk c) accumulates the ten lower tiles of X^H X over
+// rows [c * rc, (c + 1) * rc) and writes them to part[(k * kc + c) * 10 + tile].
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_gram(int N, int t, const typename cpx_t<T>::type* __restrict__ W,
+                                                  long ld, int rc, int kc,
+                                                  typename cpx_t<T>::type* __restrict__ part) {
+  typedef typename cpx_t<T>::type C2;
+  typedef typename Mfma<T>::acc Acc;
+  __shared__ T Xs[2][2][16][JP + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = blockIdx.x / kc, c = blockIdx.x % kc;
+  int p, q;
+  round_pair(N, t, k, p, q);
+  // tiles of this wave: 3, 3, 2, 2
+  const int tfirst = wave < 2 ? 3 * wave : 6 + 2 * (wave - 2);
+  const int tcount = wave < 2 ? 3 : 2;
+  Acc cr[3], ci[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { cr[i] = Mfma<T>::zero(); ci[i] = Mfma<T>::zero(); }
+  int ti[3], tj[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const int tt = tfirst + (i < tcount ? i : 0);
+    ti[i] = kTileI[tt]; tj[i] = kTileJ[tt];
+  }
+  const int row_beg = c * rc;
+  C2 reg[4];
+  const int lr = tid & 15;
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cc = (tid >> 4) + 16 * i;
+      reg[i] = W[(long)(r0 + lr) + (long)pair_col(p, q, cc) * ld];
+    }
+  };
+  load(row_beg);
+  int buf = 0;
+  for (int r0 = row_beg; r0 < row_beg + rc; r0 += 16) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int cc = (tid >> 4) + 16 * i;
+      Xs[buf][0][lr][cc] = reg[i].x;
+      Xs[buf][1][lr][cc] = reg[i].y;
+    }
+    __syncthreads();
+    if (r0 + 16 < row_beg + rc) load(r0 + 16);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = 4 * s + (lane >> 4);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        if (i < tcount) {
+          // MFMA A operand: X[kk][16 tj + l%16] (n side); B operand: conj(X[kk][16 ti + l%16]) (m side)
+          const T xr_n = Xs[buf][0][kk][16 * tj[i] + (lane & 15)];
+          const T xi_n = Xs[buf][1][kk][16 * tj[i] + (lane & 15)];
+          const T xr_m = Xs[buf][0][kk][16 * ti[i] + (lane & 15)];
+          const T xi_m = Xs[buf][1][kk][16 * ti[i] + (lane & 15)];
+          cmac<T>(xr_n, xi_n, xr_m, -xi_m, cr[i], ci[i]);
+        }
+      }
+    }
+    buf ^= 1;
+  }
+  // tile element (m_local, n_local) of G = X^H X is stored at m_local + 16 n_local
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (i < tcount) {
+      C2* dst = part + ((long)(k * kc + c) * NTILE + tfirst + i) * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int ml = lane & 15, nl = Mfma<T>::drow(lane, r);
+        C2 v; v.x = cr[i][r]; v.y = ci[i][r];
+        dst[ml + 16 * nl] = v;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- inner eigensolver
+// Eigenvectors of the pair's 64 x 64 Gram by parallel cyclic Jacobi, in FP64.
+// Each step applies 32 disjoint rotations chosen by the circle method on the
+// 64 indices: first the rotation parameters, then every 2 x 2 block of G is
+// replaced by J_P^H G_PQ J_Q (P <= Q, mirrored for P > Q) and the rotated
+// column pairs of R by R J.
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
+                                                 const typename cpx_t<T>::type* __restrict__ part,
+                                                 typename cpx_t<T>::type* __restrict__ Rout,
+                                                 int* __restrict__ flags, int* counter,
+                                                 double tol, double* maxoff, int max_inner) {
+  typedef typename cpx_t<T>::type C2;
+  __shared__ double Gr[JP][JP + LPAD], Gi[JP][JP + LPAD];
+  __shared__ double Rr[JP][JP + LPAD], Ri[JP][JP + LPAD];
+  __shared__ double rc_[32], rsr[32], rsi[32], rdi[32], rdj[32];
+  __shared__ int ri_[32], rj_[32], rrot[32];
+  __shared__ double red[256];
+  __shared__ int nrot;
+  const int tid = threadIdx.x;
+  const int k = blockIdx.x;
+
+  // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian matrix.
+  for (int e = tid; e < NTILE * 256; e += 256) {
+    const int tile = e >> 8, el = e & 255;
+    const int m = 16 * kTileI[tile] + (el & 15), n = 16 * kTileJ[tile] + (el >> 4);
+    if (m < n) continue;
+    double sr = 0.0, si = 0.0;
+    const C2* src = part + ((long)k * kc * NTILE + tile) * 256 + el;
+    for (int c = 0; c < kc; ++c) {
+      const C2 v = src[(long)c * NTILE * 256];
+      sr += (double)v.x;
+      si += (double)v.y;
+    }
+    if (m == n) {
+      Gr[m][m] = sr; Gi[m][m] = 0.0;
+    } else {
+      Gr[m][n] = sr; Gi[m][n] = si;
+      Gr[n][m] = sr; Gi[n][m] = -si;
+    }
+  }
+  __syncthreads();
+
+  // 2. Relative off-diagonal measure of the pair.
+  double off2 = 0.0;
+  for (int e = tid; e < JP * JP; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    if (i > j) {
+      const double dd = Gr[i][i] * Gr[j][j];
+      const double a2 = Gr[i][j] * Gr[i][j] + Gi[i][j] * Gi[i][j];
+      if (dd > 0.0) off2 = fmax(off2, a2 / dd);
+      else if (a2 > 0.0) off2 = 1.0;
+    }
+  }
+  red[tid] = off2;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+    __syncthreads();
+  }
+  const double off = sqrt(red[0]);
+  if (tid == 0) atomic_max_nonneg(maxoff, off);
+  if (!(off > tol)) {
+    if (tid == 0) flags[k] = 0;
+    return;
+  }
+
+  // 3. Cyclic Jacobi.
+  for (int e = tid; e < JP * JP; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    Rr[i][j] = (i == j) ? 1.0 : 0.0;
+    Ri[i][j] = 0.0;
+  }
+  const double tol_in = 4.0e-16;
+  for (int sweep = 0; sweep < max_inner; ++sweep) {
+    if (tid == 0) nrot = 0;
+    __syncthreads();
+    for (int step = 0; step < JP - 1; ++step) {
+      if (tid < 32) {
+        const int a = tid, b = JP - 1 - tid;
+        int i = (a == 0) ? 0 : ((a - 1 + step) % (JP - 1)) + 1;
+        int j = ((b - 1 + step) % (JP - 1)) + 1;
+        if (i > j) { const int tmp = i; i = j; j = tmp; }
+        const double aa = Gr[i][i], dd = Gr[j][j];
+        const double cre = Gr[i][j], cim = Gi[i][j];
+        const double ac = sqrt(cre * cre + cim * cim);
+        int rot = 0;
+        double cs = 1.0, sr = 0.0, si = 0.0, di = aa, dj = dd;
+        if (ac > tol_in * sqrt(fabs(aa * dd)) && ac > 0.0) {
+          rot = 1;
+          const double zeta = (dd - aa) / (2.0 * ac);
+          double tt;
+          if (fabs(zeta) > 1.0e150) tt = 0.5 / zeta;
+          else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          cs = 1.0 / sqrt(1.0 + tt * tt);
+          const double sn = tt * cs;
+          sr = sn * cre / ac;
+          si = sn * cim / ac;
+          di = aa - tt * ac;
+          dj = dd + tt * ac;
+          atomicAdd(&nrot, 1);
+        }
+        ri_[tid] = i; rj_[tid] = j; rrot[tid] = rot;
+        rc_[tid] = cs; rsr[tid] = sr; rsi[tid] = si; rdi[tid] = di; rdj[tid] = dj;
+      }
+      __syncthreads();
+      // 2 x 2 blocks (P, Q), P <= Q: 528 of them.
+      for (int blk = tid; blk < 528; blk += 256) {
+        int Q = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
+        while ((Q + 1) * (Q + 2) / 2 <= blk) ++Q;
+        while (Q * (Q + 1) / 2 > blk) --Q;
+        const int P = blk - Q * (Q + 1) / 2;
+        const int rP = rrot[P], rQ = rrot[Q];
+        if (!rP && !rQ) continue;
+        const int iP = ri_[P], jP = rj_[P], iQ = ri_[Q], jQ = rj_[Q];
+        if (P == Q) {
+          Gr[iP][iP] = rdi[P]; Gi[iP][iP] = 0.0;
+          Gr[jP][jP] = rdj[P]; Gi[jP][jP] = 0.0;
+          Gr[iP][jP] = 0.0; Gi[iP][jP] = 0.0;
+          Gr[jP][iP] = 0.0; Gi[jP][iP] = 0.0;
+          continue;
+        }
+        double2 g00 = make_double2(Gr[iP][iQ], Gi[iP][iQ]);
+        double2 g01 = make_double2(Gr[iP][jQ], Gi[iP][jQ]);
+        double2 g10 = make_double2(Gr[jP][iQ], Gi[jP][iQ]);
+        double2 g11 = make_double2(Gr[jP][jQ], Gi[jP][jQ]);
+        if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
+          const double c = rc_[Q];
+          const double2 sq = make_double2(rsr[Q], rsi[Q]);
+          const double2 sqc = cconj(sq);
+          const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
+          const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
+          const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
+          const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
+          g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+        }
+        if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
+          const double c = rc_[P];
+          const double2 sp = make_double2(rsr[P], rsi[P]);
+          const double2 spc = cconj(sp);
+          const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
+          const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
+          const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
+          const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
+          g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+        }
+        Gr[iP][iQ] = g00.x; Gi[iP][iQ] = g00.y;
+        Gr[iP][jQ] = g01.x; Gi[iP][jQ] = g01.y;
+        Gr[jP][iQ] = g10.x; Gi[jP][iQ] = g10.y;
+        Gr[jP][jQ] = g11.x; Gi[jP][jQ] = g11.y;
+        Gr[iQ][iP] = g00.x; Gi[iQ][iP] = -g00.y;
+        Gr[jQ][iP] = g01.x; Gi[jQ][iP] = -g01.y;
+        Gr[iQ][jP] = g10.x; Gi[iQ][jP] = -g10.y;
+        Gr[jQ][jP] = g11.x; Gi[jQ][jP] = -g11.y;
+      }
+      // R <- R J for the rotated column pairs
+      for (int e = tid; e < 32 * JP; e += 256) {
+        const int m = e >> 6, r = e & 63;
+        if (!rrot[m]) continue;
+        const int i = ri_[m], j = rj_[m];
+        const double c = rc_[m];
+        const double2 s = make_double2(rsr[m], rsi[m]);
+        const double2 ri = make_double2(Rr[r][i], Ri[r][i]);
+        const double2 rj = make_double2(Rr[r][j], Ri[r][j]);
+        const double2 ni = csub(cscale(ri, c), cmul(cconj(s), rj));
+        const double2 nj = cadd(cmul(s, ri), cscale(rj, c));
+        Rr[r][i] = ni.x; Ri[r][i] = ni.y;
+        Rr[r][j] = nj.x; Ri[r][j] = nj.y;
+      }
+      __syncthreads();
+    }
+    if (nrot == 0) break;
+    __syncthreads();
+  }
+
+  // 4. R to global, column-major 64 x 64.
+  C2* dst = Rout + (long)k * JP * JP;
+  for (int e = tid; e < JP * JP; e += 256) {
+    const int i = e & 63, j = e >> 6;
+    C2 v; v.x = (T)Rr[i][j]; v.y = (T)Ri[i][j];
+    dst[i + JP * j] = v;
+  }
+  if (tid == 0) {
+    flags[k] = 1;
+    atomicAdd(counter, 1);
+  }
+}
+
+// ---------------------------------------------------------------- rotation
+// Workgroup (pair k, row chunk): X[rows, :] <- X[rows, :] R, in place.  R goes
+// to LDS once; each wave handles 16-row strips and holds the strip's 16 x 64
+// inputs in registers (loaded as MFMA B operands: 16 consecutive rows of one
+// column per 16 lanes) before writing any output.
+template <typename T>
+__global__ __launch_bounds__(256) void k_jac_rotate(int N, int t, typename cpx_t<T>::type* W, long ld,
+                                                    const typename cpx_t<T>::type* __restrict__ Rall,
+                                                    const int* __restrict__ flags, int rows_per_wg,
+                                                    int chunks) {
+  typedef typename cpx_t<T>::type C2;
+  typedef typename Mfma<T>::acc Acc;
+  __shared__ T Rs[2][JP][JP + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int k = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
+  if (!flags[k]) return;
+  int p, q;
+  round_pair(N, t, k, p, q);
+  const C2* R = Rall + (long)k * JP * JP;
+  for (int e = tid; e < JP * JP; e += 256) {
+    const int i = e & 63, j = e >> 6;  // R[i][j], i = k index, j = n index
+    const C2 v = R[i + JP * j];
+    Rs[0][i][j] = v.x;
+    Rs[1][i][j] = v.y;
+  }
+  __syncthreads();
+  const int strips = rows_per_wg / 64;
+  for (int sidx = 0; sidx < strips; ++sidx) {
+    const int row0 = chunk * rows_per_wg + (sidx * 4 + wave) * 16;
+    C2 xf[16];
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int cidx = 4 * kk + (lane >> 4);
+      xf[kk] = W[(long)(row0 + (lane & 15)) + (long)pair_col(p, q, cidx) * ld];
+    }
+#pragma unroll 1
+    for (int tj = 0; tj < 4; ++tj) {
+      Acc cr = Mfma<T>::zero(), ci = Mfma<T>::zero();
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) {
+        const int kr = 4 * kk + (lane >> 4);
+        const T rr = Rs[0][kr][16 * tj + (lane & 15)];
+        const T ri = Rs[1][kr][16 * tj + (lane & 15)];
+        cmac<T>(rr, ri, xf[kk].x, xf[kk].y, cr, ci);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int n = 16 * tj + Mfma<T>::drow(lane, r);
+        C2 v; v.x = cr[r]; v.y = ci[r];
+        W[(long)(row0 + (lane & 15)) + (long)pair_col(p, q, n) * ld] = v;
+      }
+    }
+  }
+}
+
+int gram_chunks(int np, int pairs) {
+  // enough workgroups to fill the chip, rows per chunk a multiple of 16
+  int kc = 1;
+  const int rows16 = np / 16;
+  while (pairs * kc < 1024 && kc * 2 <= rows16 && (np % (kc * 2 * 16)) == 0 && kc < 64) kc *= 2;
+  return kc;
+}
+
+int rotate_rows(int np) {
+  if (np % 256 == 0) return 256;
+  if (np % 128 == 0) return 128;
+  return 64;
+}
+
+}  // namespace
+
+size_t jacobi_work_bytes(int np, int elem_bytes) {
+  const int N = np / JB, pairs = N / 2;
+  const int kc = gram_chunks(np, pairs);
+  size_t b = 0;
+  b += (size_t)pairs * kc * NTILE * 256 * 2 * elem_bytes;  // part
+  b = (b + 255) & ~(size_t)255;
+  b += (size_t)pairs * JP * JP * 2 * elem_bytes;           // R
+  b = (b + 255) & ~(size_t)255;
+  b += (size_t)pairs * sizeof(int) + 256;                  // flags
+  b += 256 + 256;                                          // counter, maxoff
+  return (b + 255) & ~(size_t)255;
+}
+
+void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w) {
+  const int N = np / JB, pairs = N / 2;
+  const int kc = gram_chunks(np, pairs);
+  size_t o = 0;
+  w.part = base + o;
+  o += (size_t)pairs * kc * NTILE * 256 * 2 * elem_bytes;
+  o = (o + 255) & ~(size_t)255;
+  w.R = base + o;
+  o += (size_t)pairs * JP * JP * 2 * elem_bytes;
+  o = (o + 255) & ~(size_t)255;
+  w.flags = reinterpret_cast<int*>(base + o);
+  o += (size_t)pairs * sizeof(int) + 256;
+  o = (o + 255) & ~(size_t)255;
+  w.counter = reinterpret_cast<int*>(base + o);
+  w.maxoff = reinterpret_cast<double*>(base + o + 64);
+}
+
+hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels) {
+  const int N = np / JB, pairs = N / 2;
+  const int kc = gram_chunks(np, pairs);
+  const int rc = np / kc;
+  const int rrows = rotate_rows(np);
+  const int chunks = np / rrows;
+  res = JacobiResult();
+  hipError_t e;
+  // Optional per-launch timing: an event before and after every Jacobi kernel.
+  std::vector<hipEvent_t> ev;
+  if (time_kernels) {
+    ev.resize((size_t)(N - 1) * 6);
+    for (auto& x : ev) {
+      e = hipEventCreate(&x);
+      if (e != hipSuccess) return e;
+    }
+  }
+  auto mark = [&](size_t i) {
+    if (time_kernels) (void)hipEventRecord(ev[i], s);
+  };
+  hipError_t ret = hipSuccess;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    e = hipMemsetAsync(w.counter, 0, 128, s);
+    if (e != hipSuccess) { ret = e; break; }
+    for (int t = 0; t < N - 1; ++t) {
+      const size_t b = (size_t)t * 6;
+      mark(b + 0);
+      k_jac_gram<double><<<pairs * kc, 256, 0, s>>>(N, t, W, ld, rc, kc, (double2*)w.part);
+      mark(b + 1);
+      mark(b + 2);
+      k_jac_eig<double><<<pairs, 256, 0, s>>>(N, t, kc, (const double2*)w.part, (double2*)w.R,
+                                              w.flags, w.counter, tol, w.maxoff, 30);
+      mark(b + 3);
+      mark(b + 4);
+      k_jac_rotate<double><<<pairs * chunks, 256, 0, s>>>(N, t, W, ld, (const double2*)w.R,
+                                                          w.flags, rrows, chunks);
+      mark(b + 5);
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) { ret = e; break; }
+    int cnt = 0;
+    double mo = 0.0;
+    e = hipMemcpyAsync(&cnt, w.counter, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&mo, w.maxoff, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) { ret = e; break; }
+    if (time_kernels) {
+      for (int t = 0; t < N - 1; ++t)
+        for (int kx = 0; kx < 3; ++kx) {
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, ev[(size_t)t * 6 + 2 * kx], ev[(size_t)t * 6 + 2 * kx + 1]);
+          res.kernel_ms[kx] += ms;
+          res.kernel_launches[kx] += 1;
+        }
+    }
+    res.sweeps = sweep + 1;
+    res.rotations += cnt;
+    res.pair_checks += pairs * (N - 1);
+    res.max_off = mo;
+    if (cnt == 0) { res.converged = 1; break; }
+  }
+  for (auto& x : ev) (void)hipEventDestroy(x);
+  return ret;
+}
+
+}  // namespace bse

@@ -1,0 +1,199 @@
+"""Parity of the HIP solver (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (FP64 form): eigenvalues are column norms after a one-sided Jacobi
+SVD whose rotations stop below a relative off-orthogonality of n * eps, so
+the relative eigenvalue error is bounded by a small multiple of
+eps * cond(H1) (Sec. 3.4 error estimate for the SVD route); cond(H1) is below
+100 for these inputs, giving the 1e-12 bound used here.  Eigenvectors are
+unique up to a phase (and only as a subspace inside clusters), so they are
+compared phase-aligned with a gap-dependent allowance, and through the
+residual and the Sigma-orthogonality (Fig. 2 measure).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bse as ob
+from oracle import metrics as om
+from paper_2008_08825_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def run(api, A, B, **kw):
+    print(f"[gpu] solve n={A.shape[0]} {kw}", flush=True)
+    lam, X, info = api.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV), **kw)
+    return lam.cpu().numpy(), X.resolve_conj().cpu().numpy(), info
+
+
+def check_against_oracle(A, B, lam, X, eig_tol=1e-12, vec_scale=1e-13):
+    n = A.shape[0]
+    lam_o, X_o = ob.solve_chol_svd(A, B)
+    e = om.rel_eig_err(lam[:n], lam_o)
+    assert e < eig_tol, e
+    assert om.residual(A, B, lam[:n], X[:, :n]) < 5e-14
+    assert om.sigma_orth_err(X[:, :n]) < 1e-12 * max(1, n) ** 0.5 * 10
+    err, gap = om.eigvec_errors(lam_o, X_o, X[:, :n], cluster_rtol=1e-9)
+    allow = 1e-11 + vec_scale / np.minimum(gap, 1.0)
+    assert np.all(err <= allow), (np.max(err / allow), np.argmax(err / allow))
+    return e
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 64, 65, 100, 130])
+def test_parity_small_sizes(gpu_lib, n):
+    A, B = inputs.coupled(n, seed=n, diag_lo=1.0, diag_hi=10.0, c_norm=0.3, b_norm=0.3)
+    lam, X, info = run(gpu_lib, A, B)
+    assert info["status"] == 0
+    check_against_oracle(A, B, lam, X)
+
+
+def test_parity_n256_workload(gpu_lib):
+    """The n = 256 workload (D ~ U[2, 6], coupling norms 0.5, seed 0)."""
+    A, B = inputs.workload("n256")
+    lam, X, info = run(gpu_lib, A, B)
+    assert info["status"] == 0 and info["sweeps"] >= 2
+    check_against_oracle(A, B, lam, X)
+
+
+def test_n1_closed_form(gpu_lib):
+    for a, b in [(2.0, 0.5), (3.0, -1.2), (5.0, 4.9)]:
+        lam, X, _ = run(gpu_lib, np.array([[a]], complex), np.array([[b]], complex))
+        ref = np.sqrt((a + b) * (a - b))
+        assert abs(lam[0] - ref) < 1e-14 * ref * (a + abs(b)) / (a - abs(b))
+        x = ((a + b) / (a - b)) ** 0.25
+        y = 1 / x
+        Xr = np.array([(x + y) / 2, (y - x) / 2])
+        ph = X[0, 0] / Xr[0]
+        assert abs(abs(ph) - 1) < 1e-13
+        assert np.allclose(X[:, 0], ph * Xr, atol=1e-13)
+
+
+def test_negative_half_and_pairing(gpu_lib):
+    n = 80
+    A, B = inputs.coupled(n, seed=5)
+    lam, X, _ = run(gpu_lib, A, B, want_negative=True)
+    assert lam.shape == (2 * n,) and X.shape == (2 * n, 2 * n)
+    assert np.array_equal(lam[n:], -lam[:n])
+    H = ob.bse_matrix(A, B)
+    R = H @ X - X * lam[None, :]
+    assert np.linalg.norm(R) < 1e-13 * np.linalg.norm(H) * np.linalg.norm(X)
+    sig = np.concatenate([np.ones(n), -np.ones(n)])
+    G = X.conj().T @ (sig[:, None] * X)
+    assert np.linalg.norm(G - np.diag(np.concatenate([np.ones(n), -np.ones(n)]))) < 1e-11
+
+
+def test_lower_triangle_only_and_layouts(gpu_lib):
+    n = 70
+    A, B = inputs.coupled(n, seed=6)
+    lam, X, _ = run(gpu_lib, A, B)
+    lam2, X2, _ = run(gpu_lib, inputs.garbage_upper(A, 1), inputs.garbage_upper(B, 2))
+    assert np.array_equal(lam, lam2) and np.array_equal(X, X2)
+    # column-major tensors take the 'L' path of the ABI; same eigenvalues, same eigenvectors
+    At = torch.from_numpy(A).to(DEV).mT.contiguous().mT
+    Bt = torch.from_numpy(B).to(DEV).mT.contiguous().mT
+    lam3, X3, _ = gpu_lib.solve_h1(At, Bt)
+    lam3 = lam3.cpu().numpy()
+    X3 = X3.resolve_conj().cpu().numpy()
+    assert om.rel_eig_err(lam3, lam) < 1e-13
+    err, _ = om.eigvec_errors(lam, X, X3)
+    assert np.max(err) < 1e-9
+
+
+def test_real_input(gpu_lib):
+    n = 50
+    A, B = inputs.coupled(n, seed=8, real=True)
+    lam, X, _ = run(gpu_lib, A, B)
+    check_against_oracle(A, B, lam, X)
+
+
+def test_tamm_dancoff(gpu_lib):
+    n = 90
+    A, _ = inputs.coupled(n, seed=9)
+    B = np.zeros_like(A)
+    lam, X, _ = run(gpu_lib, A, B)
+    assert om.rel_eig_err(lam, np.linalg.eigvalsh(A)) < 1e-12
+
+
+def test_condition_family(gpu_lib):
+    """Sec. 4 generator with closed-form eigenvalues sqrt(3)/2 d (kappa = 10 and 1e3).
+
+    Bound: n * eps * kappa, the error level of a Gram-based Jacobi SVD on a
+    matrix whose singular values span kappa (Table 2 gives LAPACK's level for
+    the smallest eigenvalue alone).
+    """
+    n = 200
+    for kappa in (10.0, 1e3):
+        A, B, d = inputs.condition_family(n, kappa, seed=1)
+        lam, X, _ = run(gpu_lib, A, B)
+        exact = np.sqrt(3) / 2 * d
+        e = om.rel_eig_err(lam, exact)
+        print(f"kappa={kappa:g} rel_eig_err={e:.3e}")
+        assert e < n * np.finfo(float).eps * kappa
+        assert om.residual(A, B, lam, X) < 1e-13
+
+
+@pytest.mark.parametrize("which", ["plus", "minus"])
+def test_non_hpd_status(gpu_lib, which):
+    n = 75
+    A, B = inputs.coupled(n, seed=11, diag_lo=1.0, diag_hi=2.0, c_norm=0.1, b_norm=0.1)
+    k = 67
+    B2 = B.copy()
+    if which == "minus":
+        B2[k, k] = A[k, k].real + 1.0
+    else:
+        B2[k, k] = -A[k, k].real - 1.0
+    expect = ob.chol_status(A, B2)
+    assert expect == (k + 1 if which == "plus" else n + k + 1)
+    lam, X, info = gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B2).to(DEV), check=False)
+    assert info["status"] == expect
+    with pytest.raises(gpu_lib.BSEError):
+        gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B2).to(DEV))
+
+
+def test_empty(gpu_lib):
+    z = torch.zeros((0, 0), dtype=torch.complex128, device=DEV)
+    lam, X, info = gpu_lib.solve_h1(z, z)
+    assert lam.shape == (0,) and X.shape == (0, 0) and info["status"] == 0
+
+
+def test_max_sweeps_status(gpu_lib):
+    n = 128
+    A, B = inputs.coupled(n, seed=12)
+    _, _, info = gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV),
+                                  max_sweeps=1, check=False)
+    assert info["status"] == 2 * n + 1 and info["sweeps"] == 1
+
+
+def test_deterministic(gpu_lib):
+    n = 150
+    A, B = inputs.coupled(n, seed=13)
+    lam1, X1, _ = run(gpu_lib, A, B)
+    lam2, X2, _ = run(gpu_lib, A, B)
+    assert np.array_equal(lam1, lam2) and np.array_equal(X1, X2)
+
+
+def test_backward_matches_oracle_gradient(gpu_lib):
+    n = 120
+    A, B = inputs.coupled(n, seed=14)
+    lam, X, _ = run(gpu_lib, A, B)
+    w = ob.spectrum_loss_weights(lam, k_low=16, n_omega=64)
+    GA, GB = gpu_lib.backward(torch.from_numpy(X).to(DEV), torch.from_numpy(w).to(DEV))
+    lam_o, X_o = ob.solve_chol_svd(A, B)
+    GA_o, GB_o = ob.grad_from_eigenpairs(X_o, w)
+    for G, Go in [(GA.cpu().numpy(), GA_o), (GB.cpu().numpy(), GB_o)]:
+        assert np.linalg.norm(G - Go) / np.linalg.norm(Go) < 1e-10
+        assert np.allclose(G, G.conj().T, atol=1e-12)
+
+
+def test_autograd_closed_form(gpu_lib):
+    """L = sum lambda^2 = ||A||_F^2 - ||B||_F^2 gives G_A = 2A, G_B = -2B."""
+    n = 64
+    A, B = inputs.coupled(n, seed=15)
+    At = torch.from_numpy(A).to(DEV).requires_grad_(True)
+    Bt = torch.from_numpy(B).to(DEV).requires_grad_(True)
+    lam, X = gpu_lib.BSEEig.apply(At, Bt)
+    (lam ** 2).sum().backward()
+    assert torch.allclose(At.grad, 2 * At.detach(), atol=1e-11)
+    assert torch.allclose(Bt.grad, -2 * Bt.detach(), atol=1e-11)

@@ -1,0 +1,58 @@
+"""The C-ABI library loads on the host and exports every symbol include/bse.h declares (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bse.h")
+LIB = os.path.join(ROOT, "paper_2008_08825_amd", "libbse.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(bse_[a-z0-9_]+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for required in ["bse_solve_h1", "bse_solve_batched", "bse_backward", "bse_workspace_bytes"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.fail("libbse.so is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_host_only_queries():
+    """Workspace queries and argument checks run on the host without touching a GPU."""
+    from paper_2008_08825_amd import api
+
+    lib = api.load_library()
+    o = api.make_opts()
+    assert lib.bse_workspace_bytes(0, ctypes.byref(o)) > 0
+    b256 = lib.bse_workspace_bytes(256, ctypes.byref(o))
+    b300 = lib.bse_workspace_bytes(300, ctypes.byref(o))
+    assert 0 < b256 < b300
+    assert lib.bse_workspace_bytes(-1, ctypes.byref(o)) == 0
+    bad = api.make_opts()
+    bad.reserved[0] = 1
+    assert lib.bse_workspace_bytes(10, ctypes.byref(bad)) == 0
+    info = api.BSEInfo()
+    # argument errors are detected before any device work
+    assert lib.bse_solve_h1(-1, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), ctypes.byref(info), None) == -1
+    assert lib.bse_solve_h1(4, None, 4, None, 4, None, None, 8, None, 0, ctypes.byref(o), ctypes.byref(info), None) == -2
+    assert lib.bse_solve_h1(4, 16, 3, 16, 4, 16, 16, 8, None, 0, ctypes.byref(o), ctypes.byref(info), None) == -3
+    assert lib.bse_solve_h1(4, 16, 4, 16, 4, 16, 16, 7, None, 0, ctypes.byref(o), ctypes.byref(info), None) == -8
+    assert lib.bse_solve_h1(4, 16, 4, 16, 4, 16, 16, 8, None, 0, ctypes.byref(o), ctypes.byref(info), None) == -9
+    assert lib.bse_solve_h1(4, 16, 4, 16, 4, 16, 16, 8, 16, 10, ctypes.byref(o), ctypes.byref(info), None) == -10
+    assert lib.bse_solve_h1(0, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), ctypes.byref(info), None) == 0
+    assert lib.bse_backward(-1, None, 1, None, None, 1, None, 1, None, 0, None) == -1
+    assert lib.bse_status_string(5, 4).decode() == "A - B is not positive definite"
