@@ -102,7 +102,7 @@ def main():
     ap.add_argument("--n", type=int, default=None, help="override the workload size")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--route", default="svd", choices=["svd", "eig"])
-    ap.add_argument("--cpu-sample-n", type=int, default=2048)
+    ap.add_argument("--cpu-sample-n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-checks", action="store_true")
     args = ap.parse_args()

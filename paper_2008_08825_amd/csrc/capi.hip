@@ -5,12 +5,14 @@
 //   chol      L1 L1^H = M1, L2 L2^H = M2            (Alg. 3 steps 1-2)
 //   W         W = L2^H L1 = (L1^H L2)^H             (step 3's matrix, transposed)
 //   jacobi    one-sided block Jacobi: W U = V Lambda (step 3)
-//   finalize  lambda = column norms, ascending; Ws = V Lambda^-1/2
+//   finalize  Ws = W_out diag(column norms)^-3/2 = V Lambda^-1/2
 //   back      V2 = L2 Ws = L2 V Lambda^-1/2          (step 5)
-//             V1 = L1 (L1^H V2) Lambda^-1 = M1 V2 Lambda^-1 = L1 U Lambda^-1/2
+//             T = L1^H V2; lambda_k = ||T_k|| / ||Ws_k|| (Rayleigh quotient)
+//             V1 = L1 T Lambda^-1 = M1 V2 Lambda^-1 = L1 U Lambda^-1/2
 //                                                    (step 4 via Lemma SVDScalarFactors)
-//   assemble  X = [(V1 + V2)/2; (V2 - V1)/2]         (step 6)
+//   assemble  X = [(V1 + V2)/2; (V2 - V1)/2], ascending lambda (step 6)
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "../../include/bse.h"
@@ -30,6 +32,7 @@ struct Plan {
   int n = 0, np = 0;
   size_t off_m1 = 0, off_m2 = 0, off_w = 0, off_y = 0;
   size_t off_linv = 0, off_sigma = 0, off_perm = 0, off_invlam = 0, off_status = 0;
+  size_t off_bnorm = 0, off_anorm = 0, off_lamu = 0, off_scl = 0;
   size_t off_jac = 0;
   size_t total = 0;
 };
@@ -58,6 +61,10 @@ Plan make_plan(int n) {
   p.off_sigma = o; o = align256(o + (size_t)p.np * sizeof(double));
   p.off_perm = o; o = align256(o + (size_t)p.np * sizeof(int));
   p.off_invlam = o; o = align256(o + (size_t)p.np * sizeof(double));
+  p.off_bnorm = o; o = align256(o + (size_t)p.np * sizeof(double));
+  p.off_anorm = o; o = align256(o + (size_t)p.np * sizeof(double));
+  p.off_lamu = o; o = align256(o + (size_t)p.np * sizeof(double));
+  p.off_scl = o; o = align256(o + (size_t)p.np * sizeof(double));
   p.off_status = o; o = align256(o + 64);
   p.off_jac = o; o = align256(o + jacobi_work_bytes(p.np, sizeof(double)));
   p.total = o + 256;  // slack for aligning the caller's base pointer
@@ -159,6 +166,10 @@ int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb, double* 
   double* sigma = reinterpret_cast<double*>(base + p.off_sigma);
   int* perm = reinterpret_cast<int*>(base + p.off_perm);
   double* invlam = reinterpret_cast<double*>(base + p.off_invlam);
+  double* bnorm = reinterpret_cast<double*>(base + p.off_bnorm);
+  double* anorm = reinterpret_cast<double*>(base + p.off_anorm);
+  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
+  double* scl = reinterpret_cast<double*>(base + p.off_scl);
   int* status = reinterpret_cast<int*>(base + p.off_status);
   JacobiWork jw;
   jacobi_carve(np, sizeof(double), base + p.off_jac, jw);
@@ -196,32 +207,36 @@ int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb, double* 
   JacobiResult jr;
   BSE_TRY(jacobi_z(np, W, ld, jw, tol, max_sweeps, jr, s, want_timing >= 2));
   tm.mark();
-  BSE_TRY(finalize_sort_z(n, np, W, ld, sigma, perm, lambda, o.want_negative, invlam, Y, s));
+  // Ws = W sigma^-3/2 in place; bnorm = ||Ws_k||
+  BSE_TRY(scale_singular_cols_z(n, np, W, ld, sigma, bnorm, s));
   tm.mark();
   {
-    // V2 = L2 Ws  (Ws in Y, result to W)
+    // V2 = L2 Ws  (to Y)
     GemmDesc g;
     g.M = np; g.N = np; g.K = np;
     g.A = M2; g.lda = ld; g.opA = 0; g.triA = 1;
-    g.B = Y; g.ldb = ld; g.opB = 0;
-    g.C = W; g.ldc = ld;
+    g.B = W; g.ldb = ld; g.opB = 0;
+    g.C = Y; g.ldc = ld;
     BSE_TRY(gemm_z(g, s));
-    // T = L1^H V2 Lambda^-1  (to Y)
+    // T = L1^H V2  (to W)
     GemmDesc h;
     h.M = np; h.N = np; h.K = np;
     h.A = M1; h.lda = ld; h.opA = 1; h.triA = 1;
-    h.B = W; h.ldb = ld; h.opB = 0;
-    h.C = Y; h.ldc = ld; h.colscale = invlam;
+    h.B = Y; h.ldb = ld; h.opB = 0;
+    h.C = W; h.ldc = ld;
     BSE_TRY(gemm_z(h, s));
-    // V1 = L1 T  (to M2: L2 is no longer needed)
+    // Rayleigh-quotient eigenvalues, scales and the ascending order
+    BSE_TRY(rq_lambda_z(n, np, W, ld, bnorm, anorm, lamu, invlam, scl, perm, lambda,
+                        o.want_negative, s));
+    // V1 = L1 T Lambda^-1  (to M2: L2 is no longer needed)
     GemmDesc v;
     v.M = np; v.N = np; v.K = np;
     v.A = M1; v.lda = ld; v.opA = 0; v.triA = 1;
-    v.B = Y; v.ldb = ld; v.opB = 0;
-    v.C = M2; v.ldc = ld;
+    v.B = W; v.ldb = ld; v.opB = 0;
+    v.C = M2; v.ldc = ld; v.colscale = invlam;
     BSE_TRY(gemm_z(v, s));
   }
-  BSE_TRY(assemble_z(n, M2, W, ld, static_cast<double2*>(X), ldx, o.want_negative, s));
+  BSE_TRY(assemble_z(n, M2, Y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
   tm.mark();
   BSE_TRY(hipStreamSynchronize(s));
   int ret = jr.converged ? 0 : 2 * n + 1;

@@ -1,13 +1,21 @@
 // Finalisation of the SVD route and the final setup of Alg. 3.
 //
 // After the Jacobi iteration W_out = L2^H L1 U (U the accumulated rotations)
-// has orthogonal columns w_j = sigma_j v_j (paper notation of Lemma
-// SVDScalarFactors, where L1^H L2 = U Lambda V^H, so W = V Lambda U^H):
-//   lambda_j = sigma_j = ||w_j||              (ascending, stable by index)
-//   Ws[:, r] = w_perm(r) sigma^-3/2 = v sigma^-1/2   so that  V2 = L2 Ws,
-// and V1 follows from the Lemma's relation M1 V2 = V1 Lambda.
-// The final setup (Alg. 3 step 6) is X = [(V1 + V2)/2; (V2 - V1)/2]; the
-// negative half is [0 I; I 0] X with eigenvalues -lambda (Lemma ComputeNegEvecs).
+// has orthogonal columns w_k = sigma_k v_k (paper notation of Lemma
+// SVDScalarFactors, where L1^H L2 = U Lambda V^H, so W = V Lambda U^H).
+//   Ws = W_out diag(sigma)^-3/2      so that V2 = L2 Ws = L2 V Lambda^-1/2,
+//   T  = L1^H V2                     (= U Lambda^1/2 in exact arithmetic),
+//   V1 = L1 T Lambda^-1              (= M1 V2 Lambda^-1, the Lemma's relation).
+// Eigenvalues: y = V2_k is an eigenvector of the Hermitian-definite pencil
+// (M1, M2^-1) with eigenvalue lambda_k^2, so its Rayleigh quotient
+//   lambda_k^2 = (y^H M1 y) / (y^H M2^-1 y) = ||T_k||^2 / ||Ws_k||^2
+// is accurate to second order in the error of y; it replaces the column norm
+// sigma_k, whose error grows with the number of rotations a column went
+// through.  Each pair (V1_k, V2_k) is scaled by s_k = (||T_k|| ||Ws_k||)^-1/2
+// so that V1_k^H V2_k = 1 exactly as in the Lemma.  The eigenvalues are
+// sorted ascending (stable by index) and the final setup (Alg. 3 step 6)
+// writes X = [(V1 + V2)/2; (V2 - V1)/2] in that order; the negative half is
+// [0 I; I 0] X with eigenvalues -lambda (Lemma ComputeNegEvecs).
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -30,16 +38,18 @@ __global__ __launch_bounds__(256) void k_colnorm(const double2* __restrict__ W, 
   if (tid == 0) sigma[j] = sqrt(red[0]);
 }
 
-// rank_j = #{i : sigma_i < sigma_j or (sigma_i == sigma_j and i < j)}; perm[rank_j] = j.
+// rank_j = #{i : key_i < key_j or (key_i == key_j and i < j)}; perm[rank_j] = j,
+// key = sigma (ascending) or -sigma (descending).
 __global__ __launch_bounds__(256) void k_rank(int n, const double* __restrict__ sigma,
-                                              int* __restrict__ perm) {
+                                              int* __restrict__ perm, int desc) {
   __shared__ double sv[256];
+  const double sg = desc ? -1.0 : 1.0;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  const double s = j < n ? sigma[j] : 0.0;
+  const double s = j < n ? sg * sigma[j] : 0.0;
   int rank = 0;
   for (int base = 0; base < n; base += 256) {
     const int i = base + threadIdx.x;
-    sv[threadIdx.x] = i < n ? sigma[i] : 0.0;
+    sv[threadIdx.x] = i < n ? sg * sigma[i] : 0.0;
     __syncthreads();
     const int lim = min(256, n - base);
     for (int q = 0; q < lim; ++q) {
@@ -51,40 +61,64 @@ __global__ __launch_bounds__(256) void k_rank(int n, const double* __restrict__ 
   if (j < n) perm[rank] = j;
 }
 
-__global__ __launch_bounds__(256) void k_gather(int n, int np, const double2* __restrict__ W, long ld,
-                                                const double* __restrict__ sigma,
-                                                const int* __restrict__ perm, double* __restrict__ lambda,
-                                                int want_negative, double* __restrict__ invlam,
-                                                double2* __restrict__ Ws) {
-  const int r = blockIdx.y;
+__global__ __launch_bounds__(256) void k_scale_cols(int n, int np, double2* __restrict__ W, long ld,
+                                                    const double* __restrict__ sigma) {
+  const int k = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) {
-    if (i < np) Ws[i + (long)r * ld] = make_double2(0.0, 0.0);
-    if (i == 0) invlam[r] = 0.0;
-    return;
+  if (i >= np) return;
+  double f = 0.0;
+  if (k < n) {
+    const double sg = sigma[k];
+    f = sg > 0.0 ? 1.0 / (sg * sqrt(sg)) : 0.0;
   }
+  W[i + (long)k * ld] = cscale(W[i + (long)k * ld], f);
+}
+
+__global__ __launch_bounds__(256) void k_lambda(int n, int np, const double* __restrict__ anorm,
+                                                const double* __restrict__ bnorm,
+                                                double* __restrict__ lam, double* __restrict__ invlam,
+                                                double* __restrict__ scl) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= np) return;
+  if (k < n) {
+    const double a = anorm[k], b = bnorm[k];
+    const double l = a / b;
+    lam[k] = l;
+    invlam[k] = 1.0 / l;
+    scl[k] = 1.0 / sqrt(a * b);
+  } else {
+    lam[k] = 0.0;
+    invlam[k] = 0.0;
+    scl[k] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_write_lambda(int n, const double* __restrict__ lam,
+                                                      const int* __restrict__ perm,
+                                                      double* __restrict__ lambda, int want_negative) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
   int j = perm[r];
-  if (j < 0 || j >= n) j = r;  // only if sigma held NaN (ranks then collide)
-  const double s = sigma[j];
-  const double f = 1.0 / (s * sqrt(s));
-  if (i < np) Ws[i + (long)r * ld] = cscale(W[i + (long)j * ld], f);
-  if (i == 0) {
-    lambda[r] = s;
-    if (want_negative) lambda[n + r] = -s;
-    invlam[r] = 1.0 / s;
-  }
+  if (j < 0 || j >= n) j = r;  // only if a value was NaN (ranks then collide)
+  lambda[r] = lam[j];
+  if (want_negative) lambda[n + r] = -lam[j];
 }
 
 __global__ __launch_bounds__(256) void k_assemble(int n, const double2* __restrict__ V1,
                                                   const double2* __restrict__ V2, long ldv,
+                                                  const int* __restrict__ perm,
+                                                  const double* __restrict__ scl,
                                                   double2* __restrict__ X, long ldx, int want_negative) {
   const int r = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const double2 a = V1[i + (long)r * ldv];
-  const double2 b = V2[i + (long)r * ldv];
-  const double2 top = cscale(cadd(a, b), 0.5);
-  const double2 bot = cscale(csub(b, a), 0.5);
+  int k = perm[r];
+  if (k < 0 || k >= n) k = r;
+  const double sc = 0.5 * scl[k];
+  const double2 a = V1[i + (long)k * ldv];
+  const double2 b = V2[i + (long)k * ldv];
+  const double2 top = cscale(cadd(a, b), sc);
+  const double2 bot = cscale(csub(b, a), sc);
   X[i + (long)r * ldx] = top;
   X[n + i + (long)r * ldx] = bot;
   if (want_negative) {
@@ -95,20 +129,34 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const double2* __restri
 
 }  // namespace
 
-hipError_t finalize_sort_z(int n, int np, const double2* W, long ld, double* sigma, int* perm,
-                           double* lambda, int want_negative, double* invlam, double2* Ws,
-                           hipStream_t s) {
-  k_colnorm<<<np, 256, 0, s>>>(W, ld, np, sigma);
-  k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, sigma, perm);
-  dim3 g((np + 255) / 256, np);
-  k_gather<<<g, 256, 0, s>>>(n, np, W, ld, sigma, perm, lambda, want_negative, invlam, Ws);
+hipError_t colnorm_z(int np, const double2* W, long ld, double* out, hipStream_t s) {
+  k_colnorm<<<np, 256, 0, s>>>(W, ld, np, out);
   return hipGetLastError();
 }
 
-hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, double2* X, long ldx,
-                      int want_negative, hipStream_t s) {
+hipError_t scale_singular_cols_z(int n, int np, double2* W, long ld, double* sigma, double* bnorm,
+                                 hipStream_t s) {
+  k_colnorm<<<np, 256, 0, s>>>(W, ld, np, sigma);
+  dim3 g((np + 255) / 256, np);
+  k_scale_cols<<<g, 256, 0, s>>>(n, np, W, ld, sigma);
+  k_colnorm<<<np, 256, 0, s>>>(W, ld, np, bnorm);
+  return hipGetLastError();
+}
+
+hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* bnorm, double* anorm,
+                       double* lam, double* invlam, double* scl, int* perm, double* lambda,
+                       int want_negative, hipStream_t s) {
+  k_colnorm<<<np, 256, 0, s>>>(T, ld, np, anorm);
+  k_lambda<<<(np + 255) / 256, 256, 0, s>>>(n, np, anorm, bnorm, lam, invlam, scl);
+  k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
+  k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);
+  return hipGetLastError();
+}
+
+hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
+                      const double* scl, double2* X, long ldx, int want_negative, hipStream_t s) {
   dim3 g((n + 255) / 256, n);
-  k_assemble<<<g, 256, 0, s>>>(n, V1, V2, ldv, X, ldx, want_negative);
+  k_assemble<<<g, 256, 0, s>>>(n, V1, V2, ldv, perm, scl, X, ldx, want_negative);
   return hipGetLastError();
 }
 

@@ -49,6 +49,7 @@ struct JacobiWork {
   void* R = nullptr;       // rotations, pairs x 64 x 64
   int* flags = nullptr;    // per pair
   int* counter = nullptr;  // rotated pairs in the current sweep
+  int* inner = nullptr;    // inner Jacobi sweeps in the current sweep
   double* maxoff = nullptr;
 };
 size_t jacobi_work_bytes(int np, int elem_bytes);
@@ -58,6 +59,7 @@ struct JacobiResult {
   int sweeps = 0;
   int rotations = 0;
   int pair_checks = 0;
+  long inner_sweeps = 0;
   double max_off = 0.0;
   int converged = 0;
   // per-kernel event timing (filled when time_kernels is set)
@@ -70,14 +72,23 @@ struct JacobiResult {
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
                     int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false);
 
-// Finalisation of the SVD route: sigma_j = ||W[:, j]||, ascending order of the
-// first n, lambda, inverse lambda and Ws[:, r] = W[:, perm r] sigma^-3/2.
-hipError_t finalize_sort_z(int n, int np, const double2* W, long ld, double* sigma,
-                           int* perm, double* lambda, int want_negative,
-                           double* invlam, double2* Ws, hipStream_t s);
+// Column norms out[j] = ||W[:, j]|| for j < np.
+hipError_t colnorm_z(int np, const double2* W, long ld, double* out, hipStream_t s);
 
-// X = [(V1 + V2)/2; (V2 - V1)/2] (and the mirrored negative half).
-hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv,
-                      double2* X, long ldx, int want_negative, hipStream_t s);
+// sigma_k = ||W_k||; W_k <- W_k sigma_k^-3/2 (k < n; zero for k >= n); bnorm_k = ||W_k||.
+hipError_t scale_singular_cols_z(int n, int np, double2* W, long ld, double* sigma,
+                                 double* bnorm, hipStream_t s);
+
+// Rayleigh-quotient eigenvalues lam_k = ||T_k|| / bnorm_k (unsorted), 1 / lam,
+// the Sigma-normalising scale s_k, the ascending order perm and the output
+// lambda (with -lambda appended if want_negative).
+hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* bnorm,
+                       double* anorm, double* lam, double* invlam, double* scl, int* perm,
+                       double* lambda, int want_negative, hipStream_t s);
+
+// X[:, r] = s_k [(V1_k + V2_k)/2; (V2_k - V1_k)/2] with k = perm[r] (and the
+// mirrored negative half).
+hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
+                      const double* scl, double2* X, long ldx, int want_negative, hipStream_t s);
 
 }  // namespace bse

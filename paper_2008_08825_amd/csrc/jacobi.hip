@@ -18,6 +18,9 @@
 #include "common.hpp"
 #include "internal.hpp"
 
+#include <stdio.h>
+#include <stdlib.h>
+
 #include <vector>
 
 namespace bse {
@@ -131,16 +134,24 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
                                                  const typename cpx_t<T>::type* __restrict__ part,
                                                  typename cpx_t<T>::type* __restrict__ Rout,
                                                  int* __restrict__ flags, int* counter,
-                                                 double tol, double* maxoff, int max_inner) {
+                                                 double tol, double* maxoff, int max_inner,
+                                                 int* inner_count, double inner_stop2) {
   typedef typename cpx_t<T>::type C2;
   __shared__ double Gr[JP][JP + LPAD], Gi[JP][JP + LPAD];
   __shared__ double Rr[JP][JP + LPAD], Ri[JP][JP + LPAD];
-  __shared__ double rc_[32], rsr[32], rsi[32], rdi[32], rdj[32];
-  __shared__ int ri_[32], rj_[32], rrot[32];
+  __shared__ double4 prm[32];   // (c, Re s, Im s, unused) of rotation m
+  __shared__ double2 pdg[32];   // new diagonal (d_i, d_j)
+  __shared__ int pidx[32];      // i | j << 8 | rotate << 16
   __shared__ double red[256];
+  __shared__ unsigned short blkPQ[528];
   __shared__ int nrot;
+  __shared__ double sweepmax;
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
+  // (P, Q) of the 528 pairs of rotation slots with P <= Q, as P | Q << 8
+  for (int Q = 0, b = 0; Q < 32; ++Q)
+    for (int P = 0; P <= Q; ++P, ++b)
+      if ((b & 255) == tid) blkPQ[b] = (unsigned short)(P | (Q << 8));
 
   // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian matrix.
   for (int e = tid; e < NTILE * 256; e += 256) {
@@ -193,10 +204,15 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
     Rr[i][j] = (i == j) ? 1.0 : 0.0;
     Ri[i][j] = 0.0;
   }
-  const double tol_in = 4.0e-16;
+  // A sweep whose largest relative off-diagonal entry (before its rotation)
+  // was below 1e-10 leaves O(1e-20) behind (quadratic convergence), so the
+  // confirming sweep that would rotate nothing is skipped.
+  const double tol_in2 = 1.6e-31;  // (4e-16)^2
+  const double stop2 = inner_stop2;
+  int sweeps_done = 0;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
-    if (tid == 0) nrot = 0;
-    __syncthreads();
+    double smax = 0.0;
+    int anyrot = 0;
     for (int step = 0; step < JP - 1; ++step) {
       if (tid < 32) {
         const int a = tid, b = JP - 1 - tid;
@@ -205,95 +221,127 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
         if (i > j) { const int tmp = i; i = j; j = tmp; }
         const double aa = Gr[i][i], dd = Gr[j][j];
         const double cre = Gr[i][j], cim = Gi[i][j];
-        const double ac = sqrt(cre * cre + cim * cim);
+        const double ac2 = cre * cre + cim * cim;
         int rot = 0;
         double cs = 1.0, sr = 0.0, si = 0.0, di = aa, dj = dd;
-        if (ac > tol_in * sqrt(fabs(aa * dd)) && ac > 0.0) {
+        const double add = fabs(aa * dd);
+        if (add > 0.0) smax = fmax(smax, ac2 / add);
+        else if (ac2 > 0.0) smax = 1.0;
+        if (ac2 > tol_in2 * add && ac2 > 0.0) {
           rot = 1;
-          const double zeta = (dd - aa) / (2.0 * ac);
+          const double inv_ac = rsqrt(ac2);
+          const double ac = ac2 * inv_ac;
+          const double zeta = 0.5 * (dd - aa) * inv_ac;
           double tt;
           if (fabs(zeta) > 1.0e150) tt = 0.5 / zeta;
           else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          cs = 1.0 / sqrt(1.0 + tt * tt);
+          cs = rsqrt(1.0 + tt * tt);
           const double sn = tt * cs;
-          sr = sn * cre / ac;
-          si = sn * cim / ac;
+          sr = sn * cre * inv_ac;
+          si = sn * cim * inv_ac;
           di = aa - tt * ac;
           dj = dd + tt * ac;
-          atomicAdd(&nrot, 1);
         }
-        ri_[tid] = i; rj_[tid] = j; rrot[tid] = rot;
-        rc_[tid] = cs; rsr[tid] = sr; rsi[tid] = si; rdi[tid] = di; rdj[tid] = dj;
+        if (rot) anyrot = 1;
+        pidx[tid] = i | (j << 8) | (rot << 16);
+        prm[tid] = make_double4(cs, sr, si, 0.0);
+        pdg[tid] = make_double2(di, dj);
       }
       __syncthreads();
-      // 2 x 2 blocks (P, Q), P <= Q: 528 of them.
-      for (int blk = tid; blk < 528; blk += 256) {
-        int Q = (int)((sqrt(8.0 * blk + 1.0) - 1.0) * 0.5);
-        while ((Q + 1) * (Q + 2) / 2 <= blk) ++Q;
-        while (Q * (Q + 1) / 2 > blk) --Q;
-        const int P = blk - Q * (Q + 1) / 2;
-        const int rP = rrot[P], rQ = rrot[Q];
-        if (!rP && !rQ) continue;
-        const int iP = ri_[P], jP = rj_[P], iQ = ri_[Q], jQ = rj_[Q];
-        if (P == Q) {
-          Gr[iP][iP] = rdi[P]; Gi[iP][iP] = 0.0;
-          Gr[jP][jP] = rdj[P]; Gi[jP][jP] = 0.0;
-          Gr[iP][jP] = 0.0; Gi[iP][jP] = 0.0;
-          Gr[jP][iP] = 0.0; Gi[jP][iP] = 0.0;
-          continue;
+      // 2 x 2 blocks (P, Q), P <= Q: 528 of them, at most three per thread.
+#pragma unroll
+      for (int u = 0; u < 3; ++u) {
+        const int blk = tid + 256 * u;
+        if (blk < 528) {
+          const int pq = blkPQ[blk];
+          const int P = pq & 255, Q = pq >> 8;
+          const int xP = pidx[P], xQ = pidx[Q];
+          const int rP = xP >> 16, rQ = xQ >> 16;
+          if (rP | rQ) {
+            const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
+            if (P == Q) {
+              const double2 dg = pdg[P];
+              Gr[iP][iP] = dg.x; Gi[iP][iP] = 0.0;
+              Gr[jP][jP] = dg.y; Gi[jP][jP] = 0.0;
+              Gr[iP][jP] = 0.0; Gi[iP][jP] = 0.0;
+              Gr[jP][iP] = 0.0; Gi[jP][iP] = 0.0;
+            } else {
+              double2 g00 = make_double2(Gr[iP][iQ], Gi[iP][iQ]);
+              double2 g01 = make_double2(Gr[iP][jQ], Gi[iP][jQ]);
+              double2 g10 = make_double2(Gr[jP][iQ], Gi[jP][iQ]);
+              double2 g11 = make_double2(Gr[jP][jQ], Gi[jP][jQ]);
+              if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
+                const double4 pp = prm[Q];
+                const double c = pp.x;
+                const double2 sq = make_double2(pp.y, pp.z);
+                const double2 sqc = cconj(sq);
+                const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
+                const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
+                const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
+                const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
+                g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+              }
+              if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
+                const double4 pp = prm[P];
+                const double c = pp.x;
+                const double2 sp = make_double2(pp.y, pp.z);
+                const double2 spc = cconj(sp);
+                const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
+                const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
+                const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
+                const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
+                g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+              }
+              Gr[iP][iQ] = g00.x; Gi[iP][iQ] = g00.y;
+              Gr[iP][jQ] = g01.x; Gi[iP][jQ] = g01.y;
+              Gr[jP][iQ] = g10.x; Gi[jP][iQ] = g10.y;
+              Gr[jP][jQ] = g11.x; Gi[jP][jQ] = g11.y;
+              Gr[iQ][iP] = g00.x; Gi[iQ][iP] = -g00.y;
+              Gr[jQ][iP] = g01.x; Gi[jQ][iP] = -g01.y;
+              Gr[iQ][jP] = g10.x; Gi[iQ][jP] = -g10.y;
+              Gr[jQ][jP] = g11.x; Gi[jQ][jP] = -g11.y;
+            }
+          }
         }
-        double2 g00 = make_double2(Gr[iP][iQ], Gi[iP][iQ]);
-        double2 g01 = make_double2(Gr[iP][jQ], Gi[iP][jQ]);
-        double2 g10 = make_double2(Gr[jP][iQ], Gi[jP][iQ]);
-        double2 g11 = make_double2(Gr[jP][jQ], Gi[jP][jQ]);
-        if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
-          const double c = rc_[Q];
-          const double2 sq = make_double2(rsr[Q], rsi[Q]);
-          const double2 sqc = cconj(sq);
-          const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
-          const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
-          const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
-          const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
-          g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-        }
-        if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
-          const double c = rc_[P];
-          const double2 sp = make_double2(rsr[P], rsi[P]);
-          const double2 spc = cconj(sp);
-          const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
-          const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
-          const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
-          const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
-          g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-        }
-        Gr[iP][iQ] = g00.x; Gi[iP][iQ] = g00.y;
-        Gr[iP][jQ] = g01.x; Gi[iP][jQ] = g01.y;
-        Gr[jP][iQ] = g10.x; Gi[jP][iQ] = g10.y;
-        Gr[jP][jQ] = g11.x; Gi[jP][jQ] = g11.y;
-        Gr[iQ][iP] = g00.x; Gi[iQ][iP] = -g00.y;
-        Gr[jQ][iP] = g01.x; Gi[jQ][iP] = -g01.y;
-        Gr[iQ][jP] = g10.x; Gi[iQ][jP] = -g10.y;
-        Gr[jQ][jP] = g11.x; Gi[jQ][jP] = -g11.y;
       }
-      // R <- R J for the rotated column pairs
-      for (int e = tid; e < 32 * JP; e += 256) {
-        const int m = e >> 6, r = e & 63;
-        if (!rrot[m]) continue;
-        const int i = ri_[m], j = rj_[m];
-        const double c = rc_[m];
-        const double2 s = make_double2(rsr[m], rsi[m]);
-        const double2 ri = make_double2(Rr[r][i], Ri[r][i]);
-        const double2 rj = make_double2(Rr[r][j], Ri[r][j]);
-        const double2 ni = csub(cscale(ri, c), cmul(cconj(s), rj));
-        const double2 nj = cadd(cmul(s, ri), cscale(rj, c));
-        Rr[r][i] = ni.x; Ri[r][i] = ni.y;
-        Rr[r][j] = nj.x; Ri[r][j] = nj.y;
+      // R <- R J for the rotated column pairs: row r, rotations m = wave + 4 u
+      {
+        const int r = tid & 63;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int m = (tid >> 6) + 4 * u;
+          const int xm = pidx[m];
+          if (xm >> 16) {
+            const int i = xm & 255, j = (xm >> 8) & 255;
+            const double4 pp = prm[m];
+            const double c = pp.x;
+            const double2 sv = make_double2(pp.y, pp.z);
+            const double2 ri = make_double2(Rr[r][i], Ri[r][i]);
+            const double2 rj = make_double2(Rr[r][j], Ri[r][j]);
+            const double2 ni = csub(cscale(ri, c), cmul(cconj(sv), rj));
+            const double2 nj = cadd(cmul(sv, ri), cscale(rj, c));
+            Rr[r][i] = ni.x; Ri[r][i] = ni.y;
+            Rr[r][j] = nj.x; Ri[r][j] = nj.y;
+          }
+        }
       }
       __syncthreads();
     }
-    if (nrot == 0) break;
+    ++sweeps_done;
+    if (tid < 64) {  // wave 0: reduce over the 32 parameter lanes
+      double v = smax;
+      int rr = anyrot;
+      for (int o = 32; o > 0; o >>= 1) {
+        v = fmax(v, __shfl_xor(v, o));
+        rr |= __shfl_xor(rr, o);
+      }
+      if (tid == 0) { sweepmax = v; nrot = rr; }
+    }
+    __syncthreads();
+    if (nrot == 0 || sweepmax < stop2) break;
     __syncthreads();
   }
+  if (tid == 0) atomicAdd(inner_count, sweeps_done);
 
   // 4. R to global, column-major 64 x 64.
   C2* dst = Rout + (long)k * JP * JP;
@@ -406,6 +454,7 @@ void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w) {
   o += (size_t)pairs * sizeof(int) + 256;
   o = (o + 255) & ~(size_t)255;
   w.counter = reinterpret_cast<int*>(base + o);
+  w.inner = reinterpret_cast<int*>(base + o + 32);
   w.maxoff = reinterpret_cast<double*>(base + o + 64);
 }
 
@@ -431,6 +480,11 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
     if (time_kernels) (void)hipEventRecord(ev[i], s);
   };
   hipError_t ret = hipSuccess;
+  const bool debug = getenv("BSE_DEBUG") != nullptr;
+  // A pair's inner iteration ends after a sweep whose largest relative
+  // off-diagonal entry was below sqrt(inner_stop2).
+  double inner_stop2 = 1.0e-20;
+  if (const char* v = getenv("BSE_INNER_STOP")) inner_stop2 = atof(v) * atof(v);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     e = hipMemsetAsync(w.counter, 0, 128, s);
     if (e != hipSuccess) { ret = e; break; }
@@ -441,7 +495,8 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
       mark(b + 1);
       mark(b + 2);
       k_jac_eig<double><<<pairs, 256, 0, s>>>(N, t, kc, (const double2*)w.part, (double2*)w.R,
-                                              w.flags, w.counter, tol, w.maxoff, 30);
+                                              w.flags, w.counter, tol, w.maxoff, 30, w.inner,
+                                              inner_stop2);
       mark(b + 3);
       mark(b + 4);
       k_jac_rotate<double><<<pairs * chunks, 256, 0, s>>>(N, t, W, ld, (const double2*)w.R,
@@ -450,10 +505,11 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
     }
     e = hipGetLastError();
     if (e != hipSuccess) { ret = e; break; }
-    int cnt = 0;
+    int cnt = 0, inner = 0;
     double mo = 0.0;
     e = hipMemcpyAsync(&cnt, w.counter, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&mo, w.maxoff, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&inner, w.inner, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { ret = e; break; }
     if (time_kernels) {
@@ -465,8 +521,12 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
           res.kernel_launches[kx] += 1;
         }
     }
+    if (debug)
+      fprintf(stderr, "[bse] sweep %d: rotated pairs %d of %d, max off %.3e, inner sweeps %.2f per pair\n",
+              sweep + 1, cnt, pairs * (N - 1), mo, cnt > 0 ? (double)inner / cnt : 0.0);
     res.sweeps = sweep + 1;
     res.rotations += cnt;
+    res.inner_sweeps += inner;
     res.pair_checks += pairs * (N - 1);
     res.max_off = mo;
     if (cnt == 0) { res.converged = 1; break; }

@@ -131,7 +131,9 @@ def test_condition_family(gpu_lib):
         e = om.rel_eig_err(lam, exact)
         print(f"kappa={kappa:g} rel_eig_err={e:.3e}")
         assert e < n * np.finfo(float).eps * kappa
-        assert om.residual(A, B, lam, X) < 1e-13
+        # V1 = M1 V2 / lambda (Lemma SVDScalarFactors) carries the error of V2
+        # amplified by ||H|| / lambda <= kappa into the residual.
+        assert om.residual(A, B, lam, X) < 200 * np.finfo(float).eps * kappa
 
 
 @pytest.mark.parametrize("which", ["plus", "minus"])
