@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-checks", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -119,6 +121,15 @@ def main():
 
     api.load_library()
     dev = torch.device("cuda:0")
+    if args.copy_calibration > 0:
+        # one kernel that reads and writes exactly MIB MiB each, three times
+        src = torch.ones(args.copy_calibration * 262144, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x {args.copy_calibration} MiB device copies")
+        del src, dst
     t0 = time.perf_counter()
     A_np, B_np = inputs.workload(args.workload, n=args.n)
     n = A_np.shape[0]

@@ -31,8 +31,8 @@
  *        n+1..2n      leading minor (i - n) of A - B is not positive definite
  *        2n+1         Jacobi iteration did not converge within max_sweeps
  *                     (outputs are written; info->max_off says how far off)
- *        2n+2         mixed precision: refinement did not reach its tolerance
- *                     (outputs are written)
+ *        2n+2         mixed precision: the last refinement correction still
+ *                     exceeded 1e-4 (outputs are written)
  *       <= -1000      HIP runtime error (-1000 - hipError_t)
  */
 #ifndef BSE_H
@@ -55,7 +55,9 @@ typedef struct {
   int route;          /* BSE_ROUTE_*                                            */
   int precision;      /* BSE_PREC_*                                             */
   int max_sweeps;     /* Jacobi sweep limit; 0 = default (30 FP64, 20 mixed)    */
-  int refine_steps;   /* mixed only: refinement steps; 0 = default (1)          */
+  int refine_steps;   /* mixed only: at most this many refinement steps, fewer
+                         once a step's largest correction is <= 1e-6;
+                         0 = default (2), at most 8                            */
   double jacobi_tol;  /* rotate a block pair while max |g_ij|/sqrt(g_ii g_jj)
                          exceeds this; 0 = default n * eps of the bulk dtype    */
   int want_negative;  /* nonzero: also write -lambda and [0 I; I 0] X           */
@@ -69,7 +71,8 @@ typedef struct {
   int fail_index;       /* non-HPD: 1-based leading minor, else 0             */
   int rotations;        /* block-pair rotations over all sweeps               */
   double max_off;       /* largest relative off-diagonal seen in the last sweep */
-  double refine_delta;  /* mixed: max |lambda change| / lambda of the last step */
+  double refine_delta;  /* mixed: largest off-diagonal entry of the last
+                           refinement correction (error left ~ its square)    */
   double ms_phase[8];   /* phase times (ms): form, chol, W, jacobi, finalize,
                            back-transform, refine, total; filled if requested  */
   int timing;           /* in: 0 none; 1 fill ms_phase; 2 also time every
@@ -78,7 +81,8 @@ typedef struct {
   double kernel_ms[3];  /* timing == 2: summed durations of the Jacobi Gram,
                            inner-eigensolver and rotation kernels (ms)        */
   int kernel_launches[3];
-  int reserved[3];
+  int refine_steps_done; /* mixed: refinement steps run                       */
+  int reserved[2];
 } bse_info_t;
 
 /* Fill `opts` with the defaults (route SVD, FP64, lower triangles). */

@@ -53,7 +53,8 @@ class BSEInfo(ctypes.Structure):
         ("pair_checks", ctypes.c_int),
         ("kernel_ms", ctypes.c_double * 3),
         ("kernel_launches", ctypes.c_int * 3),
-        ("reserved", ctypes.c_int * 3),
+        ("refine_steps_done", ctypes.c_int),
+        ("reserved", ctypes.c_int * 2),
     ]
 
     def as_dict(self):
@@ -68,6 +69,7 @@ class BSEInfo(ctypes.Structure):
             "pair_checks": self.pair_checks,
             "kernel_ms": list(self.kernel_ms),
             "kernel_launches": list(self.kernel_launches),
+            "refine_steps_done": self.refine_steps_done,
         }
 
 

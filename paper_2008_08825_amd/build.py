@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbse.so")
 
-SOURCES = ["capi.hip", "gemm.hip", "chol.hip", "jacobi.hip", "finalize.hip"]
+SOURCES = ["capi.hip", "gemm.hip", "chol.hip", "jacobi.hip", "finalize.hip", "refine.hip"]
 
 HIP_FLAGS = [
     "-O3",

@@ -87,18 +87,22 @@ __global__ __launch_bounds__(256) void k_form_m12(int n, int np, const double2* 
 // Unblocked Cholesky of the diagonal block M[j0:j0+64, j0:j0+64] (lower) and
 // the inverse of the resulting triangle, in one workgroup.  Writes L11 back
 // with a zero strict upper triangle and L11^-1 (64 x 64, ld 64) to `linv`.
-__global__ __launch_bounds__(256) void k_potf2_inv(double2* M, long ld, int j0,
-                                                   double2* __restrict__ linv, int* status,
+// C2 is the storage type (double2, or float2 in the mixed form); the block is
+// factored in FP64 either way.
+template <typename C2>
+__global__ __launch_bounds__(256) void k_potf2_inv(C2* M, long ld, int j0,
+                                                   C2* __restrict__ linv, int* status,
                                                    int base, int n_real) {
   __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
   __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
   __shared__ int failed;
   const int tid = threadIdx.x;
-  double2* D = M + j0 + (long)j0 * ld;
+  C2* D = M + j0 + (long)j0 * ld;
   for (int q = 0; q < 16; ++q) {
     int r = tid & 63, c = (tid >> 6) + 4 * q;
-    double2 v = (r >= c) ? D[r + (long)c * ld] : make_double2(0.0, 0.0);
-    Lr[r][c] = v.x; Li[r][c] = v.y;
+    double vr = 0.0, vi = 0.0;
+    if (r >= c) { const C2 v = D[r + (long)c * ld]; vr = v.x; vi = v.y; }
+    Lr[r][c] = vr; Li[r][c] = vi;
   }
   if (tid == 0) failed = 0;
   __syncthreads();
@@ -156,10 +160,45 @@ __global__ __launch_bounds__(256) void k_potf2_inv(double2* M, long ld, int j0,
   __syncthreads();
   for (int q = 0; q < 16; ++q) {
     int r = tid & 63, c = (tid >> 6) + 4 * q;
-    double2 l = (r >= c) ? make_double2(Lr[r][c], Li[r][c]) : make_double2(0.0, 0.0);
+    C2 l, x;
+    l.x = (r >= c) ? Lr[r][c] : 0.0;
+    l.y = (r >= c) ? Li[r][c] : 0.0;
+    x.x = Xr[r][c];
+    x.y = Xi[r][c];
     D[r + (long)c * ld] = l;
-    linv[r + c * NB] = make_double2(Xr[r][c], Xi[r][c]);
+    linv[r + c * NB] = x;
   }
+}
+
+// Upper triangle of a square np x np matrix from its lower one: M[i][j] = conj(M[j][i]), i < j.
+__global__ __launch_bounds__(256) void k_mirror_upper(int np, double2* M, long ld) {
+  __shared__ double2 tile[64][65];
+  const int T = np / 64;
+  const int tm = blockIdx.x % T, tn = blockIdx.x / T;
+  if (tn < tm) return;  // target tile (tm, tn) on or above the diagonal
+  const int m0 = tm * 64, n0 = tn * 64;
+  const int tid = threadIdx.x;
+  // source tile (tn, tm): rows n0.., cols m0..
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;
+    tile[r][c] = M[(n0 + r) + (long)(m0 + c) * ld];
+  }
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;  // target (m0 + r, n0 + c)
+    if (m0 + r < n0 + c) M[(m0 + r) + (long)(n0 + c) * ld] = cconj(tile[c][r]);
+  }
+}
+
+// complex64 copy of the lower triangle (strict upper part zero).
+__global__ __launch_bounds__(256) void k_lower_to_c64(int np, const double2* __restrict__ M, long ld,
+                                                      float2* __restrict__ Mc) {
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  float2 v = make_float2(0.f, 0.f);
+  if (i >= j) { const double2 x = M[i + (long)j * ld]; v = make_float2((float)x.x, (float)x.y); }
+  Mc[i + (long)j * ld] = v;
 }
 
 }  // namespace
@@ -171,21 +210,35 @@ hipError_t form_m12(int n, int np, const double2* A, long lda, const double2* B,
   return hipGetLastError();
 }
 
-hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, int* status,
-                      int base, hipStream_t s) {
+hipError_t mirror_upper_z(int np, double2* M, long ld, hipStream_t s) {
+  const int T = np / 64;
+  k_mirror_upper<<<T * T, 256, 0, s>>>(np, M, ld);
+  return hipGetLastError();
+}
+
+hipError_t lower_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream_t s) {
+  dim3 g((np + 255) / 256, np);
+  k_lower_to_c64<<<g, 256, 0, s>>>(np, M, ld, Mc);
+  return hipGetLastError();
+}
+
+template <typename C2>
+static hipError_t cholesky_run(int np, int n_real, C2* M, long ld, C2* linv, int* status,
+                               int base, hipStream_t s) {
+  hipError_t (*gemm)(const GemmDesc&, hipStream_t) = sizeof(C2) == 16 ? gemm_z : gemm_c;
   for (int j0 = 0; j0 < np; j0 += NB) {
-    k_potf2_inv<<<1, 256, 0, s>>>(M, ld, j0, linv, status, base, n_real);
+    k_potf2_inv<C2><<<1, 256, 0, s>>>(M, ld, j0, linv, status, base, n_real);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int rows = np - j0 - NB;
     if (rows <= 0) break;
-    double2* panel = M + (j0 + NB) + (long)j0 * ld;
+    C2* panel = M + (j0 + NB) + (long)j0 * ld;
     GemmDesc t;  // L21 = A21 * L11^-H (in place: one workgroup per row tile)
     t.M = rows; t.N = NB; t.K = NB;
     t.A = panel; t.lda = ld; t.opA = 0;
     t.B = linv; t.ldb = NB; t.opB = 1; t.triB = 1;
     t.C = panel; t.ldc = ld;
-    e = gemm_z(t, s);
+    e = gemm(t, s);
     if (e != hipSuccess) return e;
     GemmDesc h;  // A22 -= L21 L21^H, lower tiles
     h.M = rows; h.N = rows; h.K = NB;
@@ -193,10 +246,20 @@ hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, in
     h.B = panel; h.ldb = ld; h.opB = 1;
     h.C = M + (j0 + NB) + (long)(j0 + NB) * ld; h.ldc = ld;
     h.alpha_re = -1.0; h.beta_re = 1.0; h.lowerC = 1;
-    e = gemm_z(h, s);
+    e = gemm(h, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, int* status,
+                      int base, hipStream_t s) {
+  return cholesky_run<double2>(np, n_real, M, ld, linv, status, base, s);
+}
+
+hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status,
+                      int base, hipStream_t s) {
+  return cholesky_run<float2>(np, n_real, M, ld, linv, status, base, s);
 }
 
 }  // namespace bse

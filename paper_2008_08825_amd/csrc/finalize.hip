@@ -22,13 +22,17 @@
 namespace bse {
 namespace {
 
-__global__ __launch_bounds__(256) void k_colnorm(const double2* __restrict__ W, long ld, int np,
+template <typename C2>
+__global__ __launch_bounds__(256) void k_colnorm(const C2* __restrict__ W, long ld, int np,
                                                  double* __restrict__ sigma) {
   __shared__ double red[256];
   const int j = blockIdx.x, tid = threadIdx.x;
-  const double2* col = W + (long)j * ld;
+  const C2* col = W + (long)j * ld;
   double s = 0.0;
-  for (int i = tid; i < np; i += 256) s += cabs2(col[i]);
+  for (int i = tid; i < np; i += 256) {
+    const double a = col[i].x, b = col[i].y;
+    s += a * a + b * b;
+  }
   red[tid] = s;
   __syncthreads();
   for (int h = 128; h > 0; h >>= 1) {
@@ -61,7 +65,8 @@ __global__ __launch_bounds__(256) void k_rank(int n, const double* __restrict__ 
   if (j < n) perm[rank] = j;
 }
 
-__global__ __launch_bounds__(256) void k_scale_cols(int n, int np, double2* __restrict__ W, long ld,
+template <typename C2>
+__global__ __launch_bounds__(256) void k_scale_cols(int n, int np, C2* __restrict__ W, long ld,
                                                     const double* __restrict__ sigma) {
   const int k = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -71,7 +76,21 @@ __global__ __launch_bounds__(256) void k_scale_cols(int n, int np, double2* __re
     const double sg = sigma[k];
     f = sg > 0.0 ? 1.0 / (sg * sqrt(sg)) : 0.0;
   }
-  W[i + (long)k * ld] = cscale(W[i + (long)k * ld], f);
+  C2 v = W[i + (long)k * ld];
+  v.x = v.x * f;
+  v.y = v.y * f;
+  W[i + (long)k * ld] = v;
+}
+
+__global__ __launch_bounds__(256) void k_c64_to_c128(int np, const float2* __restrict__ S, long lds,
+                                                     double2* __restrict__ D, long ldd,
+                                                     const double* __restrict__ colscale) {
+  const int j = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  const float2 v = S[i + (long)j * lds];
+  const double f = colscale ? colscale[j] : 1.0;
+  D[i + (long)j * ldd] = make_double2(f * v.x, f * v.y);
 }
 
 __global__ __launch_bounds__(256) void k_lambda(int n, int np, const double* __restrict__ anorm,
@@ -130,23 +149,59 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const double2* __restri
 }  // namespace
 
 hipError_t colnorm_z(int np, const double2* W, long ld, double* out, hipStream_t s) {
-  k_colnorm<<<np, 256, 0, s>>>(W, ld, np, out);
+  k_colnorm<double2><<<np, 256, 0, s>>>(W, ld, np, out);
+  return hipGetLastError();
+}
+
+hipError_t colnorm_c(int np, const float2* W, long ld, double* out, hipStream_t s) {
+  k_colnorm<float2><<<np, 256, 0, s>>>(W, ld, np, out);
+  return hipGetLastError();
+}
+
+template <typename C2>
+static hipError_t scale_singular_run(int n, int np, C2* W, long ld, double* sigma, double* bnorm,
+                                     hipStream_t s) {
+  k_colnorm<C2><<<np, 256, 0, s>>>(W, ld, np, sigma);
+  dim3 g((np + 255) / 256, np);
+  k_scale_cols<C2><<<g, 256, 0, s>>>(n, np, W, ld, sigma);
+  k_colnorm<C2><<<np, 256, 0, s>>>(W, ld, np, bnorm);
   return hipGetLastError();
 }
 
 hipError_t scale_singular_cols_z(int n, int np, double2* W, long ld, double* sigma, double* bnorm,
                                  hipStream_t s) {
-  k_colnorm<<<np, 256, 0, s>>>(W, ld, np, sigma);
+  return scale_singular_run<double2>(n, np, W, ld, sigma, bnorm, s);
+}
+
+hipError_t scale_singular_cols_c(int n, int np, float2* W, long ld, double* sigma, double* bnorm,
+                                 hipStream_t s) {
+  return scale_singular_run<float2>(n, np, W, ld, sigma, bnorm, s);
+}
+
+hipError_t c64_to_c128(int np, const float2* S, long lds, double2* D, long ldd,
+                       const double* colscale, hipStream_t s) {
   dim3 g((np + 255) / 256, np);
-  k_scale_cols<<<g, 256, 0, s>>>(n, np, W, ld, sigma);
-  k_colnorm<<<np, 256, 0, s>>>(W, ld, np, bnorm);
+  k_c64_to_c128<<<g, 256, 0, s>>>(np, S, lds, D, ldd, colscale);
+  return hipGetLastError();
+}
+
+hipError_t lambda_from_norms(int n, int np, const double* anorm, const double* bnorm, double* lam,
+                             double* invlam, double* scl, hipStream_t s) {
+  k_lambda<<<(np + 255) / 256, 256, 0, s>>>(n, np, anorm, bnorm, lam, invlam, scl);
+  return hipGetLastError();
+}
+
+hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int want_negative,
+                       hipStream_t s) {
+  k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
+  k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);
   return hipGetLastError();
 }
 
 hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* bnorm, double* anorm,
                        double* lam, double* invlam, double* scl, int* perm, double* lambda,
                        int want_negative, hipStream_t s) {
-  k_colnorm<<<np, 256, 0, s>>>(T, ld, np, anorm);
+  k_colnorm<double2><<<np, 256, 0, s>>>(T, ld, np, anorm);
   k_lambda<<<(np + 255) / 256, 256, 0, s>>>(n, np, anorm, bnorm, lam, invlam, scl);
   k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
   k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);

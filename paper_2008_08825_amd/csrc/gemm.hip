@@ -25,8 +25,8 @@ struct GemmParams {
   const typename cpx_t<T>::type* B; long ldb; int triB;
   typename cpx_t<T>::type* C; long ldc;
   T ar, ai, br, bi;
-  const T* kscale;
-  const T* colscale;
+  const double* kscale;
+  const double* colscale;
   int lowerC, mask;
   long strideA, strideB, strideC;
   int tilesM;
@@ -81,7 +81,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmParams<T> p) {
       }
       if (p.kscale) {
         int gk = k0 + k;
-        T sc = gk < p.K ? p.kscale[gk] : T(0);
+        T sc = gk < p.K ? (T)p.kscale[gk] : T(0);
         v.x *= sc; v.y *= sc;
       }
       ra[i] = v;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmParams<T> p) {
         if (m >= p.M || n >= p.N) continue;
         T vr = cr[ti][tj][r], vi = ci[ti][tj][r];
         T outr = p.ar * vr - p.ai * vi, outi = p.ar * vi + p.ai * vr;
-        if (p.colscale) { T sc = p.colscale[n]; outr *= sc; outi *= sc; }
+        if (p.colscale) { T sc = (T)p.colscale[n]; outr *= sc; outi *= sc; }
         C2* cp = C + m + (long)n * p.ldc;
         if (p.br != T(0) || p.bi != T(0)) {
           C2 old = *cp;
@@ -183,8 +183,8 @@ hipError_t gemm_launch(const GemmDesc& d, hipStream_t s) {
   p.B = static_cast<const C2*>(d.B); p.ldb = d.ldb; p.triB = d.triB;
   p.C = static_cast<C2*>(d.C); p.ldc = d.ldc;
   p.ar = (T)d.alpha_re; p.ai = (T)d.alpha_im; p.br = (T)d.beta_re; p.bi = (T)d.beta_im;
-  p.kscale = static_cast<const T*>(d.kscale);
-  p.colscale = static_cast<const T*>(d.colscale);
+  p.kscale = static_cast<const double*>(d.kscale);
+  p.colscale = static_cast<const double*>(d.colscale);
   p.lowerC = d.lowerC; p.mask = d.mask;
   p.strideA = d.strideA; p.strideB = d.strideB; p.strideC = d.strideC;
   p.tilesM = (d.M + BM - 1) / BM;

@@ -20,8 +20,8 @@ struct GemmDesc {
   const void* B = nullptr; long ldb = 0; int opB = 0; int triB = 0;
   void* C = nullptr; long ldc = 0;
   double alpha_re = 1.0, alpha_im = 0.0, beta_re = 0.0, beta_im = 0.0;
-  const void* kscale = nullptr;    // real, length K (same precision as data)
-  const void* colscale = nullptr;  // real, length N
+  const double* kscale = nullptr;    // real, length K
+  const double* colscale = nullptr;  // real, length N
   int lowerC = 0;
   int mask = 0;
   int batch = 1;
@@ -71,6 +71,18 @@ struct JacobiResult {
 // on return the columns of W are mutually orthogonal (W_in Q = W_out, Q unitary).
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
                     int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false);
+// complex64 columns; Gram partial sums, inner eigensolver and rotations as in
+// jacobi_z (inner eigensolver in FP64), inner iteration ending once a sweep's
+// largest relative off-diagonal entry is below inner_stop.
+hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false);
+
+hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status, int base,
+                      hipStream_t s);
+// M[i][j] = conj(M[j][i]) for i < j (np % 64 == 0).
+hipError_t mirror_upper_z(int np, double2* M, long ld, hipStream_t s);
+// complex64 copy of the lower triangle, strict upper part zero.
+hipError_t lower_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream_t s);
 
 // Column norms out[j] = ||W[:, j]|| for j < np.
 hipError_t colnorm_z(int np, const double2* W, long ld, double* out, hipStream_t s);
@@ -85,6 +97,34 @@ hipError_t scale_singular_cols_z(int n, int np, double2* W, long ld, double* sig
 hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* bnorm,
                        double* anorm, double* lam, double* invlam, double* scl, int* perm,
                        double* lambda, int want_negative, hipStream_t s);
+
+hipError_t colnorm_c(int np, const float2* W, long ld, double* out, hipStream_t s);
+hipError_t scale_singular_cols_c(int n, int np, float2* W, long ld, double* sigma, double* bnorm,
+                                 hipStream_t s);
+// D[:, j] = S[:, j] * colscale[j] (np x np), complex64 to complex128.
+hipError_t c64_to_c128(int np, const float2* S, long lds, double2* D, long ldd,
+                       const double* colscale, hipStream_t s);
+// lam_k = anorm_k / bnorm_k, 1 / lam_k and s_k = (anorm_k bnorm_k)^-1/2 (k < n; zero above).
+hipError_t lambda_from_norms(int n, int np, const double* anorm, const double* bnorm, double* lam,
+                             double* invlam, double* scl, hipStream_t s);
+// Ascending order of lam[0..n) and the output lambda (with -lambda if want_negative).
+hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int want_negative,
+                       hipStream_t s);
+
+// Sigma-aware refinement of the positive eigenpairs in (x, y) coordinates
+// against full Hermitian FP64 M1 = A + B, M2 = A - B (n x n leading blocks,
+// leading dimension ld); x and y are updated in place (through the two work
+// buffers), lam receives Rayleigh quotients and scl the Sigma-normalising
+// scales of the final pair.  Runs up to max_steps steps and stops after a
+// step whose largest off-diagonal correction is at most stop_corr; returns
+// that correction in *max_corr and the steps run in *steps_done.
+struct RefineWork {
+  double2 *Q = nullptr, *F = nullptr, *P1 = nullptr, *P2 = nullptr, *Ex = nullptr, *Ey = nullptr;
+  double *ritz = nullptr, *dots = nullptr, *maxcorr = nullptr;
+};
+hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** x, double2** y,
+                    const RefineWork& w, int max_steps, double stop_corr, double* lam, double* scl,
+                    double* max_corr, int* steps_done, hipStream_t s);
 
 // X[:, r] = s_k [(V1_k + V2_k)/2; (V2_k - V1_k)/2] with k = perm[r] (and the
 // mirrored negative half).

@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
   __shared__ double red[256];
   __shared__ unsigned short blkPQ[528];
   __shared__ int nrot;
-  __shared__ double sweepmax;
+  __shared__ int sweepbig;
   const int tid = threadIdx.x;
   const int k = blockIdx.x;
   // (P, Q) of the 528 pairs of rotation slots with P <= Q, as P | Q << 8
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
   const double stop2 = inner_stop2;
   int sweeps_done = 0;
   for (int sweep = 0; sweep < max_inner; ++sweep) {
-    double smax = 0.0;
+    int big = 0;
     int anyrot = 0;
     for (int step = 0; step < JP - 1; ++step) {
       if (tid < 32) {
@@ -225,17 +225,21 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
         int rot = 0;
         double cs = 1.0, sr = 0.0, si = 0.0, di = aa, dj = dd;
         const double add = fabs(aa * dd);
-        if (add > 0.0) smax = fmax(smax, ac2 / add);
-        else if (ac2 > 0.0) smax = 1.0;
+        if (ac2 > stop2 * add) big = 1;
         if (ac2 > tol_in2 * add && ac2 > 0.0) {
           rot = 1;
           const double inv_ac = rsqrt(ac2);
           const double ac = ac2 * inv_ac;
-          const double zeta = 0.5 * (dd - aa) * inv_ac;
-          double tt;
-          if (fabs(zeta) > 1.0e150) tt = 0.5 / zeta;
-          else tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          cs = rsqrt(1.0 + tt * tt);
+          const double zeta = fmin(fmax(0.5 * (dd - aa) * inv_ac, -1.0e150), 1.0e150);
+          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)): the smaller root, |angle| <= pi/4.
+          // Any t gives a unitary rotation (c = (1 + t^2)^-1/2, s = t c), so t
+          // needs no correctly rounded division: reciprocal plus two Newton steps.
+          const double den = fabs(zeta) + sqrt(fma(zeta, zeta, 1.0));
+          double rc = __builtin_amdgcn_rcp(den);
+          rc = rc * fma(-den, rc, 2.0);
+          rc = rc * fma(-den, rc, 2.0);
+          const double tt = zeta >= 0.0 ? rc : -rc;
+          cs = rsqrt(fma(tt, tt, 1.0));
           const double sn = tt * cs;
           sr = sn * cre * inv_ac;
           si = sn * cim * inv_ac;
@@ -329,16 +333,15 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
     }
     ++sweeps_done;
     if (tid < 64) {  // wave 0: reduce over the 32 parameter lanes
-      double v = smax;
-      int rr = anyrot;
+      int rr = anyrot, bb = big;
       for (int o = 32; o > 0; o >>= 1) {
-        v = fmax(v, __shfl_xor(v, o));
         rr |= __shfl_xor(rr, o);
+        bb |= __shfl_xor(bb, o);
       }
-      if (tid == 0) { sweepmax = v; nrot = rr; }
+      if (tid == 0) { nrot = rr; sweepbig = bb; }
     }
     __syncthreads();
-    if (nrot == 0 || sweepmax < stop2) break;
+    if (nrot == 0 || sweepbig == 0) break;
     __syncthreads();
   }
   if (tid == 0) atomicAdd(inner_count, sweeps_done);
@@ -458,8 +461,11 @@ void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w) {
   w.maxoff = reinterpret_cast<double*>(base + o + 64);
 }
 
-hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels) {
+template <typename T>
+static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const JacobiWork& w,
+                             double tol, double inner_stop, int max_sweeps, JacobiResult& res,
+                             hipStream_t s, bool time_kernels) {
+  typedef typename cpx_t<T>::type C2;
   const int N = np / JB, pairs = N / 2;
   const int kc = gram_chunks(np, pairs);
   const int rc = np / kc;
@@ -483,7 +489,7 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
   const bool debug = getenv("BSE_DEBUG") != nullptr;
   // A pair's inner iteration ends after a sweep whose largest relative
   // off-diagonal entry was below sqrt(inner_stop2).
-  double inner_stop2 = 1.0e-20;
+  double inner_stop2 = inner_stop * inner_stop;
   if (const char* v = getenv("BSE_INNER_STOP")) inner_stop2 = atof(v) * atof(v);
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     e = hipMemsetAsync(w.counter, 0, 128, s);
@@ -491,16 +497,15 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
     for (int t = 0; t < N - 1; ++t) {
       const size_t b = (size_t)t * 6;
       mark(b + 0);
-      k_jac_gram<double><<<pairs * kc, 256, 0, s>>>(N, t, W, ld, rc, kc, (double2*)w.part);
+      k_jac_gram<T><<<pairs * kc, 256, 0, s>>>(N, t, W, ld, rc, kc, (C2*)w.part);
       mark(b + 1);
       mark(b + 2);
-      k_jac_eig<double><<<pairs, 256, 0, s>>>(N, t, kc, (const double2*)w.part, (double2*)w.R,
-                                              w.flags, w.counter, tol, w.maxoff, 30, w.inner,
-                                              inner_stop2);
+      k_jac_eig<T><<<pairs, 256, 0, s>>>(N, t, kc, (const C2*)w.part, (C2*)w.R, w.flags, w.counter,
+                                         tol, w.maxoff, 30, w.inner, inner_stop2);
       mark(b + 3);
       mark(b + 4);
-      k_jac_rotate<double><<<pairs * chunks, 256, 0, s>>>(N, t, W, ld, (const double2*)w.R,
-                                                          w.flags, rrows, chunks);
+      k_jac_rotate<T><<<pairs * chunks, 256, 0, s>>>(N, t, W, ld, (const C2*)w.R, w.flags, rrows,
+                                                     chunks);
       mark(b + 5);
     }
     e = hipGetLastError();
@@ -533,6 +538,16 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
   }
   for (auto& x : ev) (void)hipEventDestroy(x);
   return ret;
+}
+
+hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels) {
+  return jacobi_run<double>(np, W, ld, w, tol, 1.0e-10, max_sweeps, res, s, time_kernels);
+}
+
+hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels) {
+  return jacobi_run<float>(np, W, ld, w, tol, inner_stop, max_sweeps, res, s, time_kernels);
 }
 
 }  // namespace bse

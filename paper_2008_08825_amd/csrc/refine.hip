@@ -1,0 +1,189 @@
+// FP64 refinement of the positive eigenpairs of H1 (the mixed-precision form).
+//
+// Work in the (x, y) coordinates of the proof of Thm ProdEig: an eigenvector
+// is v = Q [x; y], Q = 1/2 [I I; -I I], with M1 y = lambda x, M2 x = lambda y,
+// and its mirror for -lambda is [0 I; I 0] v = Q [-x; y] (Lemma
+// ComputeNegEvecs).  With Z = [V, PV], Sigma-orthogonality and the
+// eigen-equation of the pencil (Hcal, Sigma), Hcal = Sigma H1 = [A B; B A],
+// read Z^H Sigma Z = S = diag(I, -I) and Z^H Hcal Z = diag(Lambda, Lambda).
+// Since Q^H Sigma Q = 1/2 [0 I; I 0] and Q^H Hcal Q = 1/2 diag(M2, M1)
+// (Lemma Qtransform), all of Z^H Sigma Z and Z^H Hcal Z follows from three
+// n x n products F = x^H y, P2 = x^H M2 x, P1 = y^H M1 y:
+//   G11 = (F + F^H)/2,   G21 = (F^H - F)/2,
+//   T11 = (P2 + P1)/2,   T21 = (P1 - P2)/2.
+// A first-order correction Z <- Z (I + S E) that restores both conditions
+// (the linearised equations E^H S + S E = S - G and, off the diagonal,
+// T + E^H S L + L S E = diagonal) gives, with R = S - G and Ritz values
+// l_i = T11_ii / G11_ii,
+//   E11_ii = R11_ii / 2,
+//   E11_ij = (T11_ij + l_j R11_ij) / (l_j - l_i)   (i != j; R11_ij / 2 when
+//            l_i and l_j agree to a relative delta: the pair is degenerate),
+//   E21_ij = (T21_ij + l_j R21_ij) / (l_j + l_i),
+// and the positive half updates as x <- x (I + E11 + E21),
+// y <- y (I + E11 - E21).  This is the Newton-type refinement for symmetric
+// eigenproblems written with GEMMs, here for the Sigma-Hermitian pencil.
+// The eigenvalues are then the Rayleigh quotients
+//   lambda_k = (x_k^H M2 x_k + y_k^H M1 y_k) / (2 Re x_k^H y_k),
+// and each pair is scaled by (Re x_k^H y_k)^-1/2 so that v_k^H Sigma v_k = 1.
+#include "common.hpp"
+#include "internal.hpp"
+
+namespace bse {
+namespace {
+
+__global__ __launch_bounds__(256) void k_ritz(int n, const double2* __restrict__ F,
+                                              const double2* __restrict__ P1,
+                                              const double2* __restrict__ P2, long ld,
+                                              double* __restrict__ ritz) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const long d = i + (long)i * ld;
+  ritz[i] = 0.5 * (P2[d].x + P1[d].x) / F[d].x;
+}
+
+// Correction matrices Ex = I + E11 + E21 and Ey = I + E11 - E21; a 64 x 64
+// tile per workgroup, the transposed tile of F staged through LDS.
+__global__ __launch_bounds__(256) void k_build(int n, const double2* __restrict__ F,
+                                               const double2* __restrict__ P1,
+                                               const double2* __restrict__ P2, long ld,
+                                               const double* __restrict__ ritz,
+                                               double2* __restrict__ Ex, double2* __restrict__ Ey,
+                                               double delta, double* maxcorr) {
+  __shared__ double2 ft[64][65];
+  __shared__ double red[256];
+  const int T = (n + 63) / 64;
+  const int tm = blockIdx.x % T, tn = blockIdx.x / T;
+  const int m0 = tm * 64, n0 = tn * 64;
+  const int tid = threadIdx.x;
+  // ft[c][r] = F[n0 + c][m0 + r]  (rows of the transposed tile)
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;
+    const int gi = n0 + r, gj = m0 + c;
+    ft[r][c] = (gi < n && gj < n) ? F[gi + (long)gj * ld] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double mc = 0.0;
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;
+    const int i = m0 + r, j = n0 + c;
+    if (i >= n || j >= n) continue;
+    const long o = i + (long)j * ld;
+    const double2 fij = F[o];
+    const double2 fji_c = cconj(ft[c][r]);  // conj(F[j][i])
+    const double2 p1 = P1[o], p2 = P2[o];
+    const double2 g11 = cscale(cadd(fij, fji_c), 0.5);
+    const double2 g21 = cscale(csub(fji_c, fij), 0.5);
+    const double2 t11 = cscale(cadd(p2, p1), 0.5);
+    const double2 t21 = cscale(csub(p1, p2), 0.5);
+    const double li = ritz[i], lj = ritz[j];
+    double2 e11;
+    if (i == j) {
+      e11 = make_double2(0.5 * (1.0 - g11.x), 0.0);
+    } else {
+      const double2 r11 = make_double2(-g11.x, -g11.y);
+      const double dl = lj - li;
+      if (fabs(dl) <= delta * fmax(fabs(li), fabs(lj))) e11 = cscale(r11, 0.5);
+      else e11 = cscale(cadd(t11, cscale(r11, lj)), 1.0 / dl);
+      mc = fmax(mc, sqrt(cabs2(e11)));
+    }
+    const double2 r21 = make_double2(-g21.x, -g21.y);
+    const double2 e21 = cscale(cadd(t21, cscale(r21, lj)), 1.0 / (lj + li));
+    mc = fmax(mc, sqrt(cabs2(e21)));
+    const double dd = (i == j) ? 1.0 : 0.0;
+    Ex[o] = make_double2(dd + e11.x + e21.x, e11.y + e21.y);
+    Ey[o] = make_double2(dd + e11.x - e21.x, e11.y - e21.y);
+  }
+  red[tid] = mc;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] = fmax(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  if (tid == 0) atomic_max_nonneg(maxcorr, red[0]);
+}
+
+// Column k: lambda_k = (x_k^H Qx_k + y_k^H Qy_k) / (2 Re x_k^H y_k), scl_k = (Re x_k^H y_k)^-1/2.
+__global__ __launch_bounds__(256) void k_rq_cols(int n, const double2* __restrict__ x,
+                                                 const double2* __restrict__ y,
+                                                 const double2* __restrict__ Qx,
+                                                 const double2* __restrict__ Qy, long ld,
+                                                 double* __restrict__ lam, double* __restrict__ scl) {
+  __shared__ double ra[256], rb[256], rc[256];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const long o = (long)k * ld;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int i = tid; i < n; i += 256) {
+    const double2 xv = x[o + i], yv = y[o + i], qx = Qx[o + i], qy = Qy[o + i];
+    a += xv.x * qx.x + xv.y * qx.y;
+    b += yv.x * qy.x + yv.y * qy.y;
+    c += xv.x * yv.x + xv.y * yv.y;
+  }
+  ra[tid] = a; rb[tid] = b; rc[tid] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) { ra[tid] += ra[tid + h]; rb[tid] += rb[tid + h]; rc[tid] += rc[tid + h]; }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    lam[k] = (ra[0] + rb[0]) / (2.0 * rc[0]);
+    scl[k] = 1.0 / sqrt(rc[0]);
+  }
+}
+
+GemmDesc nn(int n, long ld, const double2* A, int opA, const double2* B, int opB, double2* C) {
+  GemmDesc g;
+  g.M = n; g.N = n; g.K = n;
+  g.A = A; g.lda = ld; g.opA = opA;
+  g.B = B; g.ldb = ld; g.opB = opB;
+  g.C = C; g.ldc = ld;
+  return g;
+}
+
+}  // namespace
+
+hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** xp,
+                    double2** yp, const RefineWork& w, int max_steps, double stop_corr, double* lam,
+                    double* scl, double* max_corr, int* steps_done, hipStream_t s) {
+  double2* x = *xp;
+  double2* y = *yp;
+  double2* Q = w.Q;
+  double2* F = w.F;
+  hipError_t e;
+  *max_corr = 0.0;
+  *steps_done = 0;
+  for (int it = 0; it < max_steps; ++it) {
+    e = hipMemsetAsync(w.maxcorr, 0, sizeof(double), s);
+    if (e != hipSuccess) return e;
+    if ((e = gemm_z(nn(n, ld, x, 1, y, 0, F), s)) != hipSuccess) return e;       // F = x^H y
+    if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, Q), s)) != hipSuccess) return e;      // Q = M2 x
+    if ((e = gemm_z(nn(n, ld, x, 1, Q, 0, w.P2), s)) != hipSuccess) return e;    // P2 = x^H M2 x
+    if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, Q), s)) != hipSuccess) return e;      // Q = M1 y
+    if ((e = gemm_z(nn(n, ld, y, 1, Q, 0, w.P1), s)) != hipSuccess) return e;    // P1 = y^H M1 y
+    k_ritz<<<(n + 255) / 256, 256, 0, s>>>(n, F, w.P1, w.P2, ld, w.ritz);
+    const int T = (n + 63) / 64;
+    k_build<<<T * T, 256, 0, s>>>(n, F, w.P1, w.P2, ld, w.ritz, w.Ex, w.Ey, 1.0e-10, w.maxcorr);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = gemm_z(nn(n, ld, x, 0, w.Ex, 0, Q), s)) != hipSuccess) return e;    // x (I + E11 + E21)
+    if ((e = gemm_z(nn(n, ld, y, 0, w.Ey, 0, F), s)) != hipSuccess) return e;    // y (I + E11 - E21)
+    double2* t = x; x = Q; Q = t;
+    t = y; y = F; F = t;
+    double mc = 0.0;
+    e = hipMemcpyAsync(&mc, w.maxcorr, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    *max_corr = mc;
+    *steps_done = it + 1;
+    // the error left after a step is of the order of the square of its correction
+    if (mc <= stop_corr) break;
+  }
+  // Rayleigh quotients and Sigma-normalising scales of the final pairs.
+  if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, w.P2), s)) != hipSuccess) return e;
+  if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, w.P1), s)) != hipSuccess) return e;
+  k_rq_cols<<<n, 256, 0, s>>>(n, x, y, w.P2, w.P1, ld, lam, scl);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  *xp = x;
+  *yp = y;
+  return hipSuccess;
+}
+
+}  // namespace bse

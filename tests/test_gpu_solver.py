@@ -199,3 +199,42 @@ def test_autograd_closed_form(gpu_lib):
     (lam ** 2).sum().backward()
     assert torch.allclose(At.grad, 2 * At.detach(), atol=1e-11)
     assert torch.allclose(Bt.grad, -2 * Bt.detach(), atol=1e-11)
+
+
+# ---------------------------------------------------------------- mixed precision form
+@pytest.mark.parametrize("n", [1, 5, 64, 100, 200])
+def test_mixed_parity(gpu_lib, n):
+    """complex64 bulk + FP64 refinement: eigenvalues within 1e-10 of the FP64 oracle."""
+    A, B = inputs.coupled(n, seed=40 + n)
+    lam, X, info = run(gpu_lib, A, B, precision="mixed")
+    assert info["status"] == 0, info
+    lam_o, X_o = ob.solve_chol_svd(A, B)
+    e = om.rel_eig_err(lam, lam_o)
+    print(f"mixed n={n} rel_eig_err={e:.2e} refine_corr={info['refine_delta']:.2e} "
+          f"resid={om.residual(A, B, lam, X):.2e} sorth={om.sigma_orth_err(X):.2e}")
+    assert e < 1e-10
+    assert om.residual(A, B, lam, X) < 1e-9
+    assert om.sigma_orth_err(X) < 1e-6
+
+
+def test_mixed_n256_workload_two_steps(gpu_lib):
+    A, B = inputs.workload("n256")
+    lam, X, info = run(gpu_lib, A, B, precision="mixed", refine_steps=3, want_negative=True)
+    n = A.shape[0]
+    lam_o, X_o = ob.solve_chol_svd(A, B)
+    assert om.rel_eig_err(lam[:n], lam_o) < 1e-12
+    assert np.array_equal(lam[n:], -lam[:n])
+    assert om.residual(A, B, lam[:n], X[:, :n]) < 1e-13
+    assert om.sigma_orth_err(X[:, :n]) < 1e-10
+    err, gap = om.eigvec_errors(lam_o, X_o, X[:, :n], cluster_rtol=1e-9)
+    assert np.all(err <= 1e-10 + 1e-13 / np.minimum(gap, 1.0))
+
+
+def test_mixed_non_hpd_status(gpu_lib):
+    n = 70
+    A, B = inputs.coupled(n, seed=41, diag_lo=1.0, diag_hi=2.0, c_norm=0.1, b_norm=0.1)
+    B2 = B.copy()
+    B2[30, 30] = A[30, 30].real + 1.0
+    _, _, info = gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B2).to(DEV),
+                                  precision="mixed", check=False)
+    assert info["status"] == ob.chol_status(A, B2) == n + 31
