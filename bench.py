@@ -1,21 +1,32 @@
-"""Benchmark: all eigenpairs of the BSE matrix H1 on one MI355X.
+"""Benchmark: all eigenpairs of the BSE matrix H1 on one MI355X, mixed vs FP64 form.
 
-One step = one full solve through the C ABI (Cholesky x2, W = L2^H L1,
-block-Jacobi SVD, back-transform, final setup including the negative half)
-on inputs already resident in HBM.  Prints one JSON line.
+One step = one full solve through the C ABI (two Cholesky factorisations,
+W = L2^H L1, block-Jacobi SVD, back-transform, final setup including the
+negative half; the mixed form adds the FP64 refinement) on inputs already
+resident in HBM.  Both forms are timed on the same inputs; one JSON line is
+printed.
 
-value  = nominal TFLOP/s, i.e. the paper's flop model of Alg. 3 (Table 1:
-         24 2/3 n^3 real flops, times 4 for complex arithmetic = 98 2/3 n^3)
-         divided by the measured seconds per solve.
-roofline = the dominant kernel (the Jacobi rotation, X <- X R on FP64 MFMA),
-         its algorithmic flops (8 * np * 64 * 64 per rotated block pair)
-         over its summed launch durations from HIP events on the solver's stream.
-cpu_baseline = the FP64 CPU oracle (scipy, Alg. 3) timed on this host on a
-         bounded sample: one problem of the same recipe at a smaller n.
+value    nominal TFLOP/s of the mixed form: the paper's flop model of Alg. 3
+         (Table 1: 24 2/3 n^3 real flops, times 4 for complex arithmetic =
+         98 2/3 n^3 per solve) divided by the measured seconds per solve.  The
+         FP64 form's figures sit under "fp64".
+roofline the kernel with the largest summed launch time in the timed mixed
+         solves (HIP events around every Jacobi launch on the solver's stream),
+         its algorithmic work per launch over its average launch duration:
+           rotation    8 np 64^2 flops per rotated block pair (complex MACs x 8)
+           Gram        8 np 16^2 x 10 flops per block pair (ten 16 x 16 tiles)
+           eigensolver 3840 flops per applied 2 x 2 rotation (two rows and two
+                       columns of the 64 x 64 Gram and two columns of R, 64
+                       element pairs each, 20 flops per element pair)
+         "traffic" comes from profiles/traffic.json when that file was taken
+         on the current kernel source (same hash), else null.
+cpu_baseline the FP64 CPU oracle (scipy, Alg. 3) on this host on a bounded
+         sample: one problem of the same recipe at a smaller n.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,8 +37,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "s & TFLOP/s for all H1 eigenpairs, n=8192 complex, mixed vs FP64 at stated error"
-PEAK_FP64_TFLOPS = 78.6
-PEAK_FP32_TFLOPS = 157.3
+PEAK = {"fp64_mfma": 78.6, "fp32_mfma": 157.3, "fp64_valu": 78.6}
+KERNELS = ["jacobi_gram", "jacobi_eig", "jacobi_rotate"]
 
 
 def nominal_flops(n: int, route: str = "svd") -> float:
@@ -36,6 +47,12 @@ def nominal_flops(n: int, route: str = "svd") -> float:
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    path = os.path.join(ROOT, "paper_2008_08825_amd", "csrc", "jacobi.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
 def invariants(A, B, lam, X, n):
@@ -88,9 +105,78 @@ def cpu_baseline(workload: str, n_sample: int):
         "cores": int(threads),
         "kind": "oracle",
         "sample": f"one n={n_sample} solve of the {workload} recipe (seed 0) by the scipy oracle "
-                  f"(potrf x2, gesvd, back-transform), {dt:.2f} s; rate scaled by 98.67 n^3",
+                  f"(potrf x2, gesvd, back-transform, negative half), {dt:.2f} s; rate = 98.67 n^3 / s",
         "seconds": dt,
     }
+
+
+def time_form(api, A, B, precision, route, steps, warmup, work, out):
+    import numpy as np
+    import torch
+
+    kw = dict(route=route, precision=precision, want_negative=True)
+    for i in range(warmup):
+        _, _, info = api.solve_h1(A, B, work=work, out=out, **kw)
+        log(f"{precision} warmup {i}: sweeps={info['sweeps']} status={info['status']}")
+    torch.cuda.synchronize()
+    acc = {"kernel_ms": np.zeros(3), "launches": np.zeros(3), "rotations": 0, "pair_checks": 0,
+           "inner_rotations": 0.0, "phases": np.zeros(8), "sweeps": [], "refine_steps": []}
+    t0 = time.perf_counter()
+    info = None
+    for i in range(steps):
+        ts = time.perf_counter()
+        _, X, info = api.solve_h1(A, B, work=work, out=out, timing=2, **kw)
+        torch.cuda.synchronize()
+        acc["kernel_ms"] += np.array(info["kernel_ms"])
+        acc["launches"] += np.array(info["kernel_launches"])
+        acc["rotations"] += info["rotations"]
+        acc["pair_checks"] += info["pair_checks"]
+        acc["inner_rotations"] += info["inner_rotations"]
+        acc["phases"] += np.array(info["ms_phase"])
+        acc["sweeps"].append(info["sweeps"])
+        acc["refine_steps"].append(info["refine_steps_done"])
+        log(f"{precision} step {i}: {time.perf_counter() - ts:.3f}s sweeps={info['sweeps']} "
+            f"status={info['status']} refine_corr={info['refine_delta']:.2e}")
+    sec = (time.perf_counter() - t0) / steps
+    return sec, acc, info
+
+
+def kernel_report(acc, np_pad, precision, steps):
+    """Algorithmic work per launch over the average launch time, for the three Jacobi kernels."""
+    mfma_peak = PEAK["fp64_mfma"] if precision == "fp64" else PEAK["fp32_mfma"]
+    work = {
+        "jacobi_gram": 8.0 * np_pad * 256 * 10 * acc["pair_checks"],
+        "jacobi_eig": 3840.0 * acc["inner_rotations"],
+        "jacobi_rotate": 8.0 * np_pad * 64 * 64 * acc["rotations"],
+    }
+    rep = {}
+    for k, name in enumerate(KERNELS):
+        ms = acc["kernel_ms"][k]
+        launches = int(acc["launches"][k])
+        tf = work[name] / (ms * 1e-3) / 1e12 if ms > 0 else None
+        bound, peak = ("alu", PEAK["fp64_valu"]) if name == "jacobi_eig" else ("mfma", mfma_peak)
+        rep[name] = {
+            "ms_per_solve": round(ms / steps, 3),
+            "launches": launches,
+            "avg_launch_us": round(ms * 1e3 / launches, 2) if launches else None,
+            "achieved_tflops": round(tf, 3) if tf else None,
+            "bound": bound,
+            "peak_tflops": peak,
+            "frac": round(tf / peak, 4) if tf else None,
+        }
+    return rep
+
+
+def load_traffic(kernel: str, workload: str, precision: str):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha1") != kernel_source_hash():
+        return None
+    return t.get("kernels", {}).get(f"{workload}/{precision}/{kernel}")
 
 
 def main():
@@ -100,7 +186,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="n8192_clustered")
     ap.add_argument("--n", type=int, default=None, help="override the workload size")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"])
     ap.add_argument("--route", default="svd", choices=["svd", "eig"])
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -114,7 +200,6 @@ def main():
                                    "not part of this solver (--gpus must be 1)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2008_08825_amd import api, inputs
@@ -137,87 +222,72 @@ def main():
     A = torch.from_numpy(A_np).to(dev)
     B = torch.from_numpy(B_np).to(dev)
     del A_np, B_np
-    kw = dict(route=args.route, precision=args.precision, want_negative=True)
-    work = torch.empty(api.workspace_bytes(n, route=args.route, precision=args.precision,
-                                           want_negative=True), dtype=torch.uint8, device=dev)
+    np_pad = ((n + 63) // 64) * 64
+    forms = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    wbytes = max(api.workspace_bytes(n, route=args.route, precision=f, want_negative=True) for f in forms)
+    work = torch.empty(wbytes, dtype=torch.uint8, device=dev)
     lam = torch.empty(2 * n, dtype=torch.float64, device=dev)
     Xbuf = torch.empty((2 * n, 2 * n), dtype=torch.complex128, device=dev)
 
-    for i in range(args.warmup):
-        _, _, info = api.solve_h1(A, B, work=work, out=(lam, Xbuf), **kw)
-        log(f"warmup {i}: sweeps={info['sweeps']} status={info['status']}")
-    torch.cuda.synchronize()
-    times = []
-    kern = np.zeros(3)
-    launches = np.zeros(3)
-    rotations = 0
-    pair_checks = 0
-    phases = np.zeros(8)
-    sweeps = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        torch.cuda.synchronize()
-        ts = time.perf_counter()
-        _, X, info = api.solve_h1(A, B, work=work, out=(lam, Xbuf), timing=2, **kw)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - ts)
-        kern += np.array(info["kernel_ms"])
-        launches += np.array(info["kernel_launches"])
-        rotations += info["rotations"]
-        pair_checks += info["pair_checks"]
-        phases += np.array(info["ms_phase"])
-        sweeps.append(info["sweeps"])
-        log(f"step {i}: {times[-1]:.3f}s sweeps={info['sweeps']} rotations={info['rotations']}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    sec = total / args.steps
-    value = nominal_flops(n, args.route) / sec / 1e12
+    results = {}
+    lam_by = {}
+    for f in forms:
+        sec, acc, info = time_form(api, A, B, f, args.route, args.steps, args.warmup, work, (lam, Xbuf))
+        X = Xbuf.mT.conj()
+        res = {
+            "seconds_per_solve": round(sec, 4),
+            "nominal_tflops": round(nominal_flops(n, args.route) / sec / 1e12, 4),
+            "status": info["status"],
+            "jacobi_sweeps": acc["sweeps"],
+            "phase_ms": {k: round(v / args.steps, 3) for k, v in zip(api.PHASES, acc["phases"])},
+            "kernels": kernel_report(acc, np_pad, f, args.steps),
+        }
+        if f == "mixed":
+            res["refine_steps"] = acc["refine_steps"]
+            res["refine_last_correction"] = info["refine_delta"]
+        if not args.no_checks:
+            res["checks"] = invariants(A, B, lam, X, n)
+        lam_by[f] = lam[:n].clone()
+        results[f] = (res, acc)
 
-    np_pad = ((n + 63) // 64) * 64
-    # dominant kernel: Jacobi rotation; algorithmic flops 8 * np * 64 * 64 per rotated pair
-    rot_flops = 8.0 * np_pad * 64 * 64 * rotations
-    rot_ms = kern[2]
-    achieved = rot_flops / (rot_ms * 1e-3) / 1e12 if rot_ms > 0 else None
-    peak = PEAK_FP64_TFLOPS if args.precision == "fp64" else PEAK_FP32_TFLOPS
-    gram_flops = 8.0 * np_pad * 10 * 256 * pair_checks
-    eig_share = kern[1] / (phases[3] if phases[3] > 0 else 1)
-
+    main_form = "mixed" if "mixed" in results else forms[0]
+    res, acc = results[main_form]
+    dom = max(KERNELS, key=lambda k: res["kernels"][k]["ms_per_solve"])
+    kd = res["kernels"][dom]
     out = {
         "metric": METRIC,
-        "value": round(value, 4),
+        "value": res["nominal_tflops"],
         "unit": "TFLOP/s (nominal, Alg. 3 flop model 98.67 n^3 per solve)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(sec * 1e3, 3),
+        "ms_per_step": round(res["seconds_per_solve"] * 1e3, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "dtype": "f64" if main_form == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "route": args.route,
-                   "precision": args.precision, "eigenpairs": "all 2n (positive and mirrored negative)"},
-        "seconds_per_solve": round(sec, 4),
-        "jacobi_sweeps": sweeps,
-        "phase_ms": {k: round(v / args.steps, 3) for k, v in zip(api.PHASES, phases)},
-        "kernel_ms_per_solve": {"jacobi_gram": round(kern[0] / args.steps, 3),
-                                "jacobi_eig": round(kern[1] / args.steps, 3),
-                                "jacobi_rotate": round(kern[2] / args.steps, 3)},
+        "config": {"workload": args.workload, "n": n, "route": args.route, "form": main_form,
+                   "eigenpairs": "all 2n (positive and mirrored negative)"},
         "roofline": {
-            "kernel": "jacobi_rotate (X <- X R, complex, MFMA)",
-            "bound": "mfma",
-            "achieved": round(achieved, 3) if achieved else None,
-            "peak": peak,
+            "kernel": dom,
+            "bound": kd["bound"],
+            "achieved": kd["achieved_tflops"],
+            "peak": kd["peak_tflops"],
             "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4) if achieved else None,
-            "traffic": None,
-            "launches": int(launches[2]),
-            "gram_tflops": round(gram_flops / (kern[0] * 1e-3) / 1e12, 3) if kern[0] > 0 else None,
-            "eig_share_of_jacobi": round(float(eig_share), 3),
+            "frac": kd["frac"],
+            "traffic": load_traffic(dom, args.workload, main_form),
+            "avg_launch_us": kd["avg_launch_us"],
+            "launches": kd["launches"],
         },
     }
-    if not args.no_checks:
-        out["checks"] = invariants(A, B, lam, X, n)
+    for f, (r, _) in results.items():
+        out[f] = r
+    if "fp64" in results and "mixed" in results:
+        out["speedup_mixed_vs_fp64"] = round(results["fp64"][0]["seconds_per_solve"]
+                                             / results["mixed"][0]["seconds_per_solve"], 3)
+        d = ((lam_by["mixed"] - lam_by["fp64"]).abs() / lam_by["fp64"]).max().item()
+        out["mixed_vs_fp64_max_rel_eig_diff"] = d
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle at n={args.cpu_sample_n}")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n)

@@ -57,7 +57,7 @@ typedef struct {
   int max_sweeps;     /* Jacobi sweep limit; 0 = default (30 FP64, 20 mixed)    */
   int refine_steps;   /* mixed only: at most this many refinement steps, fewer
                          once a step's largest correction is <= 1e-6;
-                         0 = default (2), at most 8                            */
+                         0 = default (8), at most 8                            */
   double jacobi_tol;  /* rotate a block pair while max |g_ij|/sqrt(g_ii g_jj)
                          exceeds this; 0 = default n * eps of the bulk dtype    */
   int want_negative;  /* nonzero: also write -lambda and [0 I; I 0] X           */
@@ -82,7 +82,8 @@ typedef struct {
                            inner-eigensolver and rotation kernels (ms)        */
   int kernel_launches[3];
   int refine_steps_done; /* mixed: refinement steps run                       */
-  int reserved[2];
+  double inner_rotations; /* 2 x 2 rotations applied inside the block-pair
+                             eigensolvers, over all sweeps                    */
 } bse_info_t;
 
 /* Fill `opts` with the defaults (route SVD, FP64, lower triangles). */

@@ -54,7 +54,7 @@ class BSEInfo(ctypes.Structure):
         ("kernel_ms", ctypes.c_double * 3),
         ("kernel_launches", ctypes.c_int * 3),
         ("refine_steps_done", ctypes.c_int),
-        ("reserved", ctypes.c_int * 2),
+        ("inner_rotations", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -70,6 +70,7 @@ class BSEInfo(ctypes.Structure):
             "kernel_ms": list(self.kernel_ms),
             "kernel_launches": list(self.kernel_launches),
             "refine_steps_done": self.refine_steps_done,
+            "inner_rotations": self.inner_rotations,
         }
 
 

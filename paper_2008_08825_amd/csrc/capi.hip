@@ -159,6 +159,7 @@ void fill_info(bse_info_t* info, int ret, const JacobiResult& jr) {
   info->rotations = jr.rotations;
   info->max_off = jr.max_off;
   info->pair_checks = jr.pair_checks;
+  info->inner_rotations = jr.inner_rotations;
   for (int i = 0; i < 3; ++i) {
     info->kernel_ms[i] = jr.kernel_ms[i];
     info->kernel_launches[i] = jr.kernel_launches[i];
@@ -290,7 +291,7 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   rw.maxcorr = reinterpret_cast<double*>(base + p.off_small);
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 20;
-  const int steps = o.refine_steps > 0 ? o.refine_steps : 2;
+  const int steps = o.refine_steps > 0 ? o.refine_steps : 8;
   const double eps32 = 1.1920928955078125e-07;
   const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : 4.0 * sqrt((double)(n > 64 ? n : 64)) * eps32;
 

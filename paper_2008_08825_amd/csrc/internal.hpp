@@ -50,6 +50,7 @@ struct JacobiWork {
   int* flags = nullptr;    // per pair
   int* counter = nullptr;  // rotated pairs in the current sweep
   int* inner = nullptr;    // inner Jacobi sweeps in the current sweep
+  int* inner_rot = nullptr;  // inner Jacobi rotations applied in the current sweep
   double* maxoff = nullptr;
 };
 size_t jacobi_work_bytes(int np, int elem_bytes);
@@ -60,6 +61,7 @@ struct JacobiResult {
   int rotations = 0;
   int pair_checks = 0;
   long inner_sweeps = 0;
+  double inner_rotations = 0.0;
   double max_off = 0.0;
   int converged = 0;
   // per-kernel event timing (filled when time_kernels is set)

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
                                                  typename cpx_t<T>::type* __restrict__ Rout,
                                                  int* __restrict__ flags, int* counter,
                                                  double tol, double* maxoff, int max_inner,
-                                                 int* inner_count, double inner_stop2) {
+                                                 int* inner_count, double inner_stop2,
+                                                 int* inner_rot_count) {
   typedef typename cpx_t<T>::type C2;
   __shared__ double Gr[JP][JP + LPAD], Gi[JP][JP + LPAD];
   __shared__ double Rr[JP][JP + LPAD], Ri[JP][JP + LPAD];
@@ -210,6 +211,7 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
   const double tol_in2 = 1.6e-31;  // (4e-16)^2
   const double stop2 = inner_stop2;
   int sweeps_done = 0;
+  int applied = 0;  // rotations applied by this lane (lanes 0..31)
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     int big = 0;
     int anyrot = 0;
@@ -246,7 +248,7 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
           di = aa - tt * ac;
           dj = dd + tt * ac;
         }
-        if (rot) anyrot = 1;
+        if (rot) { anyrot = 1; ++applied; }
         pidx[tid] = i | (j << 8) | (rot << 16);
         prm[tid] = make_double4(cs, sr, si, 0.0);
         pdg[tid] = make_double2(di, dj);
@@ -345,6 +347,11 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
     __syncthreads();
   }
   if (tid == 0) atomicAdd(inner_count, sweeps_done);
+  if (tid < 64) {
+    int a = applied;
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o);
+    if (tid == 0) atomicAdd(inner_rot_count, a);
+  }
 
   // 4. R to global, column-major 64 x 64.
   C2* dst = Rout + (long)k * JP * JP;
@@ -458,6 +465,7 @@ void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w) {
   o = (o + 255) & ~(size_t)255;
   w.counter = reinterpret_cast<int*>(base + o);
   w.inner = reinterpret_cast<int*>(base + o + 32);
+  w.inner_rot = reinterpret_cast<int*>(base + o + 48);
   w.maxoff = reinterpret_cast<double*>(base + o + 64);
 }
 
@@ -501,7 +509,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
       mark(b + 1);
       mark(b + 2);
       k_jac_eig<T><<<pairs, 256, 0, s>>>(N, t, kc, (const C2*)w.part, (C2*)w.R, w.flags, w.counter,
-                                         tol, w.maxoff, 30, w.inner, inner_stop2);
+                                         tol, w.maxoff, 30, w.inner, inner_stop2, w.inner_rot);
       mark(b + 3);
       mark(b + 4);
       k_jac_rotate<T><<<pairs * chunks, 256, 0, s>>>(N, t, W, ld, (const C2*)w.R, w.flags, rrows,
@@ -510,11 +518,12 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     }
     e = hipGetLastError();
     if (e != hipSuccess) { ret = e; break; }
-    int cnt = 0, inner = 0;
+    int cnt = 0, inner = 0, irot = 0;
     double mo = 0.0;
     e = hipMemcpyAsync(&cnt, w.counter, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&mo, w.maxoff, sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(&inner, w.inner, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&irot, w.inner_rot, sizeof(int), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { ret = e; break; }
     if (time_kernels) {
@@ -532,6 +541,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     res.sweeps = sweep + 1;
     res.rotations += cnt;
     res.inner_sweeps += inner;
+    res.inner_rotations += irot;
     res.pair_checks += pairs * (N - 1);
     res.max_off = mo;
     if (cnt == 0) { res.converged = 1; break; }

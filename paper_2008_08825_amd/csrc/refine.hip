@@ -16,8 +16,8 @@
 // T + E^H S L + L S E = diagonal) gives, with R = S - G and Ritz values
 // l_i = T11_ii / G11_ii,
 //   E11_ii = R11_ii / 2,
-//   E11_ij = (T11_ij + l_j R11_ij) / (l_j - l_i)   (i != j; R11_ij / 2 when
-//            l_i and l_j agree to a relative delta: the pair is degenerate),
+//   E11_ij = (T11_ij + l_j R11_ij) / (l_j - l_i)   (i != j; its rotation
+//            part is taken with the exact 2 x 2 Jacobi angle, see k_build),
 //   E21_ij = (T21_ij + l_j R21_ij) / (l_j + l_i),
 // and the positive half updates as x <- x (I + E11 + E21),
 // y <- y (I + E11 - E21).  This is the Newton-type refinement for symmetric
@@ -27,6 +27,9 @@
 // and each pair is scaled by (Re x_k^H y_k)^-1/2 so that v_k^H Sigma v_k = 1.
 #include "common.hpp"
 #include "internal.hpp"
+
+#include <stdio.h>
+#include <stdlib.h>
 
 namespace bse {
 namespace {
@@ -80,10 +83,22 @@ __global__ __launch_bounds__(256) void k_build(int n, const double2* __restrict_
     if (i == j) {
       e11 = make_double2(0.5 * (1.0 - g11.x), 0.0);
     } else {
+      // E11_ij = R_ij / 2 + K_ij / (l_j - l_i) with K = T + (l_i + l_j) R / 2 is the
+      // first-order solution; its rotation part K / (l_j - l_i) = phase(K) / (2 zeta),
+      // zeta = (l_j - l_i) / (2 |K|), is replaced by the exact 2 x 2 Jacobi tangent
+      // phase(K) sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), equal to it for well
+      // separated pairs and bounded by 1 for close pairs, where the first-order
+      // term diverges.
       const double2 r11 = make_double2(-g11.x, -g11.y);
       const double dl = lj - li;
-      if (fabs(dl) <= delta * fmax(fabs(li), fabs(lj))) e11 = cscale(r11, 0.5);
-      else e11 = cscale(cadd(t11, cscale(r11, lj)), 1.0 / dl);
+      const double2 K = cadd(t11, cscale(r11, 0.5 * (li + lj)));
+      const double aK = sqrt(cabs2(K));
+      e11 = cscale(r11, 0.5);
+      if (aK > 0.0 && !(fabs(dl) <= delta * fmax(fabs(li), fabs(lj)) && aK <= delta * fabs(lj))) {
+        const double zeta = dl / (2.0 * aK);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        e11 = cadd(e11, cscale(K, t / aK));
+      }
       mc = fmax(mc, sqrt(cabs2(e11)));
     }
     const double2 r21 = make_double2(-g21.x, -g21.y);
@@ -173,6 +188,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     if (e != hipSuccess) return e;
     *max_corr = mc;
     *steps_done = it + 1;
+    if (getenv("BSE_DEBUG")) fprintf(stderr, "[bse] refinement step %d: largest correction %.3e\n", it + 1, mc);
     // the error left after a step is of the order of the square of its correction
     if (mc <= stop_corr) break;
   }

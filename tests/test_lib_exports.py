@@ -56,3 +56,37 @@ def test_host_only_queries():
     assert lib.bse_solve_h1(0, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), ctypes.byref(info), None) == 0
     assert lib.bse_backward(-1, None, 1, None, None, 1, None, 1, None, 0, None) == -1
     assert lib.bse_status_string(5, 4).decode() == "A - B is not positive definite"
+
+
+def test_struct_layout_matches_binding(tmp_path):
+    """sizeof and field offsets of bse_opts_t / bse_info_t agree between C and the ctypes binding."""
+    import shutil
+    import subprocess
+
+    from paper_2008_08825_amd import api
+
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "layout.c"
+    fields_o = [f for f, _ in api.BSEOpts._fields_]
+    fields_i = [f for f, _ in api.BSEInfo._fields_]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {",
+             'printf("%zu %zu\\n", sizeof(bse_opts_t), sizeof(bse_info_t));']
+    for f in fields_o:
+        lines.append(f'printf("o {f} %zu\\n", offsetof(bse_opts_t, {f}));')
+    for f in fields_i:
+        lines.append(f'printf("i {f} %zu\\n", offsetof(bse_info_t, {f}));')
+    lines.append("return 0; }")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    so, si = map(int, out[0].split())
+    assert so == ctypes.sizeof(api.BSEOpts) and si == ctypes.sizeof(api.BSEInfo)
+    for line in out[1:]:
+        if not line:
+            continue
+        kind, name, off = line.split()
+        cls = api.BSEOpts if kind == "o" else api.BSEInfo
+        assert getattr(cls, name).offset == int(off), (kind, name)
