@@ -42,6 +42,8 @@ struct Plan {
   int n = 0, np = 0, mixed = 0;
   size_t off_m1 = 0, off_m2 = 0, off_w = 0, off_y = 0;
   size_t off_x1 = 0, off_x2 = 0, off_q = 0, off_f = 0, off_p1 = 0, off_p2 = 0;
+  size_t off_z = 0, off_inv = 0;
+  int alg2 = 0;
   size_t off_lc = 0, off_wc = 0;
   size_t off_linv = 0, off_sigma = 0, off_perm = 0, off_invlam = 0, off_status = 0;
   size_t off_bnorm = 0, off_anorm = 0, off_lamu = 0, off_scl = 0, off_ritz = 0, off_small = 0;
@@ -54,6 +56,7 @@ bool opts_valid(const bse_opts_t& o) {
   if (o.precision != BSE_PREC_FP64 && o.precision != BSE_PREC_MIXED) return false;
   if (o.max_sweeps < 0 || o.refine_steps < 0 || o.refine_steps > 8 || !(o.jacobi_tol >= 0.0))
     return false;
+  if (o.route == BSE_ROUTE_EIG && o.precision != BSE_PREC_FP64) return false;  // Alg. 2: FP64 only
   if (!(o.uplo == 0 || o.uplo == 'L' || o.uplo == 'U' || o.uplo == 'l' || o.uplo == 'u')) return false;
   for (int i = 0; i < 6; ++i)
     if (o.reserved[i] != 0) return false;
@@ -65,6 +68,7 @@ Plan make_plan(int n, const bse_opts_t& o) {
   p.n = n;
   p.np = pad64(n > 0 ? n : 1);
   p.mixed = o.precision == BSE_PREC_MIXED;
+  p.alg2 = o.route == BSE_ROUTE_EIG;
   const size_t U = (size_t)p.np * p.np * sizeof(double2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -74,7 +78,12 @@ Plan make_plan(int n, const bse_opts_t& o) {
   };
   p.off_m1 = take(U);
   p.off_m2 = take(U);
-  if (!p.mixed) {
+  if (p.alg2) {
+    p.off_w = take(U);
+    p.off_y = take(U);
+    p.off_z = take(U);
+    p.off_inv = take((size_t)p.np * 64 * sizeof(double2));
+  } else if (!p.mixed) {
     p.off_w = take(U);
     p.off_y = take(U);
   } else {
@@ -255,6 +264,79 @@ int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* la
   return ret;
 }
 
+// Alg. 2 (CHOL): L L^H = A - B; M = L^H (A + B) L; M V_M = V_M D by the same
+// one-sided Jacobi (M is Hermitian positive definite, so its columns after the
+// iteration are q_k d_k); Lambda = D^1/2; V1 = L^-H V_M Lambda^1/2 (blocked
+// triangular solve), V2 = L V_M Lambda^-1/2; X = [(V1 + V2)/2; (V2 - V1)/2].
+int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
+               int ldx, char* base, const Plan& p, const bse_opts_t& o, bse_info_t* info,
+               int want_timing, hipStream_t s) {
+  const int np = p.np;
+  const long ld = np;
+  double2* M1 = reinterpret_cast<double2*>(base + p.off_m1);
+  double2* M2 = reinterpret_cast<double2*>(base + p.off_m2);
+  double2* W = reinterpret_cast<double2*>(base + p.off_w);
+  double2* Y = reinterpret_cast<double2*>(base + p.off_y);
+  double2* Z = reinterpret_cast<double2*>(base + p.off_z);
+  double2* inv = reinterpret_cast<double2*>(base + p.off_inv);
+  double2* linv = reinterpret_cast<double2*>(base + p.off_linv);
+  double* d = reinterpret_cast<double*>(base + p.off_sigma);
+  int* perm = reinterpret_cast<int*>(base + p.off_perm);
+  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
+  double* fx = reinterpret_cast<double*>(base + p.off_anorm);
+  double* fy = reinterpret_cast<double*>(base + p.off_bnorm);
+  int* status = reinterpret_cast<int*>(base + p.off_status);
+  JacobiWork jw;
+  jacobi_carve(np, sizeof(double), base + p.off_jac, jw);
+  const int upper = (o.uplo == 'U' || o.uplo == 'u');
+  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
+  const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (double)(n > 64 ? n : 64) * 2.220446049250313e-16;
+
+  Timer tm(want_timing != 0, s);
+  const int slots[8] = {0, 1, 2, 3, 4, 5, -1, -1};
+  tm.mark();
+  const int big = 0x7fffffff;
+  BSE_TRY(hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, s));
+  if (int e = form_and_check_args(n, A, lda, B, ldb, upper, base, p, s)) return e;
+  // A + B is not factored by Alg. 2; a factorisation of a copy checks its definiteness.
+  BSE_TRY(hipMemcpyAsync(Z, M1, (size_t)np * np * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  BSE_TRY(mirror_upper_z(np, M1, ld, s));
+  tm.mark();
+  BSE_TRY(cholesky_z(np, n, Z, ld, linv, status, 0, s));
+  BSE_TRY(cholesky_z(np, n, M2, ld, linv, status, n, s));
+  if (int st = read_status(status, n, info, s)) return st;
+  tm.mark();
+  {
+    GemmDesc t;  // T = (A + B) L
+    t.M = np; t.N = np; t.K = np;
+    t.A = M1; t.lda = ld; t.opA = 0;
+    t.B = M2; t.ldb = ld; t.opB = 0; t.triB = 1;
+    t.C = W; t.ldc = ld;
+    BSE_TRY(gemm_z(t, s));
+    GemmDesc m = tri_gemm(np, ld, M2, 1, W, 0, 0, Y);  // M = L^H T
+    m.mask = n;
+    BSE_TRY(gemm_z(m, s));
+  }
+  tm.mark();
+  JacobiResult jr;
+  BSE_TRY(jacobi_z(np, Y, ld, jw, tol, max_sweeps, jr, s, want_timing >= 2));
+  tm.mark();
+  BSE_TRY(colnorm_z(np, Y, ld, d, s));
+  BSE_TRY(alg2_lambda_z(n, d, lamu, perm, lambda, o.want_negative, fx, fy, s));
+  BSE_TRY(gather_scale_z(n, np, Y, ld, perm, fx, M1, s));  // V_M Lambda^1/2 (sorted)
+  BSE_TRY(gather_scale_z(n, np, Y, ld, perm, fy, W, s));   // V_M Lambda^-1/2
+  tm.mark();
+  BSE_TRY(gemm_z(tri_gemm(np, ld, M2, 0, W, 0, 0, Y), s));  // V2 = L V_M Lambda^-1/2
+  BSE_TRY(trsm_lh_z(np, M2, ld, M1, W, inv, s));            // V1 = L^-H V_M Lambda^1/2
+  BSE_TRY(assemble_z(n, W, Y, ld, nullptr, nullptr, static_cast<double2*>(X), ldx, o.want_negative, s));
+  tm.mark();
+  BSE_TRY(hipStreamSynchronize(s));
+  const int ret = jr.converged ? 0 : 2 * n + 1;
+  fill_info(info, ret, jr);
+  tm.fill(info, slots);
+  return ret;
+}
+
 int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
                 int ldx, char* base, const Plan& p, const bse_opts_t& o, bse_info_t* info,
                 int want_timing, hipStream_t s) {
@@ -400,7 +482,7 @@ int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb, double* 
   if (work_bytes < p.total) return -10;
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
-  if (o.route == BSE_ROUTE_EIG) return -11;  // the Alg. 2 route is not built into this entry yet
+  if (p.alg2) return solve_alg2(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
   if (p.mixed) return solve_mixed(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
   return solve_fp64(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
 }

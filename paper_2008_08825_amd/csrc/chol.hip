@@ -170,6 +170,46 @@ __global__ __launch_bounds__(256) void k_potf2_inv(C2* M, long ld, int j0,
   }
 }
 
+// Inverses of the 64 x 64 diagonal blocks of a lower-triangular L (one
+// workgroup per block), written as lower triangles, block b at inv + b * 64 * 64.
+__global__ __launch_bounds__(256) void k_tri_inv_blocks(const double2* __restrict__ L, long ld,
+                                                        double2* __restrict__ inv) {
+  __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
+  __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
+  const int tid = threadIdx.x;
+  const int j0 = blockIdx.x * NB;
+  const double2* D = L + j0 + (long)j0 * ld;
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;
+    const double2 v = (r >= c) ? D[r + (long)c * ld] : make_double2(0.0, 0.0);
+    Lr[r][c] = v.x; Li[r][c] = v.y;
+  }
+  __syncthreads();
+  if (tid < NB) {
+    const int c = tid;
+    for (int i = 0; i < NB; ++i) { Xr[i][c] = 0.0; Xi[i][c] = 0.0; }
+    // L has a real positive diagonal
+    Xr[c][c] = 1.0 / Lr[c][c];
+    for (int i = c + 1; i < NB; ++i) {
+      double sr = 0.0, si = 0.0;
+      for (int k = c; k < i; ++k) {
+        const double ar = Lr[i][k], ai = Li[i][k], xr = Xr[k][c], xi = Xi[k][c];
+        sr += ar * xr - ai * xi;
+        si += ar * xi + ai * xr;
+      }
+      const double dinv = 1.0 / Lr[i][i];
+      Xr[i][c] = -sr * dinv;
+      Xi[i][c] = -si * dinv;
+    }
+  }
+  __syncthreads();
+  double2* out = inv + (long)blockIdx.x * NB * NB;
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;
+    out[r + c * NB] = make_double2(Xr[r][c], Xi[r][c]);
+  }
+}
+
 // Upper triangle of a square np x np matrix from its lower one: M[i][j] = conj(M[j][i]), i < j.
 __global__ __launch_bounds__(256) void k_mirror_upper(int np, double2* M, long ld) {
   __shared__ double2 tile[64][65];
@@ -255,6 +295,33 @@ static hipError_t cholesky_run(int np, int n_real, C2* M, long ld, C2* linv, int
 hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, int* status,
                       int base, hipStream_t s) {
   return cholesky_run<double2>(np, n_real, M, ld, linv, status, base, s);
+}
+
+hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
+                     hipStream_t s) {
+  const int nb = np / NB;
+  k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int i = nb - 1; i >= 0; --i) {
+    // Z_i = (L_ii^-1)^H Rhs_i
+    GemmDesc g;
+    g.M = NB; g.N = np; g.K = NB;
+    g.A = inv + (long)i * NB * NB; g.lda = NB; g.opA = 1; g.triA = 1;
+    g.B = Rhs + (long)i * NB; g.ldb = ld; g.opB = 0;
+    g.C = Z + (long)i * NB; g.ldc = ld;
+    if ((e = gemm_z(g, s)) != hipSuccess) return e;
+    if (i == 0) break;
+    // Rhs_{0..i-1} -= (L^H)_{0..i-1, i} Z_i,  (L^H)_{r, c} = conj(L_{c, r})
+    GemmDesc u;
+    u.M = i * NB; u.N = np; u.K = NB;
+    u.A = L + (long)i * NB; u.lda = ld; u.opA = 1;
+    u.B = Z + (long)i * NB; u.ldb = ld; u.opB = 0;
+    u.C = Rhs; u.ldc = ld;
+    u.alpha_re = -1.0; u.beta_re = 1.0;
+    if ((e = gemm_z(u, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status,

@@ -123,6 +123,37 @@ __global__ __launch_bounds__(256) void k_write_lambda(int n, const double* __res
   if (want_negative) lambda[n + r] = -lam[j];
 }
 
+__global__ __launch_bounds__(256) void k_gather_scale(int n, int np, const double2* __restrict__ W,
+                                                      long ld, const int* __restrict__ perm,
+                                                      const double* __restrict__ f,
+                                                      double2* __restrict__ out) {
+  const int r = blockIdx.y;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= np) return;
+  if (r >= n) { out[i + (long)r * ld] = make_double2(0.0, 0.0); return; }
+  int k = perm[r];
+  if (k < 0 || k >= n) k = r;
+  out[i + (long)r * ld] = cscale(W[i + (long)k * ld], f[r]);
+}
+
+__global__ __launch_bounds__(256) void k_alg2_lambda(int n, const double* __restrict__ d,
+                                                     double* __restrict__ lam) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k < n) lam[k] = sqrt(d[k]);
+}
+
+__global__ __launch_bounds__(256) void k_alg2_scales(int n, const double* __restrict__ d,
+                                                     const int* __restrict__ perm,
+                                                     double* __restrict__ fx, double* __restrict__ fy) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  int k = perm[r];
+  if (k < 0 || k >= n) k = r;
+  const double dk = d[k], lk = sqrt(dk);
+  fy[r] = 1.0 / (dk * sqrt(lk));  // column of V_M Lambda^-1/2 from the column q_k d_k
+  fx[r] = sqrt(lk) / dk;          // column of V_M Lambda^1/2
+}
+
 __global__ __launch_bounds__(256) void k_assemble(int n, const double2* __restrict__ V1,
                                                   const double2* __restrict__ V2, long ldv,
                                                   const int* __restrict__ perm,
@@ -131,9 +162,9 @@ __global__ __launch_bounds__(256) void k_assemble(int n, const double2* __restri
   const int r = blockIdx.y;
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  int k = perm[r];
+  int k = perm ? perm[r] : r;
   if (k < 0 || k >= n) k = r;
-  const double sc = 0.5 * scl[k];
+  const double sc = scl ? 0.5 * scl[k] : 0.5;
   const double2 a = V1[i + (long)k * ldv];
   const double2 b = V2[i + (long)k * ldv];
   const double2 top = cscale(cadd(a, b), sc);
@@ -205,6 +236,22 @@ hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* b
   k_lambda<<<(np + 255) / 256, 256, 0, s>>>(n, np, anorm, bnorm, lam, invlam, scl);
   k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
   k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);
+  return hipGetLastError();
+}
+
+hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* perm,
+                          const double* f, double2* out, hipStream_t s) {
+  dim3 g((np + 255) / 256, np);
+  k_gather_scale<<<g, 256, 0, s>>>(n, np, W, ld, perm, f, out);
+  return hipGetLastError();
+}
+
+hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double* lambda,
+                         int want_negative, double* fx, double* fy, hipStream_t s) {
+  k_alg2_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, d, lam);
+  k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
+  k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);
+  k_alg2_scales<<<(n + 255) / 256, 256, 0, s>>>(n, d, perm, fx, fy);
   return hipGetLastError();
 }
 

@@ -81,6 +81,11 @@ hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol,
 
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status, int base,
                       hipStream_t s);
+// Z = L^-H Rhs for lower-triangular L (np x np, np % 64 == 0): block back
+// substitution with the inverses of the 64 x 64 diagonal blocks (inv holds
+// np * 64 complex values) and MFMA GEMM updates; Rhs is overwritten.
+hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
+                     hipStream_t s);
 // M[i][j] = conj(M[j][i]) for i < j (np % 64 == 0).
 hipError_t mirror_upper_z(int np, double2* M, long ld, hipStream_t s);
 // complex64 copy of the lower triangle, strict upper part zero.
@@ -128,8 +133,17 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
                     const RefineWork& w, int max_steps, double stop_corr, double* lam, double* scl,
                     double* max_corr, int* steps_done, hipStream_t s);
 
+// out[:, r] = W[:, perm r] * f_r (r < n; zero for r >= n; np rows).
+hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* perm,
+                          const double* f, double2* out, hipStream_t s);
+// Alg. 2 eigenvalue bookkeeping from d = column norms of the iterated M:
+// lam_k = sqrt(d_k), ascending order perm, output lambda (and -lambda),
+// fy_r = 1 / (d sqrt(lam)) and fx_r = sqrt(lam) / d for sorted position r.
+hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double* lambda,
+                         int want_negative, double* fx, double* fy, hipStream_t s);
+
 // X[:, r] = s_k [(V1_k + V2_k)/2; (V2_k - V1_k)/2] with k = perm[r] (and the
-// mirrored negative half).
+// mirrored negative half); perm == nullptr means k = r, scl == nullptr s_k = 1.
 hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
                       const double* scl, double2* X, long ldx, int want_negative, hipStream_t s);
 

@@ -238,3 +238,44 @@ def test_mixed_non_hpd_status(gpu_lib):
     _, _, info = gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B2).to(DEV),
                                   precision="mixed", check=False)
     assert info["status"] == ob.chol_status(A, B2) == n + 31
+
+
+# ---------------------------------------------------------------- Alg. 2 route
+@pytest.mark.parametrize("n", [1, 3, 64, 100, 200])
+def test_alg2_parity(gpu_lib, n):
+    """CHOL route: eigenvalues of L^H (A+B) L, square roots; triangular solve for V1."""
+    A, B = inputs.coupled(n, seed=60 + n)
+    lam, X, info = run(gpu_lib, A, B, route="eig")
+    assert info["status"] == 0
+    lam_o, X_o = ob.solve_chol_eig(A, B)
+    lam_s, _ = ob.solve_chol_svd(A, B)
+    e = om.rel_eig_err(lam, lam_o)
+    print(f"alg2 n={n} rel_eig_err={e:.2e} vs svd {om.rel_eig_err(lam, lam_s):.2e} "
+          f"resid={om.residual(A, B, lam, X):.2e} sorth={om.sigma_orth_err(X):.2e}")
+    assert e < 1e-11
+    assert om.residual(A, B, lam, X) < 1e-13
+    assert om.sigma_orth_err(X) < 1e-10
+    err, gap = om.eigvec_errors(lam_o, X_o, X, cluster_rtol=1e-9)
+    assert np.all(err <= 1e-10 + 1e-13 / np.minimum(gap, 1.0))
+
+
+def test_alg2_negative_half_and_status(gpu_lib):
+    n = 90
+    A, B = inputs.coupled(n, seed=61)
+    lam, X, _ = run(gpu_lib, A, B, route="eig", want_negative=True)
+    assert np.array_equal(lam[n:], -lam[:n])
+    H = ob.bse_matrix(A, B)
+    assert np.linalg.norm(H @ X - X * lam[None, :]) < 1e-12 * np.linalg.norm(H) * np.linalg.norm(X)
+    for k, sgn in [(40, 1), (55, -1)]:
+        B2 = B.copy()
+        B2[k, k] = sgn * (A[k, k].real + 1.0)
+        _, _, info = gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B2).to(DEV),
+                                      route="eig", check=False)
+        assert info["status"] == ob.chol_status(A, B2)
+
+
+def test_alg2_mixed_is_rejected(gpu_lib):
+    A, B = inputs.coupled(8, seed=62)
+    with pytest.raises(gpu_lib.BSEError):
+        gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV),
+                         route="eig", precision="mixed")
