@@ -495,11 +495,19 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
   };
   hipError_t ret = hipSuccess;
   const bool debug = getenv("BSE_DEBUG") != nullptr;
-  // A pair's inner iteration ends after a sweep whose largest relative
-  // off-diagonal entry was below sqrt(inner_stop2).
-  double inner_stop2 = inner_stop * inner_stop;
-  if (const char* v = getenv("BSE_INNER_STOP")) inner_stop2 = atof(v) * atof(v);
+  // A pair's inner iteration ends after an inner sweep whose largest relative
+  // off-diagonal entry was below s, which leaves about s^2 behind.  The
+  // rotation of a pair need not be more exact than the orthogonality the
+  // other pairs of the same outer sweep disturb it by, so s follows the
+  // previous outer sweep's largest off-diagonal measure (0.3 of it, leaving
+  // about a tenth of its square) down to the floor inner_stop; the first
+  // sweep uses 1e-3.
+  double prev_off = -1.0;
+  const bool adaptive = getenv("BSE_FIXED_INNER") == nullptr;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    double sstop = inner_stop;
+    if (adaptive) sstop = fmax(inner_stop, prev_off < 0.0 ? 1.0e-3 : fmin(1.0e-3, 0.3 * prev_off));
+    const double inner_stop2 = sstop * sstop;
     e = hipMemsetAsync(w.counter, 0, 128, s);
     if (e != hipSuccess) { ret = e; break; }
     for (int t = 0; t < N - 1; ++t) {
@@ -538,6 +546,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     if (debug)
       fprintf(stderr, "[bse] sweep %d: rotated pairs %d of %d, max off %.3e, inner sweeps %.2f per pair\n",
               sweep + 1, cnt, pairs * (N - 1), mo, cnt > 0 ? (double)inner / cnt : 0.0);
+    prev_off = mo;
     res.sweeps = sweep + 1;
     res.rotations += cnt;
     res.inner_sweeps += inner;
