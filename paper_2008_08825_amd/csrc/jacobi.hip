@@ -128,9 +128,12 @@ __global__ __launch_bounds__(256) void k_jac_gram(int N, int t, const typename c
 // Each step applies 32 disjoint rotations chosen by the circle method on the
 // 64 indices: first the rotation parameters, then every 2 x 2 block of G is
 // replaced by J_P^H G_PQ J_Q (P <= Q, mirrored for P > Q) and the rotated
-// column pairs of R by R J.
+// column pairs of R by R J.  G and R hold complex values as double2 (one
+// 16-byte LDS access per entry); EIG_THREADS threads share the updates.
+constexpr int EIG_THREADS = 512;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
+__global__ __launch_bounds__(EIG_THREADS) void k_jac_eig(int N, int t, int kc,
                                                  const typename cpx_t<T>::type* __restrict__ part,
                                                  typename cpx_t<T>::type* __restrict__ Rout,
                                                  int* __restrict__ flags, int* counter,
@@ -138,12 +141,13 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
                                                  int* inner_count, double inner_stop2,
                                                  int* inner_rot_count) {
   typedef typename cpx_t<T>::type C2;
-  __shared__ double Gr[JP][JP + LPAD], Gi[JP][JP + LPAD];
-  __shared__ double Rr[JP][JP + LPAD], Ri[JP][JP + LPAD];
+  constexpr int NT = EIG_THREADS;
+  __shared__ double2 G[JP][JP + LPAD];
+  __shared__ double2 R[JP][JP + LPAD];
   __shared__ double4 prm[32];   // (c, Re s, Im s, unused) of rotation m
   __shared__ double2 pdg[32];   // new diagonal (d_i, d_j)
   __shared__ int pidx[32];      // i | j << 8 | rotate << 16
-  __shared__ double red[256];
+  __shared__ double red[NT];
   __shared__ unsigned short blkPQ[528];
   __shared__ int nrot;
   __shared__ int sweepbig;
@@ -152,10 +156,10 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
   // (P, Q) of the 528 pairs of rotation slots with P <= Q, as P | Q << 8
   for (int Q = 0, b = 0; Q < 32; ++Q)
     for (int P = 0; P <= Q; ++P, ++b)
-      if ((b & 255) == tid) blkPQ[b] = (unsigned short)(P | (Q << 8));
+      if ((b % NT) == tid) blkPQ[b] = (unsigned short)(P | (Q << 8));
 
   // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian matrix.
-  for (int e = tid; e < NTILE * 256; e += 256) {
+  for (int e = tid; e < NTILE * 256; e += NT) {
     const int tile = e >> 8, el = e & 255;
     const int m = 16 * kTileI[tile] + (el & 15), n = 16 * kTileJ[tile] + (el >> 4);
     if (m < n) continue;
@@ -167,28 +171,28 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
       si += (double)v.y;
     }
     if (m == n) {
-      Gr[m][m] = sr; Gi[m][m] = 0.0;
+      G[m][m] = make_double2(sr, 0.0);
     } else {
-      Gr[m][n] = sr; Gi[m][n] = si;
-      Gr[n][m] = sr; Gi[n][m] = -si;
+      G[m][n] = make_double2(sr, si);
+      G[n][m] = make_double2(sr, -si);
     }
   }
   __syncthreads();
 
   // 2. Relative off-diagonal measure of the pair.
   double off2 = 0.0;
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += NT) {
     const int i = e & 63, j = e >> 6;
     if (i > j) {
-      const double dd = Gr[i][i] * Gr[j][j];
-      const double a2 = Gr[i][j] * Gr[i][j] + Gi[i][j] * Gi[i][j];
+      const double dd = G[i][i].x * G[j][j].x;
+      const double a2 = cabs2(G[i][j]);
       if (dd > 0.0) off2 = fmax(off2, a2 / dd);
       else if (a2 > 0.0) off2 = 1.0;
     }
   }
   red[tid] = off2;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = NT / 2; s > 0; s >>= 1) {
     if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
     __syncthreads();
   }
@@ -200,14 +204,13 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
   }
 
   // 3. Cyclic Jacobi.
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += NT) {
     const int i = e & 63, j = e >> 6;
-    Rr[i][j] = (i == j) ? 1.0 : 0.0;
-    Ri[i][j] = 0.0;
+    R[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   // A sweep whose largest relative off-diagonal entry (before its rotation)
-  // was below 1e-10 leaves O(1e-20) behind (quadratic convergence), so the
-  // confirming sweep that would rotate nothing is skipped.
+  // was below sqrt(inner_stop2) leaves O(inner_stop2) behind (quadratic
+  // convergence), so the confirming sweep that would rotate nothing is skipped.
   const double tol_in2 = 1.6e-31;  // (4e-16)^2
   const double stop2 = inner_stop2;
   int sweeps_done = 0;
@@ -221,8 +224,9 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
         int i = (a == 0) ? 0 : ((a - 1 + step) % (JP - 1)) + 1;
         int j = ((b - 1 + step) % (JP - 1)) + 1;
         if (i > j) { const int tmp = i; i = j; j = tmp; }
-        const double aa = Gr[i][i], dd = Gr[j][j];
-        const double cre = Gr[i][j], cim = Gi[i][j];
+        const double aa = G[i][i].x, dd = G[j][j].x;
+        const double2 cc = G[i][j];
+        const double cre = cc.x, cim = cc.y;
         const double ac2 = cre * cre + cim * cim;
         int rot = 0;
         double cs = 1.0, sr = 0.0, si = 0.0, di = aa, dj = dd;
@@ -254,10 +258,10 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
         pdg[tid] = make_double2(di, dj);
       }
       __syncthreads();
-      // 2 x 2 blocks (P, Q), P <= Q: 528 of them, at most three per thread.
+      // 2 x 2 blocks (P, Q), P <= Q: 528 of them.
 #pragma unroll
-      for (int u = 0; u < 3; ++u) {
-        const int blk = tid + 256 * u;
+      for (int u = 0; u < (528 + NT - 1) / NT; ++u) {
+        const int blk = tid + NT * u;
         if (blk < 528) {
           const int pq = blkPQ[blk];
           const int P = pq & 255, Q = pq >> 8;
@@ -267,15 +271,15 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
             const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
             if (P == Q) {
               const double2 dg = pdg[P];
-              Gr[iP][iP] = dg.x; Gi[iP][iP] = 0.0;
-              Gr[jP][jP] = dg.y; Gi[jP][jP] = 0.0;
-              Gr[iP][jP] = 0.0; Gi[iP][jP] = 0.0;
-              Gr[jP][iP] = 0.0; Gi[jP][iP] = 0.0;
+              G[iP][iP] = make_double2(dg.x, 0.0);
+              G[jP][jP] = make_double2(dg.y, 0.0);
+              G[iP][jP] = make_double2(0.0, 0.0);
+              G[jP][iP] = make_double2(0.0, 0.0);
             } else {
-              double2 g00 = make_double2(Gr[iP][iQ], Gi[iP][iQ]);
-              double2 g01 = make_double2(Gr[iP][jQ], Gi[iP][jQ]);
-              double2 g10 = make_double2(Gr[jP][iQ], Gi[jP][iQ]);
-              double2 g11 = make_double2(Gr[jP][jQ], Gi[jP][jQ]);
+              double2 g00 = G[iP][iQ];
+              double2 g01 = G[iP][jQ];
+              double2 g10 = G[jP][iQ];
+              double2 g11 = G[jP][jQ];
               if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
                 const double4 pp = prm[Q];
                 const double c = pp.x;
@@ -298,36 +302,34 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
                 const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
                 g00 = t00; g01 = t01; g10 = t10; g11 = t11;
               }
-              Gr[iP][iQ] = g00.x; Gi[iP][iQ] = g00.y;
-              Gr[iP][jQ] = g01.x; Gi[iP][jQ] = g01.y;
-              Gr[jP][iQ] = g10.x; Gi[jP][iQ] = g10.y;
-              Gr[jP][jQ] = g11.x; Gi[jP][jQ] = g11.y;
-              Gr[iQ][iP] = g00.x; Gi[iQ][iP] = -g00.y;
-              Gr[jQ][iP] = g01.x; Gi[jQ][iP] = -g01.y;
-              Gr[iQ][jP] = g10.x; Gi[iQ][jP] = -g10.y;
-              Gr[jQ][jP] = g11.x; Gi[jQ][jP] = -g11.y;
+              G[iP][iQ] = g00;
+              G[iP][jQ] = g01;
+              G[jP][iQ] = g10;
+              G[jP][jQ] = g11;
+              G[iQ][iP] = cconj(g00);
+              G[jQ][iP] = cconj(g01);
+              G[iQ][jP] = cconj(g10);
+              G[jQ][jP] = cconj(g11);
             }
           }
         }
       }
-      // R <- R J for the rotated column pairs: row r, rotations m = wave + 4 u
+      // R <- R J for the rotated column pairs: row r, rotations m = (tid / 64) + (NT / 64) u
       {
         const int r = tid & 63;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const int m = (tid >> 6) + 4 * u;
+        for (int u = 0; u < 32 / (NT / 64); ++u) {
+          const int m = (tid >> 6) + (NT / 64) * u;
           const int xm = pidx[m];
           if (xm >> 16) {
             const int i = xm & 255, j = (xm >> 8) & 255;
             const double4 pp = prm[m];
             const double c = pp.x;
             const double2 sv = make_double2(pp.y, pp.z);
-            const double2 ri = make_double2(Rr[r][i], Ri[r][i]);
-            const double2 rj = make_double2(Rr[r][j], Ri[r][j]);
-            const double2 ni = csub(cscale(ri, c), cmul(cconj(sv), rj));
-            const double2 nj = cadd(cmul(sv, ri), cscale(rj, c));
-            Rr[r][i] = ni.x; Ri[r][i] = ni.y;
-            Rr[r][j] = nj.x; Ri[r][j] = nj.y;
+            const double2 ri = R[r][i];
+            const double2 rj = R[r][j];
+            R[r][i] = csub(cscale(ri, c), cmul(cconj(sv), rj));
+            R[r][j] = cadd(cmul(sv, ri), cscale(rj, c));
           }
         }
       }
@@ -355,9 +357,9 @@ __global__ __launch_bounds__(256) void k_jac_eig(int N, int t, int kc,
 
   // 4. R to global, column-major 64 x 64.
   C2* dst = Rout + (long)k * JP * JP;
-  for (int e = tid; e < JP * JP; e += 256) {
+  for (int e = tid; e < JP * JP; e += NT) {
     const int i = e & 63, j = e >> 6;
-    C2 v; v.x = (T)Rr[i][j]; v.y = (T)Ri[i][j];
+    C2 v; v.x = (T)R[i][j].x; v.y = (T)R[i][j].y;
     dst[i + JP * j] = v;
   }
   if (tid == 0) {
@@ -516,7 +518,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
       k_jac_gram<T><<<pairs * kc, 256, 0, s>>>(N, t, W, ld, rc, kc, (C2*)w.part);
       mark(b + 1);
       mark(b + 2);
-      k_jac_eig<T><<<pairs, 256, 0, s>>>(N, t, kc, (const C2*)w.part, (C2*)w.R, w.flags, w.counter,
+      k_jac_eig<T><<<pairs, EIG_THREADS, 0, s>>>(N, t, kc, (const C2*)w.part, (C2*)w.R, w.flags, w.counter,
                                          tol, w.maxoff, 30, w.inner, inner_stop2, w.inner_rot);
       mark(b + 3);
       mark(b + 4);
