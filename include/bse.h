@@ -128,7 +128,8 @@ int bse_solve_batched(int batch, const int* n,
                       void* work, size_t work_bytes,
                       const bse_opts_t* opts, bse_info_t* info, void* stream);
 
-/* Workspace for bse_backward of order n. */
+/* Workspace for bse_backward of order n (two n x n complex128 buffers);
+ * 0 for n < 0 or n > 46000. */
 size_t bse_backward_workspace_bytes(int n);
 
 /* Gradient of a real loss L(lambda) with respect to Hermitian A and B.
@@ -143,6 +144,11 @@ size_t bse_backward_workspace_bytes(int n);
  *   w          n doubles (device)
  *   gA, ldga   n x n complex128 output (full Hermitian matrix)
  *   gB, ldgb   n x n complex128 output
+ *   work       device workspace of work_bytes >= bse_backward_workspace_bytes(n)
+ * With x = a - b and y = a + b the sums equal G_A = (P + Q)/2 and
+ * G_B = (Q - P)/2 for P = x diag(w) x^H, Q = y diag(w) y^H, so the work is two
+ * Hermitian rank-n products (lower tiles only), about 8 n^3 real flops.
+ * Synchronises on stream before returning.
  * Return codes as above (0, -i, <= -1000). */
 int bse_backward(int n, const void* X, int ldx, const double* w,
                  void* gA, int ldga, void* gB, int ldgb,

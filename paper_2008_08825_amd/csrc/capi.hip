@@ -523,11 +523,11 @@ int bse_solve_batched(int batch, const int* n, const void* const* A, const int* 
   return first;
 }
 
-size_t bse_backward_workspace_bytes(int n) { return n >= 0 ? 256 : 0; }
+size_t bse_backward_workspace_bytes(int n) { return n >= 0 && n <= 46000 ? adjoint_work_bytes(n) : 0; }
 
 int bse_backward(int n, const void* X, int ldx, const double* w, void* gA, int ldga, void* gB,
                  int ldgb, void* work, size_t work_bytes, void* stream) {
-  if (n < 0) return -1;
+  if (n < 0 || n > 46000) return -1;
   if (n > 0 && !X) return -2;
   if (ldx < (2 * n > 1 ? 2 * n : 1)) return -3;
   if (n > 0 && !w) return -4;
@@ -535,30 +535,12 @@ int bse_backward(int n, const void* X, int ldx, const double* w, void* gA, int l
   if (ldga < (n > 1 ? n : 1)) return -6;
   if (n > 0 && !gB) return -7;
   if (ldgb < (n > 1 ? n : 1)) return -8;
-  (void)work;
-  (void)work_bytes;
   if (n == 0) return 0;
+  if (!work) return -9;
+  if (work_bytes < adjoint_work_bytes(n)) return -10;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const double2* Xa = static_cast<const double2*>(X);
-  const double2* Xb = Xa + n;
-  // G_A = a diag(w) a^H + b diag(w) b^H ;  G_B = a diag(w) b^H + b diag(w) a^H
-  const double2* lhs[2] = {Xa, Xb};
-  const double2* rhsA[2] = {Xa, Xb};
-  const double2* rhsB[2] = {Xb, Xa};
-  for (int t = 0; t < 2; ++t) {
-    GemmDesc g;
-    g.M = n; g.N = n; g.K = n;
-    g.A = lhs[t]; g.lda = ldx; g.opA = 0;
-    g.B = rhsA[t]; g.ldb = ldx; g.opB = 1;
-    g.kscale = w;
-    g.C = gA; g.ldc = ldga;
-    g.beta_re = t == 0 ? 0.0 : 1.0;
-    BSE_TRY(gemm_z(g, s));
-    GemmDesc h = g;
-    h.B = rhsB[t];
-    h.C = gB; h.ldc = ldgb;
-    BSE_TRY(gemm_z(h, s));
-  }
+  BSE_TRY(adjoint_z(n, static_cast<const double2*>(X), ldx, w, static_cast<double2*>(gA), ldga,
+                    static_cast<double2*>(gB), ldgb, work, s));
   BSE_TRY(hipStreamSynchronize(s));
   return 0;
 }

@@ -147,4 +147,11 @@ hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double*
 hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
                       const double* scl, double2* X, long ldx, int want_negative, hipStream_t s);
 
+// Eigenvalue adjoint: G_A = sum_k w_k (a_k a_k^H + b_k b_k^H),
+// G_B = sum_k w_k (a_k b_k^H + b_k a_k^H) for X = [a; b] (2n x n, ldx), written
+// as full Hermitian n x n matrices; work holds adjoint_work_bytes(n) bytes.
+size_t adjoint_work_bytes(int n);
+hipError_t adjoint_z(int n, const double2* X, long ldx, const double* w, double2* gA, long ldga,
+                     double2* gB, long ldgb, void* work, hipStream_t s);
+
 }  // namespace bse

@@ -55,6 +55,9 @@ def test_host_only_queries():
     assert lib.bse_solve_h1(4, 16, 4, 16, 4, 16, 16, 8, 16, 10, ctypes.byref(o), ctypes.byref(info), None) == -10
     assert lib.bse_solve_h1(0, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), ctypes.byref(info), None) == 0
     assert lib.bse_backward(-1, None, 1, None, None, 1, None, 1, None, 0, None) == -1
+    assert lib.bse_backward(4, 16, 8, 16, 16, 4, 16, 4, None, 0, None) == -9
+    assert lib.bse_backward(4, 16, 8, 16, 16, 4, 16, 4, 16, 10, None) == -10
+    assert lib.bse_backward_workspace_bytes(4) > 2 * 16 * 16
     assert lib.bse_status_string(5, 4).decode() == "A - B is not positive definite"
 
 
