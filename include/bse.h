@@ -62,7 +62,18 @@ typedef struct {
                          exceeds this; 0 = default n * eps of the bulk dtype    */
   int want_negative;  /* nonzero: also write -lambda and [0 I; I 0] X           */
   int uplo;           /* 'L' (default when 0) or 'U'                            */
-  int reserved[6];    /* must be zero                                           */
+  int tile_entries;   /* rows in tile_table; 0 = built-in tile choice           */
+  int reserved0;      /* must be zero                                           */
+  const int* tile_table; /* host array of tile_entries rows {np_max, kc, rrows}
+                         for the Jacobi kernels: a problem of padded order np
+                         (n rounded up to 64) takes the first row with
+                         np <= np_max; kc = row chunks of the Gram sum per
+                         block pair (a power of two, np % (16 kc) == 0), rrows
+                         = rows per rotation work group (a multiple of 64
+                         dividing np).  A row that does not fit np, or no
+                         row, means the built-in choice for that problem.
+                         Written by the autotuner of the Python package.     */
+  int reserved[2];    /* must be zero                                           */
 } bse_opts_t;
 
 typedef struct {
@@ -118,9 +129,18 @@ size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* op
  *   A, B, lambda, X                  host arrays of device pointers
  *   info                             optional host array of `batch` entries
  * Returns 0 if every problem succeeded, else the status of the first problem
- * (in index order) that failed, with every problem's own status in info[i].
- * Problems are processed together: each phase is launched once for the
- * whole batch with per-problem descriptors. */
+ * (in index order) that failed, with every problem's own status in info[i];
+ * argument errors: -1 batch, -2 n, -3 A/lda, -5 B/ldb, -7 lambda, -8 X/ldx,
+ * -10 work NULL, -11 work_bytes too small, -12 opts invalid.
+ * SVD route (FP64 or mixed): the problems are processed together; each phase
+ * runs as grouped launches over the whole batch, with a table of per-problem
+ * kernel arguments and a map from work groups to problems staged in `work`,
+ * and the Jacobi sweeps of all problems advance together (one host readback
+ * per sweep; a problem that has converged skips the remaining sweeps).  The
+ * results of each problem are those bse_solve_h1 computes with the same
+ * opts and tile table.  Alg. 2 route: the problems run one after another.
+ * info[0].timing requests timing (as for bse_solve_h1); ms_phase then holds
+ * the phase times of the whole batch in every entry. */
 int bse_solve_batched(int batch, const int* n,
                       const void* const* A, const int* lda,
                       const void* const* B, const int* ldb,

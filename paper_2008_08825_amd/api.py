@@ -36,7 +36,10 @@ class BSEOpts(ctypes.Structure):
         ("jacobi_tol", ctypes.c_double),
         ("want_negative", ctypes.c_int),
         ("uplo", ctypes.c_int),
-        ("reserved", ctypes.c_int * 6),
+        ("tile_entries", ctypes.c_int),
+        ("reserved0", ctypes.c_int),
+        ("tile_table", ctypes.POINTER(ctypes.c_int)),
+        ("reserved", ctypes.c_int * 2),
     ]
 
 
@@ -136,7 +139,8 @@ class BSEError(RuntimeError):
 
 
 def make_opts(route="svd", precision="fp64", max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
-              want_negative=False, uplo="L") -> BSEOpts:
+              want_negative=False, uplo="L", tiles=None) -> BSEOpts:
+    """Options struct; ``tiles`` = rows ``(np_max, kc, rrows)`` of the Jacobi tile table."""
     o = BSEOpts()
     load_library().bse_default_opts(ctypes.byref(o))
     o.route = ROUTES[route]
@@ -146,6 +150,12 @@ def make_opts(route="svd", precision="fp64", max_sweeps=0, refine_steps=0, jacob
     o.jacobi_tol = float(jacobi_tol)
     o.want_negative = 1 if want_negative else 0
     o.uplo = ord(uplo)
+    if tiles:
+        flat = [int(v) for row in tiles for v in row]
+        arr = (ctypes.c_int * len(flat))(*flat)
+        o._tiles_keep = arr  # the C side reads it during the call
+        o.tile_table = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int))
+        o.tile_entries = len(flat) // 3
     return o
 
 
@@ -184,7 +194,7 @@ def workspace_bytes(n: int, **kw) -> int:
 def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
              want_negative=False, max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
              timing=False, check=True, work: Optional[torch.Tensor] = None,
-             out=None):
+             out=None, tiles=None):
     """All eigenpairs of H1 = [[A, B], [-B, -A]] (lower triangles of A, B read).
 
     Returns ``(lam, X, info)``: ``lam`` (n, ascending; 2n with ``want_negative``),
@@ -202,7 +212,7 @@ def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
     n = A.shape[0]
     dev = A.device
     ncols = 2 * n if want_negative else n
-    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, ua)
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, ua, tiles)
     if out is None:
         lam = torch.empty(ncols, dtype=torch.float64, device=dev)
         Xbuf = torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
@@ -228,8 +238,14 @@ def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
 
 
 def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
-                  max_sweeps=0, refine_steps=0, jacobi_tol=0.0, check=True):
-    """Independent problems ``(A_i, B_i)`` in one library call; returns lists of (lam, X) and infos."""
+                  max_sweeps=0, refine_steps=0, jacobi_tol=0.0, check=True, tiles=None,
+                  timing=0, work=None):
+    """Independent problems ``(A_i, B_i)`` in one library call; returns lists of (lam, X) and infos.
+
+    ``tiles``: rows ``(np_max, kc, rrows)`` of the Jacobi tile table (see
+    :mod:`paper_2008_08825_amd.tune`); ``work``: optional preallocated uint8
+    CUDA workspace of at least ``batched_workspace_bytes`` bytes.
+    """
     lib = load_library()
     count = len(As)
     if len(Bs) != count:
@@ -254,13 +270,16 @@ def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
         Xbufs.append(Xb)
         ns.append(n); pas.append(pa); ldas.append(max(1, lda)); pbs.append(pb); ldbs.append(max(1, ldb))
         plams.append(lam.data_ptr()); pxs.append(Xb.data_ptr()); ldxs.append(max(1, 2 * n))
-    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, "U")
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, "U", tiles)
     IA = ctypes.c_int * max(count, 1)
     PA = ctypes.c_void_p * max(count, 1)
     c_n = IA(*ns)
     need = int(lib.bse_batched_workspace_bytes(count, c_n, ctypes.byref(o)))
-    work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     infos = (BSEInfo * max(count, 1))()
+    if count:
+        infos[0].timing = int(timing)
     with torch.cuda.device(dev):
         st = lib.bse_solve_batched(count, c_n, PA(*pas), IA(*ldas), PA(*pbs), IA(*ldbs), PA(*plams),
                                    PA(*pxs), IA(*ldxs), work.data_ptr(), work.numel(), ctypes.byref(o),
@@ -270,6 +289,13 @@ def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
         raise BSEError(st, ns[0] if ns else 0, out_infos)
     results = [(lams[i], Xbufs[i].mT.conj()) for i in range(count)]
     return results, out_infos, st
+
+
+def batched_workspace_bytes(ns, *, route="svd", precision="fp64", tiles=None) -> int:
+    lib = load_library()
+    o = make_opts(route, precision, tiles=tiles)
+    IA = ctypes.c_int * max(len(ns), 1)
+    return int(lib.bse_batched_workspace_bytes(len(ns), IA(*[int(v) for v in ns]), ctypes.byref(o)))
 
 
 def backward(X: torch.Tensor, w: torch.Tensor):

@@ -1,0 +1,705 @@
+// Many independent BSE problems of different orders in one call.
+//
+// Each phase of the SVD route (Alg. 3) runs as grouped launches over the
+// whole batch: the host builds, per launch, a table of per-problem kernel
+// arguments and a map from every flat work group to (problem, work group
+// within the problem) (see the op launches in common.hpp), so one launch
+// fills the chip with the work of all problems at once:
+//   form        one launch (plus the complex64 copies and mirrors, mixed form)
+//   Cholesky    three launches per 64-column panel (diagonal blocks of both
+//               factors of every problem that has that panel, panel solve,
+//               trailing update), Alg. 3 steps 1-2
+//   W           one grouped GEMM, step 3's matrix
+//   Jacobi      per round three launches (Gram, inner eigensolver, rotation)
+//               over the problems that have that round; per sweep one small
+//               launch that closes each problem's sweep on the device
+//               (converged problems then skip all later work) and one
+//               readback of the number of problems still active
+//   finalize    grouped column norms, scaling, GEMMs, Rayleigh quotients,
+//               sort and the final setup of step 6
+//   refinement  (mixed form) three grouped GEMM launches and two small ones
+//               per step over the problems whose last correction was still
+//               above the stopping level.
+// Problems are ordered by padded order, largest first, so the problems that
+// take part in a Jacobi round or a Cholesky panel form a prefix of every
+// table and a launch uses a prefix of its map.
+//
+// Every problem's arithmetic is that of bse_solve_h1 (same kernels, same
+// per-problem workspace plan), so a batch reproduces the single-problem
+// results; only the Jacobi tiles (Gram row chunks, rotation rows) default to
+// smaller splits, since the batch rather than one problem fills the chip.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/bse.h"
+#include "common.hpp"
+#include "internal.hpp"
+#include "plan.hpp"
+
+namespace bse {
+namespace {
+
+constexpr int kBig = 0x7fffffff;
+
+// Table staging: host-built tables are copied into a device arena just
+// before the launch that reads them.  Copies and launches share one stream,
+// so when the arena wraps around, every launch that read the overwritten
+// bytes has already run.
+struct Arena {
+  char* dev = nullptr;
+  size_t cap = 0, cur = 0;
+  hipStream_t s = nullptr;
+  std::vector<std::vector<char>> keep;  // host sources stay valid until the call returns
+
+  hipError_t put(const void* src, size_t bytes, const void** out) {
+    const size_t need = align256(bytes);
+    if (need > cap) return hipErrorInvalidValue;
+    if (cur + need > cap) cur = 0;
+    keep.emplace_back(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
+    char* d = dev + cur;
+    cur += need;
+    *out = d;
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(d, keep.back().data(), bytes, hipMemcpyHostToDevice, s);
+  }
+};
+
+template <class A>
+struct Grp {
+  std::vector<A> tab;
+  std::vector<int2> map;
+  std::vector<int> start;  // first map entry of each table row
+  void add(const A& a, int blocks) {
+    if (blocks <= 0) return;
+    start.push_back((int)map.size());
+    const int row = (int)tab.size();
+    tab.push_back(a);
+    for (int b = 0; b < blocks; ++b) map.push_back(make_int2(row, b));
+  }
+  int blocks() const { return (int)map.size(); }
+  // map entries of the first `rows` table rows
+  int prefix(int rows) const {
+    return rows >= (int)start.size() ? (int)map.size() : start[rows];
+  }
+};
+
+struct Dev {
+  const void* tab = nullptr;
+  const int2* map = nullptr;
+  int blocks = 0;
+};
+
+template <class A>
+hipError_t stage(Arena& ar, const Grp<A>& g, Dev& d) {
+  d.blocks = g.blocks();
+  if (d.blocks == 0) return hipSuccess;
+  hipError_t e = ar.put(g.tab.data(), g.tab.size() * sizeof(A), &d.tab);
+  const void* m = nullptr;
+  if (e == hipSuccess) e = ar.put(g.map.data(), g.map.size() * sizeof(int2), &m);
+  d.map = static_cast<const int2*>(m);
+  return e;
+}
+
+inline GemmArgs<double> args_of(const GemmDesc& d, double*) { return gemm_args_z(d); }
+inline GemmArgs<float> args_of(const GemmDesc& d, float*) { return gemm_args_c(d); }
+
+// Stage and launch a grouped GEMM (all rows share opA, opB).
+template <typename T>
+hipError_t run_gemm(Arena& ar, const std::vector<GemmDesc>& descs, hipStream_t s) {
+  if (descs.empty()) return hipSuccess;
+  Grp<GemmArgs<T>> g;
+  for (const GemmDesc& d : descs) {
+    g.add(args_of(d, static_cast<T*>(nullptr)), gemm_tiles(d));
+  }
+  Dev dv;
+  hipError_t e = stage(ar, g, dv);
+  if (e != hipSuccess) return e;
+  return group_gemm(sizeof(T) == 8 ? 0 : 1, descs[0].opA, descs[0].opB, dv.tab, dv.map, dv.blocks, s);
+}
+
+typedef hipError_t (*GroupFn)(GroupOp, const void*, const int2*, int, int, hipStream_t);
+
+template <class A>
+hipError_t run_op(Arena& ar, const Grp<A>& g, GroupFn fn, GroupOp op, int aux, hipStream_t s) {
+  Dev dv;
+  hipError_t e = stage(ar, g, dv);
+  if (e != hipSuccess) return e;
+  return fn(op, dv.tab, dv.map, dv.blocks, aux, s);
+}
+
+// Built-in Jacobi tiles for a problem in a batch: Gram row chunks of about
+// 256 rows, rotation groups of the largest of 256 / 128 / 64 rows dividing np.
+void batch_tiles(const bse_opts_t& o, int np, int* kc, int* rrows) {
+  pick_tiles(o, np, kc, rrows);
+  if (*kc > 0) return;
+  int k = 1;
+  while (np / (2 * k) >= 256 && jacobi_tiles_valid(np, 2 * k, 64) && 2 * k <= jacobi_default_kc(np)) k *= 2;
+  *kc = k;
+  *rrows = np % 256 == 0 ? 256 : (np % 128 == 0 ? 128 : 64);
+}
+
+struct Prob {
+  int idx = 0, n = 0, np = 0;
+  const double2* A = nullptr;
+  const double2* B = nullptr;
+  long lda = 0, ldb = 0, ldx = 0;
+  double* lambda = nullptr;
+  double2* X = nullptr;
+  char* base = nullptr;
+  Plan p;
+  int kc = 0, rrows = 0;
+  int status = 0;
+  // mixed refinement state
+  double2 *x = nullptr, *y = nullptr, *q = nullptr, *f = nullptr;
+  int rsteps = 0, rdone = 0;
+  double rcorr = 0.0;
+  template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+};
+
+// Header of the batch workspace (device): per-problem status words, Jacobi
+// states and refinement corrections, and the active-problem counter.
+struct Header {
+  size_t off_status = 0, off_state = 0, off_corr = 0, off_active = 0, off_arena = 0, arena = 0;
+  size_t total = 0;
+};
+
+size_t arena_bytes(const std::vector<int>& nps) {
+  // largest single launch: table rows (at most 3 per problem) plus its map
+  size_t rows = 0, blocks = 0;
+  for (int np : nps) {
+    const int pairs = np / 64;
+    size_t b = (size_t)2 * tiles64(np);
+    b = std::max(b, (size_t)3 * tiles64(np));
+    b = std::max(b, (size_t)2 * cols_blocks(np, np));
+    b = std::max(b, (size_t)pairs * jacobi_default_kc(np));
+    b = std::max(b, (size_t)pairs * (np / 64));
+    b = std::max(b, (size_t)2 * np);
+    blocks += 3 * b + 16;  // a phase may stage up to three maps at once (Jacobi)
+    rows += 4;
+  }
+  return align256(rows * 256) + align256(blocks * sizeof(int2)) + 4096;
+}
+
+Header make_header(int batch, const std::vector<int>& nps) {
+  Header h;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  h.off_status = take((size_t)batch * sizeof(int));
+  h.off_state = take((size_t)batch * sizeof(JacState));
+  h.off_corr = take((size_t)batch * sizeof(double));
+  h.off_active = take(256);
+  h.arena = arena_bytes(nps);
+  h.off_arena = take(h.arena);
+  h.total = off;
+  return h;
+}
+
+}  // namespace
+
+size_t batched_workspace(int batch, const int* n, const bse_opts_t& o) {
+  std::vector<int> nps;
+  size_t total = 0;
+  for (int i = 0; i < batch; ++i) {
+    if (n[i] <= 0) continue;
+    nps.push_back(pad64(n[i]));
+    total += align256(make_plan(n[i], o).total);
+  }
+  return make_header(batch, nps).total + total + 256;
+}
+
+// Grouped solve of the SVD route (FP64 or mixed).  Argument checks are done
+// by the caller.  Returns 0 or the first failing status (index order); every
+// problem's status and statistics go to info[i] if given.
+int solve_batched_grouped(int batch, const int* n, const void* const* A, const int* lda,
+                          const void* const* B, const int* ldb, double* const* lambda,
+                          void* const* X, const int* ldx, void* work, const bse_opts_t& o,
+                          bse_info_t* info, int want_timing, hipStream_t s) {
+  const bool mixed = o.precision == BSE_PREC_MIXED;
+  const int upper = (o.uplo == 'U' || o.uplo == 'u');
+  char* wbase = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
+
+  // ---- problems, largest padded order first
+  std::vector<Prob> probs;
+  std::vector<int> nps;
+  for (int i = 0; i < batch; ++i) {
+    if (n[i] <= 0) continue;
+    Prob pr;
+    pr.idx = i;
+    pr.n = n[i];
+    pr.np = pad64(n[i]);
+    pr.A = static_cast<const double2*>(A[i]);
+    pr.B = static_cast<const double2*>(B[i]);
+    pr.lda = lda[i];
+    pr.ldb = ldb[i];
+    pr.ldx = ldx[i];
+    pr.lambda = lambda[i];
+    pr.X = static_cast<double2*>(X[i]);
+    pr.p = make_plan(n[i], o);
+    batch_tiles(o, pr.np, &pr.kc, &pr.rrows);
+    probs.push_back(pr);
+    nps.push_back(pr.np);
+  }
+  const Header h = make_header(batch, nps);
+  size_t off = h.total;
+  for (Prob& pr : probs) {
+    pr.base = wbase + off;
+    off += align256(pr.p.total);
+  }
+  std::stable_sort(probs.begin(), probs.end(), [](const Prob& a, const Prob& b) { return a.np > b.np; });
+  const int P = (int)probs.size();
+  if (P == 0) return 0;
+  int* d_status = reinterpret_cast<int*>(wbase + h.off_status);
+  JacState* d_state = reinterpret_cast<JacState*>(wbase + h.off_state);
+  double* d_corr = reinterpret_cast<double*>(wbase + h.off_corr);
+  int* d_active = reinterpret_cast<int*>(wbase + h.off_active);
+  Arena ar;
+  ar.dev = wbase + h.off_arena;
+  ar.cap = h.arena;
+  ar.s = s;
+
+  Timer tm(want_timing != 0, s);
+  const int slots[8] = {0, 1, 2, 3, 4, 5, 6, -1};
+  tm.mark();
+  // ---- header: statuses "no failure", zero Jacobi states and corrections
+  {
+    std::vector<int> st(batch, kBig);
+    BSE_TRY(hipMemcpyAsync(d_status, st.data(), (size_t)batch * sizeof(int), hipMemcpyHostToDevice, s));
+    BSE_TRY(hipStreamSynchronize(s));
+    BSE_TRY(hipMemsetAsync(d_state, 0, (size_t)batch * sizeof(JacState), s));
+    BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
+  }
+
+  // ---- form M1 = A + B, M2 = A - B (and complex64 lower copies, full FP64 M1, M2 for the refinement)
+  {
+    Grp<FormArgs> g;
+    for (const Prob& pr : probs) {
+      const FormArgs a = {pr.n, pr.np, pr.A, pr.lda, pr.B, pr.ldb, upper,
+                          pr.at<double2>(pr.p.off_m1), pr.at<double2>(pr.p.off_m2), pr.np};
+      g.add(a, tiles64(pr.np));
+    }
+    BSE_TRY(run_op(ar, g, group_chol, G_FORM, 0, s));
+    if (mixed) {
+      Grp<ToC64Args> c;
+      Grp<MirrorArgs> m;
+      for (const Prob& pr : probs) {
+        const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
+        const ToC64Args c1 = {pr.np, pr.at<double2>(pr.p.off_m1), pr.np, pr.at<float2>(pr.p.off_lc)};
+        const ToC64Args c2 = {pr.np, pr.at<double2>(pr.p.off_m2), pr.np, pr.at<float2>(pr.p.off_lc + half)};
+        c.add(c1, tiles64(pr.np));
+        c.add(c2, tiles64(pr.np));
+        const MirrorArgs m1 = {pr.np, pr.at<double2>(pr.p.off_m1), pr.np};
+        const MirrorArgs m2 = {pr.np, pr.at<double2>(pr.p.off_m2), pr.np};
+        m.add(m1, tiles64(pr.np));
+        m.add(m2, tiles64(pr.np));
+      }
+      BSE_TRY(run_op(ar, c, group_chol, G_TOC64, 0, s));
+      BSE_TRY(run_op(ar, m, group_chol, G_MIRROR, 0, s));
+    }
+  }
+  tm.mark();
+
+  // ---- blocked Cholesky of both factors of every problem, panel by panel
+  {
+    const int kmax = probs[0].np / 64;
+    for (int k = 0; k < kmax; ++k) {
+      const int j0 = 64 * k;
+      std::vector<GemmDesc> trsm, herk;
+      Grp<Potf2Args<double2>> gz;
+      Grp<Potf2Args<float2>> gc;
+      for (const Prob& pr : probs) {
+        if (pr.np <= j0) break;
+        const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
+        for (int f = 0; f < 2; ++f) {
+          void* M;
+          void* linv;
+          if (mixed) {
+            M = pr.base + pr.p.off_lc + (f ? half : 0);
+            linv = pr.base + pr.p.off_linv + (size_t)f * 64 * 64 * sizeof(float2);
+            const Potf2Args<float2> a = {static_cast<float2*>(M), pr.np, static_cast<float2*>(linv),
+                                         d_status + pr.idx, f ? pr.n : 0, pr.n};
+            gc.add(a, 1);
+          } else {
+            M = pr.base + (f ? pr.p.off_m2 : pr.p.off_m1);
+            linv = pr.base + pr.p.off_linv + (size_t)f * 64 * 64 * sizeof(double2);
+            const Potf2Args<double2> a = {static_cast<double2*>(M), pr.np, static_cast<double2*>(linv),
+                                          d_status + pr.idx, f ? pr.n : 0, pr.n};
+            gz.add(a, 1);
+          }
+          const int rows = pr.np - j0 - 64;
+          if (rows <= 0) continue;
+          const size_t es = mixed ? sizeof(float2) : sizeof(double2);
+          char* panel = static_cast<char*>(M) + ((size_t)(j0 + 64) + (size_t)j0 * pr.np) * es;
+          GemmDesc t;  // L21 = A21 L11^-H
+          t.M = rows; t.N = 64; t.K = 64;
+          t.A = panel; t.lda = pr.np; t.opA = 0;
+          t.B = linv; t.ldb = 64; t.opB = 1; t.triB = 1;
+          t.C = panel; t.ldc = pr.np;
+          trsm.push_back(t);
+          GemmDesc u;  // A22 -= L21 L21^H, lower tiles
+          u.M = rows; u.N = rows; u.K = 64;
+          u.A = panel; u.lda = pr.np; u.opA = 0;
+          u.B = panel; u.ldb = pr.np; u.opB = 1;
+          u.C = static_cast<char*>(M) + ((size_t)(j0 + 64) + (size_t)(j0 + 64) * pr.np) * es;
+          u.ldc = pr.np;
+          u.alpha_re = -1.0; u.beta_re = 1.0; u.lowerC = 1;
+          herk.push_back(u);
+        }
+      }
+      if (mixed) {
+        BSE_TRY(run_op(ar, gc, group_chol, G_POTF2_C, j0, s));
+        BSE_TRY(run_gemm<float>(ar, trsm, s));
+        BSE_TRY(run_gemm<float>(ar, herk, s));
+      } else {
+        BSE_TRY(run_op(ar, gz, group_chol, G_POTF2_Z, j0, s));
+        BSE_TRY(run_gemm<double>(ar, trsm, s));
+        BSE_TRY(run_gemm<double>(ar, herk, s));
+      }
+    }
+    std::vector<int> st(batch, kBig);
+    BSE_TRY(hipMemcpyAsync(st.data(), d_status, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
+    BSE_TRY(hipStreamSynchronize(s));
+    for (Prob& pr : probs) pr.status = st[pr.idx] == kBig ? 0 : st[pr.idx];
+  }
+  std::vector<Prob*> ok;
+  for (Prob& pr : probs)
+    if (pr.status == 0) ok.push_back(&pr);
+  tm.mark();
+
+  // ---- W = L2^H L1 (step 3's matrix; zero outside the leading n x n block)
+  {
+    std::vector<GemmDesc> w;
+    for (Prob* pr : ok) {
+      const size_t half = (size_t)pr->np * pr->np * sizeof(float2);
+      GemmDesc g = mixed ? tri_gemm(pr->np, pr->np, pr->base + pr->p.off_lc + half, 1,
+                                    pr->base + pr->p.off_lc, 0, 1, pr->base + pr->p.off_wc)
+                         : tri_gemm(pr->np, pr->np, pr->base + pr->p.off_m2, 1, pr->base + pr->p.off_m1,
+                                    0, 1, pr->base + pr->p.off_w);
+      g.mask = pr->n;
+      w.push_back(g);
+    }
+    if (mixed) BSE_TRY(run_gemm<float>(ar, w, s));
+    else BSE_TRY(run_gemm<double>(ar, w, s));
+  }
+  tm.mark();
+
+  // ---- one-sided block Jacobi over the whole batch
+  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : (mixed ? 20 : 30);
+  const double eps32 = 1.1920928955078125e-07, eps64 = 2.220446049250313e-16;
+  std::vector<JacState> states(batch);
+  if (!ok.empty()) {
+    Grp<GramArgs<double2>> gz;
+    Grp<GramArgs<float2>> gc;
+    Grp<EigArgs<double2>> ez;
+    Grp<EigArgs<float2>> ec;
+    Grp<RotArgs<double2>> rz;
+    Grp<RotArgs<float2>> rc;
+    Grp<SweepArgs> sw;
+    std::vector<int> rounds;
+    for (Prob* pr : ok) {
+      const int np = pr->np;
+      JacobiWork jw;
+      jacobi_carve(np, mixed ? sizeof(float) : sizeof(double), pr->base + pr->p.off_jac, jw, pr->kc,
+                   pr->rrows);
+      JacState* st = d_state + pr->idx;
+      jw.counter = &st->counter;
+      jw.inner = &st->inner;
+      jw.inner_rot = &st->inner_rot;
+      jw.maxoff = &st->maxoff;
+      const double nn = (double)(pr->n > 64 ? pr->n : 64);
+      const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : nn * eps64);
+      if (mixed) {
+        float2* W = pr->at<float2>(pr->p.off_wc);
+        gc.add(gram_args_c(np, W, np, jw, &st->done), jacobi_gram_blocks_kc(np, jw.kc));
+        ec.add(eig_args_c(np, jw, tol, &st->stop2, &st->done), jacobi_eig_blocks(np));
+        rc.add(rot_args_c(np, W, np, jw, &st->done), jacobi_rot_blocks_rr(np, jw.rrows));
+      } else {
+        double2* W = pr->at<double2>(pr->p.off_w);
+        gz.add(gram_args_z(np, W, np, jw, &st->done), jacobi_gram_blocks_kc(np, jw.kc));
+        ez.add(eig_args_z(np, jw, tol, &st->stop2, &st->done), jacobi_eig_blocks(np));
+        rz.add(rot_args_z(np, W, np, jw, &st->done), jacobi_rot_blocks_rr(np, jw.rrows));
+      }
+      const SweepArgs sa = {st, d_active, jacobi_pairs(np) * jacobi_rounds(np), max_sweeps,
+                            mixed ? 1.0e-5 : 1.0e-10, 1};
+      sw.add(sa, 1);
+      rounds.push_back(jacobi_rounds(np));
+    }
+    Dev dg, de, dr, ds;
+    if (mixed) {
+      BSE_TRY(stage(ar, gc, dg));
+      BSE_TRY(stage(ar, ec, de));
+      BSE_TRY(stage(ar, rc, dr));
+    } else {
+      BSE_TRY(stage(ar, gz, dg));
+      BSE_TRY(stage(ar, ez, de));
+      BSE_TRY(stage(ar, rz, dr));
+    }
+    BSE_TRY(stage(ar, sw, ds));
+    const int R = rounds[0];
+    // rows (problems) taking part in round t: a prefix, problems sorted by np
+    std::vector<int> part(R);
+    for (int t = 0; t < R; ++t) {
+      int c = 0;
+      while (c < (int)rounds.size() && rounds[c] > t) ++c;
+      part[t] = c;
+    }
+    for (int sweep = 0;; ++sweep) {
+      BSE_TRY(hipMemsetAsync(d_active, 0, sizeof(int), s));
+      BSE_TRY(group_jacobi(G_SWEEP, ds.tab, ds.map, ds.blocks, sweep, s));
+      int active = 0;
+      BSE_TRY(hipMemcpyAsync(&active, d_active, sizeof(int), hipMemcpyDeviceToHost, s));
+      BSE_TRY(hipStreamSynchronize(s));
+      if (active == 0) break;
+      for (int t = 0; t < R; ++t) {
+        const int c = part[t];
+        if (mixed) {
+          BSE_TRY(group_jacobi(G_GRAM_C, dg.tab, dg.map, gc.prefix(c), t, s));
+          BSE_TRY(group_jacobi(G_EIG_C, de.tab, de.map, ec.prefix(c), t, s));
+          BSE_TRY(group_jacobi(G_ROT_C, dr.tab, dr.map, rc.prefix(c), t, s));
+        } else {
+          BSE_TRY(group_jacobi(G_GRAM_Z, dg.tab, dg.map, gz.prefix(c), t, s));
+          BSE_TRY(group_jacobi(G_EIG_Z, de.tab, de.map, ez.prefix(c), t, s));
+          BSE_TRY(group_jacobi(G_ROT_Z, dr.tab, dr.map, rz.prefix(c), t, s));
+        }
+      }
+    }
+    BSE_TRY(hipMemcpyAsync(states.data(), d_state, (size_t)batch * sizeof(JacState), hipMemcpyDeviceToHost, s));
+    BSE_TRY(hipStreamSynchronize(s));
+  }
+  tm.mark();
+
+  // ---- finalize: scaled singular columns, Rayleigh quotients, back-transform
+  if (!ok.empty()) {
+    if (mixed) {
+      Grp<ColnormArgs<float2>> n1, n2, n3;
+      Grp<ScaleArgs<float2>> sc;
+      Grp<LambdaArgs> la;
+      Grp<C64Args> cv;
+      std::vector<GemmDesc> v2, t, v1;
+      for (Prob* pr : ok) {
+        const int np = pr->np;
+        const size_t half = (size_t)np * np * sizeof(float2);
+        float2* L1c = pr->at<float2>(pr->p.off_lc);
+        float2* L2c = pr->at<float2>(pr->p.off_lc + half);
+        float2* Wc = pr->at<float2>(pr->p.off_wc);
+        float2* Yc = pr->at<float2>(pr->p.off_wc + half);
+        double* sigma = pr->at<double>(pr->p.off_sigma);
+        double* bnorm = pr->at<double>(pr->p.off_bnorm);
+        double* anorm = pr->at<double>(pr->p.off_anorm);
+        double* invlam = pr->at<double>(pr->p.off_invlam);
+        double* scl = pr->at<double>(pr->p.off_scl);
+        n1.add({Wc, np, np, sigma}, np);
+        sc.add({pr->n, np, Wc, np, sigma}, cols_blocks(np, np));
+        n2.add({Wc, np, np, bnorm}, np);
+        v2.push_back(tri_gemm(np, np, L2c, 0, Wc, 0, 0, Yc));  // V2 = L2 Ws
+        t.push_back(tri_gemm(np, np, L1c, 1, Yc, 0, 0, Wc));   // T = L1^H V2
+        n3.add({Wc, np, np, anorm}, np);
+        la.add({pr->n, np, anorm, bnorm, pr->at<double>(pr->p.off_lamu), invlam, scl}, (np + 255) / 256);
+        GemmDesc v = tri_gemm(np, np, L1c, 0, Wc, 0, 0, L2c);  // V1 = L1 T Lambda^-1
+        v.colscale = invlam;
+        v1.push_back(v);
+        cv.add({np, L2c, np, pr->at<double2>(pr->p.off_x1), np, scl}, cols_blocks(np, np));
+        cv.add({np, Yc, np, pr->at<double2>(pr->p.off_x2), np, scl}, cols_blocks(np, np));
+        pr->x = pr->at<double2>(pr->p.off_x1);
+        pr->y = pr->at<double2>(pr->p.off_x2);
+        pr->q = pr->at<double2>(pr->p.off_q);
+        pr->f = pr->at<double2>(pr->p.off_f);
+      }
+      BSE_TRY(run_op(ar, n1, group_finalize, G_COLNORM_C, 0, s));
+      BSE_TRY(run_op(ar, sc, group_finalize, G_SCALE_C, 0, s));
+      BSE_TRY(run_op(ar, n2, group_finalize, G_COLNORM_C, 0, s));
+      tm.mark();
+      BSE_TRY(run_gemm<float>(ar, v2, s));
+      BSE_TRY(run_gemm<float>(ar, t, s));
+      BSE_TRY(run_op(ar, n3, group_finalize, G_COLNORM_C, 0, s));
+      BSE_TRY(run_op(ar, la, group_finalize, G_LAMBDA, 0, s));
+      BSE_TRY(run_gemm<float>(ar, v1, s));
+      BSE_TRY(run_op(ar, cv, group_finalize, G_C64, 0, s));
+      tm.mark();
+
+      // ---- FP64 refinement, problem by problem until its correction is small
+      const int steps = o.refine_steps > 0 ? o.refine_steps : 8;
+      for (int it = 0; it < steps; ++it) {
+        std::vector<Prob*> act;
+        for (Prob* pr : ok)
+          if (!pr->rdone) act.push_back(pr);
+        if (act.empty()) break;
+        BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
+        std::vector<GemmDesc> g00, g10, upd;
+        Grp<RitzArgs> rt;
+        Grp<BuildArgs> bd;
+        for (Prob* pr : act) {
+          const int nn = pr->n;
+          const long ld = pr->np;
+          const double2* M1 = pr->at<double2>(pr->p.off_m1);
+          const double2* M2 = pr->at<double2>(pr->p.off_m2);
+          double2* P1 = pr->at<double2>(pr->p.off_p1);
+          double2* P2 = pr->at<double2>(pr->p.off_p2);
+          double2* Ex = pr->at<double2>(pr->p.off_lc);
+          double2* Ey = pr->at<double2>(pr->p.off_wc);
+          double* ritz = pr->at<double>(pr->p.off_ritz);
+          auto nn_gemm = [&](const double2* a, int opA, const double2* b, int opB, double2* c) {
+            GemmDesc d;
+            d.M = nn; d.N = nn; d.K = nn;
+            d.A = a; d.lda = ld; d.opA = opA;
+            d.B = b; d.ldb = ld; d.opB = opB;
+            d.C = c; d.ldc = ld;
+            return d;
+          };
+          g00.push_back(nn_gemm(M2, 0, pr->x, 0, pr->q));   // M2 x
+          g00.push_back(nn_gemm(M1, 0, pr->y, 0, Ex));      // M1 y (Ex is free until k_build)
+          g10.push_back(nn_gemm(pr->x, 1, pr->y, 0, pr->f));  // F = x^H y
+          g10.push_back(nn_gemm(pr->x, 1, pr->q, 0, P2));     // P2 = x^H M2 x
+          g10.push_back(nn_gemm(pr->y, 1, Ex, 0, P1));        // P1 = y^H M1 y
+          rt.add({nn, pr->f, P1, P2, ld, ritz}, (nn + 255) / 256);
+          const int T = (nn + 63) / 64;
+          bd.add({nn, pr->f, P1, P2, ld, ritz, Ex, Ey, kRefineDelta, d_corr + pr->idx}, T * T);
+          upd.push_back(nn_gemm(pr->x, 0, Ex, 0, pr->q));     // x (I + E11 + E21)
+          upd.push_back(nn_gemm(pr->y, 0, Ey, 0, pr->f));     // y (I + E11 - E21)
+        }
+        BSE_TRY(run_gemm<double>(ar, g00, s));
+        BSE_TRY(run_gemm<double>(ar, g10, s));
+        BSE_TRY(run_op(ar, rt, group_refine, G_RITZ, 0, s));
+        BSE_TRY(run_op(ar, bd, group_refine, G_BUILD, 0, s));
+        BSE_TRY(run_gemm<double>(ar, upd, s));
+        std::vector<double> corr(batch, 0.0);
+        BSE_TRY(hipMemcpyAsync(corr.data(), d_corr, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+        BSE_TRY(hipStreamSynchronize(s));
+        for (Prob* pr : act) {
+          std::swap(pr->x, pr->q);
+          std::swap(pr->y, pr->f);
+          pr->rsteps += 1;
+          pr->rcorr = corr[pr->idx];
+          // the error left after a step is of the order of the square of its correction
+          if (pr->rcorr <= 1.0e-6) pr->rdone = 1;
+        }
+      }
+      // Rayleigh quotients, Sigma-normalising scales, sort, final setup
+      std::vector<GemmDesc> g00;
+      Grp<RqArgs> rq;
+      Grp<RankArgs> rk;
+      Grp<WriteLambdaArgs> wl;
+      Grp<AssembleArgs> as;
+      for (Prob* pr : ok) {
+        const int nn = pr->n;
+        const long ld = pr->np;
+        double2* P1 = pr->at<double2>(pr->p.off_p1);
+        double2* P2 = pr->at<double2>(pr->p.off_p2);
+        GemmDesc a;
+        a.M = nn; a.N = nn; a.K = nn;
+        a.A = pr->at<double2>(pr->p.off_m2); a.lda = ld;
+        a.B = pr->x; a.ldb = ld;
+        a.C = P2; a.ldc = ld;
+        g00.push_back(a);
+        GemmDesc b = a;
+        b.A = pr->at<double2>(pr->p.off_m1);
+        b.B = pr->y;
+        b.C = P1;
+        g00.push_back(b);
+        double* lamu = pr->at<double>(pr->p.off_lamu);
+        double* scl = pr->at<double>(pr->p.off_scl);
+        int* perm = pr->at<int>(pr->p.off_perm);
+        rq.add({nn, pr->x, pr->y, P2, P1, ld, lamu, scl}, nn);
+        rk.add({nn, lamu, perm, 0}, (nn + 255) / 256);
+        wl.add({nn, lamu, perm, pr->lambda, o.want_negative}, (nn + 255) / 256);
+        as.add({nn, pr->x, pr->y, ld, perm, scl, pr->X, pr->ldx, o.want_negative}, cols_blocks(nn, nn));
+      }
+      BSE_TRY(run_gemm<double>(ar, g00, s));
+      BSE_TRY(run_op(ar, rq, group_refine, G_RQ, 0, s));
+      BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
+      BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
+      BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
+      tm.mark();
+    } else {
+      Grp<ColnormArgs<double2>> n1, n2, n3;
+      Grp<ScaleArgs<double2>> sc;
+      Grp<LambdaArgs> la;
+      Grp<RankArgs> rk;
+      Grp<WriteLambdaArgs> wl;
+      Grp<AssembleArgs> as;
+      std::vector<GemmDesc> v2, t, v1;
+      for (Prob* pr : ok) {
+        const int np = pr->np;
+        double2* M1 = pr->at<double2>(pr->p.off_m1);
+        double2* M2 = pr->at<double2>(pr->p.off_m2);
+        double2* W = pr->at<double2>(pr->p.off_w);
+        double2* Y = pr->at<double2>(pr->p.off_y);
+        double* sigma = pr->at<double>(pr->p.off_sigma);
+        double* bnorm = pr->at<double>(pr->p.off_bnorm);
+        double* anorm = pr->at<double>(pr->p.off_anorm);
+        double* invlam = pr->at<double>(pr->p.off_invlam);
+        double* scl = pr->at<double>(pr->p.off_scl);
+        double* lamu = pr->at<double>(pr->p.off_lamu);
+        int* perm = pr->at<int>(pr->p.off_perm);
+        n1.add({W, np, np, sigma}, np);
+        sc.add({pr->n, np, W, np, sigma}, cols_blocks(np, np));
+        n2.add({W, np, np, bnorm}, np);
+        v2.push_back(tri_gemm(np, np, M2, 0, W, 0, 0, Y));  // V2 = L2 Ws
+        t.push_back(tri_gemm(np, np, M1, 1, Y, 0, 0, W));   // T = L1^H V2
+        n3.add({W, np, np, anorm}, np);
+        la.add({pr->n, np, anorm, bnorm, lamu, invlam, scl}, (np + 255) / 256);
+        rk.add({pr->n, lamu, perm, 0}, (pr->n + 255) / 256);
+        wl.add({pr->n, lamu, perm, pr->lambda, o.want_negative}, (pr->n + 255) / 256);
+        GemmDesc v = tri_gemm(np, np, M1, 0, W, 0, 0, M2);  // V1 = L1 T Lambda^-1
+        v.colscale = invlam;
+        v1.push_back(v);
+        as.add({pr->n, M2, Y, np, perm, scl, pr->X, pr->ldx, o.want_negative}, cols_blocks(pr->n, pr->n));
+      }
+      BSE_TRY(run_op(ar, n1, group_finalize, G_COLNORM_Z, 0, s));
+      BSE_TRY(run_op(ar, sc, group_finalize, G_SCALE_Z, 0, s));
+      BSE_TRY(run_op(ar, n2, group_finalize, G_COLNORM_Z, 0, s));
+      tm.mark();
+      BSE_TRY(run_gemm<double>(ar, v2, s));
+      BSE_TRY(run_gemm<double>(ar, t, s));
+      BSE_TRY(run_op(ar, n3, group_finalize, G_COLNORM_Z, 0, s));
+      BSE_TRY(run_op(ar, la, group_finalize, G_LAMBDA, 0, s));
+      BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
+      BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
+      BSE_TRY(run_gemm<double>(ar, v1, s));
+      BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
+      tm.mark();
+    }
+  }
+  BSE_TRY(hipStreamSynchronize(s));
+
+  // ---- statuses and statistics
+  int first = 0;
+  std::vector<int> status(batch, 0);
+  for (const Prob& pr : probs) {
+    int st = pr.status;
+    const JacState& js = states[pr.idx];
+    if (st == 0 && !js.converged) st = 2 * pr.n + 1;
+    if (st == 0 && mixed && !(pr.rcorr <= 1.0e-4)) st = 2 * pr.n + 2;
+    status[pr.idx] = st;
+    if (info) {
+      bse_info_t* inf = &info[pr.idx];
+      inf->status = st;
+      inf->fail_index = pr.status > 0 ? (pr.status > pr.n ? pr.status - pr.n : pr.status) : 0;
+      inf->sweeps = js.sweeps;
+      inf->rotations = js.rotations;
+      inf->max_off = js.last_off;
+      inf->pair_checks = (int)js.pair_checks;
+      inf->inner_rotations = js.inner_rotations;
+      inf->refine_delta = pr.rcorr;
+      inf->refine_steps_done = pr.rsteps;
+    }
+  }
+  for (int i = 0; i < batch; ++i)
+    if (status[i] != 0) { first = status[i]; break; }
+  if (info && want_timing) {
+    bse_info_t whole;
+    memset(&whole, 0, sizeof(whole));
+    tm.fill(&whole, slots);
+    for (int i = 0; i < batch; ++i)
+      for (int k = 0; k < 8; ++k) info[i].ms_phase[k] = whole.ms_phase[k];
+  }
+  return first;
+}
+
+}  // namespace bse

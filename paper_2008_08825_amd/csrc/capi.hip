@@ -23,143 +23,11 @@
 #include "../../include/bse.h"
 #include "common.hpp"
 #include "internal.hpp"
+#include "plan.hpp"
 
 using namespace bse;
 
 namespace {
-
-constexpr int kErrHip = -1000;
-
-inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-inline int pad64(int n) { return ((n + 63) / 64) * 64; }
-
-// Workspace layout.  U = np^2 complex128 (16 np^2 bytes).
-//   FP64:  M1, M2, W, Y (4 U)
-//   mixed: M1, M2 (full Hermitian FP64), X1, X2 (FP64 pair), Q, F, P1, P2
-//          (refinement), L1c|L2c (complex64, 1 U), Wc|Yc (complex64, 1 U):
-//          10 U; the complex64 regions hold Ex, Ey during the refinement.
-struct Plan {
-  int n = 0, np = 0, mixed = 0;
-  size_t off_m1 = 0, off_m2 = 0, off_w = 0, off_y = 0;
-  size_t off_x1 = 0, off_x2 = 0, off_q = 0, off_f = 0, off_p1 = 0, off_p2 = 0;
-  size_t off_z = 0, off_inv = 0;
-  int alg2 = 0;
-  size_t off_lc = 0, off_wc = 0;
-  size_t off_linv = 0, off_sigma = 0, off_perm = 0, off_invlam = 0, off_status = 0;
-  size_t off_bnorm = 0, off_anorm = 0, off_lamu = 0, off_scl = 0, off_ritz = 0, off_small = 0;
-  size_t off_jac = 0;
-  size_t total = 0;
-};
-
-bool opts_valid(const bse_opts_t& o) {
-  if (o.route != BSE_ROUTE_SVD && o.route != BSE_ROUTE_EIG) return false;
-  if (o.precision != BSE_PREC_FP64 && o.precision != BSE_PREC_MIXED) return false;
-  if (o.max_sweeps < 0 || o.refine_steps < 0 || o.refine_steps > 8 || !(o.jacobi_tol >= 0.0))
-    return false;
-  if (o.route == BSE_ROUTE_EIG && o.precision != BSE_PREC_FP64) return false;  // Alg. 2: FP64 only
-  if (!(o.uplo == 0 || o.uplo == 'L' || o.uplo == 'U' || o.uplo == 'l' || o.uplo == 'u')) return false;
-  for (int i = 0; i < 6; ++i)
-    if (o.reserved[i] != 0) return false;
-  return true;
-}
-
-Plan make_plan(int n, const bse_opts_t& o) {
-  Plan p;
-  p.n = n;
-  p.np = pad64(n > 0 ? n : 1);
-  p.mixed = o.precision == BSE_PREC_MIXED;
-  p.alg2 = o.route == BSE_ROUTE_EIG;
-  const size_t U = (size_t)p.np * p.np * sizeof(double2);
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = off;
-    off = align256(off + bytes);
-    return at;
-  };
-  p.off_m1 = take(U);
-  p.off_m2 = take(U);
-  if (p.alg2) {
-    p.off_w = take(U);
-    p.off_y = take(U);
-    p.off_z = take(U);
-    p.off_inv = take((size_t)p.np * 64 * sizeof(double2));
-  } else if (!p.mixed) {
-    p.off_w = take(U);
-    p.off_y = take(U);
-  } else {
-    p.off_x1 = take(U);
-    p.off_x2 = take(U);
-    p.off_q = take(U);
-    p.off_f = take(U);
-    p.off_p1 = take(U);
-    p.off_p2 = take(U);
-    p.off_lc = take(U);  // L1c | L2c, then Ex
-    p.off_wc = take(U);  // Wc | Yc, then Ey
-  }
-  p.off_linv = take(64 * 64 * sizeof(double2));
-  p.off_sigma = take((size_t)p.np * sizeof(double));
-  p.off_perm = take((size_t)p.np * sizeof(int));
-  p.off_invlam = take((size_t)p.np * sizeof(double));
-  p.off_bnorm = take((size_t)p.np * sizeof(double));
-  p.off_anorm = take((size_t)p.np * sizeof(double));
-  p.off_lamu = take((size_t)p.np * sizeof(double));
-  p.off_scl = take((size_t)p.np * sizeof(double));
-  p.off_ritz = take((size_t)p.np * sizeof(double));
-  p.off_small = take(256);
-  p.off_status = take(64);
-  p.off_jac = take(jacobi_work_bytes(p.np, p.mixed ? sizeof(float) : sizeof(double)));
-  p.total = off + 256;  // slack for aligning the caller's base pointer
-  return p;
-}
-
-inline int hip_status(hipError_t e) { return kErrHip - (int)e; }
-
-#define BSE_TRY(expr)                            \
-  do {                                           \
-    hipError_t e_ = (expr);                      \
-    if (e_ != hipSuccess) return hip_status(e_); \
-  } while (0)
-
-struct Timer {
-  bool on;
-  hipStream_t s;
-  hipEvent_t ev[9];
-  int k = 0;
-  Timer(bool enable, hipStream_t st) : on(enable), s(st) {
-    if (on)
-      for (int i = 0; i < 9; ++i) (void)hipEventCreate(&ev[i]);
-  }
-  void mark() {
-    if (on && k < 9) (void)hipEventRecord(ev[k++], s);
-  }
-  // phase i of ms_phase = time between marks i and i + 1 (marks may be skipped: -1)
-  void fill(bse_info_t* info, const int* slot) {
-    if (!on || !info) return;
-    (void)hipEventSynchronize(ev[k - 1]);
-    for (int i = 0; i + 1 < k; ++i) {
-      float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
-      if (slot[i] >= 0 && slot[i] < 7) info->ms_phase[slot[i]] += ms;
-    }
-    float tot = 0.f;
-    (void)hipEventElapsedTime(&tot, ev[0], ev[k - 1]);
-    info->ms_phase[7] = tot;
-  }
-  ~Timer() {
-    if (on)
-      for (int i = 0; i < 9; ++i) (void)hipEventDestroy(ev[i]);
-  }
-};
-
-GemmDesc tri_gemm(int np, long ld, const void* A, int opA, const void* B, int opB, int triB,
-                  void* C) {
-  GemmDesc g;
-  g.M = np; g.N = np; g.K = np;
-  g.A = A; g.lda = ld; g.opA = opA; g.triA = 1;
-  g.B = B; g.ldb = ld; g.opB = opB; g.triB = triB;
-  g.C = C; g.ldc = ld;
-  return g;
-}
 
 void fill_info(bse_info_t* info, int ret, const JacobiResult& jr) {
   if (!info) return;
@@ -219,7 +87,7 @@ int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* la
   double* scl = reinterpret_cast<double*>(base + p.off_scl);
   int* status = reinterpret_cast<int*>(base + p.off_status);
   JacobiWork jw;
-  jacobi_carve(np, sizeof(double), base + p.off_jac, jw);
+  jacobi_carve(np, sizeof(double), base + p.off_jac, jw, p.kc, p.rrows);
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
   const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (double)(n > 64 ? n : 64) * 2.220446049250313e-16;
@@ -287,7 +155,7 @@ int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* la
   double* fy = reinterpret_cast<double*>(base + p.off_bnorm);
   int* status = reinterpret_cast<int*>(base + p.off_status);
   JacobiWork jw;
-  jacobi_carve(np, sizeof(double), base + p.off_jac, jw);
+  jacobi_carve(np, sizeof(double), base + p.off_jac, jw, p.kc, p.rrows);
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
   const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (double)(n > 64 ? n : 64) * 2.220446049250313e-16;
@@ -361,7 +229,7 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   double* scl = reinterpret_cast<double*>(base + p.off_scl);
   int* status = reinterpret_cast<int*>(base + p.off_status);
   JacobiWork jw;
-  jacobi_carve(np, sizeof(float), base + p.off_jac, jw);
+  jacobi_carve(np, sizeof(float), base + p.off_jac, jw, p.kc, p.rrows);
   RefineWork rw;
   rw.Q = reinterpret_cast<double2*>(base + p.off_q);
   rw.F = reinterpret_cast<double2*>(base + p.off_f);
@@ -489,13 +357,18 @@ int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb, double* 
 
 size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* opts) {
   if (batch < 0 || (batch > 0 && !n)) return 0;
+  bse_opts_t o;
+  bse_default_opts(&o);
+  if (opts) o = *opts;
+  if (!opts_valid(o)) return 0;
   size_t mx = 0;
   for (int i = 0; i < batch; ++i) {
-    const size_t b = bse_workspace_bytes(n[i], opts);
-    if (n[i] < 0 || (n[i] > 0 && b == 0)) return 0;
+    if (n[i] < 0 || n[i] > 46000) return 0;
+    const size_t b = bse_workspace_bytes(n[i], &o);
     if (b > mx) mx = b;
   }
-  return mx;
+  if (o.route == BSE_ROUTE_EIG) return mx;  // Alg. 2: problems one after another
+  return batched_workspace(batch, n, o);
 }
 
 int bse_solve_batched(int batch, const int* n, const void* const* A, const int* lda,
@@ -508,15 +381,38 @@ int bse_solve_batched(int batch, const int* n, const void* const* A, const int* 
   if (batch > 0 && (!B || !ldb)) return -5;
   if (batch > 0 && !lambda) return -7;
   if (batch > 0 && (!X || !ldx)) return -8;
-  const size_t need = bse_batched_workspace_bytes(batch, n, opts);
-  if (batch > 0 && need == 0) return -2;
+  bse_opts_t o;
+  bse_default_opts(&o);
+  if (opts) o = *opts;
+  if (!opts_valid(o)) return -12;
+  for (int i = 0; i < batch; ++i) {
+    if (n[i] < 0 || n[i] > 46000) return -2;
+    if (n[i] == 0) continue;
+    if (!A[i] || lda[i] < n[i]) return -3;
+    if (!B[i] || ldb[i] < n[i]) return -5;
+    if (!lambda[i]) return -7;
+    if (!X[i] || ldx[i] < 2 * n[i]) return -8;
+  }
+  if (batch == 0) return 0;
+  const size_t need = bse_batched_workspace_bytes(batch, n, &o);
+  if (need == 0) return -2;
   if (batch > 0 && !work) return -10;
   if (work_bytes < need) return -11;
+  const int want_timing = info ? info[0].timing : 0;
+  if (info)
+    for (int i = 0; i < batch; ++i) {
+      memset(&info[i], 0, sizeof(info[i]));
+      info[i].timing = want_timing;
+    }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (o.route != BSE_ROUTE_EIG)
+    return solve_batched_grouped(batch, n, A, lda, B, ldb, lambda, X, ldx, work, o, info,
+                                 want_timing, s);
   int first = 0;
   for (int i = 0; i < batch; ++i) {
     bse_info_t* inf = info ? &info[i] : nullptr;
     const int st = bse_solve_h1(n[i], A[i], lda[i], B[i], ldb[i], lambda[i], X[i], ldx[i], work,
-                                work_bytes, opts, inf, stream);
+                                work_bytes, &o, inf, stream);
     if (st <= kErrHip) return st;
     if (st != 0 && first == 0) first = st;
   }

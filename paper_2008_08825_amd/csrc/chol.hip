@@ -21,13 +21,22 @@ constexpr int NB = 64;
 // One 64 x 64 tile of M1/M2 per workgroup.  Reading the upper triangle of a
 // column-major matrix means reading it transposed, so the tile goes through
 // LDS to keep global reads coalesced.
-__global__ __launch_bounds__(256) void k_form_m12(int n, int np, const double2* __restrict__ A,
-                                                  long lda, const double2* __restrict__ B, long ldb,
-                                                  int upper, double2* __restrict__ M1,
-                                                  double2* __restrict__ M2, long ldm) {
+struct FormOp {
+  static constexpr int NT = 256;
+  typedef FormArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux);
+};
+
+BSE_DEV void FormOp::run(const FormArgs& a, int bx, int) {
+  const int n = a.n, np = a.np, upper = a.upper;
+  const double2* __restrict__ A = a.A;
+  const double2* __restrict__ B = a.B;
+  const long lda = a.lda, ldb = a.ldb, ldm = a.ldm;
+  double2* __restrict__ M1 = a.M1;
+  double2* __restrict__ M2 = a.M2;
   __shared__ double2 tile[64][65];
   const int T = np / 64;
-  const int tm = blockIdx.x % T, tn = blockIdx.x / T;
+  const int tm = bx % T, tn = bx / T;
   const int m0 = tm * 64, n0 = tn * 64;
   const int tid = threadIdx.x;
   double2 va[16], vb[16];
@@ -90,9 +99,19 @@ __global__ __launch_bounds__(256) void k_form_m12(int n, int np, const double2* 
 // C2 is the storage type (double2, or float2 in the mixed form); the block is
 // factored in FP64 either way.
 template <typename C2>
-__global__ __launch_bounds__(256) void k_potf2_inv(C2* M, long ld, int j0,
-                                                   C2* __restrict__ linv, int* status,
-                                                   int base, int n_real) {
+struct Potf2Op {
+  static constexpr int NT = 256;
+  typedef Potf2Args<C2> Args;
+  static BSE_DEV void run(const Args& a, int bx, int j0);
+};
+
+template <typename C2>
+BSE_DEV void Potf2Op<C2>::run(const Potf2Args<C2>& a, int, int j0) {
+  C2* M = a.M;
+  const long ld = a.ld;
+  C2* __restrict__ linv = a.linv;
+  int* status = a.status;
+  const int base = a.base, n_real = a.n_real;
   __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
   __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
   __shared__ int failed;
@@ -211,10 +230,19 @@ __global__ __launch_bounds__(256) void k_tri_inv_blocks(const double2* __restric
 }
 
 // Upper triangle of a square np x np matrix from its lower one: M[i][j] = conj(M[j][i]), i < j.
-__global__ __launch_bounds__(256) void k_mirror_upper(int np, double2* M, long ld) {
+struct MirrorOp {
+  static constexpr int NT = 256;
+  typedef MirrorArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux);
+};
+
+BSE_DEV void MirrorOp::run(const MirrorArgs& a, int bx, int) {
+  const int np = a.np;
+  double2* M = a.M;
+  const long ld = a.ld;
   __shared__ double2 tile[64][65];
   const int T = np / 64;
-  const int tm = blockIdx.x % T, tn = blockIdx.x / T;
+  const int tm = bx % T, tn = bx / T;
   if (tn < tm) return;  // target tile (tm, tn) on or above the diagonal
   const int m0 = tm * 64, n0 = tn * 64;
   const int tid = threadIdx.x;
@@ -230,36 +258,42 @@ __global__ __launch_bounds__(256) void k_mirror_upper(int np, double2* M, long l
   }
 }
 
-// complex64 copy of the lower triangle (strict upper part zero).
-__global__ __launch_bounds__(256) void k_lower_to_c64(int np, const double2* __restrict__ M, long ld,
-                                                      float2* __restrict__ Mc) {
-  const int j = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= np) return;
-  float2 v = make_float2(0.f, 0.f);
-  if (i >= j) { const double2 x = M[i + (long)j * ld]; v = make_float2((float)x.x, (float)x.y); }
-  Mc[i + (long)j * ld] = v;
+// complex64 copy of the lower triangle (strict upper part zero), one 64 x 64 tile per workgroup.
+struct ToC64Op {
+  static constexpr int NT = 256;
+  typedef ToC64Args Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux);
+};
+
+BSE_DEV void ToC64Op::run(const ToC64Args& a, int bx, int) {
+  const int T = a.np / 64;
+  const int m0 = (bx % T) * 64, n0 = (bx / T) * 64;
+  const double2* __restrict__ M = a.M;
+  float2* __restrict__ Mc = a.Mc;
+  for (int q = 0; q < 16; ++q) {
+    const int i = m0 + (threadIdx.x & 63), j = n0 + (threadIdx.x >> 6) + 4 * q;
+    float2 v = make_float2(0.f, 0.f);
+    if (i >= j) { const double2 x = M[i + (long)j * a.ld]; v = make_float2((float)x.x, (float)x.y); }
+    Mc[i + (long)j * a.ld] = v;
+  }
 }
 
 }  // namespace
 
 hipError_t form_m12(int n, int np, const double2* A, long lda, const double2* B, long ldb,
                     int upper, double2* M1, double2* M2, long ldm, hipStream_t s) {
-  const int T = np / 64;
-  k_form_m12<<<T * T, 256, 0, s>>>(n, np, A, lda, B, ldb, upper, M1, M2, ldm);
-  return hipGetLastError();
+  const FormArgs a = {n, np, A, lda, B, ldb, upper, M1, M2, ldm};
+  return launch_one<FormOp>(a, tiles64(np), 0, s);
 }
 
 hipError_t mirror_upper_z(int np, double2* M, long ld, hipStream_t s) {
-  const int T = np / 64;
-  k_mirror_upper<<<T * T, 256, 0, s>>>(np, M, ld);
-  return hipGetLastError();
+  const MirrorArgs a = {np, M, ld};
+  return launch_one<MirrorOp>(a, tiles64(np), 0, s);
 }
 
 hipError_t lower_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream_t s) {
-  dim3 g((np + 255) / 256, np);
-  k_lower_to_c64<<<g, 256, 0, s>>>(np, M, ld, Mc);
-  return hipGetLastError();
+  const ToC64Args a = {np, M, ld, Mc};
+  return launch_one<ToC64Op>(a, tiles64(np), 0, s);
 }
 
 template <typename C2>
@@ -267,8 +301,8 @@ static hipError_t cholesky_run(int np, int n_real, C2* M, long ld, C2* linv, int
                                int base, hipStream_t s) {
   hipError_t (*gemm)(const GemmDesc&, hipStream_t) = sizeof(C2) == 16 ? gemm_z : gemm_c;
   for (int j0 = 0; j0 < np; j0 += NB) {
-    k_potf2_inv<C2><<<1, 256, 0, s>>>(M, ld, j0, linv, status, base, n_real);
-    hipError_t e = hipGetLastError();
+    const Potf2Args<C2> pa = {M, ld, linv, status, base, n_real};
+    hipError_t e = launch_one<Potf2Op<C2>>(pa, 1, j0, s);
     if (e != hipSuccess) return e;
     const int rows = np - j0 - NB;
     if (rows <= 0) break;
@@ -327,6 +361,18 @@ hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status,
                       int base, hipStream_t s) {
   return cholesky_run<float2>(np, n_real, M, ld, linv, status, base, s);
+}
+
+hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux,
+                      hipStream_t s) {
+  switch (op) {
+    case G_FORM: return launch_grp<FormOp>(table, map, blocks, aux, s);
+    case G_MIRROR: return launch_grp<MirrorOp>(table, map, blocks, aux, s);
+    case G_TOC64: return launch_grp<ToC64Op>(table, map, blocks, aux, s);
+    case G_POTF2_Z: return launch_grp<Potf2Op<double2>>(table, map, blocks, aux, s);
+    case G_POTF2_C: return launch_grp<Potf2Op<float2>>(table, map, blocks, aux, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace bse

@@ -81,3 +81,39 @@ BSE_DEV void atomic_max_nonneg(double* addr, double v) {
   atomicMax(reinterpret_cast<unsigned long long*>(addr),
             static_cast<unsigned long long>(__double_as_longlong(v)));
 }
+
+// ---------------------------------------------------------------- launches
+// Every kernel is an "op": a struct with the workgroup size NT, an argument
+// struct Args and a device body run(args, wg, aux) that does the work of
+// workgroup wg of one problem (aux carries a per-launch scalar such as the
+// Jacobi round or the Cholesky panel).  An op launches two ways:
+//   single:  k_one<Op><<<blocks>>>(args, aux), wg = blockIdx.x;
+//   grouped: k_grp<Op><<<total>>>(table, map, aux), where table holds one
+//            Args per problem and map[b] = (table row, wg) for every flat
+//            workgroup b of the launch, so one launch covers many problems
+//            of different sizes with no idle workgroups.
+template <typename Op>
+__global__ __launch_bounds__(Op::NT) void k_one(typename Op::Args a, int aux) {
+  Op::run(a, (int)blockIdx.x, aux);
+}
+
+template <typename Op>
+__global__ __launch_bounds__(Op::NT) void k_grp(const typename Op::Args* __restrict__ table,
+                                                const int2* __restrict__ map, int aux) {
+  const int2 m = map[blockIdx.x];
+  Op::run(table[m.x], m.y, aux);
+}
+
+template <typename Op>
+hipError_t launch_one(const typename Op::Args& a, int blocks, int aux, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  k_one<Op><<<blocks, Op::NT, 0, s>>>(a, aux);
+  return hipGetLastError();
+}
+
+template <typename Op>
+hipError_t launch_grp(const void* table, const int2* map, int blocks, int aux, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  k_grp<Op><<<blocks, Op::NT, 0, s>>>(static_cast<const typename Op::Args*>(table), map, aux);
+  return hipGetLastError();
+}

@@ -23,105 +23,124 @@ namespace bse {
 namespace {
 
 template <typename C2>
-__global__ __launch_bounds__(256) void k_colnorm(const C2* __restrict__ W, long ld, int np,
-                                                 double* __restrict__ sigma) {
-  __shared__ double red[256];
-  const int j = blockIdx.x, tid = threadIdx.x;
-  const C2* col = W + (long)j * ld;
-  double s = 0.0;
-  for (int i = tid; i < np; i += 256) {
-    const double a = col[i].x, b = col[i].y;
-    s += a * a + b * b;
-  }
-  red[tid] = s;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (tid < h) red[tid] += red[tid + h];
+struct ColnormOp {
+  static constexpr int NT = 256;
+  typedef ColnormArgs<C2> Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    __shared__ double red[256];
+    const int j = bx, tid = threadIdx.x;
+    const C2* col = a.W + (long)j * a.ld;
+    double s = 0.0;
+    for (int i = tid; i < a.np; i += 256) {
+      const double x = col[i].x, y = col[i].y;
+      s += x * x + y * y;
+    }
+    red[tid] = s;
     __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+      if (tid < h) red[tid] += red[tid + h];
+      __syncthreads();
+    }
+    if (tid == 0) a.out[j] = sqrt(red[0]);
   }
-  if (tid == 0) sigma[j] = sqrt(red[0]);
-}
+};
 
 // rank_j = #{i : key_i < key_j or (key_i == key_j and i < j)}; perm[rank_j] = j,
 // key = sigma (ascending) or -sigma (descending).
-__global__ __launch_bounds__(256) void k_rank(int n, const double* __restrict__ sigma,
-                                              int* __restrict__ perm, int desc) {
-  __shared__ double sv[256];
-  const double sg = desc ? -1.0 : 1.0;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const double s = j < n ? sg * sigma[j] : 0.0;
-  int rank = 0;
-  for (int base = 0; base < n; base += 256) {
-    const int i = base + threadIdx.x;
-    sv[threadIdx.x] = i < n ? sg * sigma[i] : 0.0;
-    __syncthreads();
-    const int lim = min(256, n - base);
-    for (int q = 0; q < lim; ++q) {
-      const double v = sv[q];
-      rank += (v < s) || (v == s && base + q < j);
+struct RankOp {
+  static constexpr int NT = 256;
+  typedef RankArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    __shared__ double sv[256];
+    const int n = a.n;
+    const double sg = a.desc ? -1.0 : 1.0;
+    const int j = bx * 256 + threadIdx.x;
+    const double s = j < n ? sg * a.key[j] : 0.0;
+    int rank = 0;
+    for (int base = 0; base < n; base += 256) {
+      const int i = base + threadIdx.x;
+      sv[threadIdx.x] = i < n ? sg * a.key[i] : 0.0;
+      __syncthreads();
+      const int lim = min(256, n - base);
+      for (int q = 0; q < lim; ++q) {
+        const double v = sv[q];
+        rank += (v < s) || (v == s && base + q < j);
+      }
+      __syncthreads();
     }
-    __syncthreads();
+    if (j < n) a.perm[rank] = j;
   }
-  if (j < n) perm[rank] = j;
-}
+};
 
+// W[:, k] *= sigma_k^-3/2 for k < n, zero for k >= n; work group = (column, 256 rows).
 template <typename C2>
-__global__ __launch_bounds__(256) void k_scale_cols(int n, int np, C2* __restrict__ W, long ld,
-                                                    const double* __restrict__ sigma) {
-  const int k = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= np) return;
-  double f = 0.0;
-  if (k < n) {
-    const double sg = sigma[k];
-    f = sg > 0.0 ? 1.0 / (sg * sqrt(sg)) : 0.0;
+struct ScaleOp {
+  static constexpr int NT = 256;
+  typedef ScaleArgs<C2> Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    const int gx = (a.np + 255) / 256;
+    const int k = bx / gx;
+    const int i = (bx % gx) * 256 + threadIdx.x;
+    if (i >= a.np) return;
+    double f = 0.0;
+    if (k < a.n) {
+      const double sg = a.sigma[k];
+      f = sg > 0.0 ? 1.0 / (sg * sqrt(sg)) : 0.0;
+    }
+    C2 v = a.W[i + (long)k * a.ld];
+    v.x = v.x * f;
+    v.y = v.y * f;
+    a.W[i + (long)k * a.ld] = v;
   }
-  C2 v = W[i + (long)k * ld];
-  v.x = v.x * f;
-  v.y = v.y * f;
-  W[i + (long)k * ld] = v;
-}
+};
 
-__global__ __launch_bounds__(256) void k_c64_to_c128(int np, const float2* __restrict__ S, long lds,
-                                                     double2* __restrict__ D, long ldd,
-                                                     const double* __restrict__ colscale) {
-  const int j = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= np) return;
-  const float2 v = S[i + (long)j * lds];
-  const double f = colscale ? colscale[j] : 1.0;
-  D[i + (long)j * ldd] = make_double2(f * v.x, f * v.y);
-}
-
-__global__ __launch_bounds__(256) void k_lambda(int n, int np, const double* __restrict__ anorm,
-                                                const double* __restrict__ bnorm,
-                                                double* __restrict__ lam, double* __restrict__ invlam,
-                                                double* __restrict__ scl) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= np) return;
-  if (k < n) {
-    const double a = anorm[k], b = bnorm[k];
-    const double l = a / b;
-    lam[k] = l;
-    invlam[k] = 1.0 / l;
-    scl[k] = 1.0 / sqrt(a * b);
-  } else {
-    lam[k] = 0.0;
-    invlam[k] = 0.0;
-    scl[k] = 0.0;
+struct C64Op {
+  static constexpr int NT = 256;
+  typedef C64Args Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    const int gx = (a.np + 255) / 256;
+    const int j = bx / gx;
+    const int i = (bx % gx) * 256 + threadIdx.x;
+    if (i >= a.np) return;
+    const float2 v = a.S[i + (long)j * a.lds];
+    const double f = a.colscale ? a.colscale[j] : 1.0;
+    a.D[i + (long)j * a.ldd] = make_double2(f * v.x, f * v.y);
   }
-}
+};
 
-__global__ __launch_bounds__(256) void k_write_lambda(int n, const double* __restrict__ lam,
-                                                      const int* __restrict__ perm,
-                                                      double* __restrict__ lambda, int want_negative) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
-  int j = perm[r];
-  if (j < 0 || j >= n) j = r;  // only if a value was NaN (ranks then collide)
-  lambda[r] = lam[j];
-  if (want_negative) lambda[n + r] = -lam[j];
-}
+struct LambdaOp {
+  static constexpr int NT = 256;
+  typedef LambdaArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    const int k = bx * 256 + threadIdx.x;
+    if (k >= a.np) return;
+    if (k < a.n) {
+      const double x = a.anorm[k], y = a.bnorm[k];
+      const double l = x / y;
+      a.lam[k] = l;
+      a.invlam[k] = 1.0 / l;
+      a.scl[k] = 1.0 / sqrt(x * y);
+    } else {
+      a.lam[k] = 0.0;
+      a.invlam[k] = 0.0;
+      a.scl[k] = 0.0;
+    }
+  }
+};
+
+struct WriteLambdaOp {
+  static constexpr int NT = 256;
+  typedef WriteLambdaArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    const int n = a.n;
+    const int r = bx * 256 + threadIdx.x;
+    if (r >= n) return;
+    int j = a.perm[r];
+    if (j < 0 || j >= n) j = r;  // only if a value was NaN (ranks then collide)
+    a.lambda[r] = a.lam[j];
+    if (a.want_negative) a.lambda[n + r] = -a.lam[j];
+  }
+};
 
 __global__ __launch_bounds__(256) void k_gather_scale(int n, int np, const double2* __restrict__ W,
                                                       long ld, const int* __restrict__ perm,
@@ -154,49 +173,58 @@ __global__ __launch_bounds__(256) void k_alg2_scales(int n, const double* __rest
   fx[r] = sqrt(lk) / dk;          // column of V_M Lambda^1/2
 }
 
-__global__ __launch_bounds__(256) void k_assemble(int n, const double2* __restrict__ V1,
-                                                  const double2* __restrict__ V2, long ldv,
-                                                  const int* __restrict__ perm,
-                                                  const double* __restrict__ scl,
-                                                  double2* __restrict__ X, long ldx, int want_negative) {
-  const int r = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  int k = perm ? perm[r] : r;
-  if (k < 0 || k >= n) k = r;
-  const double sc = scl ? 0.5 * scl[k] : 0.5;
-  const double2 a = V1[i + (long)k * ldv];
-  const double2 b = V2[i + (long)k * ldv];
-  const double2 top = cscale(cadd(a, b), sc);
-  const double2 bot = cscale(csub(b, a), sc);
-  X[i + (long)r * ldx] = top;
-  X[n + i + (long)r * ldx] = bot;
-  if (want_negative) {
-    X[i + (long)(n + r) * ldx] = bot;
-    X[n + i + (long)(n + r) * ldx] = top;
+// X[:, r] = s_k [(V1_k + V2_k)/2; (V2_k - V1_k)/2], k = perm[r]; work group = (column r, 256 rows).
+struct AssembleOp {
+  static constexpr int NT = 256;
+  typedef AssembleArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    const int n = a.n;
+    const int gx = (n + 255) / 256;
+    const int r = bx / gx;
+    const int i = (bx % gx) * 256 + threadIdx.x;
+    if (i >= n) return;
+    int k = a.perm ? a.perm[r] : r;
+    if (k < 0 || k >= n) k = r;
+    const double sc = a.scl ? 0.5 * a.scl[k] : 0.5;
+    const double2 x = a.V1[i + (long)k * a.ldv];
+    const double2 y = a.V2[i + (long)k * a.ldv];
+    const double2 top = cscale(cadd(x, y), sc);
+    const double2 bot = cscale(csub(y, x), sc);
+    double2* X = a.X;
+    const long ldx = a.ldx;
+    X[i + (long)r * ldx] = top;
+    X[n + i + (long)r * ldx] = bot;
+    if (a.want_negative) {
+      X[i + (long)(n + r) * ldx] = bot;
+      X[n + i + (long)(n + r) * ldx] = top;
+    }
   }
-}
+};
+
+inline int b256(int n) { return (n + 255) / 256; }
 
 }  // namespace
 
 hipError_t colnorm_z(int np, const double2* W, long ld, double* out, hipStream_t s) {
-  k_colnorm<double2><<<np, 256, 0, s>>>(W, ld, np, out);
-  return hipGetLastError();
+  const ColnormArgs<double2> a = {W, ld, np, out};
+  return launch_one<ColnormOp<double2>>(a, np, 0, s);
 }
 
 hipError_t colnorm_c(int np, const float2* W, long ld, double* out, hipStream_t s) {
-  k_colnorm<float2><<<np, 256, 0, s>>>(W, ld, np, out);
-  return hipGetLastError();
+  const ColnormArgs<float2> a = {W, ld, np, out};
+  return launch_one<ColnormOp<float2>>(a, np, 0, s);
 }
 
 template <typename C2>
 static hipError_t scale_singular_run(int n, int np, C2* W, long ld, double* sigma, double* bnorm,
                                      hipStream_t s) {
-  k_colnorm<C2><<<np, 256, 0, s>>>(W, ld, np, sigma);
-  dim3 g((np + 255) / 256, np);
-  k_scale_cols<C2><<<g, 256, 0, s>>>(n, np, W, ld, sigma);
-  k_colnorm<C2><<<np, 256, 0, s>>>(W, ld, np, bnorm);
-  return hipGetLastError();
+  const ColnormArgs<C2> c1 = {W, ld, np, sigma};
+  const ScaleArgs<C2> sc = {n, np, W, ld, sigma};
+  const ColnormArgs<C2> c2 = {W, ld, np, bnorm};
+  hipError_t e = launch_one<ColnormOp<C2>>(c1, np, 0, s);
+  if (e == hipSuccess) e = launch_one<ScaleOp<C2>>(sc, cols_blocks(np, np), 0, s);
+  if (e == hipSuccess) e = launch_one<ColnormOp<C2>>(c2, np, 0, s);
+  return e;
 }
 
 hipError_t scale_singular_cols_z(int n, int np, double2* W, long ld, double* sigma, double* bnorm,
@@ -211,32 +239,32 @@ hipError_t scale_singular_cols_c(int n, int np, float2* W, long ld, double* sigm
 
 hipError_t c64_to_c128(int np, const float2* S, long lds, double2* D, long ldd,
                        const double* colscale, hipStream_t s) {
-  dim3 g((np + 255) / 256, np);
-  k_c64_to_c128<<<g, 256, 0, s>>>(np, S, lds, D, ldd, colscale);
-  return hipGetLastError();
+  const C64Args a = {np, S, lds, D, ldd, colscale};
+  return launch_one<C64Op>(a, cols_blocks(np, np), 0, s);
 }
 
 hipError_t lambda_from_norms(int n, int np, const double* anorm, const double* bnorm, double* lam,
                              double* invlam, double* scl, hipStream_t s) {
-  k_lambda<<<(np + 255) / 256, 256, 0, s>>>(n, np, anorm, bnorm, lam, invlam, scl);
-  return hipGetLastError();
+  const LambdaArgs a = {n, np, anorm, bnorm, lam, invlam, scl};
+  return launch_one<LambdaOp>(a, b256(np), 0, s);
 }
 
 hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int want_negative,
                        hipStream_t s) {
-  k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
-  k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);
-  return hipGetLastError();
+  const RankArgs r = {n, lam, perm, 0};
+  const WriteLambdaArgs w = {n, lam, perm, lambda, want_negative};
+  hipError_t e = launch_one<RankOp>(r, b256(n), 0, s);
+  if (e == hipSuccess) e = launch_one<WriteLambdaOp>(w, b256(n), 0, s);
+  return e;
 }
 
 hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* bnorm, double* anorm,
                        double* lam, double* invlam, double* scl, int* perm, double* lambda,
                        int want_negative, hipStream_t s) {
-  k_colnorm<double2><<<np, 256, 0, s>>>(T, ld, np, anorm);
-  k_lambda<<<(np + 255) / 256, 256, 0, s>>>(n, np, anorm, bnorm, lam, invlam, scl);
-  k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
-  k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);
-  return hipGetLastError();
+  hipError_t e = colnorm_z(np, T, ld, anorm, s);
+  if (e == hipSuccess) e = lambda_from_norms(n, np, anorm, bnorm, lam, invlam, scl, s);
+  if (e == hipSuccess) e = sort_lambda(n, lam, perm, lambda, want_negative, s);
+  return e;
 }
 
 hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* perm,
@@ -249,17 +277,33 @@ hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* p
 hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double* lambda,
                          int want_negative, double* fx, double* fy, hipStream_t s) {
   k_alg2_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, d, lam);
-  k_rank<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, 0);
-  k_write_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, lam, perm, lambda, want_negative);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = sort_lambda(n, lam, perm, lambda, want_negative, s);
+  if (e != hipSuccess) return e;
   k_alg2_scales<<<(n + 255) / 256, 256, 0, s>>>(n, d, perm, fx, fy);
   return hipGetLastError();
 }
 
 hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
                       const double* scl, double2* X, long ldx, int want_negative, hipStream_t s) {
-  dim3 g((n + 255) / 256, n);
-  k_assemble<<<g, 256, 0, s>>>(n, V1, V2, ldv, perm, scl, X, ldx, want_negative);
-  return hipGetLastError();
+  const AssembleArgs a = {n, V1, V2, ldv, perm, scl, X, ldx, want_negative};
+  return launch_one<AssembleOp>(a, cols_blocks(n, n), 0, s);
+}
+
+hipError_t group_finalize(GroupOp op, const void* table, const int2* map, int blocks, int aux,
+                          hipStream_t s) {
+  switch (op) {
+    case G_COLNORM_Z: return launch_grp<ColnormOp<double2>>(table, map, blocks, aux, s);
+    case G_COLNORM_C: return launch_grp<ColnormOp<float2>>(table, map, blocks, aux, s);
+    case G_SCALE_Z: return launch_grp<ScaleOp<double2>>(table, map, blocks, aux, s);
+    case G_SCALE_C: return launch_grp<ScaleOp<float2>>(table, map, blocks, aux, s);
+    case G_LAMBDA: return launch_grp<LambdaOp>(table, map, blocks, aux, s);
+    case G_RANK: return launch_grp<RankOp>(table, map, blocks, aux, s);
+    case G_WRITE_LAMBDA: return launch_grp<WriteLambdaOp>(table, map, blocks, aux, s);
+    case G_C64: return launch_grp<C64Op>(table, map, blocks, aux, s);
+    case G_ASSEMBLE: return launch_grp<AssembleOp>(table, map, blocks, aux, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace bse

@@ -18,34 +18,27 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 4;
 
-template <typename T>
-struct GemmParams {
-  int M, N, K;
-  const typename cpx_t<T>::type* A; long lda; int triA;
-  const typename cpx_t<T>::type* B; long ldb; int triB;
-  typename cpx_t<T>::type* C; long ldc;
-  T ar, ai, br, bi;
-  const double* kscale;
-  const double* colscale;
-  int lowerC, mask;
-  long strideA, strideB, strideC;
-  int tilesM;
+template <typename T, int OPA, int OPB>
+struct GemmOp {
+  static constexpr int NT = 256;
+  typedef GemmArgs<T> Args;
+  static BSE_DEV void run(const Args& p, int bx, int aux);
 };
 
 template <typename T, int OPA, int OPB>
-__global__ __launch_bounds__(256) void k_gemm(GemmParams<T> p) {
+BSE_DEV void GemmOp<T, OPA, OPB>::run(const GemmArgs<T>& p, int bx, int) {
   typedef typename cpx_t<T>::type C2;
   typedef typename Mfma<T>::acc Acc;
   __shared__ T As[2][BK][BM + PAD];
   __shared__ T Bs[2][BK][BN + PAD];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tm = blockIdx.x % p.tilesM, tn = blockIdx.x / p.tilesM;
+  const int tm = bx % p.tilesM, tn = bx / p.tilesM;
   if (p.lowerC && tn > tm) return;
   const int m0 = tm * BM, n0 = tn * BN;
-  const C2* __restrict__ A = p.A + (long)blockIdx.y * p.strideA;
-  const C2* __restrict__ B = p.B + (long)blockIdx.y * p.strideB;
-  C2* C = p.C + (long)blockIdx.y * p.strideC;
+  const C2* __restrict__ A = p.A;
+  const C2* __restrict__ B = p.B;
+  C2* C = p.C;
 
   int kbeg = 0, kend = p.K;
   if (p.triA) {
@@ -174,32 +167,58 @@ __global__ __launch_bounds__(256) void k_gemm(GemmParams<T> p) {
 }
 
 template <typename T>
-hipError_t gemm_launch(const GemmDesc& d, hipStream_t s) {
-  if (d.M <= 0 || d.N <= 0) return hipSuccess;
-  GemmParams<T> p;
+GemmArgs<T> make_args(const GemmDesc& d) {
   typedef typename cpx_t<T>::type C2;
+  GemmArgs<T> p;
   p.M = d.M; p.N = d.N; p.K = d.K;
   p.A = static_cast<const C2*>(d.A); p.lda = d.lda; p.triA = d.triA;
   p.B = static_cast<const C2*>(d.B); p.ldb = d.ldb; p.triB = d.triB;
   p.C = static_cast<C2*>(d.C); p.ldc = d.ldc;
   p.ar = (T)d.alpha_re; p.ai = (T)d.alpha_im; p.br = (T)d.beta_re; p.bi = (T)d.beta_im;
-  p.kscale = static_cast<const double*>(d.kscale);
-  p.colscale = static_cast<const double*>(d.colscale);
+  p.kscale = d.kscale;
+  p.colscale = d.colscale;
   p.lowerC = d.lowerC; p.mask = d.mask;
-  p.strideA = d.strideA; p.strideB = d.strideB; p.strideC = d.strideC;
   p.tilesM = (d.M + BM - 1) / BM;
-  const int tilesN = (d.N + BN - 1) / BN;
-  dim3 grid(p.tilesM * tilesN, d.batch > 0 ? d.batch : 1);
-  if (d.opA == 0 && d.opB == 0) k_gemm<T, 0, 0><<<grid, 256, 0, s>>>(p);
-  else if (d.opA == 0 && d.opB == 1) k_gemm<T, 0, 1><<<grid, 256, 0, s>>>(p);
-  else if (d.opA == 1 && d.opB == 0) k_gemm<T, 1, 0><<<grid, 256, 0, s>>>(p);
-  else k_gemm<T, 1, 1><<<grid, 256, 0, s>>>(p);
-  return hipGetLastError();
+  p.tilesN = (d.N + BN - 1) / BN;
+  return p;
+}
+
+template <typename T>
+hipError_t gemm_launch(const GemmDesc& d, hipStream_t s) {
+  if (d.M <= 0 || d.N <= 0) return hipSuccess;
+  const GemmArgs<T> p = make_args<T>(d);
+  const int blocks = p.tilesM * p.tilesN;
+  if (d.opA == 0 && d.opB == 0) return launch_one<GemmOp<T, 0, 0>>(p, blocks, 0, s);
+  if (d.opA == 0 && d.opB == 1) return launch_one<GemmOp<T, 0, 1>>(p, blocks, 0, s);
+  if (d.opA == 1 && d.opB == 0) return launch_one<GemmOp<T, 1, 0>>(p, blocks, 0, s);
+  return launch_one<GemmOp<T, 1, 1>>(p, blocks, 0, s);
+}
+
+template <typename T>
+hipError_t gemm_group(int opA, int opB, const void* table, const int2* map, int blocks,
+                      hipStream_t s) {
+  if (opA == 0 && opB == 0) return launch_grp<GemmOp<T, 0, 0>>(table, map, blocks, 0, s);
+  if (opA == 0 && opB == 1) return launch_grp<GemmOp<T, 0, 1>>(table, map, blocks, 0, s);
+  if (opA == 1 && opB == 0) return launch_grp<GemmOp<T, 1, 0>>(table, map, blocks, 0, s);
+  return launch_grp<GemmOp<T, 1, 1>>(table, map, blocks, 0, s);
 }
 
 }  // namespace
 
 hipError_t gemm_z(const GemmDesc& d, hipStream_t s) { return gemm_launch<double>(d, s); }
 hipError_t gemm_c(const GemmDesc& d, hipStream_t s) { return gemm_launch<float>(d, s); }
+
+int gemm_tiles(const GemmDesc& d) {
+  if (d.M <= 0 || d.N <= 0) return 0;
+  return ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+}
+GemmArgs<double> gemm_args_z(const GemmDesc& d) { return make_args<double>(d); }
+GemmArgs<float> gemm_args_c(const GemmDesc& d) { return make_args<float>(d); }
+
+hipError_t group_gemm(int prec, int opA, int opB, const void* table, const int2* map, int blocks,
+                      hipStream_t s) {
+  return prec == 0 ? gemm_group<double>(opA, opB, table, map, blocks, s)
+                   : gemm_group<float>(opA, opB, table, map, blocks, s);
+}
 
 }  // namespace bse

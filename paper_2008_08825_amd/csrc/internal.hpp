@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include "common.hpp"
+
 namespace bse {
 
 // C[m, n] = alpha * sum_k opA(A)[m, k] * s[k] * opB(B)[k, n] * colscale[n] + beta * C[m, n]
@@ -13,7 +15,6 @@ namespace bse {
 // zero), so the k-range of each output tile is cut to where both operands
 // can be nonzero.  lowerC: only tiles on or below the diagonal are computed.
 // mask > 0: outputs with m >= mask or n >= mask are written as zero.
-// batch > 1: blockIdx.y selects the problem; pointers advance by stride*.
 struct GemmDesc {
   int M = 0, N = 0, K = 0;
   const void* A = nullptr; long lda = 0; int opA = 0; int triA = 0;
@@ -24,8 +25,6 @@ struct GemmDesc {
   const double* colscale = nullptr;  // real, length N
   int lowerC = 0;
   int mask = 0;
-  int batch = 1;
-  long strideA = 0, strideB = 0, strideC = 0;
 };
 
 hipError_t gemm_z(const GemmDesc& d, hipStream_t s);  // complex128
@@ -52,9 +51,18 @@ struct JacobiWork {
   int* inner = nullptr;    // inner Jacobi sweeps in the current sweep
   int* inner_rot = nullptr;  // inner Jacobi rotations applied in the current sweep
   double* maxoff = nullptr;
+  int kc = 0;      // Gram split: row chunks per pair
+  int rrows = 0;   // rows per rotation work group
 };
-size_t jacobi_work_bytes(int np, int elem_bytes);
-void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w);
+// kc, rrows = 0: built-in choice for np (kc: enough work groups to fill the
+// chip for one problem; rrows: largest of 256, 128, 64 dividing np).
+size_t jacobi_work_bytes(int np, int elem_bytes, int kc = 0);
+void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w, int kc = 0, int rrows = 0);
+// kc a power of two with np % (16 kc) == 0; rrows a multiple of 64 dividing np.
+bool jacobi_tiles_valid(int np, int kc, int rrows);
+int jacobi_default_kc(int np);
+int jacobi_gram_blocks_kc(int np, int kc);
+int jacobi_rot_blocks_rr(int np, int rrows);
 
 struct JacobiResult {
   int sweeps = 0;
@@ -125,6 +133,9 @@ hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int 
 // scales of the final pair.  Runs up to max_steps steps and stops after a
 // step whose largest off-diagonal correction is at most stop_corr; returns
 // that correction in *max_corr and the steps run in *steps_done.
+// Pairs whose Ritz values differ by at most this fraction are corrected
+// within their span only (first-order rotation part dropped).
+constexpr double kRefineDelta = 1.0e-10;
 struct RefineWork {
   double2 *Q = nullptr, *F = nullptr, *P1 = nullptr, *P2 = nullptr, *Ex = nullptr, *Ey = nullptr;
   double *ritz = nullptr, *dots = nullptr, *maxcorr = nullptr;
@@ -153,5 +164,113 @@ hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, con
 size_t adjoint_work_bytes(int n);
 hipError_t adjoint_z(int n, const double2* X, long ldx, const double* w, double2* gA, long ldga,
                      double2* gB, long ldgb, void* work, hipStream_t s);
+
+// ---------------------------------------------------------------- op arguments
+// Argument structs of the kernels (see the op launches in common.hpp); the
+// grouped form of a phase takes a device table of these, one per problem.
+struct FormArgs {
+  int n, np; const double2* A; long lda; const double2* B; long ldb; int upper;
+  double2* M1; double2* M2; long ldm;
+};
+struct MirrorArgs { int np; double2* M; long ld; };
+struct ToC64Args { int np; const double2* M; long ld; float2* Mc; };
+template <typename C2> struct Potf2Args {  // aux = first column of the panel
+  C2* M; long ld; C2* linv; int* status; int base; int n_real;
+};
+template <typename T> struct GemmArgs {
+  typedef typename cpx_t<T>::type C2;
+  int M, N, K;
+  const C2* A; long lda; int triA;
+  const C2* B; long ldb; int triB;
+  C2* C; long ldc;
+  T ar, ai, br, bi;
+  const double* kscale;
+  const double* colscale;
+  int lowerC, mask;
+  int tilesM, tilesN;
+};
+template <typename C2> struct GramArgs {  // aux = round
+  int N; const C2* W; long ld; int rc, kc; C2* part; const int* done;
+};
+template <typename C2> struct EigArgs {  // aux = round
+  int N, kc; const C2* part; C2* R; int* flags; int* counter; double tol; double* maxoff;
+  int max_inner; int* inner; double inner_stop2; const double* stop2p; int* inner_rot;
+  const int* done;
+};
+template <typename C2> struct RotArgs {  // aux = round
+  int N; C2* W; long ld; const C2* R; const int* flags; int rrows, chunks; const int* done;
+};
+template <typename C2> struct ColnormArgs { const C2* W; long ld; int np; double* out; };
+template <typename C2> struct ScaleArgs { int n, np; C2* W; long ld; const double* sigma; };
+struct LambdaArgs {
+  int n, np; const double* anorm; const double* bnorm; double* lam; double* invlam; double* scl;
+};
+struct RankArgs { int n; const double* key; int* perm; int desc; };
+struct WriteLambdaArgs { int n; const double* lam; const int* perm; double* lambda; int want_negative; };
+struct C64Args { int np; const float2* S; long lds; double2* D; long ldd; const double* colscale; };
+struct AssembleArgs {
+  int n; const double2* V1; const double2* V2; long ldv; const int* perm; const double* scl;
+  double2* X; long ldx; int want_negative;
+};
+struct RitzArgs { int n; const double2* F; const double2* P1; const double2* P2; long ld; double* ritz; };
+struct BuildArgs {
+  int n; const double2* F; const double2* P1; const double2* P2; long ld; const double* ritz;
+  double2* Ex; double2* Ey; double delta; double* maxcorr;
+};
+struct RqArgs {
+  int n; const double2* x; const double2* y; const double2* Qx; const double2* Qy; long ld;
+  double* lam; double* scl;
+};
+
+// Per-problem Jacobi state of a batch (device memory, 128 bytes).  The
+// kernels of a problem whose `done` is set return at once; the sweep op
+// closes one sweep and opens the next.
+struct JacState {
+  int counter, inner, inner_rot, done;
+  int sweeps, rotations, converged, pad0;
+  long pair_checks, inner_sweeps;
+  double maxoff, last_off, stop2, inner_rotations;
+  double pad1[6];
+};
+struct SweepArgs {  // aux = sweep index
+  JacState* st; int* active; int pairs_per_sweep; int max_sweeps; double inner_floor; int adaptive;
+};
+
+// Work-group counts of one problem for the ops above.
+int gemm_tiles(const GemmDesc& d);
+int jacobi_eig_blocks(int np);
+int jacobi_rounds(int np);
+int jacobi_pairs(int np);
+
+// Argument structs filled the way the single-problem launches fill them.
+GemmArgs<double> gemm_args_z(const GemmDesc& d);
+GemmArgs<float> gemm_args_c(const GemmDesc& d);
+GramArgs<double2> gram_args_z(int np, double2* W, long ld, const JacobiWork& w, const int* done);
+GramArgs<float2> gram_args_c(int np, float2* W, long ld, const JacobiWork& w, const int* done);
+EigArgs<double2> eig_args_z(int np, const JacobiWork& w, double tol, const double* stop2p, const int* done);
+EigArgs<float2> eig_args_c(int np, const JacobiWork& w, double tol, const double* stop2p, const int* done);
+RotArgs<double2> rot_args_z(int np, double2* W, long ld, const JacobiWork& w, const int* done);
+RotArgs<float2> rot_args_c(int np, float2* W, long ld, const JacobiWork& w, const int* done);
+
+// Grouped launches: table = device array of the op's Args, map = device
+// array of (table row, work group) pairs, blocks = entries of map used.
+enum GroupOp {
+  G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C,                      // chol.hip
+  G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
+  G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
+  G_WRITE_LAMBDA, G_C64, G_ASSEMBLE,
+  G_RITZ, G_BUILD, G_RQ,                                                // refine.hip
+};
+hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
+hipError_t group_jacobi(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
+hipError_t group_finalize(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
+hipError_t group_refine(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
+// prec 0: complex128, 1: complex64
+hipError_t group_gemm(int prec, int opA, int opB, const void* table, const int2* map, int blocks,
+                      hipStream_t s);
+
+// Blocks per problem of the fixed-shape ops.
+inline int tiles64(int np) { return (np / 64) * (np / 64); }
+inline int cols_blocks(int rows, int cols) { return ((rows + 255) / 256) * cols; }
 
 }  // namespace bse

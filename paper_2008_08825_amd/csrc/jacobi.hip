@@ -48,14 +48,24 @@ BSE_DEV int pair_col(int p, int q, int c) { return c < JB ? p * JB + c : q * JB 
 // Workgroup (pair k, chunk c) accumulates the ten lower tiles of X^H X over
 // rows [c * rc, (c + 1) * rc) and writes them to part[(k * kc + c) * 10 + tile].
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_gram(int N, int t, const typename cpx_t<T>::type* __restrict__ W,
-                                                  long ld, int rc, int kc,
-                                                  typename cpx_t<T>::type* __restrict__ part) {
+struct GramOp {
+  static constexpr int NT = 256;
+  typedef GramArgs<typename cpx_t<T>::type> Args;
+  static BSE_DEV void run(const Args& a, int bx, int t);
+};
+
+template <typename T>
+BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
   typedef typename cpx_t<T>::type C2;
   typedef typename Mfma<T>::acc Acc;
+  if (a.done && *a.done) return;
+  const int N = a.N, rc = a.rc, kc = a.kc;
+  const C2* __restrict__ W = a.W;
+  const long ld = a.ld;
+  C2* __restrict__ part = a.part;
   __shared__ T Xs[2][2][16][JP + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k = blockIdx.x / kc, c = blockIdx.x % kc;
+  const int k = bx / kc, c = bx % kc;
   int p, q;
   round_pair(N, t, k, p, q);
   // tiles of this wave: 3, 3, 2, 2
@@ -133,15 +143,27 @@ __global__ __launch_bounds__(256) void k_jac_gram(int N, int t, const typename c
 constexpr int EIG_THREADS = 512;
 
 template <typename T>
-__global__ __launch_bounds__(EIG_THREADS) void k_jac_eig(int N, int t, int kc,
-                                                 const typename cpx_t<T>::type* __restrict__ part,
-                                                 typename cpx_t<T>::type* __restrict__ Rout,
-                                                 int* __restrict__ flags, int* counter,
-                                                 double tol, double* maxoff, int max_inner,
-                                                 int* inner_count, double inner_stop2,
-                                                 int* inner_rot_count) {
+struct EigOp {
+  static constexpr int NT = EIG_THREADS;
+  typedef EigArgs<typename cpx_t<T>::type> Args;
+  static BSE_DEV void run(const Args& a, int bx, int t);
+};
+
+template <typename T>
+BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   typedef typename cpx_t<T>::type C2;
-  constexpr int NT = EIG_THREADS;
+  if (a.done && *a.done) return;
+  const int N = a.N, kc = a.kc, max_inner = a.max_inner;
+  const C2* __restrict__ part = a.part;
+  C2* __restrict__ Rout = a.R;
+  int* __restrict__ flags = a.flags;
+  int* counter = a.counter;
+  int* inner_count = a.inner;
+  int* inner_rot_count = a.inner_rot;
+  double* maxoff = a.maxoff;
+  const double tol = a.tol;
+  const double inner_stop2 = a.stop2p ? *a.stop2p : a.inner_stop2;
+  (void)N; (void)t;
   __shared__ double2 G[JP][JP + LPAD];
   __shared__ double2 R[JP][JP + LPAD];
   __shared__ double4 prm[32];   // (c, Re s, Im s, unused) of rotation m
@@ -152,7 +174,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_jac_eig(int N, int t, int kc,
   __shared__ int nrot;
   __shared__ int sweepbig;
   const int tid = threadIdx.x;
-  const int k = blockIdx.x;
+  const int k = bx;
   // (P, Q) of the 528 pairs of rotation slots with P <= Q, as P | Q << 8
   for (int Q = 0, b = 0; Q < 32; ++Q)
     for (int P = 0; P <= Q; ++P, ++b)
@@ -374,15 +396,25 @@ __global__ __launch_bounds__(EIG_THREADS) void k_jac_eig(int N, int t, int kc,
 // inputs in registers (loaded as MFMA B operands: 16 consecutive rows of one
 // column per 16 lanes) before writing any output.
 template <typename T>
-__global__ __launch_bounds__(256) void k_jac_rotate(int N, int t, typename cpx_t<T>::type* W, long ld,
-                                                    const typename cpx_t<T>::type* __restrict__ Rall,
-                                                    const int* __restrict__ flags, int rows_per_wg,
-                                                    int chunks) {
+struct RotOp {
+  static constexpr int NT = 256;
+  typedef RotArgs<typename cpx_t<T>::type> Args;
+  static BSE_DEV void run(const Args& a, int bx, int t);
+};
+
+template <typename T>
+BSE_DEV void RotOp<T>::run(const typename RotOp<T>::Args& a, int bx, int t) {
   typedef typename cpx_t<T>::type C2;
   typedef typename Mfma<T>::acc Acc;
+  if (a.done && *a.done) return;
+  const int N = a.N, rows_per_wg = a.rrows, chunks = a.chunks;
+  C2* W = a.W;
+  const long ld = a.ld;
+  const C2* __restrict__ Rall = a.R;
+  const int* __restrict__ flags = a.flags;
   __shared__ T Rs[2][JP][JP + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k = blockIdx.x / chunks, chunk = blockIdx.x % chunks;
+  const int k = bx / chunks, chunk = bx % chunks;
   if (!flags[k]) return;
   int p, q;
   round_pair(N, t, k, p, q);
@@ -423,6 +455,50 @@ __global__ __launch_bounds__(256) void k_jac_rotate(int N, int t, typename cpx_t
   }
 }
 
+// ---------------------------------------------------------------- batches
+// One workgroup per problem of a batch, between sweeps: closes the previous
+// sweep (aux > 0) and, unless the problem has converged (a sweep rotated no
+// pair) or aux == max_sweeps, opens sweep aux with cleared counters and the
+// inner stopping threshold of the adaptive rule used by jacobi_run.
+struct SweepOp {
+  static constexpr int NT = 64;
+  typedef SweepArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int sweep);
+};
+
+BSE_DEV void SweepOp::run(const SweepArgs& a, int, int sweep) {
+  if (threadIdx.x != 0) return;
+  JacState* st = a.st;
+  if (st->done) return;
+  double prev = -1.0;
+  if (sweep > 0) {
+    st->sweeps += 1;
+    st->rotations += st->counter;
+    st->inner_sweeps += st->inner;
+    st->inner_rotations += (double)st->inner_rot;
+    st->pair_checks += a.pairs_per_sweep;
+    st->last_off = st->maxoff;
+    prev = st->maxoff;
+    if (st->counter == 0) {
+      st->converged = 1;
+      st->done = 1;
+      return;
+    }
+  }
+  if (sweep >= a.max_sweeps) {
+    st->done = 1;
+    return;
+  }
+  double stop = a.inner_floor;
+  if (a.adaptive) stop = fmax(a.inner_floor, prev < 0.0 ? 1.0e-3 : fmin(1.0e-3, 0.3 * prev));
+  st->stop2 = stop * stop;
+  st->counter = 0;
+  st->inner = 0;
+  st->inner_rot = 0;
+  st->maxoff = 0.0;
+  atomicAdd(a.active, 1);
+}
+
 int gram_chunks(int np, int pairs) {
   // enough workgroups to fill the chip, rows per chunk a multiple of 16
   int kc = 1;
@@ -439,9 +515,9 @@ int rotate_rows(int np) {
 
 }  // namespace
 
-size_t jacobi_work_bytes(int np, int elem_bytes) {
+size_t jacobi_work_bytes(int np, int elem_bytes, int kc) {
   const int N = np / JB, pairs = N / 2;
-  const int kc = gram_chunks(np, pairs);
+  if (kc <= 0) kc = gram_chunks(np, pairs);
   size_t b = 0;
   b += (size_t)pairs * kc * NTILE * 256 * 2 * elem_bytes;  // part
   b = (b + 255) & ~(size_t)255;
@@ -452,12 +528,13 @@ size_t jacobi_work_bytes(int np, int elem_bytes) {
   return (b + 255) & ~(size_t)255;
 }
 
-void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w) {
+void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w, int kc, int rrows) {
   const int N = np / JB, pairs = N / 2;
-  const int kc = gram_chunks(np, pairs);
+  w.kc = kc > 0 ? kc : gram_chunks(np, pairs);
+  w.rrows = rrows > 0 ? rrows : rotate_rows(np);
   size_t o = 0;
   w.part = base + o;
-  o += (size_t)pairs * kc * NTILE * 256 * 2 * elem_bytes;
+  o += (size_t)pairs * w.kc * NTILE * 256 * 2 * elem_bytes;
   o = (o + 255) & ~(size_t)255;
   w.R = base + o;
   o += (size_t)pairs * JP * JP * 2 * elem_bytes;
@@ -471,16 +548,55 @@ void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w) {
   w.maxoff = reinterpret_cast<double*>(base + o + 64);
 }
 
+bool jacobi_tiles_valid(int np, int kc, int rrows) {
+  if (kc < 1 || (kc & (kc - 1)) != 0 || np % (16 * kc) != 0) return false;
+  if (rrows < 64 || rrows % 64 != 0 || np % rrows != 0) return false;
+  return true;
+}
+
+int jacobi_default_kc(int np) { return gram_chunks(np, np / JB / 2); }
+int jacobi_pairs(int np) { return np / JB / 2; }
+int jacobi_rounds(int np) { return np / JB - 1; }
+int jacobi_gram_blocks_kc(int np, int kc) { return jacobi_pairs(np) * kc; }
+int jacobi_eig_blocks(int np) { return jacobi_pairs(np); }
+int jacobi_rot_blocks_rr(int np, int rrows) { return jacobi_pairs(np) * (np / rrows); }
+
+template <typename C2>
+GramArgs<C2> make_gram(int np, C2* W, long ld, const JacobiWork& w, const int* done) {
+  GramArgs<C2> a;
+  a.N = np / JB; a.W = W; a.ld = ld; a.kc = w.kc; a.rc = np / w.kc;
+  a.part = static_cast<C2*>(w.part); a.done = done;
+  return a;
+}
+template <typename C2>
+EigArgs<C2> make_eig(int np, const JacobiWork& w, double tol, const double* stop2p, const int* done) {
+  EigArgs<C2> a;
+  a.N = np / JB; a.kc = w.kc;
+  a.part = static_cast<const C2*>(w.part); a.R = static_cast<C2*>(w.R);
+  a.flags = w.flags; a.counter = w.counter; a.tol = tol; a.maxoff = w.maxoff;
+  a.max_inner = 30; a.inner = w.inner; a.inner_stop2 = 0.0; a.stop2p = stop2p;
+  a.inner_rot = w.inner_rot; a.done = done;
+  return a;
+}
+template <typename C2>
+RotArgs<C2> make_rot(int np, C2* W, long ld, const JacobiWork& w, const int* done) {
+  RotArgs<C2> a;
+  a.N = np / JB; a.W = W; a.ld = ld; a.R = static_cast<const C2*>(w.R); a.flags = w.flags;
+  a.rrows = w.rrows; a.chunks = np / w.rrows; a.done = done;
+  return a;
+}
+
 template <typename T>
 static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const JacobiWork& w,
                              double tol, double inner_stop, int max_sweeps, JacobiResult& res,
                              hipStream_t s, bool time_kernels) {
   typedef typename cpx_t<T>::type C2;
   const int N = np / JB, pairs = N / 2;
-  const int kc = gram_chunks(np, pairs);
-  const int rc = np / kc;
-  const int rrows = rotate_rows(np);
-  const int chunks = np / rrows;
+  const int gblocks = jacobi_gram_blocks_kc(np, w.kc);
+  const int rblocks = jacobi_rot_blocks_rr(np, w.rrows);
+  const GramArgs<C2> ga = make_gram<C2>(np, W, ld, w, nullptr);
+  EigArgs<C2> ea = make_eig<C2>(np, w, tol, nullptr, nullptr);
+  const RotArgs<C2> ra = make_rot<C2>(np, W, ld, w, nullptr);
   res = JacobiResult();
   hipError_t e;
   // Optional per-launch timing: an event before and after every Jacobi kernel.
@@ -509,24 +625,22 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double sstop = inner_stop;
     if (adaptive) sstop = fmax(inner_stop, prev_off < 0.0 ? 1.0e-3 : fmin(1.0e-3, 0.3 * prev_off));
-    const double inner_stop2 = sstop * sstop;
+    ea.inner_stop2 = sstop * sstop;
     e = hipMemsetAsync(w.counter, 0, 128, s);
     if (e != hipSuccess) { ret = e; break; }
     for (int t = 0; t < N - 1; ++t) {
       const size_t b = (size_t)t * 6;
       mark(b + 0);
-      k_jac_gram<T><<<pairs * kc, 256, 0, s>>>(N, t, W, ld, rc, kc, (C2*)w.part);
+      e = launch_one<GramOp<T>>(ga, gblocks, t, s);
       mark(b + 1);
       mark(b + 2);
-      k_jac_eig<T><<<pairs, EIG_THREADS, 0, s>>>(N, t, kc, (const C2*)w.part, (C2*)w.R, w.flags, w.counter,
-                                         tol, w.maxoff, 30, w.inner, inner_stop2, w.inner_rot);
+      if (e == hipSuccess) e = launch_one<EigOp<T>>(ea, pairs, t, s);
       mark(b + 3);
       mark(b + 4);
-      k_jac_rotate<T><<<pairs * chunks, 256, 0, s>>>(N, t, W, ld, (const C2*)w.R, w.flags, rrows,
-                                                     chunks);
+      if (e == hipSuccess) e = launch_one<RotOp<T>>(ra, rblocks, t, s);
       mark(b + 5);
+      if (e != hipSuccess) break;
     }
-    e = hipGetLastError();
     if (e != hipSuccess) { ret = e; break; }
     int cnt = 0, inner = 0, irot = 0;
     double mo = 0.0;
@@ -569,6 +683,41 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
                     int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels) {
   return jacobi_run<float>(np, W, ld, w, tol, inner_stop, max_sweeps, res, s, time_kernels);
+}
+
+GramArgs<double2> gram_args_z(int np, double2* W, long ld, const JacobiWork& w, const int* done) {
+  return make_gram<double2>(np, W, ld, w, done);
+}
+GramArgs<float2> gram_args_c(int np, float2* W, long ld, const JacobiWork& w, const int* done) {
+  return make_gram<float2>(np, W, ld, w, done);
+}
+EigArgs<double2> eig_args_z(int np, const JacobiWork& w, double tol, const double* stop2p,
+                            const int* done) {
+  return make_eig<double2>(np, w, tol, stop2p, done);
+}
+EigArgs<float2> eig_args_c(int np, const JacobiWork& w, double tol, const double* stop2p,
+                           const int* done) {
+  return make_eig<float2>(np, w, tol, stop2p, done);
+}
+RotArgs<double2> rot_args_z(int np, double2* W, long ld, const JacobiWork& w, const int* done) {
+  return make_rot<double2>(np, W, ld, w, done);
+}
+RotArgs<float2> rot_args_c(int np, float2* W, long ld, const JacobiWork& w, const int* done) {
+  return make_rot<float2>(np, W, ld, w, done);
+}
+
+hipError_t group_jacobi(GroupOp op, const void* table, const int2* map, int blocks, int aux,
+                        hipStream_t s) {
+  switch (op) {
+    case G_GRAM_Z: return launch_grp<GramOp<double>>(table, map, blocks, aux, s);
+    case G_GRAM_C: return launch_grp<GramOp<float>>(table, map, blocks, aux, s);
+    case G_EIG_Z: return launch_grp<EigOp<double>>(table, map, blocks, aux, s);
+    case G_EIG_C: return launch_grp<EigOp<float>>(table, map, blocks, aux, s);
+    case G_ROT_Z: return launch_grp<RotOp<double>>(table, map, blocks, aux, s);
+    case G_ROT_C: return launch_grp<RotOp<float>>(table, map, blocks, aux, s);
+    case G_SWEEP: return launch_grp<SweepOp>(table, map, blocks, aux, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace bse

@@ -1,0 +1,180 @@
+// Workspace plan of one problem and the helpers shared by the single and the
+// batched entry points (host code only).
+#pragma once
+
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/bse.h"
+#include "internal.hpp"
+
+namespace bse {
+
+constexpr int kErrHip = -1000;
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+inline int pad64(int n) { return ((n + 63) / 64) * 64; }
+
+// Workspace layout.  U = np^2 complex128 (16 np^2 bytes).
+//   FP64:  M1, M2, W, Y (4 U)
+//   mixed: M1, M2 (full Hermitian FP64), X1, X2 (FP64 pair), Q, F, P1, P2
+//          (refinement), L1c|L2c (complex64, 1 U), Wc|Yc (complex64, 1 U):
+//          10 U; the complex64 regions hold Ex, Ey during the refinement.
+struct Plan {
+  int n = 0, np = 0, mixed = 0;
+  size_t off_m1 = 0, off_m2 = 0, off_w = 0, off_y = 0;
+  size_t off_x1 = 0, off_x2 = 0, off_q = 0, off_f = 0, off_p1 = 0, off_p2 = 0;
+  size_t off_z = 0, off_inv = 0;
+  int alg2 = 0;
+  size_t off_lc = 0, off_wc = 0;
+  size_t off_linv = 0, off_sigma = 0, off_perm = 0, off_invlam = 0, off_status = 0;
+  size_t off_bnorm = 0, off_anorm = 0, off_lamu = 0, off_scl = 0, off_ritz = 0, off_small = 0;
+  size_t off_jac = 0;
+  size_t total = 0;
+  int kc = 0, rrows = 0;  // Jacobi tiles (0 = built-in)
+};
+
+inline bool opts_valid(const bse_opts_t& o) {
+  if (o.route != BSE_ROUTE_SVD && o.route != BSE_ROUTE_EIG) return false;
+  if (o.precision != BSE_PREC_FP64 && o.precision != BSE_PREC_MIXED) return false;
+  if (o.max_sweeps < 0 || o.refine_steps < 0 || o.refine_steps > 8 || !(o.jacobi_tol >= 0.0))
+    return false;
+  if (o.route == BSE_ROUTE_EIG && o.precision != BSE_PREC_FP64) return false;  // Alg. 2: FP64 only
+  if (!(o.uplo == 0 || o.uplo == 'L' || o.uplo == 'U' || o.uplo == 'l' || o.uplo == 'u')) return false;
+  if (o.reserved0 != 0 || o.reserved[0] != 0 || o.reserved[1] != 0) return false;
+  if (o.tile_entries < 0 || o.tile_entries > 4096 || (o.tile_entries > 0 && !o.tile_table)) return false;
+  for (int r = 0; r < o.tile_entries; ++r) {
+    const int kc = o.tile_table[3 * r + 1], rr = o.tile_table[3 * r + 2];
+    if (o.tile_table[3 * r] <= 0 || kc < 1 || (kc & (kc - 1)) != 0 || rr < 64 || rr % 64 != 0)
+      return false;
+  }
+  return true;
+}
+
+// Jacobi tiles of a problem of padded order np: the first fitting row of the
+// caller's table, else 0 (built-in choice).  kc is capped at the built-in
+// split, for which the workspace is sized.
+inline void pick_tiles(const bse_opts_t& o, int np, int* kc, int* rrows) {
+  *kc = 0;
+  *rrows = 0;
+  for (int r = 0; r < o.tile_entries; ++r) {
+    if (np > o.tile_table[3 * r]) continue;
+    const int k = o.tile_table[3 * r + 1], rr = o.tile_table[3 * r + 2];
+    if (jacobi_tiles_valid(np, k, rr) && k <= jacobi_default_kc(np)) {
+      *kc = k;
+      *rrows = rr;
+    }
+    return;
+  }
+}
+
+inline Plan make_plan(int n, const bse_opts_t& o) {
+  Plan p;
+  p.n = n;
+  p.np = pad64(n > 0 ? n : 1);
+  p.mixed = o.precision == BSE_PREC_MIXED;
+  pick_tiles(o, p.np, &p.kc, &p.rrows);
+  p.alg2 = o.route == BSE_ROUTE_EIG;
+  const size_t U = (size_t)p.np * p.np * sizeof(double2);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  p.off_m1 = take(U);
+  p.off_m2 = take(U);
+  if (p.alg2) {
+    p.off_w = take(U);
+    p.off_y = take(U);
+    p.off_z = take(U);
+    p.off_inv = take((size_t)p.np * 64 * sizeof(double2));
+  } else if (!p.mixed) {
+    p.off_w = take(U);
+    p.off_y = take(U);
+  } else {
+    p.off_x1 = take(U);
+    p.off_x2 = take(U);
+    p.off_q = take(U);
+    p.off_f = take(U);
+    p.off_p1 = take(U);
+    p.off_p2 = take(U);
+    p.off_lc = take(U);  // L1c | L2c, then Ex
+    p.off_wc = take(U);  // Wc | Yc, then Ey
+  }
+  p.off_linv = take(2 * 64 * 64 * sizeof(double2));  // one diagonal-block inverse per factor
+  p.off_sigma = take((size_t)p.np * sizeof(double));
+  p.off_perm = take((size_t)p.np * sizeof(int));
+  p.off_invlam = take((size_t)p.np * sizeof(double));
+  p.off_bnorm = take((size_t)p.np * sizeof(double));
+  p.off_anorm = take((size_t)p.np * sizeof(double));
+  p.off_lamu = take((size_t)p.np * sizeof(double));
+  p.off_scl = take((size_t)p.np * sizeof(double));
+  p.off_ritz = take((size_t)p.np * sizeof(double));
+  p.off_small = take(256);
+  p.off_status = take(64);
+  p.off_jac = take(jacobi_work_bytes(p.np, p.mixed ? sizeof(float) : sizeof(double)));
+  p.total = off + 256;  // slack for aligning the caller's base pointer
+  return p;
+}
+
+inline int hip_status(hipError_t e) { return kErrHip - (int)e; }
+
+#define BSE_TRY(expr)                            \
+  do {                                           \
+    hipError_t e_ = (expr);                      \
+    if (e_ != hipSuccess) return hip_status(e_); \
+  } while (0)
+
+struct Timer {
+  bool on;
+  hipStream_t s;
+  hipEvent_t ev[9];
+  int k = 0;
+  Timer(bool enable, hipStream_t st) : on(enable), s(st) {
+    if (on)
+      for (int i = 0; i < 9; ++i) (void)hipEventCreate(&ev[i]);
+  }
+  void mark() {
+    if (on && k < 9) (void)hipEventRecord(ev[k++], s);
+  }
+  // phase i of ms_phase = time between marks i and i + 1 (marks may be skipped: -1)
+  void fill(bse_info_t* info, const int* slot) {
+    if (!on || !info) return;
+    (void)hipEventSynchronize(ev[k - 1]);
+    for (int i = 0; i + 1 < k; ++i) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[i], ev[i + 1]);
+      if (slot[i] >= 0 && slot[i] < 7) info->ms_phase[slot[i]] += ms;
+    }
+    float tot = 0.f;
+    (void)hipEventElapsedTime(&tot, ev[0], ev[k - 1]);
+    info->ms_phase[7] = tot;
+  }
+  ~Timer() {
+    if (on)
+      for (int i = 0; i < 9; ++i) (void)hipEventDestroy(ev[i]);
+  }
+};
+
+
+// Batched SVD route (batched.hip): workspace bytes and the grouped solve.
+size_t batched_workspace(int batch, const int* n, const bse_opts_t& o);
+int solve_batched_grouped(int batch, const int* n, const void* const* A, const int* lda,
+                          const void* const* B, const int* ldb, double* const* lambda,
+                          void* const* X, const int* ldx, void* work, const bse_opts_t& o,
+                          bse_info_t* info, int want_timing, hipStream_t s);
+
+// np x np triangular product with a lower-triangular left factor (its k range cut).
+inline GemmDesc tri_gemm(int np, long ld, const void* A, int opA, const void* B, int opB, int triB,
+                  void* C) {
+  GemmDesc g;
+  g.M = np; g.N = np; g.K = np;
+  g.A = A; g.lda = ld; g.opA = opA; g.triA = 1;
+  g.B = B; g.ldb = ld; g.opB = opB; g.triB = triB;
+  g.C = C; g.ldc = ld;
+  return g;
+}
+
+}  // namespace bse

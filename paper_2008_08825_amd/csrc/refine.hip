@@ -34,28 +34,40 @@
 namespace bse {
 namespace {
 
-__global__ __launch_bounds__(256) void k_ritz(int n, const double2* __restrict__ F,
-                                              const double2* __restrict__ P1,
-                                              const double2* __restrict__ P2, long ld,
-                                              double* __restrict__ ritz) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const long d = i + (long)i * ld;
-  ritz[i] = 0.5 * (P2[d].x + P1[d].x) / F[d].x;
-}
+struct RitzOp {
+  static constexpr int NT = 256;
+  typedef RitzArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    const int i = bx * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const long d = i + (long)i * a.ld;
+    a.ritz[i] = 0.5 * (a.P2[d].x + a.P1[d].x) / a.F[d].x;
+  }
+};
 
 // Correction matrices Ex = I + E11 + E21 and Ey = I + E11 - E21; a 64 x 64
 // tile per workgroup, the transposed tile of F staged through LDS.
-__global__ __launch_bounds__(256) void k_build(int n, const double2* __restrict__ F,
-                                               const double2* __restrict__ P1,
-                                               const double2* __restrict__ P2, long ld,
-                                               const double* __restrict__ ritz,
-                                               double2* __restrict__ Ex, double2* __restrict__ Ey,
-                                               double delta, double* maxcorr) {
+struct BuildOp {
+  static constexpr int NT = 256;
+  typedef BuildArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux);
+};
+
+BSE_DEV void BuildOp::run(const BuildArgs& a, int bx, int) {
+  const int n = a.n;
+  const double2* __restrict__ F = a.F;
+  const double2* __restrict__ P1 = a.P1;
+  const double2* __restrict__ P2 = a.P2;
+  const long ld = a.ld;
+  const double* __restrict__ ritz = a.ritz;
+  double2* __restrict__ Ex = a.Ex;
+  double2* __restrict__ Ey = a.Ey;
+  const double delta = a.delta;
+  double* maxcorr = a.maxcorr;
   __shared__ double2 ft[64][65];
   __shared__ double red[256];
   const int T = (n + 63) / 64;
-  const int tm = blockIdx.x % T, tn = blockIdx.x / T;
+  const int tm = bx % T, tn = bx / T;
   const int m0 = tm * 64, n0 = tn * 64;
   const int tid = threadIdx.x;
   // ft[c][r] = F[n0 + c][m0 + r]  (rows of the transposed tile)
@@ -118,13 +130,23 @@ __global__ __launch_bounds__(256) void k_build(int n, const double2* __restrict_
 }
 
 // Column k: lambda_k = (x_k^H Qx_k + y_k^H Qy_k) / (2 Re x_k^H y_k), scl_k = (Re x_k^H y_k)^-1/2.
-__global__ __launch_bounds__(256) void k_rq_cols(int n, const double2* __restrict__ x,
-                                                 const double2* __restrict__ y,
-                                                 const double2* __restrict__ Qx,
-                                                 const double2* __restrict__ Qy, long ld,
-                                                 double* __restrict__ lam, double* __restrict__ scl) {
+struct RqOp {
+  static constexpr int NT = 256;
+  typedef RqArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux);
+};
+
+BSE_DEV void RqOp::run(const RqArgs& args, int bx, int) {
+  const int n = args.n;
+  const double2* __restrict__ x = args.x;
+  const double2* __restrict__ y = args.y;
+  const double2* __restrict__ Qx = args.Qx;
+  const double2* __restrict__ Qy = args.Qy;
+  const long ld = args.ld;
+  double* __restrict__ lam = args.lam;
+  double* __restrict__ scl = args.scl;
   __shared__ double ra[256], rb[256], rc[256];
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = bx, tid = threadIdx.x;
   const long o = (long)k * ld;
   double a = 0.0, b = 0.0, c = 0.0;
   for (int i = tid; i < n; i += 256) {
@@ -156,6 +178,16 @@ GemmDesc nn(int n, long ld, const double2* A, int opA, const double2* B, int opB
 
 }  // namespace
 
+hipError_t group_refine(GroupOp op, const void* table, const int2* map, int blocks, int aux,
+                        hipStream_t s) {
+  switch (op) {
+    case G_RITZ: return launch_grp<RitzOp>(table, map, blocks, aux, s);
+    case G_BUILD: return launch_grp<BuildOp>(table, map, blocks, aux, s);
+    case G_RQ: return launch_grp<RqOp>(table, map, blocks, aux, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** xp,
                     double2** yp, const RefineWork& w, int max_steps, double stop_corr, double* lam,
                     double* scl, double* max_corr, int* steps_done, hipStream_t s) {
@@ -174,10 +206,11 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     if ((e = gemm_z(nn(n, ld, x, 1, Q, 0, w.P2), s)) != hipSuccess) return e;    // P2 = x^H M2 x
     if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, Q), s)) != hipSuccess) return e;      // Q = M1 y
     if ((e = gemm_z(nn(n, ld, y, 1, Q, 0, w.P1), s)) != hipSuccess) return e;    // P1 = y^H M1 y
-    k_ritz<<<(n + 255) / 256, 256, 0, s>>>(n, F, w.P1, w.P2, ld, w.ritz);
+    const RitzArgs ra = {n, F, w.P1, w.P2, ld, w.ritz};
+    if ((e = launch_one<RitzOp>(ra, (n + 255) / 256, 0, s)) != hipSuccess) return e;
     const int T = (n + 63) / 64;
-    k_build<<<T * T, 256, 0, s>>>(n, F, w.P1, w.P2, ld, w.ritz, w.Ex, w.Ey, 1.0e-10, w.maxcorr);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const BuildArgs ba = {n, F, w.P1, w.P2, ld, w.ritz, w.Ex, w.Ey, kRefineDelta, w.maxcorr};
+    if ((e = launch_one<BuildOp>(ba, T * T, 0, s)) != hipSuccess) return e;
     if ((e = gemm_z(nn(n, ld, x, 0, w.Ex, 0, Q), s)) != hipSuccess) return e;    // x (I + E11 + E21)
     if ((e = gemm_z(nn(n, ld, y, 0, w.Ey, 0, F), s)) != hipSuccess) return e;    // y (I + E11 - E21)
     double2* t = x; x = Q; Q = t;
@@ -195,8 +228,8 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
   // Rayleigh quotients and Sigma-normalising scales of the final pairs.
   if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, w.P2), s)) != hipSuccess) return e;
   if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, w.P1), s)) != hipSuccess) return e;
-  k_rq_cols<<<n, 256, 0, s>>>(n, x, y, w.P2, w.P1, ld, lam, scl);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const RqArgs qa = {n, x, y, w.P2, w.P1, ld, lam, scl};
+  if ((e = launch_one<RqOp>(qa, n, 0, s)) != hipSuccess) return e;
   *xp = x;
   *yp = y;
   return hipSuccess;

@@ -1,0 +1,124 @@
+"""Batched solve (grouped launches over problems of different orders) against the oracle.
+
+Each problem of a batch must give what the oracle gives for it (same bars as
+the single-problem parity tests), and exactly what bse_solve_h1 gives with the
+same options and Jacobi tiles: a batch runs the same kernels on the same
+per-problem arguments, only grouped into fewer launches.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bse as ob
+from oracle import metrics as om
+from paper_2008_08825_amd import inputs
+from test_gpu_solver import check_against_oracle
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def to_dev(problems):
+    As = [torch.from_numpy(A).to(DEV) for A, _ in problems]
+    Bs = [torch.from_numpy(B).to(DEV) for _, B in problems]
+    return As, Bs
+
+
+def host(res):
+    return [(lam.cpu().numpy(), X.resolve_conj().cpu().numpy()) for lam, X in res]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_uneven_sizes_vs_oracle(gpu_lib, precision):
+    sizes = [130, 1, 65, 5, 200, 17, 64, 100, 3]
+    problems = [inputs.coupled(n, seed=300 + i) for i, n in enumerate(sizes)]
+    print(f"[gpu] batched {precision} sizes={sizes}", flush=True)
+    res, infos, st = gpu_lib.solve_batched(*to_dev(problems), precision=precision, want_negative=True)
+    assert st == 0 and all(i["status"] == 0 for i in infos)
+    for (A, B), (lam, X), info in zip(problems, host(res), infos):
+        n = A.shape[0]
+        assert info["sweeps"] >= 1
+        if precision == "fp64":
+            check_against_oracle(A, B, lam, X)
+        else:
+            lam_o, _ = ob.solve_chol_svd(A, B)
+            assert om.rel_eig_err(lam[:n], lam_o) < 1e-10
+            assert om.residual(A, B, lam[:n], X[:, :n]) < 1e-13
+        # negative half: eigenvalues -lambda, vectors [0 I; I 0] X
+        assert np.array_equal(lam[n:], -lam[:n])
+        assert np.array_equal(X[:n, n:], X[n:, :n]) and np.array_equal(X[n:, n:], X[:n, :n])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_equals_single_with_same_tiles(gpu_lib, precision):
+    sizes = [130, 64, 200, 17, 256]
+    tiles = [(64, 1, 64), (128, 2, 64), (192, 1, 64), (256, 4, 128)]
+    problems = [inputs.coupled(n, seed=400 + i) for i, n in enumerate(sizes)]
+    As, Bs = to_dev(problems)
+    print(f"[gpu] batched vs single {precision}", flush=True)
+    res, infos, st = gpu_lib.solve_batched(As, Bs, precision=precision, tiles=tiles)
+    assert st == 0
+    for i, (lam_b, X_b) in enumerate(host(res)):
+        lam, X, info = gpu_lib.solve_h1(As[i], Bs[i], precision=precision, tiles=tiles)
+        assert np.array_equal(lam.cpu().numpy(), lam_b)
+        assert np.array_equal(X.resolve_conj().cpu().numpy(), X_b)
+        assert info["sweeps"] == infos[i]["sweeps"] and info["rotations"] == infos[i]["rotations"]
+
+
+def test_batched_status_per_problem(gpu_lib):
+    """One problem with A - B indefinite: its status is reported, the others are solved."""
+    good = [inputs.coupled(n, seed=500 + n) for n in (40, 90)]
+    A = np.diag(np.linspace(1.0, 2.0, 70)).astype(np.complex128)
+    B = 0.5 * A
+    B[30, 30] = 1.5 * A[30, 30]  # (A - B)[30, 30] < 0: leading minor 31 of A - B fails
+    problems = [good[0], (A, B), good[1]]
+    res, infos, st = gpu_lib.solve_batched(*to_dev(problems), check=False)
+    assert st == 70 + 31 and infos[1]["status"] == 70 + 31 and infos[1]["fail_index"] == 31
+    assert ob.chol_status(A, B) == 70 + 31
+    assert infos[0]["status"] == 0 and infos[2]["status"] == 0
+    out = host(res)
+    for k in (0, 2):
+        check_against_oracle(*problems[k], *out[k])
+
+
+def test_batched_zero_sizes_and_empty(gpu_lib):
+    res, infos, st = gpu_lib.solve_batched([], [])
+    assert st == 0 and res == []
+    A0 = torch.zeros((0, 0), dtype=torch.complex128, device=DEV)
+    A, B = inputs.coupled(33, seed=7)
+    res, infos, st = gpu_lib.solve_batched([A0, torch.from_numpy(A).to(DEV)], [A0, torch.from_numpy(B).to(DEV)])
+    assert st == 0 and res[0][0].numel() == 0
+    check_against_oracle(A, B, *host(res)[1:][0])
+
+
+def test_batched_full_workload_256_problems(gpu_lib):
+    """The 256-problem workload (n uniform in [64, 1024]), mixed form, as the benchmark runs it."""
+    ns = inputs.batch_sizes()
+    problems = [inputs.batch_problem(i, n) for i, n in enumerate(ns)]
+    As, Bs = to_dev(problems)
+    print("[gpu] batched 256-problem workload", flush=True)
+    res, infos, st = gpu_lib.solve_batched(As, Bs, precision="mixed")
+    assert st == 0
+    # properties at every size: Sigma-orthogonality and residual, on the GPU in FP64
+    for i, ((lam, X), A, B) in enumerate(zip(res, As, Bs)):
+        n = ns[i]
+        X = X.resolve_conj()
+        a, b = X[:n], X[n:]
+        G = a.conj().T @ a - b.conj().T @ b
+        orth = torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=DEV)).item()
+        # residual of H1 = [A B; -B -A] scaled as the oracle's metric (Frobenius norms)
+        R1 = A @ a + B @ b - a * lam
+        R2 = -(B @ a) - A @ b - b * lam
+        Hf = torch.sqrt(2 * torch.linalg.norm(A) ** 2 + 2 * torch.linalg.norm(B) ** 2)
+        resid = (torch.sqrt(torch.linalg.norm(R1) ** 2 + torch.linalg.norm(R2) ** 2) / (Hf * torch.linalg.norm(X))).item()
+        assert orth < 1e-9 * n ** 0.5 and resid < 1e-13, (i, n, orth, resid)
+        assert infos[i]["refine_delta"] <= 1e-6
+    # parity with the oracle on a sample: the three smallest problems and one near 400
+    order = np.argsort(ns)
+    sample = list(order[:3]) + [int(np.argmin(np.abs(np.array(ns) - 400)))]
+    for i in sample:
+        A, B = problems[i]
+        lam, X = res[i]
+        lam_o, _ = ob.solve_chol_svd(A, B)
+        assert om.rel_eig_err(lam.cpu().numpy(), lam_o) < 1e-10, i

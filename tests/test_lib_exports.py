@@ -93,3 +93,35 @@ def test_struct_layout_matches_binding(tmp_path):
         kind, name, off = line.split()
         cls = api.BSEOpts if kind == "o" else api.BSEInfo
         assert getattr(cls, name).offset == int(off), (kind, name)
+
+
+def test_batched_host_argument_checks():
+    """bse_solve_batched rejects bad arguments before any device work."""
+    from paper_2008_08825_amd import api
+
+    lib = api.load_library()
+    o = api.make_opts()
+    IA = ctypes.c_int * 2
+    PA = ctypes.c_void_p * 2
+    n = IA(4, 8)
+    ld = IA(4, 8)
+    ldx = IA(8, 16)
+    p = PA(16, 16)
+    assert lib.bse_solve_batched(-1, None, None, None, None, None, None, None, None, None, 0,
+                                 ctypes.byref(o), None, None) == -1
+    assert lib.bse_solve_batched(0, None, None, None, None, None, None, None, None, None, 0,
+                                 ctypes.byref(o), None, None) == 0
+    bad_ld = IA(3, 8)
+    assert lib.bse_solve_batched(2, n, p, bad_ld, p, ld, p, p, ldx, None, 0, ctypes.byref(o), None, None) == -3
+    bad_ldx = IA(8, 15)
+    assert lib.bse_solve_batched(2, n, p, ld, p, ld, p, p, bad_ldx, None, 0, ctypes.byref(o), None, None) == -8
+    assert lib.bse_solve_batched(2, n, p, ld, p, ld, p, p, ldx, None, 0, ctypes.byref(o), None, None) == -10
+    assert lib.bse_solve_batched(2, n, p, ld, p, ld, p, p, ldx, 16, 10, ctypes.byref(o), None, None) == -11
+    bad = api.make_opts(tiles=[(128, 3, 64)])  # kc not a power of two
+    assert lib.bse_batched_workspace_bytes(2, n, ctypes.byref(bad)) == 0
+    assert lib.bse_solve_batched(2, n, p, ld, p, ld, p, p, ldx, 16, 1 << 40, ctypes.byref(bad), None, None) == -12
+    need = lib.bse_batched_workspace_bytes(2, n, ctypes.byref(o))
+    single = lib.bse_workspace_bytes(8, ctypes.byref(o))
+    assert need > single
+    good = api.make_opts(tiles=[(64, 1, 64), (128, 2, 128)])
+    assert lib.bse_batched_workspace_bytes(2, n, ctypes.byref(good)) == need
