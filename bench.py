@@ -6,12 +6,13 @@ negative half; the mixed form adds the FP64 refinement) on inputs already
 resident in HBM.  Both forms are timed on the same inputs; one JSON line is
 printed.
 
-value    nominal TFLOP/s of the mixed form: the paper's flop model of Alg. 3
-         (Table 1: 24 2/3 n^3 real flops, times 4 for complex arithmetic =
-         98 2/3 n^3 per solve) divided by the measured seconds per solve.  The
-         FP64 form's figures sit under "fp64".
-roofline the kernel with the largest summed launch time in the timed mixed
-         solves (HIP events around every Jacobi launch on the solver's stream),
+value    nominal TFLOP/s of the faster of the two forms on this workload (named
+         in config.form): the paper's flop model of Alg. 3 (Table 1: 24 2/3 n^3
+         real flops, times 4 for complex arithmetic = 98 2/3 n^3 per solve)
+         divided by the measured seconds per solve.  Both forms' figures sit
+         under "fp64" and "mixed".
+roofline the kernel with the largest summed launch time in the timed solves
+         of that form (HIP events around every Jacobi launch on the solver's stream),
          its algorithmic work per launch over its average launch duration:
            rotation    8 np 64^2 flops per rotated block pair (complex MACs x 8)
            Gram        8 np 16^2 x 10 flops per block pair (ten 16 x 16 tiles)
@@ -22,6 +23,10 @@ roofline the kernel with the largest summed launch time in the timed mixed
          on the current kernel source (same hash), else null.
 cpu_baseline the FP64 CPU oracle (scipy, Alg. 3) on this host on a bounded
          sample: one problem of the same recipe at a smaller n.
+batched, differentiation  supplementary measurements of the other two forms:
+         the 256-problem batch (n uniform in [64, 1024]) through the grouped
+         batched entry point, and the n = 4096 forward solve + spectrum loss +
+         eigenvalue adjoint (the adjoint kernel also against the FP64 MFMA peak).
 """
 from __future__ import annotations
 
@@ -167,6 +172,112 @@ def kernel_report(acc, np_pad, precision, steps):
     return rep
 
 
+def bench_batched(api, inputs, steps, warmup):
+    """The 256-problem workload (n uniform in [64, 1024]) through bse_solve_batched, both forms."""
+    import numpy as np
+    import torch
+
+    dev = torch.device("cuda:0")
+    ns = inputs.batch_sizes()
+    t0 = time.perf_counter()
+    probs = [inputs.batch_problem(i, n) for i, n in enumerate(ns)]
+    log(f"batched inputs: {len(ns)} problems generated in {time.perf_counter() - t0:.1f}s")
+    As = [torch.from_numpy(a).to(dev) for a, _ in probs]
+    Bs = [torch.from_numpy(b).to(dev) for _, b in probs]
+    del probs
+    flops = sum((98.0 + 2.0 / 3.0) * float(n) ** 3 for n in ns)
+    out = {"workload": "256 problems, n uniform in [64, 1024] (seed 0), n=2048 recipe per problem",
+           "sum_n3": sum(float(n) ** 3 for n in ns)}
+    lam_by = {}
+    for prec in ("mixed", "fp64"):
+        need = api.batched_workspace_bytes(ns, precision=prec)
+        work = torch.empty(need, dtype=torch.uint8, device=dev)
+        for _ in range(warmup):
+            api.solve_batched(As, Bs, precision=prec, work=work, check=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res, infos, st = api.solve_batched(As, Bs, precision=prec, work=work, timing=1, check=False)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        sw = [i["sweeps"] for i in infos]
+        rs = [i["refine_steps_done"] for i in infos]
+        out[prec] = {"seconds_per_batch": round(sec, 4),
+                     "nominal_tflops": round(flops / sec / 1e12, 3),
+                     "status": st,
+                     "phase_ms": {k: round(v, 2) for k, v in zip(api.PHASES, infos[0]["ms_phase"])},
+                     "sweeps_max": max(sw), "sweeps_mean": round(float(np.mean(sw)), 2)}
+        if prec == "mixed":
+            out[prec]["refine_steps_max"] = max(rs)
+            out[prec]["refine_steps_mean"] = round(float(np.mean(rs)), 2)
+        lam_by[prec] = [lam for lam, _ in res]
+        log(f"batched {prec}: {sec:.3f}s per batch, status {st}")
+        del res, work
+    out["mixed_vs_fp64_max_rel_eig_diff"] = max(
+        ((a - b).abs() / b).max().item() for a, b in zip(lam_by["mixed"], lam_by["fp64"]))
+    return out
+
+
+def bench_differentiation(api, inputs, steps, warmup):
+    """n=4096 workload: forward solve, spectrum loss, adjoint (dL/dA, dL/dB) through BSEEig."""
+    import math
+
+    import torch
+
+    dev = torch.device("cuda:0")
+    A_np, B_np = inputs.workload("n4096")
+    n = A_np.shape[0]
+    A = torch.from_numpy(A_np).to(dev)
+    B = torch.from_numpy(B_np).to(dev)
+    om = (torch.arange(512, dtype=torch.float64, device=dev) + 0.5) * (12.0 / 512)
+
+    def loss(lam):
+        d = om[:, None] - lam[None, :]
+        return lam[:128].sum() + ((0.05 / math.pi) / (d * d + 0.05 ** 2)).sum()
+
+    def step():
+        At = A.clone().requires_grad_(True)
+        Bt = B.clone().requires_grad_(True)
+        t0 = time.perf_counter()
+        lam, X = api.BSEEig.apply(At, Bt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L = loss(lam)
+        L.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, lam.detach(), X
+
+    for _ in range(warmup):
+        step()
+    fwd = bwd = 0.0
+    for _ in range(steps):
+        f, b, lam, X = step()
+        fwd += f
+        bwd += b
+    fwd /= steps
+    bwd /= steps
+    # the adjoint kernel alone, timed with events on the solver's stream
+    w = torch.ones(n, dtype=torch.float64, device=dev)
+    api.backward(X, w)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        api.backward(X, w)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / steps
+    adj_flops = 8.0 * n ** 3  # two Hermitian rank-n products, lower halves (4 n^3 real flops each)
+    return {"workload": f"n={n} (n=2048 recipe, seed 0), loss = sum of lowest 128 eigenvalues + "
+                        "Lorentzian spectrum (eta 0.05) on 512 points in (0, 12)",
+            "forward_seconds": round(fwd, 4),
+            "forward_nominal_tflops": round(nominal_flops(n) / fwd / 1e12, 3),
+            "loss_and_backward_seconds": round(bwd, 4),
+            "adjoint_ms": round(adj_ms, 3),
+            "adjoint_tflops": round(adj_flops / (adj_ms * 1e-3) / 1e12, 3),
+            "adjoint_frac_fp64_mfma": round(adj_flops / (adj_ms * 1e-3) / 1e12 / PEAK["fp64_mfma"], 4)}
+
+
 def load_traffic(kernel: str, workload: str, precision: str):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -191,6 +302,10 @@ def main():
     ap.add_argument("--cpu-sample-n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-checks", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched (256 problems) and differentiation (n=4096) measurements")
+    ap.add_argument("--only", default="", choices=["", "batched", "differentiation"],
+                    help="run only this supplementary measurement and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -206,6 +321,10 @@ def main():
 
     api.load_library()
     dev = torch.device("cuda:0")
+    if args.only:
+        fn = bench_batched if args.only == "batched" else bench_differentiation
+        print(json.dumps({args.only: fn(api, inputs, args.steps, args.warmup)}), flush=True)
+        return
     if args.copy_calibration > 0:
         # one kernel that reads and writes exactly MIB MiB each, three times
         src = torch.ones(args.copy_calibration * 262144, dtype=torch.float32, device=dev)
@@ -250,7 +369,8 @@ def main():
         lam_by[f] = lam[:n].clone()
         results[f] = (res, acc)
 
-    main_form = "mixed" if "mixed" in results else forms[0]
+    # headline: the faster form on this workload (both are reported)
+    main_form = min(results, key=lambda f: results[f][0]["seconds_per_solve"])
     res, acc = results[main_form]
     dom = max(KERNELS, key=lambda k: res["kernels"][k]["ms_per_solve"])
     kd = res["kernels"][dom]
@@ -288,6 +408,12 @@ def main():
                                              / results["mixed"][0]["seconds_per_solve"], 3)
         d = ((lam_by["mixed"] - lam_by["fp64"]).abs() / lam_by["fp64"]).max().item()
         out["mixed_vs_fp64_max_rel_eig_diff"] = d
+    if not args.no_extras:
+        del Xbuf, work
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batched(api, inputs, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        out["differentiation"] = bench_differentiation(api, inputs, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle at n={args.cpu_sample_n}")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n)

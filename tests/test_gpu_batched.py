@@ -122,3 +122,21 @@ def test_batched_full_workload_256_problems(gpu_lib):
         lam, X = res[i]
         lam_o, _ = ob.solve_chol_svd(A, B)
         assert om.rel_eig_err(lam.cpu().numpy(), lam_o) < 1e-10, i
+
+
+def test_autotuner_small_range(gpu_lib):
+    """The tuner picks valid tiles per bucket, and a batch solved with them matches the oracle."""
+    from paper_2008_08825_amd import tune
+
+    print("[gpu] autotuner np=64,128", flush=True)
+    table, report = tune.tune(nps=(64, 128), precision="mixed", per_bucket=3, repeats=1)
+    assert [r[0] for r in table] == [64, 128]
+    for (np_, kc, rr) in table:
+        assert (kc, rr) in tune.candidates(np_)
+    sizes = [50, 128, 100, 64]
+    problems = [inputs.coupled(n, seed=600 + n) for n in sizes]
+    res, infos, st = gpu_lib.solve_batched(*to_dev(problems), precision="mixed", tiles=table)
+    assert st == 0
+    for (A, B), (lam, X) in zip(problems, host(res)):
+        lam_o, _ = ob.solve_chol_svd(A, B)
+        assert om.rel_eig_err(lam, lam_o) < 1e-10
