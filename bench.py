@@ -154,6 +154,13 @@ def kernel_report(acc, np_pad, precision, steps):
         "jacobi_eig": 3840.0 * acc["inner_rotations"],
         "jacobi_rotate": 8.0 * np_pad * 64 * 64 * acc["rotations"],
     }
+    # algorithmic HBM bytes: every checked pair reads its 64 columns (Gram);
+    # every rotated pair reads and writes them (rotation)
+    esz = 16 if precision == "fp64" else 8
+    col_bytes = np_pad * 64 * esz
+    alg_bytes = {"jacobi_gram": col_bytes * acc["pair_checks"],
+                 "jacobi_eig": 0.0,
+                 "jacobi_rotate": 2 * col_bytes * acc["rotations"]}
     rep = {}
     for k, name in enumerate(KERNELS):
         ms = acc["kernel_ms"][k]
@@ -168,6 +175,7 @@ def kernel_report(acc, np_pad, precision, steps):
             "bound": bound,
             "peak_tflops": peak,
             "frac": round(tf / peak, 4) if tf else None,
+            "alg_bytes_per_launch": round(alg_bytes[name] / launches) if launches else None,
         }
     return rep
 
@@ -287,7 +295,8 @@ def load_traffic(kernel: str, workload: str, precision: str):
         return None
     if t.get("source_sha1") != kernel_source_hash():
         return None
-    return t.get("kernels", {}).get(f"{workload}/{precision}/{kernel}")
+    e = t.get("kernels", {}).get(f"{workload}/{precision}/{kernel}")
+    return e["bytes_per_launch"] if e else None
 
 
 def main():
@@ -399,6 +408,7 @@ def main():
             "traffic": load_traffic(dom, args.workload, main_form),
             "avg_launch_us": kd["avg_launch_us"],
             "launches": kd["launches"],
+            "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
         },
     }
     for f, (r, _) in results.items():
