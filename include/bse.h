@@ -47,9 +47,20 @@ extern "C" {
 /* Route: Alg. 3 (CHOL+SVD: chol(A+B), chol(A-B), SVD of L2^H L1) or
  * Alg. 2 (CHOL: chol(A-B), Hermitian eigenproblem of L^H (A+B) L). */
 enum { BSE_ROUTE_SVD = 0, BSE_ROUTE_EIG = 1 };
-/* Arithmetic: plain FP64 throughout, or complex64 bulk work on FP32 MFMA
- * with FP64 diagonal Cholesky blocks and an FP64 residual-based refinement. */
-enum { BSE_PREC_FP64 = 0, BSE_PREC_MIXED = 1 };
+/* Arithmetic:
+ *   FP64          plain FP64 throughout;
+ *   MIXED         complex64 bulk work (Cholesky, W, Jacobi, back-transform)
+ *                 on FP32 MFMA with FP64 diagonal Cholesky blocks, then an
+ *                 FP64 residual-based refinement of the eigenpairs and FP64
+ *                 Rayleigh quotients;
+ *   MIXED_POLISH  FP64 Cholesky factors and W (a few percent of the work),
+ *                 the bulk of the one-sided Jacobi iteration in complex64 on
+ *                 FP32 MFMA, then the accumulated complex64 rotation
+ *                 V = W^-1 (W V) recovered by two FP64 triangular solves,
+ *                 made unitary in FP64 (Cholesky QR), and FP64 Jacobi sweeps
+ *                 on W V until FP64 convergence; results carry the FP64
+ *                 form's accuracy.  SVD route only. */
+enum { BSE_PREC_FP64 = 0, BSE_PREC_MIXED = 1, BSE_PREC_MIXED_POLISH = 2 };
 
 typedef struct {
   int route;          /* BSE_ROUTE_*                                            */
@@ -95,6 +106,17 @@ typedef struct {
   int refine_steps_done; /* mixed: refinement steps run                       */
   double inner_rotations; /* 2 x 2 rotations applied inside the block-pair
                              eigensolvers, over all sweeps                    */
+  /* MIXED_POLISH: the fields above describe the complex64 iteration; these
+   * the FP64 sweeps that follow it. */
+  int polish_sweeps;
+  int polish_rotations;
+  int polish_pair_checks;
+  int polish_reserved;
+  double polish_max_off;
+  double polish_inner_rotations;
+  double polish_kernel_ms[3];
+  int polish_kernel_launches[3];
+  int polish_reserved2;
 } bse_info_t;
 
 /* Fill `opts` with the defaults (route SVD, FP64, lower triangles). */
@@ -138,7 +160,8 @@ size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* op
  * and the Jacobi sweeps of all problems advance together (one host readback
  * per sweep; a problem that has converged skips the remaining sweeps).  The
  * results of each problem are those bse_solve_h1 computes with the same
- * opts and tile table.  Alg. 2 route: the problems run one after another.
+ * opts and tile table.  Alg. 2 route and the MIXED_POLISH precision: the
+ * problems run one after another.
  * info[0].timing requests timing (as for bse_solve_h1); ms_phase then holds
  * the phase times of the whole batch in every entry. */
 int bse_solve_batched(int batch, const int* n,

@@ -24,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbse.so")
 
 ROUTES = {"svd": 0, "eig": 1}
-PRECISIONS = {"fp64": 0, "mixed": 1}
+PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_polish": 2}
 
 
 class BSEOpts(ctypes.Structure):
@@ -58,6 +58,15 @@ class BSEInfo(ctypes.Structure):
         ("kernel_launches", ctypes.c_int * 3),
         ("refine_steps_done", ctypes.c_int),
         ("inner_rotations", ctypes.c_double),
+        ("polish_sweeps", ctypes.c_int),
+        ("polish_rotations", ctypes.c_int),
+        ("polish_pair_checks", ctypes.c_int),
+        ("polish_reserved", ctypes.c_int),
+        ("polish_max_off", ctypes.c_double),
+        ("polish_inner_rotations", ctypes.c_double),
+        ("polish_kernel_ms", ctypes.c_double * 3),
+        ("polish_kernel_launches", ctypes.c_int * 3),
+        ("polish_reserved2", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -74,6 +83,13 @@ class BSEInfo(ctypes.Structure):
             "kernel_launches": list(self.kernel_launches),
             "refine_steps_done": self.refine_steps_done,
             "inner_rotations": self.inner_rotations,
+            "polish_sweeps": self.polish_sweeps,
+            "polish_rotations": self.polish_rotations,
+            "polish_pair_checks": self.polish_pair_checks,
+            "polish_max_off": self.polish_max_off,
+            "polish_inner_rotations": self.polish_inner_rotations,
+            "polish_kernel_ms": list(self.polish_kernel_ms),
+            "polish_kernel_launches": list(self.polish_kernel_launches),
         }
 
 

@@ -304,6 +304,132 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   return ret;
 }
 
+// Mixed form with an FP64 Jacobi polish (BSE_PREC_MIXED_POLISH).
+//   1. M1, M2, their FP64 Cholesky factors and W = L2^H L1 in FP64.
+//   2. One-sided Jacobi on a complex64 copy of W (FP32 MFMA) to the FP32
+//      tolerance: Z = W32 V32 with V32 the product of the applied rotations.
+//   3. V' = W^-1 Z = L1^-1 (L2^-H Z) by two FP64 block triangular solves;
+//      V' is unitary up to the complex64 rounding of the iteration.
+//   4. Cholesky QR in FP64: V'^H V' = L_G L_G^H and V = V' L_G^-H is unitary
+//      to FP64 rounding, so W V = Z L_G^-H has exactly the singular values
+//      of W and nearly orthogonal columns.
+//   5. FP64 Jacobi sweeps on W V, which start in the quadratically convergent
+//      regime, until no pair exceeds the FP64 tolerance; then the FP64
+//      form's finalisation (Rayleigh quotients, back-transform, assembly).
+int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
+                 int ldx, char* base, const Plan& p, const bse_opts_t& o, bse_info_t* info,
+                 int want_timing, hipStream_t s) {
+  const int np = p.np;
+  const long ld = np;
+  double2* M1 = reinterpret_cast<double2*>(base + p.off_m1);
+  double2* M2 = reinterpret_cast<double2*>(base + p.off_m2);
+  double2* W = reinterpret_cast<double2*>(base + p.off_w);
+  double2* Y = reinterpret_cast<double2*>(base + p.off_y);
+  double2* X1 = reinterpret_cast<double2*>(base + p.off_x1);
+  double2* X2 = reinterpret_cast<double2*>(base + p.off_x2);
+  float2* Wc = reinterpret_cast<float2*>(base + p.off_x1);
+  double2* inv = reinterpret_cast<double2*>(base + p.off_inv);
+  double2* linv = reinterpret_cast<double2*>(base + p.off_linv);
+  double* sigma = reinterpret_cast<double*>(base + p.off_sigma);
+  int* perm = reinterpret_cast<int*>(base + p.off_perm);
+  double* invlam = reinterpret_cast<double*>(base + p.off_invlam);
+  double* bnorm = reinterpret_cast<double*>(base + p.off_bnorm);
+  double* anorm = reinterpret_cast<double*>(base + p.off_anorm);
+  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
+  double* scl = reinterpret_cast<double*>(base + p.off_scl);
+  int* status = reinterpret_cast<int*>(base + p.off_status);
+  JacobiWork jw32, jw64;
+  jacobi_carve(np, sizeof(float), base + p.off_jac, jw32, p.kc, p.rrows);
+  jacobi_carve(np, sizeof(double), base + p.off_jac, jw64, p.kc, p.rrows);
+  const int upper = (o.uplo == 'U' || o.uplo == 'u');
+  const double nn = (double)(n > 64 ? n : 64);
+  const double eps32 = 1.1920928955078125e-07, eps64 = 2.220446049250313e-16;
+  const int max32 = o.max_sweeps > 0 ? o.max_sweeps : 20;
+  const double tol32 = 4.0 * sqrt(nn) * eps32;
+  const double tol64 = o.jacobi_tol > 0.0 ? o.jacobi_tol : nn * eps64;
+
+  Timer tm(want_timing != 0, s);
+  const int slots[8] = {0, 1, 2, 3, 6, 4, 5, -1};
+  tm.mark();
+  const int big = 0x7fffffff;
+  BSE_TRY(hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, s));
+  if (int e = form_and_check_args(n, A, lda, B, ldb, upper, base, p, s)) return e;
+  tm.mark();
+  BSE_TRY(cholesky_z(np, n, M1, ld, linv, status, 0, s));
+  BSE_TRY(cholesky_z(np, n, M2, ld, linv, status, n, s));
+  if (int st = read_status(status, n, info, s)) return st;
+  tm.mark();
+  {
+    GemmDesc g = tri_gemm(np, ld, M2, 1, M1, 0, 1, W);  // W = L2^H L1
+    g.mask = n;
+    BSE_TRY(gemm_z(g, s));
+    BSE_TRY(z_to_c64(np, W, ld, Wc, s));
+  }
+  tm.mark();
+  JacobiResult j32;
+  BSE_TRY(jacobi_c(np, Wc, ld, jw32, tol32, 1.0e-5, max32, j32, s, want_timing >= 2));
+  tm.mark();
+  // Z = W32 V32 in FP64 (Y); V' = L1^-1 L2^-H Z (W)
+  BSE_TRY(c64_to_c128(np, Wc, ld, Y, ld, nullptr, s));
+  BSE_TRY(hipMemcpyAsync(W, Y, (size_t)np * np * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  BSE_TRY(trsm_lh_z(np, M2, ld, W, X1, inv, s));    // X1 = L2^-H Z   (W is overwritten)
+  BSE_TRY(trsm_ln_z(np, M1, ld, X1, W, inv, s));    // W  = L1^-1 X1 = V'
+  {
+    GemmDesc g;  // G = V'^H V' (lower tiles)
+    g.M = np; g.N = np; g.K = np;
+    g.A = W; g.lda = ld; g.opA = 1;
+    g.B = W; g.ldb = ld; g.opB = 0;
+    g.C = X2; g.ldc = ld;
+    g.lowerC = 1;
+    BSE_TRY(gemm_z(g, s));
+  }
+  BSE_TRY(tri_pad_z(n, np, X2, ld, 0, s));
+  BSE_TRY(cholesky_z(np, n, X2, ld, linv, status, 0, s));  // G = L_G L_G^H
+  BSE_TRY(tri_pad_z(n, np, X1, ld, 1, s));
+  BSE_TRY(trsm_ln_z(np, X2, ld, X1, W, inv, s));    // W = L_G^-1 (X1 = I is overwritten)
+  {
+    GemmDesc g;  // W V = Z L_G^-H (Y)  ->  X1
+    g.M = np; g.N = np; g.K = np;
+    g.A = Y; g.lda = ld; g.opA = 0;
+    g.B = W; g.ldb = ld; g.opB = 1; g.triB = 1;
+    g.C = X1; g.ldc = ld;
+    BSE_TRY(gemm_z(g, s));
+  }
+  JacobiResult j64;
+  const double first = fmin(1.0e-3, fmax(1.0e-10, 0.3 * j32.max_off));
+  BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, want_timing >= 2, first));
+  tm.mark();
+  BSE_TRY(scale_singular_cols_z(n, np, X1, ld, sigma, bnorm, s));  // Ws = (W V Q) sigma^-3/2
+  tm.mark();
+  BSE_TRY(gemm_z(tri_gemm(np, ld, M2, 0, X1, 0, 0, Y), s));       // V2 = L2 Ws
+  BSE_TRY(gemm_z(tri_gemm(np, ld, M1, 1, Y, 0, 0, W), s));        // T = L1^H V2
+  BSE_TRY(rq_lambda_z(n, np, W, ld, bnorm, anorm, lamu, invlam, scl, perm, lambda,
+                      o.want_negative, s));
+  {
+    GemmDesc v = tri_gemm(np, ld, M1, 0, W, 0, 0, M2);            // V1 = L1 T Lambda^-1
+    v.colscale = invlam;
+    BSE_TRY(gemm_z(v, s));
+  }
+  BSE_TRY(assemble_z(n, M2, Y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
+  tm.mark();
+  BSE_TRY(hipStreamSynchronize(s));
+  const int ret = (j32.sweeps > 0 && j64.converged) ? 0 : 2 * n + 1;
+  fill_info(info, ret, j32);
+  if (info) {
+    info->polish_sweeps = j64.sweeps;
+    info->polish_rotations = j64.rotations;
+    info->polish_pair_checks = j64.pair_checks;
+    info->polish_max_off = j64.max_off;
+    info->polish_inner_rotations = j64.inner_rotations;
+    for (int i = 0; i < 3; ++i) {
+      info->polish_kernel_ms[i] = j64.kernel_ms[i];
+      info->polish_kernel_launches[i] = j64.kernel_launches[i];
+    }
+  }
+  tm.fill(info, slots);
+  return ret;
+}
+
 }  // namespace
 
 extern "C" {
@@ -352,6 +478,7 @@ int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb, double* 
   char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
   if (p.alg2) return solve_alg2(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
   if (p.mixed) return solve_mixed(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  if (p.polish) return solve_polish(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
   return solve_fp64(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
 }
 
@@ -367,7 +494,8 @@ size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* op
     const size_t b = bse_workspace_bytes(n[i], &o);
     if (b > mx) mx = b;
   }
-  if (o.route == BSE_ROUTE_EIG) return mx;  // Alg. 2: problems one after another
+  // Alg. 2 and the polished mixed form: problems one after another
+  if (o.route == BSE_ROUTE_EIG || o.precision == BSE_PREC_MIXED_POLISH) return mx;
   return batched_workspace(batch, n, o);
 }
 
@@ -405,7 +533,7 @@ int bse_solve_batched(int batch, const int* n, const void* const* A, const int* 
       info[i].timing = want_timing;
     }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (o.route != BSE_ROUTE_EIG)
+  if (o.route != BSE_ROUTE_EIG && o.precision != BSE_PREC_MIXED_POLISH)
     return solve_batched_grouped(batch, n, A, lda, B, ldb, lambda, X, ldx, work, o, info,
                                  want_timing, s);
   int first = 0;

@@ -278,7 +278,51 @@ BSE_DEV void ToC64Op::run(const ToC64Args& a, int bx, int) {
   }
 }
 
+// complex64 copy of a whole np x np matrix, one 64 x 64 tile per workgroup.
+struct ZToCOp {
+  static constexpr int NT = 256;
+  typedef ToC64Args Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int T = a.np / 64;
+    const int m0 = (bx % T) * 64, n0 = (bx / T) * 64;
+    for (int q = 0; q < 16; ++q) {
+      const int i = m0 + (threadIdx.x & 63), j = n0 + (threadIdx.x >> 6) + 4 * q;
+      const double2 x = a.M[i + (long)j * a.ld];
+      a.Mc[i + (long)j * a.ld] = make_float2((float)x.x, (float)x.y);
+    }
+  }
+};
+
+// Lower triangle of a Hermitian n x n matrix embedded in np x np: strict
+// upper part set to zero, rows and columns n..np-1 set to the identity's.
+// mode 1 instead writes the np x np identity.
+struct TriPadArgs { int n, np; double2* M; long ld; int identity; };
+struct TriPadOp {
+  static constexpr int NT = 256;
+  typedef TriPadArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int T = a.np / 64;
+    const int m0 = (bx % T) * 64, n0 = (bx / T) * 64;
+    for (int q = 0; q < 16; ++q) {
+      const int i = m0 + (threadIdx.x & 63), j = n0 + (threadIdx.x >> 6) + 4 * q;
+      double2* p = a.M + i + (long)j * a.ld;
+      if (a.identity || i < j || i >= a.n || j >= a.n)
+        *p = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+  }
+};
+
 }  // namespace
+
+hipError_t z_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream_t s) {
+  const ToC64Args a = {np, M, ld, Mc};
+  return launch_one<ZToCOp>(a, tiles64(np), 0, s);
+}
+
+hipError_t tri_pad_z(int n, int np, double2* M, long ld, int identity, hipStream_t s) {
+  const TriPadArgs a = {n, np, M, ld, identity};
+  return launch_one<TriPadOp>(a, tiles64(np), 0, s);
+}
 
 hipError_t form_m12(int n, int np, const double2* A, long lda, const double2* B, long ldb,
                     int upper, double2* M1, double2* M2, long ldm, hipStream_t s) {
@@ -352,6 +396,33 @@ hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
     u.A = L + (long)i * NB; u.lda = ld; u.opA = 1;
     u.B = Z + (long)i * NB; u.ldb = ld; u.opB = 0;
     u.C = Rhs; u.ldc = ld;
+    u.alpha_re = -1.0; u.beta_re = 1.0;
+    if ((e = gemm_z(u, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
+                     hipStream_t s) {
+  const int nb = np / NB;
+  k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < nb; ++i) {
+    // Z_i = L_ii^-1 Rhs_i
+    GemmDesc g;
+    g.M = NB; g.N = np; g.K = NB;
+    g.A = inv + (long)i * NB * NB; g.lda = NB; g.opA = 0; g.triA = 1;
+    g.B = Rhs + (long)i * NB; g.ldb = ld; g.opB = 0;
+    g.C = Z + (long)i * NB; g.ldc = ld;
+    if ((e = gemm_z(g, s)) != hipSuccess) return e;
+    if (i == nb - 1) break;
+    // Rhs_{i+1..} -= L_{i+1.., i} Z_i
+    GemmDesc u;
+    u.M = np - (i + 1) * NB; u.N = np; u.K = NB;
+    u.A = L + (long)(i + 1) * NB + (long)i * NB * ld; u.lda = ld; u.opA = 0;
+    u.B = Z + (long)i * NB; u.ldb = ld; u.opB = 0;
+    u.C = Rhs + (long)(i + 1) * NB; u.ldc = ld;
     u.alpha_re = -1.0; u.beta_re = 1.0;
     if ((e = gemm_z(u, s)) != hipSuccess) return e;
   }

@@ -79,8 +79,11 @@ struct JacobiResult {
 
 // One-sided block-Jacobi on the np columns of W (np % 64 == 0), in place:
 // on return the columns of W are mutually orthogonal (W_in Q = W_out, Q unitary).
+// first_stop: inner stopping level of the first sweep (later sweeps follow
+// the previous sweep's largest off-diagonal measure, at most 1e-3).
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false);
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false,
+                    double first_stop = 1.0e-3);
 // complex64 columns; Gram partial sums, inner eigensolver and rotations as in
 // jacobi_z (inner eigensolver in FP64), inner iteration ending once a sweep's
 // largest relative off-diagonal entry is below inner_stop.
@@ -93,6 +96,14 @@ hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int*
 // substitution with the inverses of the 64 x 64 diagonal blocks (inv holds
 // np * 64 complex values) and MFMA GEMM updates; Rhs is overwritten.
 hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
+                     hipStream_t s);
+// complex64 copy of all np x np entries.
+hipError_t z_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream_t s);
+// identity == 0: zero the strict upper triangle of M and give rows/columns
+// n..np-1 those of the identity; identity != 0: M = I (np x np).
+hipError_t tri_pad_z(int n, int np, double2* M, long ld, int identity, hipStream_t s);
+// Z = L^-1 Rhs (forward block substitution, same conventions as trsm_lh_z).
+hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s);
 // M[i][j] = conj(M[j][i]) for i < j (np % 64 == 0).
 hipError_t mirror_upper_z(int np, double2* M, long ld, hipStream_t s);

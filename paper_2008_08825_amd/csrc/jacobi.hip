@@ -589,7 +589,7 @@ RotArgs<C2> make_rot(int np, C2* W, long ld, const JacobiWork& w, const int* don
 template <typename T>
 static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const JacobiWork& w,
                              double tol, double inner_stop, int max_sweeps, JacobiResult& res,
-                             hipStream_t s, bool time_kernels) {
+                             hipStream_t s, bool time_kernels, double first_stop = 1.0e-3) {
   typedef typename cpx_t<T>::type C2;
   const int N = np / JB, pairs = N / 2;
   const int gblocks = jacobi_gram_blocks_kc(np, w.kc);
@@ -624,7 +624,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
   const bool adaptive = getenv("BSE_FIXED_INNER") == nullptr;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double sstop = inner_stop;
-    if (adaptive) sstop = fmax(inner_stop, prev_off < 0.0 ? 1.0e-3 : fmin(1.0e-3, 0.3 * prev_off));
+    if (adaptive) sstop = fmax(inner_stop, fmin(1.0e-3, prev_off < 0.0 ? first_stop : 0.3 * prev_off));
     ea.inner_stop2 = sstop * sstop;
     e = hipMemsetAsync(w.counter, 0, 128, s);
     if (e != hipSuccess) { ret = e; break; }
@@ -676,8 +676,9 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
 }
 
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels) {
-  return jacobi_run<double>(np, W, ld, w, tol, 1.0e-10, max_sweeps, res, s, time_kernels);
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels,
+                    double first_stop) {
+  return jacobi_run<double>(np, W, ld, w, tol, 1.0e-10, max_sweeps, res, s, time_kernels, first_stop);
 }
 
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,

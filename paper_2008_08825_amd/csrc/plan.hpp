@@ -33,11 +33,15 @@ struct Plan {
   size_t off_jac = 0;
   size_t total = 0;
   int kc = 0, rrows = 0;  // Jacobi tiles (0 = built-in)
+  int polish = 0;
 };
 
 inline bool opts_valid(const bse_opts_t& o) {
   if (o.route != BSE_ROUTE_SVD && o.route != BSE_ROUTE_EIG) return false;
-  if (o.precision != BSE_PREC_FP64 && o.precision != BSE_PREC_MIXED) return false;
+  if (o.precision != BSE_PREC_FP64 && o.precision != BSE_PREC_MIXED &&
+      o.precision != BSE_PREC_MIXED_POLISH)
+    return false;
+  if (o.precision == BSE_PREC_MIXED_POLISH && o.route != BSE_ROUTE_SVD) return false;
   if (o.max_sweeps < 0 || o.refine_steps < 0 || o.refine_steps > 8 || !(o.jacobi_tol >= 0.0))
     return false;
   if (o.route == BSE_ROUTE_EIG && o.precision != BSE_PREC_FP64) return false;  // Alg. 2: FP64 only
@@ -74,6 +78,7 @@ inline Plan make_plan(int n, const bse_opts_t& o) {
   p.n = n;
   p.np = pad64(n > 0 ? n : 1);
   p.mixed = o.precision == BSE_PREC_MIXED;
+  p.polish = o.precision == BSE_PREC_MIXED_POLISH;
   pick_tiles(o, p.np, &p.kc, &p.rrows);
   p.alg2 = o.route == BSE_ROUTE_EIG;
   const size_t U = (size_t)p.np * p.np * sizeof(double2);
@@ -89,6 +94,12 @@ inline Plan make_plan(int n, const bse_opts_t& o) {
     p.off_w = take(U);
     p.off_y = take(U);
     p.off_z = take(U);
+    p.off_inv = take((size_t)p.np * 64 * sizeof(double2));
+  } else if (p.polish) {
+    p.off_w = take(U);
+    p.off_y = take(U);
+    p.off_x1 = take(U);  // complex64 W during the FP32 iteration, then solve results
+    p.off_x2 = take(U);  // Gram of the recovered rotation, its factor and inverse
     p.off_inv = take((size_t)p.np * 64 * sizeof(double2));
   } else if (!p.mixed) {
     p.off_w = take(U);

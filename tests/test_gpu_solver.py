@@ -279,3 +279,31 @@ def test_alg2_mixed_is_rejected(gpu_lib):
     with pytest.raises(gpu_lib.BSEError):
         gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV),
                          route="eig", precision="mixed")
+
+
+# ---------------------------------------------------------------- mixed form with FP64 Jacobi polish
+@pytest.mark.parametrize("n", [1, 5, 64, 100, 200])
+def test_mixed_polish_parity(gpu_lib, n):
+    """complex64 Jacobi + FP64 polish: the FP64 form's bars (eigenvalues, vectors, residual)."""
+    A, B = inputs.coupled(n, seed=700 + n)
+    lam, X, info = run(gpu_lib, A, B, precision="mixed_polish", want_negative=True)
+    check_against_oracle(A, B, lam, X)
+    assert np.array_equal(lam[n:], -lam[:n])
+    assert info["polish_sweeps"] >= 1 and info["sweeps"] >= 1
+
+
+def test_mixed_polish_n256_workload(gpu_lib):
+    A, B = inputs.workload("n256")
+    lam, X, info = run(gpu_lib, A, B, precision="mixed_polish")
+    check_against_oracle(A, B, lam, X)
+
+
+def test_mixed_polish_status_and_route(gpu_lib):
+    A, B = inputs.coupled(40, seed=71)
+    Bbad = B.copy()
+    Bbad[10, 10] = A[10, 10] + 1.0  # (A - B)[10, 10] < 0
+    lam, X, info = run(gpu_lib, A, Bbad, precision="mixed_polish", check=False)
+    assert info["status"] == ob.chol_status(A, Bbad) and info["status"] > 0
+    with pytest.raises(Exception):
+        gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV),
+                         route="eig", precision="mixed_polish")
