@@ -136,10 +136,12 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
 // ---------------------------------------------------------------- inner eigensolver
 // Eigenvectors of the pair's 64 x 64 Gram by parallel cyclic Jacobi, in FP64.
 // Each step applies 32 disjoint rotations chosen by the circle method on the
-// 64 indices: first the rotation parameters, then every 2 x 2 block of G is
-// replaced by J_P^H G_PQ J_Q (P <= Q, mirrored for P > Q) and the rotated
-// column pairs of R by R J.  G and R hold complex values as double2 (one
-// 16-byte LDS access per entry); EIG_THREADS threads share the updates.
+// 64 indices: the rotation parameters (which also give the rotated diagonal
+// 2 x 2 blocks), then every off-diagonal 2 x 2 block of G is replaced by
+// J_P^H G_PQ J_Q (P < Q), and the rotated column pairs of R by R J, the
+// last overlapped with the next step's parameters.  G keeps only its lower
+// triangle (and diagonal) up to date; G and R hold complex values as double2
+// (one 16-byte LDS access per entry).  The kernel is bound by LDS traffic.
 constexpr int EIG_THREADS = 512;
 
 template <typename T>
@@ -166,19 +168,21 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   (void)N; (void)t;
   __shared__ double2 G[JP][JP + LPAD];
   __shared__ double2 R[JP][JP + LPAD];
-  __shared__ double4 prm[32];   // (c, Re s, Im s, unused) of rotation m
-  __shared__ double2 pdg[32];   // new diagonal (d_i, d_j)
-  __shared__ int pidx[32];      // i | j << 8 | rotate << 16
+  __shared__ double4 prm[2][32];  // (c, Re s, Im s, unused) of rotation m, two steps
+  __shared__ int pidx[2][32];     // i | j << 8 | rotate << 16
   __shared__ double red[NT];
-  __shared__ unsigned short blkPQ[528];
   __shared__ int nrot;
   __shared__ int sweepbig;
   const int tid = threadIdx.x;
   const int k = bx;
-  // (P, Q) of the 528 pairs of rotation slots with P <= Q, as P | Q << 8
-  for (int Q = 0, b = 0; Q < 32; ++Q)
-    for (int P = 0; P <= Q; ++P, ++b)
-      if ((b % NT) == tid) blkPQ[b] = (unsigned short)(P | (Q << 8));
+  // (P, Q), P < Q, of this thread's off-diagonal 2 x 2 block (threads 0..495):
+  // thread b holds the b-th pair in the order Q = 1..31, P = 0..Q-1.
+  int bP = 0, bQ = 1;
+  {
+    int b = tid < 496 ? tid : 0;
+    while (b >= bQ) { b -= bQ; ++bQ; }
+    bP = b;
+  }
 
   // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian matrix.
   for (int e = tid; e < NTILE * 256; e += NT) {
@@ -237,21 +241,46 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   const double stop2 = inner_stop2;
   int sweeps_done = 0;
   int applied = 0;  // rotations applied by this lane (lanes 0..31)
+  int gstep = 0;    // steps run so far; parameters of step g sit in buffer g & 1
+  // R <- R J for the rotations of the step in buffer b: rows r, rotations m0, m0 + dm, ...
+  auto apply_r = [&](int b, int r, int m0, int dm) {
+    for (int m = m0; m < 32; m += dm) {
+      const int xm = pidx[b][m];
+      if (xm >> 16) {
+        const int i = xm & 255, j = (xm >> 8) & 255;
+        const double4 pp = prm[b][m];
+        const double c = pp.x;
+        const double2 sv = make_double2(pp.y, pp.z);
+        const double2 ri = R[r][i];
+        const double2 rj = R[r][j];
+        R[r][i] = csub(cscale(ri, c), cmul(cconj(sv), rj));
+        R[r][j] = cadd(cmul(sv, ri), cscale(rj, c));
+      }
+    }
+  };
+  // Each step runs in two phases separated by barriers:
+  //   A: lanes 0..31 of wave 0 compute the step's 32 rotations from G and
+  //      write the rotated diagonal 2 x 2 blocks (each lane touches only its
+  //      own pair's entries); meanwhile waves 1..7 apply the previous step's
+  //      rotations to R (double-buffered parameters), off the critical path;
+  //   B: the 496 off-diagonal 2 x 2 blocks G_PQ <- J_P^H G_PQ J_Q, one per
+  //      thread.
   for (int sweep = 0; sweep < max_inner; ++sweep) {
     int big = 0;
     int anyrot = 0;
-    for (int step = 0; step < JP - 1; ++step) {
+    for (int step = 0; step < JP - 1; ++step, ++gstep) {
+      const int cur = gstep & 1;
       if (tid < 32) {
         const int a = tid, b = JP - 1 - tid;
         int i = (a == 0) ? 0 : ((a - 1 + step) % (JP - 1)) + 1;
         int j = ((b - 1 + step) % (JP - 1)) + 1;
         if (i > j) { const int tmp = i; i = j; j = tmp; }
         const double aa = G[i][i].x, dd = G[j][j].x;
-        const double2 cc = G[i][j];
+        const double2 cc = cconj(G[j][i]);  // G[i][j], from the stored lower triangle
         const double cre = cc.x, cim = cc.y;
         const double ac2 = cre * cre + cim * cim;
         int rot = 0;
-        double cs = 1.0, sr = 0.0, si = 0.0, di = aa, dj = dd;
+        double cs = 1.0, sr = 0.0, si = 0.0;
         const double add = fabs(aa * dd);
         if (ac2 > stop2 * add) big = 1;
         if (ac2 > tol_in2 * add && ac2 > 0.0) {
@@ -271,88 +300,61 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
           const double sn = tt * cs;
           sr = sn * cre * inv_ac;
           si = sn * cim * inv_ac;
-          di = aa - tt * ac;
-          dj = dd + tt * ac;
+          G[i][i] = make_double2(aa - tt * ac, 0.0);
+          G[j][j] = make_double2(dd + tt * ac, 0.0);
+          G[j][i] = make_double2(0.0, 0.0);
         }
         if (rot) { anyrot = 1; ++applied; }
-        pidx[tid] = i | (j << 8) | (rot << 16);
-        prm[tid] = make_double4(cs, sr, si, 0.0);
-        pdg[tid] = make_double2(di, dj);
+        pidx[cur][tid] = i | (j << 8) | (rot << 16);
+        prm[cur][tid] = make_double4(cs, sr, si, 0.0);
+      } else if (tid >= 64 && gstep > 0) {
+        const int t7 = tid - 64;
+        apply_r(cur ^ 1, t7 & 63, t7 >> 6, (NT - 64) / 64);
       }
       __syncthreads();
-      // 2 x 2 blocks (P, Q), P <= Q: 528 of them.
-#pragma unroll
-      for (int u = 0; u < (528 + NT - 1) / NT; ++u) {
-        const int blk = tid + NT * u;
-        if (blk < 528) {
-          const int pq = blkPQ[blk];
-          const int P = pq & 255, Q = pq >> 8;
-          const int xP = pidx[P], xQ = pidx[Q];
-          const int rP = xP >> 16, rQ = xQ >> 16;
-          if (rP | rQ) {
-            const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
-            if (P == Q) {
-              const double2 dg = pdg[P];
-              G[iP][iP] = make_double2(dg.x, 0.0);
-              G[jP][jP] = make_double2(dg.y, 0.0);
-              G[iP][jP] = make_double2(0.0, 0.0);
-              G[jP][iP] = make_double2(0.0, 0.0);
-            } else {
-              double2 g00 = G[iP][iQ];
-              double2 g01 = G[iP][jQ];
-              double2 g10 = G[jP][iQ];
-              double2 g11 = G[jP][jQ];
-              if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
-                const double4 pp = prm[Q];
-                const double c = pp.x;
-                const double2 sq = make_double2(pp.y, pp.z);
-                const double2 sqc = cconj(sq);
-                const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
-                const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
-                const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
-                const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
-                g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-              }
-              if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
-                const double4 pp = prm[P];
-                const double c = pp.x;
-                const double2 sp = make_double2(pp.y, pp.z);
-                const double2 spc = cconj(sp);
-                const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
-                const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
-                const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
-                const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
-                g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-              }
-              G[iP][iQ] = g00;
-              G[iP][jQ] = g01;
-              G[jP][iQ] = g10;
-              G[jP][jQ] = g11;
-              G[iQ][iP] = cconj(g00);
-              G[jQ][iP] = cconj(g01);
-              G[iQ][jP] = cconj(g10);
-              G[jQ][jP] = cconj(g11);
-            }
-          }
-        }
-      }
-      // R <- R J for the rotated column pairs: row r, rotations m = (tid / 64) + (NT / 64) u
-      {
-        const int r = tid & 63;
-#pragma unroll
-        for (int u = 0; u < 32 / (NT / 64); ++u) {
-          const int m = (tid >> 6) + (NT / 64) * u;
-          const int xm = pidx[m];
-          if (xm >> 16) {
-            const int i = xm & 255, j = (xm >> 8) & 255;
-            const double4 pp = prm[m];
+      if (tid < 496) {
+        const int P = bP, Q = bQ;
+        const int xP = pidx[cur][P], xQ = pidx[cur][Q];
+        const int rP = xP >> 16, rQ = xQ >> 16;
+        if (rP | rQ) {
+          const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
+          // G holds its lower triangle only: entry (r, c) is G[r][c] for r > c
+          // and conj(G[c][r]) otherwise (r != c: the index sets are disjoint)
+          double2* p00 = iP > iQ ? &G[iP][iQ] : &G[iQ][iP];
+          double2* p01 = iP > jQ ? &G[iP][jQ] : &G[jQ][iP];
+          double2* p10 = jP > iQ ? &G[jP][iQ] : &G[iQ][jP];
+          double2* p11 = jP > jQ ? &G[jP][jQ] : &G[jQ][jP];
+          double2 g00 = *p00, g01 = *p01, g10 = *p10, g11 = *p11;
+          if (iP < iQ) g00 = cconj(g00);
+          if (iP < jQ) g01 = cconj(g01);
+          if (jP < iQ) g10 = cconj(g10);
+          if (jP < jQ) g11 = cconj(g11);
+          if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
+            const double4 pp = prm[cur][Q];
             const double c = pp.x;
-            const double2 sv = make_double2(pp.y, pp.z);
-            const double2 ri = R[r][i];
-            const double2 rj = R[r][j];
-            R[r][i] = csub(cscale(ri, c), cmul(cconj(sv), rj));
-            R[r][j] = cadd(cmul(sv, ri), cscale(rj, c));
+            const double2 sq = make_double2(pp.y, pp.z);
+            const double2 sqc = cconj(sq);
+            const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
+            const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
+            const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
+            const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
+            g00 = t00; g01 = t01; g10 = t10; g11 = t11;
           }
+          if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
+            const double4 pp = prm[cur][P];
+            const double c = pp.x;
+            const double2 sp = make_double2(pp.y, pp.z);
+            const double2 spc = cconj(sp);
+            const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
+            const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
+            const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
+            const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
+            g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+          }
+          *p00 = iP > iQ ? g00 : cconj(g00);
+          *p01 = iP > jQ ? g01 : cconj(g01);
+          *p10 = jP > iQ ? g10 : cconj(g10);
+          *p11 = jP > jQ ? g11 : cconj(g11);
         }
       }
       __syncthreads();
@@ -370,6 +372,9 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
     if (nrot == 0 || sweepbig == 0) break;
     __syncthreads();
   }
+  // the last step's rotations, still pending on R
+  if (gstep > 0) apply_r((gstep - 1) & 1, tid & 63, tid >> 6, NT / 64);
+  __syncthreads();
   if (tid == 0) atomicAdd(inner_count, sweeps_done);
   if (tid < 64) {
     int a = applied;
