@@ -68,16 +68,20 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
   const int k = bx / kc, c = bx % kc;
   int p, q;
   round_pair(N, t, k, p, q);
-  // tiles of this wave: 3, 3, 2, 2
-  const int tfirst = wave < 2 ? 3 * wave : 6 + 2 * (wave - 2);
-  const int tcount = wave < 2 ? 3 : 2;
+  // Work of a 16-row step: ten tiles x four k-steps, split evenly over the
+  // four waves (one per SIMD): wave w takes tiles 2w and 2w + 1 whole and
+  // half the k-steps of a shared tile (tile 8 for waves 0, 1; tile 9 for
+  // waves 2, 3; the lower wave of each couple the first two k-steps).  The
+  // two halves of a shared tile are summed through LDS at the end.
+  const int tshared = 8 + (wave >> 1);
+  const int shalf = wave & 1;
   Acc cr[3], ci[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) { cr[i] = Mfma<T>::zero(); ci[i] = Mfma<T>::zero(); }
   int ti[3], tj[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    const int tt = tfirst + (i < tcount ? i : 0);
+    const int tt = i < 2 ? 2 * wave + i : tshared;
     ti[i] = kTileI[tt]; tj[i] = kTileJ[tt];
   }
   const int row_beg = c * rc;
@@ -106,7 +110,7 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
       const int kk = 4 * s + (lane >> 4);
 #pragma unroll
       for (int i = 0; i < 3; ++i) {
-        if (i < tcount) {
+        if (i < 2 || (s >> 1) == shalf) {
           // MFMA A operand: X[kk][16 tj + l%16] (n side); B operand: conj(X[kk][16 ti + l%16]) (m side)
           const T xr_n = Xs[buf][0][kk][16 * tj[i] + (lane & 15)];
           const T xi_n = Xs[buf][1][kk][16 * tj[i] + (lane & 15)];
@@ -118,11 +122,30 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
     }
     buf ^= 1;
   }
+  // shared tiles: the upper wave of each couple hands its half to the lower one
+  __syncthreads();
+  T* hand = &Xs[0][0][0][0];  // 2 couples x 2 (re, im) x 4 registers x 64 lanes fit in Xs
+  if (shalf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      hand[(((wave >> 1) * 2 + 0) * 4 + r) * 64 + lane] = cr[2][r];
+      hand[(((wave >> 1) * 2 + 1) * 4 + r) * 64 + lane] = ci[2][r];
+    }
+  }
+  __syncthreads();
+  if (!shalf) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      cr[2][r] += hand[(((wave >> 1) * 2 + 0) * 4 + r) * 64 + lane];
+      ci[2][r] += hand[(((wave >> 1) * 2 + 1) * 4 + r) * 64 + lane];
+    }
+  }
   // tile element (m_local, n_local) of G = X^H X is stored at m_local + 16 n_local
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    if (i < tcount) {
-      C2* dst = part + ((long)(k * kc + c) * NTILE + tfirst + i) * 256;
+    if (i < 2 || !shalf) {
+      const int tt = i < 2 ? 2 * wave + i : tshared;
+      C2* dst = part + ((long)(k * kc + c) * NTILE + tt) * 256;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int ml = lane & 15, nl = Mfma<T>::drow(lane, r);
