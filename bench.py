@@ -206,19 +206,24 @@ def bench_batched(api, inputs, steps, warmup):
     As = [torch.from_numpy(a).to(dev) for a, _ in probs]
     Bs = [torch.from_numpy(b).to(dev) for _, b in probs]
     del probs
+    from paper_2008_08825_amd import tune
+
+    tiles = tune.packaged()
     flops = sum((98.0 + 2.0 / 3.0) * float(n) ** 3 for n in ns)
     out = {"workload": "256 problems, n uniform in [64, 1024] (seed 0), n=2048 recipe per problem",
-           "sum_n3": sum(float(n) ** 3 for n in ns)}
+           "sum_n3": sum(float(n) ** 3 for n in ns),
+           "tiles": "autotuned table paper_2008_08825_amd/tiles_gfx950.json"}
     lam_by = {}
     for prec in ("mixed", "fp64"):
-        need = api.batched_workspace_bytes(ns, precision=prec)
+        need = api.batched_workspace_bytes(ns, precision=prec, tiles=tiles)
         work = torch.empty(need, dtype=torch.uint8, device=dev)
         for _ in range(warmup):
-            api.solve_batched(As, Bs, precision=prec, work=work, check=False)
+            api.solve_batched(As, Bs, precision=prec, work=work, check=False, tiles=tiles)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
-            res, infos, st = api.solve_batched(As, Bs, precision=prec, work=work, timing=1, check=False)
+            res, infos, st = api.solve_batched(As, Bs, precision=prec, work=work, timing=1, check=False,
+                                               tiles=tiles)
         torch.cuda.synchronize()
         sec = (time.perf_counter() - t0) / steps
         sw = [i["sweeps"] for i in infos]
@@ -234,8 +239,26 @@ def bench_batched(api, inputs, steps, warmup):
         lam_by[prec] = [lam for lam, _ in res]
         log(f"batched {prec}: {sec:.3f}s per batch, status {st}")
         del res, work
-    out["mixed_vs_fp64_max_rel_eig_diff"] = max(
+    out["problems_per_second_mixed"] = round(len(ns) / out["mixed"]["seconds_per_batch"], 1)
+    out["worst_problem_rel_eig_diff_mixed_vs_fp64"] = max(
         ((a - b).abs() / b).max().item() for a, b in zip(lam_by["mixed"], lam_by["fp64"]))
+    # the oracle on a bounded sample of the batch (problems in index order, about 10 s)
+    from oracle import bse as ob
+    t0 = time.perf_counter()
+    done, fl = [], 0.0
+    for i, n in enumerate(ns):
+        A, B = inputs.batch_problem(i, n)
+        ts = time.perf_counter()
+        lam, X = ob.solve_chol_svd(A, B)
+        ob.negative_half(lam, X)
+        fl += (98.0 + 2.0 / 3.0) * float(n) ** 3
+        done.append(n)
+        if time.perf_counter() - t0 > 10.0 or len(done) >= 16:
+            break
+    dt = time.perf_counter() - t0
+    out["cpu_baseline"] = {"value": round(fl / dt / 1e12, 5), "unit": "TFLOP/s (nominal)",
+                           "kind": "oracle", "seconds": round(dt, 2),
+                           "sample": f"problems 0..{len(done) - 1} of the batch (n = {done}), one after another"}
     return out
 
 
@@ -263,10 +286,12 @@ def bench_differentiation(api, inputs, steps, warmup):
         lam, X = api.BSEEig.apply(At, Bt)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        lam.retain_grad()
         L = loss(lam)
         L.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        step.grads = (At.grad, Bt.grad, lam.grad)
         return t1 - t0, t2 - t1, lam.detach(), X
 
     for _ in range(warmup):
@@ -289,6 +314,30 @@ def bench_differentiation(api, inputs, steps, warmup):
     torch.cuda.synchronize()
     adj_ms = e0.elapsed_time(e1) / steps
     adj_flops = 8.0 * n ** 3  # two Hermitian rank-n products, lower halves (4 n^3 real flops each)
+    # directional derivative against a fourth-order central difference of the
+    # eigenvalues, weights frozen at dL/dlambda (the quantity the adjoint maps)
+    GA, GB, w = step.grads
+    gen = torch.Generator(device="cpu").manual_seed(3)
+
+    def herm():
+        Z = torch.randn(n, n, dtype=torch.complex128, generator=gen)
+        return ((Z + Z.mH) * (0.05 / (2.0 * n ** 0.5))).to(dev)
+
+    dA, dB = herm(), herm()
+    h = 1e-3
+    f = []
+    for tt in (-2, -1, 1, 2):
+        lam_t, _, _ = api.solve_h1(A + tt * h * dA, B + tt * h * dB)
+        f.append(float((w * lam_t).sum()))
+    fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+    ad = float((torch.vdot(GA.flatten(), dA.flatten()).real + torch.vdot(GB.flatten(), dB.flatten()).real))
+    # the oracle's forward solve and adjoint on a bounded sample (n = 1024 of the same recipe)
+    from oracle import bse as ob
+    A1, B1 = inputs.workload("n4096", n=1024)
+    t0 = time.perf_counter()
+    lam1, X1 = ob.solve_chol_svd(A1, B1)
+    ob.grad_from_eigenpairs(X1, ob.spectrum_loss_weights(lam1))
+    cdt = time.perf_counter() - t0
     return {"workload": f"n={n} (n=2048 recipe, seed 0), loss = sum of lowest 128 eigenvalues + "
                         "Lorentzian spectrum (eta 0.05) on 512 points in (0, 12)",
             "forward_seconds": round(fwd, 4),
@@ -296,7 +345,10 @@ def bench_differentiation(api, inputs, steps, warmup):
             "loss_and_backward_seconds": round(bwd, 4),
             "adjoint_ms": round(adj_ms, 3),
             "adjoint_tflops": round(adj_flops / (adj_ms * 1e-3) / 1e12, 3),
-            "adjoint_frac_fp64_mfma": round(adj_flops / (adj_ms * 1e-3) / 1e12 / PEAK["fp64_mfma"], 4)}
+            "adjoint_frac_fp64_mfma": round(adj_flops / (adj_ms * 1e-3) / 1e12 / PEAK["fp64_mfma"], 4),
+            "fd_directional_rel_err": abs(fd - ad) / max(1.0, abs(ad)),
+            "cpu_baseline": {"seconds": round(cdt, 2), "kind": "oracle",
+                             "sample": "forward solve + spectrum-loss adjoint at n = 1024 of the same recipe"}}
 
 
 def load_traffic(kernel: str, workload: str, precision: str):

@@ -23,3 +23,17 @@ def test_table_validation_and_round_trip(tmp_path):
     for bad in ([(64, 3, 64)], [(64, 1, 96)], [(128, 1, 64), (64, 1, 64)], [(0, 1, 64)]):
         with pytest.raises(ValueError):
             tune.validate(bad)
+
+
+def test_packaged_table_is_valid():
+    """Rows for the padded orders of the 256-problem batch (128..1024), each a valid candidate."""
+    table = tune.packaged()
+    assert [r[0] for r in table] == list(range(128, 1025, 64))
+    for np_, kc, rr in table:
+        assert (kc, rr) in tune.candidates(np_) and kc <= tune.default_kc(np_)
+
+
+def test_builtin_batch_choice_is_a_candidate():
+    for np_ in range(64, 4097, 64):
+        kc, rr = tune.builtin_batch_tiles(np_)
+        assert (kc, rr) in tune.candidates(np_) and kc <= tune.default_kc(np_)
