@@ -11,7 +11,8 @@
 //               trailing update), Alg. 3 steps 1-2
 //   W           one grouped GEMM, step 3's matrix
 //   Jacobi      per round three launches (Gram, inner eigensolver, rotation)
-//               over the problems that have that round; per sweep one small
+//               over the problems that have that round, recorded once as a
+//               HIP graph and replayed every sweep; per sweep one small
 //               launch that closes each problem's sweep on the device
 //               (converged problems then skip all later work) and one
 //               readback of the number of problems still active
@@ -449,26 +450,57 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       while (c < (int)rounds.size() && rounds[c] > t) ++c;
       part[t] = c;
     }
-    for (int sweep = 0;; ++sweep) {
-      BSE_TRY(hipMemsetAsync(d_active, 0, sizeof(int), s));
-      BSE_TRY(group_jacobi(G_SWEEP, ds.tab, ds.map, ds.blocks, sweep, s));
-      int active = 0;
-      BSE_TRY(hipMemcpyAsync(&active, d_active, sizeof(int), hipMemcpyDeviceToHost, s));
-      BSE_TRY(hipStreamSynchronize(s));
-      if (active == 0) break;
-      for (int t = 0; t < R; ++t) {
+    // The 3R launches of a sweep are the same in every sweep (same tables,
+    // prefixes and rounds; what changes lives in device memory), so they are
+    // recorded once into a HIP graph and the graph is replayed per sweep.
+    // Recording uses a private stream; if recording fails the launches are
+    // issued directly.
+    auto rounds_on = [&](hipStream_t st) -> hipError_t {
+      hipError_t e = hipSuccess;
+      for (int t = 0; t < R && e == hipSuccess; ++t) {
         const int c = part[t];
         if (mixed) {
-          BSE_TRY(group_jacobi(G_GRAM_C, dg.tab, dg.map, gc.prefix(c), t, s));
-          BSE_TRY(group_jacobi(G_EIG_C, de.tab, de.map, ec.prefix(c), t, s));
-          BSE_TRY(group_jacobi(G_ROT_C, dr.tab, dr.map, rc.prefix(c), t, s));
+          e = group_jacobi(G_GRAM_C, dg.tab, dg.map, gc.prefix(c), t, st);
+          if (e == hipSuccess) e = group_jacobi(G_EIG_C, de.tab, de.map, ec.prefix(c), t, st);
+          if (e == hipSuccess) e = group_jacobi(G_ROT_C, dr.tab, dr.map, rc.prefix(c), t, st);
         } else {
-          BSE_TRY(group_jacobi(G_GRAM_Z, dg.tab, dg.map, gz.prefix(c), t, s));
-          BSE_TRY(group_jacobi(G_EIG_Z, de.tab, de.map, ez.prefix(c), t, s));
-          BSE_TRY(group_jacobi(G_ROT_Z, dr.tab, dr.map, rz.prefix(c), t, s));
+          e = group_jacobi(G_GRAM_Z, dg.tab, dg.map, gz.prefix(c), t, st);
+          if (e == hipSuccess) e = group_jacobi(G_EIG_Z, de.tab, de.map, ez.prefix(c), t, st);
+          if (e == hipSuccess) e = group_jacobi(G_ROT_Z, dr.tab, dr.map, rz.prefix(c), t, st);
         }
       }
+      return e;
+    };
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    {
+      hipStream_t cap = nullptr;
+      if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess) {
+        if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+          const hipError_t e1 = rounds_on(cap);
+          const hipError_t e2 = hipStreamEndCapture(cap, &graph);
+          if (e1 != hipSuccess || e2 != hipSuccess ||
+              hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+            exec = nullptr;
+        }
+        (void)hipStreamDestroy(cap);
+      }
+      (void)hipGetLastError();  // a failed recording leaves no error behind
     }
+    hipError_t loop_err = hipSuccess;
+    for (int sweep = 0;; ++sweep) {
+      if ((loop_err = hipMemsetAsync(d_active, 0, sizeof(int), s)) != hipSuccess) break;
+      if ((loop_err = group_jacobi(G_SWEEP, ds.tab, ds.map, ds.blocks, sweep, s)) != hipSuccess) break;
+      int active = 0;
+      if ((loop_err = hipMemcpyAsync(&active, d_active, sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess) break;
+      if ((loop_err = hipStreamSynchronize(s)) != hipSuccess) break;
+      if (active == 0) break;
+      loop_err = exec ? hipGraphLaunch(exec, s) : rounds_on(s);
+      if (loop_err != hipSuccess) break;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    BSE_TRY(loop_err);
     BSE_TRY(hipMemcpyAsync(states.data(), d_state, (size_t)batch * sizeof(JacState), hipMemcpyDeviceToHost, s));
     BSE_TRY(hipStreamSynchronize(s));
   }
