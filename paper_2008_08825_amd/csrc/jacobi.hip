@@ -265,19 +265,34 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   int sweeps_done = 0;
   int applied = 0;  // rotations applied by this lane (lanes 0..31)
   int gstep = 0;    // steps run so far; parameters of step g sit in buffer g & 1
-  // R <- R J for the rotations of the step in buffer b: rows r, rotations m0, m0 + dm, ...
+  // R <- R J for the rotations of the step in buffer b: row r, rotations m0, m0 + dm, ...
+  // (at most five).  All parameters are read first, then all entries of R,
+  // so the LDS round trips overlap instead of following one another.
   auto apply_r = [&](int b, int r, int m0, int dm) {
-    for (int m = m0; m < 32; m += dm) {
-      const int xm = pidx[b][m];
-      if (xm >> 16) {
-        const int i = xm & 255, j = (xm >> 8) & 255;
-        const double4 pp = prm[b][m];
-        const double c = pp.x;
-        const double2 sv = make_double2(pp.y, pp.z);
-        const double2 ri = R[r][i];
-        const double2 rj = R[r][j];
-        R[r][i] = csub(cscale(ri, c), cmul(cconj(sv), rj));
-        R[r][j] = cadd(cmul(sv, ri), cscale(rj, c));
+    int xm[5];
+    double4 pp[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int m = m0 + dm * u;
+      const int mc = m < 32 ? m : 31;
+      xm[u] = m < 32 ? pidx[b][mc] : 0;
+      pp[u] = prm[b][mc];
+    }
+    double2 ri[5], rj[5];
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      const int i = xm[u] & 255, j = (xm[u] >> 8) & 255;
+      ri[u] = R[r][i];
+      rj[u] = R[r][j];
+    }
+#pragma unroll
+    for (int u = 0; u < 5; ++u) {
+      if (xm[u] >> 16) {
+        const int i = xm[u] & 255, j = (xm[u] >> 8) & 255;
+        const double c = pp[u].x;
+        const double2 sv = make_double2(pp[u].y, pp[u].z);
+        R[r][i] = csub(cscale(ri[u], c), cmul(cconj(sv), rj[u]));
+        R[r][j] = cadd(cmul(sv, ri[u]), cscale(rj[u], c));
       }
     }
   };
@@ -338,6 +353,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
       if (tid < 496) {
         const int P = bP, Q = bQ;
         const int xP = pidx[cur][P], xQ = pidx[cur][Q];
+        const double4 ppP = prm[cur][P], ppQ = prm[cur][Q];
         const int rP = xP >> 16, rQ = xQ >> 16;
         if (rP | rQ) {
           const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
@@ -353,7 +369,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
           if (jP < iQ) g10 = cconj(g10);
           if (jP < jQ) g11 = cconj(g11);
           if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
-            const double4 pp = prm[cur][Q];
+            const double4 pp = ppQ;
             const double c = pp.x;
             const double2 sq = make_double2(pp.y, pp.z);
             const double2 sqc = cconj(sq);
@@ -364,7 +380,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
             g00 = t00; g01 = t01; g10 = t10; g11 = t11;
           }
           if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
-            const double4 pp = prm[cur][P];
+            const double4 pp = ppP;
             const double c = pp.x;
             const double2 sp = make_double2(pp.y, pp.z);
             const double2 spc = cconj(sp);
