@@ -79,11 +79,14 @@ struct JacobiResult {
 
 // One-sided block-Jacobi on the np columns of W (np % 64 == 0), in place:
 // on return the columns of W are mutually orthogonal (W_in Q = W_out, Q unitary).
+// Largest inner stopping level of the pair eigensolver (early outer sweeps,
+// where the other pairs disturb a pair's orthogonality far more anyway).
+constexpr double kInnerStopCap = 3.0e-2;
 // first_stop: inner stopping level of the first sweep (later sweeps follow
-// the previous sweep's largest off-diagonal measure, at most 1e-3).
+// 0.3 x the previous sweep's largest off-diagonal measure, at most kInnerStopCap).
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
                     int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false,
-                    double first_stop = 1.0e-3);
+                    double first_stop = kInnerStopCap);
 // complex64 columns; Gram partial sums, inner eigensolver and rotations as in
 // jacobi_z (inner eigensolver in FP64), inner iteration ending once a sweep's
 // largest relative off-diagonal entry is below inner_stop.

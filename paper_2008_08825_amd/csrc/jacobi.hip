@@ -534,7 +534,7 @@ BSE_DEV void SweepOp::run(const SweepArgs& a, int, int sweep) {
     return;
   }
   double stop = a.inner_floor;
-  if (a.adaptive) stop = fmax(a.inner_floor, prev < 0.0 ? 1.0e-3 : fmin(1.0e-3, 0.3 * prev));
+  if (a.adaptive) stop = fmax(a.inner_floor, fmin(kInnerStopCap, prev < 0.0 ? kInnerStopCap : 0.3 * prev));
   st->stop2 = stop * stop;
   st->counter = 0;
   st->inner = 0;
@@ -633,7 +633,7 @@ RotArgs<C2> make_rot(int np, C2* W, long ld, const JacobiWork& w, const int* don
 template <typename T>
 static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const JacobiWork& w,
                              double tol, double inner_stop, int max_sweeps, JacobiResult& res,
-                             hipStream_t s, bool time_kernels, double first_stop = 1.0e-3) {
+                             hipStream_t s, bool time_kernels, double first_stop = kInnerStopCap) {
   typedef typename cpx_t<T>::type C2;
   const int N = np / JB, pairs = N / 2;
   const int gblocks = jacobi_gram_blocks_kc(np, w.kc);
@@ -662,13 +662,14 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
   // rotation of a pair need not be more exact than the orthogonality the
   // other pairs of the same outer sweep disturb it by, so s follows the
   // previous outer sweep's largest off-diagonal measure (0.3 of it, leaving
-  // about a tenth of its square) down to the floor inner_stop; the first
-  // sweep uses 1e-3.
+  // about a tenth of its square), at most kInnerStopCap and down to the
+  // floor inner_stop; the first sweep uses first_stop.
   double prev_off = -1.0;
   const bool adaptive = getenv("BSE_FIXED_INNER") == nullptr;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double sstop = inner_stop;
-    if (adaptive) sstop = fmax(inner_stop, fmin(1.0e-3, prev_off < 0.0 ? first_stop : 0.3 * prev_off));
+    if (adaptive)
+      sstop = fmax(inner_stop, fmin(kInnerStopCap, prev_off < 0.0 ? first_stop : 0.3 * prev_off));
     ea.inner_stop2 = sstop * sstop;
     e = hipMemsetAsync(w.counter, 0, 128, s);
     if (e != hipSuccess) { ret = e; break; }
