@@ -267,7 +267,7 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   }
   tm.mark();
   JacobiResult jr;
-  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, want_timing >= 2));
+  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, want_timing >= 2, 0.3));
   tm.mark();
   BSE_TRY(scale_singular_cols_c(n, np, Wc, ld, sigma, bnorm, s));
   tm.mark();
@@ -396,7 +396,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
     BSE_TRY(gemm_z(g, s));
   }
   JacobiResult j64;
-  const double first = fmin(kInnerStopCap, fmax(1.0e-10, 0.3 * j32.max_off));
+  const double first = fmin(kInnerStopCap, fmax(1.0e-10, j32.max_off));
   BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, want_timing >= 2, first));
   tm.mark();
   BSE_TRY(scale_singular_cols_z(n, np, X1, ld, sigma, bnorm, s));  // Ws = (W V Q) sigma^-3/2

@@ -82,16 +82,21 @@ struct JacobiResult {
 // Largest inner stopping level of the pair eigensolver (early outer sweeps,
 // where the other pairs disturb a pair's orthogonality far more anyway).
 constexpr double kInnerStopCap = 3.0e-2;
-// first_stop: inner stopping level of the first sweep (later sweeps follow
-// 0.3 x the previous sweep's largest off-diagonal measure, at most kInnerStopCap).
+// first_stop: inner stopping level of the first sweep (later sweeps use the
+// previous sweep's largest off-diagonal measure, at most kInnerStopCap).
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
                     int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false,
                     double first_stop = kInnerStopCap);
 // complex64 columns; Gram partial sums, inner eigensolver and rotations as in
 // jacobi_z (inner eigensolver in FP64), inner iteration ending once a sweep's
 // largest relative off-diagonal entry is below inner_stop.
+// inner_factor: multiple of the previous sweep's off-diagonal measure used as
+// the inner stopping level (1 by default; smaller values leave the columns
+// more orthogonal at the end, which the Newton refinement of the mixed form
+// needs).
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false);
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false,
+                    double inner_factor = 1.0);
 
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status, int base,
                       hipStream_t s);
@@ -248,6 +253,7 @@ struct JacState {
 };
 struct SweepArgs {  // aux = sweep index
   JacState* st; int* active; int pairs_per_sweep; int max_sweeps; double inner_floor; int adaptive;
+  double factor;  // inner stopping level = factor x previous sweep's largest off-diagonal
 };
 
 // Work-group counts of one problem for the ops above.

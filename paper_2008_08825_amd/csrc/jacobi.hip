@@ -534,7 +534,7 @@ BSE_DEV void SweepOp::run(const SweepArgs& a, int, int sweep) {
     return;
   }
   double stop = a.inner_floor;
-  if (a.adaptive) stop = fmax(a.inner_floor, fmin(kInnerStopCap, prev < 0.0 ? kInnerStopCap : 0.3 * prev));
+  if (a.adaptive) stop = fmax(a.inner_floor, fmin(kInnerStopCap, prev < 0.0 ? kInnerStopCap : a.factor * prev));
   st->stop2 = stop * stop;
   st->counter = 0;
   st->inner = 0;
@@ -633,7 +633,8 @@ RotArgs<C2> make_rot(int np, C2* W, long ld, const JacobiWork& w, const int* don
 template <typename T>
 static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const JacobiWork& w,
                              double tol, double inner_stop, int max_sweeps, JacobiResult& res,
-                             hipStream_t s, bool time_kernels, double first_stop = kInnerStopCap) {
+                             hipStream_t s, bool time_kernels, double first_stop = kInnerStopCap,
+                             double inner_factor = 1.0) {
   typedef typename cpx_t<T>::type C2;
   const int N = np / JB, pairs = N / 2;
   const int gblocks = jacobi_gram_blocks_kc(np, w.kc);
@@ -660,16 +661,16 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
   // A pair's inner iteration ends after an inner sweep whose largest relative
   // off-diagonal entry was below s, which leaves about s^2 behind.  The
   // rotation of a pair need not be more exact than the orthogonality the
-  // other pairs of the same outer sweep disturb it by, so s follows the
-  // previous outer sweep's largest off-diagonal measure (0.3 of it, leaving
-  // about a tenth of its square), at most kInnerStopCap and down to the
-  // floor inner_stop; the first sweep uses first_stop.
+  // other pairs of the same outer sweep disturb it by, so s is inner_factor
+  // times the previous outer sweep's largest off-diagonal measure (leaving
+  // about its square), at most kInnerStopCap and down to the floor
+  // inner_stop; the first sweep uses first_stop.
   double prev_off = -1.0;
   const bool adaptive = getenv("BSE_FIXED_INNER") == nullptr;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double sstop = inner_stop;
     if (adaptive)
-      sstop = fmax(inner_stop, fmin(kInnerStopCap, prev_off < 0.0 ? first_stop : 0.3 * prev_off));
+      sstop = fmax(inner_stop, fmin(kInnerStopCap, prev_off < 0.0 ? first_stop : inner_factor * prev_off));
     ea.inner_stop2 = sstop * sstop;
     e = hipMemsetAsync(w.counter, 0, 128, s);
     if (e != hipSuccess) { ret = e; break; }
@@ -727,8 +728,10 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
 }
 
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels) {
-  return jacobi_run<float>(np, W, ld, w, tol, inner_stop, max_sweeps, res, s, time_kernels);
+                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels,
+                    double inner_factor) {
+  return jacobi_run<float>(np, W, ld, w, tol, inner_stop, max_sweeps, res, s, time_kernels,
+                           kInnerStopCap, inner_factor);
 }
 
 GramArgs<double2> gram_args_z(int np, double2* W, long ld, const JacobiWork& w, const int* done) {
