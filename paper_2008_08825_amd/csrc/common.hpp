@@ -92,13 +92,25 @@ BSE_DEV void atomic_max_nonneg(double* addr, double v) {
 //            Args per problem and map[b] = (table row, wg) for every flat
 //            workgroup b of the launch, so one launch covers many problems
 //            of different sizes with no idle workgroups.
+//
+// An op may declare MIN_WAVES, the waves per SIMD its kernels must keep
+// resident (the register budget follows from it); the default is 1.
+template <typename Op, typename = void>
+struct op_min_waves {
+  static constexpr int value = 1;
+};
 template <typename Op>
-__global__ __launch_bounds__(Op::NT) void k_one(typename Op::Args a, int aux) {
+struct op_min_waves<Op, decltype((void)Op::MIN_WAVES)> {
+  static constexpr int value = Op::MIN_WAVES;
+};
+
+template <typename Op>
+__global__ __launch_bounds__(Op::NT, op_min_waves<Op>::value) void k_one(typename Op::Args a, int aux) {
   Op::run(a, (int)blockIdx.x, aux);
 }
 
 template <typename Op>
-__global__ __launch_bounds__(Op::NT) void k_grp(const typename Op::Args* __restrict__ table,
+__global__ __launch_bounds__(Op::NT, op_min_waves<Op>::value) void k_grp(const typename Op::Args* __restrict__ table,
                                                 const int2* __restrict__ map, int aux) {
   const int2 m = map[blockIdx.x];
   Op::run(table[m.x], m.y, aux);

@@ -47,112 +47,227 @@ BSE_DEV int pair_col(int p, int q, int c) { return c < JB ? p * JB + c : q * JB 
 // ---------------------------------------------------------------- Gram tiles
 // Workgroup (pair k, chunk c) accumulates the ten lower tiles of X^H X over
 // rows [c * rc, (c + 1) * rc) and writes them to part[(k * kc + c) * 10 + tile].
+//
+// Tile t of the lower triangle lies in block row gram_ti(t), block column
+// gram_tj(t) (16-column blocks of the pair).  The work of a 16-row step (ten
+// tiles x four k-steps) is split evenly over the four waves (one per SIMD):
+// wave w takes tiles 2w and 2w + 1 whole and half the k-steps of a shared tile
+// (tile 8 for waves 0, 1; tile 9 for waves 2, 3; the lower wave of each couple
+// the first two k-steps).  Every wave runs its own copy of the loop with its
+// tiles known at compile time, so the loop has no branches and the
+// accumulators stay in place.
+//
+// Staging: 16 rows x 64 columns of complex values, double-buffered in LDS.
+// Entry (row r, column c) sits at r * 64 + (c ^ r ^ 16 (r & 1)): the XOR
+// spreads the column-wise writes (sixteen rows of one column per sixteen
+// lanes) and the row-wise MFMA fragment reads (sixteen columns of four rows)
+// over all banks.
 template <typename T>
 struct GramOp {
   static constexpr int NT = 256;
+  static constexpr int MIN_WAVES = 4;  // four workgroups per CU: 1024 of them fill the chip once
   typedef GramArgs<typename cpx_t<T>::type> Args;
   static BSE_DEV void run(const Args& a, int bx, int t);
 };
 
+// complex128 stages one 16-row step ahead, complex64 two (a second set of
+// staging registers for complex128 measured no faster)
+constexpr bool kGramDeepF64 = false;
+BSE_DEV constexpr int gram_ti(int t) { return t < 1 ? 0 : t < 3 ? 1 : t < 6 ? 2 : 3; }
+BSE_DEV constexpr int gram_tj(int t) { return t - gram_ti(t) * (gram_ti(t) + 1) / 2; }
+
 template <typename T>
-BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
+struct GramLane {
   typedef typename cpx_t<T>::type C2;
   typedef typename Mfma<T>::acc Acc;
-  if (a.done && *a.done) return;
-  const int N = a.N, rc = a.rc, kc = a.kc;
-  const C2* __restrict__ W = a.W;
-  const long ld = a.ld;
-  C2* __restrict__ part = a.part;
-  __shared__ T Xs[2][2][16][JP + 4];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k = bx / kc, c = bx % kc;
-  int p, q;
-  round_pair(N, t, k, p, q);
-  // Work of a 16-row step: ten tiles x four k-steps, split evenly over the
-  // four waves (one per SIMD): wave w takes tiles 2w and 2w + 1 whole and
-  // half the k-steps of a shared tile (tile 8 for waves 0, 1; tile 9 for
-  // waves 2, 3; the lower wave of each couple the first two k-steps).  The
-  // two halves of a shared tile are summed through LDS at the end.
-  const int tshared = 8 + (wave >> 1);
-  const int shalf = wave & 1;
+  int rd[4];  // LDS offset of row 4 s + lane / 16, column lane % 16 (block 0 or 1), per k-step s
+  int bo[4];  // offset of 16-column block b for this lane's row parity
+};
+
+// One k-step (four rows) of tile t read at k-step ks: (cr, ci) += X_m^H X_n
+// contributions, split in two halves so that consecutive MFMAs of a tile are
+// independent of each other.
+template <typename T, int TT>
+BSE_DEV void gram_half1(const typename cpx_t<T>::type* X, const GramLane<T>& g, int ks,
+                        typename Mfma<T>::acc& cr, typename Mfma<T>::acc& ci,
+                        typename cpx_t<T>::type& xn, typename cpx_t<T>::type& xm) {
+  // MFMA A operand: X[k][16 tj + l % 16] (n side); B operand: conj(X[k][16 ti + l % 16]) (m side)
+  xn = X[g.rd[ks] + g.bo[gram_tj(TT)]];
+  xm = X[g.rd[ks] + g.bo[gram_ti(TT)]];
+  cr = Mfma<T>::mac(xn.x, xm.x, cr);
+  ci = Mfma<T>::mac(xn.y, xm.x, ci);
+}
+
+template <typename T>
+BSE_DEV void gram_half2(typename Mfma<T>::acc& cr, typename Mfma<T>::acc& ci,
+                        typename cpx_t<T>::type xn, typename cpx_t<T>::type xm) {
+  cr = Mfma<T>::mac(xn.y, xm.y, cr);
+  ci = Mfma<T>::mac(xn.x, -xm.y, ci);
+}
+
+template <typename T, int WV>
+BSE_DEV void gram_buffer(const typename cpx_t<T>::type* X, const GramLane<T>& g,
+                         typename Mfma<T>::acc (&cr)[3], typename Mfma<T>::acc (&ci)[3]) {
+  typedef typename cpx_t<T>::type C2;
+  constexpr int TA = 2 * WV, TB = 2 * WV + 1, TS = 8 + (WV >> 1), SH = WV & 1;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    C2 na, ma, nb, mb, ns, ms;
+    gram_half1<T, TA>(X, g, s, cr[0], ci[0], na, ma);
+    gram_half1<T, TB>(X, g, s, cr[1], ci[1], nb, mb);
+    if (s & 1) gram_half1<T, TS>(X, g, 2 * SH + (s >> 1), cr[2], ci[2], ns, ms);
+    gram_half2<T>(cr[0], ci[0], na, ma);
+    gram_half2<T>(cr[1], ci[1], nb, mb);
+    if (s & 1) gram_half2<T>(cr[2], ci[2], ns, ms);
+  }
+}
+
+// Four staged values of one thread (pair columns c0, c0 + 16, c0 + 32, c0 + 48
+// of one row), their sources in W and their swizzled places in LDS.
+template <typename T>
+struct GramStage {
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  V2 v0, v1, v2, v3;
+};
+
+template <typename T>
+struct GramSrc {
+  typedef typename cpx_t<T>::type C2;
+  typedef typename GramStage<T>::V2 V2;
+  const V2* s0;
+  const V2* s1;
+  const V2* s2;
+  const V2* s3;
+  int w0, w1, w2, w3;
+  BSE_DEV GramSrc(const C2* W, long ld, int p, int q, int c0, int lr)
+      : s0(reinterpret_cast<const V2*>(W + (long)pair_col(p, q, c0) * ld)),
+        s1(reinterpret_cast<const V2*>(W + (long)pair_col(p, q, c0 + 16) * ld)),
+        s2(reinterpret_cast<const V2*>(W + (long)pair_col(p, q, c0 + 32) * ld)),
+        s3(reinterpret_cast<const V2*>(W + (long)pair_col(p, q, c0 + 48) * ld)),
+        w0(lr * JP + 16 * (0 ^ (lr & 1)) + (c0 ^ lr)),
+        w1(lr * JP + 16 * (1 ^ (lr & 1)) + (c0 ^ lr)),
+        w2(lr * JP + 16 * (2 ^ (lr & 1)) + (c0 ^ lr)),
+        w3(lr * JP + 16 * (3 ^ (lr & 1)) + (c0 ^ lr)) {}
+  BSE_DEV void load(GramStage<T>& st, int r) const {
+    st.v0 = s0[r];
+    st.v1 = s1[r];
+    st.v2 = s2[r];
+    st.v3 = s3[r];
+  }
+  BSE_DEV void store(const GramStage<T>& st, C2* X) const {
+    V2* Xv = reinterpret_cast<V2*>(X);
+    Xv[w0] = st.v0;
+    Xv[w1] = st.v1;
+    Xv[w2] = st.v2;
+    Xv[w3] = st.v3;
+  }
+};
+
+template <typename T, int WV, bool DEEP>
+BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, int c,
+                       typename cpx_t<T>::type* Xs) {
+  typedef typename cpx_t<T>::type C2;
+  typedef typename Mfma<T>::acc Acc;
+  constexpr int TS = 8 + (WV >> 1), SH = WV & 1;
+  const int tid = threadIdx.x, lane = tid & 63, h = lane >> 4, l15 = lane & 15;
+  const int rc = a.rc, row_beg = c * rc, row_end = row_beg + rc;
+  GramLane<T> g;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int kk = 4 * s + h;
+    g.rd[s] = kk * JP + (l15 ^ kk);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) g.bo[b] = 16 * (b ^ (h & 1));
+  // staging: thread reads rows r0 + lr of pair columns c0 + 16 i (sixteen
+  // consecutive rows of a column per sixteen lanes) and stores them swizzled
+  const int lr = tid & 15, c0 = tid >> 4;
+  GramStage<T> sa, sb;
+  const GramSrc<T> src(a.W + lr, a.ld, p, q, c0, lr);
   Acc cr[3], ci[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i) { cr[i] = Mfma<T>::zero(); ci[i] = Mfma<T>::zero(); }
-  int ti[3], tj[3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const int tt = i < 2 ? 2 * wave + i : tshared;
-    ti[i] = kTileI[tt]; tj[i] = kTileJ[tt];
-  }
-  const int row_beg = c * rc;
-  C2 reg[4];
-  const int lr = tid & 15;
-  auto load = [&](int r0) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int cc = (tid >> 4) + 16 * i;
-      reg[i] = W[(long)(r0 + lr) + (long)pair_col(p, q, cc) * ld];
-    }
-  };
-  load(row_beg);
-  int buf = 0;
-  for (int r0 = row_beg; r0 < row_beg + rc; r0 += 16) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int cc = (tid >> 4) + 16 * i;
-      Xs[buf][0][lr][cc] = reg[i].x;
-      Xs[buf][1][lr][cc] = reg[i].y;
-    }
+  // DEEP: two register sets in flight (rows r0 + 16 and r0 + 32 load while
+  // the MFMAs work on r0); otherwise one.  Prefetches past the chunk re-read
+  // its last rows, so that every step issues the same loads and the waits for
+  // them stay partial.
+  src.load(sa, row_beg);
+  if constexpr (DEEP) src.load(sb, min(row_beg + 16, row_end - 16));
+  C2* X0 = Xs;
+  C2* X1 = Xs + 16 * JP;
+  int r0 = row_beg;
+  for (; r0 + 32 <= row_end; r0 += 32) {
+    src.store(sa, X0);
     __syncthreads();
-    if (r0 + 16 < row_beg + rc) load(r0 + 16);
-#pragma unroll
-    for (int s = 0; s < 4; ++s) {
-      const int kk = 4 * s + (lane >> 4);
-#pragma unroll
-      for (int i = 0; i < 3; ++i) {
-        if (i < 2 || (s >> 1) == shalf) {
-          // MFMA A operand: X[kk][16 tj + l%16] (n side); B operand: conj(X[kk][16 ti + l%16]) (m side)
-          const T xr_n = Xs[buf][0][kk][16 * tj[i] + (lane & 15)];
-          const T xi_n = Xs[buf][1][kk][16 * tj[i] + (lane & 15)];
-          const T xr_m = Xs[buf][0][kk][16 * ti[i] + (lane & 15)];
-          const T xi_m = Xs[buf][1][kk][16 * ti[i] + (lane & 15)];
-          cmac<T>(xr_n, xi_n, xr_m, -xi_m, cr[i], ci[i]);
-        }
-      }
+    src.load(sa, min(r0 + (DEEP ? 32 : 16), row_end - 16));
+    __builtin_amdgcn_sched_barrier(0);  // issue the prefetch before the MFMA work
+    gram_buffer<T, WV>(X0, g, cr, ci);
+    if constexpr (DEEP) {
+      src.store(sb, X1);
+      __syncthreads();
+      src.load(sb, min(r0 + 48, row_end - 16));
+    } else {
+      src.store(sa, X1);
+      __syncthreads();
+      src.load(sa, min(r0 + 32, row_end - 16));
     }
-    buf ^= 1;
+    __builtin_amdgcn_sched_barrier(0);
+    gram_buffer<T, WV>(X1, g, cr, ci);
   }
-  // shared tiles: the upper wave of each couple hands its half to the lower one
+  if (r0 < row_end) {  // an odd number of 16-row steps: the last one
+    src.store(sa, X0);
+    __syncthreads();
+    gram_buffer<T, WV>(X0, g, cr, ci);
+  }
+  // shared tile: the upper wave of each couple hands its half to the lower one
   __syncthreads();
-  T* hand = &Xs[0][0][0][0];  // 2 couples x 2 (re, im) x 4 registers x 64 lanes fit in Xs
-  if (shalf) {
+  T* hand = reinterpret_cast<T*>(Xs) + (WV >> 1) * 512;  // 2 (re, im) x 4 registers x 64 lanes per couple
+  if (SH) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      hand[(((wave >> 1) * 2 + 0) * 4 + r) * 64 + lane] = cr[2][r];
-      hand[(((wave >> 1) * 2 + 1) * 4 + r) * 64 + lane] = ci[2][r];
+      hand[r * 64 + lane] = cr[2][r];
+      hand[(4 + r) * 64 + lane] = ci[2][r];
     }
   }
   __syncthreads();
-  if (!shalf) {
+  if (!SH) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      cr[2][r] += hand[(((wave >> 1) * 2 + 0) * 4 + r) * 64 + lane];
-      ci[2][r] += hand[(((wave >> 1) * 2 + 1) * 4 + r) * 64 + lane];
+      cr[2][r] += hand[r * 64 + lane];
+      ci[2][r] += hand[(4 + r) * 64 + lane];
     }
   }
   // tile element (m_local, n_local) of G = X^H X is stored at m_local + 16 n_local
+  C2* out = a.part + (long)(k * a.kc + c) * NTILE * 256;
 #pragma unroll
   for (int i = 0; i < 3; ++i) {
-    if (i < 2 || !shalf) {
-      const int tt = i < 2 ? 2 * wave + i : tshared;
-      C2* dst = part + ((long)(k * kc + c) * NTILE + tt) * 256;
+    if (i < 2 || !SH) {
+      const int tt = i < 2 ? 2 * WV + i : TS;
+      C2* dst = out + tt * 256;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int ml = lane & 15, nl = Mfma<T>::drow(lane, r);
+        const int ml = l15, nl = Mfma<T>::drow(lane, r);
         C2 v; v.x = cr[i][r]; v.y = ci[i][r];
         dst[ml + 16 * nl] = v;
       }
     }
+  }
+}
+
+template <typename T>
+BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
+  typedef typename cpx_t<T>::type C2;
+  if (a.done && *a.done) return;
+  __shared__ C2 Xs[2 * 16 * JP];
+  const int k = bx / a.kc, c = bx % a.kc;
+  int p, q;
+  round_pair(a.N, t, k, p, q);
+  constexpr bool kDeep = kGramDeepF64 || sizeof(T) == 4;
+  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+    case 0: gram_wave<T, 0, kDeep>(a, p, q, k, c, Xs); break;
+    case 1: gram_wave<T, 1, kDeep>(a, p, q, k, c, Xs); break;
+    case 2: gram_wave<T, 2, kDeep>(a, p, q, k, c, Xs); break;
+    default: gram_wave<T, 3, kDeep>(a, p, q, k, c, Xs); break;
   }
 }
 
@@ -436,67 +551,133 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
 
 // ---------------------------------------------------------------- rotation
 // Workgroup (pair k, row chunk): X[rows, :] <- X[rows, :] R, in place.  R goes
-// to LDS once; each wave handles 16-row strips and holds the strip's 16 x 64
-// inputs in registers (loaded as MFMA B operands: 16 consecutive rows of one
-// column per 16 lanes) before writing any output.
+// to LDS once (rows padded in complex64 so that the MFMA fragment reads of
+// four rows x sixteen columns take the minimum two bank cycles; a complex128
+// row already fills them).  Each wave handles
+// 16-row strips: it holds the strip's 16 x 64 inputs in registers (loaded as
+// MFMA B operands: 16 consecutive rows of one column per 16 lanes) and runs
+// the k-steps outermost with the four 16-column output tiles accumulating
+// side by side, so that each input register is free after its k-step and is
+// refilled at once with the wave's next strip.
 template <typename T>
 struct RotOp {
   static constexpr int NT = 256;
+  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : 4;  // what the LDS for R allows
   typedef RotArgs<typename cpx_t<T>::type> Args;
   static BSE_DEV void run(const Args& a, int bx, int t);
 };
 
 template <typename T>
-BSE_DEV void RotOp<T>::run(const typename RotOp<T>::Args& a, int bx, int t) {
+constexpr int rot_ld() { return sizeof(T) == 4 ? JP + 16 : JP; }
+
+template <typename T, bool PREFETCH>
+BSE_DEV void rot_strip(const typename cpx_t<T>::type* Rs, typename cpx_t<T>::type (&xf)[16],
+                       typename cpx_t<T>::type* lp0, typename cpx_t<T>::type* lp1,
+                       typename cpx_t<T>::type* sp0, typename cpx_t<T>::type* sp1, long ld,
+                       int row0, int rnext, int lane) {
   typedef typename cpx_t<T>::type C2;
   typedef typename Mfma<T>::acc Acc;
+  const int h = lane >> 4, l15 = lane & 15;
+  // R is read from LDS afresh for every strip, and the lane's column pointers
+  // are opaque to the compiler here, so that neither the R fragments nor
+  // per-k-step addresses are hoisted out of the strip loop into registers
+#if defined(__HIP_DEVICE_COMPILE__)
+  __asm__ volatile("" : "+v"(lp0), "+v"(lp1), "+v"(sp0), "+v"(sp1) : : "memory");
+#endif
+  typedef T V2 __attribute__((ext_vector_type(2)));
+  typedef __attribute__((address_space(1))) V2 GV2;  // global memory (not flat) accesses
+  GV2* gl0 = (GV2*)lp0;
+  GV2* gl1 = (GV2*)lp1;
+  GV2* gs0 = (GV2*)sp0;
+  GV2* gs1 = (GV2*)sp1;
+  Acc cr[4], ci[4];
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) { cr[tj] = Mfma<T>::zero(); ci[tj] = Mfma<T>::zero(); }
+  // R fragments of k-step kk + 1 are read while the MFMAs of k-step kk run;
+  // the scheduling barriers keep the compiler from hoisting further reads
+  C2 r[4], rn[4];
+  const typename cpx_t<T>::type* Rl = Rs + h * rot_ld<T>() + l15;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) r[tj] = Rl[16 * tj];
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) {
+    if (kk + 1 < 16) {
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) rn[tj] = Rl[4 * (kk + 1) * rot_ld<T>() + 16 * tj];
+    }
+    // (cr, ci) += R[kr][n] X[row][kr]: first the products with Re R, then with Im R
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      cr[tj] = Mfma<T>::mac(r[tj].x, xf[kk].x, cr[tj]);
+      ci[tj] = Mfma<T>::mac(r[tj].x, xf[kk].y, ci[tj]);
+    }
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) {
+      cr[tj] = Mfma<T>::mac(-r[tj].y, xf[kk].y, cr[tj]);
+      ci[tj] = Mfma<T>::mac(r[tj].y, xf[kk].x, ci[tj]);
+    }
+    if (PREFETCH) {
+      const V2 v = (kk < 8 ? gl0 : gl1)[(long)(4 * (kk & 7)) * ld + rnext];
+      xf[kk].x = v.x;
+      xf[kk].y = v.y;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) r[tj] = rn[tj];
+  }
+  // D row of register rr is column 16 tj + drow(lane, rr) of the pair; the
+  // store pointers hold drow(lane, 0)
+  constexpr int rstep = sizeof(T) == 8 ? 4 : 1;
+#pragma unroll
+  for (int tj = 0; tj < 4; ++tj) {
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      V2 v; v.x = cr[tj][rr]; v.y = ci[tj][rr];
+      (tj < 2 ? gs0 : gs1)[(long)(16 * (tj & 1) + rstep * rr) * ld + row0] = v;
+    }
+  }
+}
+
+template <typename T>
+BSE_DEV void RotOp<T>::run(const typename RotOp<T>::Args& a, int bx, int t) {
+  typedef typename cpx_t<T>::type C2;
   if (a.done && *a.done) return;
   const int N = a.N, rows_per_wg = a.rrows, chunks = a.chunks;
   C2* W = a.W;
   const long ld = a.ld;
-  const C2* __restrict__ Rall = a.R;
   const int* __restrict__ flags = a.flags;
-  __shared__ T Rs[2][JP][JP + 4];
+  __shared__ C2 Rs[JP * rot_ld<T>()];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int k = bx / chunks, chunk = bx % chunks;
   if (!flags[k]) return;
   int p, q;
   round_pair(N, t, k, p, q);
-  const C2* R = Rall + (long)k * JP * JP;
+  const C2* R = a.R + (long)k * JP * JP;
   for (int e = tid; e < JP * JP; e += 256) {
     const int i = e & 63, j = e >> 6;  // R[i][j], i = k index, j = n index
-    const C2 v = R[i + JP * j];
-    Rs[0][i][j] = v.x;
-    Rs[1][i][j] = v.y;
+    Rs[i * rot_ld<T>() + j] = R[i + JP * j];
   }
-  __syncthreads();
+  // the lane's input column of k-step kk is 4 kk + lane / 16 of the pair
+  // (block p for kk < 8, block q after): lp0 / lp1 point at it for kk = 0 / 8
+  // in the lane's row; sp0 / sp1 at the output column drow(lane, 0) of
+  // block p / q
+  const int h = lane >> 4, l15 = lane & 15;
+  const int d0 = Mfma<T>::drow(lane, 0);
+  C2* lp0 = W + (long)(p * JB + h) * ld + l15;
+  C2* lp1 = W + (long)(q * JB + h) * ld + l15;
+  C2* sp0 = W + (long)(p * JB + d0) * ld + l15;
+  C2* sp1 = W + (long)(q * JB + d0) * ld + l15;
+  int row0 = chunk * rows_per_wg + wave * 16;
   const int strips = rows_per_wg / 64;
-  for (int sidx = 0; sidx < strips; ++sidx) {
-    const int row0 = chunk * rows_per_wg + (sidx * 4 + wave) * 16;
-    C2 xf[16];
+  C2 xf[16];
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const int cidx = 4 * kk + (lane >> 4);
-      xf[kk] = W[(long)(row0 + (lane & 15)) + (long)pair_col(p, q, cidx) * ld];
-    }
-#pragma unroll 1
-    for (int tj = 0; tj < 4; ++tj) {
-      Acc cr = Mfma<T>::zero(), ci = Mfma<T>::zero();
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const int kr = 4 * kk + (lane >> 4);
-        const T rr = Rs[0][kr][16 * tj + (lane & 15)];
-        const T ri = Rs[1][kr][16 * tj + (lane & 15)];
-        cmac<T>(rr, ri, xf[kk].x, xf[kk].y, cr, ci);
-      }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int n = 16 * tj + Mfma<T>::drow(lane, r);
-        C2 v; v.x = cr[r]; v.y = ci[r];
-        W[(long)(row0 + (lane & 15)) + (long)pair_col(p, q, n) * ld] = v;
-      }
-    }
+  for (int kk = 0; kk < 16; ++kk) xf[kk] = (kk < 8 ? lp0 : lp1)[(long)(4 * (kk & 7)) * ld + row0];
+  __syncthreads();
+  for (int sidx = 0; sidx + 1 < strips; ++sidx) {
+    rot_strip<T, true>(Rs, xf, lp0, lp1, sp0, sp1, ld, row0, row0 + 64, lane);
+    row0 += 64;
   }
+  rot_strip<T, false>(Rs, xf, lp0, lp1, sp0, sp1, ld, row0, row0, lane);
 }
 
 // ---------------------------------------------------------------- batches
