@@ -84,41 +84,63 @@ struct GramLane {
   int bo[4];  // offset of 16-column block b for this lane's row parity
 };
 
-// One k-step (four rows) of tile t read at k-step ks: (cr, ci) += X_m^H X_n
-// contributions, split in two halves so that consecutive MFMAs of a tile are
-// independent of each other.
-template <typename T, int TT>
-BSE_DEV void gram_half1(const typename cpx_t<T>::type* X, const GramLane<T>& g, int ks,
-                        typename Mfma<T>::acc& cr, typename Mfma<T>::acc& ci,
-                        typename cpx_t<T>::type& xn, typename cpx_t<T>::type& xm) {
-  // MFMA A operand: X[k][16 tj + l % 16] (n side); B operand: conj(X[k][16 ti + l % 16]) (m side)
-  xn = X[g.rd[ks] + g.bo[gram_tj(TT)]];
-  xm = X[g.rd[ks] + g.bo[gram_ti(TT)]];
-  cr = Mfma<T>::mac(xn.x, xm.x, cr);
-  ci = Mfma<T>::mac(xn.y, xm.x, ci);
-}
-
+// Complex products on the real MFMAs.  complex128 takes the four real
+// products per complex k-step (Re = Re Re + Im Im, Im = Re Im - Im Re);
+// complex64 the three-product form (P1 = Re Re, P2 = Im Im, P3 on the sums:
+// one MFMA in four fewer, at the normwise accuracy of the plain form, which
+// the FP64 stages that follow a complex64 iteration do not depend on).
 template <typename T>
-BSE_DEV void gram_half2(typename Mfma<T>::acc& cr, typename Mfma<T>::acc& ci,
-                        typename cpx_t<T>::type xn, typename cpx_t<T>::type xm) {
-  cr = Mfma<T>::mac(xn.y, xm.y, cr);
-  ci = Mfma<T>::mac(xn.x, -xm.y, ci);
-}
+constexpr bool cplx3m() { return sizeof(T) == 4; }
 
+// One 16-row step (four k-steps of four rows) of the wave's tiles on staged
+// buffer X: acc[i] accumulates tile i (tiles 2 WV, 2 WV + 1 and, on odd
+// k-steps, the shared tile at k-step 2 (WV & 1) + s / 2) as X_m^H X_n.  The
+// MFMAs are ordered so that consecutive ones write different accumulators.
 template <typename T, int WV>
 BSE_DEV void gram_buffer(const typename cpx_t<T>::type* X, const GramLane<T>& g,
-                         typename Mfma<T>::acc (&cr)[3], typename Mfma<T>::acc (&ci)[3]) {
+                         typename Mfma<T>::acc (&acc)[3][3]) {
   typedef typename cpx_t<T>::type C2;
   constexpr int TA = 2 * WV, TB = 2 * WV + 1, TS = 8 + (WV >> 1), SH = WV & 1;
+  constexpr int tiles[3] = {TA, TB, TS};
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    C2 na, ma, nb, mb, ns, ms;
-    gram_half1<T, TA>(X, g, s, cr[0], ci[0], na, ma);
-    gram_half1<T, TB>(X, g, s, cr[1], ci[1], nb, mb);
-    if (s & 1) gram_half1<T, TS>(X, g, 2 * SH + (s >> 1), cr[2], ci[2], ns, ms);
-    gram_half2<T>(cr[0], ci[0], na, ma);
-    gram_half2<T>(cr[1], ci[1], nb, mb);
-    if (s & 1) gram_half2<T>(cr[2], ci[2], ns, ms);
+    const int nt = (s & 1) ? 3 : 2;
+    C2 xn[3], xm[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      if (i < nt) {
+        // MFMA A operand: X[k][16 tj + l % 16] (n side); B operand: X[k][16 ti + l % 16] (m side)
+        const int ks = i < 2 ? s : 2 * SH + (s >> 1);
+        xn[i] = X[g.rd[ks] + g.bo[gram_tj(tiles[i])]];
+        xm[i] = X[g.rd[ks] + g.bo[gram_ti(tiles[i])]];
+      }
+    }
+    if constexpr (cplx3m<T>()) {
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (i < nt) acc[i][0] = Mfma<T>::mac(xn[i].x, xm[i].x, acc[i][0]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (i < nt) acc[i][1] = Mfma<T>::mac(xn[i].y, xm[i].y, acc[i][1]);
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        if (i < nt) acc[i][2] = Mfma<T>::mac(xn[i].x + xn[i].y, xm[i].x - xm[i].y, acc[i][2]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        if (i < nt) {
+          acc[i][0] = Mfma<T>::mac(xn[i].x, xm[i].x, acc[i][0]);
+          acc[i][1] = Mfma<T>::mac(xn[i].y, xm[i].x, acc[i][1]);
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        if (i < nt) {
+          acc[i][0] = Mfma<T>::mac(xn[i].y, xm[i].y, acc[i][0]);
+          acc[i][1] = Mfma<T>::mac(xn[i].x, -xm[i].y, acc[i][1]);
+        }
+      }
+    }
   }
 }
 
@@ -184,9 +206,11 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
   const int lr = tid & 15, c0 = tid >> 4;
   GramStage<T> sa, sb;
   const GramSrc<T> src(a.W + lr, a.ld, p, q, c0, lr);
-  Acc cr[3], ci[3];
+  Acc acc[3][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) { cr[i] = Mfma<T>::zero(); ci[i] = Mfma<T>::zero(); }
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[i][j] = Mfma<T>::zero();
   // DEEP: two register sets in flight (rows r0 + 16 and r0 + 32 load while
   // the MFMAs work on r0); otherwise one.  Prefetches past the chunk re-read
   // its last rows, so that every step issues the same loads and the waits for
@@ -201,7 +225,7 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
     __syncthreads();
     src.load(sa, min(r0 + (DEEP ? 32 : 16), row_end - 16));
     __builtin_amdgcn_sched_barrier(0);  // issue the prefetch before the MFMA work
-    gram_buffer<T, WV>(X0, g, cr, ci);
+    gram_buffer<T, WV>(X0, g, acc);
     if constexpr (DEEP) {
       src.store(sb, X1);
       __syncthreads();
@@ -212,12 +236,24 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
       src.load(sa, min(r0 + 32, row_end - 16));
     }
     __builtin_amdgcn_sched_barrier(0);
-    gram_buffer<T, WV>(X1, g, cr, ci);
+    gram_buffer<T, WV>(X1, g, acc);
   }
   if (r0 < row_end) {  // an odd number of 16-row steps: the last one
     src.store(sa, X0);
     __syncthreads();
-    gram_buffer<T, WV>(X0, g, cr, ci);
+    gram_buffer<T, WV>(X0, g, acc);
+  }
+  // real and imaginary parts of the tiles
+  Acc cr[3], ci[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if constexpr (cplx3m<T>()) {
+      cr[i] = acc[i][0] + acc[i][1];
+      ci[i] = acc[i][2] - acc[i][0] + acc[i][1];
+    } else {
+      cr[i] = acc[i][0];
+      ci[i] = acc[i][1];
+    }
   }
   // shared tile: the upper wave of each couple hands its half to the lower one
   __syncthreads();
@@ -590,9 +626,11 @@ BSE_DEV void rot_strip(const typename cpx_t<T>::type* Rs, typename cpx_t<T>::typ
   GV2* gl1 = (GV2*)lp1;
   GV2* gs0 = (GV2*)sp0;
   GV2* gs1 = (GV2*)sp1;
-  Acc cr[4], ci[4];
+  Acc acc[4][3];
 #pragma unroll
-  for (int tj = 0; tj < 4; ++tj) { cr[tj] = Mfma<T>::zero(); ci[tj] = Mfma<T>::zero(); }
+  for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) acc[tj][j] = Mfma<T>::zero();
   // R fragments of k-step kk + 1 are read while the MFMAs of k-step kk run;
   // the scheduling barriers keep the compiler from hoisting further reads
   C2 r[4], rn[4];
@@ -605,16 +643,28 @@ BSE_DEV void rot_strip(const typename cpx_t<T>::type* Rs, typename cpx_t<T>::typ
 #pragma unroll
       for (int tj = 0; tj < 4; ++tj) rn[tj] = Rl[4 * (kk + 1) * rot_ld<T>() + 16 * tj];
     }
-    // (cr, ci) += R[kr][n] X[row][kr]: first the products with Re R, then with Im R
+    // acc += R[kr][n] X[row][kr]
+    if constexpr (cplx3m<T>()) {
+      // P1 = Re R Re X, P2 = Im R Im X, P3 = (Re R + Im R)(Re X + Im X)
+      const T xs = xf[kk].x + xf[kk].y;
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) {
-      cr[tj] = Mfma<T>::mac(r[tj].x, xf[kk].x, cr[tj]);
-      ci[tj] = Mfma<T>::mac(r[tj].x, xf[kk].y, ci[tj]);
-    }
+      for (int tj = 0; tj < 4; ++tj) acc[tj][0] = Mfma<T>::mac(r[tj].x, xf[kk].x, acc[tj][0]);
 #pragma unroll
-    for (int tj = 0; tj < 4; ++tj) {
-      cr[tj] = Mfma<T>::mac(-r[tj].y, xf[kk].y, cr[tj]);
-      ci[tj] = Mfma<T>::mac(r[tj].y, xf[kk].x, ci[tj]);
+      for (int tj = 0; tj < 4; ++tj) acc[tj][1] = Mfma<T>::mac(r[tj].y, xf[kk].y, acc[tj][1]);
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) acc[tj][2] = Mfma<T>::mac(r[tj].x + r[tj].y, xs, acc[tj][2]);
+    } else {
+      // first the products with Re R, then with Im R
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) {
+        acc[tj][0] = Mfma<T>::mac(r[tj].x, xf[kk].x, acc[tj][0]);
+        acc[tj][1] = Mfma<T>::mac(r[tj].x, xf[kk].y, acc[tj][1]);
+      }
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj) {
+        acc[tj][0] = Mfma<T>::mac(-r[tj].y, xf[kk].y, acc[tj][0]);
+        acc[tj][1] = Mfma<T>::mac(r[tj].y, xf[kk].x, acc[tj][1]);
+      }
     }
     if (PREFETCH) {
       const V2 v = (kk < 8 ? gl0 : gl1)[(long)(4 * (kk & 7)) * ld + rnext];
@@ -632,7 +682,14 @@ BSE_DEV void rot_strip(const typename cpx_t<T>::type* Rs, typename cpx_t<T>::typ
   for (int tj = 0; tj < 4; ++tj) {
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
-      V2 v; v.x = cr[tj][rr]; v.y = ci[tj][rr];
+      V2 v;
+      if constexpr (cplx3m<T>()) {
+        v.x = acc[tj][0][rr] - acc[tj][1][rr];
+        v.y = acc[tj][2][rr] - acc[tj][0][rr] - acc[tj][1][rr];
+      } else {
+        v.x = acc[tj][0][rr];
+        v.y = acc[tj][1][rr];
+      }
       (tj < 2 ? gs0 : gs1)[(long)(16 * (tj & 1) + rstep * rr) * ld + row0] = v;
     }
   }
