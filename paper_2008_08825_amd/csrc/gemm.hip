@@ -7,20 +7,29 @@
 //
 // Tiling: a 256-thread workgroup (4 waves) owns a 64 x 64 output tile; each
 // wave a 32 x 32 quadrant of 2 x 2 MFMA tiles.  K advances in steps of 16
-// through LDS, where both operands sit in planar (re, im) form so each lane
-// reads one real per MFMA operand; global loads for the next K step are
-// issued before the MFMAs of the current one.
+// through double-buffered LDS (one barrier per step), where both operands sit
+// as interleaved complex values, swizzled so that the column-wise stores and
+// the MFMA fragment reads (four k rows x sixteen columns) spread over all
+// banks; global loads for the next K step are issued before the MFMAs of the
+// current one.  Complex products take the three-product form (P1 = Re Re,
+// P2 = Im Im, P3 on the sums): three real MFMAs per complex k-step instead
+// of four, with an error bound of the plain form's kind (a small multiple of
+// the unit roundoff times |A| |B| entrywise).
 #include "common.hpp"
 #include "internal.hpp"
 
 namespace bse {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 4;
+constexpr int BM = 64, BN = 64, BK = 16;
+
+// LDS place of operand element (k, c) of a 16 x 64 staged tile
+BSE_DEV int gemm_swz(int k, int c) { return k * 64 + (c ^ k ^ ((k & 1) << 4)); }
 
 template <typename T, int OPA, int OPB>
 struct GemmOp {
   static constexpr int NT = 256;
+  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : 4;  // as many as the LDS allows
   typedef GemmArgs<T> Args;
   static BSE_DEV void run(const Args& p, int bx, int aux);
 };
@@ -29,8 +38,8 @@ template <typename T, int OPA, int OPB>
 BSE_DEV void GemmOp<T, OPA, OPB>::run(const GemmArgs<T>& p, int bx, int) {
   typedef typename cpx_t<T>::type C2;
   typedef typename Mfma<T>::acc Acc;
-  __shared__ T As[2][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
+  __shared__ C2 As[2][BK * BM];
+  __shared__ C2 Bs[2][BK * BN];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int tm = bx % p.tilesM, tn = bx / p.tilesM;
@@ -49,96 +58,97 @@ BSE_DEV void GemmOp<T, OPA, OPB>::run(const GemmArgs<T>& p, int bx, int) {
   }
   kbeg = (kbeg / BK) * BK;
 
-  Acc cr[2][2], ci[2][2];
+  // acc[ti][tj]: P1, P2, P3 of the three-product form
+  Acc acc[2][2][3];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) { cr[i][j] = Mfma<T>::zero(); ci[i][j] = Mfma<T>::zero(); }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) acc[i][j][c] = Mfma<T>::zero();
 
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  // staging: element i of this thread, (k, m) of A and (k, n) of B
+  //   op 0 of A / op 1 of B: 64 consecutive rows of one k per wave
+  //   op 1 of A / op 0 of B: 16 consecutive k of four columns per wave
+  const int a_m = OPA == 0 ? (tid & 63) : (tid >> 4), a_k = OPA == 0 ? (tid >> 6) : (tid & 15);
+  const int b_n = OPB == 0 ? (tid >> 4) : (tid & 63), b_k = OPB == 0 ? (tid & 15) : (tid >> 6);
   C2 ra[4], rb[4];
-
   auto loadA = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      int m, k;
+      const int m = OPA == 0 ? a_m : a_m + 16 * i, k = OPA == 0 ? a_k + 4 * i : a_k;
+      const int gm = m0 + m, gk = k0 + k;
       C2 v;
-      if (OPA == 0) {
-        m = tid & 63; k = (tid >> 6) + 4 * i;
-        int gm = m0 + m, gk = k0 + k;
-        if (gm < p.M && gk < p.K) v = A[gm + (long)gk * p.lda]; else { v.x = 0; v.y = 0; }
-      } else {
-        k = tid & 15; m = (tid >> 4) + 16 * (i & 3);
-        int gm = m0 + m, gk = k0 + k;
-        if (gm < p.M && gk < p.K) { v = A[gk + (long)gm * p.lda]; v.y = -v.y; } else { v.x = 0; v.y = 0; }
-      }
-      if (p.kscale) {
-        int gk = k0 + k;
-        T sc = gk < p.K ? (T)p.kscale[gk] : T(0);
-        v.x *= sc; v.y *= sc;
+      v.x = 0; v.y = 0;
+      if (gm < p.M && gk < p.K) {
+        if (OPA == 0) v = A[gm + (long)gk * p.lda];
+        else { v = A[gk + (long)gm * p.lda]; v.y = -v.y; }
+        if (p.kscale) { const T sc = (T)p.kscale[gk]; v.x *= sc; v.y *= sc; }
       }
       ra[i] = v;
-    }
-  };
-  auto storeA = [&]() {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int m, k;
-      if (OPA == 0) { m = tid & 63; k = (tid >> 6) + 4 * i; }
-      else { k = tid & 15; m = (tid >> 4) + 16 * i; }
-      As[0][k][m] = ra[i].x; As[1][k][m] = ra[i].y;
     }
   };
   auto loadB = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
+      const int n = OPB == 0 ? b_n + 16 * i : b_n, k = OPB == 0 ? b_k : b_k + 4 * i;
+      const int gk = k0 + k, gn = n0 + n;
       C2 v;
-      if (OPB == 0) {
-        int k = tid & 15, n = (tid >> 4) + 16 * i;
-        int gk = k0 + k, gn = n0 + n;
-        if (gk < p.K && gn < p.N) v = B[gk + (long)gn * p.ldb]; else { v.x = 0; v.y = 0; }
-      } else {
-        int n = tid & 63, k = (tid >> 6) + 4 * i;
-        int gk = k0 + k, gn = n0 + n;
-        if (gk < p.K && gn < p.N) { v = B[gn + (long)gk * p.ldb]; v.y = -v.y; } else { v.x = 0; v.y = 0; }
+      v.x = 0; v.y = 0;
+      if (gk < p.K && gn < p.N) {
+        if (OPB == 0) v = B[gk + (long)gn * p.ldb];
+        else { v = B[gn + (long)gk * p.ldb]; v.y = -v.y; }
       }
       rb[i] = v;
     }
   };
-  auto storeB = [&]() {
+  auto store = [&](int buf) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      int n, k;
-      if (OPB == 0) { k = tid & 15; n = (tid >> 4) + 16 * i; }
-      else { n = tid & 63; k = (tid >> 6) + 4 * i; }
-      Bs[0][k][n] = rb[i].x; Bs[1][k][n] = rb[i].y;
+      const int m = OPA == 0 ? a_m : a_m + 16 * i, ka = OPA == 0 ? a_k + 4 * i : a_k;
+      As[buf][gemm_swz(ka, m)] = ra[i];
+      const int n = OPB == 0 ? b_n + 16 * i : b_n, kb = OPB == 0 ? b_k : b_k + 4 * i;
+      Bs[buf][gemm_swz(kb, n)] = rb[i];
     }
   };
 
   if (kbeg < kend) { loadA(kbeg); loadB(kbeg); }
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    __syncthreads();
-    storeA();
-    storeB();
+    store(buf);
     __syncthreads();
     if (k0 + BK < kend) { loadA(k0 + BK); loadB(k0 + BK); }
+    __builtin_amdgcn_sched_barrier(0);  // issue the next step's loads before the MFMAs
+    const C2* Ab = As[buf];
+    const C2* Bb = Bs[buf];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int kk = 4 * s + (lane >> 4);
-      T a_r[2], a_i[2], b_r[2], b_i[2];
+      C2 a[2], b[2];
+      T asum[2], bsum[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        a_r[t] = As[0][kk][wm + 16 * t + (lane & 15)];
-        a_i[t] = As[1][kk][wm + 16 * t + (lane & 15)];
-        b_r[t] = Bs[0][kk][wn + 16 * t + (lane & 15)];
-        b_i[t] = Bs[1][kk][wn + 16 * t + (lane & 15)];
+        a[t] = Ab[gemm_swz(kk, wm + 16 * t + (lane & 15))];
+        b[t] = Bb[gemm_swz(kk, wn + 16 * t + (lane & 15))];
+        asum[t] = a[t].x + a[t].y;
+        bsum[t] = b[t].x + b[t].y;
       }
+      // MFMA A operand: the B fragment (D row = n); B operand: the A fragment (D column = m)
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-        for (int tj = 0; tj < 2; ++tj)
-          cmac<T>(b_r[tj], b_i[tj], a_r[ti], a_i[ti], cr[ti][tj], ci[ti][tj]);
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj][0] = Mfma<T>::mac(b[tj].x, a[ti].x, acc[ti][tj][0]);
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj][1] = Mfma<T>::mac(b[tj].y, a[ti].y, acc[ti][tj][1]);
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) acc[ti][tj][2] = Mfma<T>::mac(bsum[tj], asum[ti], acc[ti][tj][2]);
     }
+    buf ^= 1;
   }
 
   // Epilogue: lane holds rows m0 + wm + 16 ti + lane % 16 of four columns.
@@ -151,7 +161,9 @@ BSE_DEV void GemmOp<T, OPA, OPB>::run(const GemmArgs<T>& p, int bx, int) {
         const int m = m0 + wm + 16 * ti + (lane & 15);
         const int n = n0 + wn + 16 * tj + Mfma<T>::drow(lane, r);
         if (m >= p.M || n >= p.N) continue;
-        T vr = cr[ti][tj][r], vi = ci[ti][tj][r];
+        // (Ar + i Ai)(Br + i Bi) = P1 - P2 + i (P3 - P1 - P2)
+        const T p1 = acc[ti][tj][0][r], p2 = acc[ti][tj][1][r], p3 = acc[ti][tj][2][r];
+        T vr = p1 - p2, vi = p3 - p1 - p2;
         T outr = p.ar * vr - p.ai * vi, outi = p.ar * vi + p.ai * vr;
         if (p.colscale) { T sc = (T)p.colscale[n]; outr *= sc; outi *= sc; }
         C2* cp = C + m + (long)n * p.ldc;
