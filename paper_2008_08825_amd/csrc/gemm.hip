@@ -26,16 +26,18 @@ constexpr int BM = 64, BN = 64, BK = 16;
 // LDS place of operand element (k, c) of a 16 x 64 staged tile
 BSE_DEV int gemm_swz(int k, int c) { return k * 64 + (c ^ k ^ ((k & 1) << 4)); }
 
-template <typename T, int OPA, int OPB>
+// KS: the product is A diag(kscale) B (only op(A) = A, op(B) = B^H is
+// instantiated with it, the form the adjoint sums take).
+template <typename T, int OPA, int OPB, bool KS = false>
 struct GemmOp {
   static constexpr int NT = 256;
-  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : 4;  // as many as the LDS allows
+  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : 3;  // registers for two staged steps
   typedef GemmArgs<T> Args;
   static BSE_DEV void run(const Args& p, int bx, int aux);
 };
 
-template <typename T, int OPA, int OPB>
-BSE_DEV void GemmOp<T, OPA, OPB>::run(const GemmArgs<T>& p, int bx, int) {
+template <typename T, int OPA, int OPB, bool KS>
+BSE_DEV void GemmOp<T, OPA, OPB, KS>::run(const GemmArgs<T>& p, int bx, int) {
   typedef typename cpx_t<T>::type C2;
   typedef typename Mfma<T>::acc Acc;
   __shared__ C2 As[2][BK * BM];
@@ -73,55 +75,52 @@ BSE_DEV void GemmOp<T, OPA, OPB>::run(const GemmArgs<T>& p, int bx, int) {
   //   op 1 of A / op 0 of B: 16 consecutive k of four columns per wave
   const int a_m = OPA == 0 ? (tid & 63) : (tid >> 4), a_k = OPA == 0 ? (tid >> 6) : (tid & 15);
   const int b_n = OPB == 0 ? (tid >> 4) : (tid & 63), b_k = OPB == 0 ? (tid & 15) : (tid >> 6);
-  C2 ra[4], rb[4];
-  auto loadA = [&](int k0) {
+  // two register sets of staged operands: steps s + 1 and s + 2 load while
+  // the MFMAs work on step s (prefetches past the last step re-read it, so
+  // that every step issues the same loads and the waits stay partial)
+  // Loads are unconditional (out-of-range lanes read a clamped in-range
+  // element) and do nothing else, so the waits for them stay partial; the
+  // masking of out-of-range elements, conjugation and k scaling happen when
+  // the staged values go to LDS.
+  C2 ra0[4], rb0[4], ra1[4], rb1[4];
+  T ks0[4], ks1[4];
+  auto load = [&](C2 (&ra)[4], C2 (&rb)[4], T (&ks)[4], int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = OPA == 0 ? a_m : a_m + 16 * i, k = OPA == 0 ? a_k + 4 * i : a_k;
-      const int gm = m0 + m, gk = k0 + k;
-      C2 v;
-      v.x = 0; v.y = 0;
-      if (gm < p.M && gk < p.K) {
-        if (OPA == 0) v = A[gm + (long)gk * p.lda];
-        else { v = A[gk + (long)gm * p.lda]; v.y = -v.y; }
-        if (p.kscale) { const T sc = (T)p.kscale[gk]; v.x *= sc; v.y *= sc; }
-      }
-      ra[i] = v;
+      const int cm = min(m0 + m, p.M - 1), ck = min(k0 + k, p.K - 1);
+      ra[i] = OPA == 0 ? A[cm + (long)ck * p.lda] : A[ck + (long)cm * p.lda];
+      if constexpr (KS) ks[i] = (T)p.kscale[ck];
     }
-  };
-  auto loadB = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int n = OPB == 0 ? b_n + 16 * i : b_n, k = OPB == 0 ? b_k : b_k + 4 * i;
-      const int gk = k0 + k, gn = n0 + n;
-      C2 v;
-      v.x = 0; v.y = 0;
-      if (gk < p.K && gn < p.N) {
-        if (OPB == 0) v = B[gk + (long)gn * p.ldb];
-        else { v = B[gn + (long)gk * p.ldb]; v.y = -v.y; }
-      }
-      rb[i] = v;
+      const int ck = min(k0 + k, p.K - 1), cn = min(n0 + n, p.N - 1);
+      rb[i] = OPB == 0 ? B[ck + (long)cn * p.ldb] : B[cn + (long)ck * p.ldb];
     }
   };
-  auto store = [&](int buf) {
+  auto store = [&](const C2 (&ra)[4], const C2 (&rb)[4], const T (&ks)[4], int k0, C2* Ab,
+                   C2* Bb) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int m = OPA == 0 ? a_m : a_m + 16 * i, ka = OPA == 0 ? a_k + 4 * i : a_k;
-      As[buf][gemm_swz(ka, m)] = ra[i];
+      const bool oka = m0 + m < p.M && k0 + ka < p.K;
+      T sa = oka ? T(1) : T(0);
+      if constexpr (KS) sa *= ks[i];
+      C2 va;
+      va.x = ra[i].x * sa;
+      va.y = OPA == 1 ? -ra[i].y * sa : ra[i].y * sa;
+      Ab[gemm_swz(ka, m)] = va;
       const int n = OPB == 0 ? b_n + 16 * i : b_n, kb = OPB == 0 ? b_k : b_k + 4 * i;
-      Bs[buf][gemm_swz(kb, n)] = rb[i];
+      const bool okb = k0 + kb < p.K && n0 + n < p.N;
+      const T sb = okb ? T(1) : T(0);
+      C2 vb;
+      vb.x = rb[i].x * sb;
+      vb.y = OPB == 1 ? -rb[i].y * sb : rb[i].y * sb;
+      Bb[gemm_swz(kb, n)] = vb;
     }
   };
-
-  if (kbeg < kend) { loadA(kbeg); loadB(kbeg); }
-  int buf = 0;
-  for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    store(buf);
-    __syncthreads();
-    if (k0 + BK < kend) { loadA(k0 + BK); loadB(k0 + BK); }
-    __builtin_amdgcn_sched_barrier(0);  // issue the next step's loads before the MFMAs
-    const C2* Ab = As[buf];
-    const C2* Bb = Bs[buf];
+  auto compute = [&](const C2* Ab, const C2* Bb) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int kk = 4 * s + (lane >> 4);
@@ -148,7 +147,31 @@ BSE_DEV void GemmOp<T, OPA, OPB>::run(const GemmArgs<T>& p, int bx, int) {
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj) acc[ti][tj][2] = Mfma<T>::mac(bsum[tj], asum[ti], acc[ti][tj][2]);
     }
-    buf ^= 1;
+  };
+
+  const int nsteps = kbeg < kend ? (kend - kbeg + BK - 1) / BK : 0;
+  auto kstep = [&](int i) { return kbeg + BK * min(i, nsteps - 1); };
+  int st = 0;
+  if (nsteps > 0) {
+    load(ra0, rb0, ks0, kstep(0));
+    load(ra1, rb1, ks1, kstep(1));
+    for (; st + 2 <= nsteps; st += 2) {
+      store(ra0, rb0, ks0, kstep(st), As[0], Bs[0]);
+      __syncthreads();
+      load(ra0, rb0, ks0, kstep(st + 2));
+      __builtin_amdgcn_sched_barrier(0);  // issue the prefetch before the MFMAs
+      compute(As[0], Bs[0]);
+      store(ra1, rb1, ks1, kstep(st + 1), As[1], Bs[1]);
+      __syncthreads();
+      load(ra1, rb1, ks1, kstep(st + 3));
+      __builtin_amdgcn_sched_barrier(0);
+      compute(As[1], Bs[1]);
+    }
+    if (st < nsteps) {  // an odd number of steps: the last one
+      store(ra0, rb0, ks0, kstep(st), As[0], Bs[0]);
+      __syncthreads();
+      compute(As[0], Bs[0]);
+    }
   }
 
   // Epilogue: lane holds rows m0 + wm + 16 ti + lane % 16 of four columns.
@@ -200,6 +223,10 @@ hipError_t gemm_launch(const GemmDesc& d, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
   const GemmArgs<T> p = make_args<T>(d);
   const int blocks = p.tilesM * p.tilesN;
+  if (d.kscale) {
+    if (d.opA == 0 && d.opB == 1) return launch_one<GemmOp<T, 0, 1, true>>(p, blocks, 0, s);
+    return hipErrorInvalidValue;
+  }
   if (d.opA == 0 && d.opB == 0) return launch_one<GemmOp<T, 0, 0>>(p, blocks, 0, s);
   if (d.opA == 0 && d.opB == 1) return launch_one<GemmOp<T, 0, 1>>(p, blocks, 0, s);
   if (d.opA == 1 && d.opB == 0) return launch_one<GemmOp<T, 1, 0>>(p, blocks, 0, s);
