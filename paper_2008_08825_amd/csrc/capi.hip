@@ -307,7 +307,8 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
 // Mixed form with an FP64 Jacobi polish (BSE_PREC_MIXED_POLISH).
 //   1. M1, M2, their FP64 Cholesky factors and W = L2^H L1 in FP64.
 //   2. One-sided Jacobi on a complex64 copy of W (FP32 MFMA) to the FP32
-//      tolerance: Z = W32 V32 with V32 the product of the applied rotations.
+//      tolerance, or until a sweep rotates fewer than 1/32 of its pairs:
+//      Z = W32 V32 with V32 the product of the applied rotations.
 //   3. V' = W^-1 Z = L1^-1 (L2^-H Z) by two FP64 block triangular solves;
 //      V' is unitary up to the complex64 rounding of the iteration.
 //   4. Cholesky QR in FP64: V'^H V' = L_G L_G^H and V = V' L_G^-H is unitary
@@ -367,7 +368,9 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   }
   tm.mark();
   JacobiResult j32;
-  BSE_TRY(jacobi_c(np, Wc, ld, jw32, tol32, 1.0e-5, max32, j32, s, want_timing >= 2));
+  // The complex64 iteration only prepares the FP64 sweeps: it ends once a
+  // sweep rotates fewer than 1/32 of its pairs, when the rest is rounding.
+  BSE_TRY(jacobi_c(np, Wc, ld, jw32, tol32, 1.0e-5, max32, j32, s, want_timing >= 2, 1.0, 1.0 / 32));
   tm.mark();
   // Z = W32 V32 in FP64 (Y); V' = L1^-1 L2^-H Z (W)
   BSE_TRY(c64_to_c128(np, Wc, ld, Y, ld, nullptr, s));
@@ -396,7 +399,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
     BSE_TRY(gemm_z(g, s));
   }
   JacobiResult j64;
-  const double first = fmin(kInnerStopCap, fmax(1.0e-10, j32.max_off));
+  const double first = fmin(kInnerStopCap, fmax(1.0e-10, fmin(j32.max_off, tol32)));
   BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, want_timing >= 2, first));
   tm.mark();
   BSE_TRY(scale_singular_cols_z(n, np, X1, ld, sigma, bnorm, s));  // Ws = (W V Q) sigma^-3/2

@@ -94,9 +94,12 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
 // the inner stopping level (1 by default; smaller values leave the columns
 // more orthogonal at the end, which the Newton refinement of the mixed form
 // needs).
+// stop_fraction: when positive, the iteration also ends after a sweep that
+// rotated fewer than this fraction of its pair checks (the sweeps that would
+// follow only chase complex64 rounding; converged stays 0 then).
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
                     int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false,
-                    double inner_factor = 1.0);
+                    double inner_factor = 1.0, double stop_fraction = 0.0);
 
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status, int base,
                       hipStream_t s);

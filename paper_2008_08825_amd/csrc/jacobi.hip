@@ -875,7 +875,7 @@ template <typename T>
 static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const JacobiWork& w,
                              double tol, double inner_stop, int max_sweeps, JacobiResult& res,
                              hipStream_t s, bool time_kernels, double first_stop = kInnerStopCap,
-                             double inner_factor = 1.0) {
+                             double inner_factor = 1.0, double stop_fraction = 0.0) {
   typedef typename cpx_t<T>::type C2;
   const int N = np / JB, pairs = N / 2;
   const int gblocks = jacobi_gram_blocks_kc(np, w.kc);
@@ -957,6 +957,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     res.pair_checks += pairs * (N - 1);
     res.max_off = mo;
     if (cnt == 0) { res.converged = 1; break; }
+    if (stop_fraction > 0.0 && cnt < stop_fraction * pairs * (N - 1)) break;
   }
   for (auto& x : ev) (void)hipEventDestroy(x);
   return ret;
@@ -970,9 +971,9 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
 
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
                     int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels,
-                    double inner_factor) {
+                    double inner_factor, double stop_fraction) {
   return jacobi_run<float>(np, W, ld, w, tol, inner_stop, max_sweeps, res, s, time_kernels,
-                           kInnerStopCap, inner_factor);
+                           kInnerStopCap, inner_factor, stop_fraction);
 }
 
 GramArgs<double2> gram_args_z(int np, double2* W, long ld, const JacobiWork& w, const int* done) {
