@@ -388,16 +388,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   }
   BSE_TRY(tri_pad_z(n, np, X2, ld, 0, s));
   BSE_TRY(cholesky_z(np, n, X2, ld, linv, status, 0, s));  // G = L_G L_G^H
-  BSE_TRY(tri_pad_z(n, np, X1, ld, 1, s));
-  BSE_TRY(trsm_ln_z(np, X2, ld, X1, W, inv, s));    // W = L_G^-1 (X1 = I is overwritten)
-  {
-    GemmDesc g;  // W V = Z L_G^-H (Y)  ->  X1
-    g.M = np; g.N = np; g.K = np;
-    g.A = Y; g.lda = ld; g.opA = 0;
-    g.B = W; g.ldb = ld; g.opB = 1; g.triB = 1;
-    g.C = X1; g.ldc = ld;
-    BSE_TRY(gemm_z(g, s));
-  }
+  BSE_TRY(trsm_rh_z(np, X2, ld, Y, X1, inv, s));    // W V = Z L_G^-H -> X1 (Y is overwritten)
   JacobiResult j64;
   const double first = fmin(kInnerStopCap, fmax(1.0e-10, fmin(j32.max_off, tol32)));
   BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, want_timing >= 2, first));

@@ -429,6 +429,33 @@ hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
   return hipSuccess;
 }
 
+hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
+                     hipStream_t s) {
+  const int nb = np / NB;
+  k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  for (int j = 0; j < nb; ++j) {
+    // Z_j = Rhs_j (L_jj^-1)^H   (column block j)
+    GemmDesc g;
+    g.M = np; g.N = NB; g.K = NB;
+    g.A = Rhs + (long)j * NB * ld; g.lda = ld; g.opA = 0;
+    g.B = inv + (long)j * NB * NB; g.ldb = NB; g.opB = 1; g.triB = 1;
+    g.C = Z + (long)j * NB * ld; g.ldc = ld;
+    if ((e = gemm_z(g, s)) != hipSuccess) return e;
+    if (j == nb - 1) break;
+    // Rhs_{j+1..} -= Z_j (L_{j+1.., j})^H
+    GemmDesc u;
+    u.M = np; u.N = np - (j + 1) * NB; u.K = NB;
+    u.A = Z + (long)j * NB * ld; u.lda = ld; u.opA = 0;
+    u.B = L + (long)(j + 1) * NB + (long)j * NB * ld; u.ldb = ld; u.opB = 1;
+    u.C = Rhs + (long)(j + 1) * NB * ld; u.ldc = ld;
+    u.alpha_re = -1.0; u.beta_re = 1.0;
+    if ((e = gemm_z(u, s)) != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status,
                       int base, hipStream_t s) {
   return cholesky_run<float2>(np, n_real, M, ld, linv, status, base, s);

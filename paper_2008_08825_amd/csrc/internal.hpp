@@ -116,6 +116,9 @@ hipError_t tri_pad_z(int n, int np, double2* M, long ld, int identity, hipStream
 // Z = L^-1 Rhs (forward block substitution, same conventions as trsm_lh_z).
 hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s);
+// Z = Rhs L^-H (column blocks left to right, same conventions as trsm_lh_z).
+hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
+                     hipStream_t s);
 // M[i][j] = conj(M[j][i]) for i < j (np % 64 == 0).
 hipError_t mirror_upper_z(int np, double2* M, long ld, hipStream_t s);
 // complex64 copy of the lower triangle, strict upper part zero.
