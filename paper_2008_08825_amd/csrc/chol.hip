@@ -93,11 +93,51 @@ BSE_DEV void FormOp::run(const FormArgs& a, int bx, int) {
   }
 }
 
+// Inverse X = L^-1 of the lower triangle L held in (Lr, Li) (real positive
+// diagonal), 256 threads, into (Xr, Xi) with a zero strict upper triangle.
+// Row elimination with one barrier per step: Y starts as I; step j subtracts
+// L[i][j] Y[j][:] / L[j][j] from every row i > j (row j is final then, up to
+// its division by L[j][j], which the last pass applies to every row).
+BSE_DEV void tri_inverse_lds(const double (*Lr)[NB + 1], const double (*Li)[NB + 1],
+                             double (*Xr)[NB + 1], double (*Xi)[NB + 1], int tid) {
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;
+    Xr[r][c] = (r == c) ? 1.0 : 0.0;
+    Xi[r][c] = 0.0;
+  }
+  __syncthreads();
+  const int c = tid & 63, i0 = tid >> 6;
+  for (int j = 0; j < NB - 1; ++j) {
+    if (c <= j) {
+      const double rj = 1.0 / Lr[j][j];
+      const double yr = Xr[j][c] * rj, yi = Xi[j][c] * rj;
+      for (int i = j + 1 + i0; i < NB; i += 4) {
+        const double lr = Lr[i][j], li = Li[i][j];
+        Xr[i][c] -= lr * yr - li * yi;
+        Xi[i][c] -= lr * yi + li * yr;
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, cc = (tid >> 6) + 4 * q;
+    const double rr = 1.0 / Lr[r][r];
+    Xr[r][cc] *= rr;
+    Xi[r][cc] *= rr;
+  }
+  __syncthreads();
+}
+
 // Unblocked Cholesky of the diagonal block M[j0:j0+64, j0:j0+64] (lower) and
 // the inverse of the resulting triangle, in one workgroup.  Writes L11 back
 // with a zero strict upper triangle and L11^-1 (64 x 64, ld 64) to `linv`.
 // C2 is the storage type (double2, or float2 in the mixed form); the block is
 // factored in FP64 either way.
+//
+// The columns stay unscaled during the elimination (step j subtracts
+// L[i][j] conj(L[k][j]) / L[j][j] from L[i][k], k > j, reading only column j,
+// which the step does not write), so each step needs one barrier; the
+// columns are scaled by 1 / sqrt(L[j][j]) at the end.
 template <typename C2>
 struct Potf2Op {
   static constexpr int NT = 256;
@@ -114,7 +154,7 @@ BSE_DEV void Potf2Op<C2>::run(const Potf2Args<C2>& a, int, int j0) {
   const int base = a.base, n_real = a.n_real;
   __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
   __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
-  __shared__ int failed;
+  __shared__ double sc[NB];
   const int tid = threadIdx.x;
   C2* D = M + j0 + (long)j0 * ld;
   for (int q = 0; q < 16; ++q) {
@@ -123,60 +163,35 @@ BSE_DEV void Potf2Op<C2>::run(const Potf2Args<C2>& a, int, int j0) {
     if (r >= c) { const C2 v = D[r + (long)c * ld]; vr = v.x; vi = v.y; }
     Lr[r][c] = vr; Li[r][c] = vi;
   }
-  if (tid == 0) failed = 0;
   __syncthreads();
+  const int i = tid & 63;
   for (int j = 0; j < NB; ++j) {
-    if (tid == 0) {
-      double d = Lr[j][j];
-      if (!(d > 0.0)) {
-        failed = 1;
-        if (j0 + j < n_real) atomicMin(status, base + j0 + j + 1);
-      } else {
-        Lr[j][j] = sqrt(d);
-        Li[j][j] = 0.0;
-      }
+    const double d = Lr[j][j];  // every thread reads the same pivot
+    if (!(d > 0.0)) {
+      // leave the block as is; the caller stops after reading the status
+      if (tid == 0 && j0 + j < n_real) atomicMin(status, base + j0 + j + 1);
+      return;
     }
-    __syncthreads();
-    if (failed) break;
-    const double inv = 1.0 / Lr[j][j];
-    if (tid > j && tid < NB) { Lr[tid][j] *= inv; Li[tid][j] *= inv; }
-    __syncthreads();
-    // trailing update of the block: L[i][k] -= L[i][j] conj(L[k][j]), j < k <= i
-    {
-      const int i = tid & 63;
-      if (i > j) {
-        const double lr = Lr[i][j], li = Li[i][j];
-        for (int k = j + 1 + (tid >> 6); k <= i; k += 4) {
-          const double kr = Lr[k][j], ki = Li[k][j];
-          Lr[i][k] -= lr * kr + li * ki;
-          Li[i][k] -= li * kr - lr * ki;
-        }
+    if (i > j) {
+      const double rd = 1.0 / d;
+      const double lr = Lr[i][j] * rd, li = Li[i][j] * rd;
+      for (int k = j + 1 + (tid >> 6); k <= i; k += 4) {
+        const double kr = Lr[k][j], ki = Li[k][j];
+        Lr[i][k] -= lr * kr + li * ki;
+        Li[i][k] -= li * kr - lr * ki;
       }
     }
     __syncthreads();
   }
-  if (failed) {
-    // leave the block as is; the caller stops after reading the status
-    return;
-  }
-  // Inverse of the lower triangle, one column per thread (forward substitution).
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) { Xr[i][c] = 0.0; Xi[i][c] = 0.0; }
-    Xr[c][c] = 1.0 / Lr[c][c];
-    for (int i = c + 1; i < NB; ++i) {
-      double sr = 0.0, si = 0.0;
-      for (int k = c; k < i; ++k) {
-        const double ar = Lr[i][k], ai = Li[i][k], xr = Xr[k][c], xi = Xi[k][c];
-        sr += ar * xr - ai * xi;
-        si += ar * xi + ai * xr;
-      }
-      const double dinv = 1.0 / Lr[i][i];
-      Xr[i][c] = -sr * dinv;
-      Xi[i][c] = -si * dinv;
-    }
+  if (tid < NB) sc[tid] = 1.0 / sqrt(Lr[tid][tid]);
+  __syncthreads();
+  for (int q = 0; q < 16; ++q) {
+    const int r = tid & 63, c = (tid >> 6) + 4 * q;
+    if (r > c) { Lr[r][c] *= sc[c]; Li[r][c] *= sc[c]; }
+    else if (r == c) { Lr[r][c] *= sc[c]; Li[r][c] = 0.0; }
   }
   __syncthreads();
+  tri_inverse_lds(Lr, Li, Xr, Xi, tid);
   for (int q = 0; q < 16; ++q) {
     int r = tid & 63, c = (tid >> 6) + 4 * q;
     C2 l, x;
@@ -204,24 +219,7 @@ __global__ __launch_bounds__(256) void k_tri_inv_blocks(const double2* __restric
     Lr[r][c] = v.x; Li[r][c] = v.y;
   }
   __syncthreads();
-  if (tid < NB) {
-    const int c = tid;
-    for (int i = 0; i < NB; ++i) { Xr[i][c] = 0.0; Xi[i][c] = 0.0; }
-    // L has a real positive diagonal
-    Xr[c][c] = 1.0 / Lr[c][c];
-    for (int i = c + 1; i < NB; ++i) {
-      double sr = 0.0, si = 0.0;
-      for (int k = c; k < i; ++k) {
-        const double ar = Lr[i][k], ai = Li[i][k], xr = Xr[k][c], xi = Xi[k][c];
-        sr += ar * xr - ai * xi;
-        si += ar * xi + ai * xr;
-      }
-      const double dinv = 1.0 / Lr[i][i];
-      Xr[i][c] = -sr * dinv;
-      Xi[i][c] = -si * dinv;
-    }
-  }
-  __syncthreads();
+  tri_inverse_lds(Lr, Li, Xr, Xi, tid);
   double2* out = inv + (long)blockIdx.x * NB * NB;
   for (int q = 0; q < 16; ++q) {
     const int r = tid & 63, c = (tid >> 6) + 4 * q;
