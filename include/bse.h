@@ -97,11 +97,15 @@ typedef struct {
                            refinement correction (error left ~ its square)    */
   double ms_phase[8];   /* phase times (ms): form, chol, W, jacobi, finalize,
                            back-transform, refine, total; filled if requested  */
-  int timing;           /* in: 0 none; 1 fill ms_phase; 2 also time every
-                           Jacobi kernel launch with HIP events on `stream`   */
+  int timing;           /* in: 0 none; 1 fill ms_phase; 2 also time the
+                           Jacobi kernels of every 8th round with HIP events
+                           on `stream` (a sample: the events then cost the
+                           solve no measurable time); 3 time every round     */
   int pair_checks;      /* block pairs examined over all sweeps               */
-  double kernel_ms[3];  /* timing == 2: summed durations of the Jacobi Gram,
-                           inner-eigensolver and rotation kernels (ms)        */
+  double kernel_ms[3];  /* timing >= 2: durations of the Jacobi Gram,
+                           inner-eigensolver and rotation kernels (ms) summed
+                           over all launches (timing 2: the timed rounds'
+                           mean duration times the number of launches)        */
   int kernel_launches[3];
   int refine_steps_done; /* mixed: refinement steps run                       */
   double inner_rotations; /* 2 x 2 rotations applied inside the block-pair

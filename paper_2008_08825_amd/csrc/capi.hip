@@ -110,7 +110,7 @@ int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* la
   }
   tm.mark();
   JacobiResult jr;
-  BSE_TRY(jacobi_z(np, W, ld, jw, tol, max_sweeps, jr, s, want_timing >= 2));
+  BSE_TRY(jacobi_z(np, W, ld, jw, tol, max_sweeps, jr, s, kernel_time_stride(want_timing)));
   tm.mark();
   BSE_TRY(scale_singular_cols_z(n, np, W, ld, sigma, bnorm, s));  // Ws = W sigma^-3/2
   tm.mark();
@@ -187,7 +187,7 @@ int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* la
   }
   tm.mark();
   JacobiResult jr;
-  BSE_TRY(jacobi_z(np, Y, ld, jw, tol, max_sweeps, jr, s, want_timing >= 2));
+  BSE_TRY(jacobi_z(np, Y, ld, jw, tol, max_sweeps, jr, s, kernel_time_stride(want_timing)));
   tm.mark();
   BSE_TRY(colnorm_z(np, Y, ld, d, s));
   BSE_TRY(alg2_lambda_z(n, d, lamu, perm, lambda, o.want_negative, fx, fy, s));
@@ -267,7 +267,7 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   }
   tm.mark();
   JacobiResult jr;
-  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, want_timing >= 2, 0.3));
+  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, kernel_time_stride(want_timing), 0.3));
   tm.mark();
   BSE_TRY(scale_singular_cols_c(n, np, Wc, ld, sigma, bnorm, s));
   tm.mark();
@@ -370,7 +370,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   JacobiResult j32;
   // The complex64 iteration only prepares the FP64 sweeps: it ends once a
   // sweep rotates fewer than 1/32 of its pairs, when the rest is rounding.
-  BSE_TRY(jacobi_c(np, Wc, ld, jw32, tol32, 1.0e-5, max32, j32, s, want_timing >= 2, 1.0, 1.0 / 32));
+  BSE_TRY(jacobi_c(np, Wc, ld, jw32, tol32, 1.0e-5, max32, j32, s, kernel_time_stride(want_timing), 1.0, 1.0 / 32));
   tm.mark();
   // Z = W32 V32 in FP64 (Y); V' = L1^-1 L2^-H Z (W)
   BSE_TRY(c64_to_c128(np, Wc, ld, Y, ld, nullptr, s));
@@ -391,7 +391,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   BSE_TRY(trsm_rh_z(np, X2, ld, Y, X1, inv, s));    // W V = Z L_G^-H -> X1 (Y is overwritten)
   JacobiResult j64;
   const double first = fmin(kInnerStopCap, fmax(1.0e-10, fmin(j32.max_off, tol32)));
-  BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, want_timing >= 2, first));
+  BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, kernel_time_stride(want_timing), first));
   tm.mark();
   BSE_TRY(scale_singular_cols_z(n, np, X1, ld, sigma, bnorm, s));  // Ws = (W V Q) sigma^-3/2
   tm.mark();

@@ -72,7 +72,8 @@ struct JacobiResult {
   double inner_rotations = 0.0;
   double max_off = 0.0;
   int converged = 0;
-  // per-kernel event timing (filled when time_kernels is set)
+  // per-kernel event timing (filled when time_stride > 0): summed durations,
+  // estimated from the timed rounds when not every round is timed
   double kernel_ms[3] = {0.0, 0.0, 0.0};
   int kernel_launches[3] = {0, 0, 0};
 };
@@ -84,9 +85,15 @@ struct JacobiResult {
 constexpr double kInnerStopCap = 3.0e-2;
 // first_stop: inner stopping level of the first sweep (later sweeps use the
 // previous sweep's largest off-diagonal measure, at most kInnerStopCap).
+// time_stride: 0 no kernel timing; k > 0 HIP events around the three
+// kernels of every k-th round (each sweep's rounds 0, k, 2k, ...).
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, int time_stride = 0,
                     double first_stop = kInnerStopCap);
+// Event stride for the `timing` option of bse_info_t: 2 times every 8th
+// round (a sample, so that the events do not slow the solve measurably), 3
+// every round.
+inline int kernel_time_stride(int timing) { return timing >= 3 ? 1 : timing == 2 ? 8 : 0; }
 // complex64 columns; Gram partial sums, inner eigensolver and rotations as in
 // jacobi_z (inner eigensolver in FP64), inner iteration ending once a sweep's
 // largest relative off-diagonal entry is below inner_stop.
@@ -98,7 +105,7 @@ hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol
 // rotated fewer than this fraction of its pair checks (the sweeps that would
 // follow only chase complex64 rounding; converged stays 0 then).
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels = false,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, int time_stride = 0,
                     double inner_factor = 1.0, double stop_fraction = 0.0);
 
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status, int base,

@@ -874,7 +874,7 @@ RotArgs<C2> make_rot(int np, C2* W, long ld, const JacobiWork& w, const int* don
 template <typename T>
 static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const JacobiWork& w,
                              double tol, double inner_stop, int max_sweeps, JacobiResult& res,
-                             hipStream_t s, bool time_kernels, double first_stop = kInnerStopCap,
+                             hipStream_t s, int time_stride, double first_stop = kInnerStopCap,
                              double inner_factor = 1.0, double stop_fraction = 0.0) {
   typedef typename cpx_t<T>::type C2;
   const int N = np / JB, pairs = N / 2;
@@ -885,7 +885,9 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
   const RotArgs<C2> ra = make_rot<C2>(np, W, ld, w, nullptr);
   res = JacobiResult();
   hipError_t e;
-  // Optional per-launch timing: an event before and after every Jacobi kernel.
+  // Optional per-launch timing: an event before and after every Jacobi kernel
+  // of every time_stride-th round.
+  const bool time_kernels = time_stride > 0;
   std::vector<hipEvent_t> ev;
   if (time_kernels) {
     ev.resize((size_t)(N - 1) * 6);
@@ -894,8 +896,9 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
       if (e != hipSuccess) return e;
     }
   }
-  auto mark = [&](size_t i) {
-    if (time_kernels) (void)hipEventRecord(ev[i], s);
+  auto timed = [&](int t) { return time_kernels && t % time_stride == 0; };
+  auto mark = [&](int t, size_t i) {
+    if (timed(t)) (void)hipEventRecord(ev[i], s);
   };
   hipError_t ret = hipSuccess;
   const bool debug = getenv("BSE_DEBUG") != nullptr;
@@ -917,15 +920,15 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     if (e != hipSuccess) { ret = e; break; }
     for (int t = 0; t < N - 1; ++t) {
       const size_t b = (size_t)t * 6;
-      mark(b + 0);
+      mark(t, b + 0);
       e = launch_one<GramOp<T>>(ga, gblocks, t, s);
-      mark(b + 1);
-      mark(b + 2);
+      mark(t, b + 1);
+      mark(t, b + 2);
       if (e == hipSuccess) e = launch_one<EigOp<T>>(ea, pairs, t, s);
-      mark(b + 3);
-      mark(b + 4);
+      mark(t, b + 3);
+      mark(t, b + 4);
       if (e == hipSuccess) e = launch_one<RotOp<T>>(ra, rblocks, t, s);
-      mark(b + 5);
+      mark(t, b + 5);
       if (e != hipSuccess) break;
     }
     if (e != hipSuccess) { ret = e; break; }
@@ -938,13 +941,21 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) { ret = e; break; }
     if (time_kernels) {
-      for (int t = 0; t < N - 1; ++t)
+      double msum[3] = {0.0, 0.0, 0.0};
+      int timed_rounds = 0;
+      for (int t = 0; t < N - 1; ++t) {
+        if (!timed(t)) continue;
+        ++timed_rounds;
         for (int kx = 0; kx < 3; ++kx) {
           float ms = 0.f;
           (void)hipEventElapsedTime(&ms, ev[(size_t)t * 6 + 2 * kx], ev[(size_t)t * 6 + 2 * kx + 1]);
-          res.kernel_ms[kx] += ms;
-          res.kernel_launches[kx] += 1;
+          msum[kx] += ms;
         }
+      }
+      for (int kx = 0; kx < 3; ++kx) {
+        res.kernel_ms[kx] += msum[kx] * (N - 1) / timed_rounds;
+        res.kernel_launches[kx] += N - 1;
+      }
     }
     if (debug)
       fprintf(stderr, "[bse] sweep %d: rotated pairs %d of %d, max off %.3e, inner sweeps %.2f per pair\n",
@@ -964,15 +975,15 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
 }
 
 hipError_t jacobi_z(int np, double2* W, long ld, const JacobiWork& w, double tol,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, int time_stride,
                     double first_stop) {
-  return jacobi_run<double>(np, W, ld, w, tol, 1.0e-10, max_sweeps, res, s, time_kernels, first_stop);
+  return jacobi_run<double>(np, W, ld, w, tol, 1.0e-10, max_sweeps, res, s, time_stride, first_stop);
 }
 
 hipError_t jacobi_c(int np, float2* W, long ld, const JacobiWork& w, double tol, double inner_stop,
-                    int max_sweeps, JacobiResult& res, hipStream_t s, bool time_kernels,
+                    int max_sweeps, JacobiResult& res, hipStream_t s, int time_stride,
                     double inner_factor, double stop_fraction) {
-  return jacobi_run<float>(np, W, ld, w, tol, inner_stop, max_sweeps, res, s, time_kernels,
+  return jacobi_run<float>(np, W, ld, w, tol, inner_stop, max_sweeps, res, s, time_stride,
                            kInnerStopCap, inner_factor, stop_fraction);
 }
 
