@@ -116,7 +116,8 @@ def test_tamm_dancoff(gpu_lib):
     assert om.rel_eig_err(lam, np.linalg.eigvalsh(A)) < 1e-12
 
 
-def test_condition_family(gpu_lib):
+@pytest.mark.parametrize("precision", ["fp64", "mixed_polish"])
+def test_condition_family(gpu_lib, precision):
     """Sec. 4 generator with closed-form eigenvalues sqrt(3)/2 d (kappa = 10 and 1e3).
 
     Bound: n * eps * kappa, the error level of a Gram-based Jacobi SVD on a
@@ -126,10 +127,10 @@ def test_condition_family(gpu_lib):
     n = 200
     for kappa in (10.0, 1e3):
         A, B, d = inputs.condition_family(n, kappa, seed=1)
-        lam, X, _ = run(gpu_lib, A, B)
+        lam, X, _ = run(gpu_lib, A, B, precision=precision)
         exact = np.sqrt(3) / 2 * d
         e = om.rel_eig_err(lam, exact)
-        print(f"kappa={kappa:g} rel_eig_err={e:.3e}")
+        print(f"{precision} kappa={kappa:g} rel_eig_err={e:.3e}")
         assert e < n * np.finfo(float).eps * kappa
         # V1 = M1 V2 / lambda (Lemma SVDScalarFactors) carries the error of V2
         # amplified by ||H|| / lambda <= kappa into the residual.
@@ -282,7 +283,7 @@ def test_alg2_mixed_is_rejected(gpu_lib):
 
 
 # ---------------------------------------------------------------- mixed form with FP64 Jacobi polish
-@pytest.mark.parametrize("n", [1, 5, 64, 100, 200])
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 100, 130, 200, 257])
 def test_mixed_polish_parity(gpu_lib, n):
     """complex64 Jacobi + FP64 polish: the FP64 form's bars (eigenvalues, vectors, residual)."""
     A, B = inputs.coupled(n, seed=700 + n)
@@ -307,3 +308,28 @@ def test_mixed_polish_status_and_route(gpu_lib):
     with pytest.raises(Exception):
         gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV),
                          route="eig", precision="mixed_polish")
+
+
+def test_mixed_polish_deterministic(gpu_lib):
+    A, B = inputs.coupled(150, seed=14)
+    lam1, X1, _ = run(gpu_lib, A, B, precision="mixed_polish")
+    lam2, X2, _ = run(gpu_lib, A, B, precision="mixed_polish")
+    assert np.array_equal(lam1, lam2) and np.array_equal(X1, X2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_polish"])
+def test_kernel_timing_options(gpu_lib, precision):
+    """timing 2 (every 8th round timed) and 3 (every round) leave the results
+    unchanged and report the same launch counts and comparable kernel times."""
+    n = 600  # np = 640: 19 rounds per sweep, so the 8th-round sample has 3 per sweep
+    A, B = inputs.coupled(n, seed=15)
+    At, Bt = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    lam0, X0, i0 = gpu_lib.solve_h1(At, Bt, precision=precision, timing=0)
+    lam2, X2, i2 = gpu_lib.solve_h1(At, Bt, precision=precision, timing=2)
+    lam3, X3, i3 = gpu_lib.solve_h1(At, Bt, precision=precision, timing=3)
+    assert torch.equal(lam0, lam2) and torch.equal(lam0, lam3)
+    assert torch.equal(X0.resolve_conj(), X2.resolve_conj()) and torch.equal(X0.resolve_conj(), X3.resolve_conj())
+    assert all(v == 0.0 for v in i0["kernel_ms"])
+    assert i2["kernel_launches"] == i3["kernel_launches"] and min(i3["kernel_launches"]) > 0
+    for a, b in zip(i2["kernel_ms"], i3["kernel_ms"]):
+        assert a > 0.0 and b > 0.0 and 0.5 < a / b < 2.0, (i2["kernel_ms"], i3["kernel_ms"])
