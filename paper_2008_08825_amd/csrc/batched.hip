@@ -417,17 +417,24 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : nn * eps64);
       if (mixed) {
         float2* W = pr->at<float2>(pr->p.off_wc);
-        gc.add(gram_args_c(np, W, np, jw, &st->done), jacobi_gram_blocks_kc(np, jw.kc));
-        ec.add(eig_args_c(np, jw, tol, &st->stop2, &st->done), jacobi_eig_blocks(np));
+        GramArgs<float2> ga = gram_args_c(np, W, np, jw, &st->done);
+        EigArgs<float2> ea = eig_args_c(np, jw, tol, &st->stop2, &st->done);
+        ga.crossp = ea.crossp = &st->cross;
+        gc.add(ga, jacobi_gram_blocks_kc(np, jw.kc));
+        ec.add(ea, jacobi_eig_blocks(np));
         rc.add(rot_args_c(np, W, np, jw, &st->done), jacobi_rot_blocks_rr(np, jw.rrows));
       } else {
         double2* W = pr->at<double2>(pr->p.off_w);
-        gz.add(gram_args_z(np, W, np, jw, &st->done), jacobi_gram_blocks_kc(np, jw.kc));
-        ez.add(eig_args_z(np, jw, tol, &st->stop2, &st->done), jacobi_eig_blocks(np));
+        GramArgs<double2> ga = gram_args_z(np, W, np, jw, &st->done);
+        EigArgs<double2> ea = eig_args_z(np, jw, tol, &st->stop2, &st->done);
+        ga.crossp = ea.crossp = &st->cross;
+        gz.add(ga, jacobi_gram_blocks_kc(np, jw.kc));
+        ez.add(ea, jacobi_eig_blocks(np));
         rz.add(rot_args_z(np, W, np, jw, &st->done), jacobi_rot_blocks_rr(np, jw.rrows));
       }
       const SweepArgs sa = {st, d_active, jacobi_pairs(np) * jacobi_rounds(np), max_sweeps,
-                            mixed ? 1.0e-5 : 1.0e-10, 1, mixed ? 0.3 : 1.0};
+                            mixed ? 1.0e-5 : 1.0e-10, 1, mixed ? 0.3 : 1.0,
+                            mixed ? kTrackLevel32 : kTrackLevel64};
       sw.add(sa, 1);
       rounds.push_back(jacobi_rounds(np));
     }

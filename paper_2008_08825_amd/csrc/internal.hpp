@@ -46,6 +46,7 @@ hipError_t form_m12(int n, int np, const double2* A, long lda, const double2* B,
 struct JacobiWork {
   void* part = nullptr;    // partial Gram tiles
   void* R = nullptr;       // rotations, pairs x 64 x 64
+  double2* track = nullptr;  // per column block: its 32 x 32 Gram (FP64)
   int* flags = nullptr;    // per pair
   int* counter = nullptr;  // rotated pairs in the current sweep
   int* inner = nullptr;    // inner Jacobi sweeps in the current sweep
@@ -83,6 +84,15 @@ struct JacobiResult {
 // Largest inner stopping level of the pair eigensolver (early outer sweeps,
 // where the other pairs disturb a pair's orthogonality far more anyway).
 constexpr double kInnerStopCap = 3.0e-2;
+// A sweep that follows one whose largest relative off-diagonal measure was
+// above this level computes only the cross blocks of the pair Grams after its
+// first round and tracks the diagonal blocks (the Gram each rotation leaves on
+// its two column blocks, kept in FP64).  The tracked blocks drift from the
+// data's by the rounding of the rotations, about 1e-11 (FP64) or 1e-5
+// (complex64) per sweep, far below the off-diagonal level of such sweeps; the
+// sweeps near convergence recompute every Gram tile.
+constexpr double kTrackLevel64 = 1.0e-4;
+constexpr double kTrackLevel32 = 1.0e-3;
 // first_stop: inner stopping level of the first sweep (later sweeps use the
 // previous sweep's largest off-diagonal measure, at most kInnerStopCap).
 // time_stride: 0 no kernel timing; k > 0 HIP events around the three
@@ -221,13 +231,19 @@ template <typename T> struct GemmArgs {
   int lowerC, mask;
   int tilesM, tilesN;
 };
+// cross != 0: rounds after the first of a sweep compute only the cross block
+// X_q^H X_p of a pair's Gram; the inner eigensolver takes the diagonal blocks
+// from `track` (per column block, the 32 x 32 Gram left by the block's last
+// rotation, FP64, column-major), which it writes back after every pair.
+// crossp, when set, points at a per-problem device flag used instead of cross.
 template <typename C2> struct GramArgs {  // aux = round
-  int N; const C2* W; long ld; int rc, kc; C2* part; const int* done;
+  int N; const C2* W; long ld; int rc, kc; C2* part; const int* done; int cross;
+  const int* crossp;
 };
 template <typename C2> struct EigArgs {  // aux = round
   int N, kc; const C2* part; C2* R; int* flags; int* counter; double tol; double* maxoff;
   int max_inner; int* inner; double inner_stop2; const double* stop2p; int* inner_rot;
-  const int* done;
+  const int* done; double2* track; int cross; const int* crossp;
 };
 template <typename C2> struct RotArgs {  // aux = round
   int N; C2* W; long ld; const C2* R; const int* flags; int rrows, chunks; const int* done;
@@ -259,7 +275,7 @@ struct RqArgs {
 // closes one sweep and opens the next.
 struct JacState {
   int counter, inner, inner_rot, done;
-  int sweeps, rotations, converged, pad0;
+  int sweeps, rotations, converged, cross;
   long pair_checks, inner_sweeps;
   double maxoff, last_off, stop2, inner_rotations;
   double pad1[6];
@@ -267,6 +283,7 @@ struct JacState {
 struct SweepArgs {  // aux = sweep index
   JacState* st; int* active; int pairs_per_sweep; int max_sweeps; double inner_floor; int adaptive;
   double factor;  // inner stopping level = factor x previous sweep's largest off-diagonal
+  double track_level;  // sweeps after one whose largest off-diagonal exceeded this track
 };
 
 // Work-group counts of one problem for the ops above.

@@ -99,15 +99,20 @@ constexpr bool cplx3m() { return true; }
 // buffer X: acc[i] accumulates tile i (tiles 2 WV, 2 WV + 1 and, on odd
 // k-steps, the shared tile at k-step 2 (WV & 1) + s / 2) as X_m^H X_n.  The
 // MFMAs are ordered so that consecutive ones write different accumulators.
-template <typename T, int WV>
+// The four tiles of the cross block X_q^H X_p (rows 32..63, columns 0..31 of
+// the pair's Gram), one per wave when only the cross block is computed.
+BSE_DEV constexpr int gram_cross_tile(int wv) { return wv < 2 ? 3 + wv : 4 + wv; }
+
+template <typename T, int WV, bool CROSS>
 BSE_DEV void gram_buffer(const typename cpx_t<T>::type* X, const GramLane<T>& g,
                          typename Mfma<T>::acc (&acc)[3][3]) {
   typedef typename cpx_t<T>::type C2;
-  constexpr int TA = 2 * WV, TB = 2 * WV + 1, TS = 8 + (WV >> 1), SH = WV & 1;
+  constexpr int TA = CROSS ? gram_cross_tile(WV) : 2 * WV, TB = 2 * WV + 1, TS = 8 + (WV >> 1);
+  constexpr int SH = WV & 1;
   constexpr int tiles[3] = {TA, TB, TS};
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const int nt = (s & 1) ? 3 : 2;
+    const int nt = CROSS ? 1 : (s & 1) ? 3 : 2;
     C2 xn[3], xm[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
@@ -188,7 +193,7 @@ struct GramSrc {
   }
 };
 
-template <typename T, int WV, bool DEEP>
+template <typename T, int WV, bool DEEP, bool CROSS>
 BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, int c,
                        typename cpx_t<T>::type* Xs) {
   typedef typename cpx_t<T>::type C2;
@@ -228,7 +233,7 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
     __syncthreads();
     src.load(sa, min(r0 + (DEEP ? 32 : 16), row_end - 16));
     __builtin_amdgcn_sched_barrier(0);  // issue the prefetch before the MFMA work
-    gram_buffer<T, WV>(X0, g, acc);
+    gram_buffer<T, WV, CROSS>(X0, g, acc);
     if constexpr (DEEP) {
       src.store(sb, X1);
       __syncthreads();
@@ -239,12 +244,12 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
       src.load(sa, min(r0 + 32, row_end - 16));
     }
     __builtin_amdgcn_sched_barrier(0);
-    gram_buffer<T, WV>(X1, g, acc);
+    gram_buffer<T, WV, CROSS>(X1, g, acc);
   }
   if (r0 < row_end) {  // an odd number of 16-row steps: the last one
     src.store(sa, X0);
     __syncthreads();
-    gram_buffer<T, WV>(X0, g, acc);
+    gram_buffer<T, WV, CROSS>(X0, g, acc);
   }
   // real and imaginary parts of the tiles
   Acc cr[3], ci[3];
@@ -257,6 +262,15 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
       cr[i] = acc[i][0];
       ci[i] = acc[i][1];
     }
+  }
+  if constexpr (CROSS) {  // one whole tile per wave
+    C2* dst = a.part + ((long)(k * a.kc + c) * NTILE + gram_cross_tile(WV)) * 256;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      C2 v; v.x = cr[0][r]; v.y = ci[0][r];
+      dst[l15 + 16 * Mfma<T>::drow(lane, r)] = v;
+    }
+    return;
   }
   // shared tile: the upper wave of each couple hands its half to the lower one
   __syncthreads();
@@ -302,11 +316,21 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
   int p, q;
   round_pair(a.N, t, k, p, q);
   constexpr bool kDeep = kGramDeepF64 || sizeof(T) == 4;
-  switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
-    case 0: gram_wave<T, 0, kDeep>(a, p, q, k, c, Xs); break;
-    case 1: gram_wave<T, 1, kDeep>(a, p, q, k, c, Xs); break;
-    case 2: gram_wave<T, 2, kDeep>(a, p, q, k, c, Xs); break;
-    default: gram_wave<T, 3, kDeep>(a, p, q, k, c, Xs); break;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  if ((a.crossp ? *a.crossp : a.cross) && t > 0) {  // only the cross block; the diagonal blocks are tracked
+    switch (wv) {
+      case 0: gram_wave<T, 0, kDeep, true>(a, p, q, k, c, Xs); break;
+      case 1: gram_wave<T, 1, kDeep, true>(a, p, q, k, c, Xs); break;
+      case 2: gram_wave<T, 2, kDeep, true>(a, p, q, k, c, Xs); break;
+      default: gram_wave<T, 3, kDeep, true>(a, p, q, k, c, Xs); break;
+    }
+    return;
+  }
+  switch (wv) {
+    case 0: gram_wave<T, 0, kDeep, false>(a, p, q, k, c, Xs); break;
+    case 1: gram_wave<T, 1, kDeep, false>(a, p, q, k, c, Xs); break;
+    case 2: gram_wave<T, 2, kDeep, false>(a, p, q, k, c, Xs); break;
+    default: gram_wave<T, 3, kDeep, false>(a, p, q, k, c, Xs); break;
   }
 }
 
@@ -342,7 +366,8 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   double* maxoff = a.maxoff;
   const double tol = a.tol;
   const double inner_stop2 = a.stop2p ? *a.stop2p : a.inner_stop2;
-  (void)N; (void)t;
+  double2* track = a.track;
+  const bool cross = (a.crossp ? *a.crossp : a.cross) && t > 0;
   __shared__ double2 G[JP][JP + LPAD];
   __shared__ double2 R[JP][JP + LPAD];
   __shared__ double4 prm[2][32];  // (c, Re s, Im s, unused) of rotation m, two steps
@@ -352,6 +377,8 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   __shared__ int sweepbig;
   const int tid = threadIdx.x;
   const int k = bx;
+  int bp, bq;  // the pair's column blocks: pair columns 0..31 and 32..63
+  round_pair(N, t, k, bp, bq);
   // (P, Q), P < Q, of this thread's off-diagonal 2 x 2 block (threads 0..495):
   // thread b holds the b-th pair in the order Q = 1..31, P = 0..Q-1.
   int bP = 0, bQ = 1;
@@ -361,11 +388,14 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
     bP = b;
   }
 
-  // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian matrix.
+  // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian
+  // matrix; with `cross`, only the cross block comes from partial tiles (tiles
+  // 3, 4, 6, 7) and the two diagonal blocks from the tracked block Grams.
   for (int e = tid; e < NTILE * 256; e += NT) {
     const int tile = e >> 8, el = e & 255;
     const int m = 16 * kTileI[tile] + (el & 15), n = 16 * kTileJ[tile] + (el >> 4);
     if (m < n) continue;
+    if (cross && !(tile == 3 || tile == 4 || tile == 6 || tile == 7)) continue;
     double sr = 0.0, si = 0.0;
     const C2* src = part + ((long)k * kc * NTILE + tile) * 256 + el;
     for (int c = 0; c < kc; ++c) {
@@ -380,7 +410,32 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
       G[n][m] = make_double2(sr, -si);
     }
   }
+  if (cross) {
+    for (int e = tid; e < 2 * JB * JB; e += NT) {
+      const int b = e >> 10, m = e & 31, n = (e >> 5) & 31;
+      if (m < n) continue;
+      const double2 v = track[(long)(b ? bq : bp) * JB * JB + m + JB * n];
+      const int mm = m + JB * b, nn = n + JB * b;
+      if (m == n) {
+        G[mm][mm] = make_double2(v.x, 0.0);
+      } else {
+        G[mm][nn] = v;
+        G[nn][mm] = cconj(v);
+      }
+    }
+  }
   __syncthreads();
+  // The diagonal blocks of G (after the pair's rotation, if any) become the
+  // tracked Grams of the pair's two column blocks; G is current in its lower
+  // triangle.
+  auto write_track = [&]() {
+    if (!track) return;
+    for (int e = tid; e < 2 * JB * JB; e += NT) {
+      const int b = e >> 10, m = e & 31, n = (e >> 5) & 31;
+      const int mm = m + JB * b, nn = n + JB * b;
+      track[(long)(b ? bq : bp) * JB * JB + m + JB * n] = mm >= nn ? G[mm][nn] : cconj(G[nn][mm]);
+    }
+  };
 
   // 2. Relative off-diagonal measure of the pair.
   double off2 = 0.0;
@@ -402,6 +457,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   const double off = sqrt(red[0]);
   if (tid == 0) atomic_max_nonneg(maxoff, off);
   if (!(off > tol)) {
+    write_track();
     if (tid == 0) flags[k] = 0;
     return;
   }
@@ -568,6 +624,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   // the last step's rotations, still pending on R
   if (gstep > 0) apply_r((gstep - 1) & 1, tid & 63, tid >> 6, NT / 64);
   __syncthreads();
+  write_track();
   if (tid == 0) atomicAdd(inner_count, sweeps_done);
   if (tid < 64) {
     int a = applied;
@@ -777,6 +834,7 @@ BSE_DEV void SweepOp::run(const SweepArgs& a, int, int sweep) {
   double stop = a.inner_floor;
   if (a.adaptive) stop = fmax(a.inner_floor, fmin(kInnerStopCap, prev < 0.0 ? kInnerStopCap : a.factor * prev));
   st->stop2 = stop * stop;
+  st->cross = (prev < 0.0 ? kInnerStopCap : prev) > a.track_level ? 1 : 0;
   st->counter = 0;
   st->inner = 0;
   st->inner_rot = 0;
@@ -808,6 +866,8 @@ size_t jacobi_work_bytes(int np, int elem_bytes, int kc) {
   b = (b + 255) & ~(size_t)255;
   b += (size_t)pairs * JP * JP * 2 * elem_bytes;           // R
   b = (b + 255) & ~(size_t)255;
+  b += (size_t)N * JB * JB * sizeof(double2);               // track
+  b = (b + 255) & ~(size_t)255;
   b += (size_t)pairs * sizeof(int) + 256;                  // flags
   b += 256 + 256;                                          // counter, maxoff
   return (b + 255) & ~(size_t)255;
@@ -823,6 +883,9 @@ void jacobi_carve(int np, int elem_bytes, char* base, JacobiWork& w, int kc, int
   o = (o + 255) & ~(size_t)255;
   w.R = base + o;
   o += (size_t)pairs * JP * JP * 2 * elem_bytes;
+  o = (o + 255) & ~(size_t)255;
+  w.track = reinterpret_cast<double2*>(base + o);
+  o += (size_t)N * JB * JB * sizeof(double2);
   o = (o + 255) & ~(size_t)255;
   w.flags = reinterpret_cast<int*>(base + o);
   o += (size_t)pairs * sizeof(int) + 256;
@@ -850,7 +913,7 @@ template <typename C2>
 GramArgs<C2> make_gram(int np, C2* W, long ld, const JacobiWork& w, const int* done) {
   GramArgs<C2> a;
   a.N = np / JB; a.W = W; a.ld = ld; a.kc = w.kc; a.rc = np / w.kc;
-  a.part = static_cast<C2*>(w.part); a.done = done;
+  a.part = static_cast<C2*>(w.part); a.done = done; a.cross = 0; a.crossp = nullptr;
   return a;
 }
 template <typename C2>
@@ -860,7 +923,7 @@ EigArgs<C2> make_eig(int np, const JacobiWork& w, double tol, const double* stop
   a.part = static_cast<const C2*>(w.part); a.R = static_cast<C2*>(w.R);
   a.flags = w.flags; a.counter = w.counter; a.tol = tol; a.maxoff = w.maxoff;
   a.max_inner = 30; a.inner = w.inner; a.inner_stop2 = 0.0; a.stop2p = stop2p;
-  a.inner_rot = w.inner_rot; a.done = done;
+  a.inner_rot = w.inner_rot; a.done = done; a.track = w.track; a.cross = 0; a.crossp = nullptr;
   return a;
 }
 template <typename C2>
@@ -880,8 +943,9 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
   const int N = np / JB, pairs = N / 2;
   const int gblocks = jacobi_gram_blocks_kc(np, w.kc);
   const int rblocks = jacobi_rot_blocks_rr(np, w.rrows);
-  const GramArgs<C2> ga = make_gram<C2>(np, W, ld, w, nullptr);
+  GramArgs<C2> ga = make_gram<C2>(np, W, ld, w, nullptr);
   EigArgs<C2> ea = make_eig<C2>(np, w, tol, nullptr, nullptr);
+  const double track_level = sizeof(T) == 8 ? kTrackLevel64 : kTrackLevel32;
   const RotArgs<C2> ra = make_rot<C2>(np, W, ld, w, nullptr);
   res = JacobiResult();
   hipError_t e;
@@ -916,6 +980,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     if (adaptive)
       sstop = fmax(inner_stop, fmin(kInnerStopCap, prev_off < 0.0 ? first_stop : inner_factor * prev_off));
     ea.inner_stop2 = sstop * sstop;
+    ga.cross = ea.cross = (prev_off < 0.0 ? first_stop : prev_off) > track_level ? 1 : 0;
     e = hipMemsetAsync(w.counter, 0, 128, s);
     if (e != hipSuccess) { ret = e; break; }
     for (int t = 0; t < N - 1; ++t) {
