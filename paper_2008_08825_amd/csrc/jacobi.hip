@@ -70,9 +70,10 @@ struct GramOp {
   static BSE_DEV void run(const Args& a, int bx, int t);
 };
 
-// complex128 stages one 16-row step ahead, complex64 two (a second set of
-// staging registers for complex128 measured no faster)
-constexpr bool kGramDeepF64 = false;
+// Register stages of the Gram kernel's row loop: complex128 one 16-row step
+// ahead, complex64 two (more stages measured no faster in either).
+template <typename T>
+constexpr int gram_stages() { return sizeof(T) == 8 ? 1 : 2; }
 BSE_DEV constexpr int gram_ti(int t) { return t < 1 ? 0 : t < 3 ? 1 : t < 6 ? 2 : 3; }
 BSE_DEV constexpr int gram_tj(int t) { return t - gram_ti(t) * (gram_ti(t) + 1) / 2; }
 
@@ -193,7 +194,7 @@ struct GramSrc {
   }
 };
 
-template <typename T, int WV, bool DEEP, bool CROSS>
+template <typename T, int WV, int NST, bool CROSS>
 BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, int c,
                        typename cpx_t<T>::type* Xs) {
   typedef typename cpx_t<T>::type C2;
@@ -212,44 +213,41 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
   // staging: thread reads rows r0 + lr of pair columns c0 + 16 i (sixteen
   // consecutive rows of a column per sixteen lanes) and stores them swizzled
   const int lr = tid & 15, c0 = tid >> 4;
-  GramStage<T> sa, sb;
   const GramSrc<T> src(a.W + lr, a.ld, p, q, c0, lr);
   Acc acc[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) acc[i][j] = Mfma<T>::zero();
-  // DEEP: two register sets in flight (rows r0 + 16 and r0 + 32 load while
-  // the MFMAs work on r0); otherwise one.  Prefetches past the chunk re-read
-  // its last rows, so that every step issues the same loads and the waits for
-  // them stay partial.
-  src.load(sa, row_beg);
-  if constexpr (DEEP) src.load(sb, min(row_beg + 16, row_end - 16));
+  // NST register stages in flight: rows r0 + 16, ..., r0 + 16 NST load while
+  // the MFMAs work on r0; 16-row steps alternate between two LDS buffers.
+  // Prefetches past the chunk re-read its last rows, so that every step
+  // issues the same loads and the waits for them stay partial.
+  GramStage<T> st[NST];
+#pragma unroll
+  for (int i = 0; i < NST; ++i) src.load(st[i], min(row_beg + 16 * i, row_end - 16));
   C2* X0 = Xs;
   C2* X1 = Xs + 16 * JP;
   int r0 = row_beg;
-  for (; r0 + 32 <= row_end; r0 += 32) {
-    src.store(sa, X0);
-    __syncthreads();
-    src.load(sa, min(r0 + (DEEP ? 32 : 16), row_end - 16));
-    __builtin_amdgcn_sched_barrier(0);  // issue the prefetch before the MFMA work
-    gram_buffer<T, WV, CROSS>(X0, g, acc);
-    if constexpr (DEEP) {
-      src.store(sb, X1);
+  for (; r0 + 16 * NST <= row_end; r0 += 16 * NST) {
+#pragma unroll
+    for (int i = 0; i < NST; ++i) {
+      C2* X = ((((r0 - row_beg) >> 4) + i) & 1) ? X1 : X0;
+      src.store(st[i], X);
       __syncthreads();
-      src.load(sb, min(r0 + 48, row_end - 16));
-    } else {
-      src.store(sa, X1);
-      __syncthreads();
-      src.load(sa, min(r0 + 32, row_end - 16));
+      src.load(st[i], min(r0 + 16 * (i + NST), row_end - 16));
+      __builtin_amdgcn_sched_barrier(0);  // issue the prefetch before the MFMA work
+      gram_buffer<T, WV, CROSS>(X, g, acc);
     }
-    __builtin_amdgcn_sched_barrier(0);
-    gram_buffer<T, WV, CROSS>(X1, g, acc);
   }
-  if (r0 < row_end) {  // an odd number of 16-row steps: the last one
-    src.store(sa, X0);
-    __syncthreads();
-    gram_buffer<T, WV, CROSS>(X0, g, acc);
+#pragma unroll
+  for (int i = 0; i < NST; ++i) {  // the last steps, fewer than NST
+    if (r0 + 16 * i < row_end) {
+      C2* X = ((((r0 - row_beg) >> 4) + i) & 1) ? X1 : X0;
+      src.store(st[i], X);
+      __syncthreads();
+      gram_buffer<T, WV, CROSS>(X, g, acc);
+    }
   }
   // real and imaginary parts of the tiles
   Acc cr[3], ci[3];
@@ -315,7 +313,7 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
   const int k = bx / a.kc, c = bx % a.kc;
   int p, q;
   round_pair(a.N, t, k, p, q);
-  constexpr bool kDeep = kGramDeepF64 || sizeof(T) == 4;
+  constexpr int kDeep = gram_stages<T>();
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if ((a.crossp ? *a.crossp : a.cross) && t > 0) {  // only the cross block; the diagonal blocks are tracked
     switch (wv) {
