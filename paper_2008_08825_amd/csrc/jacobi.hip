@@ -370,7 +370,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   __shared__ double2 R[JP][JP + LPAD];
   __shared__ double4 prm[2][32];  // (c, Re s, Im s, unused) of rotation m, two steps
   __shared__ int pidx[2][32];     // i | j << 8 | rotate << 16
-  __shared__ double red[NT];
+  __shared__ double red[NT / 64];
   __shared__ int nrot;
   __shared__ int sweepbig;
   const int tid = threadIdx.x;
@@ -446,13 +446,14 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
       else if (a2 > 0.0) off2 = 1.0;
     }
   }
-  red[tid] = off2;
+  // max over the wave by lane exchanges, then over the eight waves in LDS
+  for (int o = 32; o > 0; o >>= 1) off2 = fmax(off2, __shfl_xor(off2, o));
+  if ((tid & 63) == 0) red[tid >> 6] = off2;
   __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-    __syncthreads();
-  }
-  const double off = sqrt(red[0]);
+  double offw = red[0];
+#pragma unroll
+  for (int w = 1; w < NT / 64; ++w) offw = fmax(offw, red[w]);
+  const double off = sqrt(offw);
   if (tid == 0) atomic_max_nonneg(maxoff, off);
   if (!(off > tol)) {
     write_track();
