@@ -125,6 +125,7 @@ def time_form(api, A, B, precision, route, steps, warmup, work, out):
         log(f"{precision} warmup {i}: sweeps={info['sweeps']} status={info['status']}")
     torch.cuda.synchronize()
     acc = {"kernel_ms": np.zeros(3), "launches": np.zeros(3), "rotations": 0, "pair_checks": 0,
+           "cross_pair_checks": 0, "p_cross_pair_checks": 0,
            "inner_rotations": 0.0, "phases": np.zeros(8), "sweeps": [], "refine_steps": [],
            "p_kernel_ms": np.zeros(3), "p_launches": np.zeros(3), "p_rotations": 0, "p_pair_checks": 0,
            "p_inner_rotations": 0.0, "polish_sweeps": []}
@@ -138,6 +139,7 @@ def time_form(api, A, B, precision, route, steps, warmup, work, out):
         acc["launches"] += np.array(info["kernel_launches"])
         acc["rotations"] += info["rotations"]
         acc["pair_checks"] += info["pair_checks"]
+        acc["cross_pair_checks"] += info["cross_pair_checks"]
         acc["inner_rotations"] += info["inner_rotations"]
         acc["phases"] += np.array(info["ms_phase"])
         acc["sweeps"].append(info["sweeps"])
@@ -146,6 +148,7 @@ def time_form(api, A, B, precision, route, steps, warmup, work, out):
         acc["p_launches"] += np.array(info["polish_kernel_launches"])
         acc["p_rotations"] += info["polish_rotations"]
         acc["p_pair_checks"] += info["polish_pair_checks"]
+        acc["p_cross_pair_checks"] += info["polish_cross_pair_checks"]
         acc["p_inner_rotations"] += info["polish_inner_rotations"]
         acc["polish_sweeps"].append(info["polish_sweeps"])
         log(f"{precision} step {i}: {time.perf_counter() - ts:.3f}s sweeps={info['sweeps']} "
@@ -163,7 +166,8 @@ def kernel_report(acc, np_pad, precision, steps, prefix=""):
         acc = {k[len(prefix):]: v for k, v in acc.items() if k.startswith(prefix)}
     mfma_peak = PEAK["fp64_mfma"] if precision == "fp64" else PEAK["fp32_mfma"]
     work = {
-        "jacobi_gram": 8.0 * np_pad * 256 * 10 * acc["pair_checks"],
+        # ten 16 x 16 tiles per checked pair, four where only the cross block is computed
+        "jacobi_gram": 8.0 * np_pad * 256 * (10 * acc["pair_checks"] - 6 * acc["cross_pair_checks"]),
         "jacobi_eig": 3840.0 * acc["inner_rotations"],
         "jacobi_rotate": 8.0 * np_pad * 64 * 64 * acc["rotations"],
     }

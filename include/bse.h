@@ -115,12 +115,14 @@ typedef struct {
   int polish_sweeps;
   int polish_rotations;
   int polish_pair_checks;
-  int polish_reserved;
+  int cross_pair_checks;  /* pair checks of the iteration above whose Gram
+                             computed only the cross block (the diagonal
+                             blocks tracked: sweeps far from convergence)    */
   double polish_max_off;
   double polish_inner_rotations;
   double polish_kernel_ms[3];
   int polish_kernel_launches[3];
-  int polish_reserved2;
+  int polish_cross_pair_checks;  /* the same for the FP64 sweeps               */
 } bse_info_t;
 
 /* Fill `opts` with the defaults (route SVD, FP64, lower triangles). */

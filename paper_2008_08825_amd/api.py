@@ -61,12 +61,12 @@ class BSEInfo(ctypes.Structure):
         ("polish_sweeps", ctypes.c_int),
         ("polish_rotations", ctypes.c_int),
         ("polish_pair_checks", ctypes.c_int),
-        ("polish_reserved", ctypes.c_int),
+        ("cross_pair_checks", ctypes.c_int),
         ("polish_max_off", ctypes.c_double),
         ("polish_inner_rotations", ctypes.c_double),
         ("polish_kernel_ms", ctypes.c_double * 3),
         ("polish_kernel_launches", ctypes.c_int * 3),
-        ("polish_reserved2", ctypes.c_int),
+        ("polish_cross_pair_checks", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -79,6 +79,7 @@ class BSEInfo(ctypes.Structure):
             "refine_delta": self.refine_delta,
             "ms_phase": list(self.ms_phase),
             "pair_checks": self.pair_checks,
+            "cross_pair_checks": self.cross_pair_checks,
             "kernel_ms": list(self.kernel_ms),
             "kernel_launches": list(self.kernel_launches),
             "refine_steps_done": self.refine_steps_done,
@@ -86,6 +87,7 @@ class BSEInfo(ctypes.Structure):
             "polish_sweeps": self.polish_sweeps,
             "polish_rotations": self.polish_rotations,
             "polish_pair_checks": self.polish_pair_checks,
+            "polish_cross_pair_checks": self.polish_cross_pair_checks,
             "polish_max_off": self.polish_max_off,
             "polish_inner_rotations": self.polish_inner_rotations,
             "polish_kernel_ms": list(self.polish_kernel_ms),

@@ -434,7 +434,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       }
       const SweepArgs sa = {st, d_active, jacobi_pairs(np) * jacobi_rounds(np), max_sweeps,
                             mixed ? 1.0e-5 : 1.0e-10, 1, mixed ? 0.3 : 1.0,
-                            mixed ? kTrackLevel32 : kTrackLevel64};
+                            mixed ? kTrackLevel32 : kTrackLevel64, jacobi_pairs(np)};
       sw.add(sa, 1);
       rounds.push_back(jacobi_rounds(np));
     }
@@ -724,6 +724,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       inf->rotations = js.rotations;
       inf->max_off = js.last_off;
       inf->pair_checks = (int)js.pair_checks;
+      inf->cross_pair_checks = (int)js.cross_pair_checks;
       inf->inner_rotations = js.inner_rotations;
       inf->refine_delta = pr.rcorr;
       inf->refine_steps_done = pr.rsteps;

@@ -36,6 +36,7 @@ void fill_info(bse_info_t* info, int ret, const JacobiResult& jr) {
   info->rotations = jr.rotations;
   info->max_off = jr.max_off;
   info->pair_checks = jr.pair_checks;
+  info->cross_pair_checks = jr.cross_pair_checks;
   info->inner_rotations = jr.inner_rotations;
   for (int i = 0; i < 3; ++i) {
     info->kernel_ms[i] = jr.kernel_ms[i];
@@ -413,6 +414,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
     info->polish_sweeps = j64.sweeps;
     info->polish_rotations = j64.rotations;
     info->polish_pair_checks = j64.pair_checks;
+    info->polish_cross_pair_checks = j64.cross_pair_checks;
     info->polish_max_off = j64.max_off;
     info->polish_inner_rotations = j64.inner_rotations;
     for (int i = 0; i < 3; ++i) {

@@ -69,6 +69,7 @@ struct JacobiResult {
   int sweeps = 0;
   int rotations = 0;
   int pair_checks = 0;
+  int cross_pair_checks = 0;  // pair checks whose Gram computed only the cross block
   long inner_sweeps = 0;
   double inner_rotations = 0.0;
   double max_off = 0.0;
@@ -278,12 +279,14 @@ struct JacState {
   int sweeps, rotations, converged, cross;
   long pair_checks, inner_sweeps;
   double maxoff, last_off, stop2, inner_rotations;
-  double pad1[6];
+  long cross_pair_checks;
+  double pad1[5];
 };
 struct SweepArgs {  // aux = sweep index
   JacState* st; int* active; int pairs_per_sweep; int max_sweeps; double inner_floor; int adaptive;
   double factor;  // inner stopping level = factor x previous sweep's largest off-diagonal
   double track_level;  // sweeps after one whose largest off-diagonal exceeded this track
+  int pairs_per_round;
 };
 
 // Work-group counts of one problem for the ops above.

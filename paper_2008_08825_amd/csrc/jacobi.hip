@@ -818,6 +818,7 @@ BSE_DEV void SweepOp::run(const SweepArgs& a, int, int sweep) {
     st->inner_sweeps += st->inner;
     st->inner_rotations += (double)st->inner_rot;
     st->pair_checks += a.pairs_per_sweep;
+    if (st->cross) st->cross_pair_checks += a.pairs_per_sweep - a.pairs_per_round;
     st->last_off = st->maxoff;
     prev = st->maxoff;
     if (st->counter == 0) {
@@ -1030,6 +1031,7 @@ static hipError_t jacobi_run(int np, typename cpx_t<T>::type* W, long ld, const 
     res.inner_sweeps += inner;
     res.inner_rotations += irot;
     res.pair_checks += pairs * (N - 1);
+    if (ga.cross) res.cross_pair_checks += pairs * (N - 2);  // all rounds but the first
     res.max_off = mo;
     if (cnt == 0) { res.converged = 1; break; }
     if (stop_fraction > 0.0 && cnt < stop_fraction * pairs * (N - 1)) break;

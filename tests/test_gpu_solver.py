@@ -333,3 +333,21 @@ def test_kernel_timing_options(gpu_lib, precision):
     assert i2["kernel_launches"] == i3["kernel_launches"] and min(i3["kernel_launches"]) > 0
     for a, b in zip(i2["kernel_ms"], i3["kernel_ms"]):
         assert a > 0.0 and b > 0.0 and 0.5 < a / b < 2.0, (i2["kernel_ms"], i3["kernel_ms"])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_polish"])
+def test_tracked_gram_sweeps_reported(gpu_lib, precision):
+    """Sweeps far from convergence compute only the cross blocks of the pair
+    Grams after their first round: the count is reported, bounded by the pair
+    checks, and the FP64 sweeps of mixed_polish (which start near convergence)
+    recompute every tile."""
+    n = 600
+    A, B = inputs.coupled(n, seed=16)
+    lam, X, info = run(gpu_lib, A, B, precision=precision)
+    npad = 640
+    pairs = npad // 64
+    assert 0 < info["cross_pair_checks"] < info["pair_checks"]
+    assert info["cross_pair_checks"] % (pairs * (npad // 32 - 2)) == 0
+    if precision == "mixed_polish":
+        assert info["polish_cross_pair_checks"] == 0
+    check_against_oracle(A, B, lam, X)
