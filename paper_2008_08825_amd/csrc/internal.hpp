@@ -92,7 +92,7 @@ constexpr double kInnerStopCap = 3.0e-2;
 // data's by the rounding of the rotations, about 1e-11 (FP64) or 1e-5
 // (complex64) per sweep, far below the off-diagonal level of such sweeps; the
 // sweeps near convergence recompute every Gram tile.
-constexpr double kTrackLevel64 = 1.0e-4;
+constexpr double kTrackLevel64 = 1.0e-5;
 constexpr double kTrackLevel32 = 1.0e-3;
 // first_stop: inner stopping level of the first sweep (later sweeps use the
 // previous sweep's largest off-diagonal measure, at most kInnerStopCap).
