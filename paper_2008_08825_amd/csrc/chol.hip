@@ -373,29 +373,57 @@ hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, in
   return cholesky_run<double2>(np, n_real, M, ld, linv, status, base, s);
 }
 
+// The block triangular solves take the 64-column diagonal blocks two at a
+// time: the second block of a pair is updated with the first alone, and the
+// rest of the right-hand side with both at once (K = 128), so the remaining
+// rows pass through the update half as often as with one block at a time.
+
+// Z_i = op(L_ii^-1) Rhs_i for one 64-row block (left-side solves)
+static hipError_t trsm_diag(const double2* inv_i, int opA, int np, double2* Rhs_i, double2* Z_i,
+                            long ld, hipStream_t s) {
+  GemmDesc g;
+  g.M = NB; g.N = np; g.K = NB;
+  g.A = inv_i; g.lda = NB; g.opA = opA; g.triA = 1;
+  g.B = Rhs_i; g.ldb = ld; g.opB = 0;
+  g.C = Z_i; g.ldc = ld;
+  return gemm_z(g, s);
+}
+
+// C -= op(A) B  (rows x np, inner dimension k)
+static hipError_t trsm_update(int rows, int np, int k, const double2* A, long lda, int opA,
+                              const double2* B, long ldb, double2* C, long ldc, hipStream_t s) {
+  if (rows <= 0) return hipSuccess;
+  GemmDesc u;
+  u.M = rows; u.N = np; u.K = k;
+  u.A = A; u.lda = lda; u.opA = opA;
+  u.B = B; u.ldb = ldb; u.opB = 0;
+  u.C = C; u.ldc = ldc;
+  u.alpha_re = -1.0; u.beta_re = 1.0;
+  return gemm_z(u, s);
+}
+
 hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s) {
   const int nb = np / NB;
   k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int i = nb - 1; i >= 0; --i) {
-    // Z_i = (L_ii^-1)^H Rhs_i
-    GemmDesc g;
-    g.M = NB; g.N = np; g.K = NB;
-    g.A = inv + (long)i * NB * NB; g.lda = NB; g.opA = 1; g.triA = 1;
-    g.B = Rhs + (long)i * NB; g.ldb = ld; g.opB = 0;
-    g.C = Z + (long)i * NB; g.ldc = ld;
-    if ((e = gemm_z(g, s)) != hipSuccess) return e;
-    if (i == 0) break;
-    // Rhs_{0..i-1} -= (L^H)_{0..i-1, i} Z_i,  (L^H)_{r, c} = conj(L_{c, r})
-    GemmDesc u;
-    u.M = i * NB; u.N = np; u.K = NB;
-    u.A = L + (long)i * NB; u.lda = ld; u.opA = 1;
-    u.B = Z + (long)i * NB; u.ldb = ld; u.opB = 0;
-    u.C = Rhs; u.ldc = ld;
-    u.alpha_re = -1.0; u.beta_re = 1.0;
-    if ((e = gemm_z(u, s)) != hipSuccess) return e;
+  // back substitution with L^H: block rows i, i - 1, ... ; (L^H)_{r, c} = conj(L_{c, r})
+  for (int i = nb - 1; i >= 0; i -= 2) {
+    const long ri = (long)i * NB;
+    if ((e = trsm_diag(inv + ri * NB, 1, np, Rhs + ri, Z + ri, ld, s)) != hipSuccess) return e;
+    int lo = i;  // first block row of the pair
+    if (i >= 1) {
+      const long r1 = ri - NB;
+      // Rhs_{i-1} -= (L^H)_{i-1, i} Z_i
+      if ((e = trsm_update(NB, np, NB, L + ri + r1 * ld, ld, 1, Z + ri, ld, Rhs + r1, ld, s)) != hipSuccess) return e;
+      if ((e = trsm_diag(inv + r1 * NB, 1, np, Rhs + r1, Z + r1, ld, s)) != hipSuccess) return e;
+      lo = i - 1;
+    }
+    // Rhs_{0..lo-1} -= (L^H)_{0..lo-1, lo..i} Z_{lo..i}
+    const long rl = (long)lo * NB;
+    const int k = (i - lo + 1) * NB;
+    if ((e = trsm_update(lo * NB, np, k, L + rl, ld, 1, Z + rl, ld, Rhs, ld, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -406,23 +434,21 @@ hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
   k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int i = 0; i < nb; ++i) {
-    // Z_i = L_ii^-1 Rhs_i
-    GemmDesc g;
-    g.M = NB; g.N = np; g.K = NB;
-    g.A = inv + (long)i * NB * NB; g.lda = NB; g.opA = 0; g.triA = 1;
-    g.B = Rhs + (long)i * NB; g.ldb = ld; g.opB = 0;
-    g.C = Z + (long)i * NB; g.ldc = ld;
-    if ((e = gemm_z(g, s)) != hipSuccess) return e;
-    if (i == nb - 1) break;
-    // Rhs_{i+1..} -= L_{i+1.., i} Z_i
-    GemmDesc u;
-    u.M = np - (i + 1) * NB; u.N = np; u.K = NB;
-    u.A = L + (long)(i + 1) * NB + (long)i * NB * ld; u.lda = ld; u.opA = 0;
-    u.B = Z + (long)i * NB; u.ldb = ld; u.opB = 0;
-    u.C = Rhs + (long)(i + 1) * NB; u.ldc = ld;
-    u.alpha_re = -1.0; u.beta_re = 1.0;
-    if ((e = gemm_z(u, s)) != hipSuccess) return e;
+  for (int i = 0; i < nb; i += 2) {
+    const long ri = (long)i * NB;
+    if ((e = trsm_diag(inv + ri * NB, 0, np, Rhs + ri, Z + ri, ld, s)) != hipSuccess) return e;
+    int hi = i;  // last block row of the pair
+    if (i + 1 < nb) {
+      const long r1 = ri + NB;
+      // Rhs_{i+1} -= L_{i+1, i} Z_i
+      if ((e = trsm_update(NB, np, NB, L + r1 + ri * ld, ld, 0, Z + ri, ld, Rhs + r1, ld, s)) != hipSuccess) return e;
+      if ((e = trsm_diag(inv + r1 * NB, 0, np, Rhs + r1, Z + r1, ld, s)) != hipSuccess) return e;
+      hi = i + 1;
+    }
+    // Rhs_{hi+1..} -= L_{hi+1.., i..hi} Z_{i..hi}
+    const long rn = (long)(hi + 1) * NB;
+    const int k = (hi - i + 1) * NB;
+    if ((e = trsm_update(np - (int)rn, np, k, L + rn + ri * ld, ld, 0, Z + ri, ld, Rhs + rn, ld, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -433,23 +459,35 @@ hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
   k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int j = 0; j < nb; ++j) {
-    // Z_j = Rhs_j (L_jj^-1)^H   (column block j)
+  // Z_j = Rhs_j (L_jj^-1)^H   (column block j)
+  auto diag = [&](int j) {
     GemmDesc g;
     g.M = np; g.N = NB; g.K = NB;
     g.A = Rhs + (long)j * NB * ld; g.lda = ld; g.opA = 0;
     g.B = inv + (long)j * NB * NB; g.ldb = NB; g.opB = 1; g.triB = 1;
     g.C = Z + (long)j * NB * ld; g.ldc = ld;
-    if ((e = gemm_z(g, s)) != hipSuccess) return e;
-    if (j == nb - 1) break;
-    // Rhs_{j+1..} -= Z_j (L_{j+1.., j})^H
+    return gemm_z(g, s);
+  };
+  // Rhs_{c0..c0+cols} -= Z_{j0..j0+k} (L_{c0.., j0..j0+k})^H
+  auto update = [&](int c0, int cols, int j0, int k) {
+    if (cols <= 0) return hipSuccess;
     GemmDesc u;
-    u.M = np; u.N = np - (j + 1) * NB; u.K = NB;
-    u.A = Z + (long)j * NB * ld; u.lda = ld; u.opA = 0;
-    u.B = L + (long)(j + 1) * NB + (long)j * NB * ld; u.ldb = ld; u.opB = 1;
-    u.C = Rhs + (long)(j + 1) * NB * ld; u.ldc = ld;
+    u.M = np; u.N = cols; u.K = k;
+    u.A = Z + (long)j0 * ld; u.lda = ld; u.opA = 0;
+    u.B = L + c0 + (long)j0 * ld; u.ldb = ld; u.opB = 1;
+    u.C = Rhs + (long)c0 * ld; u.ldc = ld;
     u.alpha_re = -1.0; u.beta_re = 1.0;
-    if ((e = gemm_z(u, s)) != hipSuccess) return e;
+    return gemm_z(u, s);
+  };
+  for (int j = 0; j < nb; j += 2) {
+    if ((e = diag(j)) != hipSuccess) return e;
+    int hi = j;
+    if (j + 1 < nb) {
+      if ((e = update((j + 1) * NB, NB, j * NB, NB)) != hipSuccess) return e;
+      if ((e = diag(j + 1)) != hipSuccess) return e;
+      hi = j + 1;
+    }
+    if ((e = update((hi + 1) * NB, np - (hi + 1) * NB, j * NB, (hi - j + 1) * NB)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
