@@ -306,62 +306,99 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   }
   tm.mark();
 
-  // ---- blocked Cholesky of both factors of every problem, panel by panel
+  // ---- blocked Cholesky of both factors of every problem, two panels at a time
+  // (as the single solve: factor panel j0, update the next column block with
+  // it, factor panel j0 + 64, update the rest with both, K = 128)
   {
     const int kmax = probs[0].np / 64;
-    for (int k = 0; k < kmax; ++k) {
-      const int j0 = 64 * k;
-      std::vector<GemmDesc> trsm, herk;
+    const size_t es = mixed ? sizeof(float2) : sizeof(double2);
+    auto factor_of = [&](const Prob& pr, int f) -> void* {
+      const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
+      return mixed ? static_cast<void*>(pr.base + pr.p.off_lc + (f ? half : 0))
+                   : static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_m1));
+    };
+    auto linv_of = [&](const Prob& pr, int f) -> void* {
+      return pr.base + pr.p.off_linv + (size_t)f * 64 * 64 * es;
+    };
+    auto at = [&](void* M, const Prob& pr, int r, int c) -> char* {
+      return static_cast<char*>(M) + ((size_t)r + (size_t)c * pr.np) * es;
+    };
+    // Potf2 at column j0 and the solve of the rows below it, for every problem
+    // with np > j0
+    auto factor_panels = [&](int j0) -> int {
+      std::vector<GemmDesc> trsm;
       Grp<Potf2Args<double2>> gz;
       Grp<Potf2Args<float2>> gc;
       for (const Prob& pr : probs) {
         if (pr.np <= j0) break;
-        const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
         for (int f = 0; f < 2; ++f) {
-          void* M;
-          void* linv;
+          void* M = factor_of(pr, f);
+          void* linv = linv_of(pr, f);
           if (mixed) {
-            M = pr.base + pr.p.off_lc + (f ? half : 0);
-            linv = pr.base + pr.p.off_linv + (size_t)f * 64 * 64 * sizeof(float2);
             const Potf2Args<float2> a = {static_cast<float2*>(M), pr.np, static_cast<float2*>(linv),
                                          d_status + pr.idx, f ? pr.n : 0, pr.n};
             gc.add(a, 1);
           } else {
-            M = pr.base + (f ? pr.p.off_m2 : pr.p.off_m1);
-            linv = pr.base + pr.p.off_linv + (size_t)f * 64 * 64 * sizeof(double2);
             const Potf2Args<double2> a = {static_cast<double2*>(M), pr.np, static_cast<double2*>(linv),
                                           d_status + pr.idx, f ? pr.n : 0, pr.n};
             gz.add(a, 1);
           }
           const int rows = pr.np - j0 - 64;
           if (rows <= 0) continue;
-          const size_t es = mixed ? sizeof(float2) : sizeof(double2);
-          char* panel = static_cast<char*>(M) + ((size_t)(j0 + 64) + (size_t)j0 * pr.np) * es;
           GemmDesc t;  // L21 = A21 L11^-H
           t.M = rows; t.N = 64; t.K = 64;
-          t.A = panel; t.lda = pr.np; t.opA = 0;
+          t.A = at(M, pr, j0 + 64, j0); t.lda = pr.np; t.opA = 0;
           t.B = linv; t.ldb = 64; t.opB = 1; t.triB = 1;
-          t.C = panel; t.ldc = pr.np;
+          t.C = at(M, pr, j0 + 64, j0); t.ldc = pr.np;
           trsm.push_back(t);
-          GemmDesc u;  // A22 -= L21 L21^H, lower tiles
-          u.M = rows; u.N = rows; u.K = 64;
-          u.A = panel; u.lda = pr.np; u.opA = 0;
-          u.B = panel; u.ldb = pr.np; u.opB = 1;
-          u.C = static_cast<char*>(M) + ((size_t)(j0 + 64) + (size_t)(j0 + 64) * pr.np) * es;
-          u.ldc = pr.np;
-          u.alpha_re = -1.0; u.beta_re = 1.0; u.lowerC = 1;
-          herk.push_back(u);
         }
       }
       if (mixed) {
         BSE_TRY(run_op(ar, gc, group_chol, G_POTF2_C, j0, s));
         BSE_TRY(run_gemm<float>(ar, trsm, s));
-        BSE_TRY(run_gemm<float>(ar, herk, s));
       } else {
         BSE_TRY(run_op(ar, gz, group_chol, G_POTF2_Z, j0, s));
         BSE_TRY(run_gemm<double>(ar, trsm, s));
-        BSE_TRY(run_gemm<double>(ar, herk, s));
       }
+      return 0;
+    };
+    auto run_updates = [&](std::vector<GemmDesc>& v) -> int {
+      if (mixed) BSE_TRY(run_gemm<float>(ar, v, s));
+      else BSE_TRY(run_gemm<double>(ar, v, s));
+      return 0;
+    };
+    for (int k = 0; k < kmax; k += 2) {
+      const int j0 = 64 * k;
+      if (int e = factor_panels(j0)) return e;
+      std::vector<GemmDesc> next, rest;
+      for (const Prob& pr : probs) {
+        const int rows = pr.np - j0 - 64;
+        if (rows <= 0) break;
+        for (int f = 0; f < 2; ++f) {
+          void* M = factor_of(pr, f);
+          GemmDesc h;  // next column block: A[j0+64.., j0+64..j0+128] -= L21 L21[0..64]^H
+          h.M = rows; h.N = 64; h.K = 64;
+          h.A = at(M, pr, j0 + 64, j0); h.lda = pr.np; h.opA = 0;
+          h.B = h.A; h.ldb = pr.np; h.opB = 1;
+          h.C = at(M, pr, j0 + 64, j0 + 64); h.ldc = pr.np;
+          h.alpha_re = -1.0; h.beta_re = 1.0;
+          next.push_back(h);
+          const int rem = rows - 64;
+          if (rem <= 0) continue;
+          GemmDesc u;  // A22 -= L[rem, j0..j0+128] L[rem, j0..j0+128]^H, lower tiles
+          u.M = rem; u.N = rem; u.K = 128;
+          u.A = at(M, pr, j0 + 128, j0); u.lda = pr.np; u.opA = 0;
+          u.B = u.A; u.ldb = pr.np; u.opB = 1;
+          u.C = at(M, pr, j0 + 128, j0 + 128); u.ldc = pr.np;
+          u.alpha_re = -1.0; u.beta_re = 1.0; u.lowerC = 1;
+          rest.push_back(u);
+        }
+      }
+      if (next.empty()) continue;
+      if (int e = run_updates(next)) return e;
+      if (int e = factor_panels(j0 + 64)) return e;
+      if (!rest.empty())
+        if (int e = run_updates(rest)) return e;
     }
     std::vector<int> st(batch, kBig);
     BSE_TRY(hipMemcpyAsync(st.data(), d_status, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));

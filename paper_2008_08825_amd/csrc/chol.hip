@@ -338,32 +338,55 @@ hipError_t lower_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream
   return launch_one<ToC64Op>(a, tiles64(np), 0, s);
 }
 
+// Right-looking, two 64-column panels at a time: the first panel's block is
+// factored (Potf2), its rows below solved against the block's inverse, and
+// only the next column block updated with it; then the second panel likewise;
+// then the rest of the matrix is updated with both panels at once (K = 128),
+// so the trailing matrix passes through the update half as often.
 template <typename C2>
 static hipError_t cholesky_run(int np, int n_real, C2* M, long ld, C2* linv, int* status,
                                int base, hipStream_t s) {
   hipError_t (*gemm)(const GemmDesc&, hipStream_t) = sizeof(C2) == 16 ? gemm_z : gemm_c;
-  for (int j0 = 0; j0 < np; j0 += NB) {
+  auto factor_panel = [&](int j0) -> hipError_t {  // Potf2, then L21 = A21 L11^-H below it
     const Potf2Args<C2> pa = {M, ld, linv, status, base, n_real};
     hipError_t e = launch_one<Potf2Op<C2>>(pa, 1, j0, s);
     if (e != hipSuccess) return e;
     const int rows = np - j0 - NB;
-    if (rows <= 0) break;
+    if (rows <= 0) return hipSuccess;
     C2* panel = M + (j0 + NB) + (long)j0 * ld;
-    GemmDesc t;  // L21 = A21 * L11^-H (in place: one workgroup per row tile)
+    GemmDesc t;  // in place: one workgroup per row tile
     t.M = rows; t.N = NB; t.K = NB;
     t.A = panel; t.lda = ld; t.opA = 0;
     t.B = linv; t.ldb = NB; t.opB = 1; t.triB = 1;
     t.C = panel; t.ldc = ld;
-    e = gemm(t, s);
+    return gemm(t, s);
+  };
+  for (int j0 = 0; j0 < np; j0 += 2 * NB) {
+    hipError_t e = factor_panel(j0);
     if (e != hipSuccess) return e;
-    GemmDesc h;  // A22 -= L21 L21^H, lower tiles
-    h.M = rows; h.N = rows; h.K = NB;
-    h.A = panel; h.lda = ld; h.opA = 0;
-    h.B = panel; h.ldb = ld; h.opB = 1;
-    h.C = M + (j0 + NB) + (long)(j0 + NB) * ld; h.ldc = ld;
-    h.alpha_re = -1.0; h.beta_re = 1.0; h.lowerC = 1;
-    e = gemm(h, s);
-    if (e != hipSuccess) return e;
+    const int rows = np - j0 - NB;
+    if (rows <= 0) break;
+    {
+      GemmDesc h;  // next column block: A[j0+64.., j0+64..j0+128] -= L21 L21[0..64]^H
+      C2* panel = M + (j0 + NB) + (long)j0 * ld;
+      h.M = rows; h.N = NB; h.K = NB;
+      h.A = panel; h.lda = ld; h.opA = 0;
+      h.B = panel; h.ldb = ld; h.opB = 1;
+      h.C = M + (j0 + NB) + (long)(j0 + NB) * ld; h.ldc = ld;
+      h.alpha_re = -1.0; h.beta_re = 1.0;
+      if ((e = gemm(h, s)) != hipSuccess) return e;
+    }
+    if ((e = factor_panel(j0 + NB)) != hipSuccess) return e;
+    const int rest = rows - NB;
+    if (rest <= 0) break;
+    GemmDesc u;  // A22 -= L[rest, j0..j0+128] L[rest, j0..j0+128]^H, lower tiles
+    C2* both = M + (j0 + 2 * NB) + (long)j0 * ld;
+    u.M = rest; u.N = rest; u.K = 2 * NB;
+    u.A = both; u.lda = ld; u.opA = 0;
+    u.B = both; u.ldb = ld; u.opB = 1;
+    u.C = M + (j0 + 2 * NB) + (long)(j0 + 2 * NB) * ld; u.ldc = ld;
+    u.alpha_re = -1.0; u.beta_re = 1.0; u.lowerC = 1;
+    if ((e = gemm(u, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
