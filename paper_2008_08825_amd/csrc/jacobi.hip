@@ -335,13 +335,27 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
 // ---------------------------------------------------------------- inner eigensolver
 // Eigenvectors of the pair's 64 x 64 Gram by parallel cyclic Jacobi, in FP64.
 // Each step applies 32 disjoint rotations chosen by the circle method on the
-// 64 indices: the rotation parameters (which also give the rotated diagonal
-// 2 x 2 blocks), then every off-diagonal 2 x 2 block of G is replaced by
-// J_P^H G_PQ J_Q (P < Q), and the rotated column pairs of R by R J, the
-// last overlapped with the next step's parameters.  G keeps only its lower
-// triangle (and diagonal) up to date; G and R hold complex values as double2
-// (one 16-byte LDS access per entry).  The kernel is bound by LDS traffic.
+// 64 indices: every off-diagonal 2 x 2 block of G is replaced by
+// J_P^H G_PQ J_Q (P < Q) and the rotated column pairs of R by R J, while the
+// threads whose blocks hold the next step's pairs compute its rotation
+// parameters (which also give the rotated diagonal 2 x 2 blocks), so a step
+// takes one barrier.  G sits in LDS and keeps only its lower triangle (and
+// diagonal) up to date, complex values as double2 (one 16-byte LDS access per
+// entry); R sits in registers and moves between lanes.  The kernel is bound
+// by instruction issue and LDS latency.
 constexpr int EIG_THREADS = 512;
+
+// Whole-wave lane shifts by one: lane_down gives lane l the value of lane
+// l + 1, lane_up that of lane l - 1 (the end lanes get zero).
+template <int CTRL>
+BSE_DEV double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+BSE_DEV double2 lane_down(double2 v) { return make_double2(dpp_f64<0x130>(v.x), dpp_f64<0x130>(v.y)); }
+BSE_DEV double2 lane_up(double2 v) { return make_double2(dpp_f64<0x138>(v.x), dpp_f64<0x138>(v.y)); }
 
 template <typename T>
 struct EigOp {
@@ -377,13 +391,26 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   const int k = bx;
   int bp, bq;  // the pair's column blocks: pair columns 0..31 and 32..63
   round_pair(N, t, k, bp, bq);
-  // (P, Q), P < Q, of this thread's off-diagonal 2 x 2 block (threads 0..495):
-  // thread b holds the b-th pair in the order Q = 1..31, P = 0..Q-1.
+  // (P, Q), P < Q, of this thread's off-diagonal 2 x 2 block of a step
+  // (threads 0..495).  In the circle method the two indices of pair m of step
+  // s + 1 come from pairs m - 1 and m + 1 of step s ((0, 1) for m = 0,
+  // (30, 31) for m = 31): always the same 32 blocks, held by threads 0..31
+  // (thread m for pair m), which compute the next step's rotations right
+  // after updating their blocks.  Threads 32..495 take the other 464 blocks
+  // column by column: Q - 1 of them in column Q = 2..30 (P = Q - 2 left
+  // out), 29 in column 31 (P = 29, 30 left out).
   int bP = 0, bQ = 1;
-  {
-    int b = tid < 496 ? tid : 0;
-    while (b >= bQ) { b -= bQ; ++bQ; }
-    bP = b;
+  if (tid < 32) {
+    bP = tid == 0 ? 0 : (tid == 31 ? 30 : tid - 1);
+    bQ = tid == 0 ? 1 : (tid == 31 ? 31 : tid + 1);
+  } else if (tid < 496) {
+    int b = tid - 32, Q = 2;
+    while (b >= (Q < 31 ? Q - 1 : 29)) {
+      b -= Q < 31 ? Q - 1 : 29;
+      ++Q;
+    }
+    bQ = Q;
+    bP = (Q < 31 && b >= Q - 2) ? b + 1 : b;
   }
 
   // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian
@@ -462,9 +489,20 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   }
 
   // 3. Cyclic Jacobi.
-  for (int e = tid; e < JP * JP; e += NT) {
-    const int i = e & 63, j = e >> 6;
-    R[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  // R lives in registers, in circle-method slot order: the circle method keeps
+  // index 0 in slot 0 and moves the others one slot down the ring of slots
+  // 1..63 per step, and pair m always takes slots m and 63 - m.  Lane L of
+  // wave w holds, for rows 8 w + 2 u + L / 32 (u = 0..3), the entries of
+  // pair m = L % 32: top[u] in slot m, bot[u] in slot 63 - m.  After the
+  // rotation the entries move to the next step's slots by lane shifts.
+  // Whole sweeps bring every index back to its own slot.
+  const int lane = tid & 63, mR = lane & 31;
+  double2 top[4], bot[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = 8 * (tid >> 6) + 2 * u + (lane >> 5);
+    top[u] = make_double2(r == mR ? 1.0 : 0.0, 0.0);
+    bot[u] = make_double2(r == JP - 1 - mR ? 1.0 : 0.0, 0.0);
   }
   // A sweep whose largest relative off-diagonal entry (before its rotation)
   // was below sqrt(inner_stop2) leaves O(inner_stop2) behind (quadratic
@@ -472,156 +510,201 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   const double tol_in2 = 1.6e-31;  // (4e-16)^2
   const double stop2 = inner_stop2;
   int sweeps_done = 0;
-  int applied = 0;  // rotations applied by this lane (lanes 0..31)
-  int gstep = 0;    // steps run so far; parameters of step g sit in buffer g & 1
-  // R <- R J for the rotations of the step in buffer b: row r, rotations m0, m0 + dm, ...
-  // (at most five).  All parameters are read first, then all entries of R,
-  // so the LDS round trips overlap instead of following one another.
-  auto apply_r = [&](int b, int r, int m0, int dm) {
-    int xm[5];
-    double4 pp[5];
-#pragma unroll
-    for (int u = 0; u < 5; ++u) {
-      const int m = m0 + dm * u;
-      const int mc = m < 32 ? m : 31;
-      xm[u] = m < 32 ? pidx[b][mc] : 0;
-      pp[u] = prm[b][mc];
-    }
-    double2 ri[5], rj[5];
-#pragma unroll
-    for (int u = 0; u < 5; ++u) {
-      const int i = xm[u] & 255, j = (xm[u] >> 8) & 255;
-      ri[u] = R[r][i];
-      rj[u] = R[r][j];
-    }
-#pragma unroll
-    for (int u = 0; u < 5; ++u) {
-      if (xm[u] >> 16) {
-        const int i = xm[u] & 255, j = (xm[u] >> 8) & 255;
-        const double c = pp[u].x;
-        const double2 sv = make_double2(pp[u].y, pp[u].z);
-        R[r][i] = csub(cscale(ri[u], c), cmul(cconj(sv), rj[u]));
-        R[r][j] = cadd(cmul(sv, ri[u]), cscale(rj[u], c));
-      }
-    }
+  int applied = 0;  // rotations computed by this thread (threads 0..31)
+  // Pair m of step s: indices i < j
+  auto circle_pair = [&](int s, int m, int& i, int& j) {
+    const int a = m, b = JP - 1 - m;
+    i = (a == 0) ? 0 : ((a - 1 + s) % (JP - 1)) + 1;
+    j = ((b - 1 + s) % (JP - 1)) + 1;
+    if (i > j) { const int tmp = i; i = j; j = tmp; }
   };
-  // Each step runs in two phases separated by barriers:
-  //   A: lanes 0..31 of wave 0 compute the step's 32 rotations from G and
-  //      write the rotated diagonal 2 x 2 blocks (each lane touches only its
-  //      own pair's entries); meanwhile waves 1..7 apply the previous step's
-  //      rotations to R (double-buffered parameters), off the critical path;
-  //   B: the 496 off-diagonal 2 x 2 blocks G_PQ <- J_P^H G_PQ J_Q, one per
-  //      thread.
-  for (int sweep = 0; sweep < max_inner; ++sweep) {
-    int big = 0;
-    int anyrot = 0;
-    for (int step = 0; step < JP - 1; ++step, ++gstep) {
-      const int cur = gstep & 1;
+  // Rotation of pair m = (i, j), i < j, that zeroes G_ij = cc given G_ii = aa
+  // and G_jj = dd: writes the rotated diagonal entries and the parameters to
+  // buffer buf; returns whether it rotates (the caller zeroes G_ji) and sets
+  // big when |G_ij|^2 > stop2 |G_ii G_jj|.
+  auto pair_rotation = [&](int buf, int m, int i, int j, double aa, double dd, double2 cc,
+                           int& big) -> int {
+    const double cre = cc.x, cim = cc.y;
+    const double ac2 = cre * cre + cim * cim;
+    int rot = 0;
+    double cs = 1.0, sr = 0.0, si = 0.0;
+    const double add = fabs(aa * dd);
+    big = ac2 > stop2 * add ? 1 : 0;
+    if (ac2 > tol_in2 * add && ac2 > 0.0) {
+      rot = 1;
+      const double inv_ac = rsqrt(ac2);
+      const double ac = ac2 * inv_ac;
+      const double zeta = fmin(fmax(0.5 * (dd - aa) * inv_ac, -1.0e150), 1.0e150);
+      // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)): the smaller root, |angle| <= pi/4.
+      // Any t gives a unitary rotation (c = (1 + t^2)^-1/2, s = t c), so t
+      // needs no correctly rounded division: reciprocal plus two Newton steps.
+      const double den = fabs(zeta) + sqrt(fma(zeta, zeta, 1.0));
+      double rc = __builtin_amdgcn_rcp(den);
+      rc = rc * fma(-den, rc, 2.0);
+      rc = rc * fma(-den, rc, 2.0);
+      const double tt = zeta >= 0.0 ? rc : -rc;
+      cs = rsqrt(fma(tt, tt, 1.0));
+      const double sn = tt * cs;
+      sr = sn * cre * inv_ac;
+      si = sn * cim * inv_ac;
+      G[i][i] = make_double2(aa - tt * ac, 0.0);
+      G[j][j] = make_double2(dd + tt * ac, 0.0);
+    }
+    pidx[buf][m] = i | (j << 8) | (rot << 16);
+    prm[buf][m] = make_double4(cs, sr, si, 0.0);
+    return rot;
+  };
+  // One barrier per step.  The parameters of step s sit in buffer s & 1; in
+  // the step the 496 off-diagonal 2 x 2 blocks become G_PQ <- J_P^H G_PQ J_Q
+  // (one per thread), threads 0..31 then compute the rotations of step s + 1
+  // from their updated blocks and the rotated diagonal, and waves 1..7 apply
+  // the step's rotations to R.  Wave 0 keeps, in uniform registers, whether
+  // the sweep whose parameters it computes rotates anything and whether it
+  // meets a large entry; the verdict (go on with another sweep) is written to
+  // LDS with the sweep's last parameters and read in its last step.
+  __shared__ int scont;
+  if (max_inner > 0) {
+    int rot_any = 0, big_any = 0;
+    {
+      int rb = 0, bb = 0;
       if (tid < 32) {
-        const int a = tid, b = JP - 1 - tid;
-        int i = (a == 0) ? 0 : ((a - 1 + step) % (JP - 1)) + 1;
-        int j = ((b - 1 + step) % (JP - 1)) + 1;
-        if (i > j) { const int tmp = i; i = j; j = tmp; }
-        const double aa = G[i][i].x, dd = G[j][j].x;
-        const double2 cc = cconj(G[j][i]);  // G[i][j], from the stored lower triangle
-        const double cre = cc.x, cim = cc.y;
-        const double ac2 = cre * cre + cim * cim;
-        int rot = 0;
-        double cs = 1.0, sr = 0.0, si = 0.0;
-        const double add = fabs(aa * dd);
-        if (ac2 > stop2 * add) big = 1;
-        if (ac2 > tol_in2 * add && ac2 > 0.0) {
-          rot = 1;
-          const double inv_ac = rsqrt(ac2);
-          const double ac = ac2 * inv_ac;
-          const double zeta = fmin(fmax(0.5 * (dd - aa) * inv_ac, -1.0e150), 1.0e150);
-          // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)): the smaller root, |angle| <= pi/4.
-          // Any t gives a unitary rotation (c = (1 + t^2)^-1/2, s = t c), so t
-          // needs no correctly rounded division: reciprocal plus two Newton steps.
-          const double den = fabs(zeta) + sqrt(fma(zeta, zeta, 1.0));
-          double rc = __builtin_amdgcn_rcp(den);
-          rc = rc * fma(-den, rc, 2.0);
-          rc = rc * fma(-den, rc, 2.0);
-          const double tt = zeta >= 0.0 ? rc : -rc;
-          cs = rsqrt(fma(tt, tt, 1.0));
-          const double sn = tt * cs;
-          sr = sn * cre * inv_ac;
-          si = sn * cim * inv_ac;
-          G[i][i] = make_double2(aa - tt * ac, 0.0);
-          G[j][j] = make_double2(dd + tt * ac, 0.0);
+        int i, j;
+        circle_pair(0, tid, i, j);
+        rb = pair_rotation(0, tid, i, j, G[i][i].x, G[j][j].x, cconj(G[j][i]), bb);
+        if (rb) {
           G[j][i] = make_double2(0.0, 0.0);
-        }
-        if (rot) { anyrot = 1; ++applied; }
-        pidx[cur][tid] = i | (j << 8) | (rot << 16);
-        prm[cur][tid] = make_double4(cs, sr, si, 0.0);
-      } else if (tid >= 64 && gstep > 0) {
-        const int t7 = tid - 64;
-        apply_r(cur ^ 1, t7 & 63, t7 >> 6, (NT - 64) / 64);
-      }
-      __syncthreads();
-      if (tid < 496) {
-        const int P = bP, Q = bQ;
-        const int xP = pidx[cur][P], xQ = pidx[cur][Q];
-        const double4 ppP = prm[cur][P], ppQ = prm[cur][Q];
-        const int rP = xP >> 16, rQ = xQ >> 16;
-        if (rP | rQ) {
-          const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
-          // G holds its lower triangle only: entry (r, c) is G[r][c] for r > c
-          // and conj(G[c][r]) otherwise (r != c: the index sets are disjoint)
-          double2* p00 = iP > iQ ? &G[iP][iQ] : &G[iQ][iP];
-          double2* p01 = iP > jQ ? &G[iP][jQ] : &G[jQ][iP];
-          double2* p10 = jP > iQ ? &G[jP][iQ] : &G[iQ][jP];
-          double2* p11 = jP > jQ ? &G[jP][jQ] : &G[jQ][jP];
-          double2 g00 = *p00, g01 = *p01, g10 = *p10, g11 = *p11;
-          if (iP < iQ) g00 = cconj(g00);
-          if (iP < jQ) g01 = cconj(g01);
-          if (jP < iQ) g10 = cconj(g10);
-          if (jP < jQ) g11 = cconj(g11);
-          if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
-            const double4 pp = ppQ;
-            const double c = pp.x;
-            const double2 sq = make_double2(pp.y, pp.z);
-            const double2 sqc = cconj(sq);
-            const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
-            const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
-            const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
-            const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
-            g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-          }
-          if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
-            const double4 pp = ppP;
-            const double c = pp.x;
-            const double2 sp = make_double2(pp.y, pp.z);
-            const double2 spc = cconj(sp);
-            const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
-            const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
-            const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
-            const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
-            g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-          }
-          *p00 = iP > iQ ? g00 : cconj(g00);
-          *p01 = iP > jQ ? g01 : cconj(g01);
-          *p10 = jP > iQ ? g10 : cconj(g10);
-          *p11 = jP > jQ ? g11 : cconj(g11);
+          ++applied;
         }
       }
-      __syncthreads();
-    }
-    ++sweeps_done;
-    if (tid < 64) {  // wave 0: reduce over the 32 parameter lanes
-      int rr = anyrot, bb = big;
-      for (int o = 32; o > 0; o >>= 1) {
-        rr |= __shfl_xor(rr, o);
-        bb |= __shfl_xor(bb, o);
+      if (tid < 64) {
+        rot_any = __ballot(rb) != 0;
+        big_any = __ballot(bb) != 0;
       }
-      if (tid == 0) { nrot = rr; sweepbig = bb; }
     }
     __syncthreads();
-    if (nrot == 0 || sweepbig == 0) break;
-    __syncthreads();
+    int gstep = 0;
+    for (int sweep = 0;; ++sweep) {
+      for (int step = 0; step < JP - 1; ++step, ++gstep) {
+        const int cur = gstep & 1;
+        // the next step's rotations, unless this is the last step of the last sweep
+        const bool next = step < JP - 2 || scont;
+        int rb = 0, bb = 0;
+        if (tid < 496) {
+          const int P = bP, Q = bQ;
+          const int xP = pidx[cur][P], xQ = pidx[cur][Q];
+          const double4 ppP = prm[cur][P], ppQ = prm[cur][Q];
+          const int rP = xP >> 16, rQ = xQ >> 16;
+          const bool par = tid < 32 && next;
+          int i2 = 0, j2 = 0;
+          double aa2 = 0.0, dd2 = 0.0;
+          if (par) {
+            circle_pair(step + 1 < JP - 1 ? step + 1 : 0, tid, i2, j2);
+            aa2 = G[i2][i2].x;
+            dd2 = G[j2][j2].x;
+          }
+          if (rP | rQ | par) {
+            const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
+            // G holds its lower triangle only: entry (r, c) is G[r][c] for r > c
+            // and conj(G[c][r]) otherwise (r != c: the index sets are disjoint)
+            double2* p00 = iP > iQ ? &G[iP][iQ] : &G[iQ][iP];
+            double2* p01 = iP > jQ ? &G[iP][jQ] : &G[jQ][iP];
+            double2* p10 = jP > iQ ? &G[jP][iQ] : &G[iQ][jP];
+            double2* p11 = jP > jQ ? &G[jP][jQ] : &G[jQ][jP];
+            double2 g00 = *p00, g01 = *p01, g10 = *p10, g11 = *p11;
+            if (iP < iQ) g00 = cconj(g00);
+            if (iP < jQ) g01 = cconj(g01);
+            if (jP < iQ) g10 = cconj(g10);
+            if (jP < jQ) g11 = cconj(g11);
+            if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
+              const double4 pp = ppQ;
+              const double c = pp.x;
+              const double2 sq = make_double2(pp.y, pp.z);
+              const double2 sqc = cconj(sq);
+              const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
+              const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
+              const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
+              const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
+              g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+            }
+            if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
+              const double4 pp = ppP;
+              const double c = pp.x;
+              const double2 sp = make_double2(pp.y, pp.z);
+              const double2 spc = cconj(sp);
+              const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
+              const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
+              const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
+              const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
+              g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+            }
+            if (par) {
+              // the next pair's entry: its row index from pair P, column index from pair Q
+              const bool uP = iP == i2 || iP == j2, uQ = iQ == i2 || iQ == j2;
+              const double2 v = uP ? (uQ ? g00 : g01) : (uQ ? g10 : g11);
+              const double2 cc = (uP ? iP : jP) < (uQ ? iQ : jQ) ? v : cconj(v);  // G(i2, j2)
+              rb = pair_rotation(cur ^ 1, tid, i2, j2, aa2, dd2, cc, bb);
+              if (rb) {
+                const double2 z = make_double2(0.0, 0.0);
+                if (uP && uQ) g00 = z;
+                else if (uP) g01 = z;
+                else if (uQ) g10 = z;
+                else g11 = z;
+                ++applied;
+              }
+            }
+            *p00 = iP > iQ ? g00 : cconj(g00);
+            *p01 = iP > jQ ? g01 : cconj(g01);
+            *p10 = jP > iQ ? g10 : cconj(g10);
+            *p11 = jP > jQ ? g11 : cconj(g11);
+          }
+        }
+        {  // R <- R J_s in registers (an idle rotation has c = 1, s = 0)
+          const double4 pp = prm[cur][mR];
+          const int itop = mR == 0 ? 0 : ((mR - 1 + step) % (JP - 1)) + 1;
+          const int ibot = ((JP - 2 - mR + step) % (JP - 1)) + 1;
+          // top holds column i of the rotation and bot column j unless itop > ibot:
+          // new top = c top + a bot, new bot = c bot - conj(a) top with
+          // a = -conj(s), or a = s when swapped
+          const double c = pp.x, si = pp.z, ar = itop < ibot ? -pp.y : pp.y;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const double2 t = top[u], b = bot[u];
+            double2 nt, nb;
+            nt.x = fma(c, t.x, fma(ar, b.x, -si * b.y));
+            nt.y = fma(c, t.y, fma(ar, b.y, si * b.x));
+            nb.x = fma(c, b.x, -fma(ar, t.x, si * t.y));
+            nb.y = fma(c, b.y, fma(-ar, t.y, si * t.x));
+            // to the next step's slots: top of pair m + 1 (bottom of pair 31
+            // for m = 31, itself for m = 0); bottom of pair m - 1 (top of
+            // pair 1 for m = 0)
+            const double2 up = lane_down(nt), dn = lane_up(nb);
+            top[u] = mR == 31 ? nb : (mR == 0 ? nt : up);
+            bot[u] = mR == 0 ? up : dn;
+          }
+        }
+        if (tid < 64) {
+          const int ra = __ballot(rb) != 0, ba = __ballot(bb) != 0;
+          if (step == JP - 2) {  // first parameters of the next sweep
+            rot_any = ra;
+            big_any = ba;
+          } else {
+            rot_any |= ra;
+            big_any |= ba;
+          }
+          if (step == JP - 3 && tid == 0) scont = sweep + 1 < max_inner && rot_any && big_any;
+        }
+        __syncthreads();
+      }
+      ++sweeps_done;
+      if (!scont) break;
+    }
   }
-  // the last step's rotations, still pending on R
-  if (gstep > 0) apply_r((gstep - 1) & 1, tid & 63, tid >> 6, NT / 64);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int r = 8 * (tid >> 6) + 2 * u + (lane >> 5);
+    R[r][mR] = top[u];
+    R[r][JP - 1 - mR] = bot[u];
+  }
   __syncthreads();
   write_track();
   if (tid == 0) atomicAdd(inner_count, sweeps_done);
