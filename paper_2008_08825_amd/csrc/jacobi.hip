@@ -339,9 +339,10 @@ BSE_DEV void GramOp<T>::run(const typename GramOp<T>::Args& a, int bx, int t) {
 // J_P^H G_PQ J_Q (P < Q) and the rotated column pairs of R by R J, while the
 // threads whose blocks hold the next step's pairs compute its rotation
 // parameters (which also give the rotated diagonal 2 x 2 blocks), so a step
-// takes one barrier.  G sits in LDS and keeps only its lower triangle (and
-// diagonal) up to date, complex values as double2 (one 16-byte LDS access per
-// entry); R sits in registers and moves between lanes.  The kernel is bound
+// takes one barrier.  G sits in LDS with both triangles kept current (a
+// block update writes its mirror too, so that no access needs a conjugation
+// test), complex values as double2 (one 16-byte LDS access per entry); R sits
+// in registers and moves between lanes.  The kernel is bound
 // by instruction issue and LDS latency.
 constexpr int EIG_THREADS = 512;
 
@@ -491,16 +492,19 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   // 3. Cyclic Jacobi.
   // R lives in registers, in circle-method slot order: the circle method keeps
   // index 0 in slot 0 and moves the others one slot down the ring of slots
-  // 1..63 per step, and pair m always takes slots m and 63 - m.  Lane L of
-  // wave w holds, for rows 8 w + 2 u + L / 32 (u = 0..3), the entries of
-  // pair m = L % 32: top[u] in slot m, bot[u] in slot 63 - m.  After the
-  // rotation the entries move to the next step's slots by lane shifts.
-  // Whole sweeps bring every index back to its own slot.
-  const int lane = tid & 63, mR = lane & 31;
-  double2 top[4], bot[4];
+  // 1..63 per step, and pair m always takes slots m and 63 - m.  Waves 1..7
+  // hold R (wave 0 computes the rotations): wave w holds the row pairs
+  // g = rg0 .. rg0 + nrg - 1 (five each for waves 1..4, four for 5..7), and
+  // its lane L the entries of pair m = L % 32 in row 2 g + L / 32: top[u] in
+  // slot m, bot[u] in slot 63 - m.  After the rotation the entries move to
+  // the next step's slots by lane shifts.  Whole sweeps bring every index
+  // back to its own slot.
+  const int lane = tid & 63, mR = lane & 31, wv = tid >> 6;
+  const int rg0 = wv <= 4 ? 5 * (wv - 1) : 20 + 4 * (wv - 5), nrg = wv == 0 ? 0 : (wv <= 4 ? 5 : 4);
+  double2 top[5], bot[5];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = 8 * (tid >> 6) + 2 * u + (lane >> 5);
+  for (int u = 0; u < 5; ++u) {
+    const int r = 2 * (rg0 + u) + (lane >> 5);
     top[u] = make_double2(r == mR ? 1.0 : 0.0, 0.0);
     bot[u] = make_double2(r == JP - 1 - mR ? 1.0 : 0.0, 0.0);
   }
@@ -520,7 +524,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   };
   // Rotation of pair m = (i, j), i < j, that zeroes G_ij = cc given G_ii = aa
   // and G_jj = dd: writes the rotated diagonal entries and the parameters to
-  // buffer buf; returns whether it rotates (the caller zeroes G_ji) and sets
+  // buffer buf; returns whether it rotates (the caller zeroes G_ij and G_ji) and sets
   // big when |G_ij|^2 > stop2 |G_ii G_jj|.
   auto pair_rotation = [&](int buf, int m, int i, int j, double aa, double dd, double2 cc,
                            int& big) -> int {
@@ -573,6 +577,7 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
         rb = pair_rotation(0, tid, i, j, G[i][i].x, G[j][j].x, cconj(G[j][i]), bb);
         if (rb) {
           G[j][i] = make_double2(0.0, 0.0);
+          G[i][j] = make_double2(0.0, 0.0);
           ++applied;
         }
       }
@@ -588,77 +593,25 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
         const int cur = gstep & 1;
         // the next step's rotations, unless this is the last step of the last sweep
         const bool next = step < JP - 2 || scont;
-        int rb = 0, bb = 0;
-        if (tid < 496) {
-          const int P = bP, Q = bQ;
-          const int xP = pidx[cur][P], xQ = pidx[cur][Q];
-          const double4 ppP = prm[cur][P], ppQ = prm[cur][Q];
-          const int rP = xP >> 16, rQ = xQ >> 16;
-          const bool par = tid < 32 && next;
-          int i2 = 0, j2 = 0;
-          double aa2 = 0.0, dd2 = 0.0;
-          if (par) {
-            circle_pair(step + 1 < JP - 1 ? step + 1 : 0, tid, i2, j2);
-            aa2 = G[i2][i2].x;
-            dd2 = G[j2][j2].x;
-          }
-          if (rP | rQ | par) {
-            const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
-            // G holds its lower triangle only: entry (r, c) is G[r][c] for r > c
-            // and conj(G[c][r]) otherwise (r != c: the index sets are disjoint)
-            double2* p00 = iP > iQ ? &G[iP][iQ] : &G[iQ][iP];
-            double2* p01 = iP > jQ ? &G[iP][jQ] : &G[jQ][iP];
-            double2* p10 = jP > iQ ? &G[jP][iQ] : &G[iQ][jP];
-            double2* p11 = jP > jQ ? &G[jP][jQ] : &G[jQ][jP];
-            double2 g00 = *p00, g01 = *p01, g10 = *p10, g11 = *p11;
-            if (iP < iQ) g00 = cconj(g00);
-            if (iP < jQ) g01 = cconj(g01);
-            if (jP < iQ) g10 = cconj(g10);
-            if (jP < jQ) g11 = cconj(g11);
-            if (rQ) {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
-              const double4 pp = ppQ;
-              const double c = pp.x;
-              const double2 sq = make_double2(pp.y, pp.z);
-              const double2 sqc = cconj(sq);
-              const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
-              const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
-              const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
-              const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
-              g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-            }
-            if (rP) {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
-              const double4 pp = ppP;
-              const double c = pp.x;
-              const double2 sp = make_double2(pp.y, pp.z);
-              const double2 spc = cconj(sp);
-              const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
-              const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
-              const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
-              const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
-              g00 = t00; g01 = t01; g10 = t10; g11 = t11;
-            }
-            if (par) {
-              // the next pair's entry: its row index from pair P, column index from pair Q
-              const bool uP = iP == i2 || iP == j2, uQ = iQ == i2 || iQ == j2;
-              const double2 v = uP ? (uQ ? g00 : g01) : (uQ ? g10 : g11);
-              const double2 cc = (uP ? iP : jP) < (uQ ? iQ : jQ) ? v : cconj(v);  // G(i2, j2)
-              rb = pair_rotation(cur ^ 1, tid, i2, j2, aa2, dd2, cc, bb);
-              if (rb) {
-                const double2 z = make_double2(0.0, 0.0);
-                if (uP && uQ) g00 = z;
-                else if (uP) g01 = z;
-                else if (uQ) g10 = z;
-                else g11 = z;
-                ++applied;
-              }
-            }
-            *p00 = iP > iQ ? g00 : cconj(g00);
-            *p01 = iP > jQ ? g01 : cconj(g01);
-            *p10 = jP > iQ ? g10 : cconj(g10);
-            *p11 = jP > jQ ? g11 : cconj(g11);
-          }
+        // Loads first (the pairs' parameters, the thread's G block and, for
+        // threads 0..31, the next pair's diagonal entries; threads 496..511
+        // read block (0, 1) and leave it), then R, whose arithmetic covers
+        // their latency, then the block update.
+        const int P = bP, Q = bQ;
+        const int xP = pidx[cur][P], xQ = pidx[cur][Q];
+        const double4 ppP = prm[cur][P], ppQ = prm[cur][Q];
+        const int rP = xP >> 16, rQ = xQ >> 16;
+        const int iP = xP & 255, jP = (xP >> 8) & 255, iQ = xQ & 255, jQ = (xQ >> 8) & 255;
+        double2 g00 = G[iP][iQ], g01 = G[iP][jQ], g10 = G[jP][iQ], g11 = G[jP][jQ];
+        const bool par = tid < 32 && next;
+        int i2 = 0, j2 = 0;
+        double aa2 = 0.0, dd2 = 0.0;
+        if (tid < 32) {
+          circle_pair(step + 1 < JP - 1 ? step + 1 : 0, tid, i2, j2);
+          aa2 = G[i2][i2].x;
+          dd2 = G[j2][j2].x;
         }
-        {  // R <- R J_s in registers (an idle rotation has c = 1, s = 0)
+        if (wv > 0) {  // R <- R J_s in registers (an idle rotation has c = 1, s = 0)
           const double4 pp = prm[cur][mR];
           const int itop = mR == 0 ? 0 : ((mR - 1 + step) % (JP - 1)) + 1;
           const int ibot = ((JP - 2 - mR + step) % (JP - 1)) + 1;
@@ -667,7 +620,8 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
           // a = -conj(s), or a = s when swapped
           const double c = pp.x, si = pp.z, ar = itop < ibot ? -pp.y : pp.y;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
+          for (int u = 0; u < 5; ++u) {
+            if (u >= nrg) break;
             const double2 t = top[u], b = bot[u];
             double2 nt, nb;
             nt.x = fma(c, t.x, fma(ar, b.x, -si * b.y));
@@ -681,6 +635,50 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
             top[u] = mR == 31 ? nb : (mR == 0 ? nt : up);
             bot[u] = mR == 0 ? up : dn;
           }
+        }
+        int rb = 0, bb = 0;
+        if (tid < 496 && (rP | rQ | par)) {
+          {  // G2 <- G2 J_Q, J = [c s; -conj(s) c]
+            const double4 pp = ppQ;
+            const double c = pp.x;
+            const double2 sq = make_double2(pp.y, pp.z);
+            const double2 sqc = cconj(sq);
+            const double2 t00 = csub(cscale(g00, c), cmul(sqc, g01));
+            const double2 t01 = cadd(cmul(sq, g00), cscale(g01, c));
+            const double2 t10 = csub(cscale(g10, c), cmul(sqc, g11));
+            const double2 t11 = cadd(cmul(sq, g10), cscale(g11, c));
+            g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+          }
+          {  // G2 <- J_P^H G2, J^H = [c -s; conj(s) c]
+            const double4 pp = ppP;
+            const double c = pp.x;
+            const double2 sp = make_double2(pp.y, pp.z);
+            const double2 spc = cconj(sp);
+            const double2 t00 = csub(cscale(g00, c), cmul(sp, g10));
+            const double2 t01 = csub(cscale(g01, c), cmul(sp, g11));
+            const double2 t10 = cadd(cmul(spc, g00), cscale(g10, c));
+            const double2 t11 = cadd(cmul(spc, g01), cscale(g11, c));
+            g00 = t00; g01 = t01; g10 = t10; g11 = t11;
+          }
+          if (par) {
+            // the next pair's entry: its row index from pair P, column index from pair Q
+            const bool uP = iP == i2 || iP == j2, uQ = iQ == i2 || iQ == j2;
+            const double2 v = uP ? (uQ ? g00 : g01) : (uQ ? g10 : g11);
+            const double2 cc = (uP ? iP : jP) < (uQ ? iQ : jQ) ? v : cconj(v);  // G(i2, j2)
+            rb = pair_rotation(cur ^ 1, tid, i2, j2, aa2, dd2, cc, bb);
+            if (rb) {
+              const double2 z = make_double2(0.0, 0.0);
+              if (uP && uQ) g00 = z;
+              else if (uP) g01 = z;
+              else if (uQ) g10 = z;
+              else g11 = z;
+              ++applied;
+            }
+          }
+          G[iP][iQ] = g00; G[iQ][iP] = cconj(g00);
+          G[iP][jQ] = g01; G[jQ][iP] = cconj(g01);
+          G[jP][iQ] = g10; G[iQ][jP] = cconj(g10);
+          G[jP][jQ] = g11; G[jQ][jP] = cconj(g11);
         }
         if (tid < 64) {
           const int ra = __ballot(rb) != 0, ba = __ballot(bb) != 0;
@@ -700,8 +698,9 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
     }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int r = 8 * (tid >> 6) + 2 * u + (lane >> 5);
+  for (int u = 0; u < 5; ++u) {
+    if (u >= nrg) break;
+    const int r = 2 * (rg0 + u) + (lane >> 5);
     R[r][mR] = top[u];
     R[r][JP - 1 - mR] = bot[u];
   }
