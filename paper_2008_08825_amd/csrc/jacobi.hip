@@ -46,7 +46,8 @@ BSE_DEV int pair_col(int p, int q, int c) { return c < JB ? p * JB + c : q * JB 
 
 // ---------------------------------------------------------------- Gram tiles
 // Workgroup (pair k, chunk c) accumulates the ten lower tiles of X^H X over
-// rows [c * rc, (c + 1) * rc) and writes them to part[(k * kc + c) * 10 + tile].
+// the 16-row pieces c, c + kc, c + 2 kc, ... (rc rows) and writes them to
+// part[(k * kc + c) * 10 + tile].
 //
 // Tile t of the lower triangle lies in block row gram_ti(t), block column
 // gram_tj(t) (16-column blocks of the pair).  The work of a 16-row step (ten
@@ -201,7 +202,11 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
   typedef typename Mfma<T>::acc Acc;
   constexpr int TS = 8 + (WV >> 1), SH = WV & 1;
   const int tid = threadIdx.x, lane = tid & 63, h = lane >> 4, l15 = lane & 15;
-  const int rc = a.rc, row_beg = c * rc, row_end = row_beg + rc;
+  // The chunk's 16-row steps interleave with the other chunks': step j reads
+  // rows 16 (j kc + c) .. + 15, so the kc work groups of a pair, which run
+  // side by side, read neighbouring pieces of every column at the same time.
+  const int kc = a.kc, nsteps = a.rc >> 4;
+  auto row_of = [&](int j) { return 16 * (min(j, nsteps - 1) * kc + c); };
   GramLane<T> g;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
@@ -219,31 +224,31 @@ BSE_DEV void gram_wave(const typename GramOp<T>::Args& a, int p, int q, int k, i
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) acc[i][j] = Mfma<T>::zero();
-  // NST register stages in flight: rows r0 + 16, ..., r0 + 16 NST load while
-  // the MFMAs work on r0; 16-row steps alternate between two LDS buffers.
-  // Prefetches past the chunk re-read its last rows, so that every step
+  // NST register stages in flight: steps j + 1, ..., j + NST load while the
+  // MFMAs work on step j; steps alternate between two LDS buffers.
+  // Prefetches past the chunk re-read its last step, so that every step
   // issues the same loads and the waits for them stay partial.
   GramStage<T> st[NST];
 #pragma unroll
-  for (int i = 0; i < NST; ++i) src.load(st[i], min(row_beg + 16 * i, row_end - 16));
+  for (int i = 0; i < NST; ++i) src.load(st[i], row_of(i));
   C2* X0 = Xs;
   C2* X1 = Xs + 16 * JP;
-  int r0 = row_beg;
-  for (; r0 + 16 * NST <= row_end; r0 += 16 * NST) {
+  int j0 = 0;
+  for (; j0 + NST <= nsteps; j0 += NST) {
 #pragma unroll
     for (int i = 0; i < NST; ++i) {
-      C2* X = ((((r0 - row_beg) >> 4) + i) & 1) ? X1 : X0;
+      C2* X = ((j0 + i) & 1) ? X1 : X0;
       src.store(st[i], X);
       __syncthreads();
-      src.load(st[i], min(r0 + 16 * (i + NST), row_end - 16));
+      src.load(st[i], row_of(j0 + i + NST));
       __builtin_amdgcn_sched_barrier(0);  // issue the prefetch before the MFMA work
       gram_buffer<T, WV, CROSS>(X, g, acc);
     }
   }
 #pragma unroll
   for (int i = 0; i < NST; ++i) {  // the last steps, fewer than NST
-    if (r0 + 16 * i < row_end) {
-      C2* X = ((((r0 - row_beg) >> 4) + i) & 1) ? X1 : X0;
+    if (j0 + i < nsteps) {
+      C2* X = ((j0 + i) & 1) ? X1 : X0;
       src.store(st[i], X);
       __syncthreads();
       gram_buffer<T, WV, CROSS>(X, g, acc);
