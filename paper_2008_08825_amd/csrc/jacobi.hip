@@ -422,36 +422,66 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
   // 1. G = sum of the partial tiles (lower part), mirrored to a full Hermitian
   // matrix; with `cross`, only the cross block comes from partial tiles (tiles
   // 3, 4, 6, 7) and the two diagonal blocks from the tracked block Grams.
-  for (int e = tid; e < NTILE * 256; e += NT) {
-    const int tile = e >> 8, el = e & 255;
-    const int m = 16 * kTileI[tile] + (el & 15), n = 16 * kTileJ[tile] + (el >> 4);
-    if (m < n) continue;
-    if (cross && !(tile == 3 || tile == 4 || tile == 6 || tile == 7)) continue;
-    double sr = 0.0, si = 0.0;
-    const C2* src = part + ((long)k * kc * NTILE + tile) * 256 + el;
+  // Every thread sums five entries; the loads of several chunks are issued
+  // before the sums (the order of the sum over chunks stays 0, 1, ...).
+  {
+    constexpr int PE = NTILE * 256 / NT;
+    static_assert(PE * NT == NTILE * 256 && 4 * NT == 2 * JB * JB, "eig assembly split");
+    bool use[PE];
+    const C2* src[PE];
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      const int e = tid + u * NT, tile = e >> 8, el = e & 255;
+      const int m = 16 * kTileI[tile] + (el & 15), n = 16 * kTileJ[tile] + (el >> 4);
+      use[u] = m >= n && !(cross && !(tile == 3 || tile == 4 || tile == 6 || tile == 7));
+      src[u] = part + ((long)k * kc * NTILE + tile) * 256 + el;
+    }
+    double sr[PE], si[PE];
+#pragma unroll
+    for (int u = 0; u < PE; ++u) sr[u] = si[u] = 0.0;
+#pragma unroll 4
     for (int c = 0; c < kc; ++c) {
-      const C2 v = src[(long)c * NTILE * 256];
-      sr += (double)v.x;
-      si += (double)v.y;
+#pragma unroll
+      for (int u = 0; u < PE; ++u) {
+        if (use[u]) {
+          const C2 v = src[u][(long)c * NTILE * 256];
+          sr[u] += (double)v.x;
+          si[u] += (double)v.y;
+        }
+      }
     }
-    if (m == n) {
-      G[m][m] = make_double2(sr, 0.0);
-    } else {
-      G[m][n] = make_double2(sr, si);
-      G[n][m] = make_double2(sr, -si);
+    double2 tv[4];
+    if (cross) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT, b = e >> 10, m = e & 31, n = (e >> 5) & 31;
+        tv[u] = track[(long)(b ? bq : bp) * JB * JB + m + JB * n];
+      }
     }
-  }
-  if (cross) {
-    for (int e = tid; e < 2 * JB * JB; e += NT) {
-      const int b = e >> 10, m = e & 31, n = (e >> 5) & 31;
-      if (m < n) continue;
-      const double2 v = track[(long)(b ? bq : bp) * JB * JB + m + JB * n];
-      const int mm = m + JB * b, nn = n + JB * b;
+#pragma unroll
+    for (int u = 0; u < PE; ++u) {
+      if (!use[u]) continue;
+      const int e = tid + u * NT, tile = e >> 8, el = e & 255;
+      const int m = 16 * kTileI[tile] + (el & 15), n = 16 * kTileJ[tile] + (el >> 4);
       if (m == n) {
-        G[mm][mm] = make_double2(v.x, 0.0);
+        G[m][m] = make_double2(sr[u], 0.0);
       } else {
-        G[mm][nn] = v;
-        G[nn][mm] = cconj(v);
+        G[m][n] = make_double2(sr[u], si[u]);
+        G[n][m] = make_double2(sr[u], -si[u]);
+      }
+    }
+    if (cross) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = tid + u * NT, b = e >> 10, m = e & 31, n = (e >> 5) & 31;
+        if (m < n) continue;
+        const int mm = m + JB * b, nn = n + JB * b;
+        if (m == n) {
+          G[mm][mm] = make_double2(tv[u].x, 0.0);
+        } else {
+          G[mm][nn] = tv[u];
+          G[nn][mm] = cconj(tv[u]);
+        }
       }
     }
   }
