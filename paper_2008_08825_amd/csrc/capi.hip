@@ -100,8 +100,7 @@ int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* la
   BSE_TRY(hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, s));
   if (int e = form_and_check_args(n, A, lda, B, ldb, upper, base, p, s)) return e;
   tm.mark();
-  BSE_TRY(cholesky_z(np, n, M1, ld, linv, status, 0, s));
-  BSE_TRY(cholesky_z(np, n, M2, ld, linv, status, n, s));
+  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, linv, status, s));
   if (int st = read_status(status, n, info, s)) return st;
   tm.mark();
   {
@@ -171,8 +170,7 @@ int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* la
   BSE_TRY(hipMemcpyAsync(Z, M1, (size_t)np * np * sizeof(double2), hipMemcpyDeviceToDevice, s));
   BSE_TRY(mirror_upper_z(np, M1, ld, s));
   tm.mark();
-  BSE_TRY(cholesky_z(np, n, Z, ld, linv, status, 0, s));
-  BSE_TRY(cholesky_z(np, n, M2, ld, linv, status, n, s));
+  BSE_TRY(cholesky_pair_z(np, n, Z, M2, ld, linv, status, s));
   if (int st = read_status(status, n, info, s)) return st;
   tm.mark();
   {
@@ -257,8 +255,7 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   BSE_TRY(mirror_upper_z(np, M1, ld, s));  // full Hermitian FP64 M1, M2 for the refinement
   BSE_TRY(mirror_upper_z(np, M2, ld, s));
   tm.mark();
-  BSE_TRY(cholesky_c(np, n, L1c, ld, linv, status, 0, s));
-  BSE_TRY(cholesky_c(np, n, L2c, ld, linv, status, n, s));
+  BSE_TRY(cholesky_pair_c(np, n, L1c, L2c, ld, linv, status, s));
   if (int st = read_status(status, n, info, s)) return st;
   tm.mark();
   {
@@ -357,8 +354,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   BSE_TRY(hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, s));
   if (int e = form_and_check_args(n, A, lda, B, ldb, upper, base, p, s)) return e;
   tm.mark();
-  BSE_TRY(cholesky_z(np, n, M1, ld, linv, status, 0, s));
-  BSE_TRY(cholesky_z(np, n, M2, ld, linv, status, n, s));
+  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, linv, status, s));
   if (int st = read_status(status, n, info, s)) return st;
   tm.mark();
   {

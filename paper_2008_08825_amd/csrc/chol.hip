@@ -12,6 +12,7 @@
 #include "internal.hpp"
 
 #include <climits>
+#include <mutex>
 
 namespace bse {
 namespace {
@@ -518,6 +519,59 @@ hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status,
                       int base, hipStream_t s) {
   return cholesky_run<float2>(np, n_real, M, ld, linv, status, base, s);
+}
+
+// The two factorisations of Alg. 3 steps 1-2 are independent, and each is a
+// chain of small latency-bound steps (one work group factors a diagonal
+// block while the rest of the chip waits), so they run side by side: the
+// second on a library stream of the device (default priority), forked from
+// and joined back to the caller's stream by events.  The enqueue sequence
+// holds a lock, so calls from several host threads do not mix up the events.
+namespace {
+struct SideStream {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_side_mu;
+SideStream g_side[kMaxDevices];
+}  // namespace
+
+template <typename C2>
+static hipError_t cholesky_pair_run(int np, int n_real, C2* M1, C2* M2, long ld, C2* linv,
+                                    int* status, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) {
+    if ((e = cholesky_run<C2>(np, n_real, M1, ld, linv, status, 0, s)) != hipSuccess) return e;
+    return cholesky_run<C2>(np, n_real, M2, ld, linv + NB * NB, status, n_real, s);
+  }
+  std::lock_guard<std::mutex> lock(g_side_mu);
+  SideStream& sd = g_side[dev];
+  if (!sd.s) {
+    if ((e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  if ((e = hipEventRecord(sd.fork, s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(sd.s, sd.fork, 0)) != hipSuccess) return e;
+  const hipError_t e1 = cholesky_run<C2>(np, n_real, M1, ld, linv, status, 0, s);
+  const hipError_t e2 = cholesky_run<C2>(np, n_real, M2, ld, linv + NB * NB, status, n_real, sd.s);
+  // join even after a failed launch, so that s never runs ahead of the side stream
+  if ((e = hipEventRecord(sd.join, sd.s)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(s, sd.join, 0)) != hipSuccess) return e;
+  return e1 != hipSuccess ? e1 : e2;
+}
+
+hipError_t cholesky_pair_z(int np, int n_real, double2* M1, double2* M2, long ld, double2* linv,
+                           int* status, hipStream_t s) {
+  return cholesky_pair_run<double2>(np, n_real, M1, M2, ld, linv, status, s);
+}
+
+hipError_t cholesky_pair_c(int np, int n_real, float2* M1, float2* M2, long ld, float2* linv,
+                           int* status, hipStream_t s) {
+  return cholesky_pair_run<float2>(np, n_real, M1, M2, ld, linv, status, s);
 }
 
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux,

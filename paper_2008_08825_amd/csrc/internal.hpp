@@ -36,6 +36,14 @@ hipError_t gemm_c(const GemmDesc& d, hipStream_t s);  // complex64
 // 1-based, < n_real) is reported as atomicMin(status, base + index).
 hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv,
                       int* status, int base, hipStream_t s);
+// Both factors of Alg. 3 steps 1-2, M1 (status base 0) and M2 (base n_real):
+// M2's factorisation runs on a library stream beside s, ordered after the
+// work already on s, and s waits for it at the end.  linv holds two 64 x 64
+// inverses (one per factor).
+hipError_t cholesky_pair_z(int np, int n_real, double2* M1, double2* M2, long ld, double2* linv,
+                           int* status, hipStream_t s);
+hipError_t cholesky_pair_c(int np, int n_real, float2* M1, float2* M2, long ld, float2* linv,
+                           int* status, hipStream_t s);
 
 // M1 = A + B, M2 = A - B (lower triangles, zero strict upper part), padded to
 // np with identity; reads the `upper` or lower triangle of A, B.
