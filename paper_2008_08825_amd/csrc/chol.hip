@@ -397,10 +397,13 @@ hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, in
   return cholesky_run<double2>(np, n_real, M, ld, linv, status, base, s);
 }
 
-// The block triangular solves take the 64-column diagonal blocks two at a
-// time: the second block of a pair is updated with the first alone, and the
-// rest of the right-hand side with both at once (K = 128), so the remaining
-// rows pass through the update half as often as with one block at a time.
+// The block triangular solves take the 64-column diagonal blocks kTrsmGroup
+// at a time: a block of the group is first updated with the group's blocks
+// already solved (K = 64, 128, ...), then solved against its diagonal block's
+// inverse; after the group the rest of the right-hand side is updated with
+// all of its blocks at once (K = 64 kTrsmGroup), so the remaining rows pass
+// through the update kTrsmGroup times less often than with one block at a time.
+constexpr int kTrsmGroup = 4;
 
 // Z_i = op(L_ii^-1) Rhs_i for one 64-row block (left-side solves)
 static hipError_t trsm_diag(const double2* inv_i, int opA, int np, double2* Rhs_i, double2* Z_i,
@@ -433,21 +436,20 @@ hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // back substitution with L^H: block rows i, i - 1, ... ; (L^H)_{r, c} = conj(L_{c, r})
-  for (int i = nb - 1; i >= 0; i -= 2) {
-    const long ri = (long)i * NB;
-    if ((e = trsm_diag(inv + ri * NB, 1, np, Rhs + ri, Z + ri, ld, s)) != hipSuccess) return e;
-    int lo = i;  // first block row of the pair
-    if (i >= 1) {
-      const long r1 = ri - NB;
-      // Rhs_{i-1} -= (L^H)_{i-1, i} Z_i
-      if ((e = trsm_update(NB, np, NB, L + ri + r1 * ld, ld, 1, Z + ri, ld, Rhs + r1, ld, s)) != hipSuccess) return e;
-      if ((e = trsm_diag(inv + r1 * NB, 1, np, Rhs + r1, Z + r1, ld, s)) != hipSuccess) return e;
-      lo = i - 1;
+  for (int i = nb - 1; i >= 0; i -= kTrsmGroup) {
+    const int lo = i - kTrsmGroup + 1 > 0 ? i - kTrsmGroup + 1 : 0;  // first block row of the group
+    for (int b = i; b >= lo; --b) {
+      const long rb = (long)b * NB;
+      if (b < i) {
+        // Rhs_b -= (L^H)_{b, b+1..i} Z_{b+1..i}
+        const long r1 = rb + NB;
+        if ((e = trsm_update(NB, np, (i - b) * NB, L + r1 + rb * ld, ld, 1, Z + r1, ld, Rhs + rb, ld, s)) != hipSuccess) return e;
+      }
+      if ((e = trsm_diag(inv + rb * NB, 1, np, Rhs + rb, Z + rb, ld, s)) != hipSuccess) return e;
     }
     // Rhs_{0..lo-1} -= (L^H)_{0..lo-1, lo..i} Z_{lo..i}
     const long rl = (long)lo * NB;
-    const int k = (i - lo + 1) * NB;
-    if ((e = trsm_update(lo * NB, np, k, L + rl, ld, 1, Z + rl, ld, Rhs, ld, s)) != hipSuccess) return e;
+    if ((e = trsm_update(lo * NB, np, (i - lo + 1) * NB, L + rl, ld, 1, Z + rl, ld, Rhs, ld, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -458,21 +460,18 @@ hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
   k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  for (int i = 0; i < nb; i += 2) {
+  for (int i = 0; i < nb; i += kTrsmGroup) {
+    const int hi = i + kTrsmGroup - 1 < nb ? i + kTrsmGroup - 1 : nb - 1;  // last block row of the group
     const long ri = (long)i * NB;
-    if ((e = trsm_diag(inv + ri * NB, 0, np, Rhs + ri, Z + ri, ld, s)) != hipSuccess) return e;
-    int hi = i;  // last block row of the pair
-    if (i + 1 < nb) {
-      const long r1 = ri + NB;
-      // Rhs_{i+1} -= L_{i+1, i} Z_i
-      if ((e = trsm_update(NB, np, NB, L + r1 + ri * ld, ld, 0, Z + ri, ld, Rhs + r1, ld, s)) != hipSuccess) return e;
-      if ((e = trsm_diag(inv + r1 * NB, 0, np, Rhs + r1, Z + r1, ld, s)) != hipSuccess) return e;
-      hi = i + 1;
+    for (int b = i; b <= hi; ++b) {
+      const long rb = (long)b * NB;
+      // Rhs_b -= L_{b, i..b-1} Z_{i..b-1}
+      if (b > i && (e = trsm_update(NB, np, (b - i) * NB, L + rb + ri * ld, ld, 0, Z + ri, ld, Rhs + rb, ld, s)) != hipSuccess) return e;
+      if ((e = trsm_diag(inv + rb * NB, 0, np, Rhs + rb, Z + rb, ld, s)) != hipSuccess) return e;
     }
     // Rhs_{hi+1..} -= L_{hi+1.., i..hi} Z_{i..hi}
     const long rn = (long)(hi + 1) * NB;
-    const int k = (hi - i + 1) * NB;
-    if ((e = trsm_update(np - (int)rn, np, k, L + rn + ri * ld, ld, 0, Z + ri, ld, Rhs + rn, ld, s)) != hipSuccess) return e;
+    if ((e = trsm_update(np - (int)rn, np, (hi - i + 1) * NB, L + rn + ri * ld, ld, 0, Z + ri, ld, Rhs + rn, ld, s)) != hipSuccess) return e;
   }
   return hipSuccess;
 }
@@ -503,13 +502,11 @@ hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
     u.alpha_re = -1.0; u.beta_re = 1.0;
     return gemm_z(u, s);
   };
-  for (int j = 0; j < nb; j += 2) {
-    if ((e = diag(j)) != hipSuccess) return e;
-    int hi = j;
-    if (j + 1 < nb) {
-      if ((e = update((j + 1) * NB, NB, j * NB, NB)) != hipSuccess) return e;
-      if ((e = diag(j + 1)) != hipSuccess) return e;
-      hi = j + 1;
+  for (int j = 0; j < nb; j += kTrsmGroup) {
+    const int hi = j + kTrsmGroup - 1 < nb ? j + kTrsmGroup - 1 : nb - 1;
+    for (int c = j; c <= hi; ++c) {
+      if (c > j && (e = update(c * NB, NB, j * NB, (c - j) * NB)) != hipSuccess) return e;
+      if ((e = diag(c)) != hipSuccess) return e;
     }
     if ((e = update((hi + 1) * NB, np - (hi + 1) * NB, j * NB, (hi - j + 1) * NB)) != hipSuccess) return e;
   }
