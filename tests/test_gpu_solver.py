@@ -353,3 +353,39 @@ def test_tracked_gram_sweeps_reported(gpu_lib, precision):
         assert 0 <= info["polish_cross_pair_checks"] < info["polish_pair_checks"]
         assert info["polish_cross_pair_checks"] % per_sweep == 0
     check_against_oracle(A, B, lam, X)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_concurrent_solves_on_two_streams(gpu_lib, precision):
+    """Two host threads, each solving on a stream of its own, while the
+    library runs the second Cholesky factorisation of every solve on its own
+    stream: the results equal those of one solve at a time, bit for bit."""
+    import threading
+    n = 200
+    probs = [inputs.coupled(n, seed=s) for s in (21, 22)]
+    ref = [run(gpu_lib, A, B, precision=precision) for A, B in probs]
+    out = [None, None]
+    errs = []
+
+    def work(i):
+        try:
+            s = torch.cuda.Stream(device=DEV)
+            with torch.cuda.stream(s):
+                A, B = probs[i]
+                lam, X, info = gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV),
+                                                precision=precision)
+                s.synchronize()
+                out[i] = (lam.cpu().numpy(), X.resolve_conj().cpu().numpy(), info["status"])
+        except Exception as e:  # re-raised in the test's thread
+            errs.append(e)
+
+    print(f"[gpu] two threads, two streams, {precision}", flush=True)
+    ts = [threading.Thread(target=work, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=100)
+    assert not errs, errs
+    for i in range(2):
+        assert out[i] is not None and out[i][2] == 0
+        assert np.array_equal(out[i][0], ref[i][0]) and np.array_equal(out[i][1], ref[i][1])
