@@ -17,11 +17,17 @@
  *   - Every matrix and vector pointer is a DEVICE pointer owned by the
  *     caller.  The library never allocates or frees device memory: the
  *     caller passes a workspace of at least the size the matching
- *     *_workspace_bytes query returns.  Nothing is retained after return.
+ *     *_workspace_bytes query returns.  No data is retained after return.
  *   - All device work is enqueued on `stream` (a hipStream_t; NULL = the
- *     default stream).  The calls are synchronous: they wait on `stream`
- *     to read the device status word (and, in the Jacobi phase, once per
- *     sweep for the convergence count) before returning.
+ *     default stream), with one exception: of the two Cholesky
+ *     factorisations of Alg. 3 steps 1-2 (and of the Alg. 2 route), the
+ *     second runs on a stream the library creates once per device (default
+ *     priority, with two events; kept until the process ends), ordered after
+ *     the work already on `stream`, and `stream` waits for it before the next
+ *     step.  The calls are synchronous: they wait on `stream` to read the
+ *     device status word (and, in the Jacobi phase, once per sweep for the
+ *     convergence count) before returning.  Calls from several host threads
+ *     may run at once on different streams.
  *   - Only the triangle selected by `uplo` ('L' or 'U') of A and B is read;
  *     the imaginary parts of their diagonals are ignored.
  *   - No C++ exception crosses the ABI.  Return codes:

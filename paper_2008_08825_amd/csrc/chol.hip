@@ -537,8 +537,8 @@ SideStream g_side[kMaxDevices];
 template <typename C2>
 static hipError_t cholesky_pair_run(int np, int n_real, C2* M1, C2* M2, long ld, C2* linv,
                                     int* status, hipStream_t s) {
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
+  int dev = 0;  // the device of the caller's stream (the current device for the null stream)
+  hipError_t e = hipStreamGetDevice(s, &dev);
   if (e != hipSuccess) return e;
   if (dev < 0 || dev >= kMaxDevices) {
     if ((e = cholesky_run<C2>(np, n_real, M1, ld, linv, status, 0, s)) != hipSuccess) return e;
@@ -546,10 +546,19 @@ static hipError_t cholesky_pair_run(int np, int n_real, C2* M1, C2* M2, long ld,
   }
   std::lock_guard<std::mutex> lock(g_side_mu);
   SideStream& sd = g_side[dev];
-  if (!sd.s) {
-    if ((e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming)) != hipSuccess) return e;
+  if (!sd.s) {  // created on the stream's device, kept until the process ends
+    int cur = 0;
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
+    const hipError_t er = cur != dev ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) {
+      sd.s = nullptr;  // try again on the next call
+      return e;
+    }
+    if (er != hipSuccess) return er;
   }
   if ((e = hipEventRecord(sd.fork, s)) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(sd.s, sd.fork, 0)) != hipSuccess) return e;
