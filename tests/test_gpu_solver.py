@@ -3,7 +3,7 @@
 Tolerances (FP64 form): eigenvalues are column norms after a one-sided Jacobi
 SVD whose rotations stop below a relative off-orthogonality of n * eps, so
 the relative eigenvalue error is bounded by a small multiple of
-eps * cond(H1) (Sec. 3.4 error estimate for the SVD route); cond(H1) is below
+eps * cond(H1) (Sec. 3.3: Eq. SquaredErr and its SVD remedy); cond(H1) is below
 100 for these inputs, giving the 1e-12 bound used here.  Eigenvectors are
 unique up to a phase (and only as a subspace inside clusters), so they are
 compared phase-aligned with a gap-dependent allowance, and through the

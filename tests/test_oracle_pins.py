@@ -156,7 +156,7 @@ def test_dense_route_pinned_by_closed_forms():
 
 @pytest.mark.parametrize("n,seed", [(2, 0), (3, 1), (5, 2)])
 def test_mpmath_50_digits(n, seed):
-    """Brute-force eigenvalues at 50 digits bound the FP64 routes' error (error bound of Sec. 3.4)."""
+    """Brute-force eigenvalues at 50 digits bound the FP64 routes' error (error estimate of Sec. 3.3)."""
     A, B = inputs.coupled(n, seed=seed, diag_lo=1.0, diag_hi=3.0, c_norm=0.5, b_norm=0.4)
     ref = np.array([float(v) for v in ob.solve_mp(A, B)])
     for solve in (ob.solve_chol_svd, ob.solve_pencil):
@@ -223,7 +223,7 @@ def test_condition_family_closed_form_and_table2_levels():
         if kappa >= 1e6:
             # Squared eigenvalues (Eq. SquaredErr) cost CHOL accuracy that CHOL+SVD keeps.
             assert err_chol > 100 * err_svd
-        # Whole spectrum, CHOL+SVD: error bound eps ||H||_2 / s(lambda) of Sec. 3.4.
+        # Whole spectrum, CHOL+SVD: error estimate eps ||H||_2 / s(lambda) of Sec. 3.3.
         abs_err = np.max(np.abs(lam - exact))
         assert abs_err < 200 * EPS * np.max(exact)
 
