@@ -21,6 +21,8 @@ and ``B`` is read and the imaginary part of the diagonal is ignored
 Routes
 ------
 ``solve_chol_svd``  Alg. 3 (CHOL+SVD) with LAPACK ``gesvd``, the primary oracle.
+``eigenvalues_chol_svd``  Alg. 3 steps 1-3 only, the eigenvalues (what Table 2
+                    times and measures), for sizes where vectors cost too much.
 ``solve_chol_eig``  Alg. 2 (CHOL) with LAPACK ``heevd``.
 ``solve_pencil``    the Hermitian-definite pencil route (Thm DefiniteRealEvals).
 ``solve_dense``     nonsymmetric ``eig`` of the full ``H1`` (tiny n only).
@@ -43,6 +45,7 @@ __all__ = [
     "bse_matrix",
     "bse_hamiltonian",
     "solve_chol_svd",
+    "eigenvalues_chol_svd",
     "solve_chol_eig",
     "solve_pencil",
     "solve_dense",
@@ -107,6 +110,23 @@ def solve_chol_svd(A: np.ndarray, B: np.ndarray):
     X = _assemble(V1, V2)
     order = np.argsort(s, kind="stable")
     return s[order], X[:, order]
+
+
+def eigenvalues_chol_svd(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """Alg. 3 steps 1-3 without vectors: the singular values of ``L1^H L2``.
+
+    Sec. 4 measures and times the eigenvalues alone (Table 2); the singular
+    values of ``L1^H L2`` are the positive eigenvalues of ``H1`` (Lemma
+    SVDScalarFactors / Thm ProdEig: ``M1 M2`` has eigenvalues ``lambda^2``).
+    Same LAPACK ``potrf`` and ``gesvd`` as :func:`solve_chol_svd`, with
+    ``compute_uv=False``.  Returns the eigenvalues ascending.
+    """
+    A = hermitian_from_lower(A)
+    B = hermitian_from_lower(B)
+    L1 = sla.cholesky(A + B, lower=True)
+    L2 = sla.cholesky(A - B, lower=True)
+    s = sla.svd(L1.conj().T @ L2, compute_uv=False, lapack_driver="gesvd")
+    return np.sort(s, kind="stable")
 
 
 def solve_chol_eig(A: np.ndarray, B: np.ndarray):

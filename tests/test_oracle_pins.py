@@ -314,6 +314,69 @@ def test_spectrum_loss_weights_match_finite_differences():
         assert abs(fd - w[k]) < 1e-5 * max(1, abs(w[k]))
 
 
+# ---------------------------------------------------------------- eigenvalues only
+def eigenvalue_pins(evals):
+    """Pins of an eigenvalues-only route: closed forms, brute force, mpmath,
+    the trace and log-det identities and the Sec. 4 condition family."""
+    fails = []
+    for a, b in [(2.0, 0.5), (3.0, -1.2), (5.0, 4.9)]:
+        lam = evals(np.array([[a]], complex), np.array([[b]], complex))
+        lref = np.sqrt((a + b) * (a - b))
+        if abs(lam[0] - lref) > 8 * EPS * (a + abs(b)) / (a - abs(b)) * lref:
+            fails.append(("n1", a, b))
+    A, B, lam_ref, _ = commuting_problem(24, 3)
+    if om.rel_eig_err(evals(A, B), lam_ref) > 1e-13:
+        fails.append(("commuting",))
+    A, B = inputs.coupled(8, seed=5, diag_lo=1.0, diag_hi=4.0, c_norm=0.4, b_norm=0.4)
+    if om.rel_eig_err(evals(A, B), ob.solve_dense(A, B)[0]) > 1e-12:
+        fails.append(("dense eig",))
+    A, B = inputs.coupled(3, seed=1, diag_lo=1.0, diag_hi=3.0, c_norm=0.5, b_norm=0.4)
+    lmp = np.array([float(v) for v in ob.solve_mp(A, B)])
+    if om.rel_eig_err(evals(A, B), lmp) > 4 * EPS * 10:
+        fails.append(("mpmath",))
+    A, B = inputs.coupled(40, seed=7)
+    lam = evals(A, B)
+    Ah = ob.hermitian_from_lower(A)
+    Bh = ob.hermitian_from_lower(B)
+    tr_ref = np.linalg.norm(Ah) ** 2 - np.linalg.norm(Bh) ** 2
+    if abs(np.sum(lam ** 2) - tr_ref) > 1e-13 * abs(tr_ref):
+        fails.append(("trace identity",))
+    L1 = sla.cholesky(Ah + Bh, lower=True)
+    L2 = sla.cholesky(Ah - Bh, lower=True)
+    ld_ref = np.sum(np.log(np.diag(L1).real)) + np.sum(np.log(np.diag(L2).real))
+    if abs(np.sum(np.log(lam)) - ld_ref) > 1e-12 * max(1.0, abs(ld_ref)):
+        fails.append(("log-det identity",))
+    A, B, d = inputs.condition_family(60, 1e6, seed=4)
+    if om.rel_eig_err(evals(A, B), np.sqrt(3) / 2 * d) > 1e-9:
+        fails.append(("condition family",))
+    return fails
+
+
+def test_eigenvalues_only_route_pinned():
+    """Alg. 3 steps 1-3 without vectors (the quantity of Table 2)."""
+    assert eigenvalue_pins(ob.eigenvalues_chol_svd) == []
+    A, B = inputs.clustered(300, seed=2)
+    lam = ob.eigenvalues_chol_svd(A, B)
+    lam_v, _ = ob.solve_chol_svd(A, B)
+    assert om.rel_eig_err(lam, lam_v) < 1e-14
+    assert np.all(np.diff(lam) >= 0)
+
+
+@pytest.mark.parametrize("kind", ["svd_of_L1_L2H", "no_conj_transpose", "sqrt_of_values"])
+def test_eigenvalue_pins_catch_planted_mistakes(kind):
+    def evals(A, B):
+        A = ob.hermitian_from_lower(A)
+        B = ob.hermitian_from_lower(B)
+        L1 = sla.cholesky(A + B, lower=True)
+        L2 = sla.cholesky(A - B, lower=True)
+        M = {"svd_of_L1_L2H": L1 @ L2.conj().T, "no_conj_transpose": L1.T @ L2}.get(kind, L1.conj().T @ L2)
+        s = sla.svd(M, compute_uv=False)
+        if kind == "sqrt_of_values":  # the singular values taken as lambda^2 (Thm ProdEig's mu)
+            s = np.sqrt(s)
+        return np.sort(s)
+    assert eigenvalue_pins(evals) != []
+
+
 # ---------------------------------------------------------------- planted mistakes
 def _mutant(kind):
     def solve(A, B):
