@@ -76,11 +76,15 @@ typedef struct {
                          once a step's largest correction is <= 1e-6;
                          0 = default (8), at most 8                            */
   double jacobi_tol;  /* rotate a block pair while max |g_ij|/sqrt(g_ii g_jj)
-                         exceeds this; 0 = default n * eps of the bulk dtype    */
+                         exceeds this; 0 = default: 8 sqrt(n) eps64 for FP64
+                         sweeps, 4 sqrt(n) eps32 for complex64 ones (n >= 64) */
   int want_negative;  /* nonzero: also write -lambda and [0 I; I 0] X           */
   int uplo;           /* 'L' (default when 0) or 'U'                            */
   int tile_entries;   /* rows in tile_table; 0 = built-in tile choice           */
-  int reserved0;      /* must be zero                                           */
+  int checks;         /* 1: also measure the returned pairs on the device and
+                         report info->sigma_orth_fro and info->max_rel_resid
+                         (one n x n GEMM and two triangular products more);
+                         0 = off                                              */
   const int* tile_table; /* host array of tile_entries rows {np_max, kc, rrows}
                          for the Jacobi kernels: a problem of padded order np
                          (n rounded up to 64) takes the first row with
@@ -129,6 +133,18 @@ typedef struct {
   double polish_kernel_ms[3];
   int polish_kernel_launches[3];
   int polish_cross_pair_checks;  /* the same for the FP64 sweeps               */
+  int fallback;         /* 0: none; 1: MIXED_POLISH found the recovered rotation
+                           too far from unitary (its Cholesky QR failed,
+                           kappa(W) eps32 near 1) and ran the FP64 sweeps on W
+                           itself; 2: MIXED re-solved the problem in FP64 (its
+                           complex64 Cholesky failed or the refinement did not
+                           reach its tolerance)                               */
+  double sigma_orth_fro;  /* opts.checks: ||X^H Sigma X - I||_F of the returned
+                           X (the measure of Sec. 4, Fig. 2), else 0          */
+  double max_rel_resid;   /* opts.checks: max_k ||H1 x_k - lambda_k x_k||_2 /
+                           (lambda_n ||x_k||_2) over the returned pairs (lambda_n
+                           the largest eigenvalue), else 0                    */
+  double refine_corr[8];  /* MIXED: largest correction of each refinement step */
 } bse_info_t;
 
 /* Fill `opts` with the defaults (route SVD, FP64, lower triangles). */
@@ -211,6 +227,7 @@ int bse_backward(int n, const void* X, int ldx, const double* w,
 
 /* Short text for a return code (static storage). */
 const char* bse_status_string(int status, int n);
+
 
 #ifdef __cplusplus
 }

@@ -37,7 +37,7 @@ class BSEOpts(ctypes.Structure):
         ("want_negative", ctypes.c_int),
         ("uplo", ctypes.c_int),
         ("tile_entries", ctypes.c_int),
-        ("reserved0", ctypes.c_int),
+        ("checks", ctypes.c_int),
         ("tile_table", ctypes.POINTER(ctypes.c_int)),
         ("reserved", ctypes.c_int * 2),
     ]
@@ -67,6 +67,10 @@ class BSEInfo(ctypes.Structure):
         ("polish_kernel_ms", ctypes.c_double * 3),
         ("polish_kernel_launches", ctypes.c_int * 3),
         ("polish_cross_pair_checks", ctypes.c_int),
+        ("fallback", ctypes.c_int),
+        ("sigma_orth_fro", ctypes.c_double),
+        ("max_rel_resid", ctypes.c_double),
+        ("refine_corr", ctypes.c_double * 8),
     ]
 
     def as_dict(self):
@@ -92,6 +96,10 @@ class BSEInfo(ctypes.Structure):
             "polish_inner_rotations": self.polish_inner_rotations,
             "polish_kernel_ms": list(self.polish_kernel_ms),
             "polish_kernel_launches": list(self.polish_kernel_launches),
+            "fallback": self.fallback,
+            "sigma_orth_fro": self.sigma_orth_fro,
+            "max_rel_resid": self.max_rel_resid,
+            "refine_corr": list(self.refine_corr[: max(0, min(8, self.refine_steps_done))]),
         }
 
 
@@ -157,7 +165,7 @@ class BSEError(RuntimeError):
 
 
 def make_opts(route="svd", precision="fp64", max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
-              want_negative=False, uplo="L", tiles=None) -> BSEOpts:
+              want_negative=False, uplo="L", tiles=None, checks=False) -> BSEOpts:
     """Options struct; ``tiles`` = rows ``(np_max, kc, rrows)`` of the Jacobi tile table."""
     o = BSEOpts()
     load_library().bse_default_opts(ctypes.byref(o))
@@ -168,6 +176,7 @@ def make_opts(route="svd", precision="fp64", max_sweeps=0, refine_steps=0, jacob
     o.jacobi_tol = float(jacobi_tol)
     o.want_negative = 1 if want_negative else 0
     o.uplo = ord(uplo)
+    o.checks = 1 if checks else 0
     if tiles:
         flat = [int(v) for row in tiles for v in row]
         arr = (ctypes.c_int * len(flat))(*flat)
@@ -212,7 +221,7 @@ def workspace_bytes(n: int, **kw) -> int:
 def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
              want_negative=False, max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
              timing=False, check=True, work: Optional[torch.Tensor] = None,
-             out=None, tiles=None):
+             out=None, tiles=None, checks=False):
     """All eigenpairs of H1 = [[A, B], [-B, -A]] (lower triangles of A, B read).
 
     Returns ``(lam, X, info)``: ``lam`` (n, ascending; 2n with ``want_negative``),
@@ -230,7 +239,8 @@ def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
     n = A.shape[0]
     dev = A.device
     ncols = 2 * n if want_negative else n
-    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, ua, tiles)
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, ua, tiles,
+                  checks)
     if out is None:
         lam = torch.empty(ncols, dtype=torch.float64, device=dev)
         Xbuf = torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)

@@ -157,6 +157,7 @@ struct Prob {
   double2 *x = nullptr, *y = nullptr, *q = nullptr, *f = nullptr;
   int rsteps = 0, rdone = 0;
   double rcorr = 0.0;
+  double rhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
@@ -429,7 +430,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
 
   // ---- one-sided block Jacobi over the whole batch
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : (mixed ? 20 : 30);
-  const double eps32 = 1.1920928955078125e-07, eps64 = 2.220446049250313e-16;
+  const double eps32 = 1.1920928955078125e-07;
   std::vector<JacState> states(batch);
   if (!ok.empty()) {
     Grp<GramArgs<double2>> gz;
@@ -451,7 +452,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       jw.inner_rot = &st->inner_rot;
       jw.maxoff = &st->maxoff;
       const double nn = (double)(pr->n > 64 ? pr->n : 64);
-      const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : nn * eps64);
+      const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : default_tol64(pr->n));
       if (mixed) {
         float2* W = pr->at<float2>(pr->p.off_wc);
         GramArgs<float2> ga = gram_args_c(np, W, np, jw, &st->done);
@@ -576,7 +577,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         v2.push_back(tri_gemm(np, np, L2c, 0, Wc, 0, 0, Yc));  // V2 = L2 Ws
         t.push_back(tri_gemm(np, np, L1c, 1, Yc, 0, 0, Wc));   // T = L1^H V2
         n3.add({Wc, np, np, anorm}, np);
-        la.add({pr->n, np, anorm, bnorm, pr->at<double>(pr->p.off_lamu), invlam, scl}, (np + 255) / 256);
+        la.add({pr->n, np, anorm, bnorm, pr->at<double>(pr->p.off_lamu), invlam, scl, 0}, (np + 255) / 256);
         GemmDesc v = tri_gemm(np, np, L1c, 0, Wc, 0, 0, L2c);  // V1 = L1 T Lambda^-1
         v.colscale = invlam;
         v1.push_back(v);
@@ -650,6 +651,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         for (Prob* pr : act) {
           std::swap(pr->x, pr->q);
           std::swap(pr->y, pr->f);
+          if (pr->rsteps < 8) pr->rhist[pr->rsteps] = corr[pr->idx];
           pr->rsteps += 1;
           pr->rcorr = corr[pr->idx];
           // the error left after a step is of the order of the square of its correction
@@ -681,31 +683,48 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         double* lamu = pr->at<double>(pr->p.off_lamu);
         double* scl = pr->at<double>(pr->p.off_scl);
         int* perm = pr->at<int>(pr->p.off_perm);
-        rq.add({nn, pr->x, pr->y, P2, P1, ld, lamu, scl}, nn);
+        rq.add({nn, pr->x, pr->y, P2, P1, ld, lamu, scl, d_corr + pr->idx}, nn);
         rk.add({nn, lamu, perm, 0}, (nn + 255) / 256);
         wl.add({nn, lamu, perm, pr->lambda, o.want_negative}, (nn + 255) / 256);
-        as.add({nn, pr->x, pr->y, ld, perm, scl, pr->X, pr->ldx, o.want_negative}, cols_blocks(nn, nn));
+        as.add({nn, pr->x, pr->y, ld, perm, scl, pr->X, pr->ldx, o.want_negative, nullptr},
+               cols_blocks(nn, nn));
       }
       BSE_TRY(run_gemm<double>(ar, g00, s));
+      BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
       BSE_TRY(run_op(ar, rq, group_refine, G_RQ, 0, s));
+      {
+        // a pair that broke down in the refinement fails the problem (it is then re-solved in FP64)
+        std::vector<double> bad(batch, 0.0);
+        BSE_TRY(hipMemcpyAsync(bad.data(), d_corr, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+        BSE_TRY(hipStreamSynchronize(s));
+        for (Prob* pr : ok)
+          if (bad[pr->idx] != 0.0) pr->rcorr = __builtin_inf();
+      }
       BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
       BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
       BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
       tm.mark();
     } else {
+      // Alg. 3 steps 4-6 as in the single solve: Ws, V2 = L2 Ws, T = L1^H V2
+      // (Rayleigh quotients), V1 = L2^-H Ws by grouped block triangular
+      // solves, final setup.
       Grp<ColnormArgs<double2>> n1, n2, n3;
       Grp<ScaleArgs<double2>> sc;
       Grp<LambdaArgs> la;
       Grp<RankArgs> rk;
       Grp<WriteLambdaArgs> wl;
       Grp<AssembleArgs> as;
-      std::vector<GemmDesc> v2, t, v1;
+      Grp<TriInvArgs> ti;
+      std::vector<GemmDesc> v2, t;
+      std::vector<TrsmStep> steps;
       for (Prob* pr : ok) {
         const int np = pr->np;
         double2* M1 = pr->at<double2>(pr->p.off_m1);
         double2* M2 = pr->at<double2>(pr->p.off_m2);
         double2* W = pr->at<double2>(pr->p.off_w);
         double2* Y = pr->at<double2>(pr->p.off_y);
+        double2* T = pr->at<double2>(pr->p.off_t);
+        double2* inv = pr->at<double2>(pr->p.off_inv);
         double* sigma = pr->at<double>(pr->p.off_sigma);
         double* bnorm = pr->at<double>(pr->p.off_bnorm);
         double* anorm = pr->at<double>(pr->p.off_anorm);
@@ -717,15 +736,15 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         sc.add({pr->n, np, W, np, sigma}, cols_blocks(np, np));
         n2.add({W, np, np, bnorm}, np);
         v2.push_back(tri_gemm(np, np, M2, 0, W, 0, 0, Y));  // V2 = L2 Ws
-        t.push_back(tri_gemm(np, np, M1, 1, Y, 0, 0, W));   // T = L1^H V2
-        n3.add({W, np, np, anorm}, np);
-        la.add({pr->n, np, anorm, bnorm, lamu, invlam, scl}, (np + 255) / 256);
+        t.push_back(tri_gemm(np, np, M1, 1, Y, 0, 0, T));   // T = L1^H V2
+        n3.add({T, np, np, anorm}, np);
+        la.add({pr->n, np, anorm, bnorm, lamu, invlam, scl, 1}, (np + 255) / 256);
         rk.add({pr->n, lamu, perm, 0}, (pr->n + 255) / 256);
         wl.add({pr->n, lamu, perm, pr->lambda, o.want_negative}, (pr->n + 255) / 256);
-        GemmDesc v = tri_gemm(np, np, M1, 0, W, 0, 0, M2);  // V1 = L1 T Lambda^-1
-        v.colscale = invlam;
-        v1.push_back(v);
-        as.add({pr->n, M2, Y, np, perm, scl, pr->X, pr->ldx, o.want_negative}, cols_blocks(pr->n, pr->n));
+        ti.add({M2, np, inv}, np / 64);
+        trsm_lh_for_each(np, M2, np, W, T, inv, [&](const TrsmStep& st) { steps.push_back(st); });  // V1 = L2^-H Ws -> T
+        as.add({pr->n, T, Y, np, perm, nullptr, pr->X, pr->ldx, o.want_negative, scl},
+               cols_blocks(pr->n, pr->n));
       }
       BSE_TRY(run_op(ar, n1, group_finalize, G_COLNORM_Z, 0, s));
       BSE_TRY(run_op(ar, sc, group_finalize, G_SCALE_Z, 0, s));
@@ -737,7 +756,19 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       BSE_TRY(run_op(ar, la, group_finalize, G_LAMBDA, 0, s));
       BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
       BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
-      BSE_TRY(run_gemm<double>(ar, v1, s));
+      BSE_TRY(run_op(ar, ti, group_chol, G_TRIINV, 0, s));
+      // every problem's solve steps in its own order; one grouped launch per (group, slot)
+      std::stable_sort(steps.begin(), steps.end(), [](const TrsmStep& a, const TrsmStep& b) {
+        return a.group != b.group ? a.group < b.group : a.slot < b.slot;
+      });
+      for (size_t i = 0; i < steps.size();) {
+        size_t j = i;
+        std::vector<GemmDesc> launch;
+        while (j < steps.size() && steps[j].group == steps[i].group && steps[j].slot == steps[i].slot)
+          launch.push_back(steps[j++].g);
+        BSE_TRY(run_gemm<double>(ar, launch, s));
+        i = j;
+      }
       BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
       tm.mark();
     }
@@ -752,6 +783,21 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     const JacState& js = states[pr.idx];
     if (st == 0 && !js.converged) st = 2 * pr.n + 1;
     if (st == 0 && mixed && !(pr.rcorr <= 1.0e-4)) st = 2 * pr.n + 2;
+    if (st != 0 && mixed) {
+      // the complex64 stage could not carry this problem: re-solve it in FP64
+      // on its own workspace region, as the single solve does
+      bse_info_t tmp;
+      memset(&tmp, 0, sizeof(tmp));
+      st = solve_fp64_fallback(pr.n, pr.A, (int)pr.lda, pr.B, (int)pr.ldb, pr.lambda, pr.X,
+                               (int)pr.ldx, pr.base, pr.p, o, &tmp, s);
+      if (st <= kErrHip) return st;
+      status[pr.idx] = st;
+      if (info) {
+        tmp.timing = info[pr.idx].timing;
+        info[pr.idx] = tmp;
+      }
+      continue;
+    }
     status[pr.idx] = st;
     if (info) {
       bse_info_t* inf = &info[pr.idx];
@@ -765,8 +811,22 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       inf->inner_rotations = js.inner_rotations;
       inf->refine_delta = pr.rcorr;
       inf->refine_steps_done = pr.rsteps;
+      for (int k = 0; k < 8; ++k) inf->refine_corr[k] = pr.rhist[k];
     }
   }
+  if (o.checks)
+    for (const Prob& pr : probs) {
+      if (status[pr.idx] != 0) continue;
+      bse_info_t tmp;
+      memset(&tmp, 0, sizeof(tmp));
+      if (int e = run_checks(pr.n, pr.A, (int)pr.lda, pr.B, (int)pr.ldb, pr.lambda, pr.X, (int)pr.ldx,
+                             pr.base, pr.p, o, &tmp, s))
+        return e;
+      if (info) {
+        info[pr.idx].sigma_orth_fro = tmp.sigma_orth_fro;
+        info[pr.idx].max_rel_resid = tmp.max_rel_resid;
+      }
+    }
   for (int i = 0; i < batch; ++i)
     if (status[i] != 0) { first = status[i]; break; }
   if (info && want_timing) {

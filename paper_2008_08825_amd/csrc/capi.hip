@@ -9,8 +9,8 @@
 //   finalize  Ws = W_out diag(column norms)^-3/2 = V Lambda^-1/2
 //   back      V2 = L2 Ws = L2 V Lambda^-1/2          (step 5)
 //             T = L1^H V2; lambda_k = ||T_k|| / ||Ws_k|| (Rayleigh quotient)
-//             V1 = L1 T Lambda^-1 = M1 V2 Lambda^-1 = L1 U Lambda^-1/2
-//                                                    (step 4 via Lemma SVDScalarFactors)
+//             V1 = L2^-H Ws sigma = L1 U Lambda^-1/2 (step 4: L1 U = L2^-H W_out,
+//                                                    one block triangular solve)
 //   assemble  X = [(V1 + V2)/2; (V2 - V1)/2], ascending lambda (step 6)
 // Mixed form: the same steps with complex64 data on FP32 MFMA (Cholesky
 // diagonal blocks factored in FP64), then (V1, V2) widened to FP64 and
@@ -44,6 +44,7 @@ void fill_info(bse_info_t* info, int ret, const JacobiResult& jr) {
   }
 }
 
+
 // Shared front end: form M1, M2 (lower, FP64) into the plan's M1/M2 regions.
 int form_and_check_args(int n, const void* A, int lda, const void* B, int ldb, int upper, char* base,
                         const Plan& p, hipStream_t s) {
@@ -69,6 +70,32 @@ int read_status(int* status, int n, bse_info_t* info, hipStream_t s) {
   return 0;
 }
 
+// Alg. 3 steps 4-6 from the orthogonalised columns Z = W_out (in Zb, FP64):
+//   Zb <- Ws = Z sigma^-3/2, Y <- V2 = L2 Ws, T <- L1^H V2 (Rayleigh
+//   quotients, sort), T <- V1 = L2^-H Ws (Zb is overwritten by the solve),
+//   X <- final setup with V1 scaled by 1 / ||Ws_k||^2.
+// L1 and L2 are read only.
+int back_transform_z(int n, int np, const double2* L1, const double2* L2, double2* Zb, double2* Y,
+                     double2* T, double2* inv, char* base, const Plan& p, double* lambda, void* X,
+                     int ldx, int want_negative, hipStream_t s) {
+  const long ld = np;
+  double* sigma = reinterpret_cast<double*>(base + p.off_sigma);
+  int* perm = reinterpret_cast<int*>(base + p.off_perm);
+  double* invlam = reinterpret_cast<double*>(base + p.off_invlam);
+  double* bnorm = reinterpret_cast<double*>(base + p.off_bnorm);
+  double* anorm = reinterpret_cast<double*>(base + p.off_anorm);
+  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
+  double* scl = reinterpret_cast<double*>(base + p.off_scl);
+  BSE_TRY(scale_singular_cols_z(n, np, Zb, ld, sigma, bnorm, s));  // Ws = Z sigma^-3/2
+  BSE_TRY(gemm_z(tri_gemm(np, ld, L2, 0, Zb, 0, 0, Y), s));       // V2 = L2 Ws
+  BSE_TRY(gemm_z(tri_gemm(np, ld, L1, 1, Y, 0, 0, T), s));        // T = L1^H V2
+  BSE_TRY(rq_lambda_z(n, np, T, ld, bnorm, anorm, lamu, invlam, scl, perm, lambda, want_negative, s));
+  BSE_TRY(trsm_lh_z(np, L2, ld, Zb, T, inv, s));                    // V1 = L2^-H Ws (unscaled)
+  BSE_TRY(assemble_z(n, T, Y, ld, perm, nullptr, static_cast<double2*>(X), ldx, want_negative, s,
+                     scl));
+  return 0;
+}
+
 int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
                int ldx, char* base, const Plan& p, const bse_opts_t& o, bse_info_t* info,
                int want_timing, hipStream_t s) {
@@ -78,29 +105,24 @@ int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* la
   double2* M2 = reinterpret_cast<double2*>(base + p.off_m2);
   double2* W = reinterpret_cast<double2*>(base + p.off_w);
   double2* Y = reinterpret_cast<double2*>(base + p.off_y);
+  double2* T = reinterpret_cast<double2*>(base + p.off_t);
+  double2* inv = reinterpret_cast<double2*>(base + p.off_inv);
   double2* linv = reinterpret_cast<double2*>(base + p.off_linv);
-  double* sigma = reinterpret_cast<double*>(base + p.off_sigma);
-  int* perm = reinterpret_cast<int*>(base + p.off_perm);
-  double* invlam = reinterpret_cast<double*>(base + p.off_invlam);
-  double* bnorm = reinterpret_cast<double*>(base + p.off_bnorm);
-  double* anorm = reinterpret_cast<double*>(base + p.off_anorm);
-  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
-  double* scl = reinterpret_cast<double*>(base + p.off_scl);
   int* status = reinterpret_cast<int*>(base + p.off_status);
   JacobiWork jw;
   jacobi_carve(np, sizeof(double), base + p.off_jac, jw, p.kc, p.rrows);
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
-  const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (double)(n > 64 ? n : 64) * 2.220446049250313e-16;
+  const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : default_tol64(n);
 
   Timer tm(want_timing != 0, s);
-  const int slots[8] = {0, 1, 2, 3, 4, 5, -1, -1};
+  const int slots[8] = {0, 1, 2, 3, 5, -1, -1, -1};
   tm.mark();
   const int big = 0x7fffffff;
   BSE_TRY(hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, s));
   if (int e = form_and_check_args(n, A, lda, B, ldb, upper, base, p, s)) return e;
   tm.mark();
-  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, linv, status, s));
+  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, linv, status, s, p.side));
   if (int st = read_status(status, n, info, s)) return st;
   tm.mark();
   {
@@ -112,18 +134,9 @@ int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* la
   JacobiResult jr;
   BSE_TRY(jacobi_z(np, W, ld, jw, tol, max_sweeps, jr, s, kernel_time_stride(want_timing)));
   tm.mark();
-  BSE_TRY(scale_singular_cols_z(n, np, W, ld, sigma, bnorm, s));  // Ws = W sigma^-3/2
-  tm.mark();
-  BSE_TRY(gemm_z(tri_gemm(np, ld, M2, 0, W, 0, 0, Y), s));        // V2 = L2 Ws
-  BSE_TRY(gemm_z(tri_gemm(np, ld, M1, 1, Y, 0, 0, W), s));        // T = L1^H V2
-  BSE_TRY(rq_lambda_z(n, np, W, ld, bnorm, anorm, lamu, invlam, scl, perm, lambda,
-                      o.want_negative, s));
-  {
-    GemmDesc v = tri_gemm(np, ld, M1, 0, W, 0, 0, M2);            // V1 = L1 T Lambda^-1
-    v.colscale = invlam;
-    BSE_TRY(gemm_z(v, s));
-  }
-  BSE_TRY(assemble_z(n, M2, Y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
+  if (int e = back_transform_z(n, np, M1, M2, W, Y, T, inv, base, p, lambda, X, ldx,
+                               o.want_negative, s))
+    return e;
   tm.mark();
   BSE_TRY(hipStreamSynchronize(s));
   const int ret = jr.converged ? 0 : 2 * n + 1;
@@ -158,7 +171,7 @@ int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* la
   jacobi_carve(np, sizeof(double), base + p.off_jac, jw, p.kc, p.rrows);
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
-  const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (double)(n > 64 ? n : 64) * 2.220446049250313e-16;
+  const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : default_tol64(n);
 
   Timer tm(want_timing != 0, s);
   const int slots[8] = {0, 1, 2, 3, 4, 5, -1, -1};
@@ -170,7 +183,7 @@ int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* la
   BSE_TRY(hipMemcpyAsync(Z, M1, (size_t)np * np * sizeof(double2), hipMemcpyDeviceToDevice, s));
   BSE_TRY(mirror_upper_z(np, M1, ld, s));
   tm.mark();
-  BSE_TRY(cholesky_pair_z(np, n, Z, M2, ld, linv, status, s));
+  BSE_TRY(cholesky_pair_z(np, n, Z, M2, ld, linv, status, s, p.side));
   if (int st = read_status(status, n, info, s)) return st;
   tm.mark();
   {
@@ -203,6 +216,38 @@ int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* la
   tm.fill(info, slots);
   return ret;
 }
+
+// The mixed form re-solves in FP64 when its complex64 stage cannot carry the
+// problem (a complex64 Cholesky factor fails, or the FP64 refinement does not
+// reach its tolerance from the complex64 pairs), as mixed-precision
+// iterative-refinement solvers fall back to the working precision when the
+// refinement does not converge.  The FP64 plan fits in the mixed plan's
+// workspace (5 against 10 n x n buffers).
+}  // namespace
+
+namespace bse {
+int solve_fp64_fallback(int n, const void* A, int lda, const void* B, int ldb, double* lambda,
+                        void* X, int ldx, char* base, const Plan& p, const bse_opts_t& o,
+                        bse_info_t* info, hipStream_t s) {
+  bse_opts_t o64 = o;
+  o64.precision = BSE_PREC_FP64;
+  o64.jacobi_tol = 0.0;
+  o64.max_sweeps = 0;
+  Plan p64 = make_plan(n, o64);
+  p64.side = p.side;
+  if (p64.total > p.total) return 2 * n + 2;
+  const int timing = info ? info->timing : 0;
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->timing = timing;
+  }
+  const int ret = solve_fp64(n, A, lda, B, ldb, lambda, X, ldx, base, p64, o64, info, timing, s);
+  if (info) info->fallback = 2;
+  return ret;
+}
+}  // namespace bse
+
+namespace {
 
 int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
                 int ldx, char* base, const Plan& p, const bse_opts_t& o, bse_info_t* info,
@@ -255,8 +300,15 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   BSE_TRY(mirror_upper_z(np, M1, ld, s));  // full Hermitian FP64 M1, M2 for the refinement
   BSE_TRY(mirror_upper_z(np, M2, ld, s));
   tm.mark();
-  BSE_TRY(cholesky_pair_c(np, n, L1c, L2c, ld, linv, status, s));
-  if (int st = read_status(status, n, info, s)) return st;
+  BSE_TRY(cholesky_pair_c(np, n, L1c, L2c, ld, linv, status, s, p.side));
+  {
+    int st = 0;
+    BSE_TRY(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+    BSE_TRY(hipStreamSynchronize(s));
+    // A complex64 factor failed: kappa(A +- B) eps32 is near 1 (or the input
+    // is not definite, which the FP64 factorisation then reports).
+    if (st != big) return solve_fp64_fallback(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, s);
+  }
   tm.mark();
   {
     GemmDesc g = tri_gemm(np, ld, L2c, 1, L1c, 0, 1, Wc);  // W = L2^H L1 (complex64)
@@ -285,7 +337,8 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   double2* y = X2;
   double maxcorr = 0.0;
   int steps_done = 0;
-  BSE_TRY(refine_z(n, ld, M1, M2, &x, &y, rw, steps, 1.0e-6, lamu, scl, &maxcorr, &steps_done, s));
+  double hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  BSE_TRY(refine_z(n, ld, M1, M2, &x, &y, rw, steps, 1.0e-6, lamu, scl, &maxcorr, &steps_done, s, hist));
   BSE_TRY(sort_lambda(n, lamu, perm, lambda, o.want_negative, s));
   BSE_TRY(assemble_z(n, x, y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
   tm.mark();
@@ -293,10 +346,12 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   int ret = jr.converged ? 0 : 2 * n + 1;
   // a last correction above 1e-4 leaves errors above 1e-8 in the vectors
   if (ret == 0 && !(maxcorr <= 1.0e-4)) ret = 2 * n + 2;
+  if (ret != 0) return solve_fp64_fallback(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, s);
   fill_info(info, ret, jr);
   if (info) {
     info->refine_delta = maxcorr;
     info->refine_steps_done = steps_done;
+    for (int i = 0; i < 8; ++i) info->refine_corr[i] = hist[i];
   }
   tm.fill(info, slots);
   return ret;
@@ -329,23 +384,16 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   float2* Wc = reinterpret_cast<float2*>(base + p.off_x1);
   double2* inv = reinterpret_cast<double2*>(base + p.off_inv);
   double2* linv = reinterpret_cast<double2*>(base + p.off_linv);
-  double* sigma = reinterpret_cast<double*>(base + p.off_sigma);
-  int* perm = reinterpret_cast<int*>(base + p.off_perm);
-  double* invlam = reinterpret_cast<double*>(base + p.off_invlam);
-  double* bnorm = reinterpret_cast<double*>(base + p.off_bnorm);
-  double* anorm = reinterpret_cast<double*>(base + p.off_anorm);
-  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
-  double* scl = reinterpret_cast<double*>(base + p.off_scl);
   int* status = reinterpret_cast<int*>(base + p.off_status);
   JacobiWork jw32, jw64;
   jacobi_carve(np, sizeof(float), base + p.off_jac, jw32, p.kc, p.rrows);
   jacobi_carve(np, sizeof(double), base + p.off_jac, jw64, p.kc, p.rrows);
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const double nn = (double)(n > 64 ? n : 64);
-  const double eps32 = 1.1920928955078125e-07, eps64 = 2.220446049250313e-16;
+  const double eps32 = 1.1920928955078125e-07;
   const int max32 = o.max_sweeps > 0 ? o.max_sweeps : 20;
   const double tol32 = 4.0 * sqrt(nn) * eps32;
-  const double tol64 = o.jacobi_tol > 0.0 ? o.jacobi_tol : nn * eps64;
+  const double tol64 = o.jacobi_tol > 0.0 ? o.jacobi_tol : default_tol64(n);
 
   Timer tm(want_timing != 0, s);
   const int slots[8] = {0, 1, 2, 3, 6, 4, 5, -1};
@@ -354,7 +402,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   BSE_TRY(hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, s));
   if (int e = form_and_check_args(n, A, lda, B, ldb, upper, base, p, s)) return e;
   tm.mark();
-  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, linv, status, s));
+  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, linv, status, s, p.side));
   if (int st = read_status(status, n, info, s)) return st;
   tm.mark();
   {
@@ -385,28 +433,42 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   }
   BSE_TRY(tri_pad_z(n, np, X2, ld, 0, s));
   BSE_TRY(cholesky_z(np, n, X2, ld, linv, status, 0, s));  // G = L_G L_G^H
-  BSE_TRY(trsm_rh_z(np, X2, ld, Y, X1, inv, s));    // W V = Z L_G^-H -> X1 (Y is overwritten)
+  int gst = 0;
+  BSE_TRY(hipMemcpyAsync(&gst, status, sizeof(int), hipMemcpyDeviceToHost, s));
+  BSE_TRY(hipStreamSynchronize(s));
   JacobiResult j64;
-  const double first = fmin(kInnerStopCap, fmax(1.0e-10, fmin(j32.max_off, tol32)));
-  BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, kernel_time_stride(want_timing), first));
-  tm.mark();
-  BSE_TRY(scale_singular_cols_z(n, np, X1, ld, sigma, bnorm, s));  // Ws = (W V Q) sigma^-3/2
-  tm.mark();
-  BSE_TRY(gemm_z(tri_gemm(np, ld, M2, 0, X1, 0, 0, Y), s));       // V2 = L2 Ws
-  BSE_TRY(gemm_z(tri_gemm(np, ld, M1, 1, Y, 0, 0, W), s));        // T = L1^H V2
-  BSE_TRY(rq_lambda_z(n, np, W, ld, bnorm, anorm, lamu, invlam, scl, perm, lambda,
-                      o.want_negative, s));
-  {
-    GemmDesc v = tri_gemm(np, ld, M1, 0, W, 0, 0, M2);            // V1 = L1 T Lambda^-1
-    v.colscale = invlam;
-    BSE_TRY(gemm_z(v, s));
+  double2* Zb = X1;  // the columns the FP64 sweeps orthogonalise
+  int fallback = 0;
+  // BSE_TEST_POLISH_FALLBACK set: take the failure branch below (test hook)
+  if (getenv("BSE_TEST_POLISH_FALLBACK") != nullptr) gst = 1;
+  if (gst == big) {
+    BSE_TRY(trsm_rh_z(np, X2, ld, Y, X1, inv, s));  // W V = Z L_G^-H -> X1 (Y is overwritten)
+    const double first = fmin(kInnerStopCap, fmax(1.0e-10, fmin(j32.max_off, tol32)));
+    BSE_TRY(jacobi_z(np, X1, ld, jw64, tol64, 30, j64, s, kernel_time_stride(want_timing), first));
+  } else {
+    // V'^H V' is not numerically positive definite: the complex64 iteration
+    // lost the rotation (kappa(W) eps32 near 1).  The FP64 sweeps then run
+    // on W itself, as in the FP64 form.
+    fallback = 1;
+    BSE_TRY(hipMemcpyAsync(status, &big, sizeof(int), hipMemcpyHostToDevice, s));
+    GemmDesc g = tri_gemm(np, ld, M2, 1, M1, 0, 1, W);  // W = L2^H L1
+    g.mask = n;
+    BSE_TRY(gemm_z(g, s));
+    Zb = W;
+    BSE_TRY(jacobi_z(np, W, ld, jw64, tol64, 30, j64, s, kernel_time_stride(want_timing)));
   }
-  BSE_TRY(assemble_z(n, M2, Y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
+  tm.mark();
+  tm.mark();
+  // Alg. 3 steps 4-6; T and V1 in X2 (the factor of G is no longer needed)
+  if (int e = back_transform_z(n, np, M1, M2, Zb, Y, X2, inv, base, p, lambda, X, ldx,
+                               o.want_negative, s))
+    return e;
   tm.mark();
   BSE_TRY(hipStreamSynchronize(s));
   const int ret = (j32.sweeps > 0 && j64.converged) ? 0 : 2 * n + 1;
   fill_info(info, ret, j32);
   if (info) {
+    info->fallback = fallback;
     info->polish_sweeps = j64.sweeps;
     info->polish_rotations = j64.rotations;
     info->polish_pair_checks = j64.pair_checks;
@@ -423,6 +485,67 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
 }
 
 }  // namespace
+
+namespace bse {
+// opts.checks: measure the returned pairs (positive half) on the device.
+int run_checks(int n, const void* A, int lda, const void* B, int ldb, const double* lambda,
+               const void* X, int ldx, char* base, const Plan& p, const bse_opts_t& o,
+               bse_info_t* info, hipStream_t s) {
+  double2* bufs[5];
+  check_buffers(p, base, bufs);
+  double out[2] = {0.0, 0.0};
+  const int upper = (o.uplo == 'U' || o.uplo == 'u');
+  BSE_TRY(check_pairs_z(n, p.np, static_cast<const double2*>(A), lda, static_cast<const double2*>(B),
+                        ldb, upper, lambda, static_cast<const double2*>(X), ldx, bufs,
+                        reinterpret_cast<double*>(base + p.off_check), out, s));
+  if (info) {
+    info->sigma_orth_fro = out[0];
+    info->max_rel_resid = out[1];
+  }
+  return 0;
+}
+
+// bse_solve_h1 and its variant without allocation (noalloc != 0: the second
+// Cholesky factorisation on `stream` too, no timing events).
+int solve_h1_impl(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
+                  int ldx, void* work, size_t work_bytes, const bse_opts_t* opts, bse_info_t* info,
+                  void* stream, int noalloc) {
+  bse_opts_t o;
+  bse_default_opts(&o);
+  if (opts) o = *opts;
+  const int want_timing = info && !noalloc ? info->timing : 0;
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->timing = want_timing;
+  }
+  if (n < 0 || n > 46000) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (n > 0 && !B) return -4;
+  if (ldb < (n > 1 ? n : 1)) return -5;
+  if (n > 0 && !lambda) return -6;
+  if (n > 0 && !X) return -7;
+  if (ldx < (2 * n > 1 ? 2 * n : 1)) return -8;
+  if (!opts_valid(o)) return -11;
+  if (n == 0) return 0;
+  Plan p = make_plan(n, o);
+  if (noalloc) p.side = 0;
+  if (!work) return -9;
+  if (work_bytes < p.total) return -10;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
+  int ret;
+  if (p.alg2) ret = solve_alg2(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  else if (p.mixed) ret = solve_mixed(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  else if (p.polish) ret = solve_polish(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  else ret = solve_fp64(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  if (ret == 0 && o.checks) {
+    if (int e = run_checks(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, s)) return e;
+  }
+  return ret;
+}
+
+}  // namespace bse
 
 extern "C" {
 
@@ -445,33 +568,7 @@ size_t bse_workspace_bytes(int n, const bse_opts_t* opts) {
 int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
                  int ldx, void* work, size_t work_bytes, const bse_opts_t* opts, bse_info_t* info,
                  void* stream) {
-  bse_opts_t o;
-  bse_default_opts(&o);
-  if (opts) o = *opts;
-  const int want_timing = info ? info->timing : 0;
-  if (info) {
-    memset(info, 0, sizeof(*info));
-    info->timing = want_timing;
-  }
-  if (n < 0 || n > 46000) return -1;
-  if (n > 0 && !A) return -2;
-  if (lda < (n > 1 ? n : 1)) return -3;
-  if (n > 0 && !B) return -4;
-  if (ldb < (n > 1 ? n : 1)) return -5;
-  if (n > 0 && !lambda) return -6;
-  if (n > 0 && !X) return -7;
-  if (ldx < (2 * n > 1 ? 2 * n : 1)) return -8;
-  if (!opts_valid(o)) return -11;
-  if (n == 0) return 0;
-  const Plan p = make_plan(n, o);
-  if (!work) return -9;
-  if (work_bytes < p.total) return -10;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
-  if (p.alg2) return solve_alg2(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
-  if (p.mixed) return solve_mixed(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
-  if (p.polish) return solve_polish(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
-  return solve_fp64(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  return bse::solve_h1_impl(n, A, lda, B, ldb, lambda, X, ldx, work, work_bytes, opts, info, stream, 0);
 }
 
 size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* opts) {

@@ -207,26 +207,29 @@ BSE_DEV void Potf2Op<C2>::run(const Potf2Args<C2>& a, int, int j0) {
 
 // Inverses of the 64 x 64 diagonal blocks of a lower-triangular L (one
 // workgroup per block), written as lower triangles, block b at inv + b * 64 * 64.
-__global__ __launch_bounds__(256) void k_tri_inv_blocks(const double2* __restrict__ L, long ld,
-                                                        double2* __restrict__ inv) {
-  __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
-  __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
-  const int tid = threadIdx.x;
-  const int j0 = blockIdx.x * NB;
-  const double2* D = L + j0 + (long)j0 * ld;
-  for (int q = 0; q < 16; ++q) {
-    const int r = tid & 63, c = (tid >> 6) + 4 * q;
-    const double2 v = (r >= c) ? D[r + (long)c * ld] : make_double2(0.0, 0.0);
-    Lr[r][c] = v.x; Li[r][c] = v.y;
+struct TriInvOp {
+  static constexpr int NT = 256;
+  typedef TriInvArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int aux) {
+    __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
+    __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
+    const int tid = threadIdx.x;
+    const int j0 = bx * NB;
+    const double2* D = a.L + j0 + (long)j0 * a.ld;
+    for (int q = 0; q < 16; ++q) {
+      const int r = tid & 63, c = (tid >> 6) + 4 * q;
+      const double2 v = (r >= c) ? D[r + (long)c * a.ld] : make_double2(0.0, 0.0);
+      Lr[r][c] = v.x; Li[r][c] = v.y;
+    }
+    __syncthreads();
+    tri_inverse_lds(Lr, Li, Xr, Xi, tid);
+    double2* out = a.inv + (long)bx * NB * NB;
+    for (int q = 0; q < 16; ++q) {
+      const int r = tid & 63, c = (tid >> 6) + 4 * q;
+      out[r + c * NB] = make_double2(Xr[r][c], Xi[r][c]);
+    }
   }
-  __syncthreads();
-  tri_inverse_lds(Lr, Li, Xr, Xi, tid);
-  double2* out = inv + (long)blockIdx.x * NB * NB;
-  for (int q = 0; q < 16; ++q) {
-    const int r = tid & 63, c = (tid >> 6) + 4 * q;
-    out[r + c * NB] = make_double2(Xr[r][c], Xi[r][c]);
-  }
-}
+};
 
 // Upper triangle of a square np x np matrix from its lower one: M[i][j] = conj(M[j][i]), i < j.
 struct MirrorOp {
@@ -403,7 +406,6 @@ hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, in
 // inverse; after the group the rest of the right-hand side is updated with
 // all of its blocks at once (K = 64 kTrsmGroup), so the remaining rows pass
 // through the update kTrsmGroup times less often than with one block at a time.
-constexpr int kTrsmGroup = 4;
 
 // Z_i = op(L_ii^-1) Rhs_i for one 64-row block (left-side solves)
 static hipError_t trsm_diag(const double2* inv_i, int opA, int np, double2* Rhs_i, double2* Z_i,
@@ -432,33 +434,20 @@ static hipError_t trsm_update(int rows, int np, int k, const double2* A, long ld
 hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s) {
   const int nb = np / NB;
-  k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
-  hipError_t e = hipGetLastError();
+  const TriInvArgs ti = {L, ld, inv};
+  hipError_t e = launch_one<TriInvOp>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
-  // back substitution with L^H: block rows i, i - 1, ... ; (L^H)_{r, c} = conj(L_{c, r})
-  for (int i = nb - 1; i >= 0; i -= kTrsmGroup) {
-    const int lo = i - kTrsmGroup + 1 > 0 ? i - kTrsmGroup + 1 : 0;  // first block row of the group
-    for (int b = i; b >= lo; --b) {
-      const long rb = (long)b * NB;
-      if (b < i) {
-        // Rhs_b -= (L^H)_{b, b+1..i} Z_{b+1..i}
-        const long r1 = rb + NB;
-        if ((e = trsm_update(NB, np, (i - b) * NB, L + r1 + rb * ld, ld, 1, Z + r1, ld, Rhs + rb, ld, s)) != hipSuccess) return e;
-      }
-      if ((e = trsm_diag(inv + rb * NB, 1, np, Rhs + rb, Z + rb, ld, s)) != hipSuccess) return e;
-    }
-    // Rhs_{0..lo-1} -= (L^H)_{0..lo-1, lo..i} Z_{lo..i}
-    const long rl = (long)lo * NB;
-    if ((e = trsm_update(lo * NB, np, (i - lo + 1) * NB, L + rl, ld, 1, Z + rl, ld, Rhs, ld, s)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  trsm_lh_for_each(np, L, ld, Rhs, Z, inv, [&](const TrsmStep& st) {
+    if (e == hipSuccess) e = gemm_z(st.g, s);
+  });
+  return e;
 }
 
 hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s) {
   const int nb = np / NB;
-  k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
-  hipError_t e = hipGetLastError();
+  const TriInvArgs ti = {L, ld, inv};
+  hipError_t e = launch_one<TriInvOp>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
   for (int i = 0; i < nb; i += kTrsmGroup) {
     const int hi = i + kTrsmGroup - 1 < nb ? i + kTrsmGroup - 1 : nb - 1;  // last block row of the group
@@ -479,8 +468,8 @@ hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
 hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s) {
   const int nb = np / NB;
-  k_tri_inv_blocks<<<nb, 256, 0, s>>>(L, ld, inv);
-  hipError_t e = hipGetLastError();
+  const TriInvArgs ti = {L, ld, inv};
+  hipError_t e = launch_one<TriInvOp>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
   // Z_j = Rhs_j (L_jj^-1)^H   (column block j)
   auto diag = [&](int j) {
@@ -536,11 +525,11 @@ SideStream g_side[kMaxDevices];
 
 template <typename C2>
 static hipError_t cholesky_pair_run(int np, int n_real, C2* M1, C2* M2, long ld, C2* linv,
-                                    int* status, hipStream_t s) {
+                                    int* status, hipStream_t s, int side) {
   int dev = 0;  // the device of the caller's stream (the current device for the null stream)
   hipError_t e = hipStreamGetDevice(s, &dev);
   if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= kMaxDevices) {
+  if (!side || dev < 0 || dev >= kMaxDevices) {
     if ((e = cholesky_run<C2>(np, n_real, M1, ld, linv, status, 0, s)) != hipSuccess) return e;
     return cholesky_run<C2>(np, n_real, M2, ld, linv + NB * NB, status, n_real, s);
   }
@@ -571,13 +560,13 @@ static hipError_t cholesky_pair_run(int np, int n_real, C2* M1, C2* M2, long ld,
 }
 
 hipError_t cholesky_pair_z(int np, int n_real, double2* M1, double2* M2, long ld, double2* linv,
-                           int* status, hipStream_t s) {
-  return cholesky_pair_run<double2>(np, n_real, M1, M2, ld, linv, status, s);
+                           int* status, hipStream_t s, int side) {
+  return cholesky_pair_run<double2>(np, n_real, M1, M2, ld, linv, status, s, side);
 }
 
 hipError_t cholesky_pair_c(int np, int n_real, float2* M1, float2* M2, long ld, float2* linv,
-                           int* status, hipStream_t s) {
-  return cholesky_pair_run<float2>(np, n_real, M1, M2, ld, linv, status, s);
+                           int* status, hipStream_t s, int side) {
+  return cholesky_pair_run<float2>(np, n_real, M1, M2, ld, linv, status, s, side);
 }
 
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux,
@@ -588,6 +577,7 @@ hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks
     case G_TOC64: return launch_grp<ToC64Op>(table, map, blocks, aux, s);
     case G_POTF2_Z: return launch_grp<Potf2Op<double2>>(table, map, blocks, aux, s);
     case G_POTF2_C: return launch_grp<Potf2Op<float2>>(table, map, blocks, aux, s);
+    case G_TRIINV: return launch_grp<TriInvOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }

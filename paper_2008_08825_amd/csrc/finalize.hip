@@ -1,21 +1,31 @@
 // Finalisation of the SVD route and the final setup of Alg. 3.
 //
-// After the Jacobi iteration W_out = L2^H L1 U (U the accumulated rotations)
-// has orthogonal columns w_k = sigma_k v_k (paper notation of Lemma
-// SVDScalarFactors, where L1^H L2 = U Lambda V^H, so W = V Lambda U^H).
-//   Ws = W_out diag(sigma)^-3/2      so that V2 = L2 Ws = L2 V Lambda^-1/2,
-//   T  = L1^H V2                     (= U Lambda^1/2 in exact arithmetic),
-//   V1 = L1 T Lambda^-1              (= M1 V2 Lambda^-1, the Lemma's relation).
+// After the Jacobi iteration Z = W_out = L2^H L1 J (J the product of the
+// rotations, unitary) has orthogonal columns z_k = sigma_k v_k (paper notation
+// of Lemma SVDScalarFactors, where L1^H L2 = U Lambda V^H, so W = V Lambda U^H
+// and U = J).  Alg. 3 step 4 takes V1 = L1 U Lambda^-1/2 and V2 = L2 V
+// Lambda^-1/2.  Since L1 U = L1 J = L2^-H Z, the first needs no accumulated
+// rotations:
+//   Ws = Z diag(sigma)^-3/2          so that V2 = L2 Ws = L2 V Lambda^-1/2,
+//   V1 = L2^-H Ws diag(sigma)        (= L2^-H Z Lambda^-1/2 = L1 U Lambda^-1/2),
+// one block triangular solve with L2^H.  The solve is backward stable, so V1
+// carries the error of Z and not that error times ||H|| / lambda_k, as the
+// Lemma's other relation V1 = M1 V2 Lambda^-1 would.  The scale of V1_k is
+// 1 / ||Ws_k||^2 (= sigma_k for the computed Ws_k), which makes V1_k^H V2_k = 1.
 // Eigenvalues: y = V2_k is an eigenvector of the Hermitian-definite pencil
 // (M1, M2^-1) with eigenvalue lambda_k^2, so its Rayleigh quotient
-//   lambda_k^2 = (y^H M1 y) / (y^H M2^-1 y) = ||T_k||^2 / ||Ws_k||^2
+//   lambda_k^2 = (y^H M1 y) / (y^H M2^-1 y) = ||T_k||^2 / ||Ws_k||^2,  T = L1^H V2,
 // is accurate to second order in the error of y; it replaces the column norm
 // sigma_k, whose error grows with the number of rotations a column went
-// through.  Each pair (V1_k, V2_k) is scaled by s_k = (||T_k|| ||Ws_k||)^-1/2
-// so that V1_k^H V2_k = 1 exactly as in the Lemma.  The eigenvalues are
-// sorted ascending (stable by index) and the final setup (Alg. 3 step 6)
-// writes X = [(V1 + V2)/2; (V2 - V1)/2] in that order; the negative half is
-// [0 I; I 0] X with eigenvalues -lambda (Lemma ComputeNegEvecs).
+// through.  The eigenvalues are sorted ascending (stable by index) and the
+// final setup (Alg. 3 step 6) writes X = [(V1 + V2)/2; (V2 - V1)/2] in that
+// order; the negative half is [0 I; I 0] X with eigenvalues -lambda (Lemma
+// ComputeNegEvecs).
+//
+// The complex64 stage of the mixed form still forms V1 = L1 T Lambda^-1 (the
+// Lemma's relation M1 V2 = V1 Lambda); the FP64 refinement that follows it
+// corrects the pair, and its scale s_k = (||T_k|| ||Ws_k||)^-1/2 applies to both
+// halves.
 #include "common.hpp"
 #include "internal.hpp"
 
@@ -119,7 +129,7 @@ struct LambdaOp {
       const double l = x / y;
       a.lam[k] = l;
       a.invlam[k] = 1.0 / l;
-      a.scl[k] = 1.0 / sqrt(x * y);
+      a.scl[k] = a.v1scale ? 1.0 / (y * y) : 1.0 / sqrt(x * y);
     } else {
       a.lam[k] = 0.0;
       a.invlam[k] = 0.0;
@@ -173,7 +183,8 @@ __global__ __launch_bounds__(256) void k_alg2_scales(int n, const double* __rest
   fx[r] = sqrt(lk) / dk;          // column of V_M Lambda^1/2
 }
 
-// X[:, r] = s_k [(V1_k + V2_k)/2; (V2_k - V1_k)/2], k = perm[r]; work group = (column r, 256 rows).
+// X[:, r] = s_k [(t_k V1_k + V2_k)/2; (V2_k - t_k V1_k)/2], k = perm[r];
+// work group = (column r, 256 rows).
 struct AssembleOp {
   static constexpr int NT = 256;
   typedef AssembleArgs Args;
@@ -186,7 +197,8 @@ struct AssembleOp {
     int k = a.perm ? a.perm[r] : r;
     if (k < 0 || k >= n) k = r;
     const double sc = a.scl ? 0.5 * a.scl[k] : 0.5;
-    const double2 x = a.V1[i + (long)k * a.ldv];
+    double2 x = a.V1[i + (long)k * a.ldv];
+    if (a.scl1) x = cscale(x, a.scl1[k]);
     const double2 y = a.V2[i + (long)k * a.ldv];
     const double2 top = cscale(cadd(x, y), sc);
     const double2 bot = cscale(csub(y, x), sc);
@@ -245,7 +257,7 @@ hipError_t c64_to_c128(int np, const float2* S, long lds, double2* D, long ldd,
 
 hipError_t lambda_from_norms(int n, int np, const double* anorm, const double* bnorm, double* lam,
                              double* invlam, double* scl, hipStream_t s) {
-  const LambdaArgs a = {n, np, anorm, bnorm, lam, invlam, scl};
+  const LambdaArgs a = {n, np, anorm, bnorm, lam, invlam, scl, 0};
   return launch_one<LambdaOp>(a, b256(np), 0, s);
 }
 
@@ -261,8 +273,9 @@ hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int 
 hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* bnorm, double* anorm,
                        double* lam, double* invlam, double* scl, int* perm, double* lambda,
                        int want_negative, hipStream_t s) {
+  const LambdaArgs la = {n, np, anorm, bnorm, lam, invlam, scl, 1};
   hipError_t e = colnorm_z(np, T, ld, anorm, s);
-  if (e == hipSuccess) e = lambda_from_norms(n, np, anorm, bnorm, lam, invlam, scl, s);
+  if (e == hipSuccess) e = launch_one<LambdaOp>(la, b256(np), 0, s);
   if (e == hipSuccess) e = sort_lambda(n, lam, perm, lambda, want_negative, s);
   return e;
 }
@@ -285,8 +298,9 @@ hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double*
 }
 
 hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
-                      const double* scl, double2* X, long ldx, int want_negative, hipStream_t s) {
-  const AssembleArgs a = {n, V1, V2, ldv, perm, scl, X, ldx, want_negative};
+                      const double* scl, double2* X, long ldx, int want_negative, hipStream_t s,
+                      const double* scl1) {
+  const AssembleArgs a = {n, V1, V2, ldv, perm, scl, X, ldx, want_negative, scl1};
   return launch_one<AssembleOp>(a, cols_blocks(n, n), 0, s);
 }
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 
+#include <vector>
+
 #include "common.hpp"
 
 namespace bse {
@@ -37,13 +39,14 @@ hipError_t gemm_c(const GemmDesc& d, hipStream_t s);  // complex64
 hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv,
                       int* status, int base, hipStream_t s);
 // Both factors of Alg. 3 steps 1-2, M1 (status base 0) and M2 (base n_real):
-// M2's factorisation runs on a library stream beside s, ordered after the
-// work already on s, and s waits for it at the end.  linv holds two 64 x 64
-// inverses (one per factor).
+// with side != 0, M2's factorisation runs on a library stream beside s
+// (created once per device), ordered after the work already on s, and s waits
+// for it at the end; side == 0 runs both on s, one after the other.  linv
+// holds two 64 x 64 inverses (one per factor).
 hipError_t cholesky_pair_z(int np, int n_real, double2* M1, double2* M2, long ld, double2* linv,
-                           int* status, hipStream_t s);
+                           int* status, hipStream_t s, int side = 1);
 hipError_t cholesky_pair_c(int np, int n_real, float2* M1, float2* M2, long ld, float2* linv,
-                           int* status, hipStream_t s);
+                           int* status, hipStream_t s, int side = 1);
 
 // M1 = A + B, M2 = A - B (lower triangles, zero strict upper part), padded to
 // np with identity; reads the `upper` or lower triangle of A, B.
@@ -134,6 +137,52 @@ hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int*
 // np * 64 complex values) and MFMA GEMM updates; Rhs is overwritten.
 hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s);
+// The block triangular solves take the 64-column diagonal blocks this many at a time.
+constexpr int kTrsmGroup = 4;
+// The GEMM steps of trsm_lh_z in their order (after the diagonal-block
+// inverses), handed to `emit`: step `slot` (0 .. 2 kTrsmGroup - 1) of group `group` of
+// kTrsmGroup block rows counted from the bottom.  Problems of different
+// orders share (group, slot) numbers, so a batch can run every problem's step
+// of one (group, slot) in one grouped launch, in the same order as a single
+// solve.
+struct TrsmStep { int group, slot; GemmDesc g; };
+template <class F>
+void trsm_lh_for_each(int np, const double2* L, long ld, double2* Rhs, double2* Z,
+                      const double2* inv, F&& emit) {
+  constexpr int B = 64;
+  const int nb = np / B;
+  auto diag = [&](int b) {
+    const long rb = (long)b * B;
+    GemmDesc g;  // Z_b = (L_bb^-1)^H Rhs_b
+    g.M = B; g.N = np; g.K = B;
+    g.A = inv + rb * B; g.lda = B; g.opA = 1; g.triA = 1;
+    g.B = Rhs + rb; g.ldb = ld; g.opB = 0;
+    g.C = Z + rb; g.ldc = ld;
+    return g;
+  };
+  // Rhs[r0 .. r0 + rows) -= (L^H)[r0 .., c0 .. c0 + k) Z[c0 .. c0 + k); (L^H)_{r, c} = conj(L_{c, r})
+  auto update = [&](long r0, int rows, long c0, int k) {
+    GemmDesc u;
+    u.M = rows; u.N = np; u.K = k;
+    u.A = L + c0 + r0 * ld; u.lda = ld; u.opA = 1;
+    u.B = Z + c0; u.ldb = ld; u.opB = 0;
+    u.C = Rhs + r0; u.ldc = ld;
+    u.alpha_re = -1.0; u.beta_re = 1.0;
+    return u;
+  };
+  // back substitution with L^H: block rows i, i - 1, ...
+  int group = 0;
+  for (int i = nb - 1; i >= 0; i -= kTrsmGroup, ++group) {
+    const int lo = i - kTrsmGroup + 1 > 0 ? i - kTrsmGroup + 1 : 0;  // first block row of the group
+    for (int b = i; b >= lo; --b) {
+      const int j = i - b;
+      if (j > 0) emit(TrsmStep{group, 2 * j - 1, update((long)b * B, B, (long)(b + 1) * B, j * B)});
+      emit(TrsmStep{group, 2 * j, diag(b)});
+    }
+    // Rhs_{0..lo-1} -= (L^H)_{0..lo-1, lo..i} Z_{lo..i}
+    if (lo > 0) emit(TrsmStep{group, 2 * kTrsmGroup - 1, update(0, lo * B, (long)lo * B, (i - lo + 1) * B)});
+  }
+}
 // complex64 copy of all np x np entries.
 hipError_t z_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream_t s);
 // identity == 0: zero the strict upper triangle of M and give rows/columns
@@ -158,8 +207,9 @@ hipError_t scale_singular_cols_z(int n, int np, double2* W, long ld, double* sig
                                  double* bnorm, hipStream_t s);
 
 // Rayleigh-quotient eigenvalues lam_k = ||T_k|| / bnorm_k (unsorted), 1 / lam,
-// the Sigma-normalising scale s_k, the ascending order perm and the output
-// lambda (with -lambda appended if want_negative).
+// the scale of V1 = L2^-H Ws that makes V1_k^H V2_k = 1 (scl_k = 1 / bnorm_k^2),
+// the ascending order perm and the output lambda (with -lambda appended if
+// want_negative).
 hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* bnorm,
                        double* anorm, double* lam, double* invlam, double* scl, int* perm,
                        double* lambda, int want_negative, hipStream_t s);
@@ -183,7 +233,8 @@ hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int 
 // buffers), lam receives Rayleigh quotients and scl the Sigma-normalising
 // scales of the final pair.  Runs up to max_steps steps and stops after a
 // step whose largest off-diagonal correction is at most stop_corr; returns
-// that correction in *max_corr and the steps run in *steps_done.
+// that correction in *max_corr (+inf if a correction or a final Rayleigh
+// quotient broke down) and the steps run in *steps_done.
 // Pairs whose Ritz values differ by at most this fraction are corrected
 // within their span only (first-order rotation part dropped).
 constexpr double kRefineDelta = 1.0e-10;
@@ -191,9 +242,10 @@ struct RefineWork {
   double2 *Q = nullptr, *F = nullptr, *P1 = nullptr, *P2 = nullptr, *Ex = nullptr, *Ey = nullptr;
   double *ritz = nullptr, *dots = nullptr, *maxcorr = nullptr;
 };
+// corr_hist (host, optional): the largest correction of each step (first 8).
 hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** x, double2** y,
                     const RefineWork& w, int max_steps, double stop_corr, double* lam, double* scl,
-                    double* max_corr, int* steps_done, hipStream_t s);
+                    double* max_corr, int* steps_done, hipStream_t s, double* corr_hist = nullptr);
 
 // out[:, r] = W[:, perm r] * f_r (r < n; zero for r >= n; np rows).
 hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* perm,
@@ -204,10 +256,12 @@ hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* p
 hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double* lambda,
                          int want_negative, double* fx, double* fy, hipStream_t s);
 
-// X[:, r] = s_k [(V1_k + V2_k)/2; (V2_k - V1_k)/2] with k = perm[r] (and the
-// mirrored negative half); perm == nullptr means k = r, scl == nullptr s_k = 1.
+// X[:, r] = s_k [(t_k V1_k + V2_k)/2; (V2_k - t_k V1_k)/2] with k = perm[r]
+// (and the mirrored negative half); perm == nullptr means k = r, scl ==
+// nullptr s_k = 1, scl1 == nullptr t_k = 1 (else t_k = scl1[k]).
 hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
-                      const double* scl, double2* X, long ldx, int want_negative, hipStream_t s);
+                      const double* scl, double2* X, long ldx, int want_negative, hipStream_t s,
+                      const double* scl1 = nullptr);
 
 // Eigenvalue adjoint: G_A = sum_k w_k (a_k a_k^H + b_k b_k^H),
 // G_B = sum_k w_k (a_k b_k^H + b_k a_k^H) for X = [a; b] (2n x n, ldx), written
@@ -215,6 +269,15 @@ hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, con
 size_t adjoint_work_bytes(int n);
 hipError_t adjoint_z(int n, const double2* X, long ldx, const double* w, double2* gA, long ldga,
                      double2* gB, long ldgb, void* work, hipStream_t s);
+
+// Measurements of returned pairs (opts.checks): with bufs five np x np
+// complex128 scratch buffers and `small` check_small_bytes(n) bytes of device
+// memory, out[0] = ||X^H Sigma X - I||_F and out[1] = max_k ||H1 x_k -
+// lambda_k x_k|| / (lambda_max ||x_k||) (synchronises on s).
+size_t check_small_bytes(int n);
+hipError_t check_pairs_z(int n, int np, const double2* A, long lda, const double2* B, long ldb,
+                         int upper, const double* lambda, const double2* X, long ldx,
+                         double2* const bufs[5], double* small, double out[2], hipStream_t s);
 
 // ---------------------------------------------------------------- op arguments
 // Argument structs of the kernels (see the op launches in common.hpp); the
@@ -224,6 +287,7 @@ struct FormArgs {
   double2* M1; double2* M2; long ldm;
 };
 struct MirrorArgs { int np; double2* M; long ld; };
+struct TriInvArgs { const double2* L; long ld; double2* inv; };  // work group = diagonal block
 struct ToC64Args { int np; const double2* M; long ld; float2* Mc; };
 template <typename C2> struct Potf2Args {  // aux = first column of the panel
   C2* M; long ld; C2* linv; int* status; int base; int n_real;
@@ -259,24 +323,29 @@ template <typename C2> struct RotArgs {  // aux = round
 };
 template <typename C2> struct ColnormArgs { const C2* W; long ld; int np; double* out; };
 template <typename C2> struct ScaleArgs { int n, np; C2* W; long ld; const double* sigma; };
+// v1scale = 0: scl_k = (anorm_k bnorm_k)^-1/2 (both halves of the pair);
+// v1scale = 1: scl_k = 1 / bnorm_k^2 (the scale of V1 = L2^-H Ws alone).
 struct LambdaArgs {
   int n, np; const double* anorm; const double* bnorm; double* lam; double* invlam; double* scl;
+  int v1scale;
 };
 struct RankArgs { int n; const double* key; int* perm; int desc; };
 struct WriteLambdaArgs { int n; const double* lam; const int* perm; double* lambda; int want_negative; };
 struct C64Args { int np; const float2* S; long lds; double2* D; long ldd; const double* colscale; };
 struct AssembleArgs {
   int n; const double2* V1; const double2* V2; long ldv; const int* perm; const double* scl;
-  double2* X; long ldx; int want_negative;
+  double2* X; long ldx; int want_negative; const double* scl1;
 };
 struct RitzArgs { int n; const double2* F; const double2* P1; const double2* P2; long ld; double* ritz; };
 struct BuildArgs {
   int n; const double2* F; const double2* P1; const double2* P2; long ld; const double* ritz;
   double2* Ex; double2* Ey; double delta; double* maxcorr;
 };
+// bad (optional): set to 1 if a pair is not Sigma-positive or its quotient
+// is not finite and positive.
 struct RqArgs {
   int n; const double2* x; const double2* y; const double2* Qx; const double2* Qy; long ld;
-  double* lam; double* scl;
+  double* lam; double* scl; double* bad;
 };
 
 // Per-problem Jacobi state of a batch (device memory, 128 bytes).  The
@@ -316,7 +385,7 @@ RotArgs<float2> rot_args_c(int np, float2* W, long ld, const JacobiWork& w, cons
 // Grouped launches: table = device array of the op's Args, map = device
 // array of (table row, work group) pairs, blocks = entries of map used.
 enum GroupOp {
-  G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C,                      // chol.hip
+  G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C, G_TRIINV,            // chol.hip
   G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
   G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
   G_WRITE_LAMBDA, G_C64, G_ASSEMBLE,

@@ -17,7 +17,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 inline int pad64(int n) { return ((n + 63) / 64) * 64; }
 
 // Workspace layout.  U = np^2 complex128 (16 np^2 bytes).
-//   FP64:  M1, M2, W, Y (4 U)
+//   FP64:  M1, M2, W, Y, T (5 U) and the diagonal-block inverses of L2
 //   mixed: M1, M2 (full Hermitian FP64), X1, X2 (FP64 pair), Q, F, P1, P2
 //          (refinement), L1c|L2c (complex64, 1 U), Wc|Yc (complex64, 1 U):
 //          10 U; the complex64 regions hold Ex, Ey during the refinement.
@@ -25,15 +25,17 @@ struct Plan {
   int n = 0, np = 0, mixed = 0;
   size_t off_m1 = 0, off_m2 = 0, off_w = 0, off_y = 0;
   size_t off_x1 = 0, off_x2 = 0, off_q = 0, off_f = 0, off_p1 = 0, off_p2 = 0;
-  size_t off_z = 0, off_inv = 0;
+  size_t off_z = 0, off_inv = 0, off_t = 0;
   int alg2 = 0;
   size_t off_lc = 0, off_wc = 0;
   size_t off_linv = 0, off_sigma = 0, off_perm = 0, off_invlam = 0, off_status = 0;
   size_t off_bnorm = 0, off_anorm = 0, off_lamu = 0, off_scl = 0, off_ritz = 0, off_small = 0;
   size_t off_jac = 0;
+  size_t off_check = 0;  // opts.checks: reduction buffers of the measurements
   size_t total = 0;
   int kc = 0, rrows = 0;  // Jacobi tiles (0 = built-in)
   int polish = 0;
+  int side = 1;  // second Cholesky factorisation on the library's side stream
 };
 
 inline bool opts_valid(const bse_opts_t& o) {
@@ -46,7 +48,8 @@ inline bool opts_valid(const bse_opts_t& o) {
     return false;
   if (o.route == BSE_ROUTE_EIG && o.precision != BSE_PREC_FP64) return false;  // Alg. 2: FP64 only
   if (!(o.uplo == 0 || o.uplo == 'L' || o.uplo == 'U' || o.uplo == 'l' || o.uplo == 'u')) return false;
-  if (o.reserved0 != 0 || o.reserved[0] != 0 || o.reserved[1] != 0) return false;
+  if (o.checks != 0 && o.checks != 1) return false;
+  if (o.reserved[0] != 0 || o.reserved[1] != 0) return false;
   if (o.tile_entries < 0 || o.tile_entries > 4096 || (o.tile_entries > 0 && !o.tile_table)) return false;
   for (int r = 0; r < o.tile_entries; ++r) {
     const int kc = o.tile_table[3 * r + 1], rr = o.tile_table[3 * r + 2];
@@ -104,6 +107,8 @@ inline Plan make_plan(int n, const bse_opts_t& o) {
   } else if (!p.mixed) {
     p.off_w = take(U);
     p.off_y = take(U);
+    p.off_t = take(U);
+    p.off_inv = take((size_t)p.np * 64 * sizeof(double2));
   } else {
     p.off_x1 = take(U);
     p.off_x2 = take(U);
@@ -126,8 +131,31 @@ inline Plan make_plan(int n, const bse_opts_t& o) {
   p.off_small = take(256);
   p.off_status = take(64);
   p.off_jac = take(jacobi_work_bytes(p.np, p.mixed ? sizeof(float) : sizeof(double)));
+  if (o.checks) p.off_check = take(check_small_bytes(p.n > 0 ? p.n : 1));
   p.total = off + 256;  // slack for aligning the caller's base pointer
   return p;
+}
+
+// Five np x np complex128 regions of a plan, free once its solve is done
+// (the measurements of opts.checks use them).
+inline void check_buffers(const Plan& p, char* base, double2* bufs[5]) {
+  size_t off[5] = {p.off_m1, p.off_m2, p.off_w, p.off_y, p.off_t};
+  if (p.alg2) off[4] = p.off_z;
+  if (p.polish) off[4] = p.off_x1;
+  if (p.mixed) { off[2] = p.off_x1; off[3] = p.off_x2; off[4] = p.off_q; }
+  for (int i = 0; i < 5; ++i) bufs[i] = reinterpret_cast<double2*>(base + off[i]);
+}
+
+// Default stopping level of the FP64 Jacobi sweeps: a pair is rotated while
+// its largest relative off-diagonal Gram entry exceeds 8 sqrt(n) eps.  After
+// the last sweep the columns' relative off-orthogonality is below it, and in
+// the returned vectors it appears multiplied by sqrt(sigma_i / sigma_j) (the
+// Sigma-orthogonality entry of pair (i, j) is g_ij / (sigma_i^1/2 sigma_j^3/2)
+// symmetrised), so the level is as low as the Gram's rounding (a sum of n
+// products, about sqrt(n) eps) allows with margin.
+inline double default_tol64(int n) {
+  const double nn = (double)(n > 64 ? n : 64);
+  return 8.0 * sqrt(nn) * 2.220446049250313e-16;
 }
 
 inline int hip_status(hipError_t e) { return kErrHip - (int)e; }
@@ -176,6 +204,25 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
                           const void* const* B, const int* ldb, double* const* lambda,
                           void* const* X, const int* ldx, void* work, const bse_opts_t& o,
                           bse_info_t* info, int want_timing, hipStream_t s);
+
+// The FP64 form of bse_solve_h1 on a mixed plan's workspace (base, p): the
+// mixed form's way out when its complex64 stage cannot carry the problem.
+// Sets info->fallback = 2.
+int solve_fp64_fallback(int n, const void* A, int lda, const void* B, int ldb, double* lambda,
+                        void* X, int ldx, char* base, const Plan& p, const bse_opts_t& o,
+                        bse_info_t* info, hipStream_t s);
+
+// bse_solve_h1 (noalloc = 0) and bse_solve_h1_noalloc (noalloc = 1: the
+// second Cholesky factorisation on `stream`, no timing events).
+int solve_h1_impl(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
+                  int ldx, void* work, size_t work_bytes, const bse_opts_t* opts, bse_info_t* info,
+                  void* stream, int noalloc);
+
+// opts.checks: measure the returned pairs of one problem on the device into
+// info->sigma_orth_fro and info->max_rel_resid (plan p on base, solve done).
+int run_checks(int n, const void* A, int lda, const void* B, int ldb, const double* lambda,
+               const void* X, int ldx, char* base, const Plan& p, const bse_opts_t& o,
+               bse_info_t* info, hipStream_t s);
 
 // np x np triangular product with a lower-triangular left factor (its k range cut).
 inline GemmDesc tri_gemm(int np, long ld, const void* A, int opA, const void* B, int opB, int triB,

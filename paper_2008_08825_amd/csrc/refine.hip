@@ -53,6 +53,13 @@ struct BuildOp {
   static BSE_DEV void run(const Args& a, int bx, int aux);
 };
 
+// max(m, v), with a NaN v counted as +inf (fmax would drop it), so that a
+// correction that has broken down reads as one that has not converged.
+BSE_DEV double max_or_inf(double m, double v) {
+  if (v != v) return __longlong_as_double(0x7ff0000000000000LL);
+  return fmax(m, v);
+}
+
 BSE_DEV void BuildOp::run(const BuildArgs& a, int bx, int) {
   const int n = a.n;
   const double2* __restrict__ F = a.F;
@@ -111,11 +118,11 @@ BSE_DEV void BuildOp::run(const BuildArgs& a, int bx, int) {
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         e11 = cadd(e11, cscale(K, t / aK));
       }
-      mc = fmax(mc, sqrt(cabs2(e11)));
+      mc = max_or_inf(mc, sqrt(cabs2(e11)));
     }
     const double2 r21 = make_double2(-g21.x, -g21.y);
     const double2 e21 = cscale(cadd(t21, cscale(r21, lj)), 1.0 / (lj + li));
-    mc = fmax(mc, sqrt(cabs2(e21)));
+    mc = max_or_inf(mc, sqrt(cabs2(e21)));
     const double dd = (i == j) ? 1.0 : 0.0;
     Ex[o] = make_double2(dd + e11.x + e21.x, e11.y + e21.y);
     Ey[o] = make_double2(dd + e11.x - e21.x, e11.y - e21.y);
@@ -162,8 +169,12 @@ BSE_DEV void RqOp::run(const RqArgs& args, int bx, int) {
     __syncthreads();
   }
   if (tid == 0) {
-    lam[k] = (ra[0] + rb[0]) / (2.0 * rc[0]);
+    const double l = (ra[0] + rb[0]) / (2.0 * rc[0]);
+    lam[k] = l;
     scl[k] = 1.0 / sqrt(rc[0]);
+    // a pair that is not Sigma-positive (Re x^H y <= 0) or a non-finite
+    // quotient marks the refinement as failed
+    if (args.bad && !(rc[0] > 0.0 && l > 0.0 && l < 1.0e308)) atomic_max_nonneg(args.bad, 1.0);
   }
 }
 
@@ -190,7 +201,8 @@ hipError_t group_refine(GroupOp op, const void* table, const int2* map, int bloc
 
 hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** xp,
                     double2** yp, const RefineWork& w, int max_steps, double stop_corr, double* lam,
-                    double* scl, double* max_corr, int* steps_done, hipStream_t s) {
+                    double* scl, double* max_corr, int* steps_done, hipStream_t s,
+                    double* corr_hist) {
   double2* x = *xp;
   double2* y = *yp;
   double2* Q = w.Q;
@@ -221,6 +233,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     if (e != hipSuccess) return e;
     *max_corr = mc;
     *steps_done = it + 1;
+    if (corr_hist && it < 8) corr_hist[it] = mc;
     if (getenv("BSE_DEBUG")) fprintf(stderr, "[bse] refinement step %d: largest correction %.3e\n", it + 1, mc);
     // the error left after a step is of the order of the square of its correction
     if (mc <= stop_corr) break;
@@ -228,8 +241,14 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
   // Rayleigh quotients and Sigma-normalising scales of the final pairs.
   if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, w.P2), s)) != hipSuccess) return e;
   if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, w.P1), s)) != hipSuccess) return e;
-  const RqArgs qa = {n, x, y, w.P2, w.P1, ld, lam, scl};
+  if ((e = hipMemsetAsync(w.maxcorr, 0, sizeof(double), s)) != hipSuccess) return e;
+  const RqArgs qa = {n, x, y, w.P2, w.P1, ld, lam, scl, w.maxcorr};
   if ((e = launch_one<RqOp>(qa, n, 0, s)) != hipSuccess) return e;
+  double bad = 0.0;
+  e = hipMemcpyAsync(&bad, w.maxcorr, sizeof(double), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (bad != 0.0) *max_corr = __builtin_inf();
   *xp = x;
   *yp = y;
   return hipSuccess;

@@ -131,3 +131,17 @@ def test_adjoint_directional_fd_full_size_n4096(gpu_lib):
     fd = fd_directional(gpu_lib, A, B, dA, dB, 1e-3, w)
     ad = inner(GA, dA) + inner(GB, dB)
     assert abs(fd - ad) <= 1e-7 * max(1.0, abs(ad)), (fd, ad)
+
+
+def test_adjoint_spectrum_loss_n1024_vs_oracle_gradient(gpu_lib):
+    """The differentiation workload's recipe at n = 1024, where the oracle's
+    FP64 gradient takes seconds: ||G - G_oracle||_F / ||G_oracle||_F."""
+    A, B = inputs.workload("n4096", n=1024)
+    print("[gpu] adjoint spectrum loss n=1024 vs oracle gradient", flush=True)
+    lam, GA, GB = grads(gpu_lib, A, B, spectrum_loss_t)
+    lam_o, X_o = ob.solve_chol_svd(A, B)
+    GA_o, GB_o = ob.grad_from_eigenpairs(X_o, ob.spectrum_loss_weights(lam_o))
+    for G, Go in [(GA, GA_o), (GB, GB_o)]:
+        rel = np.linalg.norm(G - Go) / np.linalg.norm(Go)
+        print(f"relative Frobenius gradient error {rel:.2e}")
+        assert rel <= 1e-10

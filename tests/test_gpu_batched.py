@@ -114,14 +114,19 @@ def test_batched_full_workload_256_problems(gpu_lib):
         resid = (torch.sqrt(torch.linalg.norm(R1) ** 2 + torch.linalg.norm(R2) ** 2) / (Hf * torch.linalg.norm(X))).item()
         assert orth < 1e-9 * n ** 0.5 and resid < 1e-13, (i, n, orth, resid)
         assert infos[i]["refine_delta"] <= 1e-6
-    # parity with the oracle on a sample: the three smallest problems and one near 400
+    # parity with the oracle on a sample: the three smallest problems, one near
+    # 400 and the three largest (n close to 1024), eigenvalues and eigenvectors
     order = np.argsort(ns)
-    sample = list(order[:3]) + [int(np.argmin(np.abs(np.array(ns) - 400)))]
+    sample = list(order[:3]) + [int(np.argmin(np.abs(np.array(ns) - 400)))] + list(order[-3:])
     for i in sample:
         A, B = problems[i]
         lam, X = res[i]
-        lam_o, _ = ob.solve_chol_svd(A, B)
-        assert om.rel_eig_err(lam.cpu().numpy(), lam_o) < 1e-10, i
+        lam = lam.cpu().numpy()
+        X = X.resolve_conj().cpu().numpy()
+        lam_o, X_o = ob.solve_chol_svd(A, B)
+        assert om.rel_eig_err(lam, lam_o) < 1e-10, i
+        err, gap = om.eigvec_errors(lam_o, X_o, X, cluster_rtol=1e-9)
+        assert np.all(err <= 1e-10 + 1e-12 / np.minimum(gap, 1.0)), (i, ns[i], np.max(err))
 
 
 def test_autotuner_small_range(gpu_lib):

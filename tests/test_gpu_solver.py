@@ -116,25 +116,107 @@ def test_tamm_dancoff(gpu_lib):
     assert om.rel_eig_err(lam, np.linalg.eigvalsh(A)) < 1e-12
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed_polish"])
-def test_condition_family(gpu_lib, precision):
-    """Sec. 4 generator with closed-form eigenvalues sqrt(3)/2 d (kappa = 10 and 1e3).
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as f:
+        return json.load(f)
 
-    Bound: n * eps * kappa, the error level of a Gram-based Jacobi SVD on a
-    matrix whose singular values span kappa (Table 2 gives LAPACK's level for
-    the smallest eigenvalue alone).
+
+def _fig2_level(cond):
+    """Fig. 2's CHOL+SVD Sigma-orthogonality at condition `cond` (log-log interpolation)."""
+    g = _golden("fig2_sigma_orthogonality.json")
+    c = np.log10(np.array(g["condition"]))
+    v = np.log10(np.array(g["sigma_orthogonality"]["chol_svd"]))
+    return float(10 ** np.interp(np.log10(cond), c, v))
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_polish", "mixed"])
+def test_condition_family(gpu_lib, precision):
+    """Sec. 4 accuracy experiment at the paper's size and conditions.
+
+    A = Q^H diag(d) Q, B = A / 2, d equally spaced in [1, kappa / 3], n = 200:
+    the eigenvalues are sqrt(3)/2 d exactly and cond(H1) = kappa.  Gates:
+      * eigenvalues (the smallest, which Table 2 reports, and every other one):
+        relative error at most 10x Table 2's CHOL+SVD entry at that kappa
+        (LAPACK's SVD on the same construction; the error at kappa = 1e9 is
+        set by the rounding of A itself, about eps kappa);
+      * ||X^H Sigma X - I||_F at most 4x Fig. 2's CHOL+SVD value at the same
+        condition (Fig. 2 uses another, unstated generator at the same n); the
+        mixed form's refinement stops once its corrections are below 1e-6,
+        which leaves up to about 1e-12 of Sigma-orthogonality error at this n,
+        so its gate is the larger of that and 4x Fig. 2;
+      * the residual ||H1 X - X Lambda||_F / (||H1||_F ||X||_F) below 2e-13 at
+        every kappa (Alg. 3 step 4's V1 = L1 U Lambda^-1/2 is taken as
+        L2^-H W_out Lambda^-1/2, a backward stable solve, so no factor kappa).
+    The mixed form re-solves in FP64 where its complex64 stage cannot carry
+    the problem (kappa eps32 near 1); info["fallback"] says so.
     """
-    n = 200
-    for kappa in (10.0, 1e3):
+    t2 = _golden("table2_relative_error.json")
+    n = t2["n"]
+    for kappa, tab in zip(t2["kappa"], t2["relative_error"]["chol_svd"]):
         A, B, d = inputs.condition_family(n, kappa, seed=1)
-        lam, X, _ = run(gpu_lib, A, B, precision=precision)
+        lam, X, info = run(gpu_lib, A, B, precision=precision)
         exact = np.sqrt(3) / 2 * d
+        small = abs(lam[0] - exact[0]) / exact[0]
         e = om.rel_eig_err(lam, exact)
-        print(f"{precision} kappa={kappa:g} rel_eig_err={e:.3e}")
-        assert e < n * np.finfo(float).eps * kappa
-        # V1 = M1 V2 / lambda (Lemma SVDScalarFactors) carries the error of V2
-        # amplified by ||H|| / lambda <= kappa into the residual.
-        assert om.residual(A, B, lam, X) < 200 * np.finfo(float).eps * kappa
+        so = om.sigma_orth_err(X)
+        res = om.residual(A, B, lam, X)
+        print(f"{precision} kappa={kappa:g} smallest={small:.2e} max={e:.2e} (Table 2 {tab:.2e}) "
+              f"sigma_orth={so:.2e} (Fig. 2 {_fig2_level(kappa):.2e}) residual={res:.2e} "
+              f"fallback={info['fallback']}")
+        assert info["status"] == 0
+        assert small <= 10 * tab and e <= 10 * tab
+        assert so <= max(4 * _fig2_level(kappa), 1e-12 if precision == "mixed" else 0.0)
+        assert res < 2e-13
+        if precision == "mixed" and kappa <= 1e3:
+            assert info["fallback"] == 0  # the complex64 stage carries these
+
+
+def test_polish_fallback_path(gpu_lib, monkeypatch):
+    """mixed_polish with its Cholesky QR failure forced from the host: the FP64
+    sweeps then run on W itself and give the FP64 form's results."""
+    n = 130
+    A, B = inputs.coupled(n, seed=21)
+    lam64, X64, _ = run(gpu_lib, A, B)
+    monkeypatch.setenv("BSE_TEST_POLISH_FALLBACK", "1")
+    lam, X, info = run(gpu_lib, A, B, precision="mixed_polish")
+    assert info["status"] == 0 and info["fallback"] == 1
+    assert np.array_equal(lam, lam64) and np.array_equal(X, X64)
+    monkeypatch.delenv("BSE_TEST_POLISH_FALLBACK")
+    lam2, _, info2 = run(gpu_lib, A, B, precision="mixed_polish")
+    assert info2["fallback"] == 0
+    assert om.rel_eig_err(lam2, lam64) < 1e-13
+
+
+def test_mixed_fallback_high_condition(gpu_lib):
+    """kappa = 1e9 puts A - B beyond complex64 (kappa eps32 >> 1): the mixed
+    form reports the FP64 re-solve and returns the FP64 form's results."""
+    A, B, d = inputs.condition_family(160, 1e9, seed=2)
+    lam64, X64, _ = run(gpu_lib, A, B)
+    lam, X, info = run(gpu_lib, A, B, precision="mixed")
+    assert info["status"] == 0 and info["fallback"] == 2
+    assert np.array_equal(lam, lam64) and np.array_equal(X, X64)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed_polish", "mixed"])
+def test_device_checks(gpu_lib, precision):
+    """opts.checks: the device's Sigma-orthogonality and relative residual agree
+    with the same measures computed on the host from the returned pairs."""
+    n = 190
+    A, B = inputs.coupled(n, seed=22)
+    lam, X, info = run(gpu_lib, A, B, precision=precision, checks=True)
+    # both sides round differently (MFMA against host BLAS summation); the
+    # measures agree to a few percent of their size, which is itself at
+    # rounding level
+    so = om.sigma_orth_err(X)
+    assert abs(info["sigma_orth_fro"] - so) <= 0.05 * so + 1e-15
+    H = ob.bse_matrix(A, B)
+    R = H @ X - X * lam[None, :]
+    rel = np.max(np.linalg.norm(R, axis=0) / np.linalg.norm(X, axis=0)) / lam[-1]
+    assert abs(info["max_rel_resid"] - rel) <= 0.05 * rel + 1e-15
+    _, _, off = run(gpu_lib, A, B, precision=precision)
+    assert off["sigma_orth_fro"] == 0.0 and off["max_rel_resid"] == 0.0
 
 
 @pytest.mark.parametrize("which", ["plus", "minus"])
@@ -214,8 +296,11 @@ def test_mixed_parity(gpu_lib, n):
     print(f"mixed n={n} rel_eig_err={e:.2e} refine_corr={info['refine_delta']:.2e} "
           f"resid={om.residual(A, B, lam, X):.2e} sorth={om.sigma_orth_err(X):.2e}")
     assert e < 1e-10
-    assert om.residual(A, B, lam, X) < 1e-9
-    assert om.sigma_orth_err(X) < 1e-6
+    assert om.residual(A, B, lam, X) < 1e-13
+    assert om.sigma_orth_err(X) < 1e-11
+    # eigenvectors against the oracle's, phase-aligned (clusters as subspaces)
+    err, gap = om.eigvec_errors(lam_o, X_o, X, cluster_rtol=1e-9)
+    assert np.all(err <= 1e-10 + 1e-12 / np.minimum(gap, 1.0)), (np.max(err), np.min(gap))
 
 
 def test_mixed_n256_workload_two_steps(gpu_lib):
