@@ -228,6 +228,35 @@ int bse_backward(int n, const void* X, int ldx, const double* w,
 /* Short text for a return code (static storage). */
 const char* bse_status_string(int status, int n);
 
+/* Size of the device array that bse_solve_h1_noalloc works in (per GPU). */
+#define BSE_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* bse_solve_h1 for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * Same problem, arguments (less the workspace) and results as bse_solve_h1,
+ * with these differences:
+ *   - The workspace is a library-owned device array of
+ *     BSE_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, set up on the first call on
+ *     that GPU and held until the process ends; the call allocates no device
+ *     memory, creates no stream or event, and runs everything on `stream`
+ *     (both Cholesky factorisations one after the other; info->timing is
+ *     ignored).  The caller still owns A, B, lambda and X.
+ *   - Limit: the order n must satisfy bse_workspace_bytes(n, opts) <=
+ *     BSE_NOALLOC_SCRATCH_BYTES (n <= 832 for FP64 and the Alg. 2 route,
+ *     n <= 768 for MIXED_POLISH, n <= 576 for MIXED); a larger n returns -1.
+ *   - Every call on a GPU shares that GPU's array: calls that overlap on one
+ *     GPU (two streams or threads) race and must be serialised by the caller.
+ *     The array keeps the last call's contents; nothing in it has to start at
+ *     zero.
+ * Return codes as bse_solve_h1: -1 n (negative or too large for the array),
+ * -2 A, -3 lda, -4 B, -5 ldb, -6 lambda, -7 X, -8 ldx, -9 opts; 1..2n+2 as
+ * documented above; <= -1000 HIP error. */
+int bse_solve_h1_noalloc(int n, const void* A, int lda, const void* B, int ldb,
+                         double* lambda, void* X, int ldx,
+                         const bse_opts_t* opts, bse_info_t* info, void* stream);
+
+/* BSE_NOALLOC_SCRATCH_BYTES, as compiled into the library. */
+size_t bse_noalloc_scratch_bytes(void);
 
 #ifdef __cplusplus
 }

@@ -114,6 +114,8 @@ EXPORTS = [
     "bse_backward_workspace_bytes",
     "bse_backward",
     "bse_status_string",
+    "bse_solve_h1_noalloc",
+    "bse_noalloc_scratch_bytes",
 ]
 
 _lib = None
@@ -150,6 +152,11 @@ def load_library(path: Optional[str] = None):
     lib.bse_backward.restype = ci
     lib.bse_status_string.argtypes = [ci, ci]
     lib.bse_status_string.restype = ctypes.c_char_p
+    lib.bse_solve_h1_noalloc.argtypes = [ci, vp, ci, vp, ci, vp, vp, ci, ctypes.POINTER(BSEOpts),
+                                         ctypes.POINTER(BSEInfo), vp]
+    lib.bse_solve_h1_noalloc.restype = ci
+    lib.bse_noalloc_scratch_bytes.argtypes = []
+    lib.bse_noalloc_scratch_bytes.restype = ctypes.c_size_t
     if path is None:
         _lib = lib
     return lib
@@ -255,6 +262,46 @@ def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
         st = lib.bse_solve_h1(n, pa, lda, pb, ldb, lam.data_ptr(), Xbuf.data_ptr(), max(1, 2 * n),
                               work.data_ptr(), work.numel(), ctypes.byref(o), ctypes.byref(info),
                               _stream_handle(dev))
+    d = info.as_dict()
+    d["status"] = st
+    if check and st != 0:
+        raise BSEError(st, n, d)
+    X = Xbuf.mT
+    if ua == "U":
+        X = X.conj()
+    return lam, X, d
+
+
+def solve_h1_noalloc(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
+                     want_negative=False, max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
+                     check=True, out=None, checks=False):
+    """:func:`solve_h1` through ``bse_solve_h1_noalloc``: the library's own
+    per-GPU scratch array instead of a workspace (no device allocation in the
+    call; ``out`` = preallocated ``(lam, Xbuf)`` avoids torch's as well).
+    Orders whose workspace exceeds the array return status -1."""
+    lib = load_library()
+    if A.shape != B.shape:
+        raise ValueError("A and B must have the same shape")
+    A_, pa, lda, ua = _matrix_arg(A, "A")
+    B_, pb, ldb, ub = _matrix_arg(B, "B")
+    if ua != ub:
+        B_ = B_.contiguous() if ua == "U" else B_.mT.contiguous().mT
+        pb, ldb = B_.data_ptr(), (B_.stride(0) if ua == "U" else B_.stride(1))
+    n = A.shape[0]
+    dev = A.device
+    ncols = 2 * n if want_negative else n
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, ua, None,
+                  checks)
+    if out is None:
+        lam = torch.empty(ncols, dtype=torch.float64, device=dev)
+        Xbuf = torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
+    else:
+        lam, Xbuf = out
+    info = BSEInfo()
+    with torch.cuda.device(dev):
+        st = lib.bse_solve_h1_noalloc(n, pa, lda, pb, ldb, lam.data_ptr(), Xbuf.data_ptr(),
+                                      max(1, 2 * n), ctypes.byref(o), ctypes.byref(info),
+                                      _stream_handle(dev))
     d = info.as_dict()
     d["status"] = st
     if check and st != 0:

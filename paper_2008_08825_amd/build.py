@@ -16,7 +16,8 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libbse.so")
 
 SOURCES = ["capi.hip", "gemm.hip", "chol.hip", "jacobi.hip", "finalize.hip", "refine.hip",
-           "adjoint.hip", "batched.hip", "checks.hip"]
+           "adjoint.hip", "batched.hip", "checks.hip",
+           "noalloc.hip"]
 
 HIP_FLAGS = [
     "-O3",
