@@ -11,6 +11,12 @@
         file the benchmark reads (keyed by workload/form/kernel and the hash
         of the Jacobi kernel source, so the figures are ignored once the
         kernels change).
+    python -m paper_2008_08825_amd.profsummary mfma PMC_DIR [--bench BENCH_JSON]
+        executed MFMA flops per dispatch from a ``--pmc
+        SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_INSTS_VALU_MFMA_MOPS_F32`` run (each
+        count is 512 flops), and for the Jacobi kernels the benchmark's
+        kernel-side figure (exec_flops_per_launch in BENCH_JSON, the JSON line
+        the same run printed) beside it.
 """
 from __future__ import annotations
 
@@ -127,6 +133,45 @@ def traffic(fetch_dir, write_dir, copy_mib, key, json_path=None):
     return "\n".join(lines)
 
 
+def mfma(dirname: str, bench_json=None):
+    path = find(dirname, "counter_collection.csv")
+    per = defaultdict(lambda: defaultdict(float))
+    disp = defaultdict(set)
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"]
+        per[name][r["Counter_Name"]] += float(r["Counter_Value"])
+        disp[name].add(r.get("Dispatch_Id") or r.get("Correlation_Id") or len(disp[name]))
+    formula = {}
+    if bench_json:
+        with open(bench_json) as f:
+            line = [ln for ln in f if ln.strip().startswith("{")][-1]
+        b = json.loads(line)
+        for form in ("fp64", "mixed", "mixed_polish"):
+            if form not in b:
+                continue
+            for sect, prec in (("kernels", "fp64" if form == "fp64" else "mixed"), ("polish_kernels", "fp64")):
+                for k, v in b[form].get(sect, {}).items():
+                    if v.get("exec_flops_per_launch"):
+                        formula[(k, prec)] = v["exec_flops_per_launch"]
+    out = ["| kernel | dispatches | MFMA F64 GFLOP / dispatch | MFMA F32 GFLOP / dispatch | "
+           "kernel-side formula GFLOP / launch | counter / formula |", "|---|---|---|---|---|---|"]
+    rows = sorted(per, key=lambda k: -(per[k].get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+                                       + per[k].get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0)))
+    for name in rows:
+        d = max(1, len(disp[name]))
+        f64 = per[name].get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512 / d
+        f32 = per[name].get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512 / d
+        if f64 == 0.0 and f32 == 0.0:
+            continue
+        bk = bench_key(name)
+        fm = formula.get(bk) if bk else None
+        ratio = f"{(f64 + f32) / fm:.3f}" if fm else ""
+        out.append(f"| {short_name(name)} | {d} | {f64 / 1e9:,.2f} | {f32 / 1e9:,.2f} | "
+                   f"{fm / 1e9:,.2f} | {ratio} |" if fm else
+                   f"| {short_name(name)} | {d} | {f64 / 1e9:,.2f} | {f32 / 1e9:,.2f} | | |")
+    return "\n".join(out)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -139,9 +184,14 @@ def main(argv=None):
     t.add_argument("--copy-mib", type=int, required=True)
     t.add_argument("--key", required=True, help="workload/form the runs measured")
     t.add_argument("--json", default=None)
+    m = sub.add_parser("mfma")
+    m.add_argument("dir")
+    m.add_argument("--bench", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats(a.dir, a.top))
+    elif a.cmd == "mfma":
+        print(mfma(a.dir, a.bench))
     else:
         print(traffic(a.fetch_dir, a.write_dir, a.copy_mib, a.key, a.json))
 
