@@ -24,6 +24,8 @@ Routes
 ``eigenvalues_chol_svd``  Alg. 3 steps 1-3 only, the eigenvalues (what Table 2
                     times and measures), for sizes where vectors cost too much.
 ``solve_chol_eig``  Alg. 2 (CHOL) with LAPACK ``heevd``.
+``solve_tda``       the Tamm-Dancoff approximation B = 0 (Sec. 4, Table 3).
+``solve_sqrt``      Alg. 1 (SQRT), the square-root method the paper compares with.
 ``solve_pencil``    the Hermitian-definite pencil route (Thm DefiniteRealEvals).
 ``solve_dense``     nonsymmetric ``eig`` of the full ``H1`` (tiny n only).
 ``solve_mp``        mpmath eigenvalues of ``H1`` at 50 digits (n <= 6).
@@ -47,6 +49,8 @@ __all__ = [
     "solve_chol_svd",
     "eigenvalues_chol_svd",
     "solve_chol_eig",
+    "solve_tda",
+    "solve_sqrt",
     "solve_pencil",
     "solve_dense",
     "solve_mp",
@@ -148,6 +152,47 @@ def solve_chol_eig(A: np.ndarray, B: np.ndarray):
     V1 = sla.solve_triangular(L.conj().T, VM, lower=False) * np.sqrt(lam)
     V2 = (L @ VM) / np.sqrt(lam)
     X = _assemble(V1, V2)
+    order = np.argsort(lam, kind="stable")
+    return lam[order], X[:, order]
+
+
+def solve_sqrt(A: np.ndarray, B: np.ndarray):
+    """Alg. 1 (SQRT), step by step (Sec. 3.1, Lemma CrosScalarFactors).
+
+    1. ``S = (A - B)^1/2``, the principal square root, by a Hermitian
+       eigendecomposition ``A - B = V_C D_C V_C^H``, ``S = V_C D_C^1/2 V_C^H``
+    2. ``M = S (A + B) S = V_M D V_M^H``  (Hermitian eigendecomposition)
+    3. ``Lambda = D^1/2``
+    4. ``V1 = S^-1 V_M Lambda^1/2``, ``V2 = S V_M Lambda^-1/2``
+    5. ``X = [(V1 + V2)/2; (V2 - V1)/2]``
+    """
+    A = hermitian_from_lower(A)
+    B = hermitian_from_lower(B)
+    dC, VC = sla.eigh(A - B)
+    S = (VC * np.sqrt(dC)) @ VC.conj().T
+    Sinv = (VC / np.sqrt(dC)) @ VC.conj().T
+    M = S @ (A + B) @ S
+    M = (M + M.conj().T) / 2
+    d, VM = sla.eigh(M)
+    lam = np.sqrt(d)
+    V1 = (Sinv @ VM) * np.sqrt(lam)
+    V2 = (S @ VM) / np.sqrt(lam)
+    X = _assemble(V1, V2)
+    order = np.argsort(lam, kind="stable")
+    return lam[order], X[:, order]
+
+
+def solve_tda(A: np.ndarray):
+    """Tamm-Dancoff approximation (B = 0; Sec. 4 applies it to the LiF matrix, Table 3).
+
+    With ``B = 0``, ``H1 = [[A, 0], [0, -A]]``: the positive eigenpairs are
+    those of the Hermitian positive definite ``A`` (``A u = lambda u``) with
+    eigenvectors ``[u; 0]``, Sigma-normalised when ``u^H u = 1``.
+    """
+    A = hermitian_from_lower(A)
+    n = A.shape[0]
+    lam, U = sla.eigh(A)
+    X = np.vstack([U, np.zeros((n, n), dtype=U.dtype)])
     order = np.argsort(lam, kind="stable")
     return lam[order], X[:, order]
 

@@ -138,11 +138,28 @@ def all_pins(solve):
 
 
 # ---------------------------------------------------------------- the oracle routes
-@pytest.mark.parametrize("route", ["chol_svd", "chol_eig", "pencil"])
+@pytest.mark.parametrize("route", ["chol_svd", "chol_eig", "pencil", "sqrt"])
 def test_routes_meet_pins(route):
     solve = {"chol_svd": ob.solve_chol_svd, "chol_eig": ob.solve_chol_eig,
-             "pencil": ob.solve_pencil}[route]
+             "pencil": ob.solve_pencil, "sqrt": ob.solve_sqrt}[route]
     assert all_pins(solve) == []
+
+
+def test_sqrt_route_table2_levels():
+    """Alg. 1 on the Sec. 4 condition family: within 30x Table 2's SQRT row, and
+    (kappa >= 1e6) far less accurate than CHOL+SVD, as Table 2 reports."""
+    with open(os.path.join(GOLDEN, "table2_relative_error.json")) as f:
+        g = json.load(f)
+    n = g["n"]
+    for i, kappa in enumerate(g["kappa"]):
+        A, B, d = inputs.condition_family(n, kappa, seed=i)
+        exact = np.sqrt(3) / 2 * d
+        lam, _ = ob.solve_sqrt(A, B)
+        err = abs(lam[0] - exact[0]) / exact[0]
+        assert err <= 30 * g["relative_error"]["sqrt"][i] + 4 * EPS
+        if kappa >= 1e6:
+            lam_s, _ = ob.solve_chol_svd(A, B)
+            assert err > 100 * abs(lam_s[0] - exact[0]) / exact[0]
 
 
 def test_dense_route_pinned_by_closed_forms():
@@ -377,6 +394,34 @@ def test_eigenvalue_pins_catch_planted_mistakes(kind):
     assert eigenvalue_pins(evals) != []
 
 
+# ---------------------------------------------------------------- Tamm-Dancoff
+def test_tda_route_pinned():
+    """B = 0 reduces H1 to diag(A, -A): against the pinned Alg. 3 route with B = 0
+    (eigenvalues and vectors), a diagonal A (closed form), and the invariants."""
+    for n, seed in ((1, 0), (12, 1), (40, 2)):
+        A, _ = inputs.coupled(n, seed=seed)
+        Z = np.zeros_like(A)
+        lam, X = ob.solve_tda(A)
+        lam_s, X_s = ob.solve_chol_svd(A, Z)
+        assert om.rel_eig_err(lam, lam_s) < 1e-13
+        err, _ = om.eigvec_errors(lam_s, X_s, X, cluster_rtol=1e-9)
+        assert np.max(err) < 1e-9
+        assert om.residual(A, Z, lam, X) < 1e-14 and om.sigma_orth_err(X) < 1e-12
+        assert np.all(X[n:] == 0)
+    d = np.array([3.0, 1.0, 2.5, 7.0])
+    lam, X = ob.solve_tda(np.diag(d).astype(complex))
+    assert np.array_equal(lam, np.sort(d))
+    assert np.allclose(np.abs(X[:4]), np.eye(4)[:, np.argsort(d)])
+
+
+def test_tda_pin_catches_planted_mistake():
+    """Eigenvectors placed in the bottom half ([0; u], the negative half) fail the pins."""
+    A, _ = inputs.coupled(10, seed=3)
+    lam, X = ob.solve_tda(A)
+    Xbad = np.vstack([X[10:], X[:10]])
+    assert om.residual(A, np.zeros_like(A), lam, Xbad) > 1e-3
+
+
 # ---------------------------------------------------------------- planted mistakes
 def _mutant(kind):
     def solve(A, B):
@@ -431,3 +476,23 @@ def test_pins_catch_gradient_mistakes():
     assert not np.allclose(GB_bad, -2 * ob.hermitian_from_lower(B), atol=1e-8)
     GA_bad = (a * w) @ a.conj().T - (b * w) @ b.conj().T
     assert not np.allclose(GA_bad, 2 * Ah, atol=1e-8)
+
+
+@pytest.mark.parametrize("kind", ["s_for_sinv", "lambda_power", "m_order"])
+def test_sqrt_pins_catch_planted_mistakes(kind):
+    def solve(A, B):
+        A = ob.hermitian_from_lower(A)
+        B = ob.hermitian_from_lower(B)
+        dC, VC = sla.eigh(A - B)
+        S = (VC * np.sqrt(dC)) @ VC.conj().T
+        Sinv = (VC / np.sqrt(dC)) @ VC.conj().T
+        M = (A + B) @ S @ S if kind == "m_order" else S @ (A + B) @ S   # S^2 M1 is not Hermitian
+        M = (M + M.conj().T) / 2
+        d, VM = sla.eigh(M)
+        lam = np.sqrt(d)
+        V1 = ((S if kind == "s_for_sinv" else Sinv) @ VM) * np.sqrt(lam)
+        V2 = (S @ VM) * (np.sqrt(lam) if kind == "lambda_power" else 1 / np.sqrt(lam))
+        X = np.vstack([(V1 + V2) / 2, (V2 - V1) / 2])
+        o = np.argsort(lam)
+        return lam[o], X[:, o]
+    assert all_pins(solve) != []
