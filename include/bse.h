@@ -50,9 +50,18 @@
 extern "C" {
 #endif
 
-/* Route: Alg. 3 (CHOL+SVD: chol(A+B), chol(A-B), SVD of L2^H L1) or
- * Alg. 2 (CHOL: chol(A-B), Hermitian eigenproblem of L^H (A+B) L). */
-enum { BSE_ROUTE_SVD = 0, BSE_ROUTE_EIG = 1 };
+/* Route: Alg. 3 (CHOL+SVD: chol(A+B), chol(A-B), SVD of L2^H L1),
+ * Alg. 2 (CHOL: chol(A-B), Hermitian eigenproblem of L^H (A+B) L), or the
+ * Tamm-Dancoff approximation B = 0 (Sec. 4, Table 3: H1 = diag(A, -A), so the
+ * positive eigenpairs are those of the Hermitian positive definite A with
+ * eigenvectors [u; 0]; B is not read and may be NULL; one-sided Jacobi on A
+ * itself, Rayleigh-quotient eigenvalues u^H A u; FP64 only). */
+/* BSE_ROUTE_SQRT: Alg. 1 (Sec. 3.1), the square-root method the paper compares
+ * with: S = (A - B)^1/2 from the one-sided Jacobi on A - B, M = S (A + B) S,
+ * the one-sided Jacobi on M (eigenvalues lambda^2), V1 = S^-1 V_M Lambda^1/2,
+ * V2 = S V_M Lambda^-1/2; FP64 only.  It squares the eigenvalues and loses
+ * the accuracy Table 2 shows; provided for that comparison. */
+enum { BSE_ROUTE_SVD = 0, BSE_ROUTE_EIG = 1, BSE_ROUTE_TDA = 2, BSE_ROUTE_SQRT = 3 };
 /* Arithmetic:
  *   FP64          plain FP64 throughout;
  *   MIXED         complex64 bulk work (Cholesky, W, Jacobi, back-transform)
@@ -94,7 +103,11 @@ typedef struct {
                          dividing np).  A row that does not fit np, or no
                          row, means the built-in choice for that problem.
                          Written by the autotuner of the Python package.     */
-  int reserved[2];    /* must be zero                                           */
+  int values_only;    /* 1: eigenvalues only (what Sec. 4's Table 2 measures):
+                         the eigenvector recovery and final setup are skipped,
+                         X may be NULL and ldx is not checked; the eigenvalues
+                         are the ones the full solve returns.  0 = off         */
+  int reserved;       /* must be zero                                           */
 } bse_opts_t;
 
 typedef struct {

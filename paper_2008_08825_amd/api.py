@@ -23,7 +23,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbse.so")
 
-ROUTES = {"svd": 0, "eig": 1}
+ROUTES = {"svd": 0, "eig": 1, "tda": 2, "sqrt": 3}
 PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_polish": 2}
 
 
@@ -39,7 +39,8 @@ class BSEOpts(ctypes.Structure):
         ("tile_entries", ctypes.c_int),
         ("checks", ctypes.c_int),
         ("tile_table", ctypes.POINTER(ctypes.c_int)),
-        ("reserved", ctypes.c_int * 2),
+        ("values_only", ctypes.c_int),
+        ("reserved", ctypes.c_int),
     ]
 
 
@@ -172,7 +173,7 @@ class BSEError(RuntimeError):
 
 
 def make_opts(route="svd", precision="fp64", max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
-              want_negative=False, uplo="L", tiles=None, checks=False) -> BSEOpts:
+              want_negative=False, uplo="L", tiles=None, checks=False, values_only=False) -> BSEOpts:
     """Options struct; ``tiles`` = rows ``(np_max, kc, rrows)`` of the Jacobi tile table."""
     o = BSEOpts()
     load_library().bse_default_opts(ctypes.byref(o))
@@ -184,6 +185,7 @@ def make_opts(route="svd", precision="fp64", max_sweeps=0, refine_steps=0, jacob
     o.want_negative = 1 if want_negative else 0
     o.uplo = ord(uplo)
     o.checks = 1 if checks else 0
+    o.values_only = 1 if values_only else 0
     if tiles:
         flat = [int(v) for row in tiles for v in row]
         arr = (ctypes.c_int * len(flat))(*flat)
@@ -225,17 +227,23 @@ def workspace_bytes(n: int, **kw) -> int:
     return int(lib.bse_workspace_bytes(n, ctypes.byref(o)))
 
 
-def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
+def solve_h1(A: torch.Tensor, B: Optional[torch.Tensor], *, route="svd", precision="fp64",
              want_negative=False, max_sweeps=0, refine_steps=0, jacobi_tol=0.0,
              timing=False, check=True, work: Optional[torch.Tensor] = None,
-             out=None, tiles=None, checks=False):
+             out=None, tiles=None, checks=False, values_only=False):
     """All eigenpairs of H1 = [[A, B], [-B, -A]] (lower triangles of A, B read).
 
     Returns ``(lam, X, info)``: ``lam`` (n, ascending; 2n with ``want_negative``),
     ``X`` (2n x n or 2n x 2n, complex128) with ``H1 X = X diag(lam)`` and
     ``X^H Sigma X = I`` (``-I`` on the negative half), ``info`` a dict.
+    ``route="tda"``: the Tamm-Dancoff approximation B = 0 (``B`` may be None).
+    ``values_only``: eigenvalues alone, ``X`` is None.
     """
     lib = load_library()
+    if B is None:
+        if route != "tda":
+            raise ValueError("B may be None only for route='tda'")
+        B = A
     if A.shape != B.shape:
         raise ValueError("A and B must have the same shape")
     A_, pa, lda, ua = _matrix_arg(A, "A")
@@ -247,10 +255,10 @@ def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
     dev = A.device
     ncols = 2 * n if want_negative else n
     o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, ua, tiles,
-                  checks)
+                  checks, values_only)
     if out is None:
         lam = torch.empty(ncols, dtype=torch.float64, device=dev)
-        Xbuf = torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
+        Xbuf = None if values_only else torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
     else:
         lam, Xbuf = out
     need = int(lib.bse_workspace_bytes(n, ctypes.byref(o)))
@@ -259,13 +267,16 @@ def solve_h1(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
     info = BSEInfo()
     info.timing = int(timing)
     with torch.cuda.device(dev):
-        st = lib.bse_solve_h1(n, pa, lda, pb, ldb, lam.data_ptr(), Xbuf.data_ptr(), max(1, 2 * n),
+        st = lib.bse_solve_h1(n, pa, lda, pb, ldb, lam.data_ptr(),
+                              Xbuf.data_ptr() if Xbuf is not None else None, max(1, 2 * n),
                               work.data_ptr(), work.numel(), ctypes.byref(o), ctypes.byref(info),
                               _stream_handle(dev))
     d = info.as_dict()
     d["status"] = st
     if check and st != 0:
         raise BSEError(st, n, d)
+    if Xbuf is None:
+        return lam, None, d
     X = Xbuf.mT
     if ua == "U":
         X = X.conj()
@@ -314,7 +325,7 @@ def solve_h1_noalloc(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision
 
 def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
                   max_sweeps=0, refine_steps=0, jacobi_tol=0.0, check=True, tiles=None,
-                  timing=0, work=None):
+                  timing=0, work=None, values_only=False):
     """Independent problems ``(A_i, B_i)`` in one library call; returns lists of (lam, X) and infos.
 
     ``tiles``: rows ``(np_max, kc, rrows)`` of the Jacobi tile table (see
@@ -330,6 +341,10 @@ def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
     lams, Xbufs = [], []
     dev = As[0].device if count else torch.device("cuda")
     for A, B in zip(As, Bs):
+        if B is None:  # route "tda": B is not read
+            if route != "tda":
+                raise ValueError("B may be None only for route='tda'")
+            B = A
         A_, pa, lda, ua = _matrix_arg(A, "A")
         B_, pb, ldb, ub = _matrix_arg(B, "B")
         if ua != "U" or ub != "U":
@@ -340,12 +355,14 @@ def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
         n = A.shape[0]
         ncols = 2 * n if want_negative else n
         lam = torch.empty(ncols, dtype=torch.float64, device=dev)
-        Xb = torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
+        Xb = None if values_only else torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
         lams.append(lam)
         Xbufs.append(Xb)
         ns.append(n); pas.append(pa); ldas.append(max(1, lda)); pbs.append(pb); ldbs.append(max(1, ldb))
-        plams.append(lam.data_ptr()); pxs.append(Xb.data_ptr()); ldxs.append(max(1, 2 * n))
-    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, "U", tiles)
+        plams.append(lam.data_ptr()); pxs.append(Xb.data_ptr() if Xb is not None else None)
+        ldxs.append(max(1, 2 * n))
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, "U", tiles,
+                  False, values_only)
     IA = ctypes.c_int * max(count, 1)
     PA = ctypes.c_void_p * max(count, 1)
     c_n = IA(*ns)
@@ -362,13 +379,13 @@ def solve_batched(As, Bs, *, route="svd", precision="fp64", want_negative=False,
     out_infos = [infos[i].as_dict() for i in range(count)]
     if check and st != 0:
         raise BSEError(st, ns[0] if ns else 0, out_infos)
-    results = [(lams[i], Xbufs[i].mT.conj()) for i in range(count)]
+    results = [(lams[i], None if values_only else Xbufs[i].mT.conj()) for i in range(count)]
     return results, out_infos, st
 
 
-def batched_workspace_bytes(ns, *, route="svd", precision="fp64", tiles=None) -> int:
+def batched_workspace_bytes(ns, *, route="svd", precision="fp64", tiles=None, values_only=False) -> int:
     lib = load_library()
-    o = make_opts(route, precision, tiles=tiles)
+    o = make_opts(route, precision, tiles=tiles, values_only=values_only)
     IA = ctypes.c_int * max(len(ns), 1)
     return int(lib.bse_batched_workspace_bytes(len(ns), IA(*[int(v) for v in ns]), ctypes.byref(o)))
 

@@ -686,8 +686,9 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         rq.add({nn, pr->x, pr->y, P2, P1, ld, lamu, scl, d_corr + pr->idx}, nn);
         rk.add({nn, lamu, perm, 0}, (nn + 255) / 256);
         wl.add({nn, lamu, perm, pr->lambda, o.want_negative}, (nn + 255) / 256);
-        as.add({nn, pr->x, pr->y, ld, perm, scl, pr->X, pr->ldx, o.want_negative, nullptr},
-               cols_blocks(nn, nn));
+        if (!o.values_only)
+          as.add({nn, pr->x, pr->y, ld, perm, scl, pr->X, pr->ldx, o.want_negative, nullptr},
+                 cols_blocks(nn, nn));
       }
       BSE_TRY(run_gemm<double>(ar, g00, s));
       BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
@@ -741,6 +742,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         la.add({pr->n, np, anorm, bnorm, lamu, invlam, scl, 1}, (np + 255) / 256);
         rk.add({pr->n, lamu, perm, 0}, (pr->n + 255) / 256);
         wl.add({pr->n, lamu, perm, pr->lambda, o.want_negative}, (pr->n + 255) / 256);
+        if (o.values_only) continue;
         ti.add({M2, np, inv}, np / 64);
         trsm_lh_for_each(np, M2, np, W, T, inv, [&](const TrsmStep& st) { steps.push_back(st); });  // V1 = L2^-H Ws -> T
         as.add({pr->n, T, Y, np, perm, nullptr, pr->X, pr->ldx, o.want_negative, scl},

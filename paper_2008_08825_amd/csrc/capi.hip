@@ -77,7 +77,7 @@ int read_status(int* status, int n, bse_info_t* info, hipStream_t s) {
 // L1 and L2 are read only.
 int back_transform_z(int n, int np, const double2* L1, const double2* L2, double2* Zb, double2* Y,
                      double2* T, double2* inv, char* base, const Plan& p, double* lambda, void* X,
-                     int ldx, int want_negative, hipStream_t s) {
+                     int ldx, int want_negative, int values_only, hipStream_t s) {
   const long ld = np;
   double* sigma = reinterpret_cast<double*>(base + p.off_sigma);
   int* perm = reinterpret_cast<int*>(base + p.off_perm);
@@ -90,6 +90,7 @@ int back_transform_z(int n, int np, const double2* L1, const double2* L2, double
   BSE_TRY(gemm_z(tri_gemm(np, ld, L2, 0, Zb, 0, 0, Y), s));       // V2 = L2 Ws
   BSE_TRY(gemm_z(tri_gemm(np, ld, L1, 1, Y, 0, 0, T), s));        // T = L1^H V2
   BSE_TRY(rq_lambda_z(n, np, T, ld, bnorm, anorm, lamu, invlam, scl, perm, lambda, want_negative, s));
+  if (values_only) return 0;
   BSE_TRY(trsm_lh_z(np, L2, ld, Zb, T, inv, s));                    // V1 = L2^-H Ws (unscaled)
   BSE_TRY(assemble_z(n, T, Y, ld, perm, nullptr, static_cast<double2*>(X), ldx, want_negative, s,
                      scl));
@@ -135,12 +136,157 @@ int solve_fp64(int n, const void* A, int lda, const void* B, int ldb, double* la
   BSE_TRY(jacobi_z(np, W, ld, jw, tol, max_sweeps, jr, s, kernel_time_stride(want_timing)));
   tm.mark();
   if (int e = back_transform_z(n, np, M1, M2, W, Y, T, inv, base, p, lambda, X, ldx,
-                               o.want_negative, s))
+                               o.want_negative, o.values_only, s))
     return e;
   tm.mark();
   BSE_TRY(hipStreamSynchronize(s));
   const int ret = jr.converged ? 0 : 2 * n + 1;
   fill_info(info, ret, jr);
+  tm.fill(info, slots);
+  return ret;
+}
+
+// Tamm-Dancoff approximation (B = 0; Sec. 4, Table 3): H1 = diag(A, -A), so
+// the positive eigenpairs are A u = lambda u with eigenvectors [u; 0] (u^H u
+// = 1 gives the Sigma-normalisation) and the negative ones [0; u] with
+// -lambda (Lemma ComputeNegEvecs).  A is Hermitian positive definite (A + B
+// and A - B are), so the one-sided Jacobi on A itself leaves columns z_k =
+// lambda_k u_k: A J = U Lambda.  Eigenvalues are the Rayleigh quotients
+// z^H A z / z^H z (second order in the vector error), vectors z / ||z||.
+int solve_tda(int n, const void* A, int lda, double* lambda, void* X, int ldx, char* base,
+              const Plan& p, const bse_opts_t& o, bse_info_t* info, int want_timing, hipStream_t s) {
+  const int np = p.np;
+  const long ld = np;
+  double2* M1 = reinterpret_cast<double2*>(base + p.off_m1);
+  double2* M2 = reinterpret_cast<double2*>(base + p.off_m2);
+  double2* W = reinterpret_cast<double2*>(base + p.off_w);
+  double2* Y = reinterpret_cast<double2*>(base + p.off_y);
+  int* perm = reinterpret_cast<int*>(base + p.off_perm);
+  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
+  double* scl = reinterpret_cast<double*>(base + p.off_scl);
+  JacobiWork jw;
+  jacobi_carve(np, sizeof(double), base + p.off_jac, jw, p.kc, p.rrows);
+  const int upper = (o.uplo == 'U' || o.uplo == 'u');
+  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
+  const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : default_tol64(n);
+
+  Timer tm(want_timing != 0, s);
+  const int slots[8] = {0, 3, 5, -1, -1, -1, -1, -1};
+  tm.mark();
+  // M1 = A (full Hermitian, identity beyond n), W = copy; the padded columns
+  // are unit vectors orthogonal to the rest, so the sweeps leave them alone
+  BSE_TRY(form_m12(n, np, static_cast<const double2*>(A), lda, nullptr, 0, upper, M1, M2, ld, s));
+  BSE_TRY(mirror_upper_z(np, M1, ld, s));
+  BSE_TRY(hipMemcpyAsync(W, M1, (size_t)np * np * sizeof(double2), hipMemcpyDeviceToDevice, s));
+  tm.mark();
+  JacobiResult jr;
+  BSE_TRY(jacobi_z(np, W, ld, jw, tol, max_sweeps, jr, s, kernel_time_stride(want_timing)));
+  tm.mark();
+  {
+    GemmDesc g;  // Y = A Z
+    g.M = n; g.N = n; g.K = n;
+    g.A = M1; g.lda = ld; g.opA = 0;
+    g.B = W; g.ldb = ld; g.opB = 0;
+    g.C = Y; g.ldc = ld;
+    BSE_TRY(gemm_z(g, s));
+  }
+  BSE_TRY(rq_pairs_z(n, ld, W, W, Y, Y, lamu, scl, s));  // z^H A z / z^H z, 1 / ||z||
+  BSE_TRY(sort_lambda(n, lamu, perm, lambda, o.want_negative, s));
+  // final setup with V1 = V2 = z / ||z||: X = [u; 0] (and [0; u])
+  if (!o.values_only)
+    BSE_TRY(assemble_z(n, W, W, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
+  tm.mark();
+  BSE_TRY(hipStreamSynchronize(s));
+  const int ret = jr.converged ? 0 : 2 * n + 1;
+  fill_info(info, ret, jr);
+  tm.fill(info, slots);
+  return ret;
+}
+
+// Alg. 1 (SQRT, Sec. 3.1).  M1 = A + B and M2 = A - B in full; the one-sided
+// Jacobi on the Hermitian positive definite M2 leaves columns z_k = d_k v_k
+// (M2 = V_C D_C V_C^H, d the column norms), so the principal square root and
+// its inverse are Hermitian products with the columns scaled along k:
+//   S = Z diag(d^-3/2) Z^H = V_C D_C^1/2 V_C^H,   S^-1 = Z diag(d^-5/2) Z^H;
+// M = S M1 S (two GEMMs), the one-sided Jacobi on M leaves y_k = d_k v_k with
+// d = lambda^2, and V1 = S^-1 V_M Lambda^1/2 = S^-1 Y diag(d^-3/4),
+// V2 = S V_M Lambda^-1/2 = S Y diag(d^-5/4).
+int solve_sqrt(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
+               int ldx, char* base, const Plan& p, const bse_opts_t& o, bse_info_t* info,
+               int want_timing, hipStream_t s) {
+  const int np = p.np;
+  const long ld = np;
+  double2* M1 = reinterpret_cast<double2*>(base + p.off_m1);
+  double2* M2 = reinterpret_cast<double2*>(base + p.off_m2);
+  double2* Sb = reinterpret_cast<double2*>(base + p.off_w);
+  double2* Si = reinterpret_cast<double2*>(base + p.off_y);
+  double2* T = reinterpret_cast<double2*>(base + p.off_t);
+  int* perm = reinterpret_cast<int*>(base + p.off_perm);
+  double* dC = reinterpret_cast<double*>(base + p.off_sigma);
+  double* dM = reinterpret_cast<double*>(base + p.off_bnorm);
+  double* ks = reinterpret_cast<double*>(base + p.off_anorm);
+  double* kis = reinterpret_cast<double*>(base + p.off_invlam);
+  double* c1 = reinterpret_cast<double*>(base + p.off_scl);
+  double* c2 = reinterpret_cast<double*>(base + p.off_ritz);
+  double* lamu = reinterpret_cast<double*>(base + p.off_lamu);
+  JacobiWork jw;
+  jacobi_carve(np, sizeof(double), base + p.off_jac, jw, p.kc, p.rrows);
+  const int upper = (o.uplo == 'U' || o.uplo == 'u');
+  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 30;
+  const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : default_tol64(n);
+  auto full = [&](const double2* a, int opA, const double2* b, int opB, double2* c,
+                  const double* kscale, const double* colscale) {
+    GemmDesc g;
+    g.M = np; g.N = np; g.K = np;
+    g.A = a; g.lda = ld; g.opA = opA;
+    g.B = b; g.ldb = ld; g.opB = opB;
+    g.C = c; g.ldc = ld;
+    g.kscale = kscale;
+    g.colscale = colscale;
+    return gemm_z(g, s);
+  };
+
+  Timer tm(want_timing != 0, s);
+  const int slots[8] = {0, 3, 3, 5, -1, -1, -1, -1};
+  tm.mark();
+  BSE_TRY(form_m12(n, np, static_cast<const double2*>(A), lda, static_cast<const double2*>(B), ldb,
+                   upper, M1, M2, ld, s));
+  BSE_TRY(mirror_upper_z(np, M1, ld, s));
+  BSE_TRY(mirror_upper_z(np, M2, ld, s));
+  tm.mark();
+  JacobiResult j1, j2;
+  BSE_TRY(jacobi_z(np, M2, ld, jw, tol, max_sweeps, j1, s, kernel_time_stride(want_timing)));  // Z = V_C D_C
+  BSE_TRY(colnorm_z(np, M2, ld, dC, s));
+  BSE_TRY(sqrt_scales(n, np, dC, dC, ks, kis, c1, c2, lamu, s));  // ks, kis (c1, c2 redone below)
+  BSE_TRY(full(M2, 0, M2, 1, Sb, ks, nullptr));   // S = Z diag(d^-3/2) Z^H
+  BSE_TRY(full(M2, 0, M2, 1, Si, kis, nullptr));  // S^-1 = Z diag(d^-5/2) Z^H
+  BSE_TRY(full(M1, 0, Sb, 0, T, nullptr, nullptr));  // T = M1 S
+  BSE_TRY(full(Sb, 0, T, 0, M1, nullptr, nullptr));  // M = S M1 S
+  tm.mark();
+  BSE_TRY(jacobi_z(np, M1, ld, jw, tol, max_sweeps, j2, s, kernel_time_stride(want_timing)));  // Y = V_M D
+  BSE_TRY(colnorm_z(np, M1, ld, dM, s));
+  BSE_TRY(sqrt_scales(n, np, dC, dM, ks, kis, c1, c2, lamu, s));
+  BSE_TRY(sort_lambda(n, lamu, perm, lambda, o.want_negative, s));
+  tm.mark();
+  if (!o.values_only) {
+    BSE_TRY(full(Si, 0, M1, 0, M2, nullptr, c1));  // V1 = S^-1 Y d^-3/4
+    BSE_TRY(full(Sb, 0, M1, 0, T, nullptr, c2));   // V2 = S Y d^-5/4
+    BSE_TRY(assemble_z(n, M2, T, ld, perm, nullptr, static_cast<double2*>(X), ldx, o.want_negative, s));
+  }
+  tm.mark();
+  BSE_TRY(hipStreamSynchronize(s));
+  const int ret = j1.converged && j2.converged ? 0 : 2 * n + 1;
+  JacobiResult both = j2;
+  both.sweeps = j1.sweeps + j2.sweeps;
+  both.rotations = j1.rotations + j2.rotations;
+  both.pair_checks = j1.pair_checks + j2.pair_checks;
+  both.cross_pair_checks = j1.cross_pair_checks + j2.cross_pair_checks;
+  both.inner_rotations = j1.inner_rotations + j2.inner_rotations;
+  for (int i = 0; i < 3; ++i) {
+    both.kernel_ms[i] += j1.kernel_ms[i];
+    both.kernel_launches[i] += j1.kernel_launches[i];
+  }
+  fill_info(info, ret, both);
   tm.fill(info, slots);
   return ret;
 }
@@ -203,6 +349,14 @@ int solve_alg2(int n, const void* A, int lda, const void* B, int ldb, double* la
   tm.mark();
   BSE_TRY(colnorm_z(np, Y, ld, d, s));
   BSE_TRY(alg2_lambda_z(n, d, lamu, perm, lambda, o.want_negative, fx, fy, s));
+  if (o.values_only) {
+    tm.mark();
+    BSE_TRY(hipStreamSynchronize(s));
+    const int ret = jr.converged ? 0 : 2 * n + 1;
+    fill_info(info, ret, jr);
+    tm.fill(info, slots);
+    return ret;
+  }
   BSE_TRY(gather_scale_z(n, np, Y, ld, perm, fx, M1, s));  // V_M Lambda^1/2 (sorted)
   BSE_TRY(gather_scale_z(n, np, Y, ld, perm, fy, W, s));   // V_M Lambda^-1/2
   tm.mark();
@@ -340,7 +494,8 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   double hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   BSE_TRY(refine_z(n, ld, M1, M2, &x, &y, rw, steps, 1.0e-6, lamu, scl, &maxcorr, &steps_done, s, hist));
   BSE_TRY(sort_lambda(n, lamu, perm, lambda, o.want_negative, s));
-  BSE_TRY(assemble_z(n, x, y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
+  if (!o.values_only)
+    BSE_TRY(assemble_z(n, x, y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
   tm.mark();
   BSE_TRY(hipStreamSynchronize(s));
   int ret = jr.converged ? 0 : 2 * n + 1;
@@ -461,7 +616,7 @@ int solve_polish(int n, const void* A, int lda, const void* B, int ldb, double* 
   tm.mark();
   // Alg. 3 steps 4-6; T and V1 in X2 (the factor of G is no longer needed)
   if (int e = back_transform_z(n, np, M1, M2, Zb, Y, X2, inv, base, p, lambda, X, ldx,
-                               o.want_negative, s))
+                               o.want_negative, o.values_only, s))
     return e;
   tm.mark();
   BSE_TRY(hipStreamSynchronize(s));
@@ -505,6 +660,21 @@ int run_checks(int n, const void* A, int lda, const void* B, int ldb, const doub
   return 0;
 }
 
+int check_h1_args(int n, const void* A, int lda, const void* B, int ldb, const double* lambda,
+                  const void* X, int ldx, const bse_opts_t& o) {
+  if (n < 0 || n > 46000) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (!opts_valid(o)) return -11;
+  const int tda = o.route == BSE_ROUTE_TDA;
+  if (n > 0 && !B && !tda) return -4;
+  if (!tda && ldb < (n > 1 ? n : 1)) return -5;
+  if (n > 0 && !lambda) return -6;
+  if (n > 0 && !X && !o.values_only) return -7;
+  if (!o.values_only && ldx < (2 * n > 1 ? 2 * n : 1)) return -8;
+  return 0;
+}
+
 // bse_solve_h1 and its variant without allocation (noalloc != 0: the second
 // Cholesky factorisation on `stream` too, no timing events).
 int solve_h1_impl(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
@@ -518,15 +688,7 @@ int solve_h1_impl(int n, const void* A, int lda, const void* B, int ldb, double*
     memset(info, 0, sizeof(*info));
     info->timing = want_timing;
   }
-  if (n < 0 || n > 46000) return -1;
-  if (n > 0 && !A) return -2;
-  if (lda < (n > 1 ? n : 1)) return -3;
-  if (n > 0 && !B) return -4;
-  if (ldb < (n > 1 ? n : 1)) return -5;
-  if (n > 0 && !lambda) return -6;
-  if (n > 0 && !X) return -7;
-  if (ldx < (2 * n > 1 ? 2 * n : 1)) return -8;
-  if (!opts_valid(o)) return -11;
+  if (int e = check_h1_args(n, A, lda, B, ldb, lambda, X, ldx, o)) return e;
   if (n == 0) return 0;
   Plan p = make_plan(n, o);
   if (noalloc) p.side = 0;
@@ -535,7 +697,9 @@ int solve_h1_impl(int n, const void* A, int lda, const void* B, int ldb, double*
   hipStream_t s = static_cast<hipStream_t>(stream);
   char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
   int ret;
-  if (p.alg2) ret = solve_alg2(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  if (p.tda) ret = solve_tda(n, A, lda, lambda, X, ldx, base, p, o, info, want_timing, s);
+  else if (p.sqrt_route) ret = solve_sqrt(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
+  else if (p.alg2) ret = solve_alg2(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
   else if (p.mixed) ret = solve_mixed(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
   else if (p.polish) ret = solve_polish(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
   else ret = solve_fp64(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, want_timing, s);
@@ -583,8 +747,8 @@ size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* op
     const size_t b = bse_workspace_bytes(n[i], &o);
     if (b > mx) mx = b;
   }
-  // Alg. 2 and the polished mixed form: problems one after another
-  if (o.route == BSE_ROUTE_EIG || o.precision == BSE_PREC_MIXED_POLISH) return mx;
+  // Alg. 2, TDA and the polished mixed form: problems one after another
+  if (o.route != BSE_ROUTE_SVD || o.precision == BSE_PREC_MIXED_POLISH) return mx;
   return batched_workspace(batch, n, o);
 }
 
@@ -595,20 +759,21 @@ int bse_solve_batched(int batch, const int* n, const void* const* A, const int* 
   if (batch < 0) return -1;
   if (batch > 0 && !n) return -2;
   if (batch > 0 && (!A || !lda)) return -3;
-  if (batch > 0 && (!B || !ldb)) return -5;
-  if (batch > 0 && !lambda) return -7;
-  if (batch > 0 && (!X || !ldx)) return -8;
   bse_opts_t o;
   bse_default_opts(&o);
   if (opts) o = *opts;
   if (!opts_valid(o)) return -12;
+  if (batch > 0 && (!B || !ldb) && o.route != BSE_ROUTE_TDA) return -5;
+  if (batch > 0 && !lambda) return -7;
+  if (batch > 0 && (!X || !ldx) && !o.values_only) return -8;
+  const int tda = o.route == BSE_ROUTE_TDA;
   for (int i = 0; i < batch; ++i) {
     if (n[i] < 0 || n[i] > 46000) return -2;
     if (n[i] == 0) continue;
     if (!A[i] || lda[i] < n[i]) return -3;
-    if (!B[i] || ldb[i] < n[i]) return -5;
+    if (!tda && (!B[i] || ldb[i] < n[i])) return -5;
     if (!lambda[i]) return -7;
-    if (!X[i] || ldx[i] < 2 * n[i]) return -8;
+    if (!o.values_only && (!X[i] || ldx[i] < 2 * n[i])) return -8;
   }
   if (batch == 0) return 0;
   const size_t need = bse_batched_workspace_bytes(batch, n, &o);
@@ -622,14 +787,14 @@ int bse_solve_batched(int batch, const int* n, const void* const* A, const int* 
       info[i].timing = want_timing;
     }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (o.route != BSE_ROUTE_EIG && o.precision != BSE_PREC_MIXED_POLISH)
+  if (o.route == BSE_ROUTE_SVD && o.precision != BSE_PREC_MIXED_POLISH)
     return solve_batched_grouped(batch, n, A, lda, B, ldb, lambda, X, ldx, work, o, info,
                                  want_timing, s);
   int first = 0;
   for (int i = 0; i < batch; ++i) {
     bse_info_t* inf = info ? &info[i] : nullptr;
-    const int st = bse_solve_h1(n[i], A[i], lda[i], B[i], ldb[i], lambda[i], X[i], ldx[i], work,
-                                work_bytes, &o, inf, stream);
+    const int st = bse_solve_h1(n[i], A[i], lda[i], B ? B[i] : nullptr, ldb ? ldb[i] : 1, lambda[i],
+                                X ? X[i] : nullptr, ldx ? ldx[i] : 1, work, work_bytes, &o, inf, stream);
     if (st <= kErrHip) return st;
     if (st != 0 && first == 0) first = st;
   }

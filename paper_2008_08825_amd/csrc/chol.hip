@@ -46,7 +46,9 @@ BSE_DEV void FormOp::run(const FormArgs& a, int bx, int) {
       const double2* S = pass == 0 ? A : B;
       const long lds = pass == 0 ? lda : ldb;
       double2* v = pass == 0 ? va : vb;
-      if (upper) {
+      if (!S) {  // B == nullptr: B = 0 (Tamm-Dancoff)
+        for (int q = 0; q < 16; ++q) v[q] = make_double2(0.0, 0.0);
+      } else if (upper) {
         // element (i, j) of the lower triangle is conj(S[j + i * lds])
         for (int q = 0; q < 16; ++q) {
           int cc = tid & 63, rr = (tid >> 6) + 4 * q;  // cc runs along j (contiguous)

@@ -213,6 +213,33 @@ struct AssembleOp {
   }
 };
 
+// Scales of the SQRT route (Alg. 1) from the column norms dC of the iterated
+// A - B (its eigenvalues) and dM of the iterated M (the squared eigenvalues):
+// S = Z diag(dC^-3/2) Z^H, S^-1 = Z diag(dC^-5/2) Z^H, V1 = S^-1 Y dM^-3/4,
+// V2 = S Y dM^-5/4, lambda = dM^1/2 (k < n; padded columns of A - B are unit
+// vectors with dC = 1 and keep S = I there, padded V columns are zero).
+__global__ __launch_bounds__(256) void k_sqrt_scales(int n, int np, const double* __restrict__ dC,
+                                                     const double* __restrict__ dM,
+                                                     double* __restrict__ ks, double* __restrict__ kis,
+                                                     double* __restrict__ c1, double* __restrict__ c2,
+                                                     double* __restrict__ lam) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= np) return;
+  const double c = dC[k];
+  ks[k] = c > 0.0 ? 1.0 / (c * sqrt(c)) : 0.0;
+  kis[k] = c > 0.0 ? 1.0 / (c * c * sqrt(c)) : 0.0;
+  if (k < n) {
+    const double m = dM[k], q = sqrt(sqrt(m));  // m^1/4
+    c1[k] = m > 0.0 ? 1.0 / (m / q) : 0.0;       // m^-3/4
+    c2[k] = m > 0.0 ? 1.0 / (m * q) : 0.0;       // m^-5/4
+    lam[k] = sqrt(m);
+  } else {
+    c1[k] = 0.0;
+    c2[k] = 0.0;
+    lam[k] = 0.0;
+  }
+}
+
 inline int b256(int n) { return (n + 255) / 256; }
 
 }  // namespace
@@ -294,6 +321,12 @@ hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double*
   if (e == hipSuccess) e = sort_lambda(n, lam, perm, lambda, want_negative, s);
   if (e != hipSuccess) return e;
   k_alg2_scales<<<(n + 255) / 256, 256, 0, s>>>(n, d, perm, fx, fy);
+  return hipGetLastError();
+}
+
+hipError_t sqrt_scales(int n, int np, const double* dC, const double* dM, double* ks, double* kis,
+                       double* c1, double* c2, double* lam, hipStream_t s) {
+  k_sqrt_scales<<<b256(np), 256, 0, s>>>(n, np, dC, dM, ks, kis, c1, c2, lam);
   return hipGetLastError();
 }
 

@@ -49,7 +49,8 @@ hipError_t cholesky_pair_c(int np, int n_real, float2* M1, float2* M2, long ld, 
                            int* status, hipStream_t s, int side = 1);
 
 // M1 = A + B, M2 = A - B (lower triangles, zero strict upper part), padded to
-// np with identity; reads the `upper` or lower triangle of A, B.
+// np with identity; reads the `upper` or lower triangle of A, B (B == nullptr
+// reads as B = 0).
 hipError_t form_m12(int n, int np, const double2* A, long lda, const double2* B,
                     long ldb, int upper, double2* M1, double2* M2, long ldm,
                     hipStream_t s);
@@ -242,6 +243,10 @@ struct RefineWork {
   double2 *Q = nullptr, *F = nullptr, *P1 = nullptr, *P2 = nullptr, *Ex = nullptr, *Ey = nullptr;
   double *ritz = nullptr, *dots = nullptr, *maxcorr = nullptr;
 };
+// Column k < n: lam_k = (x_k^H Qx_k + y_k^H Qy_k) / (2 Re x_k^H y_k) and
+// scl_k = (Re x_k^H y_k)^-1/2.
+hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const double2* Qx,
+                      const double2* Qy, double* lam, double* scl, hipStream_t s);
 // corr_hist (host, optional): the largest correction of each step (first 8).
 hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** x, double2** y,
                     const RefineWork& w, int max_steps, double stop_corr, double* lam, double* scl,
@@ -255,6 +260,12 @@ hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* p
 // fy_r = 1 / (d sqrt(lam)) and fx_r = sqrt(lam) / d for sorted position r.
 hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double* lambda,
                          int want_negative, double* fx, double* fy, hipStream_t s);
+
+// Scales of the SQRT route (Alg. 1): from the column norms dC of the iterated
+// A - B and dM of the iterated M = S (A + B) S: ks = dC^-3/2, kis = dC^-5/2
+// (S = Z ks Z^H, S^-1 = Z kis Z^H), c1 = dM^-3/4, c2 = dM^-5/4, lam = dM^1/2.
+hipError_t sqrt_scales(int n, int np, const double* dC, const double* dM, double* ks, double* kis,
+                       double* c1, double* c2, double* lam, hipStream_t s);
 
 // X[:, r] = s_k [(t_k V1_k + V2_k)/2; (V2_k - t_k V1_k)/2] with k = perm[r]
 // (and the mirrored negative half); perm == nullptr means k = r, scl ==

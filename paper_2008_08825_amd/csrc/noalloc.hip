@@ -56,8 +56,9 @@ int bse_solve_h1_noalloc(int n, const void* A, int lda, const void* B, int ldb, 
   bse_opts_t o;
   bse_default_opts(&o);
   if (opts) o = *opts;
-  if (!bse::opts_valid(o)) return -9;
-  if (n < 0) return -1;
+  // argument numbers of bse_solve_h1 from 9 on are shifted by the two
+  // workspace arguments this entry point does not have
+  if (int e = bse::check_h1_args(n, A, lda, B, ldb, lambda, X, ldx, o)) return e == -11 ? -9 : e;
   if (n > 0 && bse_workspace_bytes(n, &o) > (size_t)BSE_NOALLOC_SCRATCH_BYTES)
     return -1;  // the workspace of order n would not fit in the scratch array
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -67,8 +68,6 @@ int bse_solve_h1_noalloc(int n, const void* A, int lda, const void* B, int ldb, 
   if (dev < 0 || dev >= kMaxDev) return bse::hip_status(hipErrorInvalidDevice);
   void* work = nullptr;
   if ((e = scratch_ptr(dev, &work)) != hipSuccess) return bse::hip_status(e);
-  // argument numbers of bse_solve_h1 from 9 on are shifted by the two
-  // workspace arguments this entry point does not have
   const int st = bse::solve_h1_impl(n, A, lda, B, ldb, lambda, X, ldx, work,
                                     (size_t)BSE_NOALLOC_SCRATCH_BYTES, &o, info, stream, 1);
   if (st == -11) return -9;

@@ -26,7 +26,7 @@ struct Plan {
   size_t off_m1 = 0, off_m2 = 0, off_w = 0, off_y = 0;
   size_t off_x1 = 0, off_x2 = 0, off_q = 0, off_f = 0, off_p1 = 0, off_p2 = 0;
   size_t off_z = 0, off_inv = 0, off_t = 0;
-  int alg2 = 0;
+  int alg2 = 0, tda = 0, sqrt_route = 0;
   size_t off_lc = 0, off_wc = 0;
   size_t off_linv = 0, off_sigma = 0, off_perm = 0, off_invlam = 0, off_status = 0;
   size_t off_bnorm = 0, off_anorm = 0, off_lamu = 0, off_scl = 0, off_ritz = 0, off_small = 0;
@@ -39,7 +39,10 @@ struct Plan {
 };
 
 inline bool opts_valid(const bse_opts_t& o) {
-  if (o.route != BSE_ROUTE_SVD && o.route != BSE_ROUTE_EIG) return false;
+  if (o.route < BSE_ROUTE_SVD || o.route > BSE_ROUTE_SQRT) return false;
+  if ((o.route == BSE_ROUTE_TDA || o.route == BSE_ROUTE_SQRT) && o.precision != BSE_PREC_FP64)
+    return false;  // TDA and SQRT: FP64 only
+  if (o.values_only != 0 && o.values_only != 1) return false;
   if (o.precision != BSE_PREC_FP64 && o.precision != BSE_PREC_MIXED &&
       o.precision != BSE_PREC_MIXED_POLISH)
     return false;
@@ -49,7 +52,7 @@ inline bool opts_valid(const bse_opts_t& o) {
   if (o.route == BSE_ROUTE_EIG && o.precision != BSE_PREC_FP64) return false;  // Alg. 2: FP64 only
   if (!(o.uplo == 0 || o.uplo == 'L' || o.uplo == 'U' || o.uplo == 'l' || o.uplo == 'u')) return false;
   if (o.checks != 0 && o.checks != 1) return false;
-  if (o.reserved[0] != 0 || o.reserved[1] != 0) return false;
+  if (o.reserved != 0) return false;
   if (o.tile_entries < 0 || o.tile_entries > 4096 || (o.tile_entries > 0 && !o.tile_table)) return false;
   for (int r = 0; r < o.tile_entries; ++r) {
     const int kc = o.tile_table[3 * r + 1], rr = o.tile_table[3 * r + 2];
@@ -84,6 +87,8 @@ inline Plan make_plan(int n, const bse_opts_t& o) {
   p.polish = o.precision == BSE_PREC_MIXED_POLISH;
   pick_tiles(o, p.np, &p.kc, &p.rrows);
   p.alg2 = o.route == BSE_ROUTE_EIG;
+  p.tda = o.route == BSE_ROUTE_TDA;
+  p.sqrt_route = o.route == BSE_ROUTE_SQRT;
   const size_t U = (size_t)p.np * p.np * sizeof(double2);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -211,6 +216,10 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
 int solve_fp64_fallback(int n, const void* A, int lda, const void* B, int ldb, double* lambda,
                         void* X, int ldx, char* base, const Plan& p, const bse_opts_t& o,
                         bse_info_t* info, hipStream_t s);
+
+// Argument checks of bse_solve_h1 (return codes -1 .. -8, -11 for opts), on the host.
+int check_h1_args(int n, const void* A, int lda, const void* B, int ldb, const double* lambda,
+                  const void* X, int ldx, const bse_opts_t& o);
 
 // bse_solve_h1 (noalloc = 0) and bse_solve_h1_noalloc (noalloc = 1: the
 // second Cholesky factorisation on `stream`, no timing events).

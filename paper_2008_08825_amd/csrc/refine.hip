@@ -199,6 +199,12 @@ hipError_t group_refine(GroupOp op, const void* table, const int2* map, int bloc
   }
 }
 
+hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const double2* Qx,
+                      const double2* Qy, double* lam, double* scl, hipStream_t s) {
+  const RqArgs qa = {n, x, y, Qx, Qy, ld, lam, scl, nullptr};
+  return launch_one<RqOp>(qa, n, 0, s);
+}
+
 hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** xp,
                     double2** yp, const RefineWork& w, int max_steps, double stop_corr, double* lam,
                     double* scl, double* max_corr, int* steps_done, hipStream_t s,

@@ -43,8 +43,25 @@ def test_host_only_queries():
     assert 0 < b256 < b300
     assert lib.bse_workspace_bytes(-1, ctypes.byref(o)) == 0
     bad = api.make_opts()
-    bad.reserved[0] = 1
+    bad.reserved = 1
     assert lib.bse_workspace_bytes(10, ctypes.byref(bad)) == 0
+    for field, value in (("values_only", 2), ("checks", 3), ("route", 4)):
+        bad = api.make_opts()
+        setattr(bad, field, value)
+        assert lib.bse_workspace_bytes(10, ctypes.byref(bad)) == 0, field
+    # the Tamm-Dancoff route is FP64 only; it accepts a NULL B (argument checks pass it)
+    tda = api.make_opts(route="tda")
+    assert lib.bse_workspace_bytes(10, ctypes.byref(tda)) > 0
+    assert lib.bse_workspace_bytes(10, ctypes.byref(api.make_opts(route="tda", precision="mixed"))) == 0
+    assert lib.bse_solve_h1(4, 16, 4, None, 0, 16, 16, 8, None, 0, ctypes.byref(tda), None, None) == -9
+    # values only: X may be NULL and ldx is not checked
+    vo = api.make_opts(values_only=True)
+    assert lib.bse_solve_h1(4, 16, 4, 16, 4, 16, None, 0, None, 0, ctypes.byref(vo), None, None) == -9
+    # the entry point without allocation: argument errors before any device work
+    assert lib.bse_solve_h1_noalloc(-1, None, 1, None, 1, None, None, 1, ctypes.byref(o), None, None) == -1
+    assert lib.bse_solve_h1_noalloc(4, None, 4, 16, 4, 16, 16, 8, ctypes.byref(o), None, None) == -2
+    assert lib.bse_solve_h1_noalloc(4, 16, 4, 16, 4, 16, 16, 8, ctypes.byref(bad), None, None) == -9
+    assert lib.bse_solve_h1_noalloc(5000, 16, 5000, 16, 5000, 16, 16, 10000, ctypes.byref(o), None, None) == -1
     info = api.BSEInfo()
     # argument errors are detected before any device work
     assert lib.bse_solve_h1(-1, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), ctypes.byref(info), None) == -1
