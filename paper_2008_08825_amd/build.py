@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libbse.so")
 
 SOURCES = ["capi.hip", "gemm.hip", "chol.hip", "jacobi.hip", "finalize.hip", "refine.hip",
            "adjoint.hip", "batched.hip", "checks.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "window.hip"]
 
 HIP_FLAGS = [
     "-O3",

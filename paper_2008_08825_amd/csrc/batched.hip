@@ -18,9 +18,11 @@
 //               readback of the number of problems still active
 //   finalize    grouped column norms, scaling, GEMMs, Rayleigh quotients,
 //               sort and the final setup of step 6
-//   refinement  (mixed form) three grouped GEMM launches and two small ones
-//               per step over the problems whose last correction was still
-//               above the stopping level.
+//   refinement  (mixed form) per step, over the problems whose last
+//               correction was still above the stopping level: grouped GEMMs
+//               for the products, per window pass one grouped launch of the
+//               window eigensolvers and grouped block GEMMs, the correction
+//               and the basis update.
 // Problems are ordered by padded order, largest first, so the problems that
 // take part in a Jacobi round or a Cholesky panel form a prefix of every
 // table and a launch uses a prefix of its map.
@@ -39,97 +41,12 @@
 #include "common.hpp"
 #include "internal.hpp"
 #include "plan.hpp"
+#include "group.hpp"
 
 namespace bse {
 namespace {
 
 constexpr int kBig = 0x7fffffff;
-
-// Table staging: host-built tables are copied into a device arena just
-// before the launch that reads them.  Copies and launches share one stream,
-// so when the arena wraps around, every launch that read the overwritten
-// bytes has already run.
-struct Arena {
-  char* dev = nullptr;
-  size_t cap = 0, cur = 0;
-  hipStream_t s = nullptr;
-  std::vector<std::vector<char>> keep;  // host sources stay valid until the call returns
-
-  hipError_t put(const void* src, size_t bytes, const void** out) {
-    const size_t need = align256(bytes);
-    if (need > cap) return hipErrorInvalidValue;
-    if (cur + need > cap) cur = 0;
-    keep.emplace_back(static_cast<const char*>(src), static_cast<const char*>(src) + bytes);
-    char* d = dev + cur;
-    cur += need;
-    *out = d;
-    if (bytes == 0) return hipSuccess;
-    return hipMemcpyAsync(d, keep.back().data(), bytes, hipMemcpyHostToDevice, s);
-  }
-};
-
-template <class A>
-struct Grp {
-  std::vector<A> tab;
-  std::vector<int2> map;
-  std::vector<int> start;  // first map entry of each table row
-  void add(const A& a, int blocks) {
-    if (blocks <= 0) return;
-    start.push_back((int)map.size());
-    const int row = (int)tab.size();
-    tab.push_back(a);
-    for (int b = 0; b < blocks; ++b) map.push_back(make_int2(row, b));
-  }
-  int blocks() const { return (int)map.size(); }
-  // map entries of the first `rows` table rows
-  int prefix(int rows) const {
-    return rows >= (int)start.size() ? (int)map.size() : start[rows];
-  }
-};
-
-struct Dev {
-  const void* tab = nullptr;
-  const int2* map = nullptr;
-  int blocks = 0;
-};
-
-template <class A>
-hipError_t stage(Arena& ar, const Grp<A>& g, Dev& d) {
-  d.blocks = g.blocks();
-  if (d.blocks == 0) return hipSuccess;
-  hipError_t e = ar.put(g.tab.data(), g.tab.size() * sizeof(A), &d.tab);
-  const void* m = nullptr;
-  if (e == hipSuccess) e = ar.put(g.map.data(), g.map.size() * sizeof(int2), &m);
-  d.map = static_cast<const int2*>(m);
-  return e;
-}
-
-inline GemmArgs<double> args_of(const GemmDesc& d, double*) { return gemm_args_z(d); }
-inline GemmArgs<float> args_of(const GemmDesc& d, float*) { return gemm_args_c(d); }
-
-// Stage and launch a grouped GEMM (all rows share opA, opB).
-template <typename T>
-hipError_t run_gemm(Arena& ar, const std::vector<GemmDesc>& descs, hipStream_t s) {
-  if (descs.empty()) return hipSuccess;
-  Grp<GemmArgs<T>> g;
-  for (const GemmDesc& d : descs) {
-    g.add(args_of(d, static_cast<T*>(nullptr)), gemm_tiles(d));
-  }
-  Dev dv;
-  hipError_t e = stage(ar, g, dv);
-  if (e != hipSuccess) return e;
-  return group_gemm(sizeof(T) == 8 ? 0 : 1, descs[0].opA, descs[0].opB, dv.tab, dv.map, dv.blocks, s);
-}
-
-typedef hipError_t (*GroupFn)(GroupOp, const void*, const int2*, int, int, hipStream_t);
-
-template <class A>
-hipError_t run_op(Arena& ar, const Grp<A>& g, GroupFn fn, GroupOp op, int aux, hipStream_t s) {
-  Dev dv;
-  hipError_t e = stage(ar, g, dv);
-  if (e != hipSuccess) return e;
-  return fn(op, dv.tab, dv.map, dv.blocks, aux, s);
-}
 
 // Built-in Jacobi tiles for a problem in a batch: Gram row chunks of about
 // 256 rows, rotation groups of the largest of 256 / 128 / 64 rows dividing np.
@@ -140,6 +57,25 @@ void batch_tiles(const bse_opts_t& o, int np, int* kc, int* rrows) {
   while (np / (2 * k) >= 256 && jacobi_tiles_valid(np, 2 * k, 64) && 2 * k <= jacobi_default_kc(np)) k *= 2;
   *kc = k;
   *rrows = np % 256 == 0 ? 256 : (np % 128 == 0 ? 128 : 64);
+}
+
+// Every problem's block triangular solve steps in its own order: one grouped
+// GEMM launch per (group, slot).
+template <typename T>
+hipError_t run_steps(Arena& ar, std::vector<TrsmStep>& steps, hipStream_t s) {
+  std::stable_sort(steps.begin(), steps.end(), [](const TrsmStep& a, const TrsmStep& b) {
+    return a.group != b.group ? a.group < b.group : a.slot < b.slot;
+  });
+  for (size_t i = 0; i < steps.size();) {
+    size_t j = i;
+    std::vector<GemmDesc> launch;
+    while (j < steps.size() && steps[j].group == steps[i].group && steps[j].slot == steps[i].slot)
+      launch.push_back(steps[j++].g);
+    hipError_t e = run_gemm<T>(ar, launch, s);
+    if (e != hipSuccess) return e;
+    i = j;
+  }
+  return hipSuccess;
 }
 
 struct Prob {
@@ -179,8 +115,15 @@ size_t arena_bytes(const std::vector<int>& nps) {
     b = std::max(b, (size_t)pairs * jacobi_default_kc(np));
     b = std::max(b, (size_t)pairs * (np / 64));
     b = std::max(b, (size_t)2 * np);
+    // the refinement's window launches: block GEMMs per window, two matrices at once
+    const int nwin = np / 64 + 2;
+    GemmDesc wd;
+    wd.M = np; wd.N = 64; wd.K = 64;
+    b = std::max(b, (size_t)2 * nwin * gemm_tiles(wd));
+    wd.M = 64; wd.N = np;
+    b = std::max(b, (size_t)2 * nwin * gemm_tiles(wd));
     blocks += 3 * b + 16;  // a phase may stage up to three maps at once (Jacobi)
-    rows += 4;
+    rows += std::max(4, 2 * nwin);
   }
   return align256(rows * 256) + align256(blocks * sizeof(int2)) + 4096;
 }
@@ -472,11 +415,15 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       }
       const SweepArgs sa = {st, d_active, jacobi_pairs(np) * jacobi_rounds(np), max_sweeps,
                             mixed ? 1.0e-5 : 1.0e-10, 1, mixed ? 0.3 : 1.0,
-                            mixed ? kTrackLevel32 : kTrackLevel64, jacobi_pairs(np)};
+                            mixed ? kTrackLevel32 : kTrackLevel64, jacobi_pairs(np),
+                            mixed ? 1.0 / 32 : 0.0};
       sw.add(sa, 1);
       rounds.push_back(jacobi_rounds(np));
     }
     Dev dg, de, dr, ds;
+    // the four tables are read by every sweep's launches: one run of the arena
+    BSE_TRY(ar.reserve(mixed ? staged_bytes(gc) + staged_bytes(ec) + staged_bytes(rc) + staged_bytes(sw)
+                             : staged_bytes(gz) + staged_bytes(ez) + staged_bytes(rz) + staged_bytes(sw)));
     if (mixed) {
       BSE_TRY(stage(ar, gc, dg));
       BSE_TRY(stage(ar, ec, de));
@@ -554,11 +501,16 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   // ---- finalize: scaled singular columns, Rayleigh quotients, back-transform
   if (!ok.empty()) {
     if (mixed) {
+      // Alg. 3 steps 4-5 in complex64 as in the single solve: V2 = L2 Ws,
+      // T = L1^H V2 (Rayleigh quotients), V1 = L2^-H Ws / ||Ws||^2 by grouped
+      // block triangular solves
       Grp<ColnormArgs<float2>> n1, n2, n3;
       Grp<ScaleArgs<float2>> sc;
       Grp<LambdaArgs> la;
       Grp<C64Args> cv;
-      std::vector<GemmDesc> v2, t, v1;
+      Grp<TriInvArgsT<float2>> ti;
+      std::vector<GemmDesc> v2, t;
+      std::vector<TrsmStep> steps;
       for (Prob* pr : ok) {
         const int np = pr->np;
         const size_t half = (size_t)np * np * sizeof(float2);
@@ -566,6 +518,8 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         float2* L2c = pr->at<float2>(pr->p.off_lc + half);
         float2* Wc = pr->at<float2>(pr->p.off_wc);
         float2* Yc = pr->at<float2>(pr->p.off_wc + half);
+        float2* Tc = pr->at<float2>(pr->p.off_q);
+        float2* invc = pr->at<float2>(pr->p.off_f);
         double* sigma = pr->at<double>(pr->p.off_sigma);
         double* bnorm = pr->at<double>(pr->p.off_bnorm);
         double* anorm = pr->at<double>(pr->p.off_anorm);
@@ -575,14 +529,13 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         sc.add({pr->n, np, Wc, np, sigma}, cols_blocks(np, np));
         n2.add({Wc, np, np, bnorm}, np);
         v2.push_back(tri_gemm(np, np, L2c, 0, Wc, 0, 0, Yc));  // V2 = L2 Ws
-        t.push_back(tri_gemm(np, np, L1c, 1, Yc, 0, 0, Wc));   // T = L1^H V2
-        n3.add({Wc, np, np, anorm}, np);
-        la.add({pr->n, np, anorm, bnorm, pr->at<double>(pr->p.off_lamu), invlam, scl, 0}, (np + 255) / 256);
-        GemmDesc v = tri_gemm(np, np, L1c, 0, Wc, 0, 0, L2c);  // V1 = L1 T Lambda^-1
-        v.colscale = invlam;
-        v1.push_back(v);
-        cv.add({np, L2c, np, pr->at<double2>(pr->p.off_x1), np, scl}, cols_blocks(np, np));
-        cv.add({np, Yc, np, pr->at<double2>(pr->p.off_x2), np, scl}, cols_blocks(np, np));
+        t.push_back(tri_gemm(np, np, L1c, 1, Yc, 0, 0, Tc));   // T = L1^H V2
+        n3.add({Tc, np, np, anorm}, np);
+        la.add({pr->n, np, anorm, bnorm, pr->at<double>(pr->p.off_lamu), invlam, scl, 1}, (np + 255) / 256);
+        ti.add({L2c, np, invc}, np / 64);
+        trsm_lh_for_each(np, L2c, np, Wc, L1c, invc, [&](const TrsmStep& st) { steps.push_back(st); });
+        cv.add({np, L1c, np, pr->at<double2>(pr->p.off_x1), np, scl}, cols_blocks(np, np));
+        cv.add({np, Yc, np, pr->at<double2>(pr->p.off_x2), np, nullptr}, cols_blocks(np, np));
         pr->x = pr->at<double2>(pr->p.off_x1);
         pr->y = pr->at<double2>(pr->p.off_x2);
         pr->q = pr->at<double2>(pr->p.off_q);
@@ -596,19 +549,42 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       BSE_TRY(run_gemm<float>(ar, t, s));
       BSE_TRY(run_op(ar, n3, group_finalize, G_COLNORM_C, 0, s));
       BSE_TRY(run_op(ar, la, group_finalize, G_LAMBDA, 0, s));
-      BSE_TRY(run_gemm<float>(ar, v1, s));
+      BSE_TRY(run_op(ar, ti, group_chol, G_TRIINV_C, 0, s));
+      BSE_TRY(run_steps<float>(ar, steps, s));
       BSE_TRY(run_op(ar, cv, group_finalize, G_C64, 0, s));
       tm.mark();
 
-      // ---- FP64 refinement, problem by problem until its correction is small
-      const int steps = o.refine_steps > 0 ? o.refine_steps : 8;
-      for (int it = 0; it < steps; ++it) {
+      // ---- FP64 refinement (as refine_z), problem by problem until its
+      // first-order correction is small.  The pairs first go into the
+      // ascending order of their eigenvalues, so that a window of the
+      // Rayleigh-Ritz passes holds spectral neighbours.
+      {
+        Grp<RankArgs> rk0;
+        Grp<GatherArgs> ga;
+        for (Prob* pr : ok) {
+          const int np = pr->np;
+          int* perm = pr->at<int>(pr->p.off_perm);
+          rk0.add({pr->n, pr->at<double>(pr->p.off_lamu), perm, 0}, (pr->n + 255) / 256);
+          ga.add({pr->n, np, pr->x, np, perm, nullptr, pr->q}, cols_blocks(np, np));
+          ga.add({pr->n, np, pr->y, np, perm, nullptr, pr->f}, cols_blocks(np, np));
+        }
+        BSE_TRY(run_op(ar, rk0, group_finalize, G_RANK, 0, s));
+        BSE_TRY(run_op(ar, ga, group_finalize, G_GATHER, 0, s));
+        for (Prob* pr : ok) {
+          std::swap(pr->x, pr->q);
+          std::swap(pr->y, pr->f);
+        }
+      }
+      const int max_steps = o.refine_steps > 0 ? o.refine_steps : 8;
+      constexpr int passes = kWindowPasses;
+      for (int it = 0; it < max_steps; ++it) {
         std::vector<Prob*> act;
         for (Prob* pr : ok)
           if (!pr->rdone) act.push_back(pr);
         if (act.empty()) break;
         BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
         std::vector<GemmDesc> g00, g10, upd;
+        Grp<MirrorArgs> mi;
         Grp<RitzArgs> rt;
         Grp<BuildArgs> bd;
         for (Prob* pr : act) {
@@ -632,18 +608,74 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           g00.push_back(nn_gemm(M2, 0, pr->x, 0, pr->q));   // M2 x
           g00.push_back(nn_gemm(M1, 0, pr->y, 0, Ex));      // M1 y (Ex is free until k_build)
           g10.push_back(nn_gemm(pr->x, 1, pr->y, 0, pr->f));  // F = x^H y
-          g10.push_back(nn_gemm(pr->x, 1, pr->q, 0, P2));     // P2 = x^H M2 x
-          g10.push_back(nn_gemm(pr->y, 1, Ex, 0, P1));        // P1 = y^H M1 y
+          GemmDesc p2 = nn_gemm(pr->x, 1, pr->q, 0, P2);      // P2 = x^H M2 x (lower tiles)
+          p2.lowerC = 1;
+          g10.push_back(p2);
+          GemmDesc p1 = nn_gemm(pr->y, 1, Ex, 0, P1);         // P1 = y^H M1 y (lower tiles)
+          p1.lowerC = 1;
+          g10.push_back(p1);
+          mi.add({(int)ld, P2, ld}, tiles64((int)ld));
+          mi.add({(int)ld, P1, ld}, tiles64((int)ld));
           rt.add({nn, pr->f, P1, P2, ld, ritz}, (nn + 255) / 256);
           const int T = (nn + 63) / 64;
           bd.add({nn, pr->f, P1, P2, ld, ritz, Ex, Ey, kRefineDelta, d_corr + pr->idx}, T * T);
-          upd.push_back(nn_gemm(pr->x, 0, Ex, 0, pr->q));     // x (I + E11 + E21)
-          upd.push_back(nn_gemm(pr->y, 0, Ey, 0, pr->f));     // y (I + E11 - E21)
         }
         BSE_TRY(run_gemm<double>(ar, g00, s));
         BSE_TRY(run_gemm<double>(ar, g10, s));
+        BSE_TRY(run_op(ar, mi, group_chol, G_MIRROR, 0, s));
+        for (int pass = 0; pass < passes; ++pass) {
+          // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
+          const int off = (pass & 1) ? 32 : 0;
+          Grp<WinArgs> wn;
+          std::vector<GemmDesc> right[3], left[3];
+          for (Prob* pr : act) {
+            const long ld = pr->np;
+            double2* Cb = window_blocks(pr->at<double2>(pr->p.off_cb0), pr->n, pass);
+            double2* P1 = pr->at<double2>(pr->p.off_p1);
+            double2* P2 = pr->at<double2>(pr->p.off_p2);
+            wn.add({pr->n, ld, pr->f, P1, P2, off, Cb, nullptr}, window_count(pr->n, off));
+            double2* mats[3] = {pr->f, P1, P2};
+            for (int k = 0; k < 3; ++k) window_congruence(pr->n, ld, mats[k], pr->q, Cb, off, right[k], left[k]);
+          }
+          {
+            Dev dv;
+            BSE_TRY(stage(ar, wn, dv));
+            BSE_TRY(group_window(dv.tab, dv.map, dv.blocks, s));
+          }
+          for (int k = 0; k < 3; ++k) {
+            BSE_TRY(run_gemm<double>(ar, right[k], s));
+            BSE_TRY(run_gemm<double>(ar, left[k], s));
+          }
+        }
         BSE_TRY(run_op(ar, rt, group_refine, G_RITZ, 0, s));
         BSE_TRY(run_op(ar, bd, group_refine, G_BUILD, 0, s));
+        // x <- x C_1 C_2 (I + E11 + E21), y <- y C_1 C_2 (I + E11 - E21)
+        for (int pass = 0; pass < passes; ++pass) {
+          const int off = (pass & 1) ? 32 : 0;
+          std::vector<GemmDesc> g;
+          for (Prob* pr : act) {
+            const double2* Cb = window_blocks(pr->at<double2>(pr->p.off_cb0), pr->n, pass);
+            window_right(pr->n, pr->np, pr->x, pr->q, Cb, off, g);
+            window_right(pr->n, pr->np, pr->y, pr->f, Cb, off, g);
+          }
+          BSE_TRY(run_gemm<double>(ar, g, s));
+          for (Prob* pr : act) {
+            std::swap(pr->x, pr->q);
+            std::swap(pr->y, pr->f);
+          }
+        }
+        for (Prob* pr : act) {
+          const int nn = pr->n;
+          const long ld = pr->np;
+          GemmDesc d;
+          d.M = nn; d.N = nn; d.K = nn;
+          d.A = pr->x; d.lda = ld; d.opA = 0;
+          d.B = pr->at<double2>(pr->p.off_lc); d.ldb = ld; d.opB = 0;
+          d.C = pr->q; d.ldc = ld;
+          upd.push_back(d);                                  // x (I + E11 + E21)
+          d.A = pr->y; d.B = pr->at<double2>(pr->p.off_wc); d.C = pr->f;
+          upd.push_back(d);                                  // y (I + E11 - E21)
+        }
         BSE_TRY(run_gemm<double>(ar, upd, s));
         std::vector<double> corr(batch, 0.0);
         BSE_TRY(hipMemcpyAsync(corr.data(), d_corr, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -655,7 +687,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           pr->rsteps += 1;
           pr->rcorr = corr[pr->idx];
           // the error left after a step is of the order of the square of its correction
-          if (pr->rcorr <= 1.0e-6) pr->rdone = 1;
+          if (pr->rcorr <= kRefineStop) pr->rdone = 1;
         }
       }
       // Rayleigh quotients, Sigma-normalising scales, sort, final setup
@@ -759,18 +791,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
       BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
       BSE_TRY(run_op(ar, ti, group_chol, G_TRIINV, 0, s));
-      // every problem's solve steps in its own order; one grouped launch per (group, slot)
-      std::stable_sort(steps.begin(), steps.end(), [](const TrsmStep& a, const TrsmStep& b) {
-        return a.group != b.group ? a.group < b.group : a.slot < b.slot;
-      });
-      for (size_t i = 0; i < steps.size();) {
-        size_t j = i;
-        std::vector<GemmDesc> launch;
-        while (j < steps.size() && steps[j].group == steps[i].group && steps[j].slot == steps[i].slot)
-          launch.push_back(steps[j++].g);
-        BSE_TRY(run_gemm<double>(ar, launch, s));
-        i = j;
-      }
+      BSE_TRY(run_steps<double>(ar, steps, s));
       BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
       tm.mark();
     }
@@ -783,7 +804,8 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   for (const Prob& pr : probs) {
     int st = pr.status;
     const JacState& js = states[pr.idx];
-    if (st == 0 && !js.converged) st = 2 * pr.n + 1;
+    // the complex64 iteration may end early (stop fraction): the refinement decides
+    if (st == 0 && !(mixed ? js.sweeps > 0 : js.converged)) st = 2 * pr.n + 1;
     if (st == 0 && mixed && !(pr.rcorr <= 1.0e-4)) st = 2 * pr.n + 2;
     if (st != 0 && mixed) {
       // the complex64 stage could not carry this problem: re-solve it in FP64

@@ -437,6 +437,11 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   rw.Ey = reinterpret_cast<double2*>(base + p.off_wc);
   rw.ritz = reinterpret_cast<double*>(base + p.off_ritz);
   rw.maxcorr = reinterpret_cast<double*>(base + p.off_small);
+  rw.Cb0 = reinterpret_cast<double2*>(base + p.off_cb0);
+  rw.arena = base + p.off_arena;
+  rw.arena_cap = refine_arena_bytes(np);
+  rw.perm = perm;
+  rw.windows = kWindowPasses;
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 20;
   const int steps = o.refine_steps > 0 ? o.refine_steps : 8;
@@ -471,34 +476,41 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   }
   tm.mark();
   JacobiResult jr;
-  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, kernel_time_stride(want_timing), 0.3));
+  // the refinement's window Rayleigh-Ritz resolves what the last sweeps would
+  // (neighbour mixing), so the complex64 iteration ends, like the polish's,
+  // once a sweep rotates fewer than 1/32 of its pairs
+  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, kernel_time_stride(want_timing), 0.3,
+                   1.0 / 32));
   tm.mark();
   BSE_TRY(scale_singular_cols_c(n, np, Wc, ld, sigma, bnorm, s));
   tm.mark();
+  // Alg. 3 steps 4-5 in complex64 as in the FP64 form: V2 = L2 Ws, T = L1^H V2
+  // (Rayleigh quotients), V1 = L2^-H Ws / ||Ws||^2 by a block triangular solve
+  // (backward stable: the x, y of each pair stay balanced to the complex64
+  // rounding, which the refinement's coupling to the negative half needs)
+  float2* Tc = reinterpret_cast<float2*>(base + p.off_q);
+  float2* invc = reinterpret_cast<float2*>(base + p.off_f);
   BSE_TRY(gemm_c(tri_gemm(np, ld, L2c, 0, Wc, 0, 0, Yc), s));  // V2 = L2 Ws
-  BSE_TRY(gemm_c(tri_gemm(np, ld, L1c, 1, Yc, 0, 0, Wc), s));  // T = L1^H V2
-  BSE_TRY(colnorm_c(np, Wc, ld, anorm, s));
-  BSE_TRY(lambda_from_norms(n, np, anorm, bnorm, lamu, invlam, scl, s));
-  {
-    GemmDesc v = tri_gemm(np, ld, L1c, 0, Wc, 0, 0, L2c);       // V1 = L1 T Lambda^-1
-    v.colscale = invlam;
-    BSE_TRY(gemm_c(v, s));
-  }
-  BSE_TRY(c64_to_c128(np, L2c, ld, X1, ld, scl, s));  // x = V1 s (FP64)
-  BSE_TRY(c64_to_c128(np, Yc, ld, X2, ld, scl, s));   // y = V2 s
+  BSE_TRY(gemm_c(tri_gemm(np, ld, L1c, 1, Yc, 0, 0, Tc), s));  // T = L1^H V2
+  BSE_TRY(colnorm_c(np, Tc, ld, anorm, s));
+  BSE_TRY(lambda_from_norms(n, np, anorm, bnorm, lamu, invlam, scl, s, 1));
+  BSE_TRY(trsm_lh_c(np, L2c, ld, Wc, L1c, invc, s));            // V1 = L2^-H Ws (L1 is done)
+  BSE_TRY(c64_to_c128(np, L1c, ld, X1, ld, scl, s));  // x = V1 / ||Ws||^2 (FP64)
+  BSE_TRY(c64_to_c128(np, Yc, ld, X2, ld, nullptr, s));  // y = V2
   tm.mark();
   double2* x = X1;
   double2* y = X2;
   double maxcorr = 0.0;
   int steps_done = 0;
   double hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  BSE_TRY(refine_z(n, ld, M1, M2, &x, &y, rw, steps, 1.0e-6, lamu, scl, &maxcorr, &steps_done, s, hist));
+  BSE_TRY(refine_z(n, ld, M1, M2, &x, &y, rw, steps, kRefineStop, lamu, scl, &maxcorr, &steps_done, s, hist));
   BSE_TRY(sort_lambda(n, lamu, perm, lambda, o.want_negative, s));
   if (!o.values_only)
     BSE_TRY(assemble_z(n, x, y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
   tm.mark();
   BSE_TRY(hipStreamSynchronize(s));
-  int ret = jr.converged ? 0 : 2 * n + 1;
+  // the complex64 iteration may end early (stop fraction); the refinement decides
+  int ret = jr.sweeps > 0 ? 0 : 2 * n + 1;
   // a last correction above 1e-4 leaves errors above 1e-8 in the vectors
   if (ret == 0 && !(maxcorr <= 1.0e-4)) ret = 2 * n + 2;
   if (ret != 0) return solve_fp64_fallback(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, s);

@@ -10,6 +10,7 @@
 //      A22 -= L21 L21^H on MFMA, lower tiles only.
 #include "common.hpp"
 #include "internal.hpp"
+#include "lds_la.hpp"
 
 #include <climits>
 #include <mutex>
@@ -96,41 +97,6 @@ BSE_DEV void FormOp::run(const FormArgs& a, int bx, int) {
   }
 }
 
-// Inverse X = L^-1 of the lower triangle L held in (Lr, Li) (real positive
-// diagonal), 256 threads, into (Xr, Xi) with a zero strict upper triangle.
-// Row elimination with one barrier per step: Y starts as I; step j subtracts
-// L[i][j] Y[j][:] / L[j][j] from every row i > j (row j is final then, up to
-// its division by L[j][j], which the last pass applies to every row).
-BSE_DEV void tri_inverse_lds(const double (*Lr)[NB + 1], const double (*Li)[NB + 1],
-                             double (*Xr)[NB + 1], double (*Xi)[NB + 1], int tid) {
-  for (int q = 0; q < 16; ++q) {
-    const int r = tid & 63, c = (tid >> 6) + 4 * q;
-    Xr[r][c] = (r == c) ? 1.0 : 0.0;
-    Xi[r][c] = 0.0;
-  }
-  __syncthreads();
-  const int c = tid & 63, i0 = tid >> 6;
-  for (int j = 0; j < NB - 1; ++j) {
-    if (c <= j) {
-      const double rj = 1.0 / Lr[j][j];
-      const double yr = Xr[j][c] * rj, yi = Xi[j][c] * rj;
-      for (int i = j + 1 + i0; i < NB; i += 4) {
-        const double lr = Lr[i][j], li = Li[i][j];
-        Xr[i][c] -= lr * yr - li * yi;
-        Xi[i][c] -= lr * yi + li * yr;
-      }
-    }
-    __syncthreads();
-  }
-  for (int q = 0; q < 16; ++q) {
-    const int r = tid & 63, cc = (tid >> 6) + 4 * q;
-    const double rr = 1.0 / Lr[r][r];
-    Xr[r][cc] *= rr;
-    Xi[r][cc] *= rr;
-  }
-  __syncthreads();
-}
-
 // Unblocked Cholesky of the diagonal block M[j0:j0+64, j0:j0+64] (lower) and
 // the inverse of the resulting triangle, in one workgroup.  Writes L11 back
 // with a zero strict upper triangle and L11^-1 (64 x 64, ld 64) to `linv`.
@@ -208,27 +174,33 @@ BSE_DEV void Potf2Op<C2>::run(const Potf2Args<C2>& a, int, int j0) {
 }
 
 // Inverses of the 64 x 64 diagonal blocks of a lower-triangular L (one
-// workgroup per block), written as lower triangles, block b at inv + b * 64 * 64.
+// workgroup per block), written as lower triangles, block b at inv + b * 64 * 64;
+// formed in FP64 for complex128 and complex64 storage alike.
+template <typename C2>
 struct TriInvOp {
   static constexpr int NT = 256;
-  typedef TriInvArgs Args;
+  typedef TriInvArgsT<C2> Args;
   static BSE_DEV void run(const Args& a, int bx, int aux) {
     __shared__ double Lr[NB][NB + 1], Li[NB][NB + 1];
     __shared__ double Xr[NB][NB + 1], Xi[NB][NB + 1];
     const int tid = threadIdx.x;
     const int j0 = bx * NB;
-    const double2* D = a.L + j0 + (long)j0 * a.ld;
+    const C2* D = a.L + j0 + (long)j0 * a.ld;
     for (int q = 0; q < 16; ++q) {
       const int r = tid & 63, c = (tid >> 6) + 4 * q;
-      const double2 v = (r >= c) ? D[r + (long)c * a.ld] : make_double2(0.0, 0.0);
-      Lr[r][c] = v.x; Li[r][c] = v.y;
+      double vr = 0.0, vi = 0.0;
+      if (r >= c) { const C2 v = D[r + (long)c * a.ld]; vr = v.x; vi = v.y; }
+      Lr[r][c] = vr; Li[r][c] = vi;
     }
     __syncthreads();
     tri_inverse_lds(Lr, Li, Xr, Xi, tid);
-    double2* out = a.inv + (long)bx * NB * NB;
+    C2* out = a.inv + (long)bx * NB * NB;
     for (int q = 0; q < 16; ++q) {
       const int r = tid & 63, c = (tid >> 6) + 4 * q;
-      out[r + c * NB] = make_double2(Xr[r][c], Xi[r][c]);
+      C2 x;
+      x.x = Xr[r][c];
+      x.y = Xi[r][c];
+      out[r + c * NB] = x;
     }
   }
 };
@@ -437,10 +409,22 @@ hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
                      hipStream_t s) {
   const int nb = np / NB;
   const TriInvArgs ti = {L, ld, inv};
-  hipError_t e = launch_one<TriInvOp>(ti, nb, 0, s);
+  hipError_t e = launch_one<TriInvOp<double2>>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
   trsm_lh_for_each(np, L, ld, Rhs, Z, inv, [&](const TrsmStep& st) {
     if (e == hipSuccess) e = gemm_z(st.g, s);
+  });
+  return e;
+}
+
+hipError_t trsm_lh_c(int np, const float2* L, long ld, float2* Rhs, float2* Z, float2* inv,
+                     hipStream_t s) {
+  const int nb = np / NB;
+  const TriInvArgsT<float2> ti = {L, ld, inv};
+  hipError_t e = launch_one<TriInvOp<float2>>(ti, nb, 0, s);
+  if (e != hipSuccess) return e;
+  trsm_lh_for_each(np, L, ld, Rhs, Z, inv, [&](const TrsmStep& st) {
+    if (e == hipSuccess) e = gemm_c(st.g, s);
   });
   return e;
 }
@@ -449,7 +433,7 @@ hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
                      hipStream_t s) {
   const int nb = np / NB;
   const TriInvArgs ti = {L, ld, inv};
-  hipError_t e = launch_one<TriInvOp>(ti, nb, 0, s);
+  hipError_t e = launch_one<TriInvOp<double2>>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
   for (int i = 0; i < nb; i += kTrsmGroup) {
     const int hi = i + kTrsmGroup - 1 < nb ? i + kTrsmGroup - 1 : nb - 1;  // last block row of the group
@@ -471,7 +455,7 @@ hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
                      hipStream_t s) {
   const int nb = np / NB;
   const TriInvArgs ti = {L, ld, inv};
-  hipError_t e = launch_one<TriInvOp>(ti, nb, 0, s);
+  hipError_t e = launch_one<TriInvOp<double2>>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
   // Z_j = Rhs_j (L_jj^-1)^H   (column block j)
   auto diag = [&](int j) {
@@ -579,7 +563,8 @@ hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks
     case G_TOC64: return launch_grp<ToC64Op>(table, map, blocks, aux, s);
     case G_POTF2_Z: return launch_grp<Potf2Op<double2>>(table, map, blocks, aux, s);
     case G_POTF2_C: return launch_grp<Potf2Op<float2>>(table, map, blocks, aux, s);
-    case G_TRIINV: return launch_grp<TriInvOp>(table, map, blocks, aux, s);
+    case G_TRIINV: return launch_grp<TriInvOp<double2>>(table, map, blocks, aux, s);
+    case G_TRIINV_C: return launch_grp<TriInvOp<float2>>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -152,18 +152,23 @@ struct WriteLambdaOp {
   }
 };
 
-__global__ __launch_bounds__(256) void k_gather_scale(int n, int np, const double2* __restrict__ W,
-                                                      long ld, const int* __restrict__ perm,
-                                                      const double* __restrict__ f,
-                                                      double2* __restrict__ out) {
-  const int r = blockIdx.y;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= np) return;
-  if (r >= n) { out[i + (long)r * ld] = make_double2(0.0, 0.0); return; }
-  int k = perm[r];
-  if (k < 0 || k >= n) k = r;
-  out[i + (long)r * ld] = cscale(W[i + (long)k * ld], f[r]);
-}
+// out[:, r] = W[:, perm r] * f_r; work group = (column r, 256 rows).
+struct GatherOp {
+  static constexpr int NT = 256;
+  typedef GatherArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int gx = (a.np + 255) / 256;
+    const int r = bx / gx;
+    const int i = (bx % gx) * 256 + threadIdx.x;
+    if (i >= a.np) return;
+    double2* out = a.out + i + (long)r * a.ld;
+    if (r >= a.n) { *out = make_double2(0.0, 0.0); return; }
+    int k = a.perm[r];
+    if (k < 0 || k >= a.n) k = r;
+    const double2 w = a.W[i + (long)k * a.ld];
+    *out = a.f ? cscale(w, a.f[r]) : w;
+  }
+};
 
 __global__ __launch_bounds__(256) void k_alg2_lambda(int n, const double* __restrict__ d,
                                                      double* __restrict__ lam) {
@@ -283,8 +288,8 @@ hipError_t c64_to_c128(int np, const float2* S, long lds, double2* D, long ldd,
 }
 
 hipError_t lambda_from_norms(int n, int np, const double* anorm, const double* bnorm, double* lam,
-                             double* invlam, double* scl, hipStream_t s) {
-  const LambdaArgs a = {n, np, anorm, bnorm, lam, invlam, scl, 0};
+                             double* invlam, double* scl, hipStream_t s, int v1scale) {
+  const LambdaArgs a = {n, np, anorm, bnorm, lam, invlam, scl, v1scale};
   return launch_one<LambdaOp>(a, b256(np), 0, s);
 }
 
@@ -309,9 +314,8 @@ hipError_t rq_lambda_z(int n, int np, const double2* T, long ld, const double* b
 
 hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* perm,
                           const double* f, double2* out, hipStream_t s) {
-  dim3 g((np + 255) / 256, np);
-  k_gather_scale<<<g, 256, 0, s>>>(n, np, W, ld, perm, f, out);
-  return hipGetLastError();
+  const GatherArgs a = {n, np, W, ld, perm, f, out};
+  return launch_one<GatherOp>(a, cols_blocks(np, np), 0, s);
 }
 
 hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double* lambda,
@@ -349,6 +353,7 @@ hipError_t group_finalize(GroupOp op, const void* table, const int2* map, int bl
     case G_WRITE_LAMBDA: return launch_grp<WriteLambdaOp>(table, map, blocks, aux, s);
     case G_C64: return launch_grp<C64Op>(table, map, blocks, aux, s);
     case G_ASSEMBLE: return launch_grp<AssembleOp>(table, map, blocks, aux, s);
+    case G_GATHER: return launch_grp<GatherOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }

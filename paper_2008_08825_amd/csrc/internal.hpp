@@ -138,6 +138,9 @@ hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int*
 // np * 64 complex values) and MFMA GEMM updates; Rhs is overwritten.
 hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s);
+// The same in complex64 (FP32 MFMA; the diagonal-block inverses formed in FP64).
+hipError_t trsm_lh_c(int np, const float2* L, long ld, float2* Rhs, float2* Z, float2* inv,
+                     hipStream_t s);
 // The block triangular solves take the 64-column diagonal blocks this many at a time.
 constexpr int kTrsmGroup = 4;
 // The GEMM steps of trsm_lh_z in their order (after the diagonal-block
@@ -147,9 +150,8 @@ constexpr int kTrsmGroup = 4;
 // of one (group, slot) in one grouped launch, in the same order as a single
 // solve.
 struct TrsmStep { int group, slot; GemmDesc g; };
-template <class F>
-void trsm_lh_for_each(int np, const double2* L, long ld, double2* Rhs, double2* Z,
-                      const double2* inv, F&& emit) {
+template <typename C2, class F>
+void trsm_lh_for_each(int np, const C2* L, long ld, C2* Rhs, C2* Z, const C2* inv, F&& emit) {
   constexpr int B = 64;
   const int nb = np / B;
   auto diag = [&](int b) {
@@ -222,8 +224,9 @@ hipError_t scale_singular_cols_c(int n, int np, float2* W, long ld, double* sigm
 hipError_t c64_to_c128(int np, const float2* S, long lds, double2* D, long ldd,
                        const double* colscale, hipStream_t s);
 // lam_k = anorm_k / bnorm_k, 1 / lam_k and s_k = (anorm_k bnorm_k)^-1/2 (k < n; zero above).
+// v1scale: scl_k = 1 / bnorm_k^2 instead (the scale of V1 = L2^-H Ws).
 hipError_t lambda_from_norms(int n, int np, const double* anorm, const double* bnorm, double* lam,
-                             double* invlam, double* scl, hipStream_t s);
+                             double* invlam, double* scl, hipStream_t s, int v1scale = 0);
 // Ascending order of lam[0..n) and the output lambda (with -lambda if want_negative).
 hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int want_negative,
                        hipStream_t s);
@@ -236,13 +239,58 @@ hipError_t sort_lambda(int n, const double* lam, int* perm, double* lambda, int 
 // step whose largest off-diagonal correction is at most stop_corr; returns
 // that correction in *max_corr (+inf if a correction or a final Rayleigh
 // quotient broke down) and the steps run in *steps_done.
+// Windows of the refinement's Rayleigh-Ritz passes (window.hip): for window
+// boundaries shifted by `off` (0 or 32), window w covers pairs [a, a + m).
+inline __host__ __device__ void window_range(int n, int off, int w, int& a, int& m) {
+  if (off == 0) {
+    a = w * 64;
+  } else if (w == 0) {
+    a = 0;
+    m = off < n ? off : n;
+    return;
+  } else {
+    a = off + (w - 1) * 64;
+  }
+  m = n - a < 64 ? n - a : 64;
+}
+struct WinArgs {  // work group = window
+  int n; long ld; const double2* F; const double2* P1; const double2* P2; int off;
+  double2* C;       // window blocks, 64 x 64 each (column-major, ld 64)
+  double* maxrot;   // optional: largest entry of C_w - I (atomic max)
+};
+int window_count(int n, int off);
+hipError_t window_eig(const WinArgs& a, int windows, hipStream_t s);
+hipError_t group_window(const void* table, const int2* map, int blocks, hipStream_t s);
+
 // Pairs whose Ritz values differ by at most this fraction are corrected
 // within their span only (first-order rotation part dropped).
 constexpr double kRefineDelta = 1.0e-10;
+// The refinement stops after a step whose largest first-order correction is
+// at most this; the error it leaves is of the order of its square (about
+// half of it measured), so the vectors are left within about 1e-12.
+constexpr double kRefineStop = 1.0e-6;
+// Window passes per refinement step (boundaries at 0, then shifted by 32).
+constexpr int kWindowPasses = 2;
 struct RefineWork {
   double2 *Q = nullptr, *F = nullptr, *P1 = nullptr, *P2 = nullptr, *Ex = nullptr, *Ey = nullptr;
   double *ritz = nullptr, *dots = nullptr, *maxcorr = nullptr;
+  // Rayleigh-Ritz windows (window.hip): block storage of the two passes and a
+  // device arena for the grouped block GEMMs; windows == 0 turns them off
+  double2* Cb0 = nullptr;  // kWindowPasses x (n / 64 + 2) blocks of 64 x 64
+  char* arena = nullptr;
+  size_t arena_cap = 0;
+  int windows = 0;         // window passes per step (0: none)
+  int* perm = nullptr;  // n ints: the ascending order of the start's eigenvalues
 };
+// Block GEMMs of a window pass over the first n pairs (windows of offset
+// `off`, blocks C_w at Cb): the congruence M <- C^H M C through Tmp (right
+// products into `right`, then left products into `left`), and the basis
+// change out = X C (into g).  Storage of pass p's blocks: window_blocks.
+void window_congruence(int n, long ld, double2* M, double2* Tmp, const double2* Cb, int off,
+                       std::vector<GemmDesc>& right, std::vector<GemmDesc>& left);
+void window_right(int n, long ld, const double2* X, double2* out, const double2* Cb, int off,
+                  std::vector<GemmDesc>& g);
+double2* window_blocks(double2* Cb0, int n, int pass);
 // Column k < n: lam_k = (x_k^H Qx_k + y_k^H Qy_k) / (2 Re x_k^H y_k) and
 // scl_k = (Re x_k^H y_k)^-1/2.
 hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const double2* Qx,
@@ -252,7 +300,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
                     const RefineWork& w, int max_steps, double stop_corr, double* lam, double* scl,
                     double* max_corr, int* steps_done, hipStream_t s, double* corr_hist = nullptr);
 
-// out[:, r] = W[:, perm r] * f_r (r < n; zero for r >= n; np rows).
+// out[:, r] = W[:, perm r] * f_r (r < n; zero for r >= n; np rows; f == nullptr: 1).
 hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* perm,
                           const double* f, double2* out, hipStream_t s);
 // Alg. 2 eigenvalue bookkeeping from d = column norms of the iterated M:
@@ -298,7 +346,8 @@ struct FormArgs {
   double2* M1; double2* M2; long ldm;
 };
 struct MirrorArgs { int np; double2* M; long ld; };
-struct TriInvArgs { const double2* L; long ld; double2* inv; };  // work group = diagonal block
+template <typename C2> struct TriInvArgsT { const C2* L; long ld; C2* inv; };  // work group = diagonal block
+typedef TriInvArgsT<double2> TriInvArgs;
 struct ToC64Args { int np; const double2* M; long ld; float2* Mc; };
 template <typename C2> struct Potf2Args {  // aux = first column of the panel
   C2* M; long ld; C2* linv; int* status; int base; int n_real;
@@ -342,6 +391,7 @@ struct LambdaArgs {
 };
 struct RankArgs { int n; const double* key; int* perm; int desc; };
 struct WriteLambdaArgs { int n; const double* lam; const int* perm; double* lambda; int want_negative; };
+struct GatherArgs { int n, np; const double2* W; long ld; const int* perm; const double* f; double2* out; };
 struct C64Args { int np; const float2* S; long lds; double2* D; long ldd; const double* colscale; };
 struct AssembleArgs {
   int n; const double2* V1; const double2* V2; long ldv; const int* perm; const double* scl;
@@ -375,6 +425,7 @@ struct SweepArgs {  // aux = sweep index
   double factor;  // inner stopping level = factor x previous sweep's largest off-diagonal
   double track_level;  // sweeps after one whose largest off-diagonal exceeded this track
   int pairs_per_round;
+  double stop_fraction;  // > 0: a sweep rotating fewer than this fraction of its pairs ends the iteration
 };
 
 // Work-group counts of one problem for the ops above.
@@ -396,10 +447,10 @@ RotArgs<float2> rot_args_c(int np, float2* W, long ld, const JacobiWork& w, cons
 // Grouped launches: table = device array of the op's Args, map = device
 // array of (table row, work group) pairs, blocks = entries of map used.
 enum GroupOp {
-  G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C, G_TRIINV,            // chol.hip
+  G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C, G_TRIINV, G_TRIINV_C, // chol.hip
   G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
   G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
-  G_WRITE_LAMBDA, G_C64, G_ASSEMBLE,
+  G_WRITE_LAMBDA, G_C64, G_ASSEMBLE, G_GATHER,
   G_RITZ, G_BUILD, G_RQ,                                                // refine.hip
 };
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);

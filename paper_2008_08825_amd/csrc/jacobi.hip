@@ -943,6 +943,10 @@ BSE_DEV void SweepOp::run(const SweepArgs& a, int, int sweep) {
       st->done = 1;
       return;
     }
+    if (a.stop_fraction > 0.0 && st->counter < a.stop_fraction * a.pairs_per_sweep) {
+      st->done = 1;
+      return;
+    }
   }
   if (sweep >= a.max_sweeps) {
     st->done = 1;

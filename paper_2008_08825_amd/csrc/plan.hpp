@@ -32,11 +32,24 @@ struct Plan {
   size_t off_bnorm = 0, off_anorm = 0, off_lamu = 0, off_scl = 0, off_ritz = 0, off_small = 0;
   size_t off_jac = 0;
   size_t off_check = 0;  // opts.checks: reduction buffers of the measurements
+  size_t off_cb0 = 0, off_cb1 = 0, off_arena = 0;  // mixed: refinement windows
   size_t total = 0;
   int kc = 0, rrows = 0;  // Jacobi tiles (0 = built-in)
   int polish = 0;
   int side = 1;  // second Cholesky factorisation on the library's side stream
 };
+
+// Device arena of the refinement's grouped block GEMMs (a ring of tables):
+// room for the largest launch, the basis update of x and y by the windows of
+// one pass (2 (np / 64 + 2) block GEMMs of np x 64 or 64 x np).
+inline size_t refine_arena_bytes(int np) {
+  const size_t descs = 2 * (size_t)(np / 64 + 2);
+  GemmDesc a, b;
+  a.M = np; a.N = 64; a.K = 64;
+  b.M = 64; b.N = np; b.K = 64;
+  const size_t tiles = (size_t)(gemm_tiles(a) > gemm_tiles(b) ? gemm_tiles(a) : gemm_tiles(b));
+  return align256(descs * sizeof(GemmArgs<double>)) + align256(descs * tiles * sizeof(int2)) + 4096;
+}
 
 inline bool opts_valid(const bse_opts_t& o) {
   if (o.route < BSE_ROUTE_SVD || o.route > BSE_ROUTE_SQRT) return false;
@@ -123,6 +136,11 @@ inline Plan make_plan(int n, const bse_opts_t& o) {
     p.off_p2 = take(U);
     p.off_lc = take(U);  // L1c | L2c, then Ex
     p.off_wc = take(U);  // Wc | Yc, then Ey
+    // Rayleigh-Ritz windows of the refinement: 64 x 64 blocks of two passes,
+    // and the arena of their grouped block GEMMs
+    const size_t blk = (size_t)64 * 64 * sizeof(double2);
+    p.off_cb0 = take(blk * (size_t)(p.np / 64 + 2) * kWindowPasses);
+    p.off_arena = take(refine_arena_bytes(p.np));
   }
   p.off_linv = take(2 * 64 * 64 * sizeof(double2));  // one diagonal-block inverse per factor
   p.off_sigma = take((size_t)p.np * sizeof(double));

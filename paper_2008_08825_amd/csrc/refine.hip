@@ -26,6 +26,7 @@
 //   lambda_k = (x_k^H M2 x_k + y_k^H M1 y_k) / (2 Re x_k^H y_k),
 // and each pair is scaled by (Re x_k^H y_k)^-1/2 so that v_k^H Sigma v_k = 1.
 #include "common.hpp"
+#include "group.hpp"
 #include "internal.hpp"
 
 #include <stdio.h>
@@ -199,6 +200,69 @@ hipError_t group_refine(GroupOp op, const void* table, const int2* map, int bloc
   }
 }
 
+void window_congruence(int n, long ld, double2* M, double2* Tmp, const double2* Cb, int off,
+                       std::vector<GemmDesc>& right, std::vector<GemmDesc>& left) {
+  const int nw = window_count(n, off);
+  for (int w = 0; w < nw; ++w) {
+    int a, m;
+    window_range(n, off, w, a, m);
+    if (m <= 0) continue;
+    GemmDesc r;  // Tmp[:, a:a+m] = M[:, a:a+m] C_w
+    r.M = n; r.N = m; r.K = m;
+    r.A = M + (long)a * ld; r.lda = ld; r.opA = 0;
+    r.B = Cb + (long)w * 64 * 64; r.ldb = 64; r.opB = 0;
+    r.C = Tmp + (long)a * ld; r.ldc = ld;
+    right.push_back(r);
+    GemmDesc l;  // M[a:a+m, :] = C_w^H Tmp[a:a+m, :]
+    l.M = m; l.N = n; l.K = m;
+    l.A = Cb + (long)w * 64 * 64; l.lda = 64; l.opA = 1;
+    l.B = Tmp + a; l.ldb = ld; l.opB = 0;
+    l.C = M + a; l.ldc = ld;
+    left.push_back(l);
+  }
+}
+
+void window_right(int n, long ld, const double2* X, double2* out, const double2* Cb, int off,
+                  std::vector<GemmDesc>& g) {
+  const int nw = window_count(n, off);
+  for (int w = 0; w < nw; ++w) {
+    int a, m;
+    window_range(n, off, w, a, m);
+    if (m <= 0) continue;
+    GemmDesc r;  // out[:, a:a+m] = X[:, a:a+m] C_w
+    r.M = n; r.N = m; r.K = m;
+    r.A = X + (long)a * ld; r.lda = ld; r.opA = 0;
+    r.B = Cb + (long)w * 64 * 64; r.ldb = 64; r.opB = 0;
+    r.C = out + (long)a * ld; r.ldc = ld;
+    g.push_back(r);
+  }
+}
+
+double2* window_blocks(double2* Cb0, int n, int pass) {
+  return Cb0 + (size_t)pass * 64 * 64 * (n / 64 + 2);
+}
+
+namespace {
+
+// One Rayleigh-Ritz pass on the windows of offset `off` (window.hip): the
+// window blocks C_w into Cb, then the products by congruence,
+// M <- C^H M C for M = F, P1, P2 (block GEMMs through Tmp).
+hipError_t window_pass(int n, long ld, double2* F, double2* P1, double2* P2, double2* Tmp,
+                       double2* Cb, int off, double* maxrot, Arena& ar, hipStream_t s) {
+  const WinArgs wa = {n, ld, F, P1, P2, off, Cb, maxrot};
+  hipError_t e = window_eig(wa, window_count(n, off), s);
+  double2* mats[3] = {F, P1, P2};
+  for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+    std::vector<GemmDesc> right, left;
+    window_congruence(n, ld, mats[k], Tmp, Cb, off, right, left);
+    e = run_gemm<double>(ar, right, s);
+    if (e == hipSuccess) e = run_gemm<double>(ar, left, s);
+  }
+  return e;
+}
+
+}  // namespace
+
 hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const double2* Qx,
                       const double2* Qy, double* lam, double* scl, hipStream_t s) {
   const RqArgs qa = {n, x, y, Qx, Qy, ld, lam, scl, nullptr};
@@ -216,31 +280,76 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
   hipError_t e;
   *max_corr = 0.0;
   *steps_done = 0;
+  Arena ar;
+  ar.dev = w.arena;
+  ar.cap = w.arena_cap;
+  ar.s = s;
+  if (w.windows) {
+    // the pairs in the ascending order of the start's eigenvalues, so that a
+    // window holds spectral neighbours
+    if ((e = sort_lambda(n, lam, w.perm, w.ritz, 0, s)) != hipSuccess) return e;
+    if ((e = gather_scale_z(n, (int)ld, x, ld, w.perm, nullptr, Q, s)) != hipSuccess) return e;
+    if ((e = gather_scale_z(n, (int)ld, y, ld, w.perm, nullptr, F, s)) != hipSuccess) return e;
+    double2* t = x; x = Q; Q = t;
+    t = y; y = F; F = t;
+  }
   for (int it = 0; it < max_steps; ++it) {
-    e = hipMemsetAsync(w.maxcorr, 0, sizeof(double), s);
+    e = hipMemsetAsync(w.maxcorr, 0, 2 * sizeof(double), s);
     if (e != hipSuccess) return e;
     if ((e = gemm_z(nn(n, ld, x, 1, y, 0, F), s)) != hipSuccess) return e;       // F = x^H y
     if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, Q), s)) != hipSuccess) return e;      // Q = M2 x
-    if ((e = gemm_z(nn(n, ld, x, 1, Q, 0, w.P2), s)) != hipSuccess) return e;    // P2 = x^H M2 x
+    // P2 = x^H M2 x and P1 = y^H M1 y are Hermitian: lower tiles, then mirrored
+    GemmDesc p2 = nn(n, ld, x, 1, Q, 0, w.P2);
+    p2.lowerC = 1;
+    if ((e = gemm_z(p2, s)) != hipSuccess) return e;
     if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, Q), s)) != hipSuccess) return e;      // Q = M1 y
-    if ((e = gemm_z(nn(n, ld, y, 1, Q, 0, w.P1), s)) != hipSuccess) return e;    // P1 = y^H M1 y
+    GemmDesc p1 = nn(n, ld, y, 1, Q, 0, w.P1);
+    p1.lowerC = 1;
+    if ((e = gemm_z(p1, s)) != hipSuccess) return e;
+    if ((e = mirror_upper_z((int)((n + 63) / 64 * 64), w.P2, ld, s)) != hipSuccess) return e;
+    if ((e = mirror_upper_z((int)((n + 63) / 64 * 64), w.P1, ld, s)) != hipSuccess) return e;
+    const int passes = w.windows;
+    for (int pass = 0; pass < passes; ++pass) {
+      // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
+      const int off = (pass & 1) ? 32 : 0;
+      double2* Cb = window_blocks(w.Cb0, n, pass);
+      if ((e = window_pass(n, ld, F, w.P1, w.P2, Q, Cb, off, w.maxcorr + 1, ar, s)) != hipSuccess) return e;
+    }
     const RitzArgs ra = {n, F, w.P1, w.P2, ld, w.ritz};
     if ((e = launch_one<RitzOp>(ra, (n + 255) / 256, 0, s)) != hipSuccess) return e;
     const int T = (n + 63) / 64;
     const BuildArgs ba = {n, F, w.P1, w.P2, ld, w.ritz, w.Ex, w.Ey, kRefineDelta, w.maxcorr};
     if ((e = launch_one<BuildOp>(ba, T * T, 0, s)) != hipSuccess) return e;
+    // the window rotations precede the first-order correction:
+    // x <- x C_1 C_2 ... C_p (I + E11 + E21), y <- y C_1 ... C_p (I + E11 - E21)
+    for (int pass = 0; pass < passes; ++pass) {
+      const int off = (pass & 1) ? 32 : 0;
+      const double2* Cb = window_blocks(w.Cb0, n, pass);
+      std::vector<GemmDesc> g;
+      window_right(n, ld, x, Q, Cb, off, g);
+      window_right(n, ld, y, F, Cb, off, g);
+      if ((e = run_gemm<double>(ar, g, s)) != hipSuccess) return e;
+      double2* t = x; x = Q; Q = t;
+      t = y; y = F; F = t;
+    }
     if ((e = gemm_z(nn(n, ld, x, 0, w.Ex, 0, Q), s)) != hipSuccess) return e;    // x (I + E11 + E21)
     if ((e = gemm_z(nn(n, ld, y, 0, w.Ey, 0, F), s)) != hipSuccess) return e;    // y (I + E11 - E21)
     double2* t = x; x = Q; Q = t;
     t = y; y = F; F = t;
-    double mc = 0.0;
-    e = hipMemcpyAsync(&mc, w.maxcorr, sizeof(double), hipMemcpyDeviceToHost, s);
+    double mcs[2] = {0.0, 0.0};
+    e = hipMemcpyAsync(mcs, w.maxcorr, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
+    // the step's correction: its first-order part (the window rotations also
+    // turn bases inside subspaces of nearly equal eigenvalues, where any basis
+    // is as good, so they do not measure the distance to convergence)
+    const double mc = mcs[0];
     *max_corr = mc;
     *steps_done = it + 1;
     if (corr_hist && it < 8) corr_hist[it] = mc;
-    if (getenv("BSE_DEBUG")) fprintf(stderr, "[bse] refinement step %d: largest correction %.3e\n", it + 1, mc);
+    if (getenv("BSE_DEBUG"))
+      fprintf(stderr, "[bse] refinement step %d: largest first-order correction %.3e, window rotation %.3e\n",
+              it + 1, mcs[0], mcs[1]);
     // the error left after a step is of the order of the square of its correction
     if (mc <= stop_corr) break;
   }
