@@ -91,7 +91,7 @@ struct Prob {
   int status = 0;
   // mixed refinement state
   double2 *x = nullptr, *y = nullptr, *q = nullptr, *f = nullptr;
-  int rsteps = 0, rdone = 0;
+  int rsteps = 0, rdone = 0, rbad = 0;
   double rcorr = 0.0;
   double rhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -138,7 +138,7 @@ Header make_header(int batch, const std::vector<int>& nps) {
   };
   h.off_status = take((size_t)batch * sizeof(int));
   h.off_state = take((size_t)batch * sizeof(JacState));
-  h.off_corr = take((size_t)batch * sizeof(double));
+  h.off_corr = take((size_t)2 * batch * sizeof(double));  // correction, then breakdown flag
   h.off_active = take(256);
   h.arena = arena_bytes(nps);
   h.off_arena = take(h.arena);
@@ -582,11 +582,12 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         for (Prob* pr : ok)
           if (!pr->rdone) act.push_back(pr);
         if (act.empty()) break;
-        BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
+        BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)2 * batch * sizeof(double), s));
         std::vector<GemmDesc> g00, g10, upd;
         Grp<MirrorArgs> mi;
         Grp<RitzArgs> rt;
         Grp<BuildArgs> bd;
+        Grp<UpdRqArgs> ur;
         for (Prob* pr : act) {
           const int nn = pr->n;
           const long ld = pr->np;
@@ -618,7 +619,11 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           mi.add({(int)ld, P1, ld}, tiles64((int)ld));
           rt.add({nn, pr->f, P1, P2, ld, ritz}, (nn + 255) / 256);
           const int T = (nn + 63) / 64;
-          bd.add({nn, pr->f, P1, P2, ld, ritz, Ex, Ey, kRefineDelta, d_corr + pr->idx}, T * T);
+          // q is free until the basis update: it takes the tile sums of the quotients
+          double* part = reinterpret_cast<double*>(pr->q);
+          bd.add({nn, pr->f, P1, P2, ld, ritz, Ex, Ey, kRefineDelta, d_corr + pr->idx, part}, T * T);
+          ur.add({nn, ld, pr->f, P1, P2, part, pr->at<double>(pr->p.off_lamu), pr->at<double>(pr->p.off_scl),
+                  d_corr + batch + pr->idx}, (nn + 255) / 256);
         }
         BSE_TRY(run_gemm<double>(ar, g00, s));
         BSE_TRY(run_gemm<double>(ar, g10, s));
@@ -649,6 +654,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         }
         BSE_TRY(run_op(ar, rt, group_refine, G_RITZ, 0, s));
         BSE_TRY(run_op(ar, bd, group_refine, G_BUILD, 0, s));
+        BSE_TRY(run_op(ar, ur, group_refine, G_UPDRQ, 0, s));
         // x <- x C_1 C_2 (I + E11 + E21), y <- y C_1 C_2 (I + E11 - E21)
         for (int pass = 0; pass < passes; ++pass) {
           const int off = (pass & 1) ? 32 : 0;
@@ -677,8 +683,8 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           upd.push_back(d);                                  // y (I + E11 - E21)
         }
         BSE_TRY(run_gemm<double>(ar, upd, s));
-        std::vector<double> corr(batch, 0.0);
-        BSE_TRY(hipMemcpyAsync(corr.data(), d_corr, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
+        std::vector<double> corr(2 * batch, 0.0);
+        BSE_TRY(hipMemcpyAsync(corr.data(), d_corr, (size_t)2 * batch * sizeof(double), hipMemcpyDeviceToHost, s));
         BSE_TRY(hipStreamSynchronize(s));
         for (Prob* pr : act) {
           std::swap(pr->x, pr->q);
@@ -686,52 +692,29 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           if (pr->rsteps < 8) pr->rhist[pr->rsteps] = corr[pr->idx];
           pr->rsteps += 1;
           pr->rcorr = corr[pr->idx];
+          pr->rbad = corr[batch + pr->idx] != 0.0;
           // the error left after a step is of the order of the square of its correction
           if (pr->rcorr <= kRefineStop) pr->rdone = 1;
         }
       }
-      // Rayleigh quotients, Sigma-normalising scales, sort, final setup
-      std::vector<GemmDesc> g00;
-      Grp<RqArgs> rq;
+      // sort and final setup (the last step left the quotients and scales);
+      // a pair that broke down in the refinement fails the problem (it is then
+      // re-solved in FP64)
       Grp<RankArgs> rk;
       Grp<WriteLambdaArgs> wl;
       Grp<AssembleArgs> as;
       for (Prob* pr : ok) {
         const int nn = pr->n;
         const long ld = pr->np;
-        double2* P1 = pr->at<double2>(pr->p.off_p1);
-        double2* P2 = pr->at<double2>(pr->p.off_p2);
-        GemmDesc a;
-        a.M = nn; a.N = nn; a.K = nn;
-        a.A = pr->at<double2>(pr->p.off_m2); a.lda = ld;
-        a.B = pr->x; a.ldb = ld;
-        a.C = P2; a.ldc = ld;
-        g00.push_back(a);
-        GemmDesc b = a;
-        b.A = pr->at<double2>(pr->p.off_m1);
-        b.B = pr->y;
-        b.C = P1;
-        g00.push_back(b);
+        if (pr->rbad) pr->rcorr = __builtin_inf();
         double* lamu = pr->at<double>(pr->p.off_lamu);
         double* scl = pr->at<double>(pr->p.off_scl);
         int* perm = pr->at<int>(pr->p.off_perm);
-        rq.add({nn, pr->x, pr->y, P2, P1, ld, lamu, scl, d_corr + pr->idx}, nn);
         rk.add({nn, lamu, perm, 0}, (nn + 255) / 256);
         wl.add({nn, lamu, perm, pr->lambda, o.want_negative}, (nn + 255) / 256);
         if (!o.values_only)
           as.add({nn, pr->x, pr->y, ld, perm, scl, pr->X, pr->ldx, o.want_negative, nullptr},
                  cols_blocks(nn, nn));
-      }
-      BSE_TRY(run_gemm<double>(ar, g00, s));
-      BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
-      BSE_TRY(run_op(ar, rq, group_refine, G_RQ, 0, s));
-      {
-        // a pair that broke down in the refinement fails the problem (it is then re-solved in FP64)
-        std::vector<double> bad(batch, 0.0);
-        BSE_TRY(hipMemcpyAsync(bad.data(), d_corr, (size_t)batch * sizeof(double), hipMemcpyDeviceToHost, s));
-        BSE_TRY(hipStreamSynchronize(s));
-        for (Prob* pr : ok)
-          if (bad[pr->idx] != 0.0) pr->rcorr = __builtin_inf();
       }
       BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
       BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));

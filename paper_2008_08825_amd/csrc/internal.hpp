@@ -401,6 +401,14 @@ struct RitzArgs { int n; const double2* F; const double2* P1; const double2* P2;
 struct BuildArgs {
   int n; const double2* F; const double2* P1; const double2* P2; long ld; const double* ritz;
   double2* Ex; double2* Ey; double delta; double* maxcorr;
+  double* part;  // optional: per-tile column sums for the updated pairs' quotients (3 x T x n)
+};
+// Rayleigh quotients and Sigma-normalising scales of the pairs after the
+// correction, from the products and the tile sums of BuildOp (work group =
+// 256 columns): lam_k, scl_k as RqOp computes them for x Ex, y Ey.
+struct UpdRqArgs {
+  int n; long ld; const double2* F; const double2* P1; const double2* P2; const double* part;
+  double* lam; double* scl; double* bad;
 };
 // bad (optional): set to 1 if a pair is not Sigma-positive or its quotient
 // is not finite and positive.
@@ -451,7 +459,7 @@ enum GroupOp {
   G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
   G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
   G_WRITE_LAMBDA, G_C64, G_ASSEMBLE, G_GATHER,
-  G_RITZ, G_BUILD, G_RQ,                                                // refine.hip
+  G_RITZ, G_BUILD, G_RQ, G_UPDRQ,                                       // refine.hip
 };
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
 hipError_t group_jacobi(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);

@@ -25,6 +25,9 @@
 // The eigenvalues are then the Rayleigh quotients
 //   lambda_k = (x_k^H M2 x_k + y_k^H M1 y_k) / (2 Re x_k^H y_k),
 // and each pair is scaled by (Re x_k^H y_k)^-1/2 so that v_k^H Sigma v_k = 1.
+// The three quotient terms of the updated pairs follow from the step's
+// products and its correction to third order in the correction (BuildOp), so
+// the last step needs no further products with M1 and M2.
 #include "common.hpp"
 #include "group.hpp"
 #include "internal.hpp"
@@ -85,48 +88,86 @@ BSE_DEV void BuildOp::run(const BuildArgs& a, int bx, int) {
     ft[r][c] = (gi < n && gj < n) ? F[gi + (long)gj * ld] : make_double2(0.0, 0.0);
   }
   __syncthreads();
+  // with part: the updated pair x Ex, y Ey has, up to terms of third order in
+  // the correction (Ex = I + a, Ey = I + b, a and b small, the products
+  // nearly diagonal in the current basis),
+  //   Re (Ex^H F Ey)_kk  = Re F_kk + sum_i Re(conj(a_ik) F_ik + F_ki b_ik + conj(a_ik) F_ii b_ik),
+  //   (Ex^H P2 Ex)_kk    = P2_kk + sum_i (2 Re(conj(a_ik) P2_ik) + |a_ik|^2 P2_ii),
+  //   (Ey^H P1 Ey)_kk    = P1_kk + sum_i (2 Re(conj(b_ik) P1_ik) + |b_ik|^2 P1_ii);
+  // each work group writes the sums over its 64 rows i, column by column.
+  const int r = tid & 63, i = m0 + r;
+  double2 fii = make_double2(0.0, 0.0), p1ii = fii, p2ii = fii;
+  if (a.part && i < n) {
+    const long d = i + (long)i * ld;
+    fii = F[d];
+    p1ii = P1[d];
+    p2ii = P2[d];
+  }
   double mc = 0.0;
   for (int q = 0; q < 16; ++q) {
-    const int r = tid & 63, c = (tid >> 6) + 4 * q;
-    const int i = m0 + r, j = n0 + c;
-    if (i >= n || j >= n) continue;
-    const long o = i + (long)j * ld;
-    const double2 fij = F[o];
-    const double2 fji_c = cconj(ft[c][r]);  // conj(F[j][i])
-    const double2 p1 = P1[o], p2 = P2[o];
-    const double2 g11 = cscale(cadd(fij, fji_c), 0.5);
-    const double2 g21 = cscale(csub(fji_c, fij), 0.5);
-    const double2 t11 = cscale(cadd(p2, p1), 0.5);
-    const double2 t21 = cscale(csub(p1, p2), 0.5);
-    const double li = ritz[i], lj = ritz[j];
-    double2 e11;
-    if (i == j) {
-      e11 = make_double2(0.5 * (1.0 - g11.x), 0.0);
-    } else {
-      // E11_ij = R_ij / 2 + K_ij / (l_j - l_i) with K = T + (l_i + l_j) R / 2 is the
-      // first-order solution; its rotation part K / (l_j - l_i) = phase(K) / (2 zeta),
-      // zeta = (l_j - l_i) / (2 |K|), is replaced by the exact 2 x 2 Jacobi tangent
-      // phase(K) sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), equal to it for well
-      // separated pairs and bounded by 1 for close pairs, where the first-order
-      // term diverges.
-      const double2 r11 = make_double2(-g11.x, -g11.y);
-      const double dl = lj - li;
-      const double2 K = cadd(t11, cscale(r11, 0.5 * (li + lj)));
-      const double aK = sqrt(cabs2(K));
-      e11 = cscale(r11, 0.5);
-      if (aK > 0.0 && !(fabs(dl) <= delta * fmax(fabs(li), fabs(lj)) && aK <= delta * fabs(lj))) {
-        const double zeta = dl / (2.0 * aK);
-        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        e11 = cadd(e11, cscale(K, t / aK));
+    const int c = (tid >> 6) + 4 * q;
+    const int j = n0 + c;
+    double sf = 0.0, s2 = 0.0, s1 = 0.0;
+    if (i < n && j < n) {
+      const long o = i + (long)j * ld;
+      const double2 fij = F[o];
+      const double2 fji_c = cconj(ft[c][r]);  // conj(F[j][i])
+      const double2 p1 = P1[o], p2 = P2[o];
+      const double2 g11 = cscale(cadd(fij, fji_c), 0.5);
+      const double2 g21 = cscale(csub(fji_c, fij), 0.5);
+      const double2 t11 = cscale(cadd(p2, p1), 0.5);
+      const double2 t21 = cscale(csub(p1, p2), 0.5);
+      const double li = ritz[i], lj = ritz[j];
+      double2 e11;
+      if (i == j) {
+        e11 = make_double2(0.5 * (1.0 - g11.x), 0.0);
+      } else {
+        // E11_ij = R_ij / 2 + K_ij / (l_j - l_i) with K = T + (l_i + l_j) R / 2 is the
+        // first-order solution; its rotation part K / (l_j - l_i) = phase(K) / (2 zeta),
+        // zeta = (l_j - l_i) / (2 |K|), is replaced by the exact 2 x 2 Jacobi tangent
+        // phase(K) sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), equal to it for well
+        // separated pairs and bounded by 1 for close pairs, where the first-order
+        // term diverges.
+        const double2 r11 = make_double2(-g11.x, -g11.y);
+        const double dl = lj - li;
+        const double2 K = cadd(t11, cscale(r11, 0.5 * (li + lj)));
+        const double aK = sqrt(cabs2(K));
+        e11 = cscale(r11, 0.5);
+        if (aK > 0.0 && !(fabs(dl) <= delta * fmax(fabs(li), fabs(lj)) && aK <= delta * fabs(lj))) {
+          const double zeta = dl / (2.0 * aK);
+          const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          e11 = cadd(e11, cscale(K, t / aK));
+        }
+        mc = max_or_inf(mc, sqrt(cabs2(e11)));
       }
-      mc = max_or_inf(mc, sqrt(cabs2(e11)));
+      const double2 r21 = make_double2(-g21.x, -g21.y);
+      const double2 e21 = cscale(cadd(t21, cscale(r21, lj)), 1.0 / (lj + li));
+      mc = max_or_inf(mc, sqrt(cabs2(e21)));
+      const double dd = (i == j) ? 1.0 : 0.0;
+      const double2 ea = cadd(e11, e21);  // Ex - I
+      const double2 eb = csub(e11, e21);  // Ey - I
+      Ex[o] = make_double2(dd + ea.x, ea.y);
+      Ey[o] = make_double2(dd + eb.x, eb.y);
+      if (a.part) {
+        const double2 fji = cconj(fji_c);
+        const double2 fb = cmul(fii, eb);
+        sf = (ea.x * fij.x + ea.y * fij.y) + (fji.x * eb.x - fji.y * eb.y) + (ea.x * fb.x + ea.y * fb.y);
+        s2 = 2.0 * (ea.x * p2.x + ea.y * p2.y) + cabs2(ea) * p2ii.x;
+        s1 = 2.0 * (eb.x * p1.x + eb.y * p1.y) + cabs2(eb) * p1ii.x;
+      }
     }
-    const double2 r21 = make_double2(-g21.x, -g21.y);
-    const double2 e21 = cscale(cadd(t21, cscale(r21, lj)), 1.0 / (lj + li));
-    mc = max_or_inf(mc, sqrt(cabs2(e21)));
-    const double dd = (i == j) ? 1.0 : 0.0;
-    Ex[o] = make_double2(dd + e11.x + e21.x, e11.y + e21.y);
-    Ey[o] = make_double2(dd + e11.x - e21.x, e11.y - e21.y);
+    if (a.part) {  // the column's sums over the wave's 64 rows
+      for (int sh = 32; sh > 0; sh >>= 1) {
+        sf += __shfl_xor(sf, sh);
+        s2 += __shfl_xor(s2, sh);
+        s1 += __shfl_xor(s1, sh);
+      }
+      if (r == 0 && j < n) {
+        a.part[((long)0 * T + tm) * n + j] = sf;
+        a.part[((long)1 * T + tm) * n + j] = s2;
+        a.part[((long)2 * T + tm) * n + j] = s1;
+      }
+    }
   }
   red[tid] = mc;
   __syncthreads();
@@ -179,6 +220,27 @@ BSE_DEV void RqOp::run(const RqArgs& args, int bx, int) {
   }
 }
 
+struct UpdRqOp {
+  static constexpr int NT = 256;
+  typedef UpdRqArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int k = bx * 256 + threadIdx.x;
+    if (k >= a.n) return;
+    const int T = (a.n + 63) / 64;
+    const long d = k + (long)k * a.ld;
+    double f = a.F[d].x, p2 = a.P2[d].x, p1 = a.P1[d].x;
+    for (int t = 0; t < T; ++t) {  // fixed order: deterministic
+      f += a.part[((long)0 * T + t) * a.n + k];
+      p2 += a.part[((long)1 * T + t) * a.n + k];
+      p1 += a.part[((long)2 * T + t) * a.n + k];
+    }
+    const double l = (p2 + p1) / (2.0 * f);
+    a.lam[k] = l;
+    a.scl[k] = 1.0 / sqrt(f);
+    if (a.bad && !(f > 0.0 && l > 0.0 && l < 1.0e308)) atomic_max_nonneg(a.bad, 1.0);
+  }
+};
+
 GemmDesc nn(int n, long ld, const double2* A, int opA, const double2* B, int opB, double2* C) {
   GemmDesc g;
   g.M = n; g.N = n; g.K = n;
@@ -196,6 +258,7 @@ hipError_t group_refine(GroupOp op, const void* table, const int2* map, int bloc
     case G_RITZ: return launch_grp<RitzOp>(table, map, blocks, aux, s);
     case G_BUILD: return launch_grp<BuildOp>(table, map, blocks, aux, s);
     case G_RQ: return launch_grp<RqOp>(table, map, blocks, aux, s);
+    case G_UPDRQ: return launch_grp<UpdRqOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -293,8 +356,9 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     double2* t = x; x = Q; Q = t;
     t = y; y = F; F = t;
   }
+  double bad = 0.0;
   for (int it = 0; it < max_steps; ++it) {
-    e = hipMemsetAsync(w.maxcorr, 0, 2 * sizeof(double), s);
+    e = hipMemsetAsync(w.maxcorr, 0, 3 * sizeof(double), s);
     if (e != hipSuccess) return e;
     if ((e = gemm_z(nn(n, ld, x, 1, y, 0, F), s)) != hipSuccess) return e;       // F = x^H y
     if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, Q), s)) != hipSuccess) return e;      // Q = M2 x
@@ -318,8 +382,13 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     const RitzArgs ra = {n, F, w.P1, w.P2, ld, w.ritz};
     if ((e = launch_one<RitzOp>(ra, (n + 255) / 256, 0, s)) != hipSuccess) return e;
     const int T = (n + 63) / 64;
-    const BuildArgs ba = {n, F, w.P1, w.P2, ld, w.ritz, w.Ex, w.Ey, kRefineDelta, w.maxcorr};
+    // Q is free until the basis update: it takes the tile sums of the quotients
+    double* part = reinterpret_cast<double*>(Q);
+    const BuildArgs ba = {n, F, w.P1, w.P2, ld, w.ritz, w.Ex, w.Ey, kRefineDelta, w.maxcorr, part};
     if ((e = launch_one<BuildOp>(ba, T * T, 0, s)) != hipSuccess) return e;
+    // quotients and scales of the pairs this step leaves (no products of M1, M2 after the last step)
+    const UpdRqArgs ua = {n, ld, F, w.P1, w.P2, part, lam, scl, w.maxcorr + 2};
+    if ((e = launch_one<UpdRqOp>(ua, (n + 255) / 256, 0, s)) != hipSuccess) return e;
     // the window rotations precede the first-order correction:
     // x <- x C_1 C_2 ... C_p (I + E11 + E21), y <- y C_1 ... C_p (I + E11 - E21)
     for (int pass = 0; pass < passes; ++pass) {
@@ -336,14 +405,15 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     if ((e = gemm_z(nn(n, ld, y, 0, w.Ey, 0, F), s)) != hipSuccess) return e;    // y (I + E11 - E21)
     double2* t = x; x = Q; Q = t;
     t = y; y = F; F = t;
-    double mcs[2] = {0.0, 0.0};
-    e = hipMemcpyAsync(mcs, w.maxcorr, 2 * sizeof(double), hipMemcpyDeviceToHost, s);
+    double mcs[3] = {0.0, 0.0, 0.0};
+    e = hipMemcpyAsync(mcs, w.maxcorr, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
     // the step's correction: its first-order part (the window rotations also
     // turn bases inside subspaces of nearly equal eigenvalues, where any basis
     // is as good, so they do not measure the distance to convergence)
     const double mc = mcs[0];
+    bad = mcs[2];
     *max_corr = mc;
     *steps_done = it + 1;
     if (corr_hist && it < 8) corr_hist[it] = mc;
@@ -353,16 +423,17 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     // the error left after a step is of the order of the square of its correction
     if (mc <= stop_corr) break;
   }
-  // Rayleigh quotients and Sigma-normalising scales of the final pairs.
-  if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, w.P2), s)) != hipSuccess) return e;
-  if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, w.P1), s)) != hipSuccess) return e;
-  if ((e = hipMemsetAsync(w.maxcorr, 0, sizeof(double), s)) != hipSuccess) return e;
-  const RqArgs qa = {n, x, y, w.P2, w.P1, ld, lam, scl, w.maxcorr};
-  if ((e = launch_one<RqOp>(qa, n, 0, s)) != hipSuccess) return e;
-  double bad = 0.0;
-  e = hipMemcpyAsync(&bad, w.maxcorr, sizeof(double), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return e;
+  if (*steps_done == 0) {
+    // no step ran: Rayleigh quotients and Sigma-normalising scales of the start
+    if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, w.P2), s)) != hipSuccess) return e;
+    if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, w.P1), s)) != hipSuccess) return e;
+    if ((e = hipMemsetAsync(w.maxcorr, 0, sizeof(double), s)) != hipSuccess) return e;
+    const RqArgs qa = {n, x, y, w.P2, w.P1, ld, lam, scl, w.maxcorr};
+    if ((e = launch_one<RqOp>(qa, n, 0, s)) != hipSuccess) return e;
+    e = hipMemcpyAsync(&bad, w.maxcorr, sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+  }
   if (bad != 0.0) *max_corr = __builtin_inf();
   *xp = x;
   *yp = y;
