@@ -91,7 +91,7 @@ struct Prob {
   int status = 0;
   // mixed refinement state
   double2 *x = nullptr, *y = nullptr, *q = nullptr, *f = nullptr;
-  int rsteps = 0, rdone = 0, rbad = 0;
+  int rsteps = 0, rdone = 0, rbad = 0, rwin = 0;
   double rcorr = 0.0;
   double rhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -138,7 +138,7 @@ Header make_header(int batch, const std::vector<int>& nps) {
   };
   h.off_status = take((size_t)batch * sizeof(int));
   h.off_state = take((size_t)batch * sizeof(JacState));
-  h.off_corr = take((size_t)2 * batch * sizeof(double));  // correction, then breakdown flag
+  h.off_corr = take((size_t)3 * batch * sizeof(double));  // correction, breakdown flag, coupled pairs
   h.off_active = take(256);
   h.arena = arena_bytes(nps);
   h.off_arena = take(h.arena);
@@ -575,8 +575,8 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           std::swap(pr->y, pr->f);
         }
       }
+      int* d_count = reinterpret_cast<int*>(d_corr + 2 * batch);
       const int max_steps = o.refine_steps > 0 ? o.refine_steps : 8;
-      constexpr int passes = kWindowPasses;
       for (int it = 0; it < max_steps; ++it) {
         std::vector<Prob*> act;
         for (Prob* pr : ok)
@@ -628,12 +628,38 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         BSE_TRY(run_gemm<double>(ar, g00, s));
         BSE_TRY(run_gemm<double>(ar, g10, s));
         BSE_TRY(run_op(ar, mi, group_chol, G_MIRROR, 0, s));
-        for (int pass = 0; pass < passes; ++pass) {
+        {
+          // Rayleigh-Ritz windows for a problem from its first step whose
+          // products couple a pair strongly on, as refine_z
+          Grp<RitzArgs> r0;
+          Grp<CoupleArgs> cp;
+          for (Prob* pr : act) {
+            if (pr->rwin) continue;
+            const long ld = pr->np;
+            double2* P1 = pr->at<double2>(pr->p.off_p1);
+            double2* P2 = pr->at<double2>(pr->p.off_p2);
+            double* ritz = pr->at<double>(pr->p.off_ritz);
+            r0.add({pr->n, pr->f, P1, P2, ld, ritz}, (pr->n + 255) / 256);
+            cp.add({pr->n, ld, pr->f, P1, P2, ritz, d_count + pr->idx}, (pr->n + 255) / 256);
+          }
+          if (cp.blocks() > 0) {
+            BSE_TRY(hipMemsetAsync(d_count, 0, (size_t)batch * sizeof(int), s));
+            BSE_TRY(run_op(ar, r0, group_refine, G_RITZ, 0, s));
+            BSE_TRY(run_op(ar, cp, group_refine, G_COUPLE, 0, s));
+            std::vector<int> counts(batch, 0);
+            BSE_TRY(hipMemcpyAsync(counts.data(), d_count, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
+            BSE_TRY(hipStreamSynchronize(s));
+            for (Prob* pr : act)
+              if (!pr->rwin) pr->rwin = counts[pr->idx] > 0 ? kWindowPasses : 0;
+          }
+        }
+        for (int pass = 0; pass < kWindowPasses; ++pass) {
           // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
           const int off = (pass & 1) ? 32 : 0;
           Grp<WinArgs> wn;
           std::vector<GemmDesc> right[3], left[3];
           for (Prob* pr : act) {
+            if (pass >= pr->rwin) continue;
             const long ld = pr->np;
             double2* Cb = window_blocks(pr->at<double2>(pr->p.off_cb0), pr->n, pass);
             double2* P1 = pr->at<double2>(pr->p.off_p1);
@@ -656,16 +682,18 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         BSE_TRY(run_op(ar, bd, group_refine, G_BUILD, 0, s));
         BSE_TRY(run_op(ar, ur, group_refine, G_UPDRQ, 0, s));
         // x <- x C_1 C_2 (I + E11 + E21), y <- y C_1 C_2 (I + E11 - E21)
-        for (int pass = 0; pass < passes; ++pass) {
+        for (int pass = 0; pass < kWindowPasses; ++pass) {
           const int off = (pass & 1) ? 32 : 0;
           std::vector<GemmDesc> g;
           for (Prob* pr : act) {
+            if (pass >= pr->rwin) continue;
             const double2* Cb = window_blocks(pr->at<double2>(pr->p.off_cb0), pr->n, pass);
             window_right(pr->n, pr->np, pr->x, pr->q, Cb, off, g);
             window_right(pr->n, pr->np, pr->y, pr->f, Cb, off, g);
           }
           BSE_TRY(run_gemm<double>(ar, g, s));
           for (Prob* pr : act) {
+            if (pass >= pr->rwin) continue;
             std::swap(pr->x, pr->q);
             std::swap(pr->y, pr->f);
           }

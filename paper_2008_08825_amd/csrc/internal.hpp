@@ -253,6 +253,17 @@ inline __host__ __device__ void window_range(int n, int off, int w, int& a, int&
   }
   m = n - a < 64 ? n - a : 64;
 }
+// Pairs the first-order correction resolves slowly: count the (i, j), i < j
+// <= i + 64, of the current products whose coupling K_ij = T11_ij - (l_i +
+// l_j) G11_ij / 2 exceeds 1 / kCoupleRatio of their Ritz gap |l_j - l_i| (the
+// correction's rotation angle is then above about 1 / kCoupleRatio, and within
+// a cluster the pairwise rotations leave errors of the order of its square).
+// Work group = 256 rows i.
+constexpr double kCoupleRatio = 16.0;
+struct CoupleArgs {
+  int n; long ld; const double2* F; const double2* P1; const double2* P2; const double* ritz;
+  int* count;
+};
 struct WinArgs {  // work group = window
   int n; long ld; const double2* F; const double2* P1; const double2* P2; int off;
   double2* C;       // window blocks, 64 x 64 each (column-major, ld 64)
@@ -279,7 +290,7 @@ struct RefineWork {
   double2* Cb0 = nullptr;  // kWindowPasses x (n / 64 + 2) blocks of 64 x 64
   char* arena = nullptr;
   size_t arena_cap = 0;
-  int windows = 0;         // window passes per step (0: none)
+  int windows = 0;         // window passes per step once a step finds strongly coupled pairs (0: none)
   int* perm = nullptr;  // n ints: the ascending order of the start's eigenvalues
 };
 // Block GEMMs of a window pass over the first n pairs (windows of offset
@@ -459,7 +470,7 @@ enum GroupOp {
   G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
   G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
   G_WRITE_LAMBDA, G_C64, G_ASSEMBLE, G_GATHER,
-  G_RITZ, G_BUILD, G_RQ, G_UPDRQ,                                       // refine.hip
+  G_RITZ, G_BUILD, G_RQ, G_UPDRQ, G_COUPLE,                             // refine.hip
 };
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
 hipError_t group_jacobi(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);

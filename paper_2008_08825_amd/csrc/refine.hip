@@ -241,6 +241,27 @@ struct UpdRqOp {
   }
 };
 
+struct CoupleOp {
+  static constexpr int NT = 256;
+  typedef CoupleArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int i = bx * 256 + threadIdx.x;
+    if (i >= a.n) return;
+    const double li = a.ritz[i];
+    int cnt = 0;
+    for (int d = 1; d <= 64 && i + d < a.n; ++d) {
+      const int j = i + d;
+      const long o = i + (long)j * a.ld, ot = j + (long)i * a.ld;
+      const double lj = a.ritz[j];
+      const double2 g11 = cscale(cadd(a.F[o], cconj(a.F[ot])), 0.5);
+      const double2 t11 = cscale(cadd(a.P2[o], a.P1[o]), 0.5);
+      const double2 K = csub(t11, cscale(g11, 0.5 * (li + lj)));
+      if (kCoupleRatio * sqrt(cabs2(K)) > fabs(lj - li)) ++cnt;
+    }
+    if (cnt) atomicAdd(a.count, cnt);
+  }
+};
+
 GemmDesc nn(int n, long ld, const double2* A, int opA, const double2* B, int opB, double2* C) {
   GemmDesc g;
   g.M = n; g.N = n; g.K = n;
@@ -259,6 +280,7 @@ hipError_t group_refine(GroupOp op, const void* table, const int2* map, int bloc
     case G_BUILD: return launch_grp<BuildOp>(table, map, blocks, aux, s);
     case G_RQ: return launch_grp<RqOp>(table, map, blocks, aux, s);
     case G_UPDRQ: return launch_grp<UpdRqOp>(table, map, blocks, aux, s);
+    case G_COUPLE: return launch_grp<CoupleOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -356,6 +378,8 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     double2* t = x; x = Q; Q = t;
     t = y; y = F; F = t;
   }
+  int* count = reinterpret_cast<int*>(w.maxcorr + 4);
+  int passes = 0;
   double bad = 0.0;
   for (int it = 0; it < max_steps; ++it) {
     e = hipMemsetAsync(w.maxcorr, 0, 3 * sizeof(double), s);
@@ -372,7 +396,22 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     if ((e = gemm_z(p1, s)) != hipSuccess) return e;
     if ((e = mirror_upper_z((int)((n + 63) / 64 * 64), w.P2, ld, s)) != hipSuccess) return e;
     if ((e = mirror_upper_z((int)((n + 63) / 64 * 64), w.P1, ld, s)) != hipSuccess) return e;
-    const int passes = w.windows;
+    // Rayleigh-Ritz windows from the first step whose products couple a pair
+    // strongly on (clusters); spectra without such pairs converge as fast
+    // without them
+    if (w.windows && !passes) {
+      const RitzArgs r0 = {n, F, w.P1, w.P2, ld, w.ritz};
+      if ((e = launch_one<RitzOp>(r0, (n + 255) / 256, 0, s)) != hipSuccess) return e;
+      if ((e = hipMemsetAsync(count, 0, sizeof(int), s)) != hipSuccess) return e;
+      const CoupleArgs ca = {n, ld, F, w.P1, w.P2, w.ritz, count};
+      if ((e = launch_one<CoupleOp>(ca, (n + 255) / 256, 0, s)) != hipSuccess) return e;
+      int strong = 0;
+      e = hipMemcpyAsync(&strong, count, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return e;
+      passes = strong > 0 ? w.windows : 0;
+      if (getenv("BSE_DEBUG")) fprintf(stderr, "[bse] refinement step %d: %d strongly coupled pairs\n", it + 1, strong);
+    }
     for (int pass = 0; pass < passes; ++pass) {
       // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
       const int off = (pass & 1) ? 32 : 0;
