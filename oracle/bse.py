@@ -59,6 +59,9 @@ __all__ = [
     "grad_from_eigenpairs",
     "spectrum_loss",
     "spectrum_loss_weights",
+    "grad_from_eigvecs",
+    "oscillator_spectrum_loss",
+    "oscillator_spectrum_partials",
 ]
 
 
@@ -329,3 +332,111 @@ def spectrum_loss_weights(lam: np.ndarray, k_low: int = 128, n_omega: int = 512,
     w = dS.sum(axis=0)
     w[:k_low] += 1.0
     return w
+
+
+def grad_from_eigvecs(lam: np.ndarray, X: np.ndarray, g_lam: np.ndarray, G_X: np.ndarray,
+                      degen_rtol: float = 1e-13):
+    """Gradient of a real loss ``L(lambda, X)`` with respect to Hermitian ``A`` and ``B``.
+
+    ``g_lam = dL/dlambda`` (n) and ``G_X`` (2n x n) with ``dL = Re tr(G_X^H dX)``
+    for the columns of ``X`` (positive half, ``X^H Sigma X = I``); returns
+    ``(G_A, G_B)`` with ``dL = Re tr(G_A^H dA) + Re tr(G_B^H dB)`` (Hermitian).
+
+    First-order perturbation of the Hermitian pencil ``(Hcal, Sigma)``,
+    ``Hcal = Sigma H1 = [[A, B], [B, A]]`` (Eq. BSEHam): with all ``2n``
+    eigenvectors ``Z = [X, P X]`` (Lemma ComputeNegEvecs, ``P = [[0, I],
+    [I, 0]]``), eigenvalues ``l = [lambda, -lambda]`` and signature
+    ``s = [1, ..., 1, -1, ..., -1]``, Thm ProdEig Eq. SigmaOrthEVecs reads
+    ``Z^H Sigma Z = diag(s)`` and ``Hcal Z = Sigma Z diag(l)``.  Differentiating,
+    with ``K = Z^H dHcal Z`` (Hermitian) and ``dZ = Z C``:
+    ``dlambda_k = K_kk`` (Thm EValSym part 3) and, off the diagonal,
+    ``C_ik = s_i K_ik / (l_k - l_i)``; the normalisation fixes ``Re C_kk = 0``
+    and the phase of each column is held (``C_kk = 0``).  Hence, with
+    ``Y = Z^H G_X``,
+
+        dL = Re sum_{i, k <= n} D_ik K_ik,
+        D_kk = g_k,
+        D_ik = s_i conj(Y_ik) / (l_k - l_i)        (i != k).
+
+    For ``i, k`` both in the positive half the terms ``(i, k)`` and ``(k, i)``
+    are combined (``K_ki = conj(K_ik)``) into
+    ``D_ik = (conj(Y_ik) - Y_ki) / (2 (lambda_k - lambda_i))`` (the same sum):
+    its numerator vanishes for losses invariant under rotations within a
+    cluster of equal eigenvalues and is a divided difference for spectral
+    functions, so it stays finite as the gap closes.  Pairs with
+    ``|lambda_k - lambda_i| <= degen_rtol * max(lambda)`` count as degenerate
+    and their term is dropped (exact for losses that see a degenerate cluster
+    only through its invariant subspace).  Finally, with
+    ``M = X D^T Z^H`` and ``tr(dHcal M) = tr(dA (M11 + M22)) + tr(dB (M12 + M21))``,
+    ``G_A`` and ``G_B`` are the Hermitian parts of ``M11 + M22`` and
+    ``M12 + M21``.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    g_lam = np.asarray(g_lam, dtype=np.float64)
+    X = np.asarray(X, dtype=np.complex128)
+    G_X = np.asarray(G_X, dtype=np.complex128)
+    n = X.shape[1]
+    a = X[:n]
+    b = X[n:]
+    Z = np.hstack([X, np.vstack([b, a])])
+    l = np.concatenate([lam, -lam])
+    s = np.concatenate([np.ones(n), -np.ones(n)])
+    Y = Z.conj().T @ G_X
+    D = np.zeros((2 * n, n), dtype=np.complex128)
+    tol = degen_rtol * (np.max(np.abs(lam)) if n else 0.0)
+    for k in range(n):
+        for i in range(2 * n):
+            if i == k:
+                D[i, k] = g_lam[k]
+            elif i < n:
+                gap = lam[k] - lam[i]
+                if abs(gap) > tol:
+                    D[i, k] = (np.conj(Y[i, k]) - Y[k, i]) / (2.0 * gap)
+            else:
+                D[i, k] = s[i] * np.conj(Y[i, k]) / (l[k] - l[i])
+    M = X @ D.T @ Z.conj().T
+    NA = M[:n, :n] + M[n:, n:]
+    NB = M[:n, n:] + M[n:, :n]
+    GA = 0.5 * (NA + NA.conj().T)
+    GB = 0.5 * (NB + NB.conj().T)
+    return GA, GB
+
+
+def _lorentz(om: np.ndarray, lam: np.ndarray, eta: float):
+    """``(phi_k, dphi_k)``: ``sum_j (eta/pi) / ((om_j - lam_k)^2 + eta^2)`` and its lam-derivative."""
+    diff = om[:, None] - lam[None, :]
+    den = diff ** 2 + eta ** 2
+    phi = ((eta / np.pi) / den).sum(axis=0)
+    dphi = ((eta / np.pi) * 2.0 * diff / den ** 2).sum(axis=0)
+    return phi, dphi
+
+
+def oscillator_spectrum_loss(lam: np.ndarray, X: np.ndarray, dip: np.ndarray, n_omega: int = 512,
+                             omega_max: float = 12.0, eta: float = 0.05) -> float:
+    """Absorption-type loss from eigenvalues and eigenvectors (Sec. 1's use of the eigenpairs).
+
+    ``L = sum_j S(omega_j)``, ``S(omega) = sum_k f_k (eta/pi) / ((omega - lambda_k)^2 + eta^2)``
+    with oscillator strengths ``f_k = |dip^H X_k|^2`` for a 2n-vector ``dip``
+    and ``omega_j = (j + 1/2) omega_max / n_omega``.  ``f_k`` does not depend on
+    the phase of ``X_k``.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    f = np.abs(np.asarray(dip).conj() @ np.asarray(X)) ** 2
+    phi, _ = _lorentz(_omegas(n_omega, omega_max), lam, eta)
+    return float((f * phi).sum())
+
+
+def oscillator_spectrum_partials(lam: np.ndarray, X: np.ndarray, dip: np.ndarray, n_omega: int = 512,
+                                 omega_max: float = 12.0, eta: float = 0.05):
+    """``(g_lam, G_X)`` of :func:`oscillator_spectrum_loss`.
+
+    ``g_k = f_k phi'(lambda_k)`` and ``G_X[:, k] = 2 dip (dip^H X_k) phi(lambda_k)``,
+    so that ``dL = sum_k g_k dlambda_k + Re tr(G_X^H dX)``.
+    """
+    lam = np.asarray(lam, dtype=np.float64)
+    dip = np.asarray(dip, dtype=np.complex128)
+    c = dip.conj() @ np.asarray(X)
+    phi, dphi = _lorentz(_omegas(n_omega, omega_max), lam, eta)
+    g = np.abs(c) ** 2 * dphi
+    G_X = 2.0 * np.outer(dip, c * phi)
+    return g, G_X
