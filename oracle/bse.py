@@ -382,18 +382,17 @@ def grad_from_eigvecs(lam: np.ndarray, X: np.ndarray, g_lam: np.ndarray, G_X: np
     l = np.concatenate([lam, -lam])
     s = np.concatenate([np.ones(n), -np.ones(n)])
     Y = Z.conj().T @ G_X
-    D = np.zeros((2 * n, n), dtype=np.complex128)
     tol = degen_rtol * (np.max(np.abs(lam)) if n else 0.0)
-    for k in range(n):
-        for i in range(2 * n):
-            if i == k:
-                D[i, k] = g_lam[k]
-            elif i < n:
-                gap = lam[k] - lam[i]
-                if abs(gap) > tol:
-                    D[i, k] = (np.conj(Y[i, k]) - Y[k, i]) / (2.0 * gap)
-            else:
-                D[i, k] = s[i] * np.conj(Y[i, k]) / (l[k] - l[i])
+    # D[i, k] for i, k in the positive half (rows 0..n-1), entry by entry as above
+    Yt = Y[:n]
+    gap = lam[None, :] - lam[:, None]                      # gap[i, k] = lambda_k - lambda_i
+    off = (np.abs(gap) > tol) & ~np.eye(n, dtype=bool)
+    Dt = np.zeros((n, n), dtype=np.complex128)
+    Dt[off] = ((np.conj(Yt) - Yt.T) / (2.0 * np.where(off, gap, 1.0)))[off]
+    Dt[np.diag_indices(n)] = g_lam
+    # the negative half (rows n..2n-1): s_i conj(Y_ik) / (l_k - l_i)
+    Db = s[n:, None] * np.conj(Y[n:]) / (l[None, :n] - l[n:, None])
+    D = np.vstack([Dt, Db])
     M = X @ D.T @ Z.conj().T
     NA = M[:n, :n] + M[n:, n:]
     NB = M[:n, n:] + M[n:, :n]
