@@ -238,6 +238,44 @@ int bse_backward(int n, const void* X, int ldx, const double* w,
                  void* gA, int ldga, void* gB, int ldgb,
                  void* work, size_t work_bytes, void* stream);
 
+/* Workspace for bse_backward_vec of order n (six n x n complex128 buffers);
+ * 0 for n < 0 or n > 46000. */
+size_t bse_backward_vec_workspace_bytes(int n);
+
+/* Gradient of a real loss L(lambda, X) of the eigenvalues and eigenvectors
+ * (e.g. oscillator strengths |d^H x_k|^2 of an absorption spectrum, the use of
+ * the eigenpairs in Sec. 1) with respect to Hermitian A and B.
+ *   lambda     n doubles (device): the positive eigenvalues of the columns of X
+ *   X, ldx     2n x n complex128, Sigma-normalised (X^H Sigma X = I), as
+ *              written by bse_solve_h1
+ *   g_lambda   n doubles (device): dL/dlambda_k
+ *   G_X, ldg   2n x n complex128: dL = Re tr(G_X^H dX) for the eigenvector part
+ *              (the gradient convention of PyTorch for complex tensors)
+ *   degen_rtol pairs with |lambda_k - lambda_i| <= degen_rtol max|lambda| count
+ *              as degenerate (0 <= degen_rtol < 1; 1e-13 is a sensible value)
+ *   gA, gB     n x n complex128 outputs (full Hermitian), dL = Re tr(G_A^H dA)
+ *              + Re tr(G_B^H dB)
+ *   work       device workspace of work_bytes >= bse_backward_vec_workspace_bytes(n)
+ * First-order perturbation of the Hermitian pencil (Sigma H1, Sigma) with all
+ * 2n eigenvectors Z = [X, P X] (Lemma ComputeNegEvecs; Thm ProdEig
+ * Eq. SigmaOrthEVecs; Thm EValSym part 3 for the eigenvalue terms): with
+ * Y = Z^H G_X, dL = Re sum D_ik K_ik over K = Z^H d(Sigma H1) Z, where
+ * D_kk = g_k, D_ik = (conj(Y_ik) - Y_ki) / (2 (lambda_k - lambda_i)) for two
+ * positive-half indices (the Hermitian-part numerator stays finite inside
+ * clusters: it vanishes for losses invariant under rotations within a cluster
+ * and is a divided difference for spectral functions; degenerate pairs get 0),
+ * and D_ik = -conj(Y_ik) / (lambda_k + lambda_i') for the negative half.
+ * The phase of each eigenvector is held, so the loss should not depend on it.
+ * Work: five n^3 complex GEMMs on MFMA (two on lower tiles only) and
+ * elementwise passes: 5 n^3 complex multiply-adds (40 n^3 real flops in the
+ * plain count, 30 n^3 executed in the three-product form).  Synchronises on stream.
+ * Returns 0, -1 n, -2 lambda, -3 X, -4 ldx, -5 g_lambda, -6 G_X, -7 ldg,
+ * -8 degen_rtol, -9 gA, -10 ldga, -11 gB, -12 ldgb, -13 work NULL,
+ * -14 work_bytes too small, or <= -1000 (HIP runtime error). */
+int bse_backward_vec(int n, const double* lambda, const void* X, int ldx, const double* g_lambda,
+                     const void* G_X, int ldg, double degen_rtol, void* gA, int ldga, void* gB,
+                     int ldgb, void* work, size_t work_bytes, void* stream);
+
 /* Short text for a return code (static storage). */
 const char* bse_status_string(int status, int n);
 

@@ -114,6 +114,8 @@ EXPORTS = [
     "bse_solve_batched",
     "bse_backward_workspace_bytes",
     "bse_backward",
+    "bse_backward_vec_workspace_bytes",
+    "bse_backward_vec",
     "bse_status_string",
     "bse_solve_h1_noalloc",
     "bse_noalloc_scratch_bytes",
@@ -151,6 +153,11 @@ def load_library(path: Optional[str] = None):
     lib.bse_backward_workspace_bytes.restype = ctypes.c_size_t
     lib.bse_backward.argtypes = [ci, vp, ci, vp, vp, ci, vp, ci, vp, ctypes.c_size_t, vp]
     lib.bse_backward.restype = ci
+    lib.bse_backward_vec_workspace_bytes.argtypes = [ci]
+    lib.bse_backward_vec_workspace_bytes.restype = ctypes.c_size_t
+    lib.bse_backward_vec.argtypes = [ci, vp, vp, ci, vp, vp, ci, ctypes.c_double, vp, ci, vp, ci, vp,
+                                     ctypes.c_size_t, vp]
+    lib.bse_backward_vec.restype = ci
     lib.bse_status_string.argtypes = [ci, ci]
     lib.bse_status_string.restype = ctypes.c_char_p
     lib.bse_solve_h1_noalloc.argtypes = [ci, vp, ci, vp, ci, vp, vp, ci, ctypes.POINTER(BSEOpts),
@@ -423,25 +430,84 @@ def backward(X: torch.Tensor, w: torch.Tensor):
     return GA, GB
 
 
+def _colmajor(M: torch.Tensor, rows: int) -> torch.Tensor:
+    """``M`` (rows x cols) or a copy whose memory is column-major with leading dimension >= rows.
+
+    The copy goes through an explicit (cols, rows) buffer: torch ignores the
+    stride of a dimension of size 1, so ``.mT.contiguous()`` may keep one."""
+    if M.stride(0) != 1 or M.stride(1) < max(1, rows):
+        buf = torch.empty((M.shape[1], M.shape[0]), dtype=M.dtype, device=M.device)
+        buf.copy_(M.mT)
+        M = buf.mT
+    return M
+
+
+def backward_vec(lam: torch.Tensor, X: torch.Tensor, g_lam: Optional[torch.Tensor],
+                 G_X: Optional[torch.Tensor], degen_rtol: float = 1e-13):
+    """``(G_A, G_B)`` for a loss of the eigenvalues and eigenvectors (``bse_backward_vec``).
+
+    ``lam`` (n) and ``X`` (2n x n) as returned by :func:`solve_h1`; ``g_lam``
+    = dL/dlam and ``G_X`` the gradient with respect to ``X`` (PyTorch's
+    convention for complex tensors); either may be None (zero).
+    """
+    lib = load_library()
+    n2, n = X.shape
+    if n2 != 2 * n:
+        raise ValueError("X must be 2n x n")
+    if X.dtype != torch.complex128 or not X.is_cuda:
+        raise TypeError("X must be a complex128 CUDA tensor")
+    dev = X.device
+    lam = lam[:n].to(dtype=torch.float64, device=dev).contiguous()
+    g = (torch.zeros(n, dtype=torch.float64, device=dev) if g_lam is None
+         else g_lam[:n].to(dtype=torch.float64, device=dev).contiguous())
+    conj = X.is_conj()
+    # buffer values: for a conjugated view the library sees conj(X) and, with
+    # Re tr(G^H conj(dX)) = Re tr(conj(G)^H dX), the gradient conj(G_X)
+    Xr = _colmajor((X.conj() if conj else X).resolve_conj(), 2 * n)
+    if G_X is None:
+        G = torch.zeros((2 * n, n), dtype=torch.complex128, device=dev)
+    else:
+        G = G_X.to(dtype=torch.complex128, device=dev)
+        G = G.conj() if conj else G
+    Gr = _colmajor(G.resolve_conj(), 2 * n)
+    gA = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    gB = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    work = torch.empty(max(1, int(lib.bse_backward_vec_workspace_bytes(n))), dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        st = lib.bse_backward_vec(n, lam.data_ptr(), Xr.data_ptr(), Xr.stride(1), g.data_ptr(),
+                                  Gr.data_ptr(), Gr.stride(1), float(degen_rtol), gA.data_ptr(), n,
+                                  gB.data_ptr(), n, work.data_ptr(), work.numel(), _stream_handle(dev))
+    if st != 0:
+        raise BSEError(st, n)
+    GA = gA.mT
+    GB = gB.mT
+    if conj:
+        GA = GA.conj()
+        GB = GB.conj()
+    return GA, GB
+
+
 class BSEEig(torch.autograd.Function):
-    """``(lam, X) = BSEEig.apply(A, B)``; backward through ``lam`` only.
+    """``(lam, X) = BSEEig.apply(A, B)``, differentiable through ``lam`` and ``X``.
 
     The gradient is the full Hermitian ``G`` with ``dL = Re tr(G^H dA)`` for
-    Hermitian perturbations; a nonzero gradient with respect to ``X`` raises.
+    Hermitian perturbations.  Losses of the eigenvalues alone take
+    ``bse_backward``; a loss that also depends on ``X`` takes
+    ``bse_backward_vec`` (it should not depend on the phase of each column).
     """
 
     @staticmethod
     def forward(ctx, A, B, route="svd", precision="fp64"):
         lam, X, _ = solve_h1(A.detach(), B.detach(), route=route, precision=precision)
-        ctx.save_for_backward(X)
-        ctx.mark_non_differentiable(X)
+        ctx.save_for_backward(lam, X)
         return lam, X
 
     @staticmethod
     def backward(ctx, g_lam, g_X):
-        (X,) = ctx.saved_tensors
+        lam, X = ctx.saved_tensors
         if g_X is not None and bool(torch.any(g_X != 0)):
-            raise NotImplementedError("gradient with respect to eigenvectors is not supported")
+            GA, GB = backward_vec(lam, X, g_lam, g_X)
+            return GA, GB, None, None
         if g_lam is None:
             return None, None, None, None
         GA, GB = backward(X, g_lam)

@@ -835,6 +835,36 @@ int bse_backward(int n, const void* X, int ldx, const double* w, void* gA, int l
   return 0;
 }
 
+size_t bse_backward_vec_workspace_bytes(int n) {
+  return n >= 0 && n <= 46000 ? adjoint_vec_work_bytes(n) : 0;
+}
+
+int bse_backward_vec(int n, const double* lambda, const void* X, int ldx, const double* g_lambda,
+                     const void* G_X, int ldg, double degen_rtol, void* gA, int ldga, void* gB,
+                     int ldgb, void* work, size_t work_bytes, void* stream) {
+  if (n < 0 || n > 46000) return -1;
+  if (n > 0 && !lambda) return -2;
+  if (n > 0 && !X) return -3;
+  if (ldx < (2 * n > 1 ? 2 * n : 1)) return -4;
+  if (n > 0 && !g_lambda) return -5;
+  if (n > 0 && !G_X) return -6;
+  if (ldg < (2 * n > 1 ? 2 * n : 1)) return -7;
+  if (!(degen_rtol >= 0.0 && degen_rtol < 1.0)) return -8;
+  if (n > 0 && !gA) return -9;
+  if (ldga < (n > 1 ? n : 1)) return -10;
+  if (n > 0 && !gB) return -11;
+  if (ldgb < (n > 1 ? n : 1)) return -12;
+  if (n == 0) return 0;
+  if (!work) return -13;
+  if (work_bytes < adjoint_vec_work_bytes(n)) return -14;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  BSE_TRY(adjoint_vec_z(n, lambda, static_cast<const double2*>(X), ldx, g_lambda,
+                        static_cast<const double2*>(G_X), ldg, degen_rtol, static_cast<double2*>(gA),
+                        ldga, static_cast<double2*>(gB), ldgb, work, s));
+  BSE_TRY(hipStreamSynchronize(s));
+  return 0;
+}
+
 const char* bse_status_string(int status, int n) {
   if (status == 0) return "success";
   if (status <= kErrHip) return "HIP runtime error";

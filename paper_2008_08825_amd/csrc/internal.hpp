@@ -337,6 +337,14 @@ hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, con
 // G_B = sum_k w_k (a_k b_k^H + b_k a_k^H) for X = [a; b] (2n x n, ldx), written
 // as full Hermitian n x n matrices; work holds adjoint_work_bytes(n) bytes.
 size_t adjoint_work_bytes(int n);
+// Eigenvector adjoint: G_A, G_B for a loss with dL = sum_k g_k dlambda_k +
+// Re tr(G_X^H dX) (first-order perturbation of the pencil (Sigma H1, Sigma)
+// with all 2n eigenvectors); pairs with |lam_k - lam_i| <= rtol max|lam|
+// count as degenerate.  work holds adjoint_vec_work_bytes(n) bytes.
+size_t adjoint_vec_work_bytes(int n);
+hipError_t adjoint_vec_z(int n, const double* lam, const double2* X, long ldx, const double* g,
+                         const double2* GX, long ldg, double rtol, double2* gA, long ldga,
+                         double2* gB, long ldgb, void* work, hipStream_t s);
 hipError_t adjoint_z(int n, const double2* X, long ldx, const double* w, double2* gA, long ldga,
                      double2* gB, long ldgb, void* work, hipStream_t s);
 

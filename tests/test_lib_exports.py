@@ -75,6 +75,26 @@ def test_host_only_queries():
     assert lib.bse_backward(4, 16, 8, 16, 16, 4, 16, 4, None, 0, None) == -9
     assert lib.bse_backward(4, 16, 8, 16, 16, 4, 16, 4, 16, 10, None) == -10
     assert lib.bse_backward_workspace_bytes(4) > 2 * 16 * 16
+    # eigenvector adjoint: every argument check returns before any device work
+    bv = lib.bse_backward_vec
+    assert bv(-1, None, None, 1, None, None, 1, 0.0, None, 1, None, 1, None, 0, None) == -1
+    assert bv(4, None, 16, 8, 16, 16, 8, 0.0, 16, 4, 16, 4, 16, 1 << 30, None) == -2
+    assert bv(4, 16, None, 8, 16, 16, 8, 0.0, 16, 4, 16, 4, 16, 1 << 30, None) == -3
+    assert bv(4, 16, 16, 7, 16, 16, 8, 0.0, 16, 4, 16, 4, 16, 1 << 30, None) == -4
+    assert bv(4, 16, 16, 8, None, 16, 8, 0.0, 16, 4, 16, 4, 16, 1 << 30, None) == -5
+    assert bv(4, 16, 16, 8, 16, None, 8, 0.0, 16, 4, 16, 4, 16, 1 << 30, None) == -6
+    assert bv(4, 16, 16, 8, 16, 16, 7, 0.0, 16, 4, 16, 4, 16, 1 << 30, None) == -7
+    assert bv(4, 16, 16, 8, 16, 16, 8, -1.0, 16, 4, 16, 4, 16, 1 << 30, None) == -8
+    assert bv(4, 16, 16, 8, 16, 16, 8, float("nan"), 16, 4, 16, 4, 16, 1 << 30, None) == -8
+    assert bv(4, 16, 16, 8, 16, 16, 8, 0.0, None, 4, 16, 4, 16, 1 << 30, None) == -9
+    assert bv(4, 16, 16, 8, 16, 16, 8, 0.0, 16, 3, 16, 4, 16, 1 << 30, None) == -10
+    assert bv(4, 16, 16, 8, 16, 16, 8, 0.0, 16, 4, None, 4, 16, 1 << 30, None) == -11
+    assert bv(4, 16, 16, 8, 16, 16, 8, 0.0, 16, 4, 16, 3, 16, 1 << 30, None) == -12
+    assert bv(4, 16, 16, 8, 16, 16, 8, 0.0, 16, 4, 16, 4, None, 1 << 30, None) == -13
+    assert bv(4, 16, 16, 8, 16, 16, 8, 0.0, 16, 4, 16, 4, 16, 10, None) == -14
+    assert bv(0, None, None, 1, None, None, 1, 0.0, None, 1, None, 1, None, 0, None) == 0
+    assert lib.bse_backward_vec_workspace_bytes(4) >= 6 * 4 * 4 * 16
+    assert lib.bse_backward_vec_workspace_bytes(-1) == 0
     assert lib.bse_status_string(5, 4).decode() == "A - B is not positive definite"
 
 
