@@ -26,7 +26,9 @@ cpu_baseline the FP64 CPU oracle (scipy, Alg. 3) on this host on a bounded
 batched, differentiation  supplementary measurements of the other two forms:
          the 256-problem batch (n uniform in [64, 1024]) through the grouped
          batched entry point, and the n = 4096 forward solve + spectrum loss +
-         eigenvalue adjoint (the adjoint kernel also against the FP64 MFMA peak).
+         eigenvalue adjoint (the adjoint kernel also against the FP64 MFMA peak),
+         with a second loss of the eigenvectors (oscillator strengths) through
+         the eigenvector adjoint.
 """
 from __future__ import annotations
 
@@ -345,7 +347,8 @@ def bench_differentiation(api, inputs, steps, warmup):
     e1.record()
     torch.cuda.synchronize()
     adj_ms = e0.elapsed_time(e1) / steps
-    adj_flops = 8.0 * n ** 3  # two Hermitian rank-n products, lower halves (4 n^3 real flops each)
+    adj_flops = 8.0 * n ** 3  # two Hermitian rank-n products, lower halves (n^3 / 2 complex MACs, 8 flops each)
+    adj_exec = 0.75 * adj_flops  # three-product complex form: 6 real flops per multiply-add
     # directional derivative against a fourth-order central difference of the
     # eigenvalues, weights frozen at dL/dlambda (the quantity the adjoint maps)
     GA, GB, w = step.grads
@@ -379,18 +382,120 @@ def bench_differentiation(api, inputs, steps, warmup):
     loss(lam_g).backward()
     g_err = max(float(np.linalg.norm(G.detach().cpu().numpy() - Go) / np.linalg.norm(Go))
                 for G, Go in ((At1.grad, GA_o), (Bt1.grad, GB_o)))
+    vec = bench_eigvec_adjoint(api, A, B, A1, B1, lam1, X1, steps, warmup)
     return {"workload": f"n={n} (n=2048 recipe, seed 0), loss = sum of lowest 128 eigenvalues + "
                         "Lorentzian spectrum (eta 0.05) on 512 points in (0, 12)",
             "forward_seconds": round(fwd, 4),
             "forward_nominal_tflops": round(nominal_flops(n) / fwd / 1e12, 3),
             "loss_and_backward_seconds": round(bwd, 4),
             "adjoint_ms": round(adj_ms, 3),
-            "adjoint_tflops": round(adj_flops / (adj_ms * 1e-3) / 1e12, 3),
-            "adjoint_frac_fp64_mfma": round(adj_flops / (adj_ms * 1e-3) / 1e12 / PEAK["fp64_mfma"], 4),
+            "adjoint_alg_tflops": round(adj_flops / (adj_ms * 1e-3) / 1e12, 3),
+            "adjoint_exec_tflops": round(adj_exec / (adj_ms * 1e-3) / 1e12, 3),
+            "adjoint_frac_fp64_mfma": round(adj_exec / (adj_ms * 1e-3) / 1e12 / PEAK["fp64_mfma"], 4),
             "fd_directional_rel_err": abs(fd - ad) / max(1.0, abs(ad)),
             "grad_rel_err_vs_oracle_n1024": g_err,
             "cpu_baseline": {"seconds": round(cdt, 2), "kind": "oracle",
-                             "sample": "forward solve + spectrum-loss adjoint at n = 1024 of the same recipe"}}
+                             "sample": "forward solve + spectrum-loss adjoint at n = 1024 of the same recipe"},
+            "eigenvector_loss": vec}
+
+
+def bench_eigvec_adjoint(api, A, B, A1, B1, lam1, X1, steps, warmup):
+    """Loss of the eigenvectors too: an absorption spectrum with oscillator
+    strengths f_k = |dip^H x_k|^2 (eta 0.05, 512 points in (0, 12)) through
+    BSEEig and bse_backward_vec at n = 4096; the adjoint kernel timed alone;
+    a directional finite difference at n = 4096; the n = 1024 gradient against
+    the oracle's (grad_from_eigvecs on the oracle's eigenpairs)."""
+    import math
+
+    import numpy as np
+    import torch
+
+    from oracle import bse as ob
+    dev = A.device
+    n = A.shape[0]
+    om = (torch.arange(512, dtype=torch.float64, device=dev) + 0.5) * (12.0 / 512)
+
+    def dip_of(m):
+        rng = np.random.default_rng(17)
+        return torch.from_numpy(rng.standard_normal(2 * m) + 1j * rng.standard_normal(2 * m)).to(dev)
+
+    def loss(lam, X, dip):
+        c = dip.conj() @ X
+        d = om[:, None] - lam[None, :]
+        return ((c * c.conj()).real * ((0.05 / math.pi) / (d * d + 0.05 ** 2)).sum(dim=0)).sum()
+
+    dip = dip_of(n)
+
+    def step():
+        At = A.clone().requires_grad_(True)
+        Bt = B.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, X = api.BSEEig.apply(At, Bt)
+        L = loss(lam, X, dip)
+        L.backward()
+        torch.cuda.synchronize()
+        step.out = (At.grad, Bt.grad, lam.detach(), X.detach())
+        return time.perf_counter() - t0
+
+    for _ in range(warmup):
+        step()
+    sec = sum(step() for _ in range(steps)) / steps
+    GA, GB, lam, X = step.out
+    # the adjoint kernel alone on the solver's stream (torch's current stream)
+    Xr = X.detach().requires_grad_(True)
+    lr = lam.detach().requires_grad_(True)
+    loss(lr, Xr, dip).backward()
+    g, GX = lr.grad, Xr.grad
+    api.backward_vec(lam, X, g, GX)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        api.backward_vec(lam, X, g, GX)
+    e1.record()
+    torch.cuda.synchronize()
+    adj_ms = e0.elapsed_time(e1) / steps
+    alg = 40.0 * n ** 3    # five n^3 complex products, 8 real flops per multiply-add (two on lower halves: 4 + 2 x 0.5)
+    exe = 0.75 * alg       # three-product complex form: 6 real flops per multiply-add
+    gen = torch.Generator(device="cpu").manual_seed(5)
+
+    def herm():
+        Z = torch.randn(n, n, dtype=torch.complex128, generator=gen)
+        return ((Z + Z.mH) * (0.05 / (2.0 * n ** 0.5))).to(dev)
+
+    dA, dB = herm(), herm()
+    h = 1e-3
+    f = []
+    for tt in (-2, -1, 1, 2):
+        lam_t, X_t, _ = api.solve_h1(A + tt * h * dA, B + tt * h * dB)
+        f.append(float(loss(lam_t, X_t, dip)))
+    fd = (f[0] - 8 * f[1] + 8 * f[2] - f[3]) / (12 * h)
+    ad = float(torch.vdot(GA.flatten(), dA.flatten()).real + torch.vdot(GB.flatten(), dB.flatten()).real)
+    # n = 1024 against the oracle (its eigenpairs from the eigenvalue leg above)
+    m = A1.shape[0]
+    dip1 = dip_of(m)
+    t0 = time.perf_counter()
+    g1, GX1 = ob.oscillator_spectrum_partials(lam1, X1, dip1.cpu().numpy(), n_omega=512, omega_max=12.0, eta=0.05)
+    GA_o, GB_o = ob.grad_from_eigvecs(lam1, X1, g1, GX1)
+    cdt = time.perf_counter() - t0
+    At1 = torch.from_numpy(A1).to(dev).requires_grad_(True)
+    Bt1 = torch.from_numpy(B1).to(dev).requires_grad_(True)
+    lam_g, X_g = api.BSEEig.apply(At1, Bt1)
+    loss(lam_g, X_g, dip1).backward()
+    g_err = max(float(np.linalg.norm(G.detach().cpu().numpy() - Go) / np.linalg.norm(Go))
+                for G, Go in ((At1.grad, GA_o), (Bt1.grad, GB_o)))
+    lam1s = np.sort(lam1)
+    return {"loss": "sum over 512 points in (0, 12) of sum_k |dip^H x_k|^2 (eta/pi) / ((omega - lambda_k)^2 + eta^2), "
+                    "eta 0.05, dip a seeded complex Gaussian 2n-vector",
+            "forward_loss_backward_seconds": round(sec, 4),
+            "adjoint_ms": round(adj_ms, 3),
+            "adjoint_alg_tflops": round(alg / (adj_ms * 1e-3) / 1e12, 3),
+            "adjoint_exec_tflops": round(exe / (adj_ms * 1e-3) / 1e12, 3),
+            "adjoint_frac_fp64_mfma": round(exe / (adj_ms * 1e-3) / 1e12 / PEAK["fp64_mfma"], 4),
+            "fd_directional_rel_err": abs(fd - ad) / max(1.0, abs(ad)),
+            "grad_rel_err_vs_oracle_n1024": g_err,
+            "gap_bar_n1024": 2.0 * m * 2.220446049250313e-16 * lam1s[-1] / float(np.min(np.diff(lam1s))),
+            "cpu_oracle_adjoint_seconds_n1024": round(cdt, 2)}
 
 
 def load_traffic(kernel: str, workload: str, precision: str):
