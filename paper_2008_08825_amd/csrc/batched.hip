@@ -414,7 +414,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         rz.add(rot_args_z(np, W, np, jw, &st->done), jacobi_rot_blocks_rr(np, jw.rrows));
       }
       const SweepArgs sa = {st, d_active, jacobi_pairs(np) * jacobi_rounds(np), max_sweeps,
-                            mixed ? 1.0e-5 : 1.0e-10, 1, mixed ? 0.3 : 1.0,
+                            mixed ? 1.0e-5 : 1.0e-10, 1, 1.0,
                             mixed ? kTrackLevel32 : kTrackLevel64, jacobi_pairs(np),
                             mixed ? 1.0 / 32 : 0.0};
       sw.add(sa, 1);

@@ -478,8 +478,9 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   JacobiResult jr;
   // the refinement's window Rayleigh-Ritz resolves what the last sweeps would
   // (neighbour mixing), so the complex64 iteration ends, like the polish's,
-  // once a sweep rotates fewer than 1/32 of its pairs
-  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, kernel_time_stride(want_timing), 0.3,
+  // once a sweep rotates fewer than 1/32 of its pairs, with the same inner
+  // stopping rule
+  BSE_TRY(jacobi_c(np, Wc, ld, jw, tol, 1.0e-5, max_sweeps, jr, s, kernel_time_stride(want_timing), 1.0,
                    1.0 / 32));
   tm.mark();
   BSE_TRY(scale_singular_cols_c(n, np, Wc, ld, sigma, bnorm, s));
