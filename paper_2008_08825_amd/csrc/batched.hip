@@ -577,6 +577,11 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       }
       int* d_count = reinterpret_cast<int*>(d_corr + 2 * batch);
       const int max_steps = o.refine_steps > 0 ? o.refine_steps : 8;
+      // window passes of a problem's current step, as refine_z: from the first
+      // step with strongly coupled pairs on, unless the previous correction was small
+      auto step_win = [](const Prob* pr) {
+        return (pr->rsteps == 0 || pr->rcorr > kWindowStop) ? pr->rwin : 0;
+      };
       for (int it = 0; it < max_steps; ++it) {
         std::vector<Prob*> act;
         for (Prob* pr : ok)
@@ -659,7 +664,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           Grp<WinArgs> wn;
           std::vector<GemmDesc> right[3], left[3];
           for (Prob* pr : act) {
-            if (pass >= pr->rwin) continue;
+            if (pass >= step_win(pr)) continue;
             const long ld = pr->np;
             double2* Cb = window_blocks(pr->at<double2>(pr->p.off_cb0), pr->n, pass);
             double2* P1 = pr->at<double2>(pr->p.off_p1);
@@ -686,14 +691,14 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           const int off = (pass & 1) ? 32 : 0;
           std::vector<GemmDesc> g;
           for (Prob* pr : act) {
-            if (pass >= pr->rwin) continue;
+            if (pass >= step_win(pr)) continue;
             const double2* Cb = window_blocks(pr->at<double2>(pr->p.off_cb0), pr->n, pass);
             window_right(pr->n, pr->np, pr->x, pr->q, Cb, off, g);
             window_right(pr->n, pr->np, pr->y, pr->f, Cb, off, g);
           }
           BSE_TRY(run_gemm<double>(ar, g, s));
           for (Prob* pr : act) {
-            if (pass >= pr->rwin) continue;
+            if (pass >= step_win(pr)) continue;
             std::swap(pr->x, pr->q);
             std::swap(pr->y, pr->f);
           }

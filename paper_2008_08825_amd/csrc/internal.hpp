@@ -282,6 +282,10 @@ constexpr double kRefineDelta = 1.0e-10;
 constexpr double kRefineStop = 1.0e-6;
 // Window passes per refinement step (boundaries at 0, then shifted by 32).
 constexpr int kWindowPasses = 2;
+// A step after one whose first-order correction was at most this runs no
+// windows: the rotations left inside near-degenerate groups are then of the
+// order of that correction's square, well inside the first-order regime.
+constexpr double kWindowStop = 1.0e-4;
 struct RefineWork {
   double2 *Q = nullptr, *F = nullptr, *P1 = nullptr, *P2 = nullptr, *Ex = nullptr, *Ey = nullptr;
   double *ritz = nullptr, *dots = nullptr, *maxcorr = nullptr;

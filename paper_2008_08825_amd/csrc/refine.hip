@@ -412,7 +412,8 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
       passes = strong > 0 ? w.windows : 0;
       if (getenv("BSE_DEBUG")) fprintf(stderr, "[bse] refinement step %d: %d strongly coupled pairs\n", it + 1, strong);
     }
-    for (int pass = 0; pass < passes; ++pass) {
+    const int step_passes = (it == 0 || *max_corr > kWindowStop) ? passes : 0;
+    for (int pass = 0; pass < step_passes; ++pass) {
       // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
       const int off = (pass & 1) ? 32 : 0;
       double2* Cb = window_blocks(w.Cb0, n, pass);
@@ -430,7 +431,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     if ((e = launch_one<UpdRqOp>(ua, (n + 255) / 256, 0, s)) != hipSuccess) return e;
     // the window rotations precede the first-order correction:
     // x <- x C_1 C_2 ... C_p (I + E11 + E21), y <- y C_1 ... C_p (I + E11 - E21)
-    for (int pass = 0; pass < passes; ++pass) {
+    for (int pass = 0; pass < step_passes; ++pass) {
       const int off = (pass & 1) ? 32 : 0;
       const double2* Cb = window_blocks(w.Cb0, n, pass);
       std::vector<GemmDesc> g;
