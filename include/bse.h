@@ -158,6 +158,8 @@ typedef struct {
                            (lambda_n ||x_k||_2) over the returned pairs (lambda_n
                            the largest eigenvalue), else 0                    */
   double refine_corr[8];  /* MIXED: largest correction of each refinement step */
+  int refine_window_steps;  /* MIXED: refinement steps that ran the Rayleigh-Ritz
+                             window passes                                     */
 } bse_info_t;
 
 /* Fill `opts` with the defaults (route SVD, FP64, lower triangles). */

@@ -72,6 +72,7 @@ class BSEInfo(ctypes.Structure):
         ("sigma_orth_fro", ctypes.c_double),
         ("max_rel_resid", ctypes.c_double),
         ("refine_corr", ctypes.c_double * 8),
+        ("refine_window_steps", ctypes.c_int),
     ]
 
     def as_dict(self):
@@ -101,6 +102,7 @@ class BSEInfo(ctypes.Structure):
             "sigma_orth_fro": self.sigma_orth_fro,
             "max_rel_resid": self.max_rel_resid,
             "refine_corr": list(self.refine_corr[: max(0, min(8, self.refine_steps_done))]),
+            "refine_window_steps": self.refine_window_steps,
         }
 
 

@@ -91,7 +91,7 @@ struct Prob {
   int status = 0;
   // mixed refinement state
   double2 *x = nullptr, *y = nullptr, *q = nullptr, *f = nullptr;
-  int rsteps = 0, rdone = 0, rbad = 0, rwin = 0;
+  int rsteps = 0, rdone = 0, rbad = 0, rwin = 0, rwsteps = 0;
   double rcorr = 0.0;
   double rhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -658,6 +658,8 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
               if (!pr->rwin) pr->rwin = counts[pr->idx] > 0 ? kWindowPasses : 0;
           }
         }
+        for (Prob* pr : act)
+          if (step_win(pr) > 0) pr->rwsteps += 1;
         for (int pass = 0; pass < kWindowPasses; ++pass) {
           // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
           const int off = (pass & 1) ? 32 : 0;
@@ -851,6 +853,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       inf->inner_rotations = js.inner_rotations;
       inf->refine_delta = pr.rcorr;
       inf->refine_steps_done = pr.rsteps;
+      inf->refine_window_steps = pr.rwsteps;
       for (int k = 0; k < 8; ++k) inf->refine_corr[k] = pr.rhist[k];
     }
   }

@@ -504,7 +504,9 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   double maxcorr = 0.0;
   int steps_done = 0;
   double hist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  BSE_TRY(refine_z(n, ld, M1, M2, &x, &y, rw, steps, kRefineStop, lamu, scl, &maxcorr, &steps_done, s, hist));
+  int win_steps = 0;
+  BSE_TRY(refine_z(n, ld, M1, M2, &x, &y, rw, steps, kRefineStop, lamu, scl, &maxcorr, &steps_done, s, hist,
+                   &win_steps));
   BSE_TRY(sort_lambda(n, lamu, perm, lambda, o.want_negative, s));
   if (!o.values_only)
     BSE_TRY(assemble_z(n, x, y, ld, perm, scl, static_cast<double2*>(X), ldx, o.want_negative, s));
@@ -519,6 +521,7 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   if (info) {
     info->refine_delta = maxcorr;
     info->refine_steps_done = steps_done;
+    info->refine_window_steps = win_steps;
     for (int i = 0; i < 8; ++i) info->refine_corr[i] = hist[i];
   }
   tm.fill(info, slots);

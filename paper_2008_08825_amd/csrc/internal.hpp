@@ -313,7 +313,8 @@ hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const 
 // corr_hist (host, optional): the largest correction of each step (first 8).
 hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** x, double2** y,
                     const RefineWork& w, int max_steps, double stop_corr, double* lam, double* scl,
-                    double* max_corr, int* steps_done, hipStream_t s, double* corr_hist = nullptr);
+                    double* max_corr, int* steps_done, hipStream_t s, double* corr_hist = nullptr,
+                    int* window_steps = nullptr);
 
 // out[:, r] = W[:, perm r] * f_r (r < n; zero for r >= n; np rows; f == nullptr: 1).
 hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* perm,

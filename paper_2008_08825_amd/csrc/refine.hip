@@ -357,7 +357,7 @@ hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const 
 hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** xp,
                     double2** yp, const RefineWork& w, int max_steps, double stop_corr, double* lam,
                     double* scl, double* max_corr, int* steps_done, hipStream_t s,
-                    double* corr_hist) {
+                    double* corr_hist, int* window_steps) {
   double2* x = *xp;
   double2* y = *yp;
   double2* Q = w.Q;
@@ -365,6 +365,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
   hipError_t e;
   *max_corr = 0.0;
   *steps_done = 0;
+  if (window_steps) *window_steps = 0;
   Arena ar;
   ar.dev = w.arena;
   ar.cap = w.arena_cap;
@@ -413,6 +414,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
       if (getenv("BSE_DEBUG")) fprintf(stderr, "[bse] refinement step %d: %d strongly coupled pairs\n", it + 1, strong);
     }
     const int step_passes = (it == 0 || *max_corr > kWindowStop) ? passes : 0;
+    if (window_steps && step_passes > 0) ++*window_steps;
     for (int pass = 0; pass < step_passes; ++pass) {
       // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
       const int off = (pass & 1) ? 32 : 0;

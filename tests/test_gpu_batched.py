@@ -66,6 +66,32 @@ def test_batched_equals_single_with_same_tiles(gpu_lib, precision):
         assert info["sweeps"] == infos[i]["sweeps"] and info["rotations"] == infos[i]["rotations"]
 
 
+def test_batched_mixed_windows_on_clustered_problems(gpu_lib):
+    """Clustered spectra take the refinement's Rayleigh-Ritz window passes (grouped window
+    eigensolvers and block GEMMs) in a batch: bit for bit the single solves' results (same
+    tiles), the same window steps, and the oracle's eigenvalues."""
+    # four tight clusters with weak coupling: at n ~ 1000 the complex64 start leaves pairs whose
+    # first-order rotation exceeds 1/16 of their gap (what switches the windows on)
+    sizes = [1024, 520, 300]
+    tiles = [(320, 1, 64), (576, 1, 64), (1024, 4, 128)]
+    problems = [inputs.clustered(n, seed=700 + i, clusters=4, width=1e-5, c_norm=1e-3, b_norm=1e-2)
+                for i, n in enumerate(sizes)]
+    As, Bs = to_dev(problems)
+    print("[gpu] batched mixed, clustered problems", flush=True)
+    res, infos, st = gpu_lib.solve_batched(As, Bs, precision="mixed", tiles=tiles)
+    assert st == 0
+    assert any(i["refine_window_steps"] > 0 for i in infos), [i["refine_window_steps"] for i in infos]
+    for i, (lam_b, X_b) in enumerate(host(res)):
+        lam, X, info = gpu_lib.solve_h1(As[i], Bs[i], precision="mixed", tiles=tiles)
+        assert np.array_equal(lam.cpu().numpy(), lam_b)
+        assert np.array_equal(X.resolve_conj().cpu().numpy(), X_b)
+        assert info["refine_window_steps"] == infos[i]["refine_window_steps"]
+        assert info["refine_steps_done"] == infos[i]["refine_steps_done"]
+        assert info["fallback"] == 0
+        lam_o = ob.eigenvalues_chol_svd(*problems[i])
+        assert om.rel_eig_err(lam_b, lam_o) < 1e-12
+
+
 def test_batched_status_per_problem(gpu_lib):
     """One problem with A - B indefinite: its status is reported, the others are solved."""
     good = [inputs.coupled(n, seed=500 + n) for n in (40, 90)]
