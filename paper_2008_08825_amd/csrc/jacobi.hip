@@ -66,7 +66,10 @@ BSE_DEV int pair_col(int p, int q, int c) { return c < JB ? p * JB + c : q * JB 
 template <typename T>
 struct GramOp {
   static constexpr int NT = 256;
-  static constexpr int MIN_WAVES = 4;  // four workgroups per CU: 1024 of them fill the chip once
+  // four workgroups per CU: 1024 of them fill the chip once.  Complex128 then
+  // spills 52 bytes per lane at 128 registers; a bound of three (no spill, 153
+  // registers, three workgroups per CU) makes the kernel 14 % slower.
+  static constexpr int MIN_WAVES = 4;
   typedef GramArgs<typename cpx_t<T>::type> Args;
   static BSE_DEV void run(const Args& a, int bx, int t);
 };
@@ -774,7 +777,10 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
 template <typename T>
 struct RotOp {
   static constexpr int NT = 256;
-  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : 4;  // what the LDS for R allows
+  // what the LDS for R allows; complex64 runs four waves per SIMD either way,
+  // and a bound of three lets the compiler fit 126 registers without the
+  // 12-byte spill that a bound of four forces (1 % faster)
+  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : 3;
   typedef RotArgs<typename cpx_t<T>::type> Args;
   static BSE_DEV void run(const Args& a, int bx, int t);
 };
