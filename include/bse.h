@@ -234,6 +234,10 @@ size_t bse_backward_workspace_bytes(int n);
  * With x = a - b and y = a + b the sums equal G_A = (P + Q)/2 and
  * G_B = (Q - P)/2 for P = x diag(w) x^H, Q = y diag(w) y^H, so the work is two
  * Hermitian rank-n products (lower tiles only), about 8 n^3 real flops.
+ * Inside a cluster of equal eigenvalues the derivative of an individual
+ * eigenvalue is not defined; the result is the gradient of L when w is
+ * constant on each such cluster (a loss of the cluster's sum), and depends on
+ * the basis chosen inside the cluster otherwise.
  * Synchronises on stream before returning.
  * Return codes as above (0, -i, <= -1000). */
 int bse_backward(int n, const void* X, int ldx, const double* w,
