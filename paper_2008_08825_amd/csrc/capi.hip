@@ -442,6 +442,7 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   rw.arena_cap = refine_arena_bytes(np);
   rw.perm = perm;
   rw.windows = kWindowPasses;
+  rw.low_update = 1;
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 20;
   const int steps = o.refine_steps > 0 ? o.refine_steps : 8;

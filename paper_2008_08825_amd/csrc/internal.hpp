@@ -295,6 +295,9 @@ struct RefineWork {
   char* arena = nullptr;
   size_t arena_cap = 0;
   int windows = 0;         // window passes per step once a step finds strongly coupled pairs (0: none)
+  // nonzero: the basis updates of all steps but the last take complex64
+  // products (Q, F, Ex and Ey must each hold ld x n complex128 values)
+  int low_update = 0;
   int* perm = nullptr;  // n ints: the ascending order of the start's eigenvalues
 };
 // Block GEMMs of a window pass over the first n pairs (windows of offset

@@ -262,6 +262,51 @@ struct CoupleOp {
   }
 };
 
+// Complex64 operands of a basis update that is not the refinement's last:
+// x, y, Ex - I and Ey - I (their n x n blocks); a 64 x 64 tile of one of the
+// four matrices per work group.
+struct LowArgs { int n; long ld; const double2* src[4]; float2* dst[4]; };
+struct LowOp {
+  static constexpr int NT = 256;
+  typedef LowArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int T = (a.n + 63) / 64;
+    const int mat = bx / (T * T), t = bx % (T * T);
+    const int i = (t % T) * 64 + (threadIdx.x & 63), j0 = (t / T) * 64 + (threadIdx.x >> 6);
+    if (i >= a.n) return;
+    const double2* __restrict__ S = a.src[mat];
+    float2* __restrict__ D = a.dst[mat];
+    const double one = mat >= 2 ? 1.0 : 0.0;
+    for (int j = j0; j < j0 + 64 && j < a.n; j += 4) {
+      double2 v = S[i + (long)j * a.ld];
+      if (i == j) v.x -= one;
+      D[i + (long)j * a.ld] = make_float2((float)v.x, (float)v.y);
+    }
+  }
+};
+
+// x += Px and y += Py, with Px = x (Ex - I) and Py = y (Ey - I) in complex64.
+struct AddLowArgs { int n; long ld; const float2* src[2]; double2* dst[2]; };
+struct AddLowOp {
+  static constexpr int NT = 256;
+  typedef AddLowArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int T = (a.n + 63) / 64;
+    const int mat = bx / (T * T), t = bx % (T * T);
+    const int i = (t % T) * 64 + (threadIdx.x & 63), j0 = (t / T) * 64 + (threadIdx.x >> 6);
+    if (i >= a.n) return;
+    const float2* __restrict__ S = a.src[mat];
+    double2* __restrict__ D = a.dst[mat];
+    for (int j = j0; j < j0 + 64 && j < a.n; j += 4) {
+      const float2 p = S[i + (long)j * a.ld];
+      double2 v = D[i + (long)j * a.ld];
+      v.x += (double)p.x;
+      v.y += (double)p.y;
+      D[i + (long)j * a.ld] = v;
+    }
+  }
+};
+
 GemmDesc nn(int n, long ld, const double2* A, int opA, const double2* B, int opB, double2* C) {
   GemmDesc g;
   g.M = n; g.N = n; g.K = n;
@@ -443,18 +488,44 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
       double2* t = x; x = Q; Q = t;
       t = y; y = F; F = t;
     }
-    if ((e = gemm_z(nn(n, ld, x, 0, w.Ex, 0, Q), s)) != hipSuccess) return e;    // x (I + E11 + E21)
-    if ((e = gemm_z(nn(n, ld, y, 0, w.Ey, 0, F), s)) != hipSuccess) return e;    // y (I + E11 - E21)
-    double2* t = x; x = Q; Q = t;
-    t = y; y = F; F = t;
+    // the step's correction, known before its basis update: its first-order
+    // part (the window rotations also turn bases inside subspaces of nearly
+    // equal eigenvalues, where any basis is as good, so they do not measure
+    // the distance to convergence)
     double mcs[3] = {0.0, 0.0, 0.0};
     e = hipMemcpyAsync(mcs, w.maxcorr, 3 * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return e;
-    // the step's correction: its first-order part (the window rotations also
-    // turn bases inside subspaces of nearly equal eigenvalues, where any basis
-    // is as good, so they do not measure the distance to convergence)
     const double mc = mcs[0];
+    const bool last = mc <= stop_corr || it + 1 == max_steps;
+    if (w.low_update && !last) {
+      // x <- x + x (Ex - I), y <- y + y (Ey - I) with the products in
+      // complex64: their rounding error, about 1e-6 of the correction, is
+      // far below the error the step leaves (the correction's square, or the
+      // next correction) and is removed by the next step's FP64 products;
+      // the last step's update stays FP64.  Q and F hold the operands, Ex and
+      // Ey the products (two complex64 n x n matrices fit in each).
+      float2* xc = reinterpret_cast<float2*>(Q);
+      float2* exc = reinterpret_cast<float2*>(F);
+      float2* px = reinterpret_cast<float2*>(w.Ex);
+      float2* py = reinterpret_cast<float2*>(w.Ey);
+      const long half = ld * (long)n;
+      const LowArgs la = {n, ld, {x, y, w.Ex, w.Ey}, {xc, xc + half, exc, exc + half}};
+      if ((e = launch_one<LowOp>(la, 4 * T * T, 0, s)) != hipSuccess) return e;
+      GemmDesc gx = nn(n, ld, nullptr, 0, nullptr, 0, nullptr);
+      GemmDesc gy = gx;
+      gx.A = xc; gx.B = exc; gx.C = px;
+      gy.A = xc + half; gy.B = exc + half; gy.C = py;
+      if ((e = gemm_c(gx, s)) != hipSuccess) return e;
+      if ((e = gemm_c(gy, s)) != hipSuccess) return e;
+      const AddLowArgs aa = {n, ld, {px, py}, {x, y}};
+      if ((e = launch_one<AddLowOp>(aa, 2 * T * T, 0, s)) != hipSuccess) return e;
+    } else {
+      if ((e = gemm_z(nn(n, ld, x, 0, w.Ex, 0, Q), s)) != hipSuccess) return e;    // x (I + E11 + E21)
+      if ((e = gemm_z(nn(n, ld, y, 0, w.Ey, 0, F), s)) != hipSuccess) return e;    // y (I + E11 - E21)
+      double2* t = x; x = Q; Q = t;
+      t = y; y = F; F = t;
+    }
     bad = mcs[2];
     *max_corr = mc;
     *steps_done = it + 1;
