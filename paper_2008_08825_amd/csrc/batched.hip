@@ -110,7 +110,7 @@ size_t arena_bytes(const std::vector<int>& nps) {
   for (int np : nps) {
     const int pairs = np / 64;
     size_t b = (size_t)2 * tiles64(np);
-    b = std::max(b, (size_t)3 * tiles64(np));
+    b = std::max(b, (size_t)4 * tiles64(np));
     b = std::max(b, (size_t)2 * cols_blocks(np, np));
     b = std::max(b, (size_t)pairs * jacobi_default_kc(np));
     b = std::max(b, (size_t)pairs * (np / 64));
@@ -705,25 +705,56 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
             std::swap(pr->y, pr->f);
           }
         }
-        for (Prob* pr : act) {
-          const int nn = pr->n;
-          const long ld = pr->np;
-          GemmDesc d;
-          d.M = nn; d.N = nn; d.K = nn;
-          d.A = pr->x; d.lda = ld; d.opA = 0;
-          d.B = pr->at<double2>(pr->p.off_lc); d.ldb = ld; d.opB = 0;
-          d.C = pr->q; d.ldc = ld;
-          upd.push_back(d);                                  // x (I + E11 + E21)
-          d.A = pr->y; d.B = pr->at<double2>(pr->p.off_wc); d.C = pr->f;
-          upd.push_back(d);                                  // y (I + E11 - E21)
-        }
-        BSE_TRY(run_gemm<double>(ar, upd, s));
+        // the step's corrections, known before the basis updates: as refine_z,
+        // all but a problem's last step update in complex64
         std::vector<double> corr(2 * batch, 0.0);
         BSE_TRY(hipMemcpyAsync(corr.data(), d_corr, (size_t)2 * batch * sizeof(double), hipMemcpyDeviceToHost, s));
         BSE_TRY(hipStreamSynchronize(s));
+        std::vector<char> low(batch, 0);
+        Grp<LowArgs> lw;
+        Grp<AddLowArgs> al;
+        std::vector<GemmDesc> lowg;
         for (Prob* pr : act) {
-          std::swap(pr->x, pr->q);
-          std::swap(pr->y, pr->f);
+          const int nn = pr->n;
+          const long ld = pr->np;
+          double2* Ex = pr->at<double2>(pr->p.off_lc);
+          double2* Ey = pr->at<double2>(pr->p.off_wc);
+          GemmDesc d;
+          d.M = nn; d.N = nn; d.K = nn;
+          d.lda = ld; d.opA = 0;
+          d.ldb = ld; d.opB = 0;
+          d.ldc = ld;
+          low[pr->idx] = !(corr[pr->idx] <= kRefineStop || pr->rsteps + 1 == max_steps);
+          if (low[pr->idx]) {
+            // operands in q and f, products in Ex and Ey (two complex64 matrices in each)
+            const int T = (nn + 63) / 64;
+            const long half = ld * (long)nn;
+            float2* xc = reinterpret_cast<float2*>(pr->q);
+            float2* exc = reinterpret_cast<float2*>(pr->f);
+            float2* px = reinterpret_cast<float2*>(Ex);
+            float2* py = reinterpret_cast<float2*>(Ey);
+            lw.add({nn, ld, {pr->x, pr->y, Ex, Ey}, {xc, xc + half, exc, exc + half}}, 4 * T * T);
+            d.A = xc; d.B = exc; d.C = px;
+            lowg.push_back(d);                               // x (Ex - I)
+            d.A = xc + half; d.B = exc + half; d.C = py;
+            lowg.push_back(d);                               // y (Ey - I)
+            al.add({nn, ld, {px, py}, {pr->x, pr->y}}, 2 * T * T);
+          } else {
+            d.A = pr->x; d.B = Ex; d.C = pr->q;
+            upd.push_back(d);                                // x (I + E11 + E21)
+            d.A = pr->y; d.B = Ey; d.C = pr->f;
+            upd.push_back(d);                                // y (I + E11 - E21)
+          }
+        }
+        BSE_TRY(run_op(ar, lw, group_refine, G_LOW, 0, s));
+        BSE_TRY(run_gemm<float>(ar, lowg, s));
+        BSE_TRY(run_op(ar, al, group_refine, G_ADDLOW, 0, s));
+        BSE_TRY(run_gemm<double>(ar, upd, s));
+        for (Prob* pr : act) {
+          if (!low[pr->idx]) {
+            std::swap(pr->x, pr->q);
+            std::swap(pr->y, pr->f);
+          }
           if (pr->rsteps < 8) pr->rhist[pr->rsteps] = corr[pr->idx];
           pr->rsteps += 1;
           pr->rcorr = corr[pr->idx];

@@ -260,6 +260,12 @@ inline __host__ __device__ void window_range(int n, int off, int w, int& a, int&
 // a cluster the pairwise rotations leave errors of the order of its square).
 // Work group = 256 rows i.
 constexpr double kCoupleRatio = 16.0;
+// Complex64 operands of a refinement step's basis update when it is not the
+// last: dst[k] = src[k] (k = 0, 1: x, y) and src[k] - I (k = 2, 3: Ex, Ey),
+// n x n blocks, work group = a 64 x 64 tile of one matrix (4 ceil(n/64)^2).
+struct LowArgs { int n; long ld; const double2* src[4]; float2* dst[4]; };
+// dst[k] += src[k] (complex64 into complex128), k = 0, 1 (2 ceil(n/64)^2 work groups).
+struct AddLowArgs { int n; long ld; const float2* src[2]; double2* dst[2]; };
 struct CoupleArgs {
   int n; long ld; const double2* F; const double2* P1; const double2* P2; const double* ritz;
   int* count;
@@ -486,7 +492,7 @@ enum GroupOp {
   G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
   G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
   G_WRITE_LAMBDA, G_C64, G_ASSEMBLE, G_GATHER,
-  G_RITZ, G_BUILD, G_RQ, G_UPDRQ, G_COUPLE,                             // refine.hip
+  G_RITZ, G_BUILD, G_RQ, G_UPDRQ, G_COUPLE, G_LOW, G_ADDLOW,                             // refine.hip
 };
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
 hipError_t group_jacobi(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);

@@ -265,7 +265,6 @@ struct CoupleOp {
 // Complex64 operands of a basis update that is not the refinement's last:
 // x, y, Ex - I and Ey - I (their n x n blocks); a 64 x 64 tile of one of the
 // four matrices per work group.
-struct LowArgs { int n; long ld; const double2* src[4]; float2* dst[4]; };
 struct LowOp {
   static constexpr int NT = 256;
   typedef LowArgs Args;
@@ -286,7 +285,6 @@ struct LowOp {
 };
 
 // x += Px and y += Py, with Px = x (Ex - I) and Py = y (Ey - I) in complex64.
-struct AddLowArgs { int n; long ld; const float2* src[2]; double2* dst[2]; };
 struct AddLowOp {
   static constexpr int NT = 256;
   typedef AddLowArgs Args;
@@ -326,6 +324,8 @@ hipError_t group_refine(GroupOp op, const void* table, const int2* map, int bloc
     case G_RQ: return launch_grp<RqOp>(table, map, blocks, aux, s);
     case G_UPDRQ: return launch_grp<UpdRqOp>(table, map, blocks, aux, s);
     case G_COUPLE: return launch_grp<CoupleOp>(table, map, blocks, aux, s);
+    case G_LOW: return launch_grp<LowOp>(table, map, blocks, aux, s);
+    case G_ADDLOW: return launch_grp<AddLowOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }
