@@ -887,7 +887,11 @@ BSE_DEV void RotOp<T>::run(const typename RotOp<T>::Args& a, int bx, int t) {
   const int* __restrict__ flags = a.flags;
   __shared__ C2 Rs[JP * rot_ld<T>()];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int k = bx / chunks, chunk = bx % chunks;
+  // pairs in descending order: the Gram launch before this one read them in
+  // ascending order, so the most recently read blocks come first (and the
+  // next round's ascending Gram starts with the most recently written ones),
+  // which the memory-side cache may still hold
+  const int k = N / 2 - 1 - bx / chunks, chunk = bx % chunks;
   if (!flags[k]) return;
   int p, q;
   round_pair(N, t, k, p, q);
