@@ -248,7 +248,7 @@ def bench_batched(api, inputs, steps, warmup):
            "sum_n3": sum(float(n) ** 3 for n in ns),
            "tiles": "autotuned table paper_2008_08825_amd/tiles_gfx950.json"}
     lam_by = {}
-    for prec in ("mixed", "fp64"):
+    for prec in ("mixed", "mixed_polish", "fp64"):
         need = api.batched_workspace_bytes(ns, precision=prec, tiles=tiles)
         work = torch.empty(need, dtype=torch.uint8, device=dev)
         for _ in range(warmup):
@@ -274,8 +274,10 @@ def bench_batched(api, inputs, steps, warmup):
         log(f"batched {prec}: {sec:.3f}s per batch, status {st}")
         del res, work
     out["problems_per_second_mixed"] = round(len(ns) / out["mixed"]["seconds_per_batch"], 1)
-    out["worst_problem_rel_eig_diff_mixed_vs_fp64"] = max(
-        ((a - b).abs() / b).max().item() for a, b in zip(lam_by["mixed"], lam_by["fp64"]))
+    out["problems_per_second_mixed_polish"] = round(len(ns) / out["mixed_polish"]["seconds_per_batch"], 1)
+    for prec in ("mixed", "mixed_polish"):
+        out[f"worst_problem_rel_eig_diff_{prec}_vs_fp64"] = max(
+            ((a - b).abs() / b).max().item() for a, b in zip(lam_by[prec], lam_by["fp64"]))
     # the oracle on a bounded sample of the batch (problems in index order, about 10 s)
     from oracle import bse as ob
     t0 = time.perf_counter()

@@ -35,6 +35,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <vector>
 
 #include "../../include/bse.h"
@@ -92,6 +93,11 @@ struct Prob {
   // mixed refinement state
   double2 *x = nullptr, *y = nullptr, *q = nullptr, *f = nullptr;
   int rsteps = 0, rdone = 0, rbad = 0, rwin = 0, rwsteps = 0;
+  // polish state: status word after the Cholesky of V'^H V', the columns the FP64 sweeps
+  // orthogonalise, the first sweep's inner stopping level, and whether W was re-formed
+  int gst = 0, fallback = 0;
+  double2* zb = nullptr;
+  double first = 0.0;
   double rcorr = 0.0;
   double rhist[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   template <class T> T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
@@ -167,6 +173,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
                           void* const* X, const int* ldx, void* work, const bse_opts_t& o,
                           bse_info_t* info, int want_timing, hipStream_t s) {
   const bool mixed = o.precision == BSE_PREC_MIXED;
+  const bool polish = o.precision == BSE_PREC_MIXED_POLISH;
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   char* wbase = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
 
@@ -210,7 +217,9 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   ar.s = s;
 
   Timer tm(want_timing != 0, s);
-  const int slots[8] = {0, 1, 2, 3, 4, 5, 6, -1};
+  // the polished form's FP64 stage (between the complex64 Jacobi and the
+  // finalize) is timed as the refinement, as in the single solve
+  const int slots[8] = {0, 1, 2, 3, polish ? 6 : 4, polish ? 4 : 5, polish ? 5 : 6, -1};
   tm.mark();
   // ---- header: statuses "no failure", zero Jacobi states and corrections
   {
@@ -250,17 +259,17 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   }
   tm.mark();
 
-  // ---- blocked Cholesky of both factors of every problem, two panels at a time
-  // (as the single solve: factor panel j0, update the next column block with
-  // it, factor panel j0 + 64, update the rest with both, K = 128)
-  {
-    const int kmax = probs[0].np / 64;
+  // ---- blocked Cholesky, two panels at a time (as the single solve: factor
+  // panel j0, update the next column block with it, factor panel j0 + 64,
+  // update the rest with both, K = 128), of nf factors of every problem of
+  // `list` (largest padded order first); a failure writes base + column into
+  // the problem's status word
+  typedef std::function<void*(const Prob&, int)> FactorFn;
+  auto cholesky_phase = [&](const std::vector<Prob*>& list, int nf, const FactorFn& factor_of,
+                            const std::function<int(const Prob&, int)>& base_of) -> int {
+    if (list.empty()) return 0;
+    const int kmax = list[0]->np / 64;
     const size_t es = mixed ? sizeof(float2) : sizeof(double2);
-    auto factor_of = [&](const Prob& pr, int f) -> void* {
-      const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
-      return mixed ? static_cast<void*>(pr.base + pr.p.off_lc + (f ? half : 0))
-                   : static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_m1));
-    };
     auto linv_of = [&](const Prob& pr, int f) -> void* {
       return pr.base + pr.p.off_linv + (size_t)f * 64 * 64 * es;
     };
@@ -273,18 +282,19 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       std::vector<GemmDesc> trsm;
       Grp<Potf2Args<double2>> gz;
       Grp<Potf2Args<float2>> gc;
-      for (const Prob& pr : probs) {
+      for (const Prob* pp : list) {
+        const Prob& pr = *pp;
         if (pr.np <= j0) break;
-        for (int f = 0; f < 2; ++f) {
+        for (int f = 0; f < nf; ++f) {
           void* M = factor_of(pr, f);
           void* linv = linv_of(pr, f);
           if (mixed) {
             const Potf2Args<float2> a = {static_cast<float2*>(M), pr.np, static_cast<float2*>(linv),
-                                         d_status + pr.idx, f ? pr.n : 0, pr.n};
+                                         d_status + pr.idx, base_of(pr, f), pr.n};
             gc.add(a, 1);
           } else {
             const Potf2Args<double2> a = {static_cast<double2*>(M), pr.np, static_cast<double2*>(linv),
-                                          d_status + pr.idx, f ? pr.n : 0, pr.n};
+                                          d_status + pr.idx, base_of(pr, f), pr.n};
             gz.add(a, 1);
           }
           const int rows = pr.np - j0 - 64;
@@ -315,10 +325,11 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       const int j0 = 64 * k;
       if (int e = factor_panels(j0)) return e;
       std::vector<GemmDesc> next, rest;
-      for (const Prob& pr : probs) {
+      for (const Prob* pp : list) {
+        const Prob& pr = *pp;
         const int rows = pr.np - j0 - 64;
         if (rows <= 0) break;
-        for (int f = 0; f < 2; ++f) {
+        for (int f = 0; f < nf; ++f) {
           void* M = factor_of(pr, f);
           GemmDesc h;  // next column block: A[j0+64.., j0+64..j0+128] -= L21 L21[0..64]^H
           h.M = rows; h.N = 64; h.K = 64;
@@ -344,10 +355,29 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       if (!rest.empty())
         if (int e = run_updates(rest)) return e;
     }
+    return 0;
+  };
+  auto read_statuses = [&]() -> int {
     std::vector<int> st(batch, kBig);
     BSE_TRY(hipMemcpyAsync(st.data(), d_status, (size_t)batch * sizeof(int), hipMemcpyDeviceToHost, s));
     BSE_TRY(hipStreamSynchronize(s));
-    for (Prob& pr : probs) pr.status = st[pr.idx] == kBig ? 0 : st[pr.idx];
+    for (Prob& pr : probs) pr.gst = st[pr.idx];
+    return 0;
+  };
+
+  // ---- Cholesky factors L1 L1^H = A + B and L2 L2^H = A - B of every problem (Alg. 3 steps 1-2)
+  {
+    std::vector<Prob*> all;
+    for (Prob& pr : probs) all.push_back(&pr);
+    const FactorFn factor_of = [&](const Prob& pr, int f) -> void* {
+      const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
+      return mixed ? static_cast<void*>(pr.base + pr.p.off_lc + (f ? half : 0))
+                   : static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_m1));
+    };
+    if (int e = cholesky_phase(all, 2, factor_of, [](const Prob& pr, int f) { return f ? pr.n : 0; }))
+      return e;
+    if (int e = read_statuses()) return e;
+    for (Prob& pr : probs) pr.status = pr.gst == kBig ? 0 : pr.gst;
   }
   std::vector<Prob*> ok;
   for (Prob& pr : probs)
@@ -368,14 +398,28 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     }
     if (mixed) BSE_TRY(run_gemm<float>(ar, w, s));
     else BSE_TRY(run_gemm<double>(ar, w, s));
+    if (polish) {
+      // the polished form iterates on a complex64 copy of W (in X1)
+      Grp<ToC64Args> c;
+      for (Prob* pr : ok)
+        c.add({pr->np, pr->at<double2>(pr->p.off_w), pr->np, pr->at<float2>(pr->p.off_x1)}, tiles64(pr->np));
+      BSE_TRY(run_op(ar, c, group_chol, G_ZTOC, 0, s));
+    }
   }
   tm.mark();
 
-  // ---- one-sided block Jacobi over the whole batch
-  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : (mixed ? 20 : 30);
+  // ---- one-sided block Jacobi over the problems of `list` (largest padded
+  // order first), complex64 (c64) or FP64, on each problem's W_of matrix;
+  // per problem tolerance tol_of and first sweep's inner level first_of
+  // (0: the default); leaves every problem's sweep state in `states`
   const double eps32 = 1.1920928955078125e-07;
   std::vector<JacState> states(batch);
-  if (!ok.empty()) {
+  auto jacobi_phase = [&](const std::vector<Prob*>& list, bool c64, int msweeps, double floor,
+                          double stop_fraction, const std::function<void*(Prob*)>& W_of,
+                          const std::function<double(Prob*)>& tol_of,
+                          const std::function<double(Prob*)>& first_of) -> int {
+    BSE_TRY(hipMemsetAsync(d_state, 0, (size_t)batch * sizeof(JacState), s));
+    if (list.empty()) return 0;
     Grp<GramArgs<double2>> gz;
     Grp<GramArgs<float2>> gc;
     Grp<EigArgs<double2>> ez;
@@ -384,20 +428,19 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     Grp<RotArgs<float2>> rc;
     Grp<SweepArgs> sw;
     std::vector<int> rounds;
-    for (Prob* pr : ok) {
+    for (Prob* pr : list) {
       const int np = pr->np;
       JacobiWork jw;
-      jacobi_carve(np, mixed ? sizeof(float) : sizeof(double), pr->base + pr->p.off_jac, jw, pr->kc,
+      jacobi_carve(np, c64 ? sizeof(float) : sizeof(double), pr->base + pr->p.off_jac, jw, pr->kc,
                    pr->rrows);
       JacState* st = d_state + pr->idx;
       jw.counter = &st->counter;
       jw.inner = &st->inner;
       jw.inner_rot = &st->inner_rot;
       jw.maxoff = &st->maxoff;
-      const double nn = (double)(pr->n > 64 ? pr->n : 64);
-      const double tol = o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : default_tol64(pr->n));
-      if (mixed) {
-        float2* W = pr->at<float2>(pr->p.off_wc);
+      const double tol = tol_of(pr);
+      if (c64) {
+        float2* W = static_cast<float2*>(W_of(pr));
         GramArgs<float2> ga = gram_args_c(np, W, np, jw, &st->done);
         EigArgs<float2> ea = eig_args_c(np, jw, tol, &st->stop2, &st->done);
         ga.crossp = ea.crossp = &st->cross;
@@ -405,7 +448,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         ec.add(ea, jacobi_eig_blocks(np));
         rc.add(rot_args_c(np, W, np, jw, &st->done), jacobi_rot_blocks_rr(np, jw.rrows));
       } else {
-        double2* W = pr->at<double2>(pr->p.off_w);
+        double2* W = static_cast<double2*>(W_of(pr));
         GramArgs<double2> ga = gram_args_z(np, W, np, jw, &st->done);
         EigArgs<double2> ea = eig_args_z(np, jw, tol, &st->stop2, &st->done);
         ga.crossp = ea.crossp = &st->cross;
@@ -413,18 +456,17 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         ez.add(ea, jacobi_eig_blocks(np));
         rz.add(rot_args_z(np, W, np, jw, &st->done), jacobi_rot_blocks_rr(np, jw.rrows));
       }
-      const SweepArgs sa = {st, d_active, jacobi_pairs(np) * jacobi_rounds(np), max_sweeps,
-                            mixed ? 1.0e-5 : 1.0e-10, 1, 1.0,
-                            mixed ? kTrackLevel32 : kTrackLevel64, jacobi_pairs(np),
-                            mixed ? 1.0 / 32 : 0.0};
+      const SweepArgs sa = {st, d_active, jacobi_pairs(np) * jacobi_rounds(np), msweeps, floor, 1, 1.0,
+                            c64 ? kTrackLevel32 : kTrackLevel64, jacobi_pairs(np), stop_fraction,
+                            first_of(pr)};
       sw.add(sa, 1);
       rounds.push_back(jacobi_rounds(np));
     }
     Dev dg, de, dr, ds;
     // the four tables are read by every sweep's launches: one run of the arena
-    BSE_TRY(ar.reserve(mixed ? staged_bytes(gc) + staged_bytes(ec) + staged_bytes(rc) + staged_bytes(sw)
-                             : staged_bytes(gz) + staged_bytes(ez) + staged_bytes(rz) + staged_bytes(sw)));
-    if (mixed) {
+    BSE_TRY(ar.reserve(c64 ? staged_bytes(gc) + staged_bytes(ec) + staged_bytes(rc) + staged_bytes(sw)
+                           : staged_bytes(gz) + staged_bytes(ez) + staged_bytes(rz) + staged_bytes(sw)));
+    if (c64) {
       BSE_TRY(stage(ar, gc, dg));
       BSE_TRY(stage(ar, ec, de));
       BSE_TRY(stage(ar, rc, dr));
@@ -451,7 +493,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       hipError_t e = hipSuccess;
       for (int t = 0; t < R && e == hipSuccess; ++t) {
         const int c = part[t];
-        if (mixed) {
+        if (c64) {
           e = group_jacobi(G_GRAM_C, dg.tab, dg.map, gc.prefix(c), t, st);
           if (e == hipSuccess) e = group_jacobi(G_EIG_C, de.tab, de.map, ec.prefix(c), t, st);
           if (e == hipSuccess) e = group_jacobi(G_ROT_C, dr.tab, dr.map, rc.prefix(c), t, st);
@@ -495,8 +537,137 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     BSE_TRY(loop_err);
     BSE_TRY(hipMemcpyAsync(states.data(), d_state, (size_t)batch * sizeof(JacState), hipMemcpyDeviceToHost, s));
     BSE_TRY(hipStreamSynchronize(s));
+    return 0;
+  };
+
+  // Alg. 3 step 3's SVD: complex64 for the mixed forms, FP64 otherwise
+  const bool c64_jacobi = mixed || polish;
+  const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : (c64_jacobi ? 20 : 30);
+  {
+    auto tol_of = [&](Prob* pr) {
+      const double nn = (double)(pr->n > 64 ? pr->n : 64);
+      // the polished form's complex64 iteration ignores opts.jacobi_tol (its
+      // FP64 sweeps take it), as the single solve
+      if (polish) return 4.0 * sqrt(nn) * eps32;
+      return o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : default_tol64(pr->n));
+    };
+    auto W_of = [&](Prob* pr) -> void* {
+      return pr->base + (mixed ? pr->p.off_wc : (polish ? pr->p.off_x1 : pr->p.off_w));
+    };
+    if (int e = jacobi_phase(ok, c64_jacobi, max_sweeps, c64_jacobi ? 1.0e-5 : 1.0e-10,
+                             c64_jacobi ? 1.0 / 32 : 0.0, W_of, tol_of, [](Prob*) { return 0.0; }))
+      return e;
   }
   tm.mark();
+  // ---- mixed_polish: the rotation of the complex64 iteration recovered and
+  // finished in FP64, as the single solve (Z = W32 V32 in FP64, V' = L1^-1
+  // L2^-H Z, Cholesky of G = V'^H V', W V = Z L_G^-H, FP64 sweeps); a problem
+  // whose G is not numerically positive definite runs its FP64 sweeps on W itself
+  std::vector<JacState> states32;
+  if (polish && !ok.empty()) {
+    states32 = states;
+    auto M1_of = [](const Prob* pr) { return pr->at<double2>(pr->p.off_m1); };
+    auto M2_of = [](const Prob* pr) { return pr->at<double2>(pr->p.off_m2); };
+    auto W_of = [](const Prob* pr) { return pr->at<double2>(pr->p.off_w); };
+    auto Y_of = [](const Prob* pr) { return pr->at<double2>(pr->p.off_y); };
+    auto X1_of = [](const Prob* pr) { return pr->at<double2>(pr->p.off_x1); };
+    auto X2_of = [](const Prob* pr) { return pr->at<double2>(pr->p.off_x2); };
+    auto inv_of = [](const Prob* pr) { return pr->at<double2>(pr->p.off_inv); };
+    {
+      Grp<C64Args> cv;
+      for (Prob* pr : ok) {
+        const int np = pr->np;
+        const float2* Wc = pr->at<float2>(pr->p.off_x1);
+        cv.add({np, Wc, np, Y_of(pr), np, nullptr}, cols_blocks(np, np));
+        cv.add({np, Wc, np, W_of(pr), np, nullptr}, cols_blocks(np, np));
+      }
+      BSE_TRY(run_op(ar, cv, group_finalize, G_C64, 0, s));
+    }
+    // X1 = L2^-H Z (W overwritten), then W = L1^-1 X1 = V' (X1 overwritten)
+    {
+      Grp<TriInvArgs> ti;
+      std::vector<TrsmStep> steps;
+      for (Prob* pr : ok) {
+        ti.add({M2_of(pr), pr->np, inv_of(pr)}, pr->np / 64);
+        trsm_lh_for_each(pr->np, (const double2*)M2_of(pr), pr->np, W_of(pr), X1_of(pr), inv_of(pr),
+                         [&](const TrsmStep& st) { steps.push_back(st); });
+      }
+      BSE_TRY(run_op(ar, ti, group_chol, G_TRIINV, 0, s));
+      BSE_TRY(run_steps<double>(ar, steps, s));
+    }
+    {
+      Grp<TriInvArgs> ti;
+      std::vector<TrsmStep> steps;
+      for (Prob* pr : ok) {
+        ti.add({M1_of(pr), pr->np, inv_of(pr)}, pr->np / 64);
+        trsm_ln_for_each(pr->np, M1_of(pr), pr->np, X1_of(pr), W_of(pr), inv_of(pr),
+                         [&](const TrsmStep& st) { steps.push_back(st); });
+      }
+      BSE_TRY(run_op(ar, ti, group_chol, G_TRIINV, 0, s));
+      BSE_TRY(run_steps<double>(ar, steps, s));
+    }
+    // G = V'^H V' (lower tiles) in X2, padded, and its Cholesky factor
+    {
+      std::vector<GemmDesc> g;
+      Grp<TriPadArgs> tp;
+      for (Prob* pr : ok) {
+        const int np = pr->np;
+        GemmDesc d;
+        d.M = np; d.N = np; d.K = np;
+        d.A = W_of(pr); d.lda = np; d.opA = 1;
+        d.B = W_of(pr); d.ldb = np; d.opB = 0;
+        d.C = X2_of(pr); d.ldc = np;
+        d.lowerC = 1;
+        g.push_back(d);
+        tp.add({pr->n, np, X2_of(pr), np, 0}, tiles64(np));
+      }
+      BSE_TRY(run_gemm<double>(ar, g, s));
+      BSE_TRY(run_op(ar, tp, group_chol, G_TRIPAD, 0, s));
+    }
+    if (int e = cholesky_phase(ok, 1, [&](const Prob& pr, int) -> void* { return X2_of(&pr); },
+                               [](const Prob&, int) { return 0; }))
+      return e;
+    if (int e = read_statuses()) return e;
+    // BSE_TEST_POLISH_FALLBACK set: every problem takes the branch of a G that
+    // is not positive definite (test hook, as in the single solve)
+    const bool force_fallback = getenv("BSE_TEST_POLISH_FALLBACK") != nullptr;
+    {
+      Grp<TriInvArgs> ti;
+      std::vector<TrsmStep> steps;
+      std::vector<GemmDesc> wg;
+      std::vector<int> reset;
+      for (Prob* pr : ok) {
+        const double nn = (double)(pr->n > 64 ? pr->n : 64);
+        const double tol32 = 4.0 * sqrt(nn) * eps32;
+        if (pr->gst == kBig && !force_fallback) {
+          // W V = Z L_G^-H -> X1 (Y overwritten)
+          ti.add({X2_of(pr), pr->np, inv_of(pr)}, pr->np / 64);
+          trsm_rh_for_each(pr->np, X2_of(pr), pr->np, Y_of(pr), X1_of(pr), inv_of(pr),
+                           [&](const TrsmStep& st) { steps.push_back(st); });
+          pr->zb = X1_of(pr);
+          pr->first = fmin(kInnerStopCap, fmax(1.0e-10, fmin(states32[pr->idx].last_off, tol32)));
+        } else {
+          // V'^H V' is not numerically positive definite: W = L2^H L1 again
+          pr->fallback = 1;
+          reset.push_back(pr->idx);
+          GemmDesc d = tri_gemm(pr->np, pr->np, M2_of(pr), 1, M1_of(pr), 0, 1, W_of(pr));
+          d.mask = pr->n;
+          wg.push_back(d);
+          pr->zb = W_of(pr);
+          pr->first = 0.0;
+        }
+      }
+      for (int i : reset) BSE_TRY(hipMemcpyAsync(d_status + i, &kBig, sizeof(int), hipMemcpyHostToDevice, s));
+      BSE_TRY(run_op(ar, ti, group_chol, G_TRIINV, 0, s));
+      BSE_TRY(run_steps<double>(ar, steps, s));
+      BSE_TRY(run_gemm<double>(ar, wg, s));
+    }
+    auto tol64_of = [&](Prob* pr) { return o.jacobi_tol > 0.0 ? o.jacobi_tol : default_tol64(pr->n); };
+    if (int e = jacobi_phase(ok, false, 30, 1.0e-10, 0.0, [](Prob* pr) -> void* { return pr->zb; },
+                             tol64_of, [](Prob* pr) { return pr->first; }))
+      return e;
+  }
+  if (polish) tm.mark();
 
   // ---- finalize: scaled singular columns, Rayleigh quotients, back-transform
   if (!ok.empty()) {
@@ -803,9 +974,10 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         const int np = pr->np;
         double2* M1 = pr->at<double2>(pr->p.off_m1);
         double2* M2 = pr->at<double2>(pr->p.off_m2);
-        double2* W = pr->at<double2>(pr->p.off_w);
+        // the polished form: the columns of its FP64 sweeps, T in X2 (as back_transform_z)
+        double2* W = polish ? pr->zb : pr->at<double2>(pr->p.off_w);
         double2* Y = pr->at<double2>(pr->p.off_y);
-        double2* T = pr->at<double2>(pr->p.off_t);
+        double2* T = pr->at<double2>(polish ? pr->p.off_x2 : pr->p.off_t);
         double2* inv = pr->at<double2>(pr->p.off_inv);
         double* sigma = pr->at<double>(pr->p.off_sigma);
         double* bnorm = pr->at<double>(pr->p.off_bnorm);
@@ -852,9 +1024,12 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   std::vector<int> status(batch, 0);
   for (const Prob& pr : probs) {
     int st = pr.status;
-    const JacState& js = states[pr.idx];
+    // the polished form: js is its complex64 iteration, jp its FP64 sweeps
+    const JacState& js = polish && !states32.empty() ? states32[pr.idx] : states[pr.idx];
+    const JacState& jp = states[pr.idx];
     // the complex64 iteration may end early (stop fraction): the refinement decides
-    if (st == 0 && !(mixed ? js.sweeps > 0 : js.converged)) st = 2 * pr.n + 1;
+    if (st == 0 && !(mixed ? js.sweeps > 0 : (polish ? js.sweeps > 0 && jp.converged : js.converged)))
+      st = 2 * pr.n + 1;
     if (st == 0 && mixed && !(pr.rcorr <= 1.0e-4)) st = 2 * pr.n + 2;
     if (st != 0 && mixed) {
       // the complex64 stage could not carry this problem: re-solve it in FP64
@@ -886,6 +1061,15 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       inf->refine_steps_done = pr.rsteps;
       inf->refine_window_steps = pr.rwsteps;
       for (int k = 0; k < 8; ++k) inf->refine_corr[k] = pr.rhist[k];
+      if (polish && pr.status == 0) {
+        inf->fallback = pr.fallback;
+        inf->polish_sweeps = jp.sweeps;
+        inf->polish_rotations = jp.rotations;
+        inf->polish_pair_checks = (int)jp.pair_checks;
+        inf->polish_cross_pair_checks = (int)jp.cross_pair_checks;
+        inf->polish_max_off = jp.last_off;
+        inf->polish_inner_rotations = jp.inner_rotations;
+      }
     }
   }
   if (o.checks)

@@ -272,7 +272,6 @@ struct ZToCOp {
 // Lower triangle of a Hermitian n x n matrix embedded in np x np: strict
 // upper part set to zero, rows and columns n..np-1 set to the identity's.
 // mode 1 instead writes the np x np identity.
-struct TriPadArgs { int n, np; double2* M; long ld; int identity; };
 struct TriPadOp {
   static constexpr int NT = 256;
   typedef TriPadArgs Args;
@@ -381,30 +380,6 @@ hipError_t cholesky_z(int np, int n_real, double2* M, long ld, double2* linv, in
 // all of its blocks at once (K = 64 kTrsmGroup), so the remaining rows pass
 // through the update kTrsmGroup times less often than with one block at a time.
 
-// Z_i = op(L_ii^-1) Rhs_i for one 64-row block (left-side solves)
-static hipError_t trsm_diag(const double2* inv_i, int opA, int np, double2* Rhs_i, double2* Z_i,
-                            long ld, hipStream_t s) {
-  GemmDesc g;
-  g.M = NB; g.N = np; g.K = NB;
-  g.A = inv_i; g.lda = NB; g.opA = opA; g.triA = 1;
-  g.B = Rhs_i; g.ldb = ld; g.opB = 0;
-  g.C = Z_i; g.ldc = ld;
-  return gemm_z(g, s);
-}
-
-// C -= op(A) B  (rows x np, inner dimension k)
-static hipError_t trsm_update(int rows, int np, int k, const double2* A, long lda, int opA,
-                              const double2* B, long ldb, double2* C, long ldc, hipStream_t s) {
-  if (rows <= 0) return hipSuccess;
-  GemmDesc u;
-  u.M = rows; u.N = np; u.K = k;
-  u.A = A; u.lda = lda; u.opA = opA;
-  u.B = B; u.ldb = ldb; u.opB = 0;
-  u.C = C; u.ldc = ldc;
-  u.alpha_re = -1.0; u.beta_re = 1.0;
-  return gemm_z(u, s);
-}
-
 hipError_t trsm_lh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s) {
   const int nb = np / NB;
@@ -435,20 +410,10 @@ hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
   const TriInvArgs ti = {L, ld, inv};
   hipError_t e = launch_one<TriInvOp<double2>>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
-  for (int i = 0; i < nb; i += kTrsmGroup) {
-    const int hi = i + kTrsmGroup - 1 < nb ? i + kTrsmGroup - 1 : nb - 1;  // last block row of the group
-    const long ri = (long)i * NB;
-    for (int b = i; b <= hi; ++b) {
-      const long rb = (long)b * NB;
-      // Rhs_b -= L_{b, i..b-1} Z_{i..b-1}
-      if (b > i && (e = trsm_update(NB, np, (b - i) * NB, L + rb + ri * ld, ld, 0, Z + ri, ld, Rhs + rb, ld, s)) != hipSuccess) return e;
-      if ((e = trsm_diag(inv + rb * NB, 0, np, Rhs + rb, Z + rb, ld, s)) != hipSuccess) return e;
-    }
-    // Rhs_{hi+1..} -= L_{hi+1.., i..hi} Z_{i..hi}
-    const long rn = (long)(hi + 1) * NB;
-    if ((e = trsm_update(np - (int)rn, np, (hi - i + 1) * NB, L + rn + ri * ld, ld, 0, Z + ri, ld, Rhs + rn, ld, s)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  trsm_ln_for_each(np, L, ld, Rhs, Z, inv, [&](const TrsmStep& st) {
+    if (e == hipSuccess) e = gemm_z(st.g, s);
+  });
+  return e;
 }
 
 hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
@@ -457,35 +422,10 @@ hipError_t trsm_rh_z(int np, const double2* L, long ld, double2* Rhs, double2* Z
   const TriInvArgs ti = {L, ld, inv};
   hipError_t e = launch_one<TriInvOp<double2>>(ti, nb, 0, s);
   if (e != hipSuccess) return e;
-  // Z_j = Rhs_j (L_jj^-1)^H   (column block j)
-  auto diag = [&](int j) {
-    GemmDesc g;
-    g.M = np; g.N = NB; g.K = NB;
-    g.A = Rhs + (long)j * NB * ld; g.lda = ld; g.opA = 0;
-    g.B = inv + (long)j * NB * NB; g.ldb = NB; g.opB = 1; g.triB = 1;
-    g.C = Z + (long)j * NB * ld; g.ldc = ld;
-    return gemm_z(g, s);
-  };
-  // Rhs_{c0..c0+cols} -= Z_{j0..j0+k} (L_{c0.., j0..j0+k})^H
-  auto update = [&](int c0, int cols, int j0, int k) {
-    if (cols <= 0) return hipSuccess;
-    GemmDesc u;
-    u.M = np; u.N = cols; u.K = k;
-    u.A = Z + (long)j0 * ld; u.lda = ld; u.opA = 0;
-    u.B = L + c0 + (long)j0 * ld; u.ldb = ld; u.opB = 1;
-    u.C = Rhs + (long)c0 * ld; u.ldc = ld;
-    u.alpha_re = -1.0; u.beta_re = 1.0;
-    return gemm_z(u, s);
-  };
-  for (int j = 0; j < nb; j += kTrsmGroup) {
-    const int hi = j + kTrsmGroup - 1 < nb ? j + kTrsmGroup - 1 : nb - 1;
-    for (int c = j; c <= hi; ++c) {
-      if (c > j && (e = update(c * NB, NB, j * NB, (c - j) * NB)) != hipSuccess) return e;
-      if ((e = diag(c)) != hipSuccess) return e;
-    }
-    if ((e = update((hi + 1) * NB, np - (hi + 1) * NB, j * NB, (hi - j + 1) * NB)) != hipSuccess) return e;
-  }
-  return hipSuccess;
+  trsm_rh_for_each(np, L, ld, Rhs, Z, inv, [&](const TrsmStep& st) {
+    if (e == hipSuccess) e = gemm_z(st.g, s);
+  });
+  return e;
 }
 
 hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int* status,
@@ -565,6 +505,8 @@ hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks
     case G_POTF2_C: return launch_grp<Potf2Op<float2>>(table, map, blocks, aux, s);
     case G_TRIINV: return launch_grp<TriInvOp<double2>>(table, map, blocks, aux, s);
     case G_TRIINV_C: return launch_grp<TriInvOp<float2>>(table, map, blocks, aux, s);
+    case G_ZTOC: return launch_grp<ZToCOp>(table, map, blocks, aux, s);
+    case G_TRIPAD: return launch_grp<TriPadOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -186,11 +186,90 @@ void trsm_lh_for_each(int np, const C2* L, long ld, C2* Rhs, C2* Z, const C2* in
     if (lo > 0) emit(TrsmStep{group, 2 * kTrsmGroup - 1, update(0, lo * B, (long)lo * B, (i - lo + 1) * B)});
   }
 }
+// The steps of Z = L^-1 Rhs (forward block substitution, trsm_ln_z), with the
+// same (group, slot) numbering as trsm_lh_for_each (groups counted from the top).
+template <class F>
+void trsm_ln_for_each(int np, const double2* L, long ld, double2* Rhs, double2* Z, const double2* inv,
+                      F&& emit) {
+  constexpr int B = 64;
+  const int nb = np / B;
+  auto diag = [&](int b) {
+    const long rb = (long)b * B;
+    GemmDesc g;  // Z_b = L_bb^-1 Rhs_b
+    g.M = B; g.N = np; g.K = B;
+    g.A = inv + rb * B; g.lda = B; g.opA = 0; g.triA = 1;
+    g.B = Rhs + rb; g.ldb = ld; g.opB = 0;
+    g.C = Z + rb; g.ldc = ld;
+    return g;
+  };
+  // Rhs[r0 .. r0 + rows) -= L[r0 .., c0 .. c0 + k) Z[c0 .. c0 + k)
+  auto update = [&](long r0, int rows, long c0, int k) {
+    GemmDesc u;
+    u.M = rows; u.N = np; u.K = k;
+    u.A = L + r0 + c0 * ld; u.lda = ld; u.opA = 0;
+    u.B = Z + c0; u.ldb = ld; u.opB = 0;
+    u.C = Rhs + r0; u.ldc = ld;
+    u.alpha_re = -1.0; u.beta_re = 1.0;
+    return u;
+  };
+  int group = 0;
+  for (int i = 0; i < nb; i += kTrsmGroup, ++group) {
+    const int hi = i + kTrsmGroup - 1 < nb ? i + kTrsmGroup - 1 : nb - 1;  // last block row of the group
+    for (int b = i; b <= hi; ++b) {
+      const int j = b - i;
+      if (j > 0) emit(TrsmStep{group, 2 * j - 1, update((long)b * B, B, (long)i * B, j * B)});
+      emit(TrsmStep{group, 2 * j, diag(b)});
+    }
+    // Rhs_{hi+1..} -= L_{hi+1.., i..hi} Z_{i..hi}
+    const int rest = np - (hi + 1) * B;
+    if (rest > 0)
+      emit(TrsmStep{group, 2 * kTrsmGroup - 1, update((long)(hi + 1) * B, rest, (long)i * B, (hi - i + 1) * B)});
+  }
+}
+
+// The steps of Z = Rhs L^-H (column blocks left to right, trsm_rh_z), numbered
+// as above.
+template <class F>
+void trsm_rh_for_each(int np, const double2* L, long ld, double2* Rhs, double2* Z, const double2* inv,
+                      F&& emit) {
+  constexpr int B = 64;
+  const int nb = np / B;
+  auto diag = [&](int j) {
+    GemmDesc g;  // Z_j = Rhs_j (L_jj^-1)^H
+    g.M = np; g.N = B; g.K = B;
+    g.A = Rhs + (long)j * B * ld; g.lda = ld; g.opA = 0;
+    g.B = inv + (long)j * B * B; g.ldb = B; g.opB = 1; g.triB = 1;
+    g.C = Z + (long)j * B * ld; g.ldc = ld;
+    return g;
+  };
+  // Rhs_{c0 .. c0 + cols} -= Z_{j0 .. j0 + k} (L_{c0 .., j0 .. j0 + k})^H
+  auto update = [&](int c0, int cols, int j0, int k) {
+    GemmDesc u;
+    u.M = np; u.N = cols; u.K = k;
+    u.A = Z + (long)j0 * ld; u.lda = ld; u.opA = 0;
+    u.B = L + c0 + (long)j0 * ld; u.ldb = ld; u.opB = 1;
+    u.C = Rhs + (long)c0 * ld; u.ldc = ld;
+    u.alpha_re = -1.0; u.beta_re = 1.0;
+    return u;
+  };
+  int group = 0;
+  for (int j = 0; j < nb; j += kTrsmGroup, ++group) {
+    const int hi = j + kTrsmGroup - 1 < nb ? j + kTrsmGroup - 1 : nb - 1;
+    for (int c = j; c <= hi; ++c) {
+      const int q = c - j;
+      if (q > 0) emit(TrsmStep{group, 2 * q - 1, update(c * B, B, j * B, q * B)});
+      emit(TrsmStep{group, 2 * q, diag(c)});
+    }
+    const int rest = np - (hi + 1) * B;
+    if (rest > 0) emit(TrsmStep{group, 2 * kTrsmGroup - 1, update((hi + 1) * B, rest, j * B, (hi - j + 1) * B)});
+  }
+}
 // complex64 copy of all np x np entries.
 hipError_t z_to_c64(int np, const double2* M, long ld, float2* Mc, hipStream_t s);
 // identity == 0: zero the strict upper triangle of M and give rows/columns
 // n..np-1 those of the identity; identity != 0: M = I (np x np).
 hipError_t tri_pad_z(int n, int np, double2* M, long ld, int identity, hipStream_t s);
+struct TriPadArgs { int n, np; double2* M; long ld; int identity; };
 // Z = L^-1 Rhs (forward block substitution, same conventions as trsm_lh_z).
 hipError_t trsm_ln_z(int np, const double2* L, long ld, double2* Rhs, double2* Z, double2* inv,
                      hipStream_t s);
@@ -467,6 +546,7 @@ struct SweepArgs {  // aux = sweep index
   double track_level;  // sweeps after one whose largest off-diagonal exceeded this track
   int pairs_per_round;
   double stop_fraction;  // > 0: a sweep rotating fewer than this fraction of its pairs ends the iteration
+  double first_stop;     // > 0: the first sweep's inner stopping level and tracking measure (default kInnerStopCap)
 };
 
 // Work-group counts of one problem for the ops above.
@@ -488,7 +568,7 @@ RotArgs<float2> rot_args_c(int np, float2* W, long ld, const JacobiWork& w, cons
 // Grouped launches: table = device array of the op's Args, map = device
 // array of (table row, work group) pairs, blocks = entries of map used.
 enum GroupOp {
-  G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C, G_TRIINV, G_TRIINV_C, // chol.hip
+  G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C, G_TRIINV, G_TRIINV_C, G_ZTOC, G_TRIPAD,  // chol.hip
   G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
   G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
   G_WRITE_LAMBDA, G_C64, G_ASSEMBLE, G_GATHER,

@@ -963,9 +963,10 @@ BSE_DEV void SweepOp::run(const SweepArgs& a, int, int sweep) {
     return;
   }
   double stop = a.inner_floor;
-  if (a.adaptive) stop = fmax(a.inner_floor, fmin(kInnerStopCap, prev < 0.0 ? kInnerStopCap : a.factor * prev));
+  const double first = a.first_stop > 0.0 ? a.first_stop : kInnerStopCap;
+  if (a.adaptive) stop = fmax(a.inner_floor, fmin(kInnerStopCap, prev < 0.0 ? first : a.factor * prev));
   st->stop2 = stop * stop;
-  st->cross = (prev < 0.0 ? kInnerStopCap : prev) > a.track_level ? 1 : 0;
+  st->cross = (prev < 0.0 ? first : prev) > a.track_level ? 1 : 0;
   st->counter = 0;
   st->inner = 0;
   st->inner_rot = 0;

@@ -29,7 +29,7 @@ def host(res):
     return [(lam.cpu().numpy(), X.resolve_conj().cpu().numpy()) for lam, X in res]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_polish"])
 def test_batched_uneven_sizes_vs_oracle(gpu_lib, precision):
     sizes = [130, 1, 65, 5, 200, 17, 64, 100, 3]
     problems = [inputs.coupled(n, seed=300 + i) for i, n in enumerate(sizes)]
@@ -39,7 +39,7 @@ def test_batched_uneven_sizes_vs_oracle(gpu_lib, precision):
     for (A, B), (lam, X), info in zip(problems, host(res), infos):
         n = A.shape[0]
         assert info["sweeps"] >= 1
-        if precision == "fp64":
+        if precision != "mixed":
             check_against_oracle(A, B, lam, X)
         else:
             lam_o, _ = ob.solve_chol_svd(A, B)
@@ -50,7 +50,7 @@ def test_batched_uneven_sizes_vs_oracle(gpu_lib, precision):
         assert np.array_equal(X[:n, n:], X[n:, :n]) and np.array_equal(X[n:, n:], X[:n, :n])
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "mixed_polish"])
 def test_batched_equals_single_with_same_tiles(gpu_lib, precision):
     sizes = [130, 64, 200, 17, 256]
     tiles = [(64, 1, 64), (128, 2, 64), (192, 1, 64), (256, 4, 128)]
@@ -64,6 +64,34 @@ def test_batched_equals_single_with_same_tiles(gpu_lib, precision):
         assert np.array_equal(lam.cpu().numpy(), lam_b)
         assert np.array_equal(X.resolve_conj().cpu().numpy(), X_b)
         assert info["sweeps"] == infos[i]["sweeps"] and info["rotations"] == infos[i]["rotations"]
+        if precision == "mixed_polish":
+            assert info["polish_sweeps"] == infos[i]["polish_sweeps"] >= 1
+            assert info["polish_rotations"] == infos[i]["polish_rotations"]
+            assert info["max_off"] == infos[i]["max_off"] and infos[i]["fallback"] == 0
+
+
+def test_batched_polish_fallback_branch(gpu_lib, monkeypatch):
+    """The polished form's branch for a rotation that cannot be recovered (V'^H V' not
+    positive definite; forced by the test hook), grouped: each problem's FP64 sweeps then
+    run on W itself, bit for bit as the single solve's branch and as the FP64 form."""
+    sizes = [130, 17, 200]
+    tiles = [(64, 1, 64), (192, 1, 64), (256, 4, 128)]
+    problems = [inputs.coupled(n, seed=450 + i) for i, n in enumerate(sizes)]
+    As, Bs = to_dev(problems)
+    monkeypatch.setenv("BSE_TEST_POLISH_FALLBACK", "1")
+    print("[gpu] batched mixed_polish, forced fallback branch", flush=True)
+    res, infos, st = gpu_lib.solve_batched(As, Bs, precision="mixed_polish", tiles=tiles)
+    assert st == 0 and all(i["fallback"] == 1 for i in infos)
+    for i, (lam_b, X_b) in enumerate(host(res)):
+        lam, X, info = gpu_lib.solve_h1(As[i], Bs[i], precision="mixed_polish", tiles=tiles)
+        assert info["fallback"] == 1
+        assert np.array_equal(lam.cpu().numpy(), lam_b)
+        assert np.array_equal(X.resolve_conj().cpu().numpy(), X_b)
+        lam64, X64, _ = gpu_lib.solve_h1(As[i], Bs[i], tiles=tiles)
+        assert np.array_equal(lam64.cpu().numpy(), lam_b)
+    monkeypatch.delenv("BSE_TEST_POLISH_FALLBACK")
+    res2, infos2, st2 = gpu_lib.solve_batched(As, Bs, precision="mixed_polish", tiles=tiles)
+    assert st2 == 0 and all(i["fallback"] == 0 for i in infos2)
 
 
 def test_batched_mixed_windows_on_clustered_problems(gpu_lib):
@@ -92,14 +120,15 @@ def test_batched_mixed_windows_on_clustered_problems(gpu_lib):
         assert om.rel_eig_err(lam_b, lam_o) < 1e-12
 
 
-def test_batched_status_per_problem(gpu_lib):
+@pytest.mark.parametrize("precision", ["fp64", "mixed_polish"])
+def test_batched_status_per_problem(gpu_lib, precision):
     """One problem with A - B indefinite: its status is reported, the others are solved."""
     good = [inputs.coupled(n, seed=500 + n) for n in (40, 90)]
     A = np.diag(np.linspace(1.0, 2.0, 70)).astype(np.complex128)
     B = 0.5 * A
     B[30, 30] = 1.5 * A[30, 30]  # (A - B)[30, 30] < 0: leading minor 31 of A - B fails
     problems = [good[0], (A, B), good[1]]
-    res, infos, st = gpu_lib.solve_batched(*to_dev(problems), check=False)
+    res, infos, st = gpu_lib.solve_batched(*to_dev(problems), precision=precision, check=False)
     assert st == 70 + 31 and infos[1]["status"] == 70 + 31 and infos[1]["fail_index"] == 31
     assert ob.chol_status(A, B) == 70 + 31
     assert infos[0]["status"] == 0 and infos[2]["status"] == 0
