@@ -1,15 +1,17 @@
 // Many independent BSE problems of different orders in one call.
 //
-// Each phase of the SVD route (Alg. 3) runs as grouped launches over the
-// whole batch: the host builds, per launch, a table of per-problem kernel
-// arguments and a map from every flat work group to (problem, work group
-// within the problem) (see the op launches in common.hpp), so one launch
-// fills the chip with the work of all problems at once:
+// Each phase of the SVD route (Alg. 3; FP64, mixed and mixed_polish) and of
+// Alg. 2 runs as grouped launches over the whole batch: the host builds, per
+// launch, a table of per-problem kernel arguments and a map from every flat
+// work group to (problem, work group within the problem) (see the op
+// launches in common.hpp), so one launch fills the chip with the work of all
+// problems at once:
 //   form        one launch (plus the complex64 copies and mirrors, mixed form)
 //   Cholesky    three launches per 64-column panel (diagonal blocks of both
 //               factors of every problem that has that panel, panel solve,
 //               trailing update), Alg. 3 steps 1-2
-//   W           one grouped GEMM, step 3's matrix
+//   W           one grouped GEMM, step 3's matrix (Alg. 2: two, for
+//               M = L^H (A + B) L)
 //   Jacobi      per round three launches (Gram, inner eigensolver, rotation)
 //               over the problems that have that round, recorded once as a
 //               HIP graph and replayed every sweep; per sweep one small
@@ -22,7 +24,10 @@
 //               correction was still above the stopping level: grouped GEMMs
 //               for the products, per window pass one grouped launch of the
 //               window eigensolvers and grouped block GEMMs, the correction
-//               and the basis update.
+//               and the basis update;
+//   polish      (mixed_polish) the rotation of the complex64 iteration
+//               recovered in FP64 by grouped block triangular solves and a
+//               grouped Cholesky, then grouped FP64 sweeps.
 // Problems are ordered by padded order, largest first, so the problems that
 // take part in a Jacobi round or a Cholesky panel form a prefix of every
 // table and a launch uses a prefix of its map.
@@ -174,6 +179,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
                           bse_info_t* info, int want_timing, hipStream_t s) {
   const bool mixed = o.precision == BSE_PREC_MIXED;
   const bool polish = o.precision == BSE_PREC_MIXED_POLISH;
+  const bool alg2 = o.route == BSE_ROUTE_EIG;  // Alg. 2 (FP64 only)
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   char* wbase = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
 
@@ -239,6 +245,17 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       g.add(a, tiles64(pr.np));
     }
     BSE_TRY(run_op(ar, g, group_chol, G_FORM, 0, s));
+    if (alg2) {
+      // Alg. 2 does not factor A + B; a factorisation of a copy checks its
+      // definiteness, and A + B itself is kept whole (mirrored) for T = (A + B) L
+      Grp<MirrorArgs> m;
+      for (const Prob& pr : probs) {
+        BSE_TRY(hipMemcpyAsync(pr.base + pr.p.off_z, pr.base + pr.p.off_m1,
+                               (size_t)pr.np * pr.np * sizeof(double2), hipMemcpyDeviceToDevice, s));
+        m.add({pr.np, pr.at<double2>(pr.p.off_m1), pr.np}, tiles64(pr.np));
+      }
+      BSE_TRY(run_op(ar, m, group_chol, G_MIRROR, 0, s));
+    }
     if (mixed) {
       Grp<ToC64Args> c;
       Grp<MirrorArgs> m;
@@ -371,6 +388,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     for (Prob& pr : probs) all.push_back(&pr);
     const FactorFn factor_of = [&](const Prob& pr, int f) -> void* {
       const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
+      if (alg2) return static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_z));
       return mixed ? static_cast<void*>(pr.base + pr.p.off_lc + (f ? half : 0))
                    : static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_m1));
     };
@@ -384,8 +402,26 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     if (pr.status == 0) ok.push_back(&pr);
   tm.mark();
 
-  // ---- W = L2^H L1 (step 3's matrix; zero outside the leading n x n block)
-  {
+  // ---- W = L2^H L1 (step 3's matrix; zero outside the leading n x n block);
+  // Alg. 2: M = L^H (A + B) L with L L^H = A - B
+  if (alg2) {
+    std::vector<GemmDesc> tg, mg;
+    for (Prob* pr : ok) {
+      const int np = pr->np;
+      GemmDesc t;  // T = (A + B) L
+      t.M = np; t.N = np; t.K = np;
+      t.A = pr->base + pr->p.off_m1; t.lda = np; t.opA = 0;
+      t.B = pr->base + pr->p.off_m2; t.ldb = np; t.opB = 0; t.triB = 1;
+      t.C = pr->base + pr->p.off_w; t.ldc = np;
+      tg.push_back(t);
+      GemmDesc m = tri_gemm(np, np, pr->base + pr->p.off_m2, 1, pr->base + pr->p.off_w, 0, 0,
+                            pr->base + pr->p.off_y);  // M = L^H T
+      m.mask = pr->n;
+      mg.push_back(m);
+    }
+    BSE_TRY(run_gemm<double>(ar, tg, s));
+    BSE_TRY(run_gemm<double>(ar, mg, s));
+  } else {
     std::vector<GemmDesc> w;
     for (Prob* pr : ok) {
       const size_t half = (size_t)pr->np * pr->np * sizeof(float2);
@@ -552,7 +588,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       return o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : default_tol64(pr->n));
     };
     auto W_of = [&](Prob* pr) -> void* {
-      return pr->base + (mixed ? pr->p.off_wc : (polish ? pr->p.off_x1 : pr->p.off_w));
+      return pr->base + (mixed ? pr->p.off_wc : (polish ? pr->p.off_x1 : (alg2 ? pr->p.off_y : pr->p.off_w)));
     };
     if (int e = jacobi_phase(ok, c64_jacobi, max_sweeps, c64_jacobi ? 1.0e-5 : 1.0e-10,
                              c64_jacobi ? 1.0 / 32 : 0.0, W_of, tol_of, [](Prob*) { return 0.0; }))
@@ -671,7 +707,59 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
 
   // ---- finalize: scaled singular columns, Rayleigh quotients, back-transform
   if (!ok.empty()) {
-    if (mixed) {
+    if (alg2) {
+      // Alg. 2 after its eigensolver, as the single solve: d = column norms of
+      // the iterated M, lambda = sqrt(d) ascending, the sorted columns scaled
+      // by Lambda^(1/2) and Lambda^(-1/2), V2 = L V_M Lambda^-1/2 and
+      // V1 = L^-H V_M Lambda^1/2 by grouped block triangular solves
+      Grp<ColnormArgs<double2>> cn;
+      Grp<Alg2Args> al;
+      Grp<RankArgs> rk;
+      Grp<WriteLambdaArgs> wl;
+      Grp<GatherArgs> ga;
+      Grp<TriInvArgs> ti;
+      Grp<AssembleArgs> as;
+      std::vector<GemmDesc> v2;
+      std::vector<TrsmStep> steps;
+      for (Prob* pr : ok) {
+        const int np = pr->np;
+        double2* M1 = pr->at<double2>(pr->p.off_m1);
+        double2* M2 = pr->at<double2>(pr->p.off_m2);
+        double2* W = pr->at<double2>(pr->p.off_w);
+        double2* Y = pr->at<double2>(pr->p.off_y);
+        double2* inv = pr->at<double2>(pr->p.off_inv);
+        double* d = pr->at<double>(pr->p.off_sigma);
+        int* perm = pr->at<int>(pr->p.off_perm);
+        double* lamu = pr->at<double>(pr->p.off_lamu);
+        double* fx = pr->at<double>(pr->p.off_anorm);
+        double* fy = pr->at<double>(pr->p.off_bnorm);
+        cn.add({Y, np, np, d}, np);
+        al.add({pr->n, d, lamu, perm, fx, fy}, (pr->n + 255) / 256);
+        rk.add({pr->n, lamu, perm, 0}, (pr->n + 255) / 256);
+        wl.add({pr->n, lamu, perm, pr->lambda, o.want_negative}, (pr->n + 255) / 256);
+        if (o.values_only) continue;
+        ga.add({pr->n, np, Y, np, perm, fx, M1}, cols_blocks(np, np));  // V_M Lambda^1/2 (sorted)
+        ga.add({pr->n, np, Y, np, perm, fy, W}, cols_blocks(np, np));   // V_M Lambda^-1/2
+        v2.push_back(tri_gemm(np, np, M2, 0, W, 0, 0, Y));             // V2 = L V_M Lambda^-1/2
+        ti.add({M2, np, inv}, np / 64);
+        trsm_lh_for_each(np, (const double2*)M2, np, M1, W, inv,
+                         [&](const TrsmStep& st) { steps.push_back(st); });  // V1 = L^-H V_M Lambda^1/2
+        as.add({pr->n, W, Y, np, nullptr, nullptr, pr->X, pr->ldx, o.want_negative, nullptr},
+               cols_blocks(pr->n, pr->n));
+      }
+      BSE_TRY(run_op(ar, cn, group_finalize, G_COLNORM_Z, 0, s));
+      BSE_TRY(run_op(ar, al, group_finalize, G_ALG2_LAMBDA, 0, s));
+      BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
+      BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
+      BSE_TRY(run_op(ar, al, group_finalize, G_ALG2_SCALES, 0, s));
+      BSE_TRY(run_op(ar, ga, group_finalize, G_GATHER, 0, s));
+      tm.mark();
+      BSE_TRY(run_gemm<double>(ar, v2, s));
+      BSE_TRY(run_op(ar, ti, group_chol, G_TRIINV, 0, s));
+      BSE_TRY(run_steps<double>(ar, steps, s));
+      BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
+      tm.mark();
+    } else if (mixed) {
       // Alg. 3 steps 4-5 in complex64 as in the single solve: V2 = L2 Ws,
       // T = L1^H V2 (Rayleigh quotients), V1 = L2^-H Ws / ||Ws||^2 by grouped
       // block triangular solves

@@ -170,23 +170,30 @@ struct GatherOp {
   }
 };
 
-__global__ __launch_bounds__(256) void k_alg2_lambda(int n, const double* __restrict__ d,
-                                                     double* __restrict__ lam) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k < n) lam[k] = sqrt(d[k]);
-}
+// Alg. 2: lam_k = sqrt(d_k) (work group = 256 entries)
+struct Alg2LambdaOp {
+  static constexpr int NT = 256;
+  typedef Alg2Args Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int k = bx * 256 + threadIdx.x;
+    if (k < a.n) a.lam[k] = sqrt(a.d[k]);
+  }
+};
 
-__global__ __launch_bounds__(256) void k_alg2_scales(int n, const double* __restrict__ d,
-                                                     const int* __restrict__ perm,
-                                                     double* __restrict__ fx, double* __restrict__ fy) {
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  if (r >= n) return;
-  int k = perm[r];
-  if (k < 0 || k >= n) k = r;
-  const double dk = d[k], lk = sqrt(dk);
-  fy[r] = 1.0 / (dk * sqrt(lk));  // column of V_M Lambda^-1/2 from the column q_k d_k
-  fx[r] = sqrt(lk) / dk;          // column of V_M Lambda^1/2
-}
+// Alg. 2: the column scales of the sorted pairs (work group = 256 entries)
+struct Alg2ScalesOp {
+  static constexpr int NT = 256;
+  typedef Alg2Args Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int r = bx * 256 + threadIdx.x;
+    if (r >= a.n) return;
+    int k = a.perm[r];
+    if (k < 0 || k >= a.n) k = r;
+    const double dk = a.d[k], lk = sqrt(dk);
+    a.fy[r] = 1.0 / (dk * sqrt(lk));  // column of V_M Lambda^-1/2 from the column q_k d_k
+    a.fx[r] = sqrt(lk) / dk;          // column of V_M Lambda^1/2
+  }
+};
 
 // X[:, r] = s_k [(t_k V1_k + V2_k)/2; (V2_k - t_k V1_k)/2], k = perm[r];
 // work group = (column r, 256 rows).
@@ -320,12 +327,11 @@ hipError_t gather_scale_z(int n, int np, const double2* W, long ld, const int* p
 
 hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double* lambda,
                          int want_negative, double* fx, double* fy, hipStream_t s) {
-  k_alg2_lambda<<<(n + 255) / 256, 256, 0, s>>>(n, d, lam);
-  hipError_t e = hipGetLastError();
+  const Alg2Args a = {n, d, lam, perm, fx, fy};
+  hipError_t e = launch_one<Alg2LambdaOp>(a, b256(n), 0, s);
   if (e == hipSuccess) e = sort_lambda(n, lam, perm, lambda, want_negative, s);
-  if (e != hipSuccess) return e;
-  k_alg2_scales<<<(n + 255) / 256, 256, 0, s>>>(n, d, perm, fx, fy);
-  return hipGetLastError();
+  if (e == hipSuccess) e = launch_one<Alg2ScalesOp>(a, b256(n), 0, s);
+  return e;
 }
 
 hipError_t sqrt_scales(int n, int np, const double* dC, const double* dM, double* ks, double* kis,
@@ -354,6 +360,8 @@ hipError_t group_finalize(GroupOp op, const void* table, const int2* map, int bl
     case G_C64: return launch_grp<C64Op>(table, map, blocks, aux, s);
     case G_ASSEMBLE: return launch_grp<AssembleOp>(table, map, blocks, aux, s);
     case G_GATHER: return launch_grp<GatherOp>(table, map, blocks, aux, s);
+    case G_ALG2_LAMBDA: return launch_grp<Alg2LambdaOp>(table, map, blocks, aux, s);
+    case G_ALG2_SCALES: return launch_grp<Alg2ScalesOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }

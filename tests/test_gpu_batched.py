@@ -200,3 +200,44 @@ def test_autotuner_small_range(gpu_lib):
     for (A, B), (lam, X) in zip(problems, host(res)):
         lam_o, _ = ob.solve_chol_svd(A, B)
         assert om.rel_eig_err(lam, lam_o) < 1e-10
+
+
+def test_batched_alg2_equals_single_and_oracle(gpu_lib):
+    """Alg. 2 (CHOL) in grouped launches: bit for bit the single solves (same tiles), the
+    oracle's Alg. 2 pairs at the single tests' bars, the negative half, values only, and a
+    problem with A + B indefinite reported while the others are solved."""
+    sizes = [130, 1, 65, 200, 17]
+    tiles = [(64, 1, 64), (192, 1, 64), (256, 4, 128)]
+    problems = [inputs.coupled(n, seed=600 + i) for i, n in enumerate(sizes)]
+    As, Bs = to_dev(problems)
+    print("[gpu] batched alg2 vs single", flush=True)
+    res, infos, st = gpu_lib.solve_batched(As, Bs, route="eig", want_negative=True, tiles=tiles)
+    assert st == 0
+    out = host(res)
+    for i, (lam_b, X_b) in enumerate(out):
+        A, B = problems[i]
+        n = A.shape[0]
+        lam, X, info = gpu_lib.solve_h1(As[i], Bs[i], route="eig", want_negative=True, tiles=tiles)
+        assert np.array_equal(lam.cpu().numpy(), lam_b)
+        assert np.array_equal(X.resolve_conj().cpu().numpy(), X_b)
+        assert info["sweeps"] == infos[i]["sweeps"] and info["rotations"] == infos[i]["rotations"]
+        lam_o, X_o = ob.solve_chol_eig(A, B)
+        assert om.rel_eig_err(lam_b[:n], lam_o) < 1e-11
+        assert om.residual(A, B, lam_b[:n], X_b[:, :n]) < 1e-13
+        err, gap = om.eigvec_errors(lam_o, X_o, X_b[:, :n], cluster_rtol=1e-9)
+        assert np.all(err <= 1e-10 + 1e-13 / np.minimum(gap, 1.0))
+        assert np.array_equal(lam_b[n:], -lam_b[:n])
+    resv, _, stv = gpu_lib.solve_batched(As, Bs, route="eig", want_negative=True, tiles=tiles,
+                                         values_only=True)
+    assert stv == 0
+    for (lam_v, _), (lam_b, _) in zip(resv, out):
+        assert np.array_equal(lam_v.cpu().numpy(), lam_b)
+    # A + B indefinite in the middle problem: status k (leading minor k of A + B)
+    A, B = inputs.coupled(90, seed=61)
+    B2 = B.copy()
+    B2[40, 40] = A[40, 40].real + 1.0
+    bad = [problems[0], (A, B2), problems[3]]
+    res3, infos3, st3 = gpu_lib.solve_batched(*to_dev(bad), route="eig", check=False, tiles=tiles)
+    assert st3 == ob.chol_status(A, B2) == infos3[1]["status"]
+    assert infos3[0]["status"] == 0 and infos3[2]["status"] == 0
+    assert np.array_equal(host(res3)[0][0], out[0][0][:sizes[0]])
