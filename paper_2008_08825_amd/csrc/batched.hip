@@ -921,7 +921,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           if (step_win(pr) > 0) pr->rwsteps += 1;
         for (int pass = 0; pass < kWindowPasses; ++pass) {
           // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
-          const int off = (pass & 1) ? 32 : 0;
+          const int off = window_offset(pass);
           Grp<WinArgs> wn;
           std::vector<GemmDesc> right[3], left[3];
           for (Prob* pr : act) {
@@ -949,7 +949,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         BSE_TRY(run_op(ar, ur, group_refine, G_UPDRQ, 0, s));
         // x <- x C_1 C_2 (I + E11 + E21), y <- y C_1 C_2 (I + E11 - E21)
         for (int pass = 0; pass < kWindowPasses; ++pass) {
-          const int off = (pass & 1) ? 32 : 0;
+          const int off = window_offset(pass);
           std::vector<GemmDesc> g;
           for (Prob* pr : act) {
             if (pass >= step_win(pr)) continue;

@@ -367,6 +367,8 @@ constexpr double kRefineDelta = 1.0e-10;
 constexpr double kRefineStop = 1.0e-6;
 // Window passes per refinement step (boundaries at 0, then shifted by 32).
 constexpr int kWindowPasses = 2;
+// Boundary offset of window pass p: 0, 32 (and 16, 48 for passes 2, 3).
+inline int window_offset(int pass) { return (pass & 1) * 32 + ((pass >> 1) & 1) * 16; }
 // A step after one whose first-order correction was at most this runs no
 // windows: the rotations left inside near-degenerate groups are then of the
 // order of that correction's square, well inside the first-order regime.

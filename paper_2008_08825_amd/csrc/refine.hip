@@ -462,7 +462,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     if (window_steps && step_passes > 0) ++*window_steps;
     for (int pass = 0; pass < step_passes; ++pass) {
       // Rayleigh-Ritz on windows of 64 pairs, boundaries alternately at 0 and at 32
-      const int off = (pass & 1) ? 32 : 0;
+      const int off = window_offset(pass);
       double2* Cb = window_blocks(w.Cb0, n, pass);
       if ((e = window_pass(n, ld, F, w.P1, w.P2, Q, Cb, off, w.maxcorr + 1, ar, s)) != hipSuccess) return e;
     }
@@ -479,7 +479,7 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     // the window rotations precede the first-order correction:
     // x <- x C_1 C_2 ... C_p (I + E11 + E21), y <- y C_1 ... C_p (I + E11 - E21)
     for (int pass = 0; pass < step_passes; ++pass) {
-      const int off = (pass & 1) ? 32 : 0;
+      const int off = window_offset(pass);
       const double2* Cb = window_blocks(w.Cb0, n, pass);
       std::vector<GemmDesc> g;
       window_right(n, ld, x, Q, Cb, off, g);
