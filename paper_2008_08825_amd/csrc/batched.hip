@@ -1,7 +1,8 @@
 // Many independent BSE problems of different orders in one call.
 //
-// Each phase of the SVD route (Alg. 3; FP64, mixed and mixed_polish) and of
-// Alg. 2 runs as grouped launches over the whole batch: the host builds, per
+// Each phase of the SVD route (Alg. 3; FP64, mixed and mixed_polish), of
+// Alg. 2 and of the Tamm-Dancoff case runs as grouped launches over the whole
+// batch: the host builds, per
 // launch, a table of per-problem kernel arguments and a map from every flat
 // work group to (problem, work group within the problem) (see the op
 // launches in common.hpp), so one launch fills the chip with the work of all
@@ -180,6 +181,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   const bool mixed = o.precision == BSE_PREC_MIXED;
   const bool polish = o.precision == BSE_PREC_MIXED_POLISH;
   const bool alg2 = o.route == BSE_ROUTE_EIG;  // Alg. 2 (FP64 only)
+  const bool tda = o.route == BSE_ROUTE_TDA;   // B = 0 (FP64 only): the Hermitian eigenproblem of A
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   char* wbase = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
 
@@ -193,9 +195,9 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     pr.n = n[i];
     pr.np = pad64(n[i]);
     pr.A = static_cast<const double2*>(A[i]);
-    pr.B = static_cast<const double2*>(B[i]);
+    pr.B = B ? static_cast<const double2*>(B[i]) : nullptr;  // TDA: B = 0, may be absent
     pr.lda = lda[i];
-    pr.ldb = ldb[i];
+    pr.ldb = ldb ? ldb[i] : 0;
     pr.ldx = ldx[i];
     pr.lambda = lambda[i];
     pr.X = static_cast<double2*>(X[i]);
@@ -240,7 +242,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   {
     Grp<FormArgs> g;
     for (const Prob& pr : probs) {
-      const FormArgs a = {pr.n, pr.np, pr.A, pr.lda, pr.B, pr.ldb, upper,
+      const FormArgs a = {pr.n, pr.np, pr.A, pr.lda, tda ? nullptr : pr.B, tda ? 0 : pr.ldb, upper,
                           pr.at<double2>(pr.p.off_m1), pr.at<double2>(pr.p.off_m2), pr.np};
       g.add(a, tiles64(pr.np));
     }
@@ -255,6 +257,16 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         m.add({pr.np, pr.at<double2>(pr.p.off_m1), pr.np}, tiles64(pr.np));
       }
       BSE_TRY(run_op(ar, m, group_chol, G_MIRROR, 0, s));
+    }
+    if (tda) {
+      // M1 = A in full (identity beyond n) and its copy W, the Jacobi's matrix;
+      // the padded columns are unit vectors orthogonal to the rest
+      Grp<MirrorArgs> m;
+      for (const Prob& pr : probs) m.add({pr.np, pr.at<double2>(pr.p.off_m1), pr.np}, tiles64(pr.np));
+      BSE_TRY(run_op(ar, m, group_chol, G_MIRROR, 0, s));
+      for (const Prob& pr : probs)
+        BSE_TRY(hipMemcpyAsync(pr.base + pr.p.off_w, pr.base + pr.p.off_m1,
+                               (size_t)pr.np * pr.np * sizeof(double2), hipMemcpyDeviceToDevice, s));
     }
     if (mixed) {
       Grp<ToC64Args> c;
@@ -392,10 +404,12 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       return mixed ? static_cast<void*>(pr.base + pr.p.off_lc + (f ? half : 0))
                    : static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_m1));
     };
-    if (int e = cholesky_phase(all, 2, factor_of, [](const Prob& pr, int f) { return f ? pr.n : 0; }))
-      return e;
-    if (int e = read_statuses()) return e;
-    for (Prob& pr : probs) pr.status = pr.gst == kBig ? 0 : pr.gst;
+    if (!tda) {  // the Tamm-Dancoff case factors nothing
+      if (int e = cholesky_phase(all, 2, factor_of, [](const Prob& pr, int f) { return f ? pr.n : 0; }))
+        return e;
+      if (int e = read_statuses()) return e;
+      for (Prob& pr : probs) pr.status = pr.gst == kBig ? 0 : pr.gst;
+    }
   }
   std::vector<Prob*> ok;
   for (Prob& pr : probs)
@@ -404,7 +418,9 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
 
   // ---- W = L2^H L1 (step 3's matrix; zero outside the leading n x n block);
   // Alg. 2: M = L^H (A + B) L with L L^H = A - B
-  if (alg2) {
+  if (tda) {
+    // (W is the copy of A made with the form)
+  } else if (alg2) {
     std::vector<GemmDesc> tg, mg;
     for (Prob* pr : ok) {
       const int np = pr->np;
@@ -707,7 +723,42 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
 
   // ---- finalize: scaled singular columns, Rayleigh quotients, back-transform
   if (!ok.empty()) {
-    if (alg2) {
+    if (tda) {
+      // as the single solve: Y = A Z, Rayleigh quotients z^H A z / z^H z and
+      // 1 / ||z||, sorted, X = [u; 0] (and [0; u]) with u = z / ||z||
+      std::vector<GemmDesc> g;
+      Grp<RqArgs> rq;
+      Grp<RankArgs> rk;
+      Grp<WriteLambdaArgs> wl;
+      Grp<AssembleArgs> as;
+      for (Prob* pr : ok) {
+        const int np = pr->np;
+        double2* M1 = pr->at<double2>(pr->p.off_m1);
+        double2* W = pr->at<double2>(pr->p.off_w);
+        double2* Y = pr->at<double2>(pr->p.off_y);
+        int* perm = pr->at<int>(pr->p.off_perm);
+        double* lamu = pr->at<double>(pr->p.off_lamu);
+        double* scl = pr->at<double>(pr->p.off_scl);
+        GemmDesc d;
+        d.M = pr->n; d.N = pr->n; d.K = pr->n;
+        d.A = M1; d.lda = np; d.opA = 0;
+        d.B = W; d.ldb = np; d.opB = 0;
+        d.C = Y; d.ldc = np;
+        g.push_back(d);
+        rq.add({pr->n, W, W, Y, Y, np, lamu, scl, nullptr}, pr->n);
+        rk.add({pr->n, lamu, perm, 0}, (pr->n + 255) / 256);
+        wl.add({pr->n, lamu, perm, pr->lambda, o.want_negative}, (pr->n + 255) / 256);
+        if (!o.values_only)
+          as.add({pr->n, W, W, np, perm, scl, pr->X, pr->ldx, o.want_negative, nullptr}, cols_blocks(pr->n, pr->n));
+      }
+      BSE_TRY(run_gemm<double>(ar, g, s));
+      BSE_TRY(run_op(ar, rq, group_refine, G_RQ, 0, s));
+      BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
+      BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
+      tm.mark();
+      BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
+      tm.mark();
+    } else if (alg2) {
       // Alg. 2 after its eigensolver, as the single solve: d = column norms of
       // the iterated M, lambda = sqrt(d) ascending, the sorted columns scaled
       // by Lambda^(1/2) and Lambda^(-1/2), V2 = L V_M Lambda^-1/2 and

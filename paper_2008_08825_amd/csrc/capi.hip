@@ -764,8 +764,8 @@ size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* op
     const size_t b = bse_workspace_bytes(n[i], &o);
     if (b > mx) mx = b;
   }
-  // SQRT and TDA: problems one after another
-  if (o.route != BSE_ROUTE_SVD && o.route != BSE_ROUTE_EIG) return mx;
+  // SQRT: problems one after another
+  if (o.route == BSE_ROUTE_SQRT) return mx;
   return batched_workspace(batch, n, o);
 }
 
@@ -804,7 +804,7 @@ int bse_solve_batched(int batch, const int* n, const void* const* A, const int* 
       info[i].timing = want_timing;
     }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (o.route == BSE_ROUTE_SVD || o.route == BSE_ROUTE_EIG)
+  if (o.route != BSE_ROUTE_SQRT)
     return solve_batched_grouped(batch, n, A, lda, B, ldb, lambda, X, ldx, work, o, info,
                                  want_timing, s);
   int first = 0;

@@ -241,3 +241,32 @@ def test_batched_alg2_equals_single_and_oracle(gpu_lib):
     assert st3 == ob.chol_status(A, B2) == infos3[1]["status"]
     assert infos3[0]["status"] == 0 and infos3[2]["status"] == 0
     assert np.array_equal(host(res3)[0][0], out[0][0][:sizes[0]])
+
+
+def test_batched_tda_equals_single_and_oracle(gpu_lib):
+    """Tamm-Dancoff batches (B = 0, Hermitian eigenproblem of A) in grouped launches: bit for
+    bit the single solves (same tiles), the oracle's eigenpairs, values only."""
+    sizes = [65, 1, 130, 2, 200]
+    tiles = [(64, 1, 64), (192, 1, 64), (256, 4, 128)]
+    As_h = [inputs.coupled(n, seed=620 + i)[0] for i, n in enumerate(sizes)]
+    As = [torch.from_numpy(A).to(DEV) for A in As_h]
+    print("[gpu] batched tda vs single", flush=True)
+    res, infos, st = gpu_lib.solve_batched(As, [None] * len(As), route="tda", want_negative=True, tiles=tiles)
+    assert st == 0
+    out = host(res)
+    for i, (lam_b, X_b) in enumerate(out):
+        n = sizes[i]
+        lam, X, info = gpu_lib.solve_h1(As[i], None, route="tda", want_negative=True, tiles=tiles)
+        assert np.array_equal(lam.cpu().numpy(), lam_b)
+        assert np.array_equal(X.resolve_conj().cpu().numpy(), X_b)
+        assert info["sweeps"] == infos[i]["sweeps"]
+        lam_o, X_o = ob.solve_tda(As_h[i])
+        assert om.rel_eig_err(lam_b[:n], lam_o) < 1e-13
+        assert om.residual(As_h[i], np.zeros_like(As_h[i]), lam_b[:n], X_b[:, :n]) < 5e-14
+        err, gap = om.eigvec_errors(lam_o, X_o, X_b[:, :n], cluster_rtol=1e-9)
+        assert np.all(err <= 1e-11 + 1e-13 / np.minimum(gap, 1.0))
+    resv, _, stv = gpu_lib.solve_batched(As, [None] * len(As), route="tda", want_negative=True,
+                                         tiles=tiles, values_only=True)
+    assert stv == 0
+    for (lam_v, X_v), (lam_b, _) in zip(resv, out):
+        assert X_v is None and np.array_equal(lam_v.cpu().numpy(), lam_b)
