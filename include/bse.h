@@ -197,15 +197,13 @@ size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* op
  * (in index order) that failed, with every problem's own status in info[i];
  * argument errors: -1 batch, -2 n, -3 A/lda, -5 B/ldb, -7 lambda, -8 X/ldx,
  * -10 work NULL, -11 work_bytes too small, -12 opts invalid.
- * SVD (any precision), Alg. 2 and TDA routes: the problems are processed
- * together; each phase
+ * Every route and precision: the problems are processed together; each phase
  * runs as grouped launches over the whole batch, with a table of per-problem
  * kernel arguments and a map from work groups to problems staged in `work`,
  * and the Jacobi sweeps of all problems advance together (one host readback
  * per sweep; a problem that has converged skips the remaining sweeps).  The
  * results of each problem are those bse_solve_h1 computes with the same
- * opts and tile table.  SQRT route (Alg. 1): the problems run one after
- * another.
+ * opts and tile table.
  * info[0].timing requests timing (as for bse_solve_h1); ms_phase then holds
  * the phase times of the whole batch in every entry. */
 int bse_solve_batched(int batch, const int* n,

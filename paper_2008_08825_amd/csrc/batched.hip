@@ -1,7 +1,7 @@
 // Many independent BSE problems of different orders in one call.
 //
-// Each phase of the SVD route (Alg. 3; FP64, mixed and mixed_polish), of
-// Alg. 2 and of the Tamm-Dancoff case runs as grouped launches over the whole
+// Each phase of every route (Alg. 3 in FP64, mixed and mixed_polish, Alg. 2,
+// Alg. 1 and the Tamm-Dancoff case) runs as grouped launches over the whole
 // batch: the host builds, per
 // launch, a table of per-problem kernel arguments and a map from every flat
 // work group to (problem, work group within the problem) (see the op
@@ -182,6 +182,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   const bool polish = o.precision == BSE_PREC_MIXED_POLISH;
   const bool alg2 = o.route == BSE_ROUTE_EIG;  // Alg. 2 (FP64 only)
   const bool tda = o.route == BSE_ROUTE_TDA;   // B = 0 (FP64 only): the Hermitian eigenproblem of A
+  const bool sqrt_route = o.route == BSE_ROUTE_SQRT;  // Alg. 1 (FP64 only)
   const int upper = (o.uplo == 'U' || o.uplo == 'u');
   char* wbase = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
 
@@ -227,7 +228,10 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   Timer tm(want_timing != 0, s);
   // the polished form's FP64 stage (between the complex64 Jacobi and the
   // finalize) is timed as the refinement, as in the single solve
-  const int slots[8] = {0, 1, 2, 3, polish ? 6 : 4, polish ? 4 : 5, polish ? 5 : 6, -1};
+  // (Alg. 1: both of its Jacobi iterations as the Jacobi phase)
+  int slots[8] = {0, 1, 2, 3, 4, 5, 6, -1};
+  if (polish) { slots[4] = 6; slots[5] = 4; slots[6] = 5; }
+  if (sqrt_route) { slots[4] = 3; slots[5] = 4; slots[6] = 5; }
   tm.mark();
   // ---- header: statuses "no failure", zero Jacobi states and corrections
   {
@@ -255,6 +259,15 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         BSE_TRY(hipMemcpyAsync(pr.base + pr.p.off_z, pr.base + pr.p.off_m1,
                                (size_t)pr.np * pr.np * sizeof(double2), hipMemcpyDeviceToDevice, s));
         m.add({pr.np, pr.at<double2>(pr.p.off_m1), pr.np}, tiles64(pr.np));
+      }
+      BSE_TRY(run_op(ar, m, group_chol, G_MIRROR, 0, s));
+    }
+    if (sqrt_route) {
+      // Alg. 1 works with A + B and A - B in full
+      Grp<MirrorArgs> m;
+      for (const Prob& pr : probs) {
+        m.add({pr.np, pr.at<double2>(pr.p.off_m1), pr.np}, tiles64(pr.np));
+        m.add({pr.np, pr.at<double2>(pr.p.off_m2), pr.np}, tiles64(pr.np));
       }
       BSE_TRY(run_op(ar, m, group_chol, G_MIRROR, 0, s));
     }
@@ -404,7 +417,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       return mixed ? static_cast<void*>(pr.base + pr.p.off_lc + (f ? half : 0))
                    : static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_m1));
     };
-    if (!tda) {  // the Tamm-Dancoff case factors nothing
+    if (!tda && !sqrt_route) {  // the Tamm-Dancoff case and Alg. 1 factor nothing
       if (int e = cholesky_phase(all, 2, factor_of, [](const Prob& pr, int f) { return f ? pr.n : 0; }))
         return e;
       if (int e = read_statuses()) return e;
@@ -418,8 +431,8 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
 
   // ---- W = L2^H L1 (step 3's matrix; zero outside the leading n x n block);
   // Alg. 2: M = L^H (A + B) L with L L^H = A - B
-  if (tda) {
-    // (W is the copy of A made with the form)
+  if (tda || sqrt_route) {
+    // (TDA: W is the copy of A made with the form; Alg. 1 iterates on A - B)
   } else if (alg2) {
     std::vector<GemmDesc> tg, mg;
     for (Prob* pr : ok) {
@@ -604,6 +617,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       return o.jacobi_tol > 0.0 ? o.jacobi_tol : (mixed ? 4.0 * sqrt(nn) * eps32 : default_tol64(pr->n));
     };
     auto W_of = [&](Prob* pr) -> void* {
+      if (sqrt_route) return pr->base + pr->p.off_m2;  // Z = V_C D_C
       return pr->base + (mixed ? pr->p.off_wc : (polish ? pr->p.off_x1 : (alg2 ? pr->p.off_y : pr->p.off_w)));
     };
     if (int e = jacobi_phase(ok, c64_jacobi, max_sweeps, c64_jacobi ? 1.0e-5 : 1.0e-10,
@@ -721,9 +735,107 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   }
   if (polish) tm.mark();
 
+  // ---- Alg. 1 after the Jacobi on A - B (columns z_k = d_k v_k): the square
+  // root S = Z diag(d^-3/2) Z^H and its inverse (one grouped launch), M = S (A + B) S,
+  // and the Jacobi on M (as solve_sqrt)
+  std::vector<JacState> states1;
+  if (sqrt_route && !ok.empty()) {
+    states1 = states;
+    Grp<ColnormArgs<double2>> cn;
+    Grp<SqrtScalesArgs> sq;
+    std::vector<GemmDesc> sg, tg, mg;
+    auto full = [](int np, const void* a, int opA, const void* b, int opB, void* c, const double* kscale,
+                   const double* colscale) {
+      GemmDesc g;
+      g.M = np; g.N = np; g.K = np;
+      g.A = a; g.lda = np; g.opA = opA;
+      g.B = b; g.ldb = np; g.opB = opB;
+      g.C = c; g.ldc = np;
+      g.kscale = kscale;
+      g.colscale = colscale;
+      return g;
+    };
+    for (Prob* pr : ok) {
+      const int np = pr->np;
+      double2* M1 = pr->at<double2>(pr->p.off_m1);
+      double2* M2 = pr->at<double2>(pr->p.off_m2);
+      double2* Sb = pr->at<double2>(pr->p.off_w);
+      double2* Si = pr->at<double2>(pr->p.off_y);
+      double2* T = pr->at<double2>(pr->p.off_t);
+      double* dC = pr->at<double>(pr->p.off_sigma);
+      double* ks = pr->at<double>(pr->p.off_anorm);
+      double* kis = pr->at<double>(pr->p.off_invlam);
+      cn.add({M2, np, np, dC}, np);
+      // ks, kis (c1, c2 redone after the second iteration)
+      sq.add({pr->n, np, dC, dC, ks, kis, pr->at<double>(pr->p.off_scl), pr->at<double>(pr->p.off_ritz),
+              pr->at<double>(pr->p.off_lamu)}, (np + 255) / 256);
+      sg.push_back(full(np, M2, 0, M2, 1, Sb, ks, nullptr));   // S = Z diag(d^-3/2) Z^H
+      sg.push_back(full(np, M2, 0, M2, 1, Si, kis, nullptr));  // S^-1 = Z diag(d^-5/2) Z^H
+      tg.push_back(full(np, M1, 0, Sb, 0, T, nullptr, nullptr));  // T = M1 S
+      mg.push_back(full(np, Sb, 0, T, 0, M1, nullptr, nullptr));  // M = S M1 S
+    }
+    BSE_TRY(run_op(ar, cn, group_finalize, G_COLNORM_Z, 0, s));
+    BSE_TRY(run_op(ar, sq, group_finalize, G_SQRT_SCALES, 0, s));
+    BSE_TRY(run_gemm<double>(ar, sg, s));
+    BSE_TRY(run_gemm<double>(ar, tg, s));
+    BSE_TRY(run_gemm<double>(ar, mg, s));
+    auto tol_of = [&](Prob* pr) { return o.jacobi_tol > 0.0 ? o.jacobi_tol : default_tol64(pr->n); };
+    if (int e = jacobi_phase(ok, false, max_sweeps, 1.0e-10, 0.0,
+                             [](Prob* pr) -> void* { return pr->base + pr->p.off_m1; }, tol_of,
+                             [](Prob*) { return 0.0; }))
+      return e;
+  }
+  if (sqrt_route) tm.mark();
+
   // ---- finalize: scaled singular columns, Rayleigh quotients, back-transform
   if (!ok.empty()) {
-    if (tda) {
+    if (sqrt_route) {
+      // Y = V_M D in M1: d = lambda^2, V1 = S^-1 Y d^-3/4, V2 = S Y d^-5/4
+      Grp<ColnormArgs<double2>> cn;
+      Grp<SqrtScalesArgs> sq;
+      Grp<RankArgs> rk;
+      Grp<WriteLambdaArgs> wl;
+      Grp<AssembleArgs> as;
+      std::vector<GemmDesc> vg;
+      for (Prob* pr : ok) {
+        const int np = pr->np;
+        double2* M1 = pr->at<double2>(pr->p.off_m1);
+        double2* M2 = pr->at<double2>(pr->p.off_m2);
+        double2* Sb = pr->at<double2>(pr->p.off_w);
+        double2* Si = pr->at<double2>(pr->p.off_y);
+        double2* T = pr->at<double2>(pr->p.off_t);
+        double* dC = pr->at<double>(pr->p.off_sigma);
+        double* dM = pr->at<double>(pr->p.off_bnorm);
+        double* c1 = pr->at<double>(pr->p.off_scl);
+        double* c2 = pr->at<double>(pr->p.off_ritz);
+        double* lamu = pr->at<double>(pr->p.off_lamu);
+        int* perm = pr->at<int>(pr->p.off_perm);
+        cn.add({M1, np, np, dM}, np);
+        sq.add({pr->n, np, dC, dM, pr->at<double>(pr->p.off_anorm), pr->at<double>(pr->p.off_invlam), c1, c2,
+                lamu}, (np + 255) / 256);
+        rk.add({pr->n, lamu, perm, 0}, (pr->n + 255) / 256);
+        wl.add({pr->n, lamu, perm, pr->lambda, o.want_negative}, (pr->n + 255) / 256);
+        if (o.values_only) continue;
+        GemmDesc g;
+        g.M = np; g.N = np; g.K = np;
+        g.A = Si; g.lda = np; g.opA = 0;
+        g.B = M1; g.ldb = np; g.opB = 0;
+        g.C = M2; g.ldc = np;
+        g.colscale = c1;
+        vg.push_back(g);  // V1 = S^-1 Y d^-3/4
+        g.A = Sb; g.C = T; g.colscale = c2;
+        vg.push_back(g);  // V2 = S Y d^-5/4
+        as.add({pr->n, M2, T, np, perm, nullptr, pr->X, pr->ldx, o.want_negative, nullptr}, cols_blocks(pr->n, pr->n));
+      }
+      BSE_TRY(run_op(ar, cn, group_finalize, G_COLNORM_Z, 0, s));
+      BSE_TRY(run_op(ar, sq, group_finalize, G_SQRT_SCALES, 0, s));
+      BSE_TRY(run_op(ar, rk, group_finalize, G_RANK, 0, s));
+      BSE_TRY(run_op(ar, wl, group_finalize, G_WRITE_LAMBDA, 0, s));
+      tm.mark();
+      BSE_TRY(run_gemm<double>(ar, vg, s));
+      BSE_TRY(run_op(ar, as, group_finalize, G_ASSEMBLE, 0, s));
+      tm.mark();
+    } else if (tda) {
       // as the single solve: Y = A Z, Rayleigh quotients z^H A z / z^H z and
       // 1 / ||z||, sorted, X = [u; 0] (and [0; u]) with u = z / ||z||
       std::vector<GemmDesc> g;
@@ -1163,11 +1275,15 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   std::vector<int> status(batch, 0);
   for (const Prob& pr : probs) {
     int st = pr.status;
-    // the polished form: js is its complex64 iteration, jp its FP64 sweeps
-    const JacState& js = polish && !states32.empty() ? states32[pr.idx] : states[pr.idx];
+    // the polished form: js is its complex64 iteration, jp its FP64 sweeps;
+    // Alg. 1: js the iteration on A - B, jp the one on M
+    const JacState& js = polish && !states32.empty() ? states32[pr.idx]
+                         : (sqrt_route && !states1.empty() ? states1[pr.idx] : states[pr.idx]);
     const JacState& jp = states[pr.idx];
     // the complex64 iteration may end early (stop fraction): the refinement decides
-    if (st == 0 && !(mixed ? js.sweeps > 0 : (polish ? js.sweeps > 0 && jp.converged : js.converged)))
+    if (st == 0 && !(mixed ? js.sweeps > 0
+                           : (polish ? js.sweeps > 0 && jp.converged
+                                     : (sqrt_route ? js.converged && jp.converged : js.converged))))
       st = 2 * pr.n + 1;
     if (st == 0 && mixed && !(pr.rcorr <= 1.0e-4)) st = 2 * pr.n + 2;
     if (st != 0 && mixed) {
@@ -1196,6 +1312,14 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       inf->pair_checks = (int)js.pair_checks;
       inf->cross_pair_checks = (int)js.cross_pair_checks;
       inf->inner_rotations = js.inner_rotations;
+      if (sqrt_route) {  // both iterations together (the last one's level), as the single solve
+        inf->sweeps += jp.sweeps;
+        inf->rotations += jp.rotations;
+        inf->max_off = jp.last_off;
+        inf->pair_checks += (int)jp.pair_checks;
+        inf->cross_pair_checks += (int)jp.cross_pair_checks;
+        inf->inner_rotations += jp.inner_rotations;
+      }
       inf->refine_delta = pr.rcorr;
       inf->refine_steps_done = pr.rsteps;
       inf->refine_window_steps = pr.rwsteps;

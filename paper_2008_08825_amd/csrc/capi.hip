@@ -758,14 +758,8 @@ size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* op
   bse_default_opts(&o);
   if (opts) o = *opts;
   if (!opts_valid(o)) return 0;
-  size_t mx = 0;
-  for (int i = 0; i < batch; ++i) {
+  for (int i = 0; i < batch; ++i)
     if (n[i] < 0 || n[i] > 46000) return 0;
-    const size_t b = bse_workspace_bytes(n[i], &o);
-    if (b > mx) mx = b;
-  }
-  // SQRT: problems one after another
-  if (o.route == BSE_ROUTE_SQRT) return mx;
   return batched_workspace(batch, n, o);
 }
 
@@ -804,18 +798,7 @@ int bse_solve_batched(int batch, const int* n, const void* const* A, const int* 
       info[i].timing = want_timing;
     }
   hipStream_t s = static_cast<hipStream_t>(stream);
-  if (o.route != BSE_ROUTE_SQRT)
-    return solve_batched_grouped(batch, n, A, lda, B, ldb, lambda, X, ldx, work, o, info,
-                                 want_timing, s);
-  int first = 0;
-  for (int i = 0; i < batch; ++i) {
-    bse_info_t* inf = info ? &info[i] : nullptr;
-    const int st = bse_solve_h1(n[i], A[i], lda[i], B ? B[i] : nullptr, ldb ? ldb[i] : 1, lambda[i],
-                                X ? X[i] : nullptr, ldx ? ldx[i] : 1, work, work_bytes, &o, inf, stream);
-    if (st <= kErrHip) return st;
-    if (st != 0 && first == 0) first = st;
-  }
-  return first;
+  return solve_batched_grouped(batch, n, A, lda, B, ldb, lambda, X, ldx, work, o, info, want_timing, s);
 }
 
 size_t bse_backward_workspace_bytes(int n) { return n >= 0 && n <= 46000 ? adjoint_work_bytes(n) : 0; }

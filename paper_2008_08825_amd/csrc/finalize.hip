@@ -230,27 +230,28 @@ struct AssembleOp {
 // S = Z diag(dC^-3/2) Z^H, S^-1 = Z diag(dC^-5/2) Z^H, V1 = S^-1 Y dM^-3/4,
 // V2 = S Y dM^-5/4, lambda = dM^1/2 (k < n; padded columns of A - B are unit
 // vectors with dC = 1 and keep S = I there, padded V columns are zero).
-__global__ __launch_bounds__(256) void k_sqrt_scales(int n, int np, const double* __restrict__ dC,
-                                                     const double* __restrict__ dM,
-                                                     double* __restrict__ ks, double* __restrict__ kis,
-                                                     double* __restrict__ c1, double* __restrict__ c2,
-                                                     double* __restrict__ lam) {
-  const int k = blockIdx.x * 256 + threadIdx.x;
-  if (k >= np) return;
-  const double c = dC[k];
-  ks[k] = c > 0.0 ? 1.0 / (c * sqrt(c)) : 0.0;
-  kis[k] = c > 0.0 ? 1.0 / (c * c * sqrt(c)) : 0.0;
-  if (k < n) {
-    const double m = dM[k], q = sqrt(sqrt(m));  // m^1/4
-    c1[k] = m > 0.0 ? 1.0 / (m / q) : 0.0;       // m^-3/4
-    c2[k] = m > 0.0 ? 1.0 / (m * q) : 0.0;       // m^-5/4
-    lam[k] = sqrt(m);
-  } else {
-    c1[k] = 0.0;
-    c2[k] = 0.0;
-    lam[k] = 0.0;
+// Alg. 1 scales (sqrt_scales); work group = 256 of the np entries
+struct SqrtScalesOp {
+  static constexpr int NT = 256;
+  typedef SqrtScalesArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int k = bx * 256 + threadIdx.x;
+    if (k >= a.np) return;
+    const double c = a.dC[k];
+    a.ks[k] = c > 0.0 ? 1.0 / (c * sqrt(c)) : 0.0;
+    a.kis[k] = c > 0.0 ? 1.0 / (c * c * sqrt(c)) : 0.0;
+    if (k < a.n) {
+      const double m = a.dM[k], q = sqrt(sqrt(m));  // m^1/4
+      a.c1[k] = m > 0.0 ? 1.0 / (m / q) : 0.0;       // m^-3/4
+      a.c2[k] = m > 0.0 ? 1.0 / (m * q) : 0.0;       // m^-5/4
+      a.lam[k] = sqrt(m);
+    } else {
+      a.c1[k] = 0.0;
+      a.c2[k] = 0.0;
+      a.lam[k] = 0.0;
+    }
   }
-}
+};
 
 inline int b256(int n) { return (n + 255) / 256; }
 
@@ -336,8 +337,8 @@ hipError_t alg2_lambda_z(int n, const double* d, double* lam, int* perm, double*
 
 hipError_t sqrt_scales(int n, int np, const double* dC, const double* dM, double* ks, double* kis,
                        double* c1, double* c2, double* lam, hipStream_t s) {
-  k_sqrt_scales<<<b256(np), 256, 0, s>>>(n, np, dC, dM, ks, kis, c1, c2, lam);
-  return hipGetLastError();
+  const SqrtScalesArgs a = {n, np, dC, dM, ks, kis, c1, c2, lam};
+  return launch_one<SqrtScalesOp>(a, b256(np), 0, s);
 }
 
 hipError_t assemble_z(int n, const double2* V1, const double2* V2, long ldv, const int* perm,
@@ -362,6 +363,7 @@ hipError_t group_finalize(GroupOp op, const void* table, const int2* map, int bl
     case G_GATHER: return launch_grp<GatherOp>(table, map, blocks, aux, s);
     case G_ALG2_LAMBDA: return launch_grp<Alg2LambdaOp>(table, map, blocks, aux, s);
     case G_ALG2_SCALES: return launch_grp<Alg2ScalesOp>(table, map, blocks, aux, s);
+    case G_SQRT_SCALES: return launch_grp<SqrtScalesOp>(table, map, blocks, aux, s);
     default: return hipErrorInvalidValue;
   }
 }

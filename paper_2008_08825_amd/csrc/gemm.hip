@@ -234,8 +234,12 @@ hipError_t gemm_launch(const GemmDesc& d, hipStream_t s) {
 }
 
 template <typename T>
-hipError_t gemm_group(int opA, int opB, const void* table, const int2* map, int blocks,
+hipError_t gemm_group(int opA, int opB, int ks, const void* table, const int2* map, int blocks,
                       hipStream_t s) {
+  if (ks) {
+    if (opA == 0 && opB == 1) return launch_grp<GemmOp<T, 0, 1, true>>(table, map, blocks, 0, s);
+    return hipErrorInvalidValue;
+  }
   if (opA == 0 && opB == 0) return launch_grp<GemmOp<T, 0, 0>>(table, map, blocks, 0, s);
   if (opA == 0 && opB == 1) return launch_grp<GemmOp<T, 0, 1>>(table, map, blocks, 0, s);
   if (opA == 1 && opB == 0) return launch_grp<GemmOp<T, 1, 0>>(table, map, blocks, 0, s);
@@ -254,10 +258,10 @@ int gemm_tiles(const GemmDesc& d) {
 GemmArgs<double> gemm_args_z(const GemmDesc& d) { return make_args<double>(d); }
 GemmArgs<float> gemm_args_c(const GemmDesc& d) { return make_args<float>(d); }
 
-hipError_t group_gemm(int prec, int opA, int opB, const void* table, const int2* map, int blocks,
-                      hipStream_t s) {
-  return prec == 0 ? gemm_group<double>(opA, opB, table, map, blocks, s)
-                   : gemm_group<float>(opA, opB, table, map, blocks, s);
+hipError_t group_gemm(int prec, int opA, int opB, int ks, const void* table, const int2* map,
+                      int blocks, hipStream_t s) {
+  return prec == 0 ? gemm_group<double>(opA, opB, ks, table, map, blocks, s)
+                   : gemm_group<float>(opA, opB, ks, table, map, blocks, s);
 }
 
 }  // namespace bse

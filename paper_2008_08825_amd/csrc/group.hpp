@@ -95,10 +95,15 @@ inline hipError_t stage(Arena& ar, const Grp<A>& g, Dev& d) {
 inline GemmArgs<double> args_of(const GemmDesc& d, double*) { return gemm_args_z(d); }
 inline GemmArgs<float> args_of(const GemmDesc& d, float*) { return gemm_args_c(d); }
 
-// Stage and launch a grouped GEMM (all rows share opA, opB).
+// Stage and launch a grouped GEMM (all rows share opA, opB, and either all or
+// none have a k scaling).
 template <typename T>
 inline hipError_t run_gemm(Arena& ar, const std::vector<GemmDesc>& descs, hipStream_t s) {
   if (descs.empty()) return hipSuccess;
+  const int ks = descs[0].kscale != nullptr;
+  for (const GemmDesc& d : descs)
+    if ((d.kscale != nullptr) != (ks != 0) || d.opA != descs[0].opA || d.opB != descs[0].opB)
+      return hipErrorInvalidValue;
   Grp<GemmArgs<T>> g;
   for (const GemmDesc& d : descs) {
     g.add(args_of(d, static_cast<T*>(nullptr)), gemm_tiles(d));
@@ -106,7 +111,7 @@ inline hipError_t run_gemm(Arena& ar, const std::vector<GemmDesc>& descs, hipStr
   Dev dv;
   hipError_t e = stage(ar, g, dv);
   if (e != hipSuccess) return e;
-  return group_gemm(sizeof(T) == 8 ? 0 : 1, descs[0].opA, descs[0].opB, dv.tab, dv.map, dv.blocks, s);
+  return group_gemm(sizeof(T) == 8 ? 0 : 1, descs[0].opA, descs[0].opB, ks, dv.tab, dv.map, dv.blocks, s);
 }
 
 typedef hipError_t (*GroupFn)(GroupOp, const void*, const int2*, int, int, hipStream_t);

@@ -509,6 +509,11 @@ struct GatherArgs { int n, np; const double2* W; long ld; const int* perm; const
 struct C64Args { int np; const float2* S; long lds; double2* D; long ldd; const double* colscale; };
 // Alg. 2 bookkeeping from the column norms d of the iterated M (alg2_lambda_z)
 struct Alg2Args { int n; const double* d; double* lam; const int* perm; double* fx; double* fy; };
+// Alg. 1 scales from the column norms dC of the iterated A - B and dM of the iterated M (sqrt_scales)
+struct SqrtScalesArgs {
+  int n, np; const double* dC; const double* dM; double* ks; double* kis; double* c1; double* c2;
+  double* lam;
+};
 struct AssembleArgs {
   int n; const double2* V1; const double2* V2; long ldv; const int* perm; const double* scl;
   double2* X; long ldx; int want_negative; const double* scl1;
@@ -575,7 +580,7 @@ enum GroupOp {
   G_FORM, G_MIRROR, G_TOC64, G_POTF2_Z, G_POTF2_C, G_TRIINV, G_TRIINV_C, G_ZTOC, G_TRIPAD,  // chol.hip
   G_GRAM_Z, G_GRAM_C, G_EIG_Z, G_EIG_C, G_ROT_Z, G_ROT_C, G_SWEEP,      // jacobi.hip
   G_COLNORM_Z, G_COLNORM_C, G_SCALE_Z, G_SCALE_C, G_LAMBDA, G_RANK,     // finalize.hip
-  G_WRITE_LAMBDA, G_C64, G_ASSEMBLE, G_GATHER, G_ALG2_LAMBDA, G_ALG2_SCALES,
+  G_WRITE_LAMBDA, G_C64, G_ASSEMBLE, G_GATHER, G_ALG2_LAMBDA, G_ALG2_SCALES, G_SQRT_SCALES,
   G_RITZ, G_BUILD, G_RQ, G_UPDRQ, G_COUPLE, G_LOW, G_ADDLOW,                             // refine.hip
 };
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
@@ -583,8 +588,8 @@ hipError_t group_jacobi(GroupOp op, const void* table, const int2* map, int bloc
 hipError_t group_finalize(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
 hipError_t group_refine(GroupOp op, const void* table, const int2* map, int blocks, int aux, hipStream_t s);
 // prec 0: complex128, 1: complex64
-hipError_t group_gemm(int prec, int opA, int opB, const void* table, const int2* map, int blocks,
-                      hipStream_t s);
+hipError_t group_gemm(int prec, int opA, int opB, int ks, const void* table, const int2* map,
+                      int blocks, hipStream_t s);
 
 // Blocks per problem of the fixed-shape ops.
 inline int tiles64(int np) { return (np / 64) * (np / 64); }

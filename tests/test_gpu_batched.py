@@ -270,3 +270,34 @@ def test_batched_tda_equals_single_and_oracle(gpu_lib):
     assert stv == 0
     for (lam_v, X_v), (lam_b, _) in zip(resv, out):
         assert X_v is None and np.array_equal(lam_v.cpu().numpy(), lam_b)
+
+
+def test_batched_sqrt_route_equals_single_and_oracle(gpu_lib):
+    """Alg. 1 (SQRT) batches in grouped launches (both Jacobi iterations, the k-scaled square
+    root products): bit for bit the single solves (same tiles), the oracle's Alg. 1 pairs at
+    the single test's bars, values only."""
+    sizes = [130, 3, 65, 200]
+    tiles = [(64, 1, 64), (192, 1, 64), (256, 4, 128)]
+    problems = [inputs.coupled(n, seed=640 + i) for i, n in enumerate(sizes)]
+    As, Bs = to_dev(problems)
+    print("[gpu] batched sqrt route vs single", flush=True)
+    res, infos, st = gpu_lib.solve_batched(As, Bs, route="sqrt", want_negative=True, tiles=tiles)
+    assert st == 0
+    out = host(res)
+    for i, (lam_b, X_b) in enumerate(out):
+        A, B = problems[i]
+        n = A.shape[0]
+        lam, X, info = gpu_lib.solve_h1(As[i], Bs[i], route="sqrt", want_negative=True, tiles=tiles)
+        assert np.array_equal(lam.cpu().numpy(), lam_b)
+        assert np.array_equal(X.resolve_conj().cpu().numpy(), X_b)
+        assert info["sweeps"] == infos[i]["sweeps"] and info["rotations"] == infos[i]["rotations"]
+        lam_o, X_o = ob.solve_sqrt(A, B)
+        assert om.rel_eig_err(lam_b[:n], lam_o) < 1e-12
+        assert om.residual(A, B, lam_b[:n], X_b[:, :n]) < 1e-13
+        err, gap = om.eigvec_errors(lam_o, X_o, X_b[:, :n], cluster_rtol=1e-9)
+        assert np.all(err <= 1e-10 + 1e-12 / np.minimum(gap, 1.0))
+    resv, _, stv = gpu_lib.solve_batched(As, Bs, route="sqrt", want_negative=True, tiles=tiles,
+                                         values_only=True)
+    assert stv == 0
+    for (lam_v, X_v), (lam_b, _) in zip(resv, out):
+        assert X_v is None and np.array_equal(lam_v.cpu().numpy(), lam_b)
