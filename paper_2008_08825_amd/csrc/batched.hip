@@ -242,7 +242,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
     BSE_TRY(hipMemsetAsync(d_corr, 0, (size_t)batch * sizeof(double), s));
   }
 
-  // ---- form M1 = A + B, M2 = A - B (and complex64 lower copies, full FP64 M1, M2 for the refinement)
+  // ---- form M1 = A + B, M2 = A - B (lower; complex64 copies for the mixed form)
   {
     Grp<FormArgs> g;
     for (const Prob& pr : probs) {
@@ -282,21 +282,17 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
                                (size_t)pr.np * pr.np * sizeof(double2), hipMemcpyDeviceToDevice, s));
     }
     if (mixed) {
+      // complex64 copies of the lower triangles (the FP64 M1, M2 stay lower: the
+      // refinement works with their FP64 Cholesky factors)
       Grp<ToC64Args> c;
-      Grp<MirrorArgs> m;
       for (const Prob& pr : probs) {
         const size_t half = (size_t)pr.np * pr.np * sizeof(float2);
         const ToC64Args c1 = {pr.np, pr.at<double2>(pr.p.off_m1), pr.np, pr.at<float2>(pr.p.off_lc)};
         const ToC64Args c2 = {pr.np, pr.at<double2>(pr.p.off_m2), pr.np, pr.at<float2>(pr.p.off_lc + half)};
         c.add(c1, tiles64(pr.np));
         c.add(c2, tiles64(pr.np));
-        const MirrorArgs m1 = {pr.np, pr.at<double2>(pr.p.off_m1), pr.np};
-        const MirrorArgs m2 = {pr.np, pr.at<double2>(pr.p.off_m2), pr.np};
-        m.add(m1, tiles64(pr.np));
-        m.add(m2, tiles64(pr.np));
       }
       BSE_TRY(run_op(ar, c, group_chol, G_TOC64, 0, s));
-      BSE_TRY(run_op(ar, m, group_chol, G_MIRROR, 0, s));
     }
   }
   tm.mark();
@@ -308,10 +304,10 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
   // the problem's status word
   typedef std::function<void*(const Prob&, int)> FactorFn;
   auto cholesky_phase = [&](const std::vector<Prob*>& list, int nf, const FactorFn& factor_of,
-                            const std::function<int(const Prob&, int)>& base_of) -> int {
+                            const std::function<int(const Prob&, int)>& base_of, bool c64) -> int {
     if (list.empty()) return 0;
     const int kmax = list[0]->np / 64;
-    const size_t es = mixed ? sizeof(float2) : sizeof(double2);
+    const size_t es = c64 ? sizeof(float2) : sizeof(double2);
     auto linv_of = [&](const Prob& pr, int f) -> void* {
       return pr.base + pr.p.off_linv + (size_t)f * 64 * 64 * es;
     };
@@ -330,7 +326,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
         for (int f = 0; f < nf; ++f) {
           void* M = factor_of(pr, f);
           void* linv = linv_of(pr, f);
-          if (mixed) {
+          if (c64) {
             const Potf2Args<float2> a = {static_cast<float2*>(M), pr.np, static_cast<float2*>(linv),
                                          d_status + pr.idx, base_of(pr, f), pr.n};
             gc.add(a, 1);
@@ -349,7 +345,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           trsm.push_back(t);
         }
       }
-      if (mixed) {
+      if (c64) {
         BSE_TRY(run_op(ar, gc, group_chol, G_POTF2_C, j0, s));
         BSE_TRY(run_gemm<float>(ar, trsm, s));
       } else {
@@ -359,7 +355,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       return 0;
     };
     auto run_updates = [&](std::vector<GemmDesc>& v) -> int {
-      if (mixed) BSE_TRY(run_gemm<float>(ar, v, s));
+      if (c64) BSE_TRY(run_gemm<float>(ar, v, s));
       else BSE_TRY(run_gemm<double>(ar, v, s));
       return 0;
     };
@@ -418,7 +414,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
                    : static_cast<void*>(pr.base + (f ? pr.p.off_m2 : pr.p.off_m1));
     };
     if (!tda && !sqrt_route) {  // the Tamm-Dancoff case and Alg. 1 factor nothing
-      if (int e = cholesky_phase(all, 2, factor_of, [](const Prob& pr, int f) { return f ? pr.n : 0; }))
+      if (int e = cholesky_phase(all, 2, factor_of, [](const Prob& pr, int f) { return f ? pr.n : 0; }, mixed))
         return e;
       if (int e = read_statuses()) return e;
       for (Prob& pr : probs) pr.status = pr.gst == kBig ? 0 : pr.gst;
@@ -691,7 +687,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       BSE_TRY(run_op(ar, tp, group_chol, G_TRIPAD, 0, s));
     }
     if (int e = cholesky_phase(ok, 1, [&](const Prob& pr, int) -> void* { return X2_of(&pr); },
-                               [](const Prob&, int) { return 0; }))
+                               [](const Prob&, int) { return 0; }, false))
       return e;
     if (int e = read_statuses()) return e;
     // BSE_TEST_POLISH_FALLBACK set: every problem takes the branch of a G that
@@ -976,6 +972,24 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
       BSE_TRY(run_op(ar, cv, group_finalize, G_C64, 0, s));
       tm.mark();
 
+      // ---- FP64 Cholesky factors of M1, M2 (in place) for the refinement's
+      // products, as the single solve; a problem whose factorisation fails
+      // skips the refinement and is re-solved in FP64 below
+      {
+        std::vector<Prob*> all(ok.begin(), ok.end());
+        const FactorFn fac = [](const Prob& pr, int f) -> void* {
+          return pr.base + (f ? pr.p.off_m2 : pr.p.off_m1);
+        };
+        if (int e = cholesky_phase(all, 2, fac, [](const Prob& pr, int f) { return f ? pr.n : 0; }, false))
+          return e;
+        if (int e = read_statuses()) return e;
+        for (Prob* pr : ok)
+          if (pr->gst != kBig) {
+            pr->status = pr->gst;
+            pr->rdone = 1;
+          }
+      }
+
       // ---- FP64 refinement (as refine_z), problem by problem until its
       // first-order correction is small.  The pairs first go into the
       // ascending order of their eigenvalues, so that a window of the
@@ -1033,13 +1047,18 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
             d.C = c; d.ldc = ld;
             return d;
           };
-          g00.push_back(nn_gemm(M2, 0, pr->x, 0, pr->q));   // M2 x
-          g00.push_back(nn_gemm(M1, 0, pr->y, 0, Ex));      // M1 y (Ex is free until k_build)
+          // M1, M2 hold the Cholesky factors L1, L2
+          GemmDesc t2 = nn_gemm(M2, 1, pr->x, 0, pr->q);      // L2^H x
+          t2.triA = 1;
+          g00.push_back(t2);
+          GemmDesc t1 = nn_gemm(M1, 1, pr->y, 0, Ex);         // L1^H y (Ex is free until k_build)
+          t1.triA = 1;
+          g00.push_back(t1);
           g10.push_back(nn_gemm(pr->x, 1, pr->y, 0, pr->f));  // F = x^H y
-          GemmDesc p2 = nn_gemm(pr->x, 1, pr->q, 0, P2);      // P2 = x^H M2 x (lower tiles)
+          GemmDesc p2 = nn_gemm(pr->q, 1, pr->q, 0, P2);      // P2 = x^H M2 x (lower tiles)
           p2.lowerC = 1;
           g10.push_back(p2);
-          GemmDesc p1 = nn_gemm(pr->y, 1, Ex, 0, P1);         // P1 = y^H M1 y (lower tiles)
+          GemmDesc p1 = nn_gemm(Ex, 1, Ex, 0, P1);            // P1 = y^H M1 y (lower tiles)
           p1.lowerC = 1;
           g10.push_back(p1);
           mi.add({(int)ld, P2, ld}, tiles64((int)ld));

@@ -457,8 +457,6 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   if (int e = form_and_check_args(n, A, lda, B, ldb, upper, base, p, s)) return e;
   BSE_TRY(lower_to_c64(np, M1, ld, L1c, s));
   BSE_TRY(lower_to_c64(np, M2, ld, L2c, s));
-  BSE_TRY(mirror_upper_z(np, M1, ld, s));  // full Hermitian FP64 M1, M2 for the refinement
-  BSE_TRY(mirror_upper_z(np, M2, ld, s));
   tm.mark();
   BSE_TRY(cholesky_pair_c(np, n, L1c, L2c, ld, linv, status, s, p.side));
   {
@@ -500,6 +498,15 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   BSE_TRY(c64_to_c128(np, L1c, ld, X1, ld, scl, s));  // x = V1 / ||Ws||^2 (FP64)
   BSE_TRY(c64_to_c128(np, Yc, ld, X2, ld, nullptr, s));  // y = V2
   tm.mark();
+  // FP64 Cholesky factors of M1, M2 (in place; the strict upper parts stay
+  // zero) for the refinement's products
+  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, reinterpret_cast<double2*>(linv), status, s, p.side));
+  {
+    int st = 0;
+    BSE_TRY(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));
+    BSE_TRY(hipStreamSynchronize(s));
+    if (st != big) return solve_fp64_fallback(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, s);
+  }
   double2* x = X1;
   double2* y = X2;
   double maxcorr = 0.0;

@@ -400,8 +400,10 @@ double2* window_blocks(double2* Cb0, int n, int pass);
 // scl_k = (Re x_k^H y_k)^-1/2.
 hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const double2* Qx,
                       const double2* Qy, double* lam, double* scl, hipStream_t s);
-// corr_hist (host, optional): the largest correction of each step (first 8).
-hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** x, double2** y,
+// L1, L2: the FP64 Cholesky factors of M1 = A + B and M2 = A - B (lower,
+// zero strict upper part); corr_hist (host, optional): the largest correction
+// of each step (first 8).
+hipError_t refine_z(int n, long ld, const double2* L1, const double2* L2, double2** x, double2** y,
                     const RefineWork& w, int max_steps, double stop_corr, double* lam, double* scl,
                     double* max_corr, int* steps_done, hipStream_t s, double* corr_hist = nullptr,
                     int* window_steps = nullptr);

@@ -8,7 +8,9 @@
 // read Z^H Sigma Z = S = diag(I, -I) and Z^H Hcal Z = diag(Lambda, Lambda).
 // Since Q^H Sigma Q = 1/2 [0 I; I 0] and Q^H Hcal Q = 1/2 diag(M2, M1)
 // (Lemma Qtransform), all of Z^H Sigma Z and Z^H Hcal Z follows from three
-// n x n products F = x^H y, P2 = x^H M2 x, P1 = y^H M1 y:
+// n x n products F = x^H y, P2 = x^H M2 x, P1 = y^H M1 y (the latter two as
+// Grams of L2^H x and L1^H y with the FP64 Cholesky factors M = L L^H of
+// Alg. 3 steps 1-2: a triangular product and half a Gram each):
 //   G11 = (F + F^H)/2,   G21 = (F^H - F)/2,
 //   T11 = (P2 + P1)/2,   T21 = (P1 - P2)/2.
 // A first-order correction Z <- Z (I + S E) that restores both conditions
@@ -399,7 +401,7 @@ hipError_t rq_pairs_z(int n, long ld, const double2* x, const double2* y, const 
   return launch_one<RqOp>(qa, n, 0, s);
 }
 
-hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double2** xp,
+hipError_t refine_z(int n, long ld, const double2* L1, const double2* L2, double2** xp,
                     double2** yp, const RefineWork& w, int max_steps, double stop_corr, double* lam,
                     double* scl, double* max_corr, int* steps_done, hipStream_t s,
                     double* corr_hist, int* window_steps) {
@@ -431,13 +433,18 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
     e = hipMemsetAsync(w.maxcorr, 0, 3 * sizeof(double), s);
     if (e != hipSuccess) return e;
     if ((e = gemm_z(nn(n, ld, x, 1, y, 0, F), s)) != hipSuccess) return e;       // F = x^H y
-    if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, Q), s)) != hipSuccess) return e;      // Q = M2 x
-    // P2 = x^H M2 x and P1 = y^H M1 y are Hermitian: lower tiles, then mirrored
-    GemmDesc p2 = nn(n, ld, x, 1, Q, 0, w.P2);
+    // P2 = x^H M2 x = (L2^H x)^H (L2^H x) and P1 = (L1^H y)^H (L1^H y): a
+    // triangular product, then the lower tiles of a Gram (mirrored below)
+    GemmDesc t2 = nn(n, ld, L2, 1, x, 0, Q);                                     // Q = L2^H x
+    t2.triA = 1;
+    if ((e = gemm_z(t2, s)) != hipSuccess) return e;
+    GemmDesc p2 = nn(n, ld, Q, 1, Q, 0, w.P2);
     p2.lowerC = 1;
     if ((e = gemm_z(p2, s)) != hipSuccess) return e;
-    if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, Q), s)) != hipSuccess) return e;      // Q = M1 y
-    GemmDesc p1 = nn(n, ld, y, 1, Q, 0, w.P1);
+    GemmDesc t1 = nn(n, ld, L1, 1, y, 0, Q);                                     // Q = L1^H y
+    t1.triA = 1;
+    if ((e = gemm_z(t1, s)) != hipSuccess) return e;
+    GemmDesc p1 = nn(n, ld, Q, 1, Q, 0, w.P1);
     p1.lowerC = 1;
     if ((e = gemm_z(p1, s)) != hipSuccess) return e;
     if ((e = mirror_upper_z((int)((n + 63) / 64 * 64), w.P2, ld, s)) != hipSuccess) return e;
@@ -538,8 +545,16 @@ hipError_t refine_z(int n, long ld, const double2* M1, const double2* M2, double
   }
   if (*steps_done == 0) {
     // no step ran: Rayleigh quotients and Sigma-normalising scales of the start
-    if ((e = gemm_z(nn(n, ld, M2, 0, x, 0, w.P2), s)) != hipSuccess) return e;
-    if ((e = gemm_z(nn(n, ld, M1, 0, y, 0, w.P1), s)) != hipSuccess) return e;
+    // M2 x = L2 (L2^H x) and M1 y = L1 (L1^H y)
+    for (int f = 0; f < 2; ++f) {
+      const double2* L = f ? L1 : L2;
+      GemmDesc a = nn(n, ld, L, 1, f ? y : x, 0, Q);
+      a.triA = 1;
+      if ((e = gemm_z(a, s)) != hipSuccess) return e;
+      GemmDesc b = nn(n, ld, L, 0, Q, 0, f ? w.P1 : w.P2);
+      b.triA = 1;
+      if ((e = gemm_z(b, s)) != hipSuccess) return e;
+    }
     if ((e = hipMemsetAsync(w.maxcorr, 0, sizeof(double), s)) != hipSuccess) return e;
     const RqArgs qa = {n, x, y, w.P2, w.P1, ld, lam, scl, w.maxcorr};
     if ((e = launch_one<RqOp>(qa, n, 0, s)) != hipSuccess) return e;
