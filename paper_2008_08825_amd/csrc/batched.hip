@@ -990,7 +990,7 @@ int solve_batched_grouped(int batch, const int* n, const void* const* A, const i
           }
       }
 
-      // ---- FP64 refinement (as refine_z), problem by problem until its
+      // ---- FP64 refinement (as refine_z), each problem until its
       // first-order correction is small.  The pairs first go into the
       // ascending order of their eigenvalues, so that a window of the
       // Rayleigh-Ritz passes holds spectral neighbours.
