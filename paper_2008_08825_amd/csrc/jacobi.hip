@@ -751,12 +751,13 @@ BSE_DEV void EigOp<T>::run(const typename EigOp<T>::Args& a, int bx, int t) {
     if (tid == 0) atomicAdd(inner_rot_count, a);
   }
 
-  // 4. R to global, column-major 64 x 64.
+  // 4. R to global, row-major 64 x 64 (the rotation kernel then stages it
+  // into LDS row by row, each wave's stores to consecutive banks)
   C2* dst = Rout + (long)k * JP * JP;
   for (int e = tid; e < JP * JP; e += NT) {
-    const int i = e & 63, j = e >> 6;
+    const int j = e & 63, i = e >> 6;
     C2 v; v.x = (T)R[i][j].x; v.y = (T)R[i][j].y;
-    dst[i + JP * j] = v;
+    dst[j + JP * i] = v;
   }
   if (tid == 0) {
     flags[k] = 1;
@@ -897,8 +898,8 @@ BSE_DEV void RotOp<T>::run(const typename RotOp<T>::Args& a, int bx, int t) {
   round_pair(N, t, k, p, q);
   const C2* R = a.R + (long)k * JP * JP;
   for (int e = tid; e < JP * JP; e += 256) {
-    const int i = e & 63, j = e >> 6;  // R[i][j], i = k index, j = n index
-    Rs[i * rot_ld<T>() + j] = R[i + JP * j];
+    const int j = e & 63, i = e >> 6;  // R[i][j], i = k index, j = n index (row-major in memory)
+    Rs[i * rot_ld<T>() + j] = R[j + JP * i];
   }
   // the lane's input column of k-step kk is 4 kk + lane / 16 of the pair
   // (block p for kk < 8, block q after): lp0 / lp1 point at it for kk = 0 / 8
