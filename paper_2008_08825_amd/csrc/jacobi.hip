@@ -29,7 +29,12 @@ namespace {
 constexpr int JB = 32;      // columns per block
 constexpr int JP = 64;      // columns per pair
 constexpr int NTILE = 10;   // 16 x 16 tiles on or below the diagonal of a 64 x 64 Gram
-constexpr int LPAD = 1;
+// Row padding of the inner eigensolver's 64 x 64 LDS arrays (entries of 16
+// bytes).  Its step loop reads and writes 2 x 2 blocks at circle-ordering
+// indices; a count of the bank cycles of those accesses over a sweep (16, 8
+// or 32 lanes per LDS cycle) puts a padding of 5 entries at 1.7-2.3 times the
+// conflict-free count, against 1.8-3.4 for a padding of 1.
+constexpr int LPAD = 5;
 
 __device__ __constant__ int kTileI[NTILE] = {0, 1, 1, 2, 2, 2, 3, 3, 3, 3};
 __device__ __constant__ int kTileJ[NTILE] = {0, 0, 1, 0, 1, 2, 0, 1, 2, 3};
