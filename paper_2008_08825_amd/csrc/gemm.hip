@@ -31,7 +31,11 @@ BSE_DEV int gemm_swz(int k, int c) { return k * 64 + (c ^ k ^ ((k & 1) << 4)); }
 template <typename T, int OPA, int OPB, bool KS = false>
 struct GemmOp {
   static constexpr int NT = 256;
-  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : 3;  // registers for two staged steps
+  // registers for two staged steps: complex128 two waves per SIMD; complex64
+  // three (the compiler then fits op(A) = A^H in 168 registers without a
+  // spill under a bound of two, while op(A) = A spills 8 bytes under three and
+  // needs 174 registers, two waves, without it)
+  static constexpr int MIN_WAVES = sizeof(T) == 8 ? 2 : (OPA == 1 ? 2 : 3);
   typedef GemmArgs<T> Args;
   static BSE_DEV void run(const Args& p, int bx, int aux);
 };
