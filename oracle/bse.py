@@ -29,6 +29,9 @@ Routes
 ``solve_pencil``    the Hermitian-definite pencil route (Thm DefiniteRealEvals).
 ``solve_dense``     nonsymmetric ``eig`` of the full ``H1`` (tiny n only).
 ``solve_mp``        mpmath eigenvalues of ``H1`` at 50 digits (n <= 6).
+``solve_form2``     form II (Eq. Hform2): the Hermitian-definite pencil of its
+                    Hamiltonian, the definition of its eigenpairs (no algorithm
+                    of the paper is involved).
 
 Paper readings used here: the display of Lemma Qtransform has the two
 off-diagonal blocks swapped; direct computation (and the proof of Thm ProdEig)
@@ -55,6 +58,11 @@ __all__ = [
     "solve_dense",
     "solve_mp",
     "negative_half",
+    "symmetric_from_lower",
+    "bse_matrix_form2",
+    "bse_hamiltonian_form2",
+    "solve_form2",
+    "negative_half_form2",
     "chol_status",
     "grad_from_eigenpairs",
     "spectrum_loss",
@@ -258,6 +266,54 @@ def negative_half(lam: np.ndarray, X: np.ndarray):
     """Lemma ComputeNegEvecs (form I): ``-lambda`` with ``[[0, I], [I, 0]] X``."""
     n = X.shape[0] // 2
     PX = np.vstack([X[n:], X[:n]])
+    return -lam, PX
+
+
+def symmetric_from_lower(M: np.ndarray) -> np.ndarray:
+    """Complex symmetric (``M = M^T``, no conjugation) matrix defined by the lower triangle of ``M``."""
+    M = np.asarray(M).astype(np.complex128)
+    L = np.tril(M, -1)
+    return L + L.T + np.diag(M.diagonal())
+
+
+def bse_matrix_form2(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """``H2 = [[A, B], [-B^H, -A^T]]`` (Eq. Hform2), ``A = A^H``, ``B = B^T``, from lower triangles."""
+    A = hermitian_from_lower(A)
+    B = symmetric_from_lower(B)
+    return np.block([[A, B], [-B.conj().T, -A.T]])
+
+
+def bse_hamiltonian_form2(A: np.ndarray, B: np.ndarray) -> np.ndarray:
+    """``Hcal2 = Sigma H2 = [[A, B], [conj(B), conj(A)]]``, Hermitian (positive definite by assumption)."""
+    A = hermitian_from_lower(A)
+    B = symmetric_from_lower(B)
+    return np.block([[A, B], [B.conj(), A.conj()]])
+
+
+def solve_form2(A: np.ndarray, B: np.ndarray):
+    """Positive eigenpairs of a form-II BSE matrix by the Hermitian-definite pencil.
+
+    ``H2 x = lambda x`` with ``H2 = Sigma Hcal2`` is ``Sigma z = mu Hcal2 z`` with
+    ``mu = 1 / lambda`` (as the pencil route of form I; the proof of Thm
+    DefiniteRealEvals holds for any Hermitian positive definite Hamiltonian).
+    LAPACK ``hegv`` returns ``z^H Hcal2 z = 1``; the positive pairs are
+    rescaled to ``x = z / sqrt(mu)``, ``x^H Sigma x = 1``.
+    """
+    n = A.shape[0]
+    Hc = bse_hamiltonian_form2(A, B)
+    S = np.diag(np.concatenate([np.ones(n), -np.ones(n)])).astype(np.complex128)
+    mu, Z = sla.eigh(S, Hc)
+    pos = mu > 0
+    lam = 1.0 / mu[pos]
+    V = Z[:, pos] / np.sqrt(mu[pos])
+    order = np.argsort(lam, kind="stable")
+    return lam[order], V[:, order]
+
+
+def negative_half_form2(lam: np.ndarray, X: np.ndarray):
+    """Lemma ComputeNegEvecs (form II): ``-lambda`` with ``[[0, I], [I, 0]] conj(X)``."""
+    n = X.shape[0] // 2
+    PX = np.vstack([X[n:], X[:n]]).conj()
     return -lam, PX
 
 
