@@ -186,6 +186,36 @@ int bse_solve_h1(int n, const void* A, int lda, const void* B, int ldb,
                  void* work, size_t work_bytes,
                  const bse_opts_t* opts, bse_info_t* info, void* stream);
 
+/* Workspace bytes bse_solve_h2 needs for order n under `opts` (NULL =
+ * defaults); 0 for an invalid n (n > 23000) or opts (route TDA included). */
+size_t bse_workspace_bytes_h2(int n, const bse_opts_t* opts);
+
+/* All eigenpairs of a BSE matrix of form II (Eq. Hform2),
+ *   H2 = [A B; -B^H -A^T],  A = A^H,  B = B^T (complex symmetric),
+ * with the Hamiltonian [A B; conj(B) conj(A)] positive definite (Thm Form2
+ * gives the structure; the paper has no algorithm for it).  The problem is
+ * mapped to a real form-I problem of order 2n, A' = [Re A  -Im A; Im A  Re A],
+ * B' = [Re B  Im B; Im B  -Re B], whose eigenvalues are those of H2, each
+ * twice; bse_solve_h1 solves it with `opts` (route SVD, EIG or SQRT, any
+ * precision allowed there) and each pair becomes one eigenpair of H2.
+ *   n, A, lda, B, ldb   as bse_solve_h1 (triangle `uplo` of A and of B read;
+ *                       B's other triangle is its transpose, no conjugation)
+ *   lambda   n doubles (2n if want_negative: +lambda ascending, then -lambda)
+ *   X, ldx   2n x n complex128 (2n x 2n if want_negative), ldx >= max(1, 2n):
+ *            eigenvectors with x^H Sigma x = 1; the negative half is
+ *            [0 I; I 0] conj(X) (Lemma ComputeNegEvecs, part 2)
+ *   work     device workspace of work_bytes >= bse_workspace_bytes_h2(n, opts)
+ * opts.checks is ignored.  For an eigenvalue of H2 that is (numerically)
+ * multiple, the returned vectors of its group need not be independent (the
+ * eigenvalues are unaffected).  Returns 0; -1 n, -2 A, -3 lda, -4 B, -5 ldb,
+ * -6 lambda, -7 X, -8 ldx, -9 work NULL, -10 work_bytes too small, -11 opts
+ * invalid or route TDA; a positive status is bse_solve_h1's for the order-2n
+ * problem (e.g. 1..2n: A' + B' not positive definite); <= -1000 HIP error. */
+int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb,
+                 double* lambda, void* X, int ldx,
+                 void* work, size_t work_bytes,
+                 const bse_opts_t* opts, bse_info_t* info, void* stream);
+
 /* Workspace for bse_solve_batched over `batch` problems of orders n[0..batch). */
 size_t bse_batched_workspace_bytes(int batch, const int* n, const bse_opts_t* opts);
 

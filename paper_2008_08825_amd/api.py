@@ -121,6 +121,8 @@ EXPORTS = [
     "bse_status_string",
     "bse_solve_h1_noalloc",
     "bse_noalloc_scratch_bytes",
+    "bse_workspace_bytes_h2",
+    "bse_solve_h2",
 ]
 
 _lib = None
@@ -144,6 +146,11 @@ def load_library(path: Optional[str] = None):
     lib.bse_solve_h1.argtypes = [ci, vp, ci, vp, ci, vp, vp, ci, vp, ctypes.c_size_t,
                                  ctypes.POINTER(BSEOpts), ctypes.POINTER(BSEInfo), vp]
     lib.bse_solve_h1.restype = ci
+    lib.bse_workspace_bytes_h2.argtypes = [ci, ctypes.POINTER(BSEOpts)]
+    lib.bse_workspace_bytes_h2.restype = ctypes.c_size_t
+    lib.bse_solve_h2.argtypes = [ci, vp, ci, vp, ci, vp, vp, ci, vp, ctypes.c_size_t,
+                                 ctypes.POINTER(BSEOpts), ctypes.POINTER(BSEInfo), vp]
+    lib.bse_solve_h2.restype = ci
     lib.bse_batched_workspace_bytes.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(BSEOpts)]
     lib.bse_batched_workspace_bytes.restype = ctypes.c_size_t
     lib.bse_solve_batched.argtypes = [ci, ctypes.POINTER(ci), ctypes.POINTER(vp), ctypes.POINTER(ci),
@@ -290,6 +297,47 @@ def solve_h1(A: torch.Tensor, B: Optional[torch.Tensor], *, route="svd", precisi
     if ua == "U":
         X = X.conj()
     return lam, X, d
+
+
+def solve_h2(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64", want_negative=False,
+             max_sweeps=0, refine_steps=0, jacobi_tol=0.0, check=True,
+             work: Optional[torch.Tensor] = None, tiles=None, values_only=False):
+    """All eigenpairs of a form-II matrix H2 = [[A, B], [-B^H, -A^T]] (A Hermitian,
+    B complex symmetric; lower triangles read) through ``bse_solve_h2``.
+
+    Returns ``(lam, X, info)`` as :func:`solve_h1`; the negative half is
+    ``[[0, I], [I, 0]] conj(X)``.
+    """
+    lib = load_library()
+    if A.shape != B.shape or A.dim() != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("A and B must be square and of the same shape")
+    n = A.shape[0]
+    dev = A.device
+    # column-major copies: the transposed view of B is B itself but that of A is conj(A),
+    # so the row-major trick of solve_h1 does not apply to form II
+    Ac = A.to(torch.complex128).mT.contiguous()
+    Bc = B.to(torch.complex128).mT.contiguous()
+    ncols = 2 * n if want_negative else n
+    o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, "L", tiles,
+                  False, values_only)
+    lam = torch.empty(ncols, dtype=torch.float64, device=dev)
+    Xbuf = None if values_only else torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
+    need = int(lib.bse_workspace_bytes_h2(n, ctypes.byref(o)))
+    if need == 0 and n > 0:
+        raise ValueError("invalid order or options for form II")
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    info = BSEInfo()
+    with torch.cuda.device(dev):
+        st = lib.bse_solve_h2(n, Ac.data_ptr(), max(1, n), Bc.data_ptr(), max(1, n), lam.data_ptr(),
+                              Xbuf.data_ptr() if Xbuf is not None else None, max(1, 2 * n),
+                              work.data_ptr(), work.numel(), ctypes.byref(o), ctypes.byref(info),
+                              _stream_handle(dev))
+    d = info.as_dict()
+    d["status"] = st
+    if check and st != 0:
+        raise BSEError(st, 2 * n, d)
+    return lam, (None if Xbuf is None else Xbuf.mT), d
 
 
 def solve_h1_noalloc(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",

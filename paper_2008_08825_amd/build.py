@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libbse.so")
 
 SOURCES = ["capi.hip", "gemm.hip", "chol.hip", "jacobi.hip", "finalize.hip", "refine.hip",
            "adjoint.hip", "batched.hip", "checks.hip",
-           "noalloc.hip", "window.hip"]
+           "noalloc.hip", "window.hip", "form2.hip"]
 
 HIP_FLAGS = [
     "-O3",

@@ -1,0 +1,187 @@
+// BSE matrices of form II (Eq. Hform2): H2 = [A B; -B^H -A^T], A Hermitian,
+// B complex symmetric, the Hamiltonian Sigma H2 = [A B; conj(B) conj(A)]
+// Hermitian positive definite.
+//
+// The paper characterises form II (Thm Form2) but gives no algorithm for it;
+// it notes that real form-II matrices are treated with the idea of Alg. 3,
+// and a real form-II matrix is a form-I matrix.  A complex one becomes a real
+// form-I matrix of twice the order: writing A = Ar + i Ai, B = Br + i Bi and
+// x = [u; v], the real vector z = [Re u; Im u; Re v; -Im v] satisfies
+// H1' z = lambda z with
+//   H1' = [A' B'; -B' -A'],  A' = [Ar -Ai; Ai Ar],  B' = [Br Bi; Bi -Br],
+// both real symmetric (A Hermitian, B symmetric), and A' +- B' positive
+// definite exactly when the Hamiltonian is (a real congruence of it).  Every
+// eigenvalue of H2 appears twice in H1' (z and the image of i x), so the
+// form-I solver (any route and precision) runs on (A', B') of order 2n, and
+// eigenpair k of H2 is eigenvalue 2k of H1' with the complex vector of its
+// eigenvector; the Sigma-normalisation carries over (z^T Sigma' z = x^H Sigma x).
+// For an eigenvalue of H2 that is (numerically) multiple, the two vectors
+// taken from a group of 2m equal eigenvalues of H1' need not span its
+// eigenspace; eigenvalues are unaffected.
+#include "../../include/bse.h"
+#include "common.hpp"
+#include "internal.hpp"
+#include "plan.hpp"
+
+namespace bse {
+namespace {
+
+// A' and B' (order 2n, both triangles, padding left to the form-I solver):
+// one 64 x 64 tile of the 2n x 2n matrices per work group.
+struct RealifyArgs {
+  int n, upper; const double2* A; long lda; const double2* B; long ldb; double2* At; double2* Bt; long ld;
+};
+struct RealifyOp {
+  static constexpr int NT = 256;
+  typedef RealifyArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int m = 2 * a.n, T = (m + 63) / 64;
+    const int i = (bx % T) * 64 + (threadIdx.x & 63), j0 = (bx / T) * 64 + (threadIdx.x >> 6);
+    if (i >= m) return;
+    const int bi = i >= a.n, ri = i - bi * a.n;
+    for (int j = j0; j < j0 + 64 && j < m; j += 4) {
+      const int bj = j >= a.n, rj = j - bj * a.n;
+      // A[ri][rj] (Hermitian, real diagonal) and B[ri][rj] (symmetric) from the stored triangle
+      const bool low = ri >= rj;
+      const bool st = a.upper ? !low : low;  // element (ri, rj) itself is stored
+      const int r = st ? ri : rj, c = st ? rj : ri;
+      double2 av = a.A[r + (long)c * a.lda];
+      if (!st) av.y = -av.y;
+      if (ri == rj) av.y = 0.0;
+      const double2 bv = a.B[r + (long)c * a.ldb];
+      // A' = [Ar -Ai; Ai Ar], B' = [Br Bi; Bi -Br] (real, stored as complex128)
+      const double at = bi == bj ? av.x : (bi ? av.y : -av.y);
+      const double bt = bi != bj ? bv.y : (bi ? -bv.x : bv.x);
+      a.At[i + (long)j * a.ld] = make_double2(at, 0.0);
+      a.Bt[i + (long)j * a.ld] = make_double2(bt, 0.0);
+    }
+  }
+};
+
+// lambda_k = (lambda'_2k + lambda'_2k+1) / 2 and x_k from z = column 2k of
+// X' (order 2n, positive half): u = z1 + i z2, v = z3 - i z4; with the
+// negative half, -lambda_k and [0 I; I 0] conj(x_k) (Lemma ComputeNegEvecs,
+// part 2).  Work group = (column k, 256 rows of x).
+struct ExtractArgs {
+  int n; const double* lam2; const double2* X2; long ldx2; double* lambda; double2* X; long ldx;
+  int want_negative, values_only;
+};
+struct ExtractOp {
+  static constexpr int NT = 256;
+  typedef ExtractArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int n = a.n, gx = (2 * n + 255) / 256;
+    const int k = bx / gx, r = (bx % gx) * 256 + threadIdx.x;
+    if (k >= n) return;
+    if (r == 0) {
+      const double l = 0.5 * (a.lam2[2 * k] + a.lam2[2 * k + 1]);
+      a.lambda[k] = l;
+      if (a.want_negative) a.lambda[n + k] = -l;
+    }
+    if (a.values_only || r >= 2 * n) return;
+    const double2* z = a.X2 + (long)(2 * k) * a.ldx2;
+    const int q = r % n;
+    double2 x;
+    if (r < n) x = make_double2(z[q].x, z[n + q].x);              // u = Re part + i Im part
+    else x = make_double2(z[2 * n + q].x, -z[3 * n + q].x);      // v = conj(w)
+    a.X[r + (long)k * a.ldx] = x;
+    if (a.want_negative) {  // [0 I; I 0] conj(x): row r of x goes to row r +- n, conjugated
+      const int rn = r < n ? r + n : r - n;
+      a.X[rn + (long)(n + k) * a.ldx] = make_double2(x.x, -x.y);
+    }
+  }
+};
+
+struct H2Layout {
+  size_t off_at = 0, off_bt = 0, off_lam = 0, off_x = 0, off_inner = 0;
+};
+
+H2Layout h2_layout(int n, const bse_opts_t& o) {
+  H2Layout L;
+  const size_t m = (size_t)2 * n;
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off = align256(off + b);
+    return at;
+  };
+  L.off_at = take(m * m * sizeof(double2));
+  L.off_bt = take(m * m * sizeof(double2));
+  L.off_lam = take(m * sizeof(double));
+  L.off_x = take(o.values_only ? 0 : 2 * m * m * sizeof(double2));
+  L.off_inner = take(0);
+  return L;
+}
+
+bse_opts_t inner_opts(const bse_opts_t& o) {
+  bse_opts_t io = o;
+  io.uplo = 'L';
+  io.want_negative = 0;
+  io.checks = 0;
+  return io;
+}
+
+}  // namespace
+}  // namespace bse
+
+extern "C" {
+
+size_t bse_workspace_bytes_h2(int n, const bse_opts_t* opts) {
+  bse_opts_t o;
+  bse_default_opts(&o);
+  if (opts) o = *opts;
+  if (n < 0 || n > 23000 || !bse::opts_valid(o) || o.route == BSE_ROUTE_TDA) return 0;
+  const bse::H2Layout L = bse::h2_layout(n, o);
+  const bse_opts_t io = bse::inner_opts(o);
+  const size_t inner = bse_workspace_bytes(2 * n, &io);
+  if (inner == 0) return 0;
+  return L.off_inner + inner + 256;
+}
+
+int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* lambda, void* X,
+                 int ldx, void* work, size_t work_bytes, const bse_opts_t* opts, bse_info_t* info,
+                 void* stream) {
+  bse_opts_t o;
+  bse_default_opts(&o);
+  if (opts) o = *opts;
+  if (n < 0 || n > 23000) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (n > 0 && !B) return -4;
+  if (ldb < (n > 1 ? n : 1)) return -5;
+  if (n > 0 && !lambda) return -6;
+  if (n > 0 && !X && !o.values_only) return -7;
+  if (!o.values_only && ldx < (2 * n > 1 ? 2 * n : 1)) return -8;
+  if (!bse::opts_valid(o) || o.route == BSE_ROUTE_TDA) return -11;
+  if (n == 0) return 0;
+  const size_t need = bse_workspace_bytes_h2(n, &o);
+  if (!work) return -9;
+  if (work_bytes < need) return -10;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(work) + 255) & ~(uintptr_t)255);
+  const bse::H2Layout L = bse::h2_layout(n, o);
+  const int m = 2 * n;
+  double2* At = reinterpret_cast<double2*>(base + L.off_at);
+  double2* Bt = reinterpret_cast<double2*>(base + L.off_bt);
+  double* lam2 = reinterpret_cast<double*>(base + L.off_lam);
+  double2* X2 = o.values_only ? nullptr : reinterpret_cast<double2*>(base + L.off_x);
+  const int upper = (o.uplo == 'U' || o.uplo == 'u');
+  const bse::RealifyArgs ra = {n, upper, static_cast<const double2*>(A), lda, static_cast<const double2*>(B),
+                               ldb, At, Bt, m};
+  const int T = (m + 63) / 64;
+  hipError_t e = launch_one<bse::RealifyOp>(ra, T * T, 0, s);
+  if (e != hipSuccess) return bse::hip_status(e);
+  const bse_opts_t io = bse::inner_opts(o);
+  const int st = bse_solve_h1(m, At, m, Bt, m, lam2, X2, m > 0 ? 2 * m : 1, base + L.off_inner,
+                              work_bytes - (size_t)(base - static_cast<char*>(work)) - L.off_inner, &io,
+                              info, stream);
+  if (st != 0) return st;
+  const bse::ExtractArgs ea = {n, lam2, X2, 2 * m, lambda, static_cast<double2*>(X), ldx, o.want_negative,
+                               o.values_only};
+  e = launch_one<bse::ExtractOp>(ea, n * ((2 * n + 255) / 256), 0, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bse::hip_status(e);
+  return 0;
+}
+
+}  // extern "C"

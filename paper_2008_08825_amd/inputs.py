@@ -87,6 +87,23 @@ def coupled(n: int, seed: int = 0, diag_lo: float = 1.0, diag_hi: float = 10.0,
     return _as_complex(A, real), _as_complex(B, real)
 
 
+def coupled_form2(n: int, seed: int = 0, diag_lo: float = 1.0, diag_hi: float = 10.0,
+                  c_norm: float = 0.3, b_norm: float = 0.3):
+    """Form-II input (Eq. Hform2): A Hermitian as in ``coupled``, B complex symmetric
+    (B = B^T) of spectral norm about ``b_norm`` (Gaussian, symmetrised), so that the
+    Hamiltonian [A B; conj(B) conj(A)] is positive definite when b_norm < diag_lo - c_norm."""
+    rng = np.random.default_rng(seed)
+    D = rng.uniform(diag_lo, diag_hi, size=n)
+    C = hermitian_gaussian(rng, n, c_norm, False)
+    A = C.astype(np.complex128)
+    A[np.diag_indices(n)] += D
+    G = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    S = G + G.T
+    nrm = np.linalg.norm(S, 2) if n > 0 else 1.0
+    B = S * (b_norm / nrm) if nrm > 0 else S
+    return A, B
+
+
 def clustered(n: int, seed: int = 0, diag_lo: float = 1.0, diag_hi: float = 10.0,
               c_norm: float = 0.3, b_norm: float = 0.3, clusters: int = 50,
               width: float = 1e-3):

@@ -1,0 +1,92 @@
+"""Form II (Eq. Hform2) through bse_solve_h2 on the GPU against the oracle's pencil solver.
+
+The library maps a complex form-II problem to a real form-I problem of twice
+the order and solves that with the form-I path; the oracle takes the
+Hermitian-definite pencil of the form-II Hamiltonian (no code shared).
+Checks: eigenvalues, eigenvectors (phase-aligned), residual with H2 itself,
+Sigma-orthonormality, the negative half of Lemma ComputeNegEvecs part 2,
+ragged orders around the 32- and 64-wide tiles, the decoupled closed form,
+real data (form II = form I), the other precisions and routes, values only.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import bse as ob
+from oracle import metrics as om
+from paper_2008_08825_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def sig(n):
+    return np.concatenate([np.ones(n), -np.ones(n)])
+
+
+def run(api, A, B, **kw):
+    lam, X, info = api.solve_h2(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV), **kw)
+    return lam.cpu().numpy(), (None if X is None else X.resolve_conj().cpu().numpy()), info
+
+
+@pytest.mark.parametrize("n", [1, 3, 33, 64, 100, 130])
+def test_form2_vs_oracle(gpu_lib, n):
+    A, B = inputs.coupled_form2(n, seed=800 + n)
+    print(f"[gpu] form II n={n}", flush=True)
+    lam, X, info = run(gpu_lib, A, B, want_negative=True)
+    assert info["status"] == 0
+    lam_o, X_o = ob.solve_form2(A, B)
+    assert om.rel_eig_err(lam[:n], lam_o) < 1e-12
+    H = ob.bse_matrix_form2(A, B)
+    Xp = X[:, :n]
+    assert np.linalg.norm(H @ Xp - Xp * lam[None, :n]) <= 1e-13 * np.linalg.norm(H, 2) * np.linalg.norm(Xp)
+    G = Xp.conj().T @ (sig(n)[:, None] * Xp)
+    assert np.abs(G - np.eye(n)).max() < 1e-11
+    err, gap = om.eigvec_errors(lam_o, X_o, Xp, cluster_rtol=1e-9)
+    assert np.all(err <= 1e-10 + 1e-13 / np.minimum(gap, 1.0)), (np.max(err), np.min(gap))
+    # negative half: -lambda with [0 I; I 0] conj(x)
+    assert np.array_equal(lam[n:], -lam[:n])
+    assert np.array_equal(X[:n, n:], X[n:, :n].conj()) and np.array_equal(X[n:, n:], X[:n, :n].conj())
+
+
+def test_form2_decoupled_closed_form(gpu_lib):
+    """A = Q^H diag(a) Q, B = Q^H diag(b) conj(Q): lambda_i = sqrt(a_i^2 - |b_i|^2)."""
+    n = 40
+    rng = np.random.default_rng(41)
+    Q = inputs.haar_unitary(rng, n)
+    a = rng.uniform(1.0, 5.0, n)
+    b = a * rng.uniform(0.0, 0.9, n) * np.exp(2j * np.pi * rng.uniform(size=n))
+    A = Q.conj().T @ (a[:, None] * Q)
+    A = (A + A.conj().T) / 2
+    B = Q.conj().T @ (b[:, None] * Q.conj())
+    B = (B + B.T) / 2
+    lam, _, _ = run(gpu_lib, A, B)
+    lref = np.sort(np.sqrt(a * a - np.abs(b) ** 2))
+    assert np.max(np.abs(lam - lref) / lref) < 1e-13
+
+
+def test_form2_real_data_equals_form1(gpu_lib):
+    A, B = inputs.coupled(70, seed=9, real=True)
+    lam2, _, _ = run(gpu_lib, A, B)
+    lam1, _, _ = gpu_lib.solve_h1(torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV))
+    assert om.rel_eig_err(lam2, lam1.cpu().numpy()) < 1e-13
+
+
+@pytest.mark.parametrize("kw", [dict(precision="mixed"), dict(precision="mixed_polish"), dict(route="eig")])
+def test_form2_other_forms(gpu_lib, kw):
+    n = 100
+    A, B = inputs.coupled_form2(n, seed=900)
+    lam, X, info = run(gpu_lib, A, B, **kw)
+    assert info["status"] == 0
+    lam_o, _ = ob.solve_form2(A, B)
+    assert om.rel_eig_err(lam, lam_o) < (1e-10 if kw.get("precision") == "mixed" else 1e-11)
+    H = ob.bse_matrix_form2(A, B)
+    assert np.linalg.norm(H @ X - X * lam[None, :]) <= 1e-12 * np.linalg.norm(H, 2) * np.linalg.norm(X)
+
+
+def test_form2_values_only(gpu_lib):
+    A, B = inputs.coupled_form2(65, seed=7)
+    full, _, _ = run(gpu_lib, A, B, want_negative=True)
+    vals, X, _ = run(gpu_lib, A, B, want_negative=True, values_only=True)
+    assert X is None and np.array_equal(full, vals)

@@ -162,3 +162,32 @@ def test_batched_host_argument_checks():
     assert need > single
     good = api.make_opts(tiles=[(64, 1, 64), (128, 2, 128)])
     assert lib.bse_batched_workspace_bytes(2, n, ctypes.byref(good)) == need
+
+
+def test_form2_host_argument_checks():
+    """bse_solve_h2 (form II) rejects bad arguments and the TDA route before any device work."""
+    from paper_2008_08825_amd import api
+
+    lib = api.load_library()
+    o = api.make_opts()
+    n4 = lib.bse_workspace_bytes_h2(4, ctypes.byref(o))
+    assert n4 >= lib.bse_workspace_bytes(8, ctypes.byref(o)) + 2 * 8 * 8 * 16
+    assert lib.bse_workspace_bytes_h2(-1, ctypes.byref(o)) == 0
+    assert lib.bse_workspace_bytes_h2(23001, ctypes.byref(o)) == 0
+    tda = api.make_opts(route="tda")
+    assert lib.bse_workspace_bytes_h2(4, ctypes.byref(tda)) == 0
+    h2 = lib.bse_solve_h2
+    assert h2(-1, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), None, None) == -1
+    assert h2(4, None, 4, 16, 4, 16, 16, 8, 16, 1 << 30, ctypes.byref(o), None, None) == -2
+    assert h2(4, 16, 3, 16, 4, 16, 16, 8, 16, 1 << 30, ctypes.byref(o), None, None) == -3
+    assert h2(4, 16, 4, None, 4, 16, 16, 8, 16, 1 << 30, ctypes.byref(o), None, None) == -4
+    assert h2(4, 16, 4, 16, 3, 16, 16, 8, 16, 1 << 30, ctypes.byref(o), None, None) == -5
+    assert h2(4, 16, 4, 16, 4, None, 16, 8, 16, 1 << 30, ctypes.byref(o), None, None) == -6
+    assert h2(4, 16, 4, 16, 4, 16, None, 8, 16, 1 << 30, ctypes.byref(o), None, None) == -7
+    assert h2(4, 16, 4, 16, 4, 16, 16, 7, 16, 1 << 30, ctypes.byref(o), None, None) == -8
+    assert h2(4, 16, 4, 16, 4, 16, 16, 8, None, 0, ctypes.byref(o), None, None) == -9
+    assert h2(4, 16, 4, 16, 4, 16, 16, 8, 16, 10, ctypes.byref(o), None, None) == -10
+    assert h2(4, 16, 4, 16, 4, 16, 16, 8, 16, 1 << 30, ctypes.byref(tda), None, None) == -11
+    assert h2(0, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), None, None) == 0
+    vo = api.make_opts(values_only=True)
+    assert h2(4, 16, 4, 16, 4, 16, None, 0, None, 0, ctypes.byref(vo), None, None) == -9
