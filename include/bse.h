@@ -1,6 +1,6 @@
 /*
  * bse.h -- C ABI of the MI355X (gfx950) solver for the Bethe-Salpeter
- * eigenproblem of form I.
+ * eigenproblem of form I (and of form II through it: bse_solve_h2).
  *
  * Problem (Benner & Penke, Sec. 1 Eq. Hform1; Alg. 3 Require/Ensure):
  *   H1 = [ A  B ; -B  -A ]  with  A = A^H, B = B^H  in C^{n x n}

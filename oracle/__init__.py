@@ -1,4 +1,4 @@
-"""FP64 CPU oracle for the BSE form-I eigenproblem -- test infrastructure.
+"""FP64 CPU oracle for the BSE eigenproblem (forms I and II) -- test infrastructure.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package.  It shares no code with the HIP solver.
