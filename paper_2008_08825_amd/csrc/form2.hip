@@ -15,13 +15,21 @@
 // form-I solver (any route and precision) runs on (A', B') of order 2n, and
 // eigenpair k of H2 is eigenvalue 2k of H1' with the complex vector of its
 // eigenvector; the Sigma-normalisation carries over (z^T Sigma' z = x^H Sigma x).
-// For an eigenvalue of H2 that is (numerically) multiple, the two vectors
-// taken from a group of 2m equal eigenvalues of H1' need not span its
-// eigenspace; eigenvalues are unaffected.
+// An eigenvalue of H2 of multiplicity m (numerically: a run of m eigenvalues
+// whose gaps are below kClusterGap lambda_max) gives 2m equal eigenvalues of
+// H1' whose 2m complex vectors span its m-dimensional eigenspace; a pivoted
+// Gram-Schmidt in the Sigma inner product (positive definite on the
+// eigenspaces of positive eigenvalues) picks m of them and makes them
+// Sigma-orthonormal (runs of up to kClusterMax; longer runs keep one vector
+// per pair, which may leave them dependent).
 #include "../../include/bse.h"
 #include "common.hpp"
 #include "internal.hpp"
 #include "plan.hpp"
+
+#include <math.h>
+
+#include <vector>
 
 namespace bse {
 namespace {
@@ -92,8 +100,124 @@ struct ExtractOp {
   }
 };
 
+constexpr double kClusterGap = 1.0e-12;
+constexpr int kClusterMax = 64;
+
+// Y[:, j] = complex vector of column j of X' (all 2n columns), for the runs of
+// multiple eigenvalues.  Work group = (column j, 256 rows of x).
+struct MapArgs { int n; const double2* X2; long ldx2; double2* Y; long ldy; };
+struct MapOp {
+  static constexpr int NT = 256;
+  typedef MapArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int n = a.n, gx = (2 * n + 255) / 256;
+    const int j = bx / gx, r = (bx % gx) * 256 + threadIdx.x;
+    if (j >= 2 * n || r >= 2 * n) return;
+    const double2* z = a.X2 + (long)j * a.ldx2;
+    const int q = r % n;
+    a.Y[r + (long)j * a.ldy] = r < n ? make_double2(z[q].x, z[n + q].x) : make_double2(z[2 * n + q].x, -z[3 * n + q].x);
+  }
+};
+
+// One work group per run of m (2 <= m <= kClusterMax) eigenvalues of H2 that
+// are numerically equal, starting at eigenvalue k0 (runs[w] = (k0, m)): among
+// the 2m vectors Y[:, 2 k0 .. 2 k0 + 2m), m steps of pivoted Gram-Schmidt in
+// the inner product <x, y> = x^H Sigma y take the candidate of largest
+// remaining norm, normalise it into column k0 + t of X (and its negative-half
+// image), and remove it from the other candidates.
+struct ClusterArgs { int n; const int2* runs; double2* Y; long ldy; double2* X; long ldx; int want_negative; };
+struct ClusterOp {
+  static constexpr int NT = 256;
+  typedef ClusterArgs Args;
+  static BSE_DEV void run(const Args& a, int w, int) {
+    __shared__ double red[2][NT];
+    __shared__ double nrm[2 * kClusterMax];
+    __shared__ int alive[2 * kClusterMax];
+    __shared__ int piv;
+    const int n = a.n, rows = 2 * n, tid = threadIdx.x;
+    const int k0 = a.runs[w].x, m = a.runs[w].y, c0 = 2 * k0, nc = 2 * m;
+    for (int c = tid; c < nc; c += NT) alive[c] = 1;
+    __syncthreads();
+    // sum over rows r of f(r) by the whole work group, result in red[0][0]
+    auto reduce2 = [&](double vr, double vi) {
+      red[0][tid] = vr;
+      red[1][tid] = vi;
+      __syncthreads();
+      for (int o = NT / 2; o > 0; o >>= 1) {
+        if (tid < o) {
+          red[0][tid] += red[0][tid + o];
+          red[1][tid] += red[1][tid + o];
+        }
+        __syncthreads();
+      }
+    };
+    for (int t = 0; t < m; ++t) {
+      // Sigma-norms of the candidates left
+      for (int c = 0; c < nc; ++c) {
+        if (!alive[c]) continue;  // uniform: alive is in LDS, read after a barrier
+        const double2* y = a.Y + (long)(c0 + c) * a.ldy;
+        double sacc = 0.0;
+        for (int r = tid; r < rows; r += NT) {
+          const double2 v = y[r];
+          const double q = v.x * v.x + v.y * v.y;
+          sacc += r < n ? q : -q;
+        }
+        reduce2(sacc, 0.0);
+        if (tid == 0) nrm[c] = red[0][0];
+        __syncthreads();
+      }
+      if (tid == 0) {
+        int best = -1;
+        for (int c = 0; c < nc; ++c)
+          if (alive[c] && (best < 0 || nrm[c] > nrm[best])) best = c;
+        piv = best;
+        alive[best] = 0;
+      }
+      __syncthreads();
+      const int p = piv;
+      const double inv = nrm[p] > 0.0 ? 1.0 / sqrt(nrm[p]) : 0.0;
+      double2* q = a.Y + (long)(c0 + p) * a.ldy;
+      for (int r = tid; r < rows; r += NT) {
+        double2 v = q[r];
+        v.x *= inv;
+        v.y *= inv;
+        q[r] = v;
+        a.X[r + (long)(k0 + t) * a.ldx] = v;
+        if (a.want_negative) {
+          const int rn = r < n ? r + n : r - n;
+          a.X[rn + (long)(n + k0 + t) * a.ldx] = make_double2(v.x, -v.y);
+        }
+      }
+      __syncthreads();
+      // remove q from the other candidates: y <- y - (q^H Sigma y) q
+      for (int c = 0; c < nc; ++c) {
+        if (!alive[c]) continue;
+        double2* y = a.Y + (long)(c0 + c) * a.ldy;
+        double cr = 0.0, ci = 0.0;
+        for (int r = tid; r < rows; r += NT) {
+          const double2 qv = q[r], v = y[r];
+          const double sg = r < n ? 1.0 : -1.0;
+          cr += sg * (qv.x * v.x + qv.y * v.y);
+          ci += sg * (qv.x * v.y - qv.y * v.x);
+        }
+        reduce2(cr, ci);
+        const double2 cf = make_double2(red[0][0], red[1][0]);
+        __syncthreads();
+        for (int r = tid; r < rows; r += NT) {
+          const double2 qv = q[r];
+          double2 v = y[r];
+          v.x -= cf.x * qv.x - cf.y * qv.y;
+          v.y -= cf.x * qv.y + cf.y * qv.x;
+          y[r] = v;
+        }
+        __syncthreads();
+      }
+    }
+  }
+};
+
 struct H2Layout {
-  size_t off_at = 0, off_bt = 0, off_lam = 0, off_x = 0, off_inner = 0;
+  size_t off_at = 0, off_bt = 0, off_lam = 0, off_x = 0, off_runs = 0, off_inner = 0;
 };
 
 H2Layout h2_layout(int n, const bse_opts_t& o) {
@@ -109,6 +233,7 @@ H2Layout h2_layout(int n, const bse_opts_t& o) {
   L.off_bt = take(m * m * sizeof(double2));
   L.off_lam = take(m * sizeof(double));
   L.off_x = take(o.values_only ? 0 : 2 * m * m * sizeof(double2));
+  L.off_runs = take((size_t)(n + 1) * sizeof(int2));
   L.off_inner = take(0);
   return L;
 }
@@ -179,7 +304,33 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
   const bse::ExtractArgs ea = {n, lam2, X2, 2 * m, lambda, static_cast<double2*>(X), ldx, o.want_negative,
                                o.values_only};
   e = launch_one<bse::ExtractOp>(ea, n * ((2 * n + 255) / 256), 0, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return bse::hip_status(e);
+  if (!o.values_only && n > 1) {
+    // runs of numerically equal eigenvalues of H2 (pairs k, k + 1 joined when
+    // the gap between copies 2k + 1 and 2k + 2 is below kClusterGap lambda_max)
+    std::vector<double> l2(m);
+    e = hipMemcpyAsync(l2.data(), lam2, (size_t)m * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bse::hip_status(e);
+    const double tol = bse::kClusterGap * fabs(l2[m - 1]);
+    std::vector<int2> runs;
+    for (int k = 0; k < n;) {
+      int e1 = k + 1;
+      while (e1 < n && l2[2 * e1] - l2[2 * e1 - 1] <= tol) ++e1;
+      if (e1 - k >= 2 && e1 - k <= bse::kClusterMax) runs.push_back(make_int2(k, e1 - k));
+      k = e1;
+    }
+    if (!runs.empty()) {
+      int2* d_runs = reinterpret_cast<int2*>(base + L.off_runs);
+      e = hipMemcpyAsync(d_runs, runs.data(), runs.size() * sizeof(int2), hipMemcpyHostToDevice, s);
+      const bse::MapArgs ma = {n, X2, 2 * m, At, m};  // A' is free: Y in its place (2n x 2n)
+      if (e == hipSuccess) e = launch_one<bse::MapOp>(ma, m * ((2 * n + 255) / 256), 0, s);
+      const bse::ClusterArgs ca = {n, d_runs, At, m, static_cast<double2*>(X), ldx, o.want_negative};
+      if (e == hipSuccess) e = launch_one<bse::ClusterOp>(ca, (int)runs.size(), 0, s);
+      if (e != hipSuccess) return bse::hip_status(e);
+    }
+  }
+  e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bse::hip_status(e);
   return 0;
 }

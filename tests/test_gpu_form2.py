@@ -90,3 +90,38 @@ def test_form2_values_only(gpu_lib):
     full, _, _ = run(gpu_lib, A, B, want_negative=True)
     vals, X, _ = run(gpu_lib, A, B, want_negative=True, values_only=True)
     assert X is None and np.array_equal(full, vals)
+
+
+@pytest.mark.parametrize("case", ["decoupled_triple", "b_zero_repeated"])
+def test_form2_multiple_eigenvalues(gpu_lib, case):
+    """A multiple eigenvalue of H2 (a run of 2m equal eigenvalues of the order-2n problem): the
+    Sigma Gram-Schmidt over the run returns a Sigma-orthonormal basis of its eigenspace."""
+    n = 24
+    rng = np.random.default_rng(77)
+    Q = inputs.haar_unitary(rng, n)
+    a = rng.uniform(1.0, 5.0, n)
+    a[:3] = 2.0
+    a[10:14] = 3.5
+    if case == "decoupled_triple":
+        b = a * rng.uniform(0.1, 0.8, n) * np.exp(2j * np.pi * rng.uniform(size=n))
+        b[:3] = 0.5 * np.exp(2j * np.pi * rng.uniform(size=3))
+        b[10:14] = 1.2 * np.exp(2j * np.pi * rng.uniform(size=4))
+    else:
+        b = np.zeros(n, complex)
+    A = Q.conj().T @ (a[:, None] * Q)
+    A = (A + A.conj().T) / 2
+    B = Q.conj().T @ (b[:, None] * Q.conj())
+    B = (B + B.T) / 2
+    lam, X, info = run(gpu_lib, A, B, want_negative=True)
+    assert info["status"] == 0
+    lref = np.sort(np.sqrt(a * a - np.abs(b) ** 2))
+    assert np.max(np.abs(lam[:n] - lref) / lref) < 1e-13
+    H = ob.bse_matrix_form2(A, B)
+    Xp = X[:, :n]
+    assert np.linalg.norm(H @ Xp - Xp * lam[None, :n]) <= 1e-12 * np.linalg.norm(H, 2) * np.linalg.norm(Xp)
+    G = Xp.conj().T @ (sig(n)[:, None] * Xp)
+    assert np.abs(G - np.eye(n)).max() < 1e-11, np.abs(G - np.eye(n)).max()
+    lam_o, X_o = ob.solve_form2(A, B)
+    err, gap = om.eigvec_errors(lam_o, X_o, Xp, cluster_rtol=1e-9)
+    assert np.all(err <= 1e-10 + 1e-13 / np.minimum(gap, 1.0)), (np.max(err), np.min(gap))
+    assert np.array_equal(X[:n, n:], X[n:, :n].conj()) and np.array_equal(X[n:, n:], X[:n, :n].conj())
