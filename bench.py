@@ -500,6 +500,48 @@ def bench_eigvec_adjoint(api, A, B, A1, B1, lam1, X1, steps, warmup):
             "cpu_oracle_adjoint_seconds_n1024": round(cdt, 2)}
 
 
+def bench_form2(api, inputs, steps, warmup, n=2048):
+    """Form II (Eq. Hform2) at n = 2048 through bse_solve_h2 (a real form-I problem of
+    order 4096 on the device), FP64 and mixed; Sigma-orthonormality, the residual with H2
+    (max_k |H2 x_k - lambda_k x_k| / (lambda_max |x_k|)) and the trace identity
+    sum lambda^2 = |A|_F^2 - |B|_F^2 checked on the GPU."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    A, B = inputs.coupled_form2(n, seed=2048)
+    At = torch.from_numpy(A).to(dev)
+    Bt = torch.from_numpy(B).to(dev)
+    H = torch.cat([torch.cat([At, Bt], 1), torch.cat([-Bt.conj(), -At.conj()], 1)], 0)
+    sig = torch.cat([torch.ones(n, dtype=torch.float64, device=dev), -torch.ones(n, dtype=torch.float64, device=dev)])
+    tr = (At.abs().pow(2).sum() - Bt.abs().pow(2).sum()).item()
+    out = {"workload": f"form II, n = {n} (coupled_form2 recipe, seed 2048): all n eigenpairs",
+           "flops_note": "solved as a real form-I problem of order 2n"}
+    lam_by = {}
+    for prec in ("fp64", "mixed"):
+        for _ in range(max(warmup, 1)):
+            api.solve_h2(At, Bt, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            lam, X, info = api.solve_h2(At, Bt, precision=prec)
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / steps
+        X = X.resolve_conj()
+        G = X.conj().mT @ (sig[:, None] * X)
+        orth = torch.linalg.norm(G - torch.eye(n, dtype=G.dtype, device=dev)).item()
+        R = H @ X - X * lam[None, :]
+        res = (torch.linalg.norm(R, dim=0) / (torch.linalg.norm(X, dim=0) * lam.max())).max().item()
+        out[prec] = {"seconds_per_solve": round(sec, 4), "status": info["status"],
+                     "sigma_orth_fro": orth, "max_rel_resid": res,
+                     "trace_identity_rel_err": abs(lam.pow(2).sum().item() - tr) / abs(tr)}
+        lam_by[prec] = lam
+        log(f"form2 {prec}: {sec:.3f}s per solve")
+        del X, G, R
+    out["mixed_vs_fp64_max_rel_eig_diff"] = ((lam_by["mixed"] - lam_by["fp64"]).abs()
+                                             / lam_by["fp64"]).max().item()
+    return out
+
+
 def load_traffic(kernel: str, workload: str, precision: str):
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -528,7 +570,7 @@ def main():
     ap.add_argument("--no-checks", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched (256 problems) and differentiation (n=4096) measurements")
-    ap.add_argument("--only", default="", choices=["", "batched", "differentiation"],
+    ap.add_argument("--only", default="", choices=["", "batched", "differentiation", "form2"],
                     help="run only this supplementary measurement and print its JSON (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
@@ -546,7 +588,8 @@ def main():
     api.load_library()
     dev = torch.device("cuda:0")
     if args.only:
-        fn = bench_batched if args.only == "batched" else bench_differentiation
+        fn = {"batched": bench_batched, "differentiation": bench_differentiation,
+              "form2": bench_form2}[args.only]
         print(json.dumps({args.only: fn(api, inputs, args.steps, args.warmup)}), flush=True)
         return
     if args.copy_calibration > 0:
@@ -676,6 +719,8 @@ def main():
         out["batched"] = bench_batched(api, inputs, args.steps, args.warmup)
         torch.cuda.empty_cache()
         out["differentiation"] = bench_differentiation(api, inputs, args.steps, args.warmup)
+        torch.cuda.empty_cache()
+        out["form2"] = bench_form2(api, inputs, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle at n={args.cpu_sample_n}")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample_n)

@@ -22,6 +22,15 @@
 // eigenspaces of positive eigenvalues) picks m of them and makes them
 // Sigma-orthonormal (runs of up to kClusterMax; longer runs keep one vector
 // per pair, which may leave them dependent).
+// The real solver makes its vectors orthogonal in the real inner product
+// z^T Sigma' z' = Re(x^H Sigma x') only; the imaginary part pairs x with the
+// image of i x', whose span the computed doubled pair matches only to the
+// eigenvector accuracy (about eps / gap), so close eigenvalues leave the
+// complex vectors Sigma-orthogonal only to that level.  One step
+// X <- X (I - (X^H Sigma X - I) / 2) (three GEMMs, second order in the
+// departure) restores Sigma-orthonormality to rounding; it mixes a vector
+// only with others by amounts inverse to their gaps, so residuals stay at
+// rounding level.  The negative half is written last from the final X.
 #include "../../include/bse.h"
 #include "common.hpp"
 #include "internal.hpp"
@@ -68,8 +77,7 @@ struct RealifyOp {
 
 // lambda_k = (lambda'_2k + lambda'_2k+1) / 2 and x_k from z = column 2k of
 // X' (order 2n, positive half): u = z1 + i z2, v = z3 - i z4; with the
-// negative half, -lambda_k and [0 I; I 0] conj(x_k) (Lemma ComputeNegEvecs,
-// part 2).  Work group = (column k, 256 rows of x).
+// negative half, -lambda_k.  Work group = (column k, 256 rows of x).
 struct ExtractArgs {
   int n; const double* lam2; const double2* X2; long ldx2; double* lambda; double2* X; long ldx;
   int want_negative, values_only;
@@ -93,10 +101,6 @@ struct ExtractOp {
     if (r < n) x = make_double2(z[q].x, z[n + q].x);              // u = Re part + i Im part
     else x = make_double2(z[2 * n + q].x, -z[3 * n + q].x);      // v = conj(w)
     a.X[r + (long)k * a.ldx] = x;
-    if (a.want_negative) {  // [0 I; I 0] conj(x): row r of x goes to row r +- n, conjugated
-      const int rn = r < n ? r + n : r - n;
-      a.X[rn + (long)(n + k) * a.ldx] = make_double2(x.x, -x.y);
-    }
   }
 };
 
@@ -123,9 +127,9 @@ struct MapOp {
 // are numerically equal, starting at eigenvalue k0 (runs[w] = (k0, m)): among
 // the 2m vectors Y[:, 2 k0 .. 2 k0 + 2m), m steps of pivoted Gram-Schmidt in
 // the inner product <x, y> = x^H Sigma y take the candidate of largest
-// remaining norm, normalise it into column k0 + t of X (and its negative-half
-// image), and remove it from the other candidates.
-struct ClusterArgs { int n; const int2* runs; double2* Y; long ldy; double2* X; long ldx; int want_negative; };
+// remaining norm, normalise it into column k0 + t of X and remove it from the
+// other candidates.
+struct ClusterArgs { int n; const int2* runs; double2* Y; long ldy; double2* X; long ldx; };
 struct ClusterOp {
   static constexpr int NT = 256;
   typedef ClusterArgs Args;
@@ -183,10 +187,6 @@ struct ClusterOp {
         v.y *= inv;
         q[r] = v;
         a.X[r + (long)(k0 + t) * a.ldx] = v;
-        if (a.want_negative) {
-          const int rn = r < n ? r + n : r - n;
-          a.X[rn + (long)(n + k0 + t) * a.ldx] = make_double2(v.x, -v.y);
-        }
       }
       __syncthreads();
       // remove q from the other candidates: y <- y - (q^H Sigma y) q
@@ -213,6 +213,34 @@ struct ClusterOp {
         __syncthreads();
       }
     }
+  }
+};
+
+// E <- E - I (E is n x n, column-major with leading dimension n).
+struct DiagArgs { int n; double2* E; };
+struct DiagOp {
+  static constexpr int NT = 256;
+  typedef DiagArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int j = bx * NT + threadIdx.x;
+    if (j < a.n) a.E[j + (long)j * a.n].x -= 1.0;
+  }
+};
+
+// Negative half (Lemma ComputeNegEvecs, part 2): column n + k of X is
+// [0 I; I 0] conj(x_k), row r of x_k going to row r +- n, conjugated.
+// Work group = (column k, 256 rows).
+struct NegArgs { int n; double2* X; long ldx; };
+struct NegOp {
+  static constexpr int NT = 256;
+  typedef NegArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int n = a.n, gx = (2 * n + 255) / 256;
+    const int k = bx / gx, r = (bx % gx) * 256 + threadIdx.x;
+    if (k >= n || r >= 2 * n) return;
+    const double2 v = a.X[r + (long)k * a.ldx];
+    const int rn = r < n ? r + n : r - n;
+    a.X[rn + (long)(n + k) * a.ldx] = make_double2(v.x, -v.y);
   }
 };
 
@@ -305,6 +333,7 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
                                o.values_only};
   e = launch_one<bse::ExtractOp>(ea, n * ((2 * n + 255) / 256), 0, s);
   if (e != hipSuccess) return bse::hip_status(e);
+  std::vector<int2> runs;  // lives until the final synchronisation (copied from)
   if (!o.values_only && n > 1) {
     // runs of numerically equal eigenvalues of H2 (pairs k, k + 1 joined when
     // the gap between copies 2k + 1 and 2k + 2 is below kClusterGap lambda_max)
@@ -313,7 +342,6 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bse::hip_status(e);
     const double tol = bse::kClusterGap * fabs(l2[m - 1]);
-    std::vector<int2> runs;
     for (int k = 0; k < n;) {
       int e1 = k + 1;
       while (e1 < n && l2[2 * e1] - l2[2 * e1 - 1] <= tol) ++e1;
@@ -325,10 +353,40 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
       e = hipMemcpyAsync(d_runs, runs.data(), runs.size() * sizeof(int2), hipMemcpyHostToDevice, s);
       const bse::MapArgs ma = {n, X2, 2 * m, At, m};  // A' is free: Y in its place (2n x 2n)
       if (e == hipSuccess) e = launch_one<bse::MapOp>(ma, m * ((2 * n + 255) / 256), 0, s);
-      const bse::ClusterArgs ca = {n, d_runs, At, m, static_cast<double2*>(X), ldx, o.want_negative};
+      const bse::ClusterArgs ca = {n, d_runs, At, m, static_cast<double2*>(X), ldx};
       if (e == hipSuccess) e = launch_one<bse::ClusterOp>(ca, (int)runs.size(), 0, s);
       if (e != hipSuccess) return bse::hip_status(e);
     }
+  }
+  if (!o.values_only) {
+    // X <- X - X E / 2 with E = X^H Sigma X - I: Xc = copy of X in A''s place
+    // (2n x n), E in B''s place (n x n), both free once the solve is done
+    double2* Xp = static_cast<double2*>(X);
+    double2* Xc = At;
+    double2* E = Bt;
+    e = hipMemcpy2DAsync(Xc, (size_t)m * sizeof(double2), Xp, (size_t)ldx * sizeof(double2),
+                         (size_t)m * sizeof(double2), n, hipMemcpyDeviceToDevice, s);
+    bse::GemmDesc g;
+    g.M = n; g.N = n; g.K = n;
+    g.A = Xc; g.lda = m; g.opA = 1;
+    g.B = Xc; g.ldb = m; g.opB = 0;
+    g.C = E; g.ldc = n;
+    if (e == hipSuccess) e = bse::gemm_z(g, s);  // u^H u
+    g.A = Xc + n; g.B = Xc + n;
+    g.alpha_re = -1.0; g.beta_re = 1.0;
+    if (e == hipSuccess) e = bse::gemm_z(g, s);  // - v^H v
+    const bse::DiagArgs da = {n, E};
+    if (e == hipSuccess) e = launch_one<bse::DiagOp>(da, (n + 255) / 256, 0, s);
+    bse::GemmDesc h;
+    h.M = m; h.N = n; h.K = n;
+    h.A = Xc; h.lda = m; h.opA = 0;
+    h.B = E; h.ldb = n; h.opB = 0;
+    h.C = Xp; h.ldc = ldx;
+    h.alpha_re = -0.5; h.beta_re = 1.0;
+    if (e == hipSuccess) e = bse::gemm_z(h, s);
+    const bse::NegArgs na = {n, Xp, ldx};
+    if (e == hipSuccess && o.want_negative) e = launch_one<bse::NegOp>(na, n * ((2 * n + 255) / 256), 0, s);
+    if (e != hipSuccess) return bse::hip_status(e);
   }
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bse::hip_status(e);
