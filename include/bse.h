@@ -208,8 +208,8 @@ size_t bse_workspace_bytes_h2(int n, const bse_opts_t* opts);
  * opts.checks is ignored.  An eigenvalue of H2 of multiplicity m (a run of
  * eigenvalues whose gaps are at most 1e-12 lambda_max) gets m Sigma-orthonormal
  * vectors of its eigenspace (a pivoted Gram-Schmidt in the Sigma inner product
- * over the run's 2m candidates) when m <= 64; a longer run keeps one vector
- * per doubled pair, which need not be independent.  A final step
+ * over the run's 2m candidates; one work group per run up to m = 64, two
+ * launches per vector beyond).  A final step
  * X <- X (I - (X^H Sigma X - I) / 2) makes the vectors Sigma-orthonormal to
  * rounding (the real solve fixes only Re(x^H Sigma y)).  Returns 0; -1 n, -2 A, -3 lda, -4 B, -5 ldb,
  * -6 lambda, -7 X, -8 ldx, -9 work NULL, -10 work_bytes too small, -11 opts

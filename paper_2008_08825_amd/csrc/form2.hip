@@ -20,8 +20,9 @@
 // H1' whose 2m complex vectors span its m-dimensional eigenspace; a pivoted
 // Gram-Schmidt in the Sigma inner product (positive definite on the
 // eigenspaces of positive eigenvalues) picks m of them and makes them
-// Sigma-orthonormal (runs of up to kClusterMax; longer runs keep one vector
-// per pair, which may leave them dependent).
+// Sigma-orthonormal (runs of up to kClusterMax in one work group each; a
+// longer run takes one grid-wide update launch and one selection launch per
+// vector).
 // The real solver makes its vectors orthogonal in the real inner product
 // z^T Sigma' z' = Re(x^H Sigma x') only; the imaginary part pairs x with the
 // image of i x', whose span the computed doubled pair matches only to the
@@ -216,6 +217,115 @@ struct ClusterOp {
   }
 };
 
+// The same selection for a run longer than kClusterMax, spread over the
+// chip: per step, PivUpdOp (one work group per candidate) removes the last
+// chosen vector q from every live candidate and recomputes its Sigma-norm
+// (first = 1: only the norms), and PivSelOp (one work group) takes the live
+// candidate of largest norm, normalises it into Y (the next q) and into
+// column k0 + t of X.  nrm / alive / piv live in the workspace.
+struct PivArgs {
+  int n; double2* Y; long ldy; int c0, nc; double* nrm; int* alive; int* piv; double2* X; long ldx;
+  int col, first;
+};
+BSE_DEV void wg_sum2(double (&red)[2][256], double& vr, double& vi) {
+  const int tid = threadIdx.x;
+  red[0][tid] = vr;
+  red[1][tid] = vi;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) {
+      red[0][tid] += red[0][tid + o];
+      red[1][tid] += red[1][tid + o];
+    }
+    __syncthreads();
+  }
+  vr = red[0][0];
+  vi = red[1][0];
+  __syncthreads();
+}
+struct PivUpdOp {
+  static constexpr int NT = 256;
+  typedef PivArgs Args;
+  static BSE_DEV void run(const Args& a, int c, int) {
+    __shared__ double red[2][NT];
+    const int n = a.n, rows = 2 * n, tid = threadIdx.x;
+    if (c >= a.nc) return;
+    if (a.first) {
+      if (tid == 0) a.alive[c] = 1;
+    } else if (!a.alive[c]) {
+      return;  // uniform: one value per work group
+    }
+    double2* y = a.Y + (long)(a.c0 + c) * a.ldy;
+    double cr = 0.0, ci = 0.0;
+    if (!a.first) {
+      const double2* q = a.Y + (long)(a.c0 + a.piv[0]) * a.ldy;
+      for (int r = tid; r < rows; r += NT) {
+        const double2 qv = q[r], v = y[r];
+        const double sg = r < n ? 1.0 : -1.0;
+        cr += sg * (qv.x * v.x + qv.y * v.y);
+        ci += sg * (qv.x * v.y - qv.y * v.x);
+      }
+      wg_sum2(red, cr, ci);
+    }
+    double s = 0.0, s_im = 0.0;
+    for (int r = tid; r < rows; r += NT) {
+      double2 v = y[r];
+      if (!a.first) {
+        const double2 qv = a.Y[(long)(a.c0 + a.piv[0]) * a.ldy + r];
+        v.x -= cr * qv.x - ci * qv.y;
+        v.y -= cr * qv.y + ci * qv.x;
+        y[r] = v;
+      }
+      const double w = v.x * v.x + v.y * v.y;
+      s += r < n ? w : -w;
+    }
+    wg_sum2(red, s, s_im);
+    if (tid == 0) a.nrm[c] = s;
+  }
+};
+struct PivSelOp {
+  static constexpr int NT = 256;
+  typedef PivArgs Args;
+  static BSE_DEV void run(const Args& a, int, int) {
+    __shared__ double bv[NT];
+    __shared__ int bi[NT];
+    const int tid = threadIdx.x, rows = 2 * a.n;
+    double best = -1.0e300;
+    int arg = -1;
+    for (int c = tid; c < a.nc; c += NT)
+      if (a.alive[c] && a.nrm[c] > best) {
+        best = a.nrm[c];
+        arg = c;
+      }
+    bv[tid] = best;
+    bi[tid] = arg;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+      if (tid < o && (bv[tid + o] > bv[tid] || (bv[tid + o] == bv[tid] && bi[tid + o] >= 0 &&
+                                                 (bi[tid] < 0 || bi[tid + o] < bi[tid])))) {
+        bv[tid] = bv[tid + o];
+        bi[tid] = bi[tid + o];
+      }
+      __syncthreads();
+    }
+    const int p = bi[0];
+    if (p < 0) return;  // no live candidate (cannot happen for nc = 2 m, m steps)
+    const double inv = bv[0] > 0.0 ? 1.0 / sqrt(bv[0]) : 0.0;
+    double2* q = a.Y + (long)(a.c0 + p) * a.ldy;
+    for (int r = tid; r < rows; r += NT) {
+      double2 v = q[r];
+      v.x *= inv;
+      v.y *= inv;
+      q[r] = v;
+      a.X[r + (long)a.col * a.ldx] = v;
+    }
+    if (tid == 0) {
+      a.piv[0] = p;
+      a.alive[p] = 0;
+    }
+  }
+};
+
 // E <- E - I (E is n x n, column-major with leading dimension n).
 struct DiagArgs { int n; double2* E; };
 struct DiagOp {
@@ -334,6 +444,7 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
   e = launch_one<bse::ExtractOp>(ea, n * ((2 * n + 255) / 256), 0, s);
   if (e != hipSuccess) return bse::hip_status(e);
   std::vector<int2> runs;  // lives until the final synchronisation (copied from)
+  std::vector<int2> long_runs;
   if (!o.values_only && n > 1) {
     // runs of numerically equal eigenvalues of H2 (pairs k, k + 1 joined when
     // the gap between copies 2k + 1 and 2k + 2 is below kClusterGap lambda_max)
@@ -346,15 +457,34 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
       int e1 = k + 1;
       while (e1 < n && l2[2 * e1] - l2[2 * e1 - 1] <= tol) ++e1;
       if (e1 - k >= 2 && e1 - k <= bse::kClusterMax) runs.push_back(make_int2(k, e1 - k));
+      if (e1 - k > bse::kClusterMax) long_runs.push_back(make_int2(k, e1 - k));
       k = e1;
+    }
+    if (!runs.empty() || !long_runs.empty()) {
+      const bse::MapArgs ma = {n, X2, 2 * m, At, m};  // A' is free: Y in its place (2n x 2n)
+      e = launch_one<bse::MapOp>(ma, m * ((2 * n + 255) / 256), 0, s);
+      if (e != hipSuccess) return bse::hip_status(e);
     }
     if (!runs.empty()) {
       int2* d_runs = reinterpret_cast<int2*>(base + L.off_runs);
       e = hipMemcpyAsync(d_runs, runs.data(), runs.size() * sizeof(int2), hipMemcpyHostToDevice, s);
-      const bse::MapArgs ma = {n, X2, 2 * m, At, m};  // A' is free: Y in its place (2n x 2n)
-      if (e == hipSuccess) e = launch_one<bse::MapOp>(ma, m * ((2 * n + 255) / 256), 0, s);
       const bse::ClusterArgs ca = {n, d_runs, At, m, static_cast<double2*>(X), ldx};
       if (e == hipSuccess) e = launch_one<bse::ClusterOp>(ca, (int)runs.size(), 0, s);
+      if (e != hipSuccess) return bse::hip_status(e);
+    }
+    // longer runs: norms, live flags and the pivot in B''s place (2n + 2n + 1 words)
+    double* nrm = reinterpret_cast<double*>(Bt);
+    int* alive = reinterpret_cast<int*>(nrm + m);
+    int* piv = alive + m;
+    for (const int2& r : long_runs) {
+      bse::PivArgs pa = {n, At, m, 2 * r.x, 2 * r.y, nrm, alive, piv, static_cast<double2*>(X), ldx, r.x, 1};
+      e = launch_one<bse::PivUpdOp>(pa, pa.nc, 0, s);
+      for (int t = 0; t < r.y && e == hipSuccess; ++t) {
+        pa.col = r.x + t;
+        e = launch_one<bse::PivSelOp>(pa, 1, 0, s);
+        pa.first = 0;
+        if (e == hipSuccess && t + 1 < r.y) e = launch_one<bse::PivUpdOp>(pa, pa.nc, 0, s);
+      }
       if (e != hipSuccess) return bse::hip_status(e);
     }
   }

@@ -151,3 +151,40 @@ def test_form2_sigma_orthonormal_close_eigenvalues(gpu_lib, precision):
     tr = np.linalg.norm(A) ** 2 - np.linalg.norm(B) ** 2
     assert abs(np.sum(lam[:n] ** 2) - tr) / tr < 1e-14
     assert np.array_equal(X[:n, n:], X[n:, :n].conj()) and np.array_equal(X[n:, n:], X[:n, :n].conj())
+
+
+@pytest.mark.parametrize("case", ["scalar_A_B_zero", "run_of_80"])
+def test_form2_long_run_of_a_multiple_eigenvalue(gpu_lib, case):
+    """Multiplicity above 64 (the grid-wide selection): A = 2 I, B = 0 (every eigenvalue
+    equal), and a decoupled problem with one eigenvalue of multiplicity 80 among others."""
+    rng = np.random.default_rng(5)
+    if case == "scalar_A_B_zero":
+        n = 100
+        A = 2.0 * np.eye(n, dtype=complex)
+        B = np.zeros((n, n), complex)
+        lref = np.full(n, 2.0)
+    else:
+        n = 120
+        Q = inputs.haar_unitary(rng, n)
+        a = rng.uniform(1.0, 5.0, n)
+        a[20:100] = 2.5
+        b = a * rng.uniform(0.1, 0.8, n) * np.exp(2j * np.pi * rng.uniform(size=n))
+        b[20:100] = 0.9 * np.exp(2j * np.pi * rng.uniform(size=80))
+        A = Q.conj().T @ (a[:, None] * Q)
+        A = (A + A.conj().T) / 2
+        B = Q.conj().T @ (b[:, None] * Q.conj())
+        B = (B + B.T) / 2
+        lref = np.sort(np.sqrt(a * a - np.abs(b) ** 2))
+    print(f"[gpu] form II long run {case}", flush=True)
+    lam, X, info = run(gpu_lib, A, B, want_negative=True)
+    assert info["status"] == 0
+    assert np.max(np.abs(lam[:n] - lref) / lref) < 1e-13
+    Xp = X[:, :n]
+    G = Xp.conj().T @ (sig(n)[:, None] * Xp)
+    assert np.linalg.norm(G - np.eye(n)) < 1e-12, np.linalg.norm(G - np.eye(n))
+    H = ob.bse_matrix_form2(A, B)
+    assert np.linalg.norm(H @ Xp - Xp * lam[None, :n]) <= 1e-13 * np.linalg.norm(H, 2) * np.linalg.norm(Xp)
+    lam_o, X_o = ob.solve_form2(A, B)
+    err, gap = om.eigvec_errors(lam_o, X_o, Xp, cluster_rtol=1e-9)
+    assert np.all(err <= 1e-10 + 1e-13 / np.minimum(gap, 1.0)), (np.max(err), np.min(gap))
+    assert np.array_equal(X[:n, n:], X[n:, :n].conj()) and np.array_equal(X[n:, n:], X[:n, :n].conj())
