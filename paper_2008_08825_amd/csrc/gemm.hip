@@ -23,6 +23,32 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 16;
 
+// Work group -> output tile.  A lower-triangle output of a square tile grid
+// launches only its T (T + 1) / 2 lower tiles, row by row; a product with one
+// triangular operand dispatches its tiles longest k-range first (the tiles of
+// one block row of op(A) share a k-range), so that the short ones fill the
+// end of the launch; otherwise tile rows vary fastest.
+__host__ __device__ inline bool lower_packed(int lowerC, int tilesM, int tilesN) {
+  return lowerC && tilesM == tilesN;
+}
+template <int OPA, typename P>
+BSE_DEV inline void tile_of(const P& p, int bx, int& tm, int& tn) {
+  if (lower_packed(p.lowerC, p.tilesM, p.tilesN)) {
+    int r = (int)((sqrt(8.0 * bx + 1.0) - 1.0) * 0.5);
+    while ((r + 1) * (r + 2) / 2 <= bx) ++r;
+    while (r * (r + 1) / 2 > bx) --r;
+    tm = r;
+    tn = bx - r * (r + 1) / 2;
+  } else if (p.triA && !p.triB && !p.lowerC) {
+    tm = bx / p.tilesN;
+    tn = bx % p.tilesN;
+    if (OPA == 0) tm = p.tilesM - 1 - tm;  // lower op(A): the last block rows are the longest
+  } else {
+    tm = bx % p.tilesM;
+    tn = bx / p.tilesM;
+  }
+}
+
 // LDS place of operand element (k, c) of a 16 x 64 staged tile
 BSE_DEV int gemm_swz(int k, int c) { return k * 64 + (c ^ k ^ ((k & 1) << 4)); }
 
@@ -48,7 +74,8 @@ BSE_DEV void GemmOp<T, OPA, OPB, KS>::run(const GemmArgs<T>& p, int bx, int) {
   __shared__ C2 Bs[2][BK * BN];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tm = bx % p.tilesM, tn = bx / p.tilesM;
+  int tm, tn;
+  tile_of<OPA>(p, bx, tm, tn);
   if (p.lowerC && tn > tm) return;
   const int m0 = tm * BM, n0 = tn * BN;
   const C2* __restrict__ A = p.A;
@@ -226,7 +253,7 @@ template <typename T>
 hipError_t gemm_launch(const GemmDesc& d, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
   const GemmArgs<T> p = make_args<T>(d);
-  const int blocks = p.tilesM * p.tilesN;
+  const int blocks = gemm_tiles(d);
   if (d.kscale) {
     if (d.opA == 0 && d.opB == 1) return launch_one<GemmOp<T, 0, 1, true>>(p, blocks, 0, s);
     return hipErrorInvalidValue;
@@ -257,7 +284,8 @@ hipError_t gemm_c(const GemmDesc& d, hipStream_t s) { return gemm_launch<float>(
 
 int gemm_tiles(const GemmDesc& d) {
   if (d.M <= 0 || d.N <= 0) return 0;
-  return ((d.M + BM - 1) / BM) * ((d.N + BN - 1) / BN);
+  const int tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+  return lower_packed(d.lowerC, tm, tn) ? tm * (tm + 1) / 2 : tm * tn;
 }
 GemmArgs<double> gemm_args_z(const GemmDesc& d) { return make_args<double>(d); }
 GemmArgs<float> gemm_args_c(const GemmDesc& d) { return make_args<float>(d); }
