@@ -472,7 +472,7 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
       if (e == hipSuccess) e = launch_one<bse::ClusterOp>(ca, (int)runs.size(), 0, s);
       if (e != hipSuccess) return bse::hip_status(e);
     }
-    // longer runs: norms, live flags and the pivot in B''s place (2n + 2n + 1 words)
+    // longer runs: norms, live flags and the pivot in B's place (2n + 2n + 1 words)
     double* nrm = reinterpret_cast<double*>(Bt);
     int* alive = reinterpret_cast<int*>(nrm + m);
     int* piv = alive + m;
@@ -489,8 +489,8 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
     }
   }
   if (!o.values_only) {
-    // X <- X - X E / 2 with E = X^H Sigma X - I: Xc = copy of X in A''s place
-    // (2n x n), E in B''s place (n x n), both free once the solve is done
+    // X <- X - X E / 2 with E = X^H Sigma X - I: Xc = copy of X in A's place
+    // (2n x n), E in B's place (n x n), both free once the solve is done
     double2* Xp = static_cast<double2*>(X);
     double2* Xc = At;
     double2* E = Bt;
