@@ -467,19 +467,6 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
     // is not definite, which the FP64 factorisation then reports).
     if (st != big) return solve_fp64_fallback(n, A, lda, B, ldb, lambda, X, ldx, base, p, o, info, s);
   }
-  // FP64 Cholesky factors of M1, M2 (in place; the strict upper parts stay
-  // zero) for the refinement's products: they depend on the input only, so
-  // they are made on the library stream while the complex64 iteration runs
-  // (whose inner eigensolver leaves half of the chip idle), and s waits for
-  // them just before the refinement (or on any return before it)
-  struct JoinGuard {
-    hipStream_t s;
-    int forked = 0;
-    ~JoinGuard() {
-      if (forked) (void)cholesky_join(s);
-    }
-  } fork{s};
-  BSE_TRY(cholesky_fork_z(np, n, M1, M2, ld, reinterpret_cast<double2*>(linv), status, s, p.side, &fork.forked));
   tm.mark();
   {
     GemmDesc g = tri_gemm(np, ld, L2c, 1, L1c, 0, 1, Wc);  // W = L2^H L1 (complex64)
@@ -511,10 +498,9 @@ int solve_mixed(int n, const void* A, int lda, const void* B, int ldb, double* l
   BSE_TRY(c64_to_c128(np, L1c, ld, X1, ld, scl, s));  // x = V1 / ||Ws||^2 (FP64)
   BSE_TRY(c64_to_c128(np, Yc, ld, X2, ld, nullptr, s));  // y = V2
   tm.mark();
-  if (fork.forked) {
-    fork.forked = 0;
-    BSE_TRY(cholesky_join(s));
-  }
+  // FP64 Cholesky factors of M1, M2 (in place; the strict upper parts stay
+  // zero) for the refinement's products
+  BSE_TRY(cholesky_pair_z(np, n, M1, M2, ld, reinterpret_cast<double2*>(linv), status, s, p.side));
   {
     int st = 0;
     BSE_TRY(hipMemcpyAsync(&st, status, sizeof(int), hipMemcpyDeviceToHost, s));

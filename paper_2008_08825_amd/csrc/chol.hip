@@ -442,34 +442,11 @@ hipError_t cholesky_c(int np, int n_real, float2* M, long ld, float2* linv, int*
 namespace {
 struct SideStream {
   hipStream_t s = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr, late = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 constexpr int kMaxDevices = 64;
 std::mutex g_side_mu;
 SideStream g_side[kMaxDevices];
-
-// The library stream of device dev, created on first use (with g_side_mu held).
-hipError_t side_of(int dev, SideStream** out) {
-  SideStream& sd = g_side[dev];
-  hipError_t e = hipSuccess;
-  if (!sd.s) {  // created on the stream's device, kept until the process ends
-    int cur = 0;
-    if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
-    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
-    e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.late, hipEventDisableTiming);
-    const hipError_t er = cur != dev ? hipSetDevice(cur) : hipSuccess;
-    if (e != hipSuccess) {
-      sd.s = nullptr;  // try again on the next call
-      return e;
-    }
-    if (er != hipSuccess) return er;
-  }
-  *out = &sd;
-  return hipSuccess;
-}
 }  // namespace
 
 template <typename C2>
@@ -483,9 +460,21 @@ static hipError_t cholesky_pair_run(int np, int n_real, C2* M1, C2* M2, long ld,
     return cholesky_run<C2>(np, n_real, M2, ld, linv + NB * NB, status, n_real, s);
   }
   std::lock_guard<std::mutex> lock(g_side_mu);
-  SideStream* sp = nullptr;
-  if ((e = side_of(dev, &sp)) != hipSuccess) return e;
-  SideStream& sd = *sp;
+  SideStream& sd = g_side[dev];
+  if (!sd.s) {  // created on the stream's device, kept until the process ends
+    int cur = 0;
+    if ((e = hipGetDevice(&cur)) != hipSuccess) return e;
+    if (cur != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    e = hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&sd.join, hipEventDisableTiming);
+    const hipError_t er = cur != dev ? hipSetDevice(cur) : hipSuccess;
+    if (e != hipSuccess) {
+      sd.s = nullptr;  // try again on the next call
+      return e;
+    }
+    if (er != hipSuccess) return er;
+  }
   if ((e = hipEventRecord(sd.fork, s)) != hipSuccess) return e;
   if ((e = hipStreamWaitEvent(sd.s, sd.fork, 0)) != hipSuccess) return e;
   const hipError_t e1 = cholesky_run<C2>(np, n_real, M1, ld, linv, status, 0, s);
@@ -504,38 +493,6 @@ hipError_t cholesky_pair_z(int np, int n_real, double2* M1, double2* M2, long ld
 hipError_t cholesky_pair_c(int np, int n_real, float2* M1, float2* M2, long ld, float2* linv,
                            int* status, hipStream_t s, int side) {
   return cholesky_pair_run<float2>(np, n_real, M1, M2, ld, linv, status, s, side);
-}
-
-hipError_t cholesky_fork_z(int np, int n_real, double2* M1, double2* M2, long ld, double2* linv,
-                           int* status, hipStream_t s, int side, int* forked) {
-  *forked = 0;
-  int dev = 0;
-  hipError_t e = hipStreamGetDevice(s, &dev);
-  if (e != hipSuccess) return e;
-  if (!side || dev < 0 || dev >= kMaxDevices) return cholesky_pair_run<double2>(np, n_real, M1, M2, ld, linv, status, s, 0);
-  std::lock_guard<std::mutex> lock(g_side_mu);
-  SideStream* sd = nullptr;
-  if ((e = side_of(dev, &sd)) != hipSuccess) return e;
-  if ((e = hipEventRecord(sd->fork, s)) != hipSuccess) return e;
-  if ((e = hipStreamWaitEvent(sd->s, sd->fork, 0)) != hipSuccess) return e;
-  *forked = 1;  // from here on s must wait for the side stream before the factors are touched
-  const hipError_t e1 = cholesky_run<double2>(np, n_real, M1, ld, linv, status, 0, sd->s);
-  const hipError_t e2 = cholesky_run<double2>(np, n_real, M2, ld, linv + NB * NB, status, n_real, sd->s);
-  if ((e = hipEventRecord(sd->late, sd->s)) != hipSuccess) return e;
-  return e1 != hipSuccess ? e1 : e2;
-}
-
-hipError_t cholesky_join(hipStream_t s) {
-  int dev = 0;
-  hipError_t e = hipStreamGetDevice(s, &dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lock(g_side_mu);
-  SideStream& sd = g_side[dev];
-  if (!sd.s) return hipErrorInvalidValue;
-  // waits for the last recording of `late`, which is at or after this
-  // call's own fork work on the side stream
-  return hipStreamWaitEvent(s, sd.late, 0);
 }
 
 hipError_t group_chol(GroupOp op, const void* table, const int2* map, int blocks, int aux,

@@ -47,14 +47,6 @@ hipError_t cholesky_pair_z(int np, int n_real, double2* M1, double2* M2, long ld
                            int* status, hipStream_t s, int side = 1);
 hipError_t cholesky_pair_c(int np, int n_real, float2* M1, float2* M2, long ld, float2* linv,
                            int* status, hipStream_t s, int side = 1);
-// Both FP64 factors on the library stream, one after the other, ordered after
-// the work already on s, without making s wait: s goes on, and
-// cholesky_join(s) must come before anything on s touches M1, M2, linv or
-// status (also on error paths) when *forked is set.  side == 0 or no library
-// stream: cholesky_pair_z on s (*forked = 0).
-hipError_t cholesky_fork_z(int np, int n_real, double2* M1, double2* M2, long ld, double2* linv,
-                           int* status, hipStream_t s, int side, int* forked);
-hipError_t cholesky_join(hipStream_t s);
 
 // M1 = A + B, M2 = A - B (lower triangles, zero strict upper part), padded to
 // np with identity; reads the `upper` or lower triangle of A, B (B == nullptr
