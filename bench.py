@@ -150,7 +150,7 @@ def time_form(api, A, B, precision, route, steps, warmup, work, out):
            "cross_pair_checks": 0, "p_cross_pair_checks": 0,
            "inner_rotations": 0.0, "phases": np.zeros(8), "sweeps": [], "refine_steps": [],
            "p_kernel_ms": np.zeros(3), "p_launches": np.zeros(3), "p_rotations": 0, "p_pair_checks": 0,
-           "p_inner_rotations": 0.0, "polish_sweeps": []}
+           "p_inner_rotations": 0.0, "polish_sweeps": [], "step_seconds": []}
     t0 = time.perf_counter()
     info = None
     for i in range(steps):
@@ -173,6 +173,7 @@ def time_form(api, A, B, precision, route, steps, warmup, work, out):
         acc["p_cross_pair_checks"] += info["polish_cross_pair_checks"]
         acc["p_inner_rotations"] += info["polish_inner_rotations"]
         acc["polish_sweeps"].append(info["polish_sweeps"])
+        acc["step_seconds"].append(round(time.perf_counter() - ts, 4))
         log(f"{precision} step {i}: {time.perf_counter() - ts:.3f}s sweeps={info['sweeps']} "
             f"status={info['status']} refine_corr={info['refine_delta']:.2e}")
     sec = (time.perf_counter() - t0) / steps
@@ -558,8 +559,8 @@ def load_traffic(kernel: str, workload: str, precision: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="n8192_clustered")
     ap.add_argument("--n", type=int, default=None, help="override the workload size")
     ap.add_argument("--precision", default="all", choices=["all", "both", "fp64", "mixed", "mixed_polish"],
@@ -581,6 +582,7 @@ def main():
                                    "not part of this solver (--gpus must be 1)"}))
         sys.exit(2)
 
+    import numpy as np
     import torch
 
     from paper_2008_08825_amd import api, inputs
@@ -621,7 +623,6 @@ def main():
     oracle_lam = None
     golden = os.path.join(ROOT, "tests", "golden", f"oracle_{args.workload}_eigenvalues.txt")
     if args.n in (None, n) and os.path.exists(golden):
-        import numpy as np
         vals = np.loadtxt(golden)
         if vals.shape == (n,):
             oracle_lam = torch.from_numpy(vals).to(dev)
@@ -633,6 +634,8 @@ def main():
         X = Xbuf.mT.conj()
         res = {
             "seconds_per_solve": round(sec, 4),
+            "step_seconds": acc["step_seconds"],
+            "median_seconds": round(float(np.median(acc["step_seconds"])), 4),
             "nominal_tflops": round(nominal_flops(n, args.route) / sec / 1e12, 4),
             "status": info["status"],
             "jacobi_sweeps": acc["sweeps"],
