@@ -211,10 +211,12 @@ size_t bse_workspace_bytes_h2(int n, const bse_opts_t* opts);
  * over the run's 2m candidates; one work group per run up to m = 64, two
  * launches per vector beyond).  A final step
  * X <- X (I - (X^H Sigma X - I) / 2) makes the vectors Sigma-orthonormal to
- * rounding (the real solve fixes only Re(x^H Sigma y)).  Returns 0; -1 n, -2 A, -3 lda, -4 B, -5 ldb,
- * -6 lambda, -7 X, -8 ldx, -9 work NULL, -10 work_bytes too small, -11 opts
- * invalid or route TDA; a positive status is bse_solve_h1's for the order-2n
- * problem (e.g. 1..2n: A' + B' not positive definite); <= -1000 HIP error. */
+ * rounding (the real solve fixes only Re(x^H Sigma y)).  The call reads the
+ * eigenvalues back to the host to find the runs and returns after `stream`
+ * has finished.  Returns 0; -1 n, -2 A, -3 lda, -4 B, -5 ldb, -6 lambda,
+ * -7 X, -8 ldx, -9 work NULL, -10 work_bytes too small, -11 opts invalid or
+ * route TDA; a positive status is bse_solve_h1's for the order-2n problem
+ * (e.g. 1..2n: A' + B' not positive definite); <= -1000 HIP error. */
 int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb,
                  double* lambda, void* X, int ldx,
                  void* work, size_t work_bytes,
