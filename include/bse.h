@@ -205,9 +205,12 @@ size_t bse_workspace_bytes_h2(int n, const bse_opts_t* opts);
  *            eigenvectors with x^H Sigma x = 1; the negative half is
  *            [0 I; I 0] conj(X) (Lemma ComputeNegEvecs, part 2)
  *   work     device workspace of work_bytes >= bse_workspace_bytes_h2(n, opts)
- * opts.checks is ignored.  An eigenvalue of H2 of multiplicity m (a run of
- * eigenvalues whose gaps are at most 1e-12 lambda_max) gets m Sigma-orthonormal
- * vectors of its eigenspace (a pivoted Gram-Schmidt in the Sigma inner product
+ * opts.checks fills info->sigma_orth_fro (||X^H Sigma X - I||_F) and
+ * info->max_rel_resid (max_k ||H2 x_k - lambda_k x_k|| / (lambda_n ||x_k||)),
+ * measured on the order-2n problem with the real vectors of x_k and i x_k;
+ * the other info fields are those of the order-2n solve.  An eigenvalue of
+ * H2 of multiplicity m (a run of eigenvalues whose gaps are at most 1e-12
+ * lambda_max) gets m Sigma-orthonormal vectors of its eigenspace (a pivoted Gram-Schmidt in the Sigma inner product
  * over the run's 2m candidates; one work group per run up to m = 64, two
  * launches per vector beyond).  A final step
  * X <- X (I - (X^H Sigma X - I) / 2) makes the vectors Sigma-orthonormal to

@@ -301,12 +301,13 @@ def solve_h1(A: torch.Tensor, B: Optional[torch.Tensor], *, route="svd", precisi
 
 def solve_h2(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64", want_negative=False,
              max_sweeps=0, refine_steps=0, jacobi_tol=0.0, check=True,
-             work: Optional[torch.Tensor] = None, tiles=None, values_only=False):
+             work: Optional[torch.Tensor] = None, tiles=None, values_only=False, checks=False):
     """All eigenpairs of a form-II matrix H2 = [[A, B], [-B^H, -A^T]] (A Hermitian,
     B complex symmetric; lower triangles read) through ``bse_solve_h2``.
 
     Returns ``(lam, X, info)`` as :func:`solve_h1`; the negative half is
-    ``[[0, I], [I, 0]] conj(X)``.
+    ``[[0, I], [I, 0]] conj(X)``.  ``checks`` fills ``info["sigma_orth_fro"]``
+    (``|X^H Sigma X - I|_F``) and ``info["max_rel_resid"]`` on the device.
     """
     lib = load_library()
     if A.shape != B.shape or A.dim() != 2 or A.shape[0] != A.shape[1]:
@@ -319,7 +320,7 @@ def solve_h2(A: torch.Tensor, B: torch.Tensor, *, route="svd", precision="fp64",
     Bc = B.to(torch.complex128).mT.contiguous()
     ncols = 2 * n if want_negative else n
     o = make_opts(route, precision, max_sweeps, refine_steps, jacobi_tol, want_negative, "L", tiles,
-                  False, values_only)
+                  checks, values_only)
     lam = torch.empty(ncols, dtype=torch.float64, device=dev)
     Xbuf = None if values_only else torch.empty((ncols, 2 * n), dtype=torch.complex128, device=dev)
     need = int(lib.bse_workspace_bytes_h2(n, ctypes.byref(o)))

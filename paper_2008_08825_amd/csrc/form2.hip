@@ -38,6 +38,7 @@
 #include "plan.hpp"
 
 #include <math.h>
+#include <string.h>
 
 #include <vector>
 
@@ -354,6 +355,33 @@ struct NegOp {
   }
 };
 
+// opts.checks: the real vectors of the order-2n problem for the measurement,
+// Z[:, 2k] = z(x_k) and Z[:, 2k + 1] = z(i x_k), z(x) = [Re u; Im u; Re v;
+// -Im v] for x = [u; v] (complex128 storage, zero imaginary parts), and
+// their eigenvalues lam2[2k] = lam2[2k + 1] = lambda_k.  Work group =
+// (column k, 256 rows of x).
+struct ZArgs { int n; const double2* X; long ldx; const double* lambda; double2* Z; long ldz; double* lam2; };
+struct ZOp {
+  static constexpr int NT = 256;
+  typedef ZArgs Args;
+  static BSE_DEV void run(const Args& a, int bx, int) {
+    const int n = a.n, gx = (2 * n + 255) / 256;
+    const int k = bx / gx, r = (bx % gx) * 256 + threadIdx.x;
+    if (k >= n || r >= 2 * n) return;
+    if (r == 0) a.lam2[2 * k] = a.lam2[2 * k + 1] = a.lambda[k];
+    const double2 x = a.X[r + (long)k * a.ldx];
+    double2* z0 = a.Z + (long)(2 * k) * a.ldz;
+    double2* z1 = z0 + a.ldz;
+    // x -> (Re, Im) rows of u (r < n) or (Re, -Im) rows of v; i x = (-Im x, Re x)
+    const int q = r < n ? r : r + n;  // row of the real part: u at 0.., v at 2n..
+    const double s = r < n ? 1.0 : -1.0;
+    z0[q] = make_double2(x.x, 0.0);
+    z0[q + n] = make_double2(s * x.y, 0.0);
+    z1[q] = make_double2(-x.y, 0.0);
+    z1[q + n] = make_double2(s * x.x, 0.0);
+  }
+};
+
 struct H2Layout {
   size_t off_at = 0, off_bt = 0, off_lam = 0, off_x = 0, off_runs = 0, off_inner = 0;
 };
@@ -376,11 +404,13 @@ H2Layout h2_layout(int n, const bse_opts_t& o) {
   return L;
 }
 
-bse_opts_t inner_opts(const bse_opts_t& o) {
+// Options of the order-2n solve; `ws` keeps opts.checks for the workspace
+// plan (its measurement buffers serve the form-II measurement afterwards).
+bse_opts_t inner_opts(const bse_opts_t& o, bool ws = false) {
   bse_opts_t io = o;
   io.uplo = 'L';
   io.want_negative = 0;
-  io.checks = 0;
+  io.checks = ws ? o.checks : 0;
   return io;
 }
 
@@ -395,7 +425,7 @@ size_t bse_workspace_bytes_h2(int n, const bse_opts_t* opts) {
   if (opts) o = *opts;
   if (n < 0 || n > 23000 || !bse::opts_valid(o) || o.route == BSE_ROUTE_TDA) return 0;
   const bse::H2Layout L = bse::h2_layout(n, o);
-  const bse_opts_t io = bse::inner_opts(o);
+  const bse_opts_t io = bse::inner_opts(o, true);
   const size_t inner = bse_workspace_bytes(2 * n, &io);
   if (inner == 0) return 0;
   return L.off_inner + inner + 256;
@@ -517,6 +547,26 @@ int bse_solve_h2(int n, const void* A, int lda, const void* B, int ldb, double* 
     const bse::NegArgs na = {n, Xp, ldx};
     if (e == hipSuccess && o.want_negative) e = launch_one<bse::NegOp>(na, n * ((2 * n + 255) / 256), 0, s);
     if (e != hipSuccess) return bse::hip_status(e);
+  }
+  if (o.checks && !o.values_only) {
+    // measure on the order-2n problem: (A', B') formed again, Z = [z(x_k),
+    // z(i x_k)] in X's place; the real Sigma'-Gram of Z is a real form of
+    // X^H Sigma X (Frobenius norm sqrt(2) times), the residuals are those of
+    // the x_k; the form-I measurement's buffers are in the order-2n workspace
+    e = launch_one<bse::RealifyOp>(ra, T * T, 0, s);
+    const bse::ZArgs za = {n, static_cast<const double2*>(X), ldx, lambda, X2, 2 * m, lam2};
+    if (e == hipSuccess) e = launch_one<bse::ZOp>(za, n * ((2 * n + 255) / 256), 0, s);
+    if (e != hipSuccess) return bse::hip_status(e);
+    const bse_opts_t iw = bse::inner_opts(o, true);
+    const bse::Plan P = bse::make_plan(m, iw);
+    bse_info_t ci;
+    memset(&ci, 0, sizeof(ci));
+    const int cst = bse::run_checks(m, At, m, Bt, m, lam2, X2, 2 * m, base + L.off_inner, P, iw, &ci, s);
+    if (cst != 0) return cst;
+    if (info) {
+      info->sigma_orth_fro = ci.sigma_orth_fro / sqrt(2.0);
+      info->max_rel_resid = ci.max_rel_resid;
+    }
   }
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return bse::hip_status(e);

@@ -188,3 +188,24 @@ def test_form2_long_run_of_a_multiple_eigenvalue(gpu_lib, case):
     err, gap = om.eigvec_errors(lam_o, X_o, Xp, cluster_rtol=1e-9)
     assert np.all(err <= 1e-10 + 1e-13 / np.minimum(gap, 1.0)), (np.max(err), np.min(gap))
     assert np.array_equal(X[:n, n:], X[n:, :n].conj()) and np.array_equal(X[n:, n:], X[:n, :n].conj())
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_form2_device_checks(gpu_lib, precision):
+    """opts.checks for form II: Sigma-orthonormality and the largest relative residual
+    measured on the device (through the order-2n problem) against the host's measures
+    of the returned pairs."""
+    n = 100
+    A, B = inputs.coupled_form2(n, seed=901)
+    lam, X, info = run(gpu_lib, A, B, precision=precision, checks=True)
+    G = X.conj().T @ (sig(n)[:, None] * X)
+    so = np.linalg.norm(G - np.eye(n))
+    # both at rounding level after the final re-orthonormalisation: compare absolutely
+    assert 0.0 < info["sigma_orth_fro"] < 1e-12 and so < 1e-12
+    assert abs(info["sigma_orth_fro"] - so) <= 1e-13, (info["sigma_orth_fro"], so)
+    H = ob.bse_matrix_form2(A, B)
+    R = H @ X - X * lam[None, :]
+    rel = np.max(np.linalg.norm(R, axis=0) / np.linalg.norm(X, axis=0)) / lam[-1]
+    assert abs(info["max_rel_resid"] - rel) <= 0.1 * rel + 2e-15, (info["max_rel_resid"], rel)
+    _, _, off = run(gpu_lib, A, B, precision=precision)
+    assert off["sigma_orth_fro"] == 0.0 and off["max_rel_resid"] == 0.0
