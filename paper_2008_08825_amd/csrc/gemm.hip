@@ -32,7 +32,7 @@ __host__ __device__ inline bool lower_packed(int lowerC, int tilesM, int tilesN)
   return lowerC && tilesM == tilesN;
 }
 template <int OPA, typename P>
-BSE_DEV inline void tile_of(const P& p, int bx, int& tm, int& tn) {
+BSE_DEV void tile_of(const P& p, int bx, int& tm, int& tn) {
   if (lower_packed(p.lowerC, p.tilesM, p.tilesN)) {
     int r = (int)((sqrt(8.0 * bx + 1.0) - 1.0) * 0.5);
     while ((r + 1) * (r + 2) / 2 <= bx) ++r;
