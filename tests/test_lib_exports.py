@@ -176,6 +176,11 @@ def test_form2_host_argument_checks():
     assert lib.bse_workspace_bytes_h2(23001, ctypes.byref(o)) == 0
     tda = api.make_opts(route="tda")
     assert lib.bse_workspace_bytes_h2(4, ctypes.byref(tda)) == 0
+    # opts.checks: the order-2n workspace also holds the measurement's reduction buffers
+    chk = api.make_opts(checks=True)
+    assert lib.bse_workspace_bytes_h2(100, ctypes.byref(chk)) - lib.bse_workspace_bytes_h2(100, ctypes.byref(o)) \
+        == lib.bse_workspace_bytes(200, ctypes.byref(chk)) - lib.bse_workspace_bytes(200, ctypes.byref(o))
+    assert lib.bse_workspace_bytes(200, ctypes.byref(chk)) > lib.bse_workspace_bytes(200, ctypes.byref(o))
     h2 = lib.bse_solve_h2
     assert h2(-1, None, 1, None, 1, None, None, 1, None, 0, ctypes.byref(o), None, None) == -1
     assert h2(4, None, 4, 16, 4, 16, 16, 8, 16, 1 << 30, ctypes.byref(o), None, None) == -2
