@@ -5,8 +5,9 @@ Hermitian, ``B`` complex symmetric) but no algorithm; the oracle takes the
 Hermitian-definite pencil of its Hamiltonian.  Pins: the n = 1 closed form,
 a family that decouples into 2 x 2 problems (``A = Q^H diag(a) Q``,
 ``B = Q^H diag(b) conj(Q)``), real data (where form II is form I), the
-nonsymmetric eigensolver on ``H2``, the eigenvector relations and Lemma
-ComputeNegEvecs part 2; a planted mistake must fail them.
+nonsymmetric eigensolver on ``H2``, the eigenvector relations, Lemma
+ComputeNegEvecs part 2 and the closed-form eigenspace of a multiple eigenvalue;
+a planted mistake must fail them.
 """
 import numpy as np
 import pytest
@@ -110,3 +111,31 @@ def test_planted_mistake_fails_the_pins(monkeypatch):
     except Exception:  # the wrong "Hamiltonian" is not Hermitian
         ok = False
     assert not ok
+
+
+def test_multiple_eigenvalue_eigenspace():
+    """A repeated (a_i, b_i) makes an eigenvalue of multiplicity 5; the oracle's vectors for it are
+    Sigma-orthonormal and span the closed-form eigenspace {[Q^H e_i b_i; Q^T e_i (lambda - a_i)]}
+    (each 2 x 2 block [[a, b], [-conj(b), -a]] has the eigenvector [b; lambda - a])."""
+    n = 12
+    rng = np.random.default_rng(4)
+    Q = inputs.haar_unitary(rng, n)
+    a = rng.uniform(1.0, 5.0, n)
+    b = a * rng.uniform(0.1, 0.8, n) * np.exp(2j * np.pi * rng.uniform(size=n))
+    run = np.arange(3, 8)
+    a[run], b[run] = 2.0, 0.6 - 0.8j
+    A = Q.conj().T @ (a[:, None] * Q)
+    A = (A + A.conj().T) / 2
+    B = Q.conj().T @ (b[:, None] * Q.conj())
+    B = (B + B.T) / 2
+    lam, X = ob.solve_form2(A, B)
+    check_pairs(A, B, lam, X)
+    lr = np.sqrt(2.0 ** 2 - abs(0.6 - 0.8j) ** 2)
+    sel = np.abs(lam - lr) <= 1e-9 * lr
+    assert sel.sum() == run.size
+    E = np.eye(n)
+    Xc = np.stack([np.concatenate([Q.conj().T @ E[:, i] * b[i], Q.T @ E[:, i] * (lr - a[i])]) for i in run], 1)
+    Pc = Xc @ np.linalg.pinv(Xc)
+    Xo = X[:, sel]
+    Po = Xo @ np.linalg.pinv(Xo)
+    assert np.linalg.norm(Pc - Po) <= 1e-12
