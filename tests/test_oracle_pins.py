@@ -145,6 +145,39 @@ def test_routes_meet_pins(route):
     assert all_pins(solve) == []
 
 
+@pytest.mark.parametrize("route", ["chol_svd", "chol_eig", "pencil", "sqrt"])
+def test_multiple_eigenvalue_eigenspace(route):
+    """A repeated (a_i, b_i) in the commuting family gives an eigenvalue of multiplicity 6;
+    each route returns Sigma-orthonormal vectors for it that span the closed-form eigenspace
+    (the commuting family's vectors of the repeated indices)."""
+    solve = {"chol_svd": ob.solve_chol_svd, "chol_eig": ob.solve_chol_eig,
+             "pencil": ob.solve_pencil, "sqrt": ob.solve_sqrt}[route]
+    n = 14
+    rng = np.random.default_rng(8)
+    Q = inputs.haar_unitary(rng, n)
+    a = rng.uniform(1.0, 5.0, n)
+    b = a * rng.uniform(-0.8, 0.8, n)
+    run = np.arange(4, 10)
+    a[run], b[run] = 3.0, 1.0
+    A = Q.conj().T @ (a[:, None] * Q)
+    B = Q.conj().T @ (b[:, None] * Q)
+    A = (A + A.conj().T) / 2
+    B = (B + B.conj().T) / 2
+    lam, X = solve(A, B)
+    assert om.sigma_orth_err(X) < 1e-12
+    assert om.residual(A, B, lam, X) < 1e-13
+    lr = np.sqrt(8.0)
+    sel = np.abs(lam - lr) <= 1e-9 * lr
+    assert sel.sum() == run.size
+    alpha = ((a + b) / (a - b)) ** 0.25
+    q = Q.conj().T[:, run]
+    x, y = q * alpha[None, run], q / alpha[None, run]
+    Xc = np.vstack([(x + y) / 2, (y - x) / 2])
+    Pc = Xc @ np.linalg.pinv(Xc)
+    Po = X[:, sel] @ np.linalg.pinv(X[:, sel])
+    assert np.linalg.norm(Pc - Po) <= 1e-11
+
+
 def test_sqrt_route_table2_levels():
     """Alg. 1 on the Sec. 4 condition family: within 30x Table 2's SQRT row, and
     (kappa >= 1e6) far less accurate than CHOL+SVD, as Table 2 reports."""
